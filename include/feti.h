@@ -1,0 +1,200 @@
+/*
+ * feti.h - C ABI of the MI355X FETI library (Total FETI and FETI-DP with k-scaling,
+ * full orthogonalisation and rank-revealing simultaneous search directions) for
+ * SIMP-heterogeneous linear elasticity on structured Q4 / Hex8 grids.
+ *
+ * Method: Medricky, Doskar, Pultarova, Zeman, "Comparison of FETI-based domain
+ * decomposition methods for topology optimization problems", arXiv 2111.11728.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Grid: unit square (cube) elements, thickness 1. Nodes are numbered
+ *   lexicographically, x fastest; DOFs are interleaved, dof = dim*node + component;
+ *   elements are numbered lexicographically, x fastest.
+ * - Subdomains are the boxes of a tensor-product partition, numbered x fastest.
+ *   Local DOFs of a subdomain follow the same lexicographic rule inside its box.
+ * - Lagrange-multiplier rows (lambda) are ordered node by node in increasing global
+ *   node number, then component, then Dirichlet rows by subdomain (TFETI only) or
+ *   gluing pairs (a, b), a < b, with +1 on a and -1 on b. Every free DOF shared by m
+ *   subdomains gets all m(m-1)/2 pairs (redundant at cross-points, Sec. 3.1).
+ * - Blocks of lambda vectors are row-major [n_lambda x k] (k contiguous).
+ * - Unless stated otherwise every array argument is a DEVICE pointer, read or
+ *   written in stream order on the stream given to feti_setup; the caller owns it
+ *   and the library keeps no reference to it after the call returns. Host
+ *   pointers are marked "host".
+ * - No entry point throws; each returns a feti_status. On error the message is
+ *   available from feti_last_error() (thread-local) and outputs are unspecified,
+ *   except FETI_ENOCONV / FETI_EBREAKDOWN from feti_solve, which still write u and info.
+ */
+#ifndef FETI_H
+#define FETI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct feti_ctx feti_ctx;
+
+typedef enum {
+    FETI_OK = 0,
+    FETI_EINVAL = -1,      /* invalid argument (sizes, densities, options) */
+    FETI_ENOMEM = -2,      /* device or host allocation failed */
+    FETI_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+    FETI_ENOTSPD = -4,     /* non-positive pivot in a subdomain or coarse Cholesky */
+    FETI_ENOCONV = -5,     /* max_it reached before the tolerance; u and info written */
+    FETI_EBREAKDOWN = -6   /* Krylov breakdown: no independent direction left (rank 0) */
+} feti_status;
+
+enum { FETI_TFETI = 0, FETI_DP = 1 };                       /* Sec. 2.1 / Sec. 2.2 */
+enum { FETI_MULT = 0, FETI_KSCALE = 1 };                    /* Sec. 3.1 */
+enum { FETI_PCG = 0, FETI_FO = 1, FETI_SFETI = 2 };         /* Sec. 2, Sec. 3.2, Sec. 3.3 */
+enum { FETI_DIRICHLET = 0, FETI_LUMPED = 1 };               /* Sec. 3.1, Eq. (13) */
+enum { FETI_FP64 = 0, FETI_FP32 = 1, FETI_BF16X3 = 2 };     /* arithmetic of the F*Lambda product */
+
+/* Structured grid and boundary conditions (Sec. 2, Eq. 2). */
+typedef struct {
+    int dim;                  /* 2 (bilinear Q4, plane stress) or 3 (trilinear Hex8) */
+    int nel[3];               /* elements per axis (nel[2] ignored in 2D) */
+    double nu;                /* Poisson ratio, in (-1, 0.5) */
+    int n_fixed;              /* number of clamped global DOFs (value 0) */
+    const int* fixed_dofs;    /* host: clamped global DOF numbers */
+} feti_mesh;
+
+/* Partition into subdomains (Sec. 2) and the grouping of subdomains into
+ * simultaneous search directions (Sec. 3.3, Algorithm 1). */
+typedef struct {
+    int nsub[3];              /* subdomains per axis */
+    const int* cuts[3];       /* host: per axis nsub[a]+1 increasing element indices from 0 to nel[a];
+                                 NULL = uniform (nel[a] must then be divisible by nsub[a]) */
+    int group[3];             /* S-FETI: subdomain blocks per axis forming one direction
+                                 (0 or all 1 = one direction per subdomain) */
+} feti_partition;
+
+typedef struct {
+    int method;               /* FETI_TFETI or FETI_DP */
+    int scaling;              /* FETI_MULT or FETI_KSCALE */
+    int krylov;               /* FETI_PCG, FETI_FO or FETI_SFETI */
+    int precond;              /* FETI_DIRICHLET or FETI_LUMPED */
+    int precision;            /* FETI_FP64, FETI_FP32 or FETI_BF16X3: arithmetic of F*Lambda inside
+                                 the Krylov loop; Gram products, the coarse problem and the
+                                 true residual stay FP64 */
+    double tol;               /* stop when sqrt(r^T z) <= tol * sqrt(r_0^T z_0) (Eq. 16, relative) */
+    int max_it;               /* Krylov iteration cap (<= 0: n_lambda) */
+    double rr_tol;            /* rank-revealing pivot threshold on the Jacobi-scaled Gram matrix
+                                 (<= 0: 1e-12) */
+    int reorth;               /* passes of block classical Gram-Schmidt against the stored
+                                 directions (1 or 2; 0 = 2) */
+    int max_refine;           /* mixed precision: FP64 residual restarts after the first pass
+                                 (< 0: 4) */
+} feti_opts;
+
+typedef struct {
+    int iters;                /* Krylov iterations over all passes */
+    int refinements;          /* FP64 residual restarts performed */
+    int status;               /* feti_status of the solve */
+    double eps0;              /* sqrt(r_0^T z_0) */
+    double eps;               /* final sqrt(r^T z) of the recurrence */
+    double true_rel_res;      /* FP64 sqrt(r_t^T M r_t) / eps0 with r_t = P(d - F lambda) */
+    int kept_directions;      /* total directions kept by the rank-revealing factorisation */
+    double* res_hist;         /* host, optional: eps per iterate (first entry eps0) */
+    int res_hist_cap;
+    int* rank_hist;           /* host, optional: rank kept per iteration (same capacity) */
+    double t_solve_ms;        /* wall time of feti_solve on the host clock */
+} feti_info;
+
+typedef struct {
+    int n_sub, n_dof, n_el, n_lambda, n_cg, n_alpha, n_groups;
+    int nb_max, nb_min, n_loc_max, n_i_max, band_max;
+    long long sum_nb2;        /* sum over subdomains of n_b^2 (entries of all explicit F_s) */
+    long long sum_nb_nc;      /* sum over subdomains of n_b * n_c */
+    long long device_bytes;   /* device memory held by a context */
+} feti_sizes;
+
+/* Builds the integer topology only (no device work) and reports the interface sizes.
+ * Host-only; usable without a GPU. */
+feti_status feti_plan_sizes(const feti_mesh* mesh, const feti_partition* part,
+                            const feti_opts* opts, feti_sizes* out);
+
+/* Host-only export of the topology, for checking it against an independent
+ * construction. what: 0 = per lambda row [side0 subdomain, side0 local DOF, side0 sign,
+ * side1 subdomain (-1 if none), side1 local DOF, side1 sign] (6 ints per row);
+ * 1 = per subdomain [n_loc, n_i, n_b, n_c, band] (5 ints); 2 = global corner DOFs.
+ * out has capacity cap ints; *n_out receives the number written. */
+feti_status feti_plan_export(const feti_mesh* mesh, const feti_partition* part,
+                             const feti_opts* opts, int what, int* out, long long cap,
+                             long long* n_out);
+
+/* Setup (Sec. 2.1 / 2.2 operators, Sec. 3.1 preconditioner and scaling): assembles every
+ * subdomain stiffness K^s = sum_e (Emin + rho_e^p (E0 - Emin)) K0 (Eq. 1), factorises
+ * it, forms the explicit local dual operators F_s, the preconditioner blocks and the
+ * coarse problem on the device.
+ * rho: device [n_el] densities in [0, 1]. p >= 1, 0 < Emin < E0.
+ * stream: a hipStream_t (NULL = the null stream); every later call on the context runs
+ * on it. The context owns all of its device memory. */
+feti_status feti_setup(const feti_mesh* mesh, const feti_partition* part, const feti_opts* opts,
+                       const double* rho, double p, double E0, double Emin,
+                       void* stream, feti_ctx** out);
+
+/* Same topology, new densities: repeats assembly, factorisation and operator formation. */
+feti_status feti_update_rho(feti_ctx* ctx, const double* rho);
+
+/* Solves K u = f (Eq. 2) by the configured FETI variant.
+ * f: device [n_dof] global load (entries on clamped DOFs are ignored).
+ * u: device [n_dof] output, the average of the subdomain copies.
+ * lambda_init: device [n_lambda] warm start or NULL (FETI-DP: 0; TFETI: the
+ * minimum-norm lambda with G lambda = e).
+ * info: host, optional. Returns FETI_ENOCONV / FETI_EBREAKDOWN with u written. */
+feti_status feti_solve(feti_ctx* ctx, const double* f, double* u, const double* lambda_init,
+                       feti_info* info);
+
+/* Compliance c = f^T u and its gradient dc/drho_e = -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e
+ * (self-adjoint), after feti_update_rho(rho) and feti_solve(f).
+ * rho: device [n_el] or NULL (keep the current densities); f: device [n_dof] or NULL
+ * (reuse the last load); c: device scalar; dc_drho: device [n_el]; u: device [n_dof] or NULL. */
+feti_status feti_compliance_and_grad(feti_ctx* ctx, const double* rho, const double* f,
+                                     double* c, double* dc_drho, double* u, feti_info* info);
+
+feti_status feti_destroy(feti_ctx* ctx);
+
+const char* feti_last_error(void);
+
+/* ---- entry points of single steps of the Krylov loop (kernel-level access) ---- */
+
+feti_status feti_get_sizes(feti_ctx* ctx, feti_sizes* out);
+
+/* Q = F Lambda for a block of k directions (Sec. 2.1 Eq. 7: F = B K^+ B^T; Sec. 2.2 Eq. 12
+ * with u_c condensed: F_rr + F_rc Kbar_cc^{-1} F_rc^T). Lambda, Q: device [n_lambda x k]
+ * row-major FP64; precision selects the arithmetic of the local products
+ * (FP64, FP32 or BF16 split into hi + lo with three products). 1 <= k <= 64. */
+feti_status feti_apply_F(feti_ctx* ctx, int k, int precision, const double* Lambda, double* Q);
+
+/* Z = [.., B~^s S~^s B~^sT r, ..] (Sec. 3.1 Eq. 13, Algorithm 1): r device [n_lambda];
+ * Z device [n_lambda x n_groups] (one_column = 0) or [n_lambda] summed (one_column = 1). */
+feti_status feti_apply_precond(feti_ctx* ctx, const double* r, double* Z, int one_column);
+
+/* Y <- P Y with P = I - G^T (G G^T)^{-1} G (TFETI, Sec. 3.3); identity for FETI-DP.
+ * Y device [n_lambda x k], in place. */
+feti_status feti_project(feti_ctx* ctx, int k, double* Y);
+
+/* d (right-hand side of the lambda system) and lambda_0 for load f:
+ * TFETI d = B K^+ f (c = 0), lambda_0 = G^T (G G^T)^{-1} e; FETI-DP d = d_r - F_rc
+ * Kbar_cc^{-1} fbar_c, lambda_0 = 0. f device [n_dof]; d, lambda0 device [n_lambda]. */
+feti_status feti_rhs(feti_ctx* ctx, const double* f, double* d, double* lambda0);
+
+/* Copies one local matrix of subdomain s to host memory (for checking against the
+ * oracle). what: 0 = F_s [n_b x n_b]; 1 = S~^s preconditioner block [n_b x n_b];
+ * 2 = F_rc^s [n_b x n_c]; 3 = Kbar_cc^s [n_c x n_c]; 4 = scaling weight of every lambda row on
+ * each side [n_lambda x 2] (s ignored); 5 = global Kbar_cc [n_cg x n_cg] (s ignored);
+ * 6 = diagonal of K^s [n_loc]. out: host, capacity cap doubles; rows/cols: host, receive the shape. */
+feti_status feti_get_local(feti_ctx* ctx, int s, int what, double* out, long long cap,
+                           int* rows, int* cols);
+
+/* Milliseconds of the last call's device work, measured with HIP events on the context's
+ * stream: what 0 = last feti_apply_F (the local product kernel only), 1 = last feti_apply_F
+ * total, 2 = last feti_setup / feti_update_rho, 3 = last feti_solve. */
+feti_status feti_last_timing(feti_ctx* ctx, int what, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FETI_H */

@@ -1,0 +1,53 @@
+// Shared device-side definitions of the FETI library (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+
+#include "classes.hpp"
+#include "feti.h"
+
+namespace feti {
+
+constexpr int kMaxDirs = 64;      // widest block of search directions per launch
+constexpr int kWG = 256;          // threads per workgroup of the setup kernels (4 wavefronts)
+
+// Per-subdomain metadata, one struct per subdomain in device memory.
+struct SubMeta {
+    int lo[3];          // first element per axis
+    int nn[3];          // local nodes per axis
+    int n_loc, n_i, n_b, n_c, n_beta, grp;
+    int n_lines;        // block-tridiagonal blocks of K_ii (grid rows in 2D, planes in 3D)
+    int ldF;            // leading dimension (columns) of the row-major F_s storage, n_b rounded up to 16
+    int rows_F;         // n_b + n_c rounded up to 16 (rows of the augmented [F_s; F_rc^T] operator)
+    int pad_;
+    long long off_loc, off_i, off_b, off_c;   // prefix offsets of the per-DOF arrays
+    long long line0;    // first entry of this subdomain in the line table
+    long long off_L;    // block-tridiagonal factor storage (doubles)
+    long long off_Z;    // Z = L^{-1} K_i,beta, row-major [n_i x n_beta]
+    long long off_S;    // S = K_beta,beta - Z^T Z, row-major [n_beta x n_beta]
+    long long off_F;    // [rows_F x ldF] row-major F_s and F_rc^T (FP64 master copy)
+    long long off_Fsw;  // MFMA-swizzled copies (elements, same offset for every precision)
+    long long off_P;    // preconditioner block S~ [n_b x n_b] row-major; also work buffers of that size
+    long long off_Kc;   // Kbar_cc^s [n_c x n_c]
+    long long off_R;    // TFETI: R_b [n_b x n_rbm] row-major
+};
+
+// One block (grid line / plane) of the block-tridiagonal interior matrix.
+struct LineMeta {
+    int i0;             // first interior index of the block
+    int n;              // interior DOFs in the block
+    int n_prev;         // interior DOFs of the previous block (0 for the first)
+    int pad_;
+    long long off_diag; // n x n dense diagonal block (lower triangle holds L_kk after factorisation)
+    long long off_sub;  // n x n_prev dense block coupling to the previous block (L_{k,k-1})
+};
+
+__device__ __forceinline__ double warp_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace feti

@@ -1,0 +1,1239 @@
+// C ABI of the FETI library: context, setup pipeline, Krylov drivers, recovery.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "feti.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace feti;
+
+namespace {
+
+thread_local std::string g_err;
+
+feti_status fail(feti_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+struct HipError {
+    std::string msg;
+};
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) throw HipError{std::string(#x) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+#define CHECK_LAUNCH() HIPCHK(hipGetLastError())
+
+// Unit-modulus element stiffness by full Gauss quadrature on the unit square / cube
+// (bilinear / trilinear shape functions, corners x fastest, DOFs interleaved).
+std::vector<double> element_K0(int dim, double nu) {
+    const int nc = 1 << dim, ne = dim * nc, ns = dim == 2 ? 3 : 6;
+    std::vector<double> D(ns * ns, 0.0), K(ne * ne, 0.0);
+    if (dim == 2) {
+        const double c = 1.0 / (1.0 - nu * nu);
+        D[0] = c; D[1] = c * nu; D[3] = c * nu; D[4] = c; D[8] = c * 0.5 * (1.0 - nu);
+    } else {
+        const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = 1.0 / (2.0 * (1.0 + nu));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) D[i * 6 + j] = lam + (i == j ? 2.0 * mu : 0.0);
+        for (int i = 3; i < 6; ++i) D[i * 6 + i] = mu;
+    }
+    const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+    const int ngp = 1 << dim;
+    std::vector<double> B(ns * ne);
+    for (int g = 0; g < ngp; ++g) {
+        const double xi[3] = {gp[g & 1], gp[(g >> 1) & 1], dim == 3 ? gp[(g >> 2) & 1] : 0.0};
+        const double w = dim == 2 ? 0.25 : 0.125;
+        std::fill(B.begin(), B.end(), 0.0);
+        for (int a = 0; a < nc; ++a) {
+            const int o[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+            double dN[3];
+            for (int d = 0; d < dim; ++d) {
+                double v = o[d] ? 1.0 : -1.0;
+                for (int d2 = 0; d2 < dim; ++d2)
+                    if (d2 != d) v *= o[d2] ? xi[d2] : 1.0 - xi[d2];
+                dN[d] = v;
+            }
+            if (dim == 2) {
+                B[0 * ne + 2 * a] = dN[0];
+                B[1 * ne + 2 * a + 1] = dN[1];
+                B[2 * ne + 2 * a] = dN[1];
+                B[2 * ne + 2 * a + 1] = dN[0];
+            } else {
+                B[0 * ne + 3 * a] = dN[0];
+                B[1 * ne + 3 * a + 1] = dN[1];
+                B[2 * ne + 3 * a + 2] = dN[2];
+                B[3 * ne + 3 * a + 1] = dN[2];
+                B[3 * ne + 3 * a + 2] = dN[1];
+                B[4 * ne + 3 * a] = dN[2];
+                B[4 * ne + 3 * a + 2] = dN[0];
+                B[5 * ne + 3 * a] = dN[1];
+                B[5 * ne + 3 * a + 1] = dN[0];
+            }
+        }
+        for (int i = 0; i < ne; ++i)
+            for (int j = 0; j < ne; ++j) {
+                double v = 0.0;
+                for (int p = 0; p < ns; ++p)
+                    for (int q = 0; q < ns; ++q) v += B[p * ne + i] * D[p * ns + q] * B[q * ne + j];
+                K[i * ne + j] += w * v;
+            }
+    }
+    return K;
+}
+
+long long rup(long long x, long long m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+// -----------------------------------------------------------------------------------------
+struct feti_ctx {
+    Plan P;
+    feti_opts opts{};
+    double p = 3, E0 = 1, Emin = 1e-6;
+    hipStream_t st = nullptr;
+    DevTopo t;
+    std::vector<SubMeta> hsubs;
+    std::vector<LineMeta> hlines;
+    std::vector<void*> allocs;
+    long long bytes = 0;
+
+    // numeric state
+    double *rho = nullptr, *L = nullptr, *Z = nullptr, *S = nullptr, *diag = nullptr, *F64 = nullptr;
+    double* sw64 = nullptr;
+    float* sw32 = nullptr;
+    __hip_bfloat16 *swhi = nullptr, *swlo = nullptr;
+    double *P64 = nullptr, *W1 = nullptr, *W2 = nullptr;
+    float* P32 = nullptr;
+    double *Kc = nullptr, *Kcc = nullptr, *Kcc_w = nullptr, *Kcc_inv = nullptr;
+    double *Rb = nullptr, *Cit = nullptr, *tau = nullptr, *GG = nullptr, *GG_w = nullptr, *GG_inv = nullptr;
+    double *w = nullptr, *bg_w = nullptr;
+    int* info = nullptr;
+    GemmDesc *d_syrk = nullptr, *d_F = nullptr, *d_one = nullptr;
+    PotrfDesc *d_potrf = nullptr, *d_potrf_one = nullptr;
+    TrsmDesc *d_trsm = nullptr, *d_trsm_one = nullptr;
+    int syrk_tiles = 0, F_tiles = 0, max_nb_cols = 0;
+    int n_alpha = 0;
+
+    // solve buffers
+    double *f_last = nullptr, *fi = nullptr, *fbeta = nullptr, *h = nullptr, *g = nullptr, *yb = nullptr,
+           *yc = nullptr, *fbar_s = nullptr, *d = nullptr, *lam0 = nullptr, *lam = nullptr, *lt = nullptr,
+           *r = nullptr, *xb = nullptr, *ubeta = nullptr, *ui = nullptr, *uloc = nullptr, *uc = nullptr,
+           *alpha = nullptr, *e = nullptr, *GY = nullptr, *tcoef = nullptr, *u_int = nullptr;
+    double *Ybuf = nullptr, *Tbuf = nullptr, *vbuf = nullptr, *Qtmp = nullptr, *Tsum = nullptr;
+    double *Zk = nullptr, *Qk = nullptr, *Delta = nullptr, *Tm = nullptr, *gam = nullptr, *part = nullptr,
+           *scal = nullptr, *Psi = nullptr, *tmpv = nullptr, *zv = nullptr, *K0dev = nullptr;
+    int* rank_dev = nullptr;
+    const double** qk_ptr = nullptr;    // device table holding the single pointer Qk
+    long long psi_cap = 0;
+    // history of F-orthonormal directions
+    std::vector<double*> hist_chunks;
+    std::vector<const double*> WH, QH;
+    const double** WH_dev = nullptr;
+    const double** QH_dev = nullptr;
+    int hist_cap = 0, hist_kd = 0;
+    bool have_f = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double last_ms[4] = {0, 0, 0, 0};
+
+    template <typename T>
+    T* alloc(long long n) {
+        if (n <= 0) n = 1;
+        void* p = nullptr;
+        HIPCHK(hipMalloc(&p, sizeof(T) * n));
+        allocs.push_back(p);
+        bytes += sizeof(T) * n;
+        return (T*)p;
+    }
+    template <typename T>
+    T* upload(const std::vector<T>& v) {
+        T* p = alloc<T>((long long)v.size());
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+        return p;
+    }
+    ~feti_ctx() {
+        hipStreamSynchronize(st);
+        for (void* p : allocs) hipFree(p);
+        for (double* p : hist_chunks) hipFree(p);
+        if (WH_dev) hipFree(WH_dev);
+        if (QH_dev) hipFree(QH_dev);
+        if (Psi) hipFree(Psi);
+        for (auto& e : ev)
+            if (e) hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+void build_layout(feti_ctx* c) {
+    Plan& P = c->P;
+    const int ns = P.n_sub;
+    c->hsubs.assign(ns, SubMeta{});
+    c->hlines.clear();
+    long long oL = 0, oZ = 0, oS = 0, oF = 0, oP = 0, oKc = 0, oR = 0;
+    DevTopo& t = c->t;
+    const int nrbm = P.method == FETI_TFETI ? (P.dim == 2 ? 3 : 6) : 0;
+    for (int s = 0; s < ns; ++s) {
+        SubMeta& M = c->hsubs[s];
+        for (int a = 0; a < 3; ++a) {
+            M.lo[a] = P.lo[3 * s + a];
+            M.nn[a] = P.nn[3 * s + a];
+        }
+        M.n_loc = P.n_loc[s];
+        M.n_i = P.n_i[s];
+        M.n_b = P.n_b[s];
+        M.n_c = P.n_c[s];
+        M.n_beta = M.n_b + M.n_c;
+        M.grp = P.grp[s];
+        M.ldF = (int)rup(std::max(M.n_b, 1), 32);
+        M.rows_F = (int)rup(std::max(M.n_b + M.n_c, 1), 16);
+        M.off_loc = P.off_loc[s];
+        M.off_i = P.off_i[s];
+        M.off_b = P.off_b[s];
+        M.off_c = P.off_c[s];
+        // lines: grid rows (2D) or planes (3D) of interior DOFs
+        const int nlines = P.dim == 2 ? M.nn[1] : M.nn[2];
+        const int per_line_nodes = P.dim == 2 ? M.nn[0] : M.nn[0] * M.nn[1];
+        M.n_lines = nlines;
+        M.line0 = (long long)c->hlines.size();
+        M.off_L = oL;
+        int i0 = 0, prev = 0;
+        for (int k = 0; k < nlines; ++k) {
+            int n = 0;
+            for (int ln = k * per_line_nodes; ln < (k + 1) * per_line_nodes; ++ln)
+                for (int cc = 0; cc < P.dim; ++cc)
+                    if (P.lcls[M.off_loc + (long long)ln * P.dim + cc] == CLS_I) ++n;
+            LineMeta Lm{};
+            Lm.i0 = i0;
+            Lm.n = n;
+            Lm.n_prev = prev;
+            Lm.off_diag = oL;
+            oL += (long long)n * n;
+            Lm.off_sub = oL;
+            oL += (long long)n * prev;
+            c->hlines.push_back(Lm);
+            t.max_line = std::max(t.max_line, n);
+            i0 += n;
+            prev = n;
+        }
+        M.off_Z = oZ;
+        oZ += (long long)M.n_i * M.n_beta;
+        M.off_S = oS;
+        oS += (long long)M.n_beta * M.n_beta;
+        M.off_F = oF;
+        M.off_Fsw = oF;
+        oF += (long long)M.rows_F * M.ldF;
+        M.off_P = oP;
+        oP += (long long)M.n_b * M.n_b;
+        M.off_Kc = oKc;
+        oKc += (long long)M.n_c * M.n_c;
+        M.off_R = oR;
+        oR += (long long)M.n_b * nrbm;
+        t.max_nodes = std::max(t.max_nodes, M.nn[0] * M.nn[1] * M.nn[2]);
+        t.max_beta = std::max(t.max_beta, M.n_beta);
+        t.max_nb = std::max(t.max_nb, M.n_b);
+        t.max_nc = std::max(t.max_nc, M.n_c);
+        t.max_ni = std::max(t.max_ni, M.n_i);
+        t.max_nloc = std::max(t.max_nloc, M.n_loc);
+        t.max_rows_F = std::max(t.max_rows_F, M.rows_F);
+    }
+    t.dim = P.dim;
+    t.n_sub = ns;
+    t.n_lambda = P.n_lambda;
+    t.n_cg = P.n_cg;
+    t.n_groups = P.n_groups;
+    t.n_rbm = nrbm;
+    for (int a = 0; a < 3; ++a) {
+        t.nel[a] = P.dim > a ? P.nel[a] : 0;
+        t.nsub[a] = P.nsub[a];
+    }
+    t.nb_tot = P.off_b[ns];
+    t.nc_tot = P.off_c[ns];
+    t.ni_tot = P.off_i[ns];
+    t.nloc_tot = P.off_loc[ns];
+    t.n_dof = P.n_dof;
+    c->n_alpha = ns * nrbm;
+
+    // ---- device buffers ----
+    c->L = c->alloc<double>(oL);
+    c->Z = c->alloc<double>(oZ);
+    c->S = c->alloc<double>(oS);
+    c->F64 = c->alloc<double>(oF);
+    c->sw64 = c->alloc<double>(oF);
+    c->sw32 = c->alloc<float>(oF);
+    c->swhi = c->alloc<__hip_bfloat16>(oF);
+    c->swlo = c->alloc<__hip_bfloat16>(oF);
+    c->P64 = c->alloc<double>(oP);
+    c->P32 = c->alloc<float>(oP);
+    c->W1 = c->alloc<double>(oP);
+    c->W2 = c->alloc<double>(oP);
+    c->Kc = c->alloc<double>(oKc);
+    c->Rb = c->alloc<double>(oR);
+    c->Cit = c->alloc<double>(36ll * ns);
+    c->tau = c->alloc<double>(ns);
+    c->diag = c->alloc<double>(t.nloc_tot);
+    c->rho = c->alloc<double>(P.n_el);
+    c->info = c->alloc<int>(ns + 8);
+    const int ncg = P.n_cg;
+    c->Kcc = c->alloc<double>((long long)ncg * ncg);
+    c->Kcc_w = c->alloc<double>((long long)ncg * ncg);
+    c->Kcc_inv = c->alloc<double>((long long)ncg * ncg);
+    const int na = c->n_alpha;
+    c->GG = c->alloc<double>((long long)na * na);
+    c->GG_w = c->alloc<double>((long long)na * na);
+    c->GG_inv = c->alloc<double>((long long)na * na);
+    c->w = c->alloc<double>(2ll * P.n_lambda);
+    c->bg_w = c->alloc<double>((long long)P.bg_row.size());
+
+    // descriptors
+    std::vector<GemmDesc> dsy(ns), dF(ns);
+    std::vector<PotrfDesc> dpo(ns);
+    std::vector<TrsmDesc> dtr(ns);
+    for (int s = 0; s < ns; ++s) {
+        const SubMeta& M = c->hsubs[s];
+        dsy[s] = GemmDesc{M.off_Z, M.off_Z, M.off_S, M.n_beta, M.n_beta, M.n_i, M.n_beta, M.n_beta, M.n_beta};
+        dF[s] = GemmDesc{M.off_P, M.off_P, M.off_F, M.n_b, M.n_b, M.n_b, M.n_b, M.n_b, M.ldF};
+        dpo[s] = PotrfDesc{M.off_P, M.n_b, M.n_b};
+        dtr[s] = TrsmDesc{M.off_P, M.off_P, M.n_b, M.n_b, M.n_b, M.n_b};
+        const int tb = (M.n_beta + 63) / 64, tf = (M.n_b + 63) / 64;
+        c->syrk_tiles = std::max(c->syrk_tiles, tb * tb);
+        c->F_tiles = std::max(c->F_tiles, tf * tf);
+        c->max_nb_cols = std::max(c->max_nb_cols, M.n_b);
+    }
+    c->d_syrk = c->upload(dsy);
+    c->d_F = c->upload(dF);
+    c->d_potrf = c->upload(dpo);
+    c->d_trsm = c->upload(dtr);
+    const int nsmall = std::max(ncg, na);
+    c->d_one = c->upload(std::vector<GemmDesc>{GemmDesc{0, 0, 0, nsmall, nsmall, nsmall, nsmall, nsmall, nsmall}});
+    c->d_potrf_one = c->upload(std::vector<PotrfDesc>{PotrfDesc{0, nsmall, nsmall}});
+    c->d_trsm_one = c->upload(std::vector<TrsmDesc>{TrsmDesc{0, 0, nsmall, nsmall, nsmall, nsmall}});
+
+    // F*Lambda work list: 128-row tiles, subdomain s on XCD s % 8
+    std::vector<std::vector<std::pair<int, int>>> bucket(8);
+    for (int s = 0; s < ns; ++s)
+        for (int r0 = 0; r0 < c->hsubs[s].rows_F; r0 += 128) bucket[s % 8].push_back({s, r0});
+    size_t mx = 0;
+    for (auto& b : bucket) mx = std::max(mx, b.size());
+    std::vector<int> ts, tr;
+    for (size_t i = 0; i < mx; ++i)
+        for (int x = 0; x < 8; ++x) {
+            if (i < bucket[x].size()) {
+                ts.push_back(bucket[x][i].first);
+                tr.push_back(bucket[x][i].second);
+            } else {
+                ts.push_back(-1);
+                tr.push_back(0);
+            }
+        }
+    // trim trailing dummies
+    while (!ts.empty() && ts.back() < 0) {
+        ts.pop_back();
+        tr.pop_back();
+    }
+    t.n_m_tiles = (int)ts.size();
+
+    // topology arrays
+    std::vector<int> bq_s(t.nb_tot);
+    for (int s = 0; s < ns; ++s)
+        for (long long q = P.off_b[s]; q < P.off_b[s + 1]; ++q) bq_s[q] = s;
+    t.subs = c->upload(c->hsubs);
+    t.lines = c->upload(c->hlines);
+    t.lcls = c->upload(P.lcls);
+    t.lidx = c->upload(P.lidx);
+    t.lglob = c->upload(P.lglob);
+    t.lown = c->upload(P.lown);
+    t.i_loc = c->upload(P.i_loc);
+    t.b_loc = c->upload(P.b_loc);
+    t.c_loc = c->upload(P.c_loc);
+    t.c_glob = c->upload(P.c_glob);
+    t.bq_s = c->upload(bq_s);
+    t.row_s = c->upload(P.row_s);
+    t.row_j = c->upload(P.row_j);
+    t.row_sg = c->upload(P.row_sg);
+    t.row_sh = c->upload(P.row_sh);
+    t.sh_ptr = c->upload(P.sh_ptr);
+    t.sh_s = c->upload(P.sh_s);
+    t.sh_l = c->upload(P.sh_l);
+    t.bg_ptr = c->upload(P.bg_ptr);
+    t.bg_row = c->upload(P.bg_row);
+    t.bg_sg = c->upload(P.bg_sg);
+    t.cc_ptr = c->upload(P.cc_ptr);
+    t.cc_s = c->upload(P.cc_s);
+    t.cc_j = c->upload(P.cc_j);
+    for (int a = 0; a < 3; ++a) {
+        t.ax_first[a] = c->upload(P.ax_first[a]);
+        t.ax_cnt[a] = c->upload(P.ax_cnt[a]);
+    }
+    t.m_tile_sub = c->upload(ts);
+    t.m_tile_row = c->upload(tr);
+    std::vector<double> K0 = element_K0(P.dim, P.nu);
+    c->K0dev = c->upload(K0);
+    t.K0dev = c->K0dev;
+    upload_K0(K0.data(), (int)std::lround(std::sqrt((double)K0.size())), c->st);
+    CHECK_LAUNCH();
+
+    // solve buffers
+    const long long nl = std::max(1, P.n_lambda);
+    const long long nbk = std::max<long long>(1, t.nb_tot), nck = std::max<long long>(1, t.nc_tot);
+    c->f_last = c->alloc<double>(P.n_dof);
+    c->fi = c->alloc<double>(t.ni_tot);
+    c->fbeta = c->alloc<double>(t.nb_tot + t.nc_tot);
+    c->h = c->alloc<double>(t.ni_tot);
+    c->g = c->alloc<double>(t.nb_tot + t.nc_tot);
+    c->yb = c->alloc<double>(nbk);
+    c->yc = c->alloc<double>(nck);
+    c->fbar_s = c->alloc<double>(nck);
+    c->Tsum = c->alloc<double>(nck);
+    c->d = c->alloc<double>(nl);
+    c->lam0 = c->alloc<double>(nl);
+    c->lam = c->alloc<double>(nl);
+    c->lt = c->alloc<double>(nl);
+    c->r = c->alloc<double>(nl);
+    c->zv = c->alloc<double>(nl);
+    c->tmpv = c->alloc<double>(nl);
+    c->xb = c->alloc<double>(nbk);
+    c->ubeta = c->alloc<double>(t.nb_tot + t.nc_tot);
+    c->ui = c->alloc<double>(t.ni_tot);
+    c->uloc = c->alloc<double>(t.nloc_tot);
+    c->uc = c->alloc<double>(std::max(1, ncg));
+    c->alpha = c->alloc<double>(std::max(1, na));
+    c->e = c->alloc<double>(std::max(1, na));
+    c->GY = c->alloc<double>((long long)std::max(1, na) * kMaxDirs);
+    c->tcoef = c->alloc<double>((long long)std::max(1, na) * kMaxDirs);
+    c->u_int = c->alloc<double>(P.n_dof);
+    c->Ybuf = c->alloc<double>(nbk * kMaxDirs);
+    c->Tbuf = c->alloc<double>(nck * kMaxDirs);
+    c->vbuf = c->alloc<double>((long long)std::max(1, ncg) * kMaxDirs);
+    c->Qtmp = c->alloc<double>(nl * kMaxDirs);
+    c->Zk = c->alloc<double>(nl * kMaxDirs);
+    c->Qk = c->alloc<double>(nl * kMaxDirs);
+    c->Delta = c->alloc<double>(kMaxDirs * kMaxDirs);
+    c->Tm = c->alloc<double>(kMaxDirs * kMaxDirs);
+    c->gam = c->alloc<double>(kMaxDirs);
+    c->part = c->alloc<double>(kGramPartCap);
+    c->scal = c->alloc<double>(16);
+    c->rank_dev = c->alloc<int>(4);
+    c->qk_ptr = c->upload(std::vector<const double*>{c->Qk});
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+}
+
+struct Timer {
+    feti_ctx* c;
+    int slot;
+    Timer(feti_ctx* c_, int s) : c(c_), slot(s) { HIPCHK(hipEventRecord(c->ev[0], c->st)); }
+    void stop() {
+        HIPCHK(hipEventRecord(c->ev[1], c->st));
+        HIPCHK(hipEventSynchronize(c->ev[1]));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        c->last_ms[slot] = ms;
+    }
+};
+
+void check_info(feti_ctx* c, int n, const char* what) {
+    std::vector<int> h(n);
+    HIPCHK(hipMemcpyAsync(h.data(), c->info, sizeof(int) * n, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int i = 0; i < n; ++i)
+        if (h[i]) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "%s: non-positive pivot (matrix %d, row %d)", what, i, h[i] - 1);
+            throw std::runtime_error(buf);
+        }
+}
+
+// Dense SPD n x n matrix A (device) -> Ainv (device), via Cholesky, X = L^{-1}, Ainv = X^T X.
+void dense_spd_inverse(feti_ctx* c, int n, const double* A, double* work, double* Ainv, const char* what) {
+    if (n == 0) return;
+    std::vector<GemmDesc> gd{GemmDesc{0, 0, 0, n, n, n, n, n, n}};
+    std::vector<PotrfDesc> pd{PotrfDesc{0, n, n}};
+    std::vector<TrsmDesc> td{TrsmDesc{0, 0, n, n, n, n}};
+    HIPCHK(hipMemcpyAsync(c->d_one, gd.data(), sizeof(GemmDesc), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->d_potrf_one, pd.data(), sizeof(PotrfDesc), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->d_trsm_one, td.data(), sizeof(TrsmDesc), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(work, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), c->st));
+    launch_potrf(c->d_potrf_one, 1, work, c->info, c->st);
+    CHECK_LAUNCH();
+    check_info(c, 1, what);
+    launch_set_identity(Ainv, n, n, c->st);
+    launch_trsm(c->d_trsm_one, 1, n, work, Ainv, c->st);
+    // Ainv currently holds X = L^{-1}; form X^T X into work, then copy
+    launch_gemm_tn(c->d_one, 1, ((n + 63) / 64) * ((n + 63) / 64), Ainv, Ainv, work, 1.0, 0.0, 1, c->st);
+    CHECK_LAUNCH();
+    HIPCHK(hipMemcpyAsync(Ainv, work, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c->st));
+}
+
+// Assembly, factorisation and explicit local operators for the current densities.
+void numeric_setup(feti_ctx* c) {
+    Timer tm(c, 2);
+    const Plan& P = c->P;
+    DevTopo& t = c->t;
+    hipStream_t st = c->st;
+    const auto& H = c->hsubs;
+    auto zero = [&](void* p, long long bytes) {
+        if (bytes > 0) HIPCHK(hipMemsetAsync(p, 0, bytes, st));
+    };
+    long long nL = 0, nZ = 0, nS = 0, nF = 0;
+    if (!H.empty()) {
+        const SubMeta& Ml = H.back();
+        const LineMeta& Ll = c->hlines.back();
+        nL = Ll.off_sub + (long long)Ll.n * Ll.n_prev;
+        nZ = Ml.off_Z + (long long)Ml.n_i * Ml.n_beta;
+        nS = Ml.off_S + (long long)Ml.n_beta * Ml.n_beta;
+        nF = Ml.off_F + (long long)Ml.rows_F * Ml.ldF;
+    }
+    zero(c->L, nL * 8);
+    zero(c->Z, nZ * 8);
+    zero(c->S, nS * 8);
+    zero(c->F64, nF * 8);
+    zero(c->diag, t.nloc_tot * 8);
+    zero(c->info, (t.n_sub + 8) * 4);
+    launch_assemble(t, c->rho, c->p, c->E0, c->Emin, c->L, c->Z, c->S, c->diag, st);
+    CHECK_LAUNCH();
+    launch_bt_factor(t, c->L, c->info, st);
+    CHECK_LAUNCH();
+    check_info(c, t.n_sub, "interior Cholesky");
+    launch_bt_forward(t, c->L, c->Z, st);
+    CHECK_LAUNCH();
+    if (c->opts.precond == FETI_LUMPED) launch_copy_Sbb(t, c->S, c->P64, 0, st);
+    launch_gemm_tn(c->d_syrk, t.n_sub, c->syrk_tiles, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
+    CHECK_LAUNCH();
+    if (c->opts.precond == FETI_DIRICHLET) launch_copy_Sbb(t, c->S, c->P64, 0, st);
+    long long nP = H.empty() ? 0 : H.back().off_P + (long long)H.back().n_b * H.back().n_b;
+    launch_to_f32(c->P64, c->P32, nP, st);
+    if (P.method == FETI_TFETI)
+        launch_tfeti_rbm(t, c->S, c->Rb, c->Cit, c->tau, c->W1, st);
+    else
+        launch_copy_Sbb(t, c->S, c->W1, 0, st);
+    CHECK_LAUNCH();
+    zero(c->info, (t.n_sub + 8) * 4);
+    launch_potrf(c->d_potrf, t.n_sub, c->W1, c->info, st);
+    CHECK_LAUNCH();
+    check_info(c, t.n_sub, "interface Schur complement Cholesky");
+    launch_copy_Sbb(t, c->S, c->W2, 1, st);
+    launch_trsm(c->d_trsm, t.n_sub, c->max_nb_cols, c->W1, c->W2, st);
+    launch_gemm_tn(c->d_F, t.n_sub, c->F_tiles, c->W2, c->W2, c->F64, 1.0, 0.0, 1, st);
+    CHECK_LAUNCH();
+    if (P.method == FETI_TFETI)
+        launch_tfeti_fix(t, c->Rb, c->tau, c->F64, st);
+    else
+        launch_frc(t, c->S, c->F64, c->Kc, st);
+    CHECK_LAUNCH();
+    launch_swizzle(t, c->F64, c->sw64, c->sw32, c->swhi, c->swlo, st);
+    launch_weights(t, c->opts.scaling == FETI_KSCALE, c->diag, c->w, c->bg_w, st);
+    CHECK_LAUNCH();
+    if (P.method == FETI_DP && P.n_cg > 0) {
+        zero(c->Kcc, (long long)P.n_cg * P.n_cg * 8);
+        launch_coarse_assemble(t, c->Kc, c->Kcc, st);
+        CHECK_LAUNCH();
+        dense_spd_inverse(c, P.n_cg, c->Kcc, c->Kcc_w, c->Kcc_inv, "coarse Cholesky");
+    }
+    if (P.method == FETI_TFETI && c->n_alpha > 0) {
+        zero(c->GG, (long long)c->n_alpha * c->n_alpha * 8);
+        launch_ggt_assemble(t, c->Rb, c->GG, st);
+        CHECK_LAUNCH();
+        dense_spd_inverse(c, c->n_alpha, c->GG, c->GG_w, c->GG_inv, "G G^T Cholesky");
+    }
+    tm.stop();
+}
+
+// ---------------------------------------------------------------- operator applications
+
+// Q = F Lambda (n_lambda x k) in the given precision.
+void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool time_it = false) {
+    DevTopo& t = c->t;
+    hipStream_t st = c->st;
+    const void* A = prec == FETI_FP64 ? (const void*)c->sw64 : prec == FETI_FP32 ? (const void*)c->sw32 : (const void*)c->swhi;
+    const int f32 = prec != FETI_FP64;
+    if (time_it) HIPCHK(hipEventRecord(c->ev[2], st));
+    launch_flambda(t, prec, k, Lam, A, c->swlo, c->Ybuf, c->Tbuf, st);
+    CHECK_LAUNCH();
+    if (time_it) HIPCHK(hipEventRecord(c->ev[3], st));
+    const double* v = nullptr;
+    if (c->P.method == FETI_DP && c->P.n_cg > 0) {
+        launch_coarse(t, k, f32, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->vbuf, st);
+        v = c->vbuf;
+    }
+    launch_scatter(t, k, f32, c->Ybuf, c->F64, v, Q, st);
+    CHECK_LAUNCH();
+}
+
+void project(feti_ctx* c, int k, double* Y) {
+    if (c->P.method != FETI_TFETI || c->P.n_lambda == 0) return;
+    DevTopo& t = c->t;
+    launch_proj_G(t, k, Y, c->Rb, c->GY, c->st);
+    launch_small_gemm(c->n_alpha, k, c->n_alpha, c->GG_inv, c->GY, c->tcoef, 1.0, c->st);
+    launch_proj_apply(t, k, c->tcoef, c->Rb, 1.0, Y, c->st);
+    CHECK_LAUNCH();
+}
+
+void precondition(feti_ctx* c, const double* r, double* Z, int one_column, int use_f32) {
+    DevTopo& t = c->t;
+    launch_precond_local(t, use_f32, r, c->bg_w, c->P64, c->P32, c->yb, c->st);
+    launch_precond_scatter(t, one_column, c->w, c->yb, Z, c->st);
+    CHECK_LAUNCH();
+}
+
+double read_scalar(feti_ctx* c, const double* dptr) {
+    double v = 0;
+    HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return v;
+}
+
+// dot(a, b) of n-vectors into c->scal[slot]
+void ddot(feti_ctx* c, int n, const double* a, const double* b, int slot) {
+    launch_rowsum_dot(n, 1, a, b, c->part, c->scal + slot, c->st);
+    CHECK_LAUNCH();
+}
+
+// RHS: d and lambda_0 from the global load f.
+void compute_rhs(feti_ctx* c, const double* f) {
+    DevTopo& t = c->t;
+    hipStream_t st = c->st;
+    const Plan& P = c->P;
+    if (f != c->f_last) HIPCHK(hipMemcpyAsync(c->f_last, f, sizeof(double) * P.n_dof, hipMemcpyDeviceToDevice, st));
+    c->have_f = true;
+    launch_scatter_f(t, f, c->fi, c->fbeta, st);
+    HIPCHK(hipMemcpyAsync(c->h, c->fi, sizeof(double) * std::max<long long>(1, t.ni_tot), hipMemcpyDeviceToDevice, st));
+    launch_bt_fsolve1(t, c->L, c->h, st);
+    launch_zt_gemv(t, c->Z, c->h, c->fbeta, c->g, st);
+    launch_local_F(t, c->F64, c->g, c->yb, c->yc, st);
+    CHECK_LAUNCH();
+    if (P.n_lambda > 0) {
+        if (P.method == FETI_DP) {
+            launch_fbar(t, c->g, c->yc, c->fbar_s, st);
+            const double* v = nullptr;
+            if (P.n_cg > 0) {
+                launch_coarse(t, 1, 0, c->fbar_s, nullptr, c->Kcc_inv, -1.0, c->vbuf, st);
+                v = c->vbuf;
+            }
+            launch_scatter(t, 1, 0, c->yb, c->F64, v, c->d, st);
+            HIPCHK(hipMemsetAsync(c->lam0, 0, sizeof(double) * P.n_lambda, st));
+        } else {
+            launch_scatter(t, 1, 0, c->yb, c->F64, nullptr, c->d, st);
+            launch_tfeti_e(t, c->fi, c->fbeta, c->Cit, c->e, st);
+            launch_small_gemm(c->n_alpha, 1, c->n_alpha, c->GG_inv, c->e, c->tcoef, 1.0, st);
+            HIPCHK(hipMemsetAsync(c->lam0, 0, sizeof(double) * P.n_lambda, st));
+            launch_proj_apply(t, 1, c->tcoef, c->Rb, -1.0, c->lam0, st);
+        }
+        CHECK_LAUNCH();
+    } else if (P.method == FETI_DP) {
+        launch_fbar(t, c->g, c->yc, c->fbar_s, st);
+    }
+}
+
+// r = P (d - F lam)  (FP64), true residual
+void true_residual(feti_ctx* c, const double* lam, double* r) {
+    const int n = c->P.n_lambda;
+    apply_F(c, 1, FETI_FP64, lam, c->Qtmp);
+    launch_axpby(n, 1.0, c->d, 0.0, r, c->st);
+    launch_axpby(n, -1.0, c->Qtmp, 1.0, r, c->st);
+    project(c, 1, r);
+}
+
+void ensure_history(feti_ctx* c, int kd, int need) {
+    const int n = c->P.n_lambda;
+    if (kd != c->hist_kd) {
+        for (double* p : c->hist_chunks) hipFree(p);
+        c->hist_chunks.clear();
+        c->WH.clear();
+        c->QH.clear();
+        c->hist_cap = 0;
+        c->hist_kd = kd;
+    }
+    if (need <= c->hist_cap) return;
+    int newcap = std::max(need, std::max(16, 2 * c->hist_cap));
+    const int add = newcap - c->hist_cap;
+    const long long blk = (long long)n * kd;
+    double* p = nullptr;
+    HIPCHK(hipMalloc(&p, sizeof(double) * blk * 2 * add));
+    c->hist_chunks.push_back(p);
+    for (int i = 0; i < add; ++i) {
+        c->WH.push_back(p + blk * (2ll * i));
+        c->QH.push_back(p + blk * (2ll * i + 1));
+    }
+    c->hist_cap = newcap;
+    // pointer tables (device): rebuild at full size
+    const double** wdev = nullptr;
+    const double** qdev = nullptr;
+    HIPCHK(hipMalloc(&wdev, sizeof(double*) * newcap));
+    HIPCHK(hipMalloc(&qdev, sizeof(double*) * newcap));
+    HIPCHK(hipMemcpy(wdev, c->WH.data(), sizeof(double*) * newcap, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(qdev, c->QH.data(), sizeof(double*) * newcap, hipMemcpyHostToDevice));
+    if (c->WH_dev) {
+        hipStreamSynchronize(c->st);
+        hipFree(c->WH_dev);
+        hipFree(c->QH_dev);
+    }
+    c->WH_dev = wdev;
+    c->QH_dev = qdev;
+    const long long pc = (long long)newcap * kd * kd;
+    if (pc > c->psi_cap) {
+        if (c->Psi) {
+            hipStreamSynchronize(c->st);
+            hipFree(c->Psi);
+        }
+        HIPCHK(hipMalloc(&c->Psi, sizeof(double) * pc));
+        c->psi_cap = pc;
+    }
+}
+
+struct KrylovOut {
+    int iters = 0;
+    int kept = 0;
+    double eps = 0;
+    int status = FETI_OK;
+};
+
+// One pass of PCG on the correction: lt accumulates, r is the residual (updated).
+KrylovOut run_pcg(feti_ctx* c, int prec, double eps0, double tol, int max_it, std::vector<double>& hist) {
+    KrylovOut o;
+    const int n = c->P.n_lambda;
+    hipStream_t st = c->st;
+    const int pf32 = prec != FETI_FP64;
+    precondition(c, c->r, c->zv, 1, pf32);
+    HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    project(c, 1, c->Zk);  // w = P z
+    ddot(c, n, c->r, c->zv, 0);
+    double rz = read_scalar(c, c->scal);
+    o.eps = std::sqrt(std::max(rz, 0.0));
+    if (o.eps <= tol * eps0) return o;
+    for (int it = 0; it < max_it; ++it) {
+        apply_F(c, 1, prec, c->Zk, c->Qk);
+        ddot(c, n, c->Zk, c->Qk, 1);
+        const double wq = read_scalar(c, c->scal + 1);
+        if (!(wq > 0.0)) {
+            o.status = FETI_EBREAKDOWN;
+            break;
+        }
+        const double a = rz / wq;
+        launch_axpby(n, a, c->Zk, 1.0, c->lt, st);
+        project(c, 1, c->Qk);
+        launch_axpby(n, -a, c->Qk, 1.0, c->r, st);
+        precondition(c, c->r, c->zv, 1, pf32);
+        ddot(c, n, c->r, c->zv, 0);
+        const double rz_new = read_scalar(c, c->scal);
+        o.iters = it + 1;
+        o.eps = std::sqrt(std::max(rz_new, 0.0));
+        hist.push_back(o.eps);
+        if (o.eps <= tol * eps0) break;
+        const double beta = rz_new / rz;
+        rz = rz_new;
+        HIPCHK(hipMemcpyAsync(c->Qtmp, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        project(c, 1, c->Qtmp);
+        launch_axpby(n, 1.0, c->Qtmp, beta, c->Zk, st);
+        CHECK_LAUNCH();
+    }
+    return o;
+}
+
+// One pass of Algorithm 1 (simultaneous directions; kd = 1 is full orthogonalisation).
+KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int max_it, std::vector<double>& hist,
+                    std::vector<int>& ranks) {
+    KrylovOut o;
+    const int n = c->P.n_lambda;
+    hipStream_t st = c->st;
+    const int pf32 = prec != FETI_FP64;
+    const int one = kd == 1;
+    const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
+    const int passes = c->opts.reorth == 1 ? 1 : 2;
+    precondition(c, c->r, c->Zk, one, pf32);
+    launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
+    o.eps = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
+    if (o.eps <= tol * eps0) return o;
+    project(c, kd, c->Zk);  // W_0 = P Z_0 (in place)
+    int nb = 0;
+    for (int it = 0; it < max_it && o.kept < n; ++it) {
+        ensure_history(c, kd, nb + 1);
+        double* Wn = (double*)c->WH[nb];
+        double* Qn = (double*)c->QH[nb];
+        apply_F(c, kd, prec, c->Zk, c->Qk);
+        // Delta = Q^T W
+        launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
+        launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st);
+        launch_apply_T(n, kd, c->Tm, c->Zk, c->Qk, Wn, Qn, st);
+        // gamma = W^T r
+        launch_gram(n, kd, 1, c->WH_dev + nb, 1, c->r, c->part, c->gam, st);
+        if (c->P.method == FETI_TFETI) {
+            launch_update_lr(n, kd, Wn, nullptr, c->gam, c->lt, nullptr, st);
+            HIPCHK(hipMemsetAsync(c->tmpv, 0, sizeof(double) * n, st));
+            launch_update_lr(n, kd, Qn, nullptr, c->gam, c->tmpv, nullptr, st);
+            project(c, 1, c->tmpv);
+            launch_axpby(n, -1.0, c->tmpv, 1.0, c->r, st);
+        } else {
+            launch_update_lr(n, kd, Wn, Qn, c->gam, c->lt, c->r, st);
+        }
+        CHECK_LAUNCH();
+        ++nb;
+        precondition(c, c->r, c->Zk, one, pf32);
+        launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
+        project(c, kd, c->Zk);
+        for (int pass = 0; pass < passes; ++pass) {
+            launch_gram(n, kd, kd, c->QH_dev, nb, c->Zk, c->part, c->Psi, st);
+            launch_orth_update(n, kd, c->WH_dev, nb, c->Psi, c->Zk, st);
+        }
+        CHECK_LAUNCH();
+        int rank = 0;
+        double ez = 0;
+        HIPCHK(hipMemcpyAsync(&rank, c->rank_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&ez, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ranks.push_back(rank);
+        o.iters = it + 1;
+        if (rank == 0) {
+            o.status = FETI_EBREAKDOWN;
+            break;
+        }
+        o.kept += rank;
+        o.eps = std::sqrt(std::max(ez, 0.0));
+        hist.push_back(o.eps);
+        if (o.eps <= tol * eps0) break;
+    }
+    return o;
+}
+
+// recovery of u from lambda (c->lam)
+void recover(feti_ctx* c, double* u) {
+    DevTopo& t = c->t;
+    hipStream_t st = c->st;
+    const Plan& P = c->P;
+    const double* alpha = nullptr;
+    if (P.n_lambda > 0)
+        launch_gather_B(t, c->lam, c->xb, st);
+    else if (t.nb_tot)
+        HIPCHK(hipMemsetAsync(c->xb, 0, sizeof(double) * t.nb_tot, st));
+    if (P.method == FETI_DP) {
+        if (P.n_cg > 0) {
+            if (P.n_lambda > 0) {
+                launch_flambda(t, FETI_FP64, 1, c->lam, c->sw64, nullptr, c->Ybuf, c->Tbuf, st);
+                launch_axpby(t.nc_tot, 1.0, c->fbar_s, 1.0, c->Tbuf, st);
+                launch_coarse(t, 1, 0, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->uc, st);
+            } else {
+                launch_coarse(t, 1, 0, c->fbar_s, nullptr, c->Kcc_inv, 1.0, c->uc, st);
+            }
+        }
+        launch_dp_ub(t, c->F64, c->S, c->g, c->xb, c->uc, c->ubeta, st);
+    } else {
+        // alpha = (G G^T)^{-1} G (d - F lambda)
+        apply_F(c, 1, FETI_FP64, c->lam, c->Qtmp);
+        launch_axpby(P.n_lambda, 1.0, c->d, -1.0, c->Qtmp, st);
+        launch_proj_G(t, 1, c->Qtmp, c->Rb, c->GY, st);
+        launch_small_gemm(c->n_alpha, 1, c->n_alpha, c->GG_inv, c->GY, c->alpha, 1.0, st);
+        launch_tfeti_ub(t, c->F64, c->g, c->xb, c->ubeta, st);
+        alpha = c->alpha;
+    }
+    CHECK_LAUNCH();
+    launch_z_gemv(t, c->Z, c->ubeta, c->h, c->ui, st);
+    launch_bt_bsolve1(t, c->L, c->ui, st);
+    launch_assemble_loc(t, c->ui, c->ubeta, c->Cit, alpha, c->uloc, st);
+    launch_average(t, c->uloc, u, st);
+    CHECK_LAUNCH();
+}
+
+feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_init, feti_info* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipEventRecord(c->ev[0], c->st));
+    const Plan& P = c->P;
+    const int n = P.n_lambda;
+    hipStream_t st = c->st;
+    compute_rhs(c, f);
+    std::vector<double> hist;
+    std::vector<int> ranks;
+    KrylovOut tot;
+    int refinements = 0;
+    double eps0 = 0.0, true_rel = 0.0;
+    int status = FETI_OK;
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(c->lam, lam_init ? lam_init : c->lam0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        true_residual(c, c->lam, c->r);
+        const int prec = c->opts.precision;
+        const int kd = c->opts.krylov == FETI_SFETI ? P.n_groups : 1;
+        // eps0 = sqrt(r0^T z0) with the FP64 preconditioner
+        precondition(c, c->r, c->zv, 1, 0);
+        ddot(c, n, c->r, c->zv, 0);
+        eps0 = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
+        hist.push_back(eps0);
+        const double tol = c->opts.tol > 0 ? c->opts.tol : 1e-8;
+        int max_it = c->opts.max_it > 0 ? c->opts.max_it : n;
+        const int max_ref = prec == FETI_FP64 ? 0 : (c->opts.max_refine >= 0 ? c->opts.max_refine : 4);
+        if (eps0 > 0.0) {
+            for (int pass = 0;; ++pass) {
+                HIPCHK(hipMemsetAsync(c->lt, 0, sizeof(double) * n, st));
+                KrylovOut o;
+                const int left = max_it - tot.iters;
+                if (c->opts.krylov == FETI_PCG)
+                    o = run_pcg(c, prec, eps0, tol, left, hist);
+                else
+                    o = run_sfeti(c, prec, kd, eps0, tol, left, hist, ranks);
+                tot.iters += o.iters;
+                tot.kept += o.kept;
+                tot.eps = o.eps;
+                launch_axpby(n, 1.0, c->lt, 1.0, c->lam, st);
+                CHECK_LAUNCH();
+                // FP64 true residual
+                true_residual(c, c->lam, c->r);
+                precondition(c, c->r, c->zv, 1, 0);
+                ddot(c, n, c->r, c->zv, 0);
+                const double et = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
+                true_rel = et / eps0;
+                if (o.status != FETI_OK) {
+                    status = o.status;
+                    break;
+                }
+                if (true_rel <= tol) break;
+                if (pass >= max_ref || tot.iters >= max_it) {
+                    status = FETI_ENOCONV;
+                    break;
+                }
+                ++refinements;
+            }
+        }
+    }
+    recover(c, u);
+    HIPCHK(hipEventRecord(c->ev[1], st));
+    HIPCHK(hipEventSynchronize(c->ev[1]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    c->last_ms[3] = ms;
+    if (info) {
+        info->iters = tot.iters;
+        info->refinements = refinements;
+        info->status = status;
+        info->eps0 = eps0;
+        info->eps = tot.eps;
+        info->true_rel_res = true_rel;
+        info->kept_directions = tot.kept;
+        if (info->res_hist && info->res_hist_cap > 0)
+            for (int i = 0; i < (int)hist.size() && i < info->res_hist_cap; ++i) info->res_hist[i] = hist[i];
+        if (info->rank_hist && info->res_hist_cap > 0)
+            for (int i = 0; i < info->res_hist_cap; ++i) info->rank_hist[i] = i < (int)ranks.size() ? ranks[i] : 0;
+        info->t_solve_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status == FETI_ENOCONV) return fail(FETI_ENOCONV, "iteration limit reached before the tolerance");
+    if (status == FETI_EBREAKDOWN) return fail(FETI_EBREAKDOWN, "Krylov breakdown: no independent search direction");
+    return FETI_OK;
+}
+
+feti_status validate_opts(const feti_opts* o) {
+    if (!o) return fail(FETI_EINVAL, "null options");
+    if (o->scaling != FETI_MULT && o->scaling != FETI_KSCALE) return fail(FETI_EINVAL, "unknown scaling");
+    if (o->krylov != FETI_PCG && o->krylov != FETI_FO && o->krylov != FETI_SFETI) return fail(FETI_EINVAL, "unknown krylov");
+    if (o->precond != FETI_DIRICHLET && o->precond != FETI_LUMPED) return fail(FETI_EINVAL, "unknown preconditioner");
+    if (o->precision != FETI_FP64 && o->precision != FETI_FP32 && o->precision != FETI_BF16X3)
+        return fail(FETI_EINVAL, "unknown precision");
+    if (!(o->tol >= 0.0)) return fail(FETI_EINVAL, "tol must be >= 0");
+    return FETI_OK;
+}
+
+template <typename F>
+feti_status guarded(F&& fn) {
+    try {
+        return fn();
+    } catch (const HipError& e) {
+        return fail(FETI_EHIP, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(FETI_ENOMEM, "host allocation failed");
+    } catch (const std::length_error& e) {
+        return fail(FETI_ENOMEM, e.what());
+    } catch (const std::runtime_error& e) {
+        return fail(FETI_ENOTSPD, e.what());
+    }
+}
+
+}  // namespace
+
+// ===================================================================================== C ABI
+extern "C" {
+
+const char* feti_last_error(void) { return g_err.c_str(); }
+
+feti_status feti_plan_sizes(const feti_mesh* mesh, const feti_partition* part, const feti_opts* opts,
+                            feti_sizes* out) {
+    if (!out) return fail(FETI_EINVAL, "null output");
+    try {
+        Plan P;
+        std::string err = build_plan(mesh, part, opts, P);
+        if (!err.empty()) return fail(FETI_EINVAL, err);
+        feti_sizes z{};
+        z.n_sub = P.n_sub;
+        z.n_dof = P.n_dof;
+        z.n_el = P.n_el;
+        z.n_lambda = P.n_lambda;
+        z.n_cg = P.n_cg;
+        z.n_alpha = P.n_alpha;
+        z.n_groups = P.n_groups;
+        z.nb_min = P.n_sub ? *std::min_element(P.n_b.begin(), P.n_b.end()) : 0;
+        z.nb_max = P.n_sub ? *std::max_element(P.n_b.begin(), P.n_b.end()) : 0;
+        z.n_loc_max = P.n_sub ? *std::max_element(P.n_loc.begin(), P.n_loc.end()) : 0;
+        z.n_i_max = P.n_sub ? *std::max_element(P.n_i.begin(), P.n_i.end()) : 0;
+        z.band_max = P.n_sub ? *std::max_element(P.band.begin(), P.band.end()) : 0;
+        z.sum_nb2 = P.sum_nb2();
+        z.sum_nb_nc = P.sum_nb_nc();
+        *out = z;
+        return FETI_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(FETI_ENOMEM, "host allocation failed");
+    }
+}
+
+feti_status feti_plan_export(const feti_mesh* mesh, const feti_partition* part, const feti_opts* opts, int what,
+                             int* out, long long cap, long long* n_out) {
+    try {
+        Plan P;
+        std::string err = build_plan(mesh, part, opts, P);
+        if (!err.empty()) return fail(FETI_EINVAL, err);
+        std::vector<int> v;
+        if (what == 0) {
+            for (int r = 0; r < P.n_lambda; ++r)
+                for (int t = 0; t < 2; ++t) {
+                    const int s = P.row_s[2 * r + t];
+                    v.push_back(s);
+                    v.push_back(s >= 0 ? P.b_loc[P.off_b[s] + P.row_j[2 * r + t]] : -1);
+                    v.push_back(P.row_sg[2 * r + t]);
+                }
+        } else if (what == 1) {
+            for (int s = 0; s < P.n_sub; ++s) {
+                v.push_back(P.n_loc[s]);
+                v.push_back(P.n_i[s]);
+                v.push_back(P.n_b[s]);
+                v.push_back(P.n_c[s]);
+                v.push_back(P.band[s]);
+            }
+        } else if (what == 2) {
+            v = P.corner_dofs;
+        } else {
+            return fail(FETI_EINVAL, "unknown export");
+        }
+        if (n_out) *n_out = (long long)v.size();
+        if ((long long)v.size() > cap) return fail(FETI_EINVAL, "output capacity too small");
+        if (out && !v.empty()) memcpy(out, v.data(), sizeof(int) * v.size());
+        return FETI_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(FETI_ENOMEM, "host allocation failed");
+    }
+}
+
+feti_status feti_setup(const feti_mesh* mesh, const feti_partition* part, const feti_opts* opts, const double* rho,
+                       double p, double E0, double Emin, void* stream, feti_ctx** out) {
+    if (!out) return fail(FETI_EINVAL, "null output");
+    *out = nullptr;
+    feti_status vs = validate_opts(opts);
+    if (vs != FETI_OK) return vs;
+    if (!(p >= 1.0) || !(E0 > 0.0) || !(Emin > 0.0) || !(Emin < E0))
+        return fail(FETI_EINVAL, "need p >= 1 and 0 < Emin < E0");
+    if (!rho) return fail(FETI_EINVAL, "null density array");
+    std::unique_ptr<feti_ctx> c(new feti_ctx());
+    std::string err = build_plan(mesh, part, opts, c->P);
+    if (!err.empty()) return fail(FETI_EINVAL, err);
+    if (opts->krylov == FETI_SFETI && c->P.n_groups > kMaxDirs)
+        return fail(FETI_EINVAL, "more than 64 simultaneous directions: set partition.group");
+    c->opts = *opts;
+    c->p = p;
+    c->E0 = E0;
+    c->Emin = Emin;
+    c->st = (hipStream_t)stream;
+    feti_status rs = guarded([&]() -> feti_status {
+        build_layout(c.get());
+        HIPCHK(hipMemcpyAsync(c->rho, rho, sizeof(double) * c->P.n_el, hipMemcpyDeviceToDevice, c->st));
+        numeric_setup(c.get());
+        return FETI_OK;
+    });
+    if (rs != FETI_OK) return rs;
+    *out = c.release();
+    return FETI_OK;
+}
+
+feti_status feti_update_rho(feti_ctx* c, const double* rho) {
+    if (!c || !rho) return fail(FETI_EINVAL, "null argument");
+    return guarded([&]() -> feti_status {
+        HIPCHK(hipMemcpyAsync(c->rho, rho, sizeof(double) * c->P.n_el, hipMemcpyDeviceToDevice, c->st));
+        numeric_setup(c);
+        return FETI_OK;
+    });
+}
+
+feti_status feti_solve(feti_ctx* c, const double* f, double* u, const double* lambda_init, feti_info* info) {
+    if (!c || !f || !u) return fail(FETI_EINVAL, "null argument");
+    return guarded([&]() -> feti_status { return do_solve(c, f, u, lambda_init, info); });
+}
+
+feti_status feti_compliance_and_grad(feti_ctx* c, const double* rho, const double* f, double* cval, double* dc,
+                                     double* u, feti_info* info) {
+    if (!c || !cval || !dc) return fail(FETI_EINVAL, "null argument");
+    if (!f && !c->have_f) return fail(FETI_EINVAL, "no load given and none stored");
+    return guarded([&]() -> feti_status {
+        if (rho) {
+            HIPCHK(hipMemcpyAsync(c->rho, rho, sizeof(double) * c->P.n_el, hipMemcpyDeviceToDevice, c->st));
+            numeric_setup(c);
+        }
+        double* uu = u ? u : c->u_int;
+        feti_status s = do_solve(c, f ? f : c->f_last, uu, nullptr, info);
+        if (s != FETI_OK && s != FETI_ENOCONV) return s;
+        launch_compliance(c->t, c->f_last, uu, c->rho, c->p, c->E0, c->Emin, c->part, cval, dc, c->st);
+        CHECK_LAUNCH();
+        return s;
+    });
+}
+
+feti_status feti_destroy(feti_ctx* c) {
+    if (!c) return FETI_OK;
+    delete c;
+    return FETI_OK;
+}
+
+feti_status feti_get_sizes(feti_ctx* c, feti_sizes* out) {
+    if (!c || !out) return fail(FETI_EINVAL, "null argument");
+    const Plan& P = c->P;
+    feti_sizes z{};
+    z.n_sub = P.n_sub;
+    z.n_dof = P.n_dof;
+    z.n_el = P.n_el;
+    z.n_lambda = P.n_lambda;
+    z.n_cg = P.n_cg;
+    z.n_alpha = P.n_alpha;
+    z.n_groups = P.n_groups;
+    z.nb_min = *std::min_element(P.n_b.begin(), P.n_b.end());
+    z.nb_max = *std::max_element(P.n_b.begin(), P.n_b.end());
+    z.n_loc_max = *std::max_element(P.n_loc.begin(), P.n_loc.end());
+    z.n_i_max = *std::max_element(P.n_i.begin(), P.n_i.end());
+    z.band_max = *std::max_element(P.band.begin(), P.band.end());
+    z.sum_nb2 = P.sum_nb2();
+    z.sum_nb_nc = P.sum_nb_nc();
+    z.device_bytes = c->bytes;
+    *out = z;
+    return FETI_OK;
+}
+
+feti_status feti_apply_F(feti_ctx* c, int k, int precision, const double* Lambda, double* Q) {
+    if (!c || !Lambda || !Q) return fail(FETI_EINVAL, "null argument");
+    if (k < 1 || k > kMaxDirs) return fail(FETI_EINVAL, "k must lie in [1, 64]");
+    if (precision != FETI_FP64 && precision != FETI_FP32 && precision != FETI_BF16X3)
+        return fail(FETI_EINVAL, "unknown precision");
+    return guarded([&]() -> feti_status {
+        HIPCHK(hipEventRecord(c->ev[0], c->st));
+        apply_F(c, k, precision, Lambda, Q, true);
+        HIPCHK(hipEventRecord(c->ev[1], c->st));
+        HIPCHK(hipEventSynchronize(c->ev[1]));
+        float a = 0, b = 0;
+        HIPCHK(hipEventElapsedTime(&a, c->ev[2], c->ev[3]));
+        HIPCHK(hipEventElapsedTime(&b, c->ev[0], c->ev[1]));
+        c->last_ms[0] = a;
+        c->last_ms[1] = b;
+        return FETI_OK;
+    });
+}
+
+feti_status feti_apply_precond(feti_ctx* c, const double* r, double* Z, int one_column) {
+    if (!c || !r || !Z) return fail(FETI_EINVAL, "null argument");
+    return guarded([&]() -> feti_status {
+        precondition(c, r, Z, one_column, 0);
+        return FETI_OK;
+    });
+}
+
+feti_status feti_project(feti_ctx* c, int k, double* Y) {
+    if (!c || !Y) return fail(FETI_EINVAL, "null argument");
+    if (k < 1 || k > kMaxDirs) return fail(FETI_EINVAL, "k must lie in [1, 64]");
+    return guarded([&]() -> feti_status {
+        project(c, k, Y);
+        return FETI_OK;
+    });
+}
+
+feti_status feti_rhs(feti_ctx* c, const double* f, double* d, double* lambda0) {
+    if (!c || !f) return fail(FETI_EINVAL, "null argument");
+    return guarded([&]() -> feti_status {
+        compute_rhs(c, f);
+        const int n = c->P.n_lambda;
+        if (n > 0) {
+            if (d) HIPCHK(hipMemcpyAsync(d, c->d, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+            if (lambda0) HIPCHK(hipMemcpyAsync(lambda0, c->lam0, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+        }
+        return FETI_OK;
+    });
+}
+
+feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long cap, int* rows, int* cols) {
+    if (!c || !out || !rows || !cols) return fail(FETI_EINVAL, "null argument");
+    const Plan& P = c->P;
+    if (what <= 3 || what == 6)
+        if (s < 0 || s >= P.n_sub) return fail(FETI_EINVAL, "subdomain out of range");
+    return guarded([&]() -> feti_status {
+        HIPCHK(hipStreamSynchronize(c->st));
+        std::vector<double> v;
+        int nr = 0, nc = 0;
+        auto fetch = [&](const double* src, long long n) {
+            v.resize(n);
+            if (n) HIPCHK(hipMemcpy(v.data(), src, sizeof(double) * n, hipMemcpyDeviceToHost));
+        };
+        if (what == 0 || what == 2) {
+            const SubMeta& M = c->hsubs[s];
+            std::vector<double> F;
+            const long long n = (long long)M.rows_F * M.ldF;
+            F.resize(n);
+            HIPCHK(hipMemcpy(F.data(), c->F64 + M.off_F, sizeof(double) * n, hipMemcpyDeviceToHost));
+            if (what == 0) {
+                nr = nc = M.n_b;
+                for (int i = 0; i < M.n_b; ++i)
+                    for (int j = 0; j < M.n_b; ++j) v.push_back(F[(long long)i * M.ldF + j]);
+            } else {
+                nr = M.n_b;
+                nc = M.n_c;
+                for (int j = 0; j < M.n_b; ++j)
+                    for (int q = 0; q < M.n_c; ++q) v.push_back(F[(long long)(M.n_b + q) * M.ldF + j]);
+            }
+        } else if (what == 1) {
+            const SubMeta& M = c->hsubs[s];
+            nr = nc = M.n_b;
+            fetch(c->P64 + M.off_P, (long long)M.n_b * M.n_b);
+        } else if (what == 3) {
+            const SubMeta& M = c->hsubs[s];
+            nr = nc = M.n_c;
+            fetch(c->Kc + M.off_Kc, (long long)M.n_c * M.n_c);
+        } else if (what == 4) {
+            nr = P.n_lambda;
+            nc = 2;
+            fetch(c->w, 2ll * P.n_lambda);
+        } else if (what == 5) {
+            nr = nc = P.n_cg;
+            fetch(c->Kcc, (long long)P.n_cg * P.n_cg);
+        } else if (what == 6) {
+            const SubMeta& M = c->hsubs[s];
+            nr = M.n_loc;
+            nc = 1;
+            fetch(c->diag + M.off_loc, M.n_loc);
+        } else {
+            return fail(FETI_EINVAL, "unknown matrix");
+        }
+        *rows = nr;
+        *cols = nc;
+        if ((long long)v.size() > cap) return fail(FETI_EINVAL, "output capacity too small");
+        if (!v.empty()) memcpy(out, v.data(), sizeof(double) * v.size());
+        return FETI_OK;
+    });
+}
+
+feti_status feti_last_timing(feti_ctx* c, int what, double* ms) {
+    if (!c || !ms || what < 0 || what > 3) return fail(FETI_EINVAL, "bad argument");
+    *ms = c->last_ms[what];
+    return FETI_OK;
+}
+
+}  // extern "C"

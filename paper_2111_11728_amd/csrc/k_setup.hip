@@ -1,0 +1,636 @@
+// Setup kernels: SIMP assembly of the subdomain stiffness blocks, block-tridiagonal
+// Cholesky of the interior blocks, the interface Schur complement, explicit local dual
+// operators F_s, preconditioner blocks, scaling weights and coarse matrices.
+#include "dense_wg.hpp"
+#include "kernels.hpp"
+
+namespace feti {
+
+__constant__ double c_K0[24 * 24];
+
+// ---------------------------------------------------------------------------------------
+// Assembly (Sec. 1 Eq. 1 and Sec. 2 Eq. 3): K^s = sum_e (Emin + rho_e^p (E0 - Emin)) K0.
+// One thread per (subdomain, local node a); it forms every dpn x dpn block K_ab with its
+// 3^dim neighbours b and routes each entry by the classes of its two DOFs:
+//   (i, i) -> block-tridiagonal storage of K_ii (diagonal and sub-diagonal line blocks),
+//   (i, beta) -> Z (becomes L^{-1} K_i,beta), (beta, beta) -> S (becomes the Schur complement),
+//   diagonal -> diag (k-scaling). Each entry has exactly one writer: no atomics.
+__global__ void k_assemble(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines, int dim,
+                           int nelx, int nely, const double* __restrict__ rho, double p, double E0,
+                           double Emin, const int8_t* __restrict__ lcls, const int* __restrict__ lidx,
+                           double* __restrict__ Lbuf, double* __restrict__ Zbuf, double* __restrict__ Sbuf,
+                           double* __restrict__ diag) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int nnodes = M.nn[0] * M.nn[1] * M.nn[2];
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nnodes) return;
+    const int dpn = dim, ne = dpn << dim;  // element DOFs
+    const int ax = a % M.nn[0], ay = (a / M.nn[0]) % M.nn[1], az = a / (M.nn[0] * M.nn[1]);
+    const int ex_max = M.nn[0] - 1, ey_max = M.nn[1] - 1, ez_max = dim == 3 ? M.nn[2] - 1 : 1;
+    const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+    const int line_a = dim == 2 ? ay : az;
+    for (int dz = zlo; dz <= zhi; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int bx = ax + dx, by = ay + dy, bz = az + dz;
+                if (bx < 0 || by < 0 || bz < 0 || bx >= M.nn[0] || by >= M.nn[1] || bz >= M.nn[2]) continue;
+                const int b = bx + M.nn[0] * (by + M.nn[1] * bz);
+                double blk[9];
+                for (int q = 0; q < 9; ++q) blk[q] = 0.0;
+                // elements containing both nodes
+                const int ex0 = max(max(ax, bx) - 1, 0), ex1 = min(min(ax, bx), ex_max - 1);
+                const int ey0 = max(max(ay, by) - 1, 0), ey1 = min(min(ay, by), ey_max - 1);
+                const int ez0 = dim == 3 ? max(max(az, bz) - 1, 0) : 0;
+                const int ez1 = dim == 3 ? min(min(az, bz), ez_max - 1) : 0;
+                for (int ez = ez0; ez <= ez1; ++ez)
+                    for (int ey = ey0; ey <= ey1; ++ey)
+                        for (int ex = ex0; ex <= ex1; ++ex) {
+                            const int ca = (ax - ex) + 2 * (ay - ey) + (dim == 3 ? 4 * (az - ez) : 0);
+                            const int cb = (bx - ex) + 2 * (by - ey) + (dim == 3 ? 4 * (bz - ez) : 0);
+                            const long long ge = (long long)(M.lo[0] + ex) +
+                                                 (long long)nelx * ((M.lo[1] + ey) + (long long)nely * (M.lo[2] + ez));
+                            const double E = Emin + pow(rho[ge], p) * (E0 - Emin);
+                            for (int ci = 0; ci < dpn; ++ci)
+                                for (int cj = 0; cj < dpn; ++cj)
+                                    blk[ci * dpn + cj] += E * c_K0[(ca * dpn + ci) * ne + cb * dpn + cj];
+                        }
+                const int line_b = dim == 2 ? by : bz;
+                for (int ci = 0; ci < dpn; ++ci) {
+                    const long long pl = M.off_loc + (long long)a * dpn + ci;
+                    const int cp = lcls[pl], ip = lidx[pl];
+                    for (int cj = 0; cj < dpn; ++cj) {
+                        const long long ql = M.off_loc + (long long)b * dpn + cj;
+                        const double v = blk[ci * dpn + cj];
+                        if (pl == ql) diag[pl] = v;
+                        const int cq = lcls[ql], iq = lidx[ql];
+                        if (cp == CLS_X || cq == CLS_X) continue;
+                        if (cp == CLS_I) {
+                            if (cq == CLS_I) {
+                                const LineMeta La = lines[M.line0 + line_a];
+                                if (line_a == line_b) {
+                                    Lbuf[La.off_diag + (long long)(ip - La.i0) * La.n + (iq - La.i0)] = v;
+                                } else if (line_b == line_a - 1) {
+                                    const int i0b = La.i0 - La.n_prev;
+                                    Lbuf[La.off_sub + (long long)(ip - La.i0) * La.n_prev + (iq - i0b)] = v;
+                                }
+                            } else {
+                                const int jb = cq == CLS_B ? iq : M.n_b + iq;
+                                Zbuf[M.off_Z + (long long)ip * M.n_beta + jb] = v;
+                            }
+                        } else if (cq != CLS_I) {
+                            const int jp = cp == CLS_B ? ip : M.n_b + ip;
+                            const int jq = cq == CLS_B ? iq : M.n_b + iq;
+                            Sbuf[M.off_S + (long long)jp * M.n_beta + jq] = v;
+                        }
+                    }
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------------------
+// Block-tridiagonal Cholesky of K_ii, one workgroup per subdomain, blocks = grid lines
+// (2D) or planes (3D): D_k = A_kk - L_{k,k-1} L_{k,k-1}^T = L_kk L_kk^T,
+// L_{k+1,k} = A_{k+1,k} L_kk^{-T}.
+__global__ void __launch_bounds__(256) k_bt_factor(const SubMeta* __restrict__ subs,
+                                                   const LineMeta* __restrict__ lines, double* Lbuf,
+                                                   int* info) {
+    __shared__ double lds[kLdsDoubles];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    for (int k = 0; k < M.n_lines; ++k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        double* D = Lbuf + Lk.off_diag;
+        if (Lk.n_prev > 0) {
+            const double* Ls = Lbuf + Lk.off_sub;
+            wg_gemm_sub(Lk.n, Lk.n, Lk.n_prev, Ls, Lk.n_prev, 1, Ls, 1, Lk.n_prev, D, Lk.n, 1, true, lds);
+        }
+        const int r = wg_potrf(Lk.n, D, Lk.n, lds);
+        if (r) {
+            if (threadIdx.x == 0) info[s] = Lk.i0 + r;
+            return;
+        }
+        if (k + 1 < M.n_lines) {
+            const LineMeta Ln = lines[M.line0 + k + 1];
+            if (Ln.n > 0) {
+                // X = A_{k+1,k} L_kk^{-T}: solve L_kk X^T = A^T in place (X^T(i, c) = X[c][i])
+                wg_trsm_lower(Lk.n, Ln.n, D, Lk.n, Lbuf + Ln.off_sub, 1, Lk.n, lds);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Z <- L^{-1} Z for one chunk of 64 columns of Z = K_i,beta (row-major n_i x n_beta).
+__global__ void __launch_bounds__(256) k_bt_forward(const SubMeta* __restrict__ subs,
+                                                    const LineMeta* __restrict__ lines,
+                                                    const double* __restrict__ Lbuf, double* Zbuf) {
+    __shared__ double lds[kLdsDoubles];
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int c0 = blockIdx.x * 64;
+    if (c0 >= M.n_beta || M.n_i == 0) return;
+    const int nc = min(64, M.n_beta - c0);
+    double* Z = Zbuf + M.off_Z + c0;
+    for (int k = 0; k < M.n_lines; ++k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        double* Zk = Z + (long long)Lk.i0 * M.n_beta;
+        if (Lk.n_prev > 0) {
+            const double* Zp = Z + (long long)(Lk.i0 - Lk.n_prev) * M.n_beta;
+            wg_gemm_sub(Lk.n, nc, Lk.n_prev, Lbuf + Lk.off_sub, Lk.n_prev, 1, Zp, M.n_beta, 1, Zk, M.n_beta, 1,
+                        false, lds);
+        }
+        wg_trsm_lower(Lk.n, nc, Lbuf + Lk.off_diag, Lk.n, Zk, M.n_beta, 1, lds);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched C = beta C + alpha A^T B (A: k x m, B: k x n, row-major), 64x64 tiles per
+// workgroup. symmetric: only tiles on or below the diagonal are computed and each is
+// written to both (i, j) and (j, i) (requires A == B).
+__global__ void __launch_bounds__(256) k_gemm_tn(const GemmDesc* __restrict__ desc, const double* Abase,
+                                                 const double* Bbase, double* Cbase, double alpha,
+                                                 double beta, int symmetric) {
+    __shared__ double As[16 * 64];
+    __shared__ double Bs[16 * 64];
+    const GemmDesc d = desc[blockIdx.y];
+    const int tn = (d.n + 63) / 64;
+    const int ti = blockIdx.x / tn, tj = blockIdx.x % tn;
+    if (ti * 64 >= d.m) return;
+    if (symmetric && tj > ti) return;
+    const double* A = Abase + d.a;
+    const double* B = Bbase + d.b;
+    double* C = Cbase + d.c;
+    const int i0 = ti * 64, j0 = tj * 64;
+    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int k0 = 0; k0 < d.k; k0 += 16) {
+        for (int e = tid; e < 16 * 64; e += 256) {
+            const int kk = e >> 6, ii = e & 63;
+            const bool kin = k0 + kk < d.k;
+            As[e] = (kin && i0 + ii < d.m) ? A[(long long)(k0 + kk) * d.lda + i0 + ii] : 0.0;
+            Bs[e] = (kin && j0 + ii < d.n) ? B[(long long)(k0 + kk) * d.ldb + j0 + ii] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk * 64 + tr * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[kk * 64 + tc * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + tr * 4 + r, j = j0 + tc * 4 + c;
+            if (i >= d.m || j >= d.n) continue;
+            if (symmetric && j > i) continue;
+            double* dst = C + (long long)i * d.ldc + j;
+            *dst = beta == 0.0 ? alpha * acc[r][c] : beta * *dst + alpha * acc[r][c];
+            if (symmetric && i != j) {
+                double* dt = C + (long long)j * d.ldc + i;
+                *dt = beta == 0.0 ? alpha * acc[r][c] : beta * *dt + alpha * acc[r][c];
+            }
+        }
+}
+
+// Batched in-place Cholesky (one workgroup per matrix).
+__global__ void __launch_bounds__(256) k_potrf(const PotrfDesc* __restrict__ desc, double* base, int* info) {
+    __shared__ double lds[kLdsDoubles];
+    const PotrfDesc d = desc[blockIdx.x];
+    const int r = wg_potrf(d.n, base + d.a, d.lda, lds);
+    if (threadIdx.x == 0) info[blockIdx.x] = r;
+}
+
+// Batched B <- L^{-1} B, one workgroup per (matrix, chunk of 64 columns of B).
+__global__ void __launch_bounds__(256) k_trsm(const TrsmDesc* __restrict__ desc, const double* Lbase,
+                                              double* Bbase) {
+    __shared__ double lds[kLdsDoubles];
+    const TrsmDesc d = desc[blockIdx.y];
+    const int c0 = blockIdx.x * 64;
+    if (c0 >= d.ncols) return;
+    const int nc = min(64, d.ncols - c0);
+    wg_trsm_lower(d.n, nc, Lbase + d.l, d.ldl, Bbase + d.b + c0, d.ldb, 1, lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// Element-wise helpers on per-subdomain square blocks.
+
+// dst[s] (n_b x n_b, ld n_b) = S_bb of subdomain s (the leading block of S, ld n_beta);
+// identity != 0 writes the identity instead.
+__global__ void k_copy_Sbb(const SubMeta* __restrict__ subs, const double* __restrict__ Sbuf, double* dst,
+                           int identity) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const long long nn = (long long)M.n_b * M.n_b;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / M.n_b), j = (int)(e % M.n_b);
+        dst[M.off_P + e] = identity ? (i == j ? 1.0 : 0.0) : Sbuf[M.off_S + (long long)i * M.n_beta + j];
+    }
+}
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long long n) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        dst[e] = (float)src[e];
+}
+
+// ---------------------------------------------------------------------------------------
+// TFETI: rigid-body modes restricted to the interface DOFs b, orthonormalised
+// (Rhat_b = R_b C^{-T}, C C^T = R_b^T R_b), and the regularised matrix
+// W = S_bb + tau Rhat Rhat^T whose inverse gives the pseudo-inverse
+// S_bb^+ = W^{-1} - Rhat Rhat^T / tau (exact when S_bb R_b = 0).
+__device__ inline void rbm_row(int dim, int comp, double x, double y, double z, double* r) {
+    // translations, then rotations about z, x, y: (-y, x, 0), (0, -z, y), (z, 0, -x)
+    const int nm = dim == 2 ? 3 : 6;
+    for (int m = 0; m < nm; ++m) r[m] = 0.0;
+    r[comp] = 1.0;
+    if (dim == 2) {
+        r[2] = comp == 0 ? -y : x;
+    } else {
+        r[3] = comp == 0 ? -y : (comp == 1 ? x : 0.0);
+        r[4] = comp == 1 ? -z : (comp == 2 ? y : 0.0);
+        r[5] = comp == 0 ? z : (comp == 2 ? -x : 0.0);
+    }
+}
+
+__device__ inline void local_dof_coords(const SubMeta& M, int dim, int l, int* comp, double* x, double* y,
+                                        double* z) {
+    const int node = l / dim;
+    *comp = l % dim;
+    const int ix = node % M.nn[0], iy = (node / M.nn[0]) % M.nn[1], iz = node / (M.nn[0] * M.nn[1]);
+    *x = ix - 0.5 * (M.nn[0] - 1);
+    *y = iy - 0.5 * (M.nn[1] - 1);
+    *z = iz - 0.5 * (M.nn[2] - 1);
+}
+
+__global__ void __launch_bounds__(256) k_tfeti_rbm(const SubMeta* __restrict__ subs, int dim,
+                                                   const int* __restrict__ b_loc, const double* __restrict__ Sbuf,
+                                                   double* Rb, double* Cit, double* tau, double* Wbuf) {
+    __shared__ double red[256][21];
+    __shared__ double Gm[36], Ci[36];
+    __shared__ double tsum[256];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int nm = dim == 2 ? 3 : 6;
+    const int tid = threadIdx.x;
+    double g[21];
+    for (int q = 0; q < 21; ++q) g[q] = 0.0;
+    double dsum = 0.0;
+    for (int j = tid; j < M.n_b; j += 256) {
+        int comp;
+        double x, y, z, r[6];
+        local_dof_coords(M, dim, b_loc[M.off_b + j], &comp, &x, &y, &z);
+        rbm_row(dim, comp, x, y, z, r);
+        int q = 0;
+        for (int a = 0; a < nm; ++a)
+            for (int b = 0; b <= a; ++b) g[q++] += r[a] * r[b];
+        dsum += Sbuf[M.off_S + (long long)j * M.n_beta + j];
+    }
+    for (int q = 0; q < 21; ++q) red[tid][q] = g[q];
+    tsum[tid] = dsum;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int u = 0; u < 256; ++u) t += tsum[u];
+        tau[s] = t / M.n_b;
+        int q = 0;
+        for (int a = 0; a < nm; ++a)
+            for (int b = 0; b <= a; ++b) {
+                double v = 0.0;
+                for (int u = 0; u < 256; ++u) v += red[u][q];
+                Gm[a * nm + b] = v;
+                Gm[b * nm + a] = v;
+                ++q;
+            }
+        // Cholesky Gm = C C^T (lower), then Ci = C^{-T} (upper)
+        double C[36];
+        for (int a = 0; a < nm; ++a)
+            for (int b = 0; b < nm; ++b) C[a * nm + b] = 0.0;
+        for (int j = 0; j < nm; ++j) {
+            double d = Gm[j * nm + j];
+            for (int k = 0; k < j; ++k) d -= C[j * nm + k] * C[j * nm + k];
+            d = sqrt(d);
+            C[j * nm + j] = d;
+            for (int i = j + 1; i < nm; ++i) {
+                double v = Gm[i * nm + j];
+                for (int k = 0; k < j; ++k) v -= C[i * nm + k] * C[j * nm + k];
+                C[i * nm + j] = v / d;
+            }
+        }
+        // inverse of lower C, then transpose
+        double Inv[36];
+        for (int c = 0; c < nm; ++c)
+            for (int i = 0; i < nm; ++i) {
+                double v = i == c ? 1.0 : 0.0;
+                for (int k = 0; k < i; ++k) v -= C[i * nm + k] * Inv[k * nm + c];
+                Inv[i * nm + c] = v / C[i * nm + i];
+            }
+        for (int a = 0; a < nm; ++a)
+            for (int b = 0; b < nm; ++b) {
+                Ci[a * nm + b] = Inv[b * nm + a];
+                Cit[s * 36 + a * nm + b] = Inv[b * nm + a];
+            }
+    }
+    __syncthreads();
+    for (int j = tid; j < M.n_b; j += 256) {
+        int comp;
+        double x, y, z, r[6];
+        local_dof_coords(M, dim, b_loc[M.off_b + j], &comp, &x, &y, &z);
+        rbm_row(dim, comp, x, y, z, r);
+        for (int m = 0; m < nm; ++m) {
+            double v = 0.0;
+            for (int a = 0; a < nm; ++a) v += r[a] * Ci[a * nm + m];
+            Rb[M.off_R + (long long)j * nm + m] = v;
+        }
+    }
+    __syncthreads();
+    const double t = tau[s];
+    const long long nn = (long long)M.n_b * M.n_b;
+    for (long long e = tid; e < nn; e += 256) {
+        const int i = (int)(e / M.n_b), j = (int)(e % M.n_b);
+        double v = 0.0;
+        for (int m = 0; m < nm; ++m) v += Rb[M.off_R + (long long)i * nm + m] * Rb[M.off_R + (long long)j * nm + m];
+        Wbuf[M.off_P + e] = Sbuf[M.off_S + (long long)i * M.n_beta + j] + t * v;
+    }
+}
+
+// F_s -= Rhat Rhat^T / tau (TFETI pseudo-inverse correction).
+__global__ void k_tfeti_fix(const SubMeta* __restrict__ subs, int nm, const double* __restrict__ Rb,
+                            const double* __restrict__ tau, double* F64) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const long long nn = (long long)M.n_b * M.n_b;
+    const double it = 1.0 / tau[s];
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / M.n_b), j = (int)(e % M.n_b);
+        double v = 0.0;
+        for (int m = 0; m < nm; ++m) v += Rb[M.off_R + (long long)i * nm + m] * Rb[M.off_R + (long long)j * nm + m];
+        F64[M.off_F + (long long)i * M.ldF + j] -= it * v;
+    }
+}
+
+// FETI-DP: F_rc^T = S_cb F_s (rows n_b.. of the augmented operator) and
+// Kbar_cc^s = S_cc - S_cb F_s S_bc (eliminating b after i from the interface Schur complement).
+__global__ void __launch_bounds__(256) k_frc(const SubMeta* __restrict__ subs, const double* __restrict__ Sbuf,
+                                             double* F64, double* Kc) {
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int nb = M.n_b, nc = M.n_c;
+    if (nc == 0) return;
+    const double* S = Sbuf + M.off_S;
+    double* F = F64 + M.off_F;
+    for (long long e = threadIdx.x; e < (long long)nc * nb; e += 256) {
+        const int c = (int)(e / nb), j = (int)(e % nb);
+        double v = 0.0;
+        for (int q = 0; q < nb; ++q) v += S[(long long)(nb + c) * M.n_beta + q] * F[(long long)q * M.ldF + j];
+        F[(long long)(nb + c) * M.ldF + j] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * nc; e += 256) {
+        const int c = e / nc, c2 = e % nc;
+        double v = S[(long long)(nb + c) * M.n_beta + nb + c2];
+        for (int j = 0; j < nb; ++j) v -= F[(long long)(nb + c) * M.ldF + j] * S[(long long)j * M.n_beta + nb + c2];
+        Kc[M.off_Kc + e] = v;
+    }
+}
+
+// MFMA operand layouts of the augmented operator A_s = [F_s; F_rc^T] (rows_F x ldF):
+//  FP64 / FP32 (16x16x4 MFMA): element ((rb*KQ + kq)*64 + lane)*4 + q holds
+//      A[16 rb + lane%16][16 kq + 4 q + lane/16],  KQ = ldF/16;
+//  BF16 (16x16x32 MFMA): element ((rb*KB + kb)*64 + lane)*8 + q holds
+//      A[16 rb + lane%16][32 kb + 8 (lane/16) + q],  KB = ldF/32;
+// stored as a hi part (round to nearest) and a lo part (the rounded remainder).
+__global__ void k_swizzle(const SubMeta* __restrict__ subs, const double* __restrict__ F64, double* sw64,
+                          float* sw32, __hip_bfloat16* swhi, __hip_bfloat16* swlo) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const long long tot = (long long)M.rows_F * M.ldF;
+    const int KQ = M.ldF / 16, KB = M.ldF / 32;
+    const int nrow = M.n_b + M.n_c;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+        {
+            const int q = (int)(e & 3), lane = (int)((e >> 2) & 63);
+            const long long blk = e >> 8;
+            const int rb = (int)(blk / KQ), kq = (int)(blk % KQ);
+            const int row = 16 * rb + (lane & 15), col = 16 * kq + 4 * q + (lane >> 4);
+            const double v = (row < nrow && col < M.n_b) ? F64[M.off_F + (long long)row * M.ldF + col] : 0.0;
+            sw64[M.off_Fsw + e] = v;
+            sw32[M.off_Fsw + e] = (float)v;
+        }
+        {
+            const int q = (int)(e & 7), lane = (int)((e >> 3) & 63);
+            const long long blk = e >> 9;
+            const int rb = (int)(blk / KB), kb = (int)(blk % KB);
+            const int row = 16 * rb + (lane & 15), col = 32 * kb + 8 * (lane >> 4) + q;
+            const double v = (row < nrow && col < M.n_b) ? F64[M.off_F + (long long)row * M.ldF + col] : 0.0;
+            const float vf = (float)v;
+            const __hip_bfloat16 hi = __float2bfloat16(vf);
+            const __hip_bfloat16 lo = __float2bfloat16(vf - __bfloat162float(hi));
+            swhi[M.off_Fsw + e] = hi;
+            swlo[M.off_Fsw + e] = lo;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Scaling weights (Sec. 3.1): per lambda row and side. Dirichlet rows: 1. Multiplicity:
+// 1/m. k-scaling (Eq. 15, multi-domain form): the weight of side a is K^b_jj / sum_q K^q_jj
+// with the sum over every subdomain sharing the DOF.
+__global__ void k_weights(int n_lambda, int kscale, const int* __restrict__ row_s, const int* __restrict__ row_j,
+                          const int* __restrict__ row_sh, const int* __restrict__ sh_ptr,
+                          const int* __restrict__ sh_s, const int* __restrict__ sh_l,
+                          const SubMeta* __restrict__ subs, const int* __restrict__ b_loc,
+                          const double* __restrict__ diag, double* w) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_lambda) return;
+    const int sh = row_sh[r];
+    if (sh < 0) {
+        w[2 * r] = 1.0;
+        w[2 * r + 1] = 0.0;
+        return;
+    }
+    const int m = sh_ptr[sh + 1] - sh_ptr[sh];
+    if (!kscale) {
+        w[2 * r] = 1.0 / m;
+        w[2 * r + 1] = 1.0 / m;
+        return;
+    }
+    double tot = 0.0;
+    for (int q = sh_ptr[sh]; q < sh_ptr[sh + 1]; ++q) tot += diag[subs[sh_s[q]].off_loc + sh_l[q]];
+    double dside[2];
+    for (int t = 0; t < 2; ++t) {
+        const int s = row_s[2 * r + t];
+        const SubMeta& M = subs[s];
+        dside[t] = diag[M.off_loc + b_loc[M.off_b + row_j[2 * r + t]]];
+    }
+    w[2 * r] = dside[1] / tot;
+    w[2 * r + 1] = dside[0] / tot;
+}
+
+// Weight of every gather entry (b DOF, row): the weight of the b DOF's own side of the row.
+__global__ void k_bg_weights(long long nb_tot, const int* __restrict__ bq_s, const SubMeta* __restrict__ subs,
+                             const int* __restrict__ bg_ptr, const int* __restrict__ bg_row,
+                             const int* __restrict__ row_s, const int* __restrict__ row_j,
+                             const double* __restrict__ w, double* bg_w) {
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= nb_tot) return;
+    const int s = bq_s[q];
+    const int j = (int)(q - subs[s].off_b);
+    for (int e = bg_ptr[q]; e < bg_ptr[q + 1]; ++e) {
+        const int r = bg_row[e];
+        const int t = (row_s[2 * r] == s && row_j[2 * r] == j) ? 0 : 1;
+        bg_w[e] = w[2 * r + t];
+    }
+}
+
+// Coarse matrix Kbar_cc = sum_s B_c^sT Kbar_cc^s B_c^s (Sec. 2.2), one thread per global
+// corner row (owner computes, fixed summation order).
+__global__ void k_coarse_assemble(int n_cg, const int* __restrict__ cc_ptr, const int* __restrict__ cc_s,
+                                  const int* __restrict__ cc_j, const SubMeta* __restrict__ subs,
+                                  const int* __restrict__ c_glob, const double* __restrict__ Kc, double* Kg) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_cg) return;
+    for (int e = cc_ptr[p]; e < cc_ptr[p + 1]; ++e) {
+        const int s = cc_s[e], jc = cc_j[e];
+        const SubMeta& M = subs[s];
+        for (int c2 = 0; c2 < M.n_c; ++c2)
+            Kg[(long long)p * n_cg + c_glob[M.off_c + c2]] += Kc[M.off_Kc + jc * M.n_c + c2];
+    }
+}
+
+// TFETI: G G^T with G = -Rhat^T B^T, one thread per subdomain owning its rows of G G^T.
+__global__ void k_ggt_assemble(int n_sub, int nm, const SubMeta* __restrict__ subs, const int* __restrict__ bg_ptr,
+                               const int* __restrict__ bg_row, const int8_t* __restrict__ bg_sg,
+                               const int* __restrict__ row_s, const int* __restrict__ row_j,
+                               const int8_t* __restrict__ row_sg, const double* __restrict__ Rb, double* GG) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sub) return;
+    const SubMeta M = subs[s];
+    const int na = n_sub * nm;
+    for (int j = 0; j < M.n_b; ++j) {
+        const long long q = M.off_b + j;
+        for (int e = bg_ptr[q]; e < bg_ptr[q + 1]; ++e) {
+            const int r = bg_row[e];
+            const double sg = bg_sg[e];
+            for (int t = 0; t < 2; ++t) {
+                const int s2 = row_s[2 * r + t];
+                if (s2 < 0) continue;
+                const SubMeta& M2 = subs[s2];
+                const int j2 = row_j[2 * r + t];
+                const double sg2 = row_sg[2 * r + t];
+                for (int m = 0; m < nm; ++m)
+                    for (int m2 = 0; m2 < nm; ++m2)
+                        GG[(long long)(s * nm + m) * na + s2 * nm + m2] +=
+                            sg * sg2 * Rb[M.off_R + (long long)j * nm + m] * Rb[M2.off_R + (long long)j2 * nm + m2];
+            }
+        }
+    }
+}
+
+__global__ void k_set_identity(double* A, int n, long long lda) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)n * n) return;
+    const int i = (int)(e / n), j = (int)(e % n);
+    A[(long long)i * lda + j] = i == j ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------------------
+// host launchers
+
+void upload_K0(const double* K0, int n, hipStream_t st) {
+    hipMemcpyToSymbolAsync(HIP_SYMBOL(c_K0), K0, sizeof(double) * n * n, 0, hipMemcpyHostToDevice, st);
+}
+
+void launch_assemble(const DevTopo& t, const double* rho, double p, double E0, double Emin, double* L, double* Z,
+                     double* S, double* diag, hipStream_t st) {
+    dim3 grid((t.max_nodes + 255) / 256, t.n_sub);
+    k_assemble<<<grid, 256, 0, st>>>(t.subs, t.lines, t.dim, t.nel[0], t.nel[1], rho, p, E0, Emin, t.lcls, t.lidx,
+                                     L, Z, S, diag);
+}
+
+void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st) {
+    k_bt_factor<<<t.n_sub, 256, 0, st>>>(t.subs, t.lines, L, info);
+}
+
+void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st) {
+    dim3 grid((t.max_beta + 63) / 64, t.n_sub);
+    k_bt_forward<<<grid, 256, 0, st>>>(t.subs, t.lines, L, Z);
+}
+
+void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* A, const double* B, double* C,
+                    double alpha, double beta, int symmetric, hipStream_t st) {
+    if (nbatch == 0 || max_tiles == 0) return;
+    k_gemm_tn<<<dim3(max_tiles, nbatch), 256, 0, st>>>(d, A, B, C, alpha, beta, symmetric);
+}
+
+void launch_potrf(const PotrfDesc* d, int nbatch, double* base, int* info, hipStream_t st) {
+    if (nbatch) k_potrf<<<nbatch, 256, 0, st>>>(d, base, info);
+}
+
+void launch_trsm(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st) {
+    if (nbatch && max_cols) k_trsm<<<dim3((max_cols + 63) / 64, nbatch), 256, 0, st>>>(d, L, B);
+}
+
+void launch_copy_Sbb(const DevTopo& t, const double* S, double* dst, int identity, hipStream_t st) {
+    k_copy_Sbb<<<dim3(64, t.n_sub), 256, 0, st>>>(t.subs, S, dst, identity);
+}
+
+void launch_to_f32(const double* src, float* dst, long long n, hipStream_t st) {
+    if (n > 0) k_to_f32<<<(int)std::min<long long>((n + 255) / 256, 65535), 256, 0, st>>>(src, dst, n);
+}
+
+void launch_tfeti_rbm(const DevTopo& t, const double* S, double* Rb, double* Cit, double* tau, double* W,
+                      hipStream_t st) {
+    k_tfeti_rbm<<<t.n_sub, 256, 0, st>>>(t.subs, t.dim, t.b_loc, S, Rb, Cit, tau, W);
+}
+
+void launch_tfeti_fix(const DevTopo& t, const double* Rb, const double* tau, double* F64, hipStream_t st) {
+    k_tfeti_fix<<<dim3(64, t.n_sub), 256, 0, st>>>(t.subs, t.dim == 2 ? 3 : 6, Rb, tau, F64);
+}
+
+void launch_frc(const DevTopo& t, const double* S, double* F64, double* Kc, hipStream_t st) {
+    k_frc<<<t.n_sub, 256, 0, st>>>(t.subs, S, F64, Kc);
+}
+
+void launch_swizzle(const DevTopo& t, const double* F64, double* sw64, float* sw32, __hip_bfloat16* hi,
+                    __hip_bfloat16* lo, hipStream_t st) {
+    k_swizzle<<<dim3(256, t.n_sub), 256, 0, st>>>(t.subs, F64, sw64, sw32, hi, lo);
+}
+
+void launch_weights(const DevTopo& t, int kscale, const double* diag, double* w, double* bg_w, hipStream_t st) {
+    if (t.n_lambda == 0) return;
+    k_weights<<<(t.n_lambda + 255) / 256, 256, 0, st>>>(t.n_lambda, kscale, t.row_s, t.row_j, t.row_sh, t.sh_ptr,
+                                                         t.sh_s, t.sh_l, t.subs, t.b_loc, diag, w);
+    k_bg_weights<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, t.bq_s, t.subs, t.bg_ptr, t.bg_row,
+                                                                 t.row_s, t.row_j, w, bg_w);
+}
+
+void launch_coarse_assemble(const DevTopo& t, const double* Kc, double* Kg, hipStream_t st) {
+    if (t.n_cg) k_coarse_assemble<<<(t.n_cg + 255) / 256, 256, 0, st>>>(t.n_cg, t.cc_ptr, t.cc_s, t.cc_j, t.subs,
+                                                                          t.c_glob, Kc, Kg);
+}
+
+void launch_ggt_assemble(const DevTopo& t, const double* Rb, double* GG, hipStream_t st) {
+    k_ggt_assemble<<<(t.n_sub + 63) / 64, 64, 0, st>>>(t.n_sub, t.dim == 2 ? 3 : 6, t.subs, t.bg_ptr, t.bg_row,
+                                                       t.bg_sg, t.row_s, t.row_j, t.row_sg, Rb, GG);
+}
+
+void launch_set_identity(double* A, int n, long long lda, hipStream_t st) {
+    if (n) k_set_identity<<<(int)(((long long)n * n + 255) / 256), 256, 0, st>>>(A, n, lda);
+}
+
+}  // namespace feti

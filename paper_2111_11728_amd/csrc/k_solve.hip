@@ -1,0 +1,427 @@
+// Solve-phase kernels: distribution of the load to the subdomains, the right-hand sides
+// of the dual problems (Sec. 2.1 Eq. 7: d = B K^+ f - c, e = -R^T f; Sec. 2.2 Eq. 12:
+// d_r, fbar_c), recovery of the primal solution, averaging of the subdomain copies and
+// the compliance with its adjoint gradient.
+#include "kernels.hpp"
+
+namespace feti {
+
+// f^s: a global load entry goes to the lowest-numbered subdomain holding its DOF.
+__global__ void k_scatter_f(const SubMeta* __restrict__ subs, const int8_t* __restrict__ lcls,
+                            const int* __restrict__ lidx, const int* __restrict__ lglob,
+                            const int8_t* __restrict__ lown, const double* __restrict__ f, double* fi, double* fbeta) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= M.n_loc) return;
+    const long long q = M.off_loc + l;
+    const double v = lown[q] ? f[lglob[q]] : 0.0;
+    const long long ob = M.off_b + M.off_c;
+    switch (lcls[q]) {
+        case CLS_I: fi[M.off_i + lidx[q]] = v; break;
+        case CLS_B: fbeta[ob + lidx[q]] = v; break;
+        case CLS_C: fbeta[ob + M.n_b + lidx[q]] = v; break;
+        default: break;
+    }
+}
+
+void launch_scatter_f(const DevTopo& t, const double* f, double* fi, double* fbeta, hipStream_t st) {
+    k_scatter_f<<<dim3((t.max_nloc + 255) / 256, t.n_sub), 256, 0, st>>>(t.subs, t.lcls, t.lidx, t.lglob, t.lown, f,
+                                                                         fi, fbeta);
+}
+
+// h <- L^{-1} h for the block-tridiagonal factor, one wavefront per subdomain.
+__global__ void __launch_bounds__(64) k_bt_fsolve1(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
+                                                   const double* __restrict__ Lbuf, double* h) {
+    extern __shared__ double xs[];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int lane = threadIdx.x;
+    double* hs = h + M.off_i;
+    for (int k = 0; k < M.n_lines; ++k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        for (int r = lane; r < Lk.n; r += 64) {
+            double v = hs[Lk.i0 + r];
+            const double* Ls = Lbuf + Lk.off_sub + (long long)r * Lk.n_prev;
+            for (int q = 0; q < Lk.n_prev; ++q) v -= Ls[q] * hs[Lk.i0 - Lk.n_prev + q];
+            xs[r] = v;
+        }
+        __syncthreads();
+        const double* D = Lbuf + Lk.off_diag;
+        for (int r = 0; r < Lk.n; ++r) {
+            const double xr = xs[r] / D[(long long)r * Lk.n + r];
+            __syncthreads();
+            if (lane == 0) xs[r] = xr;
+            for (int q = r + 1 + lane; q < Lk.n; q += 64) xs[q] -= D[(long long)q * Lk.n + r] * xr;
+            __syncthreads();
+        }
+        for (int r = lane; r < Lk.n; r += 64) hs[Lk.i0 + r] = xs[r];
+        __syncthreads();
+    }
+}
+
+// x <- L^{-T} x (backward, block upper-bidiagonal L^T), one wavefront per subdomain.
+__global__ void __launch_bounds__(64) k_bt_bsolve1(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
+                                                   const double* __restrict__ Lbuf, double* x) {
+    extern __shared__ double xs[];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int lane = threadIdx.x;
+    double* xg = x + M.off_i;
+    for (int k = M.n_lines - 1; k >= 0; --k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        // t_k -= L_{k+1,k}^T x_{k+1}
+        LineMeta Ln;
+        Ln.n = 0;
+        if (k + 1 < M.n_lines) Ln = lines[M.line0 + k + 1];
+        for (int q = lane; q < Lk.n; q += 64) {
+            double v = xg[Lk.i0 + q];
+            if (Ln.n > 0) {
+                const double* Ls = Lbuf + Ln.off_sub;
+                for (int r = 0; r < Ln.n; ++r) v -= Ls[(long long)r * Lk.n + q] * xg[Ln.i0 + r];
+            }
+            xs[q] = v;
+        }
+        __syncthreads();
+        const double* D = Lbuf + Lk.off_diag;
+        for (int r = Lk.n - 1; r >= 0; --r) {
+            const double xr = xs[r] / D[(long long)r * Lk.n + r];
+            __syncthreads();
+            if (lane == 0) xs[r] = xr;
+            for (int q = lane; q < r; q += 64) xs[q] -= D[(long long)r * Lk.n + q] * xr;
+            __syncthreads();
+        }
+        for (int q = lane; q < Lk.n; q += 64) xg[Lk.i0 + q] = xs[q];
+        __syncthreads();
+    }
+}
+
+void launch_bt_fsolve1(const DevTopo& t, const double* L, double* h, hipStream_t st) {
+    k_bt_fsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, h);
+}
+
+void launch_bt_bsolve1(const DevTopo& t, const double* L, double* x, hipStream_t st) {
+    k_bt_bsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, x);
+}
+
+// g = fbeta - Z^T h  (thread per interface column)
+__global__ void k_zt_gemv(const SubMeta* __restrict__ subs, const double* __restrict__ Z, const double* __restrict__ h,
+                          const double* __restrict__ fbeta, double* g) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M.n_beta) return;
+    const long long ob = M.off_b + M.off_c;
+    double v = fbeta[ob + j];
+    const double* Zs = Z + M.off_Z + j;
+    const double* hs = h + M.off_i;
+    for (int i = 0; i < M.n_i; ++i) v -= Zs[(long long)i * M.n_beta] * hs[i];
+    g[ob + j] = v;
+}
+
+void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g,
+                    hipStream_t st) {
+    k_zt_gemv<<<dim3((t.max_beta + 255) / 256, t.n_sub), 256, 0, st>>>(t.subs, Z, h, fbeta, g);
+}
+
+// x = h - Z ubeta  (wavefront per interior row)
+__global__ void __launch_bounds__(256) k_z_gemv(const SubMeta* __restrict__ subs, const double* __restrict__ Z,
+                                                const double* __restrict__ ubeta, const double* __restrict__ h,
+                                                double* x) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= M.n_i) return;
+    const long long ob = M.off_b + M.off_c;
+    const double* Zr = Z + M.off_Z + (long long)i * M.n_beta;
+    double v = 0.0;
+    for (int j = lane; j < M.n_beta; j += 64) v += Zr[j] * ubeta[ob + j];
+    v = warp_sum(v);
+    if (lane == 0) x[M.off_i + i] = h[M.off_i + i] - v;
+}
+
+void launch_z_gemv(const DevTopo& t, const double* Z, const double* ubeta, const double* h, double* x,
+                   hipStream_t st) {
+    k_z_gemv<<<dim3((t.max_ni + 3) / 4, t.n_sub), 256, 0, st>>>(t.subs, Z, ubeta, h, x);
+}
+
+// y = [F_s; F_rc^sT] g_b (FP64), wavefront per row
+__global__ void __launch_bounds__(256) k_local_F(const SubMeta* __restrict__ subs, const double* __restrict__ F64,
+                                                 const double* __restrict__ g, double* yb, double* yc) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= M.n_b + M.n_c) return;
+    const long long ob = M.off_b + M.off_c;
+    const double* Fr = F64 + M.off_F + (long long)row * M.ldF;
+    double v = 0.0;
+    for (int j = lane; j < M.n_b; j += 64) v += Fr[j] * g[ob + j];
+    v = warp_sum(v);
+    if (lane == 0) {
+        if (row < M.n_b)
+            yb[M.off_b + row] = v;
+        else
+            yc[M.off_c + row - M.n_b] = v;
+    }
+}
+
+void launch_local_F(const DevTopo& t, const double* F64, const double* g, double* yb, double* yc, hipStream_t st) {
+    k_local_F<<<dim3((t.max_nb + t.max_nc + 3) / 4, t.n_sub), 256, 0, st>>>(t.subs, F64, g, yb, yc);
+}
+
+// fbar_c^s = g_c - F_rc^sT g_b   (the local reduced corner load)
+__global__ void k_fbar(const SubMeta* __restrict__ subs, int n_sub, const double* __restrict__ g,
+                       const double* __restrict__ yc, double* fbar_s) {
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    for (int c = threadIdx.x; c < M.n_c; c += blockDim.x)
+        fbar_s[M.off_c + c] = g[M.off_b + M.off_c + M.n_b + c] - yc[M.off_c + c];
+}
+
+void launch_fbar(const DevTopo& t, const double* g, const double* yc, double* fbar_s, hipStream_t st) {
+    k_fbar<<<t.n_sub, 64, 0, st>>>(t.subs, t.n_sub, g, yc, fbar_s);
+}
+
+// xb = B^sT lambda for every interface DOF
+__global__ void k_gather_B(long long nb_tot, const int* __restrict__ bg_ptr, const int* __restrict__ bg_row,
+                           const int8_t* __restrict__ bg_sg, const double* __restrict__ lam, double* xb) {
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= nb_tot) return;
+    double v = 0.0;
+    for (int e = bg_ptr[q]; e < bg_ptr[q + 1]; ++e) v += bg_sg[e] * lam[bg_row[e]];
+    xb[q] = v;
+}
+
+void launch_gather_B(const DevTopo& t, const double* lam, double* xb, hipStream_t st) {
+    if (t.nb_tot) k_gather_B<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, t.bg_ptr, t.bg_row, t.bg_sg, lam, xb);
+}
+
+// Interface displacements: u_b = F_s (g_b - S_bc u_c^s - (B^sT lambda)_b), u_beta = [u_b; u_c^s]
+// (FETI-DP; for TFETI n_c = 0 and F_s is the pseudo-inverse block).
+__global__ void __launch_bounds__(256) k_interface_u(const SubMeta* __restrict__ subs, const double* __restrict__ F64,
+                                                     const double* __restrict__ S, const double* __restrict__ g,
+                                                     const double* __restrict__ xb, const double* __restrict__ uc,
+                                                     const int* __restrict__ c_glob, double* ubeta) {
+    extern __shared__ double sh[];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    double* ucs = sh;              // n_c
+    double* gh = sh + M.n_c;       // n_b
+    const long long ob = M.off_b + M.off_c;
+    for (int c = threadIdx.x; c < M.n_c; c += 256) ucs[c] = uc[c_glob[M.off_c + c]];
+    __syncthreads();
+    for (int j = threadIdx.x; j < M.n_b; j += 256) {
+        double v = g[ob + j] - xb[M.off_b + j];
+        for (int c = 0; c < M.n_c; ++c) v -= S[M.off_S + (long long)j * M.n_beta + M.n_b + c] * ucs[c];
+        gh[j] = v;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int row = wave; row < M.n_b; row += 4) {
+        const double* Fr = F64 + M.off_F + (long long)row * M.ldF;
+        double v = 0.0;
+        for (int j = lane; j < M.n_b; j += 64) v += Fr[j] * gh[j];
+        v = warp_sum(v);
+        if (lane == 0) ubeta[ob + row] = v;
+    }
+    for (int c = threadIdx.x; c < M.n_c; c += 256) ubeta[ob + M.n_b + c] = ucs[c];
+}
+
+void launch_dp_ub(const DevTopo& t, const double* F64, const double* S, const double* g, const double* xb,
+                  const double* uc, double* ubeta, hipStream_t st) {
+    k_interface_u<<<t.n_sub, 256, sizeof(double) * (t.max_nb + t.max_nc + 1), st>>>(t.subs, F64, S, g, xb, uc,
+                                                                                   t.c_glob, ubeta);
+}
+
+void launch_tfeti_ub(const DevTopo& t, const double* F64, const double* g, const double* xb, double* ubeta,
+                     hipStream_t st) {
+    k_interface_u<<<t.n_sub, 256, sizeof(double) * (t.max_nb + 1), st>>>(t.subs, F64, nullptr, g, xb, nullptr,
+                                                                        t.c_glob, ubeta);
+}
+
+// ---- rigid-body modes of a local DOF (same basis as the setup kernels) ----
+__device__ inline void rbm_of_local(const SubMeta& M, int dim, int l, double* r) {
+    const int node = l / dim, comp = l % dim;
+    const int ix = node % M.nn[0], iy = (node / M.nn[0]) % M.nn[1], iz = node / (M.nn[0] * M.nn[1]);
+    const double x = ix - 0.5 * (M.nn[0] - 1), y = iy - 0.5 * (M.nn[1] - 1), z = iz - 0.5 * (M.nn[2] - 1);
+    const int nm = dim == 2 ? 3 : 6;
+    for (int m = 0; m < nm; ++m) r[m] = 0.0;
+    r[comp] = 1.0;
+    if (dim == 2) {
+        r[2] = comp == 0 ? -y : x;
+    } else {
+        r[3] = comp == 0 ? -y : (comp == 1 ? x : 0.0);
+        r[4] = comp == 1 ? -z : (comp == 2 ? y : 0.0);
+        r[5] = comp == 0 ? z : (comp == 2 ? -x : 0.0);
+    }
+}
+
+// TFETI e_s = -Rhat_s^T f^s with Rhat_s = R_s C_s^{-T} over all local DOFs.
+__global__ void __launch_bounds__(256) k_tfeti_e(const SubMeta* __restrict__ subs, int dim, const int8_t* __restrict__ lcls,
+                                                 const int* __restrict__ lidx, const double* __restrict__ fi,
+                                                 const double* __restrict__ fbeta, const double* __restrict__ Cit,
+                                                 double* e) {
+    __shared__ double red[256][6];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int nm = dim == 2 ? 3 : 6;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int l = threadIdx.x; l < M.n_loc; l += 256) {
+        const long long q = M.off_loc + l;
+        double f = 0.0;
+        if (lcls[q] == CLS_I) f = fi[M.off_i + lidx[q]];
+        else if (lcls[q] == CLS_B) f = fbeta[M.off_b + M.off_c + lidx[q]];
+        if (f == 0.0) continue;
+        double r[6];
+        rbm_of_local(M, dim, l, r);
+        for (int m = 0; m < nm; ++m) acc[m] += r[m] * f;
+    }
+    for (int m = 0; m < 6; ++m) red[threadIdx.x][m] = acc[m];
+    __syncthreads();
+    if (threadIdx.x < nm) {
+        const int m = threadIdx.x;
+        double tot[6];
+        for (int a = 0; a < nm; ++a) {
+            double v = 0.0;
+            for (int u = 0; u < 256; ++u) v += red[u][a];
+            tot[a] = v;
+        }
+        double v = 0.0;
+        for (int a = 0; a < nm; ++a) v += tot[a] * Cit[s * 36 + a * nm + m];
+        e[s * nm + m] = -v;
+    }
+}
+
+void launch_tfeti_e(const DevTopo& t, const double* fi, const double* fbeta, const double* Cit, double* e,
+                    hipStream_t st) {
+    k_tfeti_e<<<t.n_sub, 256, 0, st>>>(t.subs, t.dim, t.lcls, t.lidx, fi, fbeta, Cit, e);
+}
+
+// Local displacement vector u^s (local DOF order) from its interior and interface parts,
+// plus the rigid-body part Rhat_s alpha_s for TFETI.
+__global__ void k_assemble_loc(const SubMeta* __restrict__ subs, int dim, const int8_t* __restrict__ lcls,
+                               const int* __restrict__ lidx, const double* __restrict__ ui,
+                               const double* __restrict__ ubeta, const double* __restrict__ Cit,
+                               const double* __restrict__ alpha, double* uloc) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= M.n_loc) return;
+    const long long q = M.off_loc + l;
+    const long long ob = M.off_b + M.off_c;
+    double v = 0.0;
+    switch (lcls[q]) {
+        case CLS_I: v = ui[M.off_i + lidx[q]]; break;
+        case CLS_B: v = ubeta[ob + lidx[q]]; break;
+        case CLS_C: v = ubeta[ob + M.n_b + lidx[q]]; break;
+        default: v = 0.0; break;
+    }
+    if (alpha) {
+        const int nm = dim == 2 ? 3 : 6;
+        double r[6];
+        rbm_of_local(M, dim, l, r);
+        for (int m = 0; m < nm; ++m) {
+            double rh = 0.0;
+            for (int a = 0; a < nm; ++a) rh += r[a] * Cit[s * 36 + a * nm + m];
+            v += rh * alpha[s * nm + m];
+        }
+    }
+    uloc[q] = v;
+}
+
+void launch_assemble_loc(const DevTopo& t, const double* ui, const double* ubeta, const double* Cit,
+                         const double* alpha, double* uloc, hipStream_t st) {
+    k_assemble_loc<<<dim3((t.max_nloc + 255) / 256, t.n_sub), 256, 0, st>>>(t.subs, t.dim, t.lcls, t.lidx, ui, ubeta,
+                                                                            Cit, alpha, uloc);
+}
+
+// Global u = average of the subdomain copies of every DOF.
+__global__ void k_average(long long n_dof, int dim, int nx, int ny, int nsx, int nsy, const int* __restrict__ axf0,
+                          const int* __restrict__ axc0, const int* __restrict__ axf1, const int* __restrict__ axc1,
+                          const int* __restrict__ axf2, const int* __restrict__ axc2,
+                          const SubMeta* __restrict__ subs, const double* __restrict__ uloc, double* u) {
+    const long long gd = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (gd >= n_dof) return;
+    const long long node = gd / dim;
+    const int comp = (int)(gd % dim);
+    const int x = (int)(node % (nx + 1));
+    const int y = (int)((node / (nx + 1)) % (ny + 1));
+    const int z = dim == 3 ? (int)(node / ((long long)(nx + 1) * (ny + 1))) : 0;
+    double acc = 0.0;
+    int cnt = 0;
+    for (int kz = 0; kz < axc2[z]; ++kz)
+        for (int ky = 0; ky < axc1[y]; ++ky)
+            for (int kx = 0; kx < axc0[x]; ++kx) {
+                const int s = (axf0[x] + kx) + nsx * ((axf1[y] + ky) + nsy * (axf2[z] + kz));
+                const SubMeta& M = subs[s];
+                const int ln = (x - M.lo[0]) + M.nn[0] * ((y - M.lo[1]) + M.nn[1] * (z - M.lo[2]));
+                acc += uloc[M.off_loc + (long long)ln * dim + comp];
+                ++cnt;
+            }
+    u[gd] = acc / cnt;
+}
+
+void launch_average(const DevTopo& t, const double* uloc, double* u, hipStream_t st) {
+    k_average<<<(int)((t.n_dof + 255) / 256), 256, 0, st>>>(t.n_dof, t.dim, t.nel[0], t.nel[1], t.nsub[0], t.nsub[1],
+                                                           t.ax_first[0], t.ax_cnt[0], t.ax_first[1], t.ax_cnt[1],
+                                                           t.ax_first[2], t.ax_cnt[2], t.subs, uloc, u);
+}
+
+// Compliance c = f^T u (two-stage reduction) and gradient
+// dc/drho_e = -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e (one thread per element).
+__global__ void __launch_bounds__(256) k_dot_part(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                                                  double* part) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) v += a[i] * b[i];
+    v = warp_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_parts(int n, const double* __restrict__ part, double* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double v = 0.0;
+        for (int i = 0; i < n; ++i) v += part[i];
+        *out = v;
+    }
+}
+
+__global__ void k_grad(long long n_el, int dim, int nx, int ny, const double* __restrict__ K0,
+                       const double* __restrict__ u, const double* __restrict__ rho, double p, double E0, double Emin,
+                       double* g) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= n_el) return;
+    const int ex = (int)(e % nx), ey = (int)((e / nx) % ny), ez = dim == 3 ? (int)(e / ((long long)nx * ny)) : 0;
+    const int ncorner = 1 << dim, ne = dim * ncorner;
+    double ue[24];
+    for (int a = 0; a < ncorner; ++a) {
+        const int x = ex + (a & 1), y = ey + ((a >> 1) & 1), z = ez + ((a >> 2) & 1);
+        const long long node = x + (long long)(nx + 1) * (y + (long long)(ny + 1) * z);
+        for (int c = 0; c < dim; ++c) ue[a * dim + c] = u[node * dim + c];
+    }
+    double en = 0.0;
+    for (int i = 0; i < ne; ++i) {
+        double v = 0.0;
+        for (int j = 0; j < ne; ++j) v += K0[i * ne + j] * ue[j];
+        en += ue[i] * v;
+    }
+    g[e] = -p * pow(rho[e], p - 1.0) * (E0 - Emin) * en;
+}
+
+void launch_compliance(const DevTopo& t, const double* f, const double* u, const double* rho, double p, double E0,
+                       double Emin, double* part, double* c, double* g, hipStream_t st) {
+    // part must hold 256 doubles; t.K0dev holds the unit element matrix
+    k_dot_part<<<256, 256, 0, st>>>(t.n_dof, f, u, part);
+    k_sum_parts<<<1, 64, 0, st>>>(256, part, c);
+    if (g) {
+        const long long n_el = (long long)t.nel[0] * t.nel[1] * (t.dim == 3 ? t.nel[2] : 1);
+        k_grad<<<(int)((n_el + 255) / 256), 256, 0, st>>>(n_el, t.dim, t.nel[0], t.nel[1], t.K0dev, u, rho, p, E0,
+                                                          Emin, g);
+    }
+}
+
+}  // namespace feti

@@ -1,0 +1,158 @@
+// Host-side launchers of the FETI kernels and the device views they take.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace feti {
+
+// Descriptors of batched dense operations (offsets in elements from a base pointer).
+struct GemmDesc {   // C[m x n] = beta C + alpha A^T B, A: k x m (lda), B: k x n (ldb), row-major
+    long long a, b, c;
+    int m, n, k, lda, ldb, ldc;
+};
+struct PotrfDesc {
+    long long a;
+    int n, lda;
+};
+struct TrsmDesc {   // B <- L^{-1} B, L: n x n (ldl), B: n x ncols (ldb), row-major
+    long long l, b;
+    int n, ldl, ncols, ldb;
+};
+
+// Device copies of the topology (pointers into one device allocation).
+struct DevTopo {
+    int dim = 2, n_sub = 0, n_lambda = 0, n_cg = 0, n_groups = 0, n_rbm = 0;
+    int nel[3] = {0, 0, 0}, nsub[3] = {1, 1, 1};
+    int max_nodes = 0, max_beta = 0, max_nb = 0, max_rows_F = 0, max_nloc = 0, max_nc = 0, max_ni = 0;
+    int max_line = 0;
+    const double* K0dev = nullptr;    // unit-modulus element matrix (row-major)
+    long long nb_tot = 0, nc_tot = 0, ni_tot = 0, nloc_tot = 0, n_dof = 0;
+    const SubMeta* subs = nullptr;
+    const LineMeta* lines = nullptr;
+    const int8_t* lcls = nullptr;
+    const int* lidx = nullptr;
+    const int* lglob = nullptr;
+    const int8_t* lown = nullptr;
+    const int* i_loc = nullptr;
+    const int* b_loc = nullptr;
+    const int* c_loc = nullptr;
+    const int* c_glob = nullptr;
+    const int* bq_s = nullptr;       // subdomain of every b DOF
+    const int* row_s = nullptr;
+    const int* row_j = nullptr;
+    const int8_t* row_sg = nullptr;
+    const int* row_sh = nullptr;
+    const int* sh_ptr = nullptr;
+    const int* sh_s = nullptr;
+    const int* sh_l = nullptr;
+    const int* bg_ptr = nullptr;
+    const int* bg_row = nullptr;
+    const int8_t* bg_sg = nullptr;
+    const int* cc_ptr = nullptr;
+    const int* cc_s = nullptr;
+    const int* cc_j = nullptr;
+    const int* ax_first[3] = {nullptr, nullptr, nullptr};
+    const int* ax_cnt[3] = {nullptr, nullptr, nullptr};
+    const int* m_tile_sub = nullptr;  // F*Lambda work list: subdomain of every 128-row tile
+    const int* m_tile_row = nullptr;  // first row of the tile
+    int n_m_tiles = 0;
+};
+
+// ---- setup (k_setup.hip) ----
+void upload_K0(const double* K0, int n, hipStream_t st);
+void launch_assemble(const DevTopo& t, const double* rho, double p, double E0, double Emin, double* L, double* Z,
+                     double* S, double* diag, hipStream_t st);
+void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st);
+void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st);
+void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* A, const double* B, double* C,
+                    double alpha, double beta, int symmetric, hipStream_t st);
+void launch_potrf(const PotrfDesc* d, int nbatch, double* base, int* info, hipStream_t st);
+void launch_trsm(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st);
+void launch_copy_Sbb(const DevTopo& t, const double* S, double* dst, int identity, hipStream_t st);
+void launch_to_f32(const double* src, float* dst, long long n, hipStream_t st);
+void launch_tfeti_rbm(const DevTopo& t, const double* S, double* Rb, double* Cit, double* tau, double* W,
+                      hipStream_t st);
+void launch_tfeti_fix(const DevTopo& t, const double* Rb, const double* tau, double* F64, hipStream_t st);
+void launch_frc(const DevTopo& t, const double* S, double* F64, double* Kc, hipStream_t st);
+void launch_swizzle(const DevTopo& t, const double* F64, double* sw64, float* sw32, __hip_bfloat16* hi,
+                    __hip_bfloat16* lo, hipStream_t st);
+void launch_weights(const DevTopo& t, int kscale, const double* diag, double* w, double* bg_w, hipStream_t st);
+void launch_coarse_assemble(const DevTopo& t, const double* Kc, double* Kg, hipStream_t st);
+void launch_ggt_assemble(const DevTopo& t, const double* Rb, double* GG, hipStream_t st);
+void launch_set_identity(double* A, int n, long long lda, hipStream_t st);
+
+// ---- operator application (k_apply.hip) ----
+// Y/T outputs of the local products: Y [nb_tot x k], T [nc_tot x k], row-major, type by precision.
+void launch_flambda(const DevTopo& t, int precision, int k, const double* Lambda, const void* Fsw,
+                    const void* Fsw_lo, void* Y, void* T, hipStream_t st);
+// t = add + sum_s B_c^sT T_s (n_cg x k), v = scale * Kinv t
+void launch_coarse(const DevTopo& t, int k, int ytype_f32, const void* T, const double* add, const double* Kinv,
+                   double scale, double* v, hipStream_t st);
+// Q[row] = sum over sides sign * (Y[b] + F_rc[b,:] . v[corners])   (v may be null)
+void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, const double* F64, const double* v,
+                    double* Q, hipStream_t st);
+// x_s = B~^sT r gathered and multiplied: y_s = P_s x_s  (P_s FP64 or FP32)
+void launch_precond_local(const DevTopo& t, int use_f32, const double* r, const double* bg_w, const double* P64,
+                          const float* P32, double* y, hipStream_t st);
+// Z[row][g(s)] = sum over sides sign * w * y_s[j]; one_column sums into column 0
+void launch_precond_scatter(const DevTopo& t, int one_column, const double* w, const double* y, double* Z,
+                            hipStream_t st);
+// TFETI projector pieces
+void launch_proj_G(const DevTopo& t, int k, const double* Y, const double* Rb, double* GY, hipStream_t st);
+void launch_small_gemm(int m, int n, int kk, const double* A, const double* B, double* C, double alpha,
+                       hipStream_t st);  // C[m x n] = alpha A[m x kk] B[kk x n], row-major, B/C ld n
+void launch_proj_apply(const DevTopo& t, int k, const double* tcoef, const double* Rb, double sign, double* Y,
+                       hipStream_t st);  // Y[row] += sign * sum_sides sg * Rb[j] . tcoef[s]
+
+// ---- Krylov (k_krylov.hip) ----
+// partial Gram: for every block b < nblk (A_b = Aptrs[b]) and row chunk c:
+// part[(b*nchunk + c)][ka x kb] = A_b[rows of c]^T B[rows of c]
+void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
+                 double* out, hipStream_t st);
+int gram_chunks(int n, int nblk);
+constexpr long long kGramPartCap = 2048ll * kMaxDirs * kMaxDirs;   // doubles in the partial-sum buffer
+void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st);
+void launch_apply_T(int n, int k, const double* T, const double* W, const double* Q, double* Wo, double* Qo,
+                    hipStream_t st);
+// lam += W g; r -= Qg_scale * Q g  (Q may be null)
+void launch_update_lr(int n, int k, const double* W, const double* Q, const double* g, double* lam, double* r,
+                      hipStream_t st);
+void launch_orth_update(int n, int k, const double* const* Wptrs, int nblk, const double* Psi, double* W,
+                        hipStream_t st);
+void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st);
+void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st);  // y = a x + b y
+void launch_pcg_update(int n, const double* sc, const double* w, const double* q, double* lam, double* r,
+                       hipStream_t st);
+void launch_pcg_dir(int n, const double* sc, const double* z, double* w, hipStream_t st);
+
+// ---- solve-phase (k_solve.hip) ----
+void launch_scatter_f(const DevTopo& t, const double* f, double* fi, double* fbeta, hipStream_t st);
+void launch_bt_fsolve1(const DevTopo& t, const double* L, double* h, hipStream_t st);
+void launch_bt_bsolve1(const DevTopo& t, const double* L, double* x, hipStream_t st);
+void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g,
+                    hipStream_t st);  // g = fbeta - Z^T h
+void launch_z_gemv(const DevTopo& t, const double* Z, const double* ubeta, const double* h, double* x,
+                   hipStream_t st);   // x = h - Z ubeta
+void launch_local_F(const DevTopo& t, const double* F64, const double* g, double* yb, double* yc, hipStream_t st);
+void launch_fbar(const DevTopo& t, const double* g, const double* yc, double* fbar_s, hipStream_t st);
+void launch_gather_B(const DevTopo& t, const double* lam, double* xb, hipStream_t st);   // xb = B^T lam per subdomain
+void launch_dp_ub(const DevTopo& t, const double* F64, const double* S, const double* g, const double* xb,
+                  const double* uc, double* ubeta, hipStream_t st);
+void launch_tfeti_ub(const DevTopo& t, const double* F64, const double* g, const double* xb, double* ubeta,
+                     hipStream_t st);
+void launch_tfeti_e(const DevTopo& t, const double* fi, const double* fbeta, const double* Cit, double* e,
+                    hipStream_t st);
+void launch_assemble_loc(const DevTopo& t, const double* ui, const double* ubeta, const double* Cit,
+                         const double* alpha, double* uloc, hipStream_t st);
+void launch_average(const DevTopo& t, const double* uloc, double* u, hipStream_t st);
+void launch_compliance(const DevTopo& t, const double* f, const double* u, const double* rho, double p, double E0,
+                       double Emin, double* part, double* c, double* g, hipStream_t st);
+
+}  // namespace feti
