@@ -50,6 +50,7 @@ enum { FETI_MULT = 0, FETI_KSCALE = 1 };                    /* Sec. 3.1 */
 enum { FETI_PCG = 0, FETI_FO = 1, FETI_SFETI = 2 };         /* Sec. 2, Sec. 3.2, Sec. 3.3 */
 enum { FETI_DIRICHLET = 0, FETI_LUMPED = 1 };               /* Sec. 3.1, Eq. (13) */
 enum { FETI_FP64 = 0, FETI_FP32 = 1, FETI_BF16X3 = 2 };     /* arithmetic of the F*Lambda product */
+enum { FETI_PURE = 16 };   /* or-ed into feti_apply_F's precision: no per-subdomain FP64 fallback */
 
 /* Structured grid and boundary conditions (Sec. 2, Eq. 2). */
 typedef struct {
@@ -84,8 +85,8 @@ typedef struct {
                                  (<= 0: 1e-12) */
     int reorth;               /* passes of block classical Gram-Schmidt against the stored
                                  directions (1 or 2; 0 = 2) */
-    int max_refine;           /* mixed precision: FP64 residual restarts after the first pass
-                                 (< 0: 4) */
+    int max_refine;           /* mixed precision: FP64 residual restarts with the reduced-precision
+                                 operator after the first pass (< 0: 4); further passes use FP64 */
 } feti_opts;
 
 typedef struct {
@@ -100,6 +101,8 @@ typedef struct {
     int res_hist_cap;
     int* rank_hist;           /* host, optional: rank kept per iteration (same capacity) */
     double t_solve_ms;        /* wall time of feti_solve on the host clock */
+    int fp64_fallback;        /* 1 if a reduced-precision pass broke down or stagnated and the
+                                 solve was finished with the FP64 operator */
 } feti_info;
 
 typedef struct {
@@ -108,6 +111,8 @@ typedef struct {
     long long sum_nb2;        /* sum over subdomains of n_b^2 (entries of all explicit F_s) */
     long long sum_nb_nc;      /* sum over subdomains of n_b * n_c */
     long long device_bytes;   /* device memory held by a context */
+    int n_fp64_subs;          /* FETI-DP with a reduced precision: subdomains whose F_s failed the
+                                 round-off test at the last setup and run in FP64 */
 } feti_sizes;
 
 /* Builds the integer topology only (no device work) and reports the interface sizes.
@@ -165,7 +170,10 @@ feti_status feti_get_sizes(feti_ctx* ctx, feti_sizes* out);
 /* Q = F Lambda for a block of k directions (Sec. 2.1 Eq. 7: F = B K^+ B^T; Sec. 2.2 Eq. 12
  * with u_c condensed: F_rr + F_rc Kbar_cc^{-1} F_rc^T). Lambda, Q: device [n_lambda x k]
  * row-major FP64; precision selects the arithmetic of the local products
- * (FP64, FP32 or BF16 split into hi + lo with three products). 1 <= k <= 64. */
+ * (FP64, FP32 or BF16 split into hi + lo with three products). For FETI-DP with the
+ * context's own reduced precision, subdomains whose F_s failed the setup's round-off test
+ * (Cholesky pivots of F_s and of its rounding differing by more than 2 percent) run in FP64;
+ * or-ing FETI_PURE forces every subdomain to the reduced precision. 1 <= k <= 64. */
 feti_status feti_apply_F(feti_ctx* ctx, int k, int precision, const double* Lambda, double* Q);
 
 /* Z = [.., B~^s S~^s B~^sT r, ..] (Sec. 3.1 Eq. 13, Algorithm 1): r device [n_lambda];

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -97,6 +98,16 @@ std::vector<double> element_K0(int dim, double nu) {
 
 long long rup(long long x, long long m) { return (x + m - 1) / m * m; }
 
+// FETI_VERBOSE=1 prints one line per Krylov iteration (and per restart) to stderr.
+int verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("FETI_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v;
+}
+
 }  // namespace
 
 // -----------------------------------------------------------------------------------------
@@ -138,6 +149,15 @@ struct feti_ctx {
            *scal = nullptr, *Psi = nullptr, *tmpv = nullptr, *zv = nullptr, *K0dev = nullptr;
     int* rank_dev = nullptr;
     const double** qk_ptr = nullptr;    // device table holding the single pointer Qk
+    const double** zk_ptr = nullptr;    // device table holding the single pointer Zk
+    double* tcbuf = nullptr;            // coarse right-hand sides t (n_cg x k)
+    // per-subdomain precision selection for the reduced-precision F*Lambda (FETI-DP)
+    double* pivdev = nullptr;
+    int *tl_low_sub = nullptr, *tl_low_row = nullptr, *tl_low_end = nullptr;
+    int *tl_64_sub = nullptr, *tl_64_row = nullptr, *tl_64_end = nullptr;
+    TileList tl_low, tl_64;
+    bool hybrid = false;
+    int n_fp64_subs = 0;
     long long psi_cap = 0;
     // history of F-orthonormal directions
     std::vector<double*> hist_chunks;
@@ -178,6 +198,39 @@ struct feti_ctx {
 
 namespace {
 
+// XCD-aware list of 128-row tiles (subdomain s runs on XCD s % 8; dummy tiles pad the
+// interleaving). A subdomain contributes tiles over its F_s rows [0, rowT) and, when it has
+// corners, over its F_rc^T rows [rowT, rows_F); keep(s, is_T) selects which.
+template <typename Keep>
+void make_tiles(const feti_ctx* c, Keep keep, std::vector<int>& ts, std::vector<int>& tr, std::vector<int>& te) {
+    struct Tl { int s, r0, end; };
+    std::vector<std::vector<Tl>> bucket(8);
+    for (int s = 0; s < (int)c->hsubs.size(); ++s) {
+        const SubMeta& M = c->hsubs[s];
+        if (keep(s, false))
+            for (int r0 = 0; r0 < M.rowT; r0 += 128) bucket[s % 8].push_back({s, r0, M.rowT});
+        if (M.rows_F > M.rowT && keep(s, true))
+            for (int r0 = M.rowT; r0 < M.rows_F; r0 += 128) bucket[s % 8].push_back({s, r0, M.rows_F});
+    }
+    size_t mx = 0;
+    for (auto& b : bucket) mx = std::max(mx, b.size());
+    ts.clear();
+    tr.clear();
+    te.clear();
+    for (size_t i = 0; i < mx; ++i)
+        for (int x = 0; x < 8; ++x) {
+            const bool in = i < bucket[x].size();
+            ts.push_back(in ? bucket[x][i].s : -1);
+            tr.push_back(in ? bucket[x][i].r0 : 0);
+            te.push_back(in ? bucket[x][i].end : 0);
+        }
+    while (!ts.empty() && ts.back() < 0) {
+        ts.pop_back();
+        tr.pop_back();
+        te.pop_back();
+    }
+}
+
 void build_layout(feti_ctx* c) {
     Plan& P = c->P;
     const int ns = P.n_sub;
@@ -199,7 +252,8 @@ void build_layout(feti_ctx* c) {
         M.n_beta = M.n_b + M.n_c;
         M.grp = P.grp[s];
         M.ldF = (int)rup(std::max(M.n_b, 1), 32);
-        M.rows_F = (int)rup(std::max(M.n_b + M.n_c, 1), 16);
+        M.rowT = (int)rup(std::max(M.n_b, 1), 16);
+        M.rows_F = M.rowT + (int)rup(M.n_c, 16);
         M.off_loc = P.off_loc[s];
         M.off_i = P.off_i[s];
         M.off_b = P.off_b[s];
@@ -322,28 +376,9 @@ void build_layout(feti_ctx* c) {
     c->d_potrf_one = c->upload(std::vector<PotrfDesc>{PotrfDesc{0, nsmall, nsmall}});
     c->d_trsm_one = c->upload(std::vector<TrsmDesc>{TrsmDesc{0, 0, nsmall, nsmall, nsmall, nsmall}});
 
-    // F*Lambda work list: 128-row tiles, subdomain s on XCD s % 8
-    std::vector<std::vector<std::pair<int, int>>> bucket(8);
-    for (int s = 0; s < ns; ++s)
-        for (int r0 = 0; r0 < c->hsubs[s].rows_F; r0 += 128) bucket[s % 8].push_back({s, r0});
-    size_t mx = 0;
-    for (auto& b : bucket) mx = std::max(mx, b.size());
-    std::vector<int> ts, tr;
-    for (size_t i = 0; i < mx; ++i)
-        for (int x = 0; x < 8; ++x) {
-            if (i < bucket[x].size()) {
-                ts.push_back(bucket[x][i].first);
-                tr.push_back(bucket[x][i].second);
-            } else {
-                ts.push_back(-1);
-                tr.push_back(0);
-            }
-        }
-    // trim trailing dummies
-    while (!ts.empty() && ts.back() < 0) {
-        ts.pop_back();
-        tr.pop_back();
-    }
+    // F*Lambda work list: 128-row tiles of every subdomain's augmented operator
+    std::vector<int> ts, tr, te;
+    make_tiles(c, [](int, bool) { return true; }, ts, tr, te);
     t.n_m_tiles = (int)ts.size();
 
     // topology arrays
@@ -368,6 +403,17 @@ void build_layout(feti_ctx* c) {
     t.sh_ptr = c->upload(P.sh_ptr);
     t.sh_s = c->upload(P.sh_s);
     t.sh_l = c->upload(P.sh_l);
+    {
+        int R = 1;
+        for (long long q = 0; q < t.nb_tot; ++q) R = std::max(R, P.bg_ptr[q + 1] - P.bg_ptr[q]);
+        std::vector<int> gm((size_t)std::max<long long>(1, t.nb_tot) * R, 0);
+        for (long long q = 0; q < t.nb_tot; ++q)
+            for (int e = P.bg_ptr[q], u = 0; e < P.bg_ptr[q + 1]; ++e, ++u)
+                gm[q * R + u] = P.bg_sg[e] > 0 ? P.bg_row[e] + 1 : -(P.bg_row[e] + 1);
+        t.gmap = c->upload(gm);
+        t.gmap_R = R;
+    }
+    if (t.max_nc > 32) throw std::runtime_error("more than 32 corner DOFs in one subdomain");
     t.bg_ptr = c->upload(P.bg_ptr);
     t.bg_row = c->upload(P.bg_row);
     t.bg_sg = c->upload(P.bg_sg);
@@ -380,6 +426,14 @@ void build_layout(feti_ctx* c) {
     }
     t.m_tile_sub = c->upload(ts);
     t.m_tile_row = c->upload(tr);
+    t.m_tile_end = c->upload(te);
+    c->tl_low_sub = c->alloc<int>(ts.size());
+    c->tl_low_row = c->alloc<int>(ts.size());
+    c->tl_low_end = c->alloc<int>(ts.size());
+    c->tl_64_sub = c->alloc<int>(ts.size());
+    c->tl_64_row = c->alloc<int>(ts.size());
+    c->tl_64_end = c->alloc<int>(ts.size());
+    c->pivdev = c->alloc<double>(ns);
     std::vector<double> K0 = element_K0(P.dim, P.nu);
     c->K0dev = c->upload(K0);
     t.K0dev = c->K0dev;
@@ -428,7 +482,58 @@ void build_layout(feti_ctx* c) {
     c->scal = c->alloc<double>(16);
     c->rank_dev = c->alloc<int>(4);
     c->qk_ptr = c->upload(std::vector<const double*>{c->Qk});
+    c->zk_ptr = c->upload(std::vector<const double*>{c->Zk});
+    c->tcbuf = c->alloc<double>((long long)std::max(1, ncg) * kMaxDirs);
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+}
+
+void check_info(feti_ctx* c, int n, const char* what);
+
+// Round-off test of the reduced-precision operator, per subdomain: factorise F_s and its
+// rounding to the context's precision in FP64; a subdomain keeps the reduced precision only
+// if every Cholesky pivot agrees to 2 percent (otherwise rounding has reached the smallest
+// eigenvalues of F_s and its tiles run in FP64).
+void classify_precision(feti_ctx* c) {
+    DevTopo& t = c->t;
+    hipStream_t st = c->st;
+    c->hybrid = false;
+    c->n_fp64_subs = 0;
+    if (c->opts.precision == FETI_FP64 || c->P.method != FETI_DP) return;
+    launch_copy_F_rounded(t, c->F64, FETI_FP64, c->W1, st);
+    launch_copy_F_rounded(t, c->F64, c->opts.precision, c->W2, st);
+    HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * (t.n_sub + 8), st));
+    launch_potrf(c->d_potrf, t.n_sub, c->W1, c->info, st);
+    CHECK_LAUNCH();
+    check_info(c, t.n_sub, "Cholesky of F_s");
+    HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * (t.n_sub + 8), st));
+    launch_potrf(c->d_potrf, t.n_sub, c->W2, c->info, st);
+    launch_pivot_compare(t, c->W1, c->W2, c->info, c->pivdev, st);
+    CHECK_LAUNCH();
+    std::vector<double> dev(t.n_sub);
+    HIPCHK(hipMemcpyAsync(dev.data(), c->pivdev, sizeof(double) * t.n_sub, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int> ok(t.n_sub);
+    for (int s = 0; s < t.n_sub; ++s) {
+        ok[s] = dev[s] <= 2e-2 ? 1 : 0;
+        c->n_fp64_subs += 1 - ok[s];
+    }
+    std::vector<int> ts, tr, te;
+    auto upload3 = [&](int* ds, int* dr, int* de) {
+        if (ts.empty()) return;
+        HIPCHK(hipMemcpyAsync(ds, ts.data(), sizeof(int) * ts.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dr, tr.data(), sizeof(int) * tr.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(de, te.data(), sizeof(int) * te.size(), hipMemcpyHostToDevice, st));
+    };
+    // reduced precision: F_s rows of the subdomains that passed; FP64: the others' F_s rows
+    // and every F_rc^T row (the coarse right-hand side stays FP64: Kbar_cc^{-1} amplifies its errors)
+    make_tiles(c, [&](int s, bool isT) { return !isT && ok[s]; }, ts, tr, te);
+    upload3(c->tl_low_sub, c->tl_low_row, c->tl_low_end);
+    c->tl_low = TileList{c->tl_low_sub, c->tl_low_row, c->tl_low_end, (int)ts.size()};
+    make_tiles(c, [&](int s, bool isT) { return isT || !ok[s]; }, ts, tr, te);
+    upload3(c->tl_64_sub, c->tl_64_row, c->tl_64_end);
+    c->tl_64 = TileList{c->tl_64_sub, c->tl_64_row, c->tl_64_end, (int)ts.size()};
+    HIPCHK(hipStreamSynchronize(st));
+    c->hybrid = true;
 }
 
 struct Timer {
@@ -537,6 +642,7 @@ void numeric_setup(feti_ctx* c) {
     launch_swizzle(t, c->F64, c->sw64, c->sw32, c->swhi, c->swlo, st);
     launch_weights(t, c->opts.scaling == FETI_KSCALE, c->diag, c->w, c->bg_w, st);
     CHECK_LAUNCH();
+    classify_precision(c);
     if (P.method == FETI_DP && P.n_cg > 0) {
         zero(c->Kcc, (long long)P.n_cg * P.n_cg * 8);
         launch_coarse_assemble(t, c->Kc, c->Kcc, st);
@@ -554,22 +660,29 @@ void numeric_setup(feti_ctx* c) {
 
 // ---------------------------------------------------------------- operator applications
 
-// Q = F Lambda (n_lambda x k) in the given precision.
-void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool time_it = false) {
+// Q = F Lambda (n_lambda x k) in the given precision. A reduced precision uses the
+// per-subdomain selection of the setup (FP64 tiles for the subdomains that failed the
+// round-off test, FP64 outputs) unless `pure` forces every tile to the reduced precision.
+void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool time_it = false, bool pure = false) {
     DevTopo& t = c->t;
     hipStream_t st = c->st;
     const void* A = prec == FETI_FP64 ? (const void*)c->sw64 : prec == FETI_FP32 ? (const void*)c->sw32 : (const void*)c->swhi;
-    const int f32 = prec != FETI_FP64;
+    const bool hyb = prec != FETI_FP64 && !pure && c->hybrid && prec == c->opts.precision;
+    const int f32 = prec != FETI_FP64 && !hyb;
     if (time_it) HIPCHK(hipEventRecord(c->ev[2], st));
-    launch_flambda(t, prec, k, Lam, A, c->swlo, c->Ybuf, c->Tbuf, st);
+    if (hyb) {
+        launch_flambda(t, FETI_FP64, k, Lam, c->sw64, nullptr, c->Ybuf, c->Tbuf, st, &c->tl_64, 1);
+        launch_flambda(t, prec, k, Lam, A, c->swlo, c->Ybuf, c->Tbuf, st, &c->tl_low, 1);
+    } else {
+        launch_flambda(t, prec, k, Lam, A, c->swlo, c->Ybuf, c->Tbuf, st);
+    }
     CHECK_LAUNCH();
     if (time_it) HIPCHK(hipEventRecord(c->ev[3], st));
-    const double* v = nullptr;
     if (c->P.method == FETI_DP && c->P.n_cg > 0) {
-        launch_coarse(t, k, f32, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->vbuf, st);
-        v = c->vbuf;
+        launch_coarse(t, k, f32, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->vbuf, c->tcbuf, st);
+        launch_fold_coarse(t, k, f32, c->F64, c->vbuf, c->Ybuf, st);
     }
-    launch_scatter(t, k, f32, c->Ybuf, c->F64, v, Q, st);
+    launch_scatter(t, k, f32, c->Ybuf, Q, st);
     CHECK_LAUNCH();
 }
 
@@ -584,7 +697,8 @@ void project(feti_ctx* c, int k, double* Y) {
 
 void precondition(feti_ctx* c, const double* r, double* Z, int one_column, int use_f32) {
     DevTopo& t = c->t;
-    launch_precond_local(t, use_f32, r, c->bg_w, c->P64, c->P32, c->yb, c->st);
+    (void)use_f32;  // the preconditioner blocks stay FP64: FP32 rounding can make them indefinite
+    launch_precond_local(t, 0, r, c->bg_w, c->P64, c->P32, c->yb, c->st);
     launch_precond_scatter(t, one_column, c->w, c->yb, Z, c->st);
     CHECK_LAUNCH();
 }
@@ -618,15 +732,14 @@ void compute_rhs(feti_ctx* c, const double* f) {
     if (P.n_lambda > 0) {
         if (P.method == FETI_DP) {
             launch_fbar(t, c->g, c->yc, c->fbar_s, st);
-            const double* v = nullptr;
             if (P.n_cg > 0) {
-                launch_coarse(t, 1, 0, c->fbar_s, nullptr, c->Kcc_inv, -1.0, c->vbuf, st);
-                v = c->vbuf;
+                launch_coarse(t, 1, 0, c->fbar_s, nullptr, c->Kcc_inv, -1.0, c->vbuf, c->tcbuf, st);
+                launch_fold_coarse(t, 1, 0, c->F64, c->vbuf, c->yb, st);
             }
-            launch_scatter(t, 1, 0, c->yb, c->F64, v, c->d, st);
+            launch_scatter(t, 1, 0, c->yb, c->d, st);
             HIPCHK(hipMemsetAsync(c->lam0, 0, sizeof(double) * P.n_lambda, st));
         } else {
-            launch_scatter(t, 1, 0, c->yb, c->F64, nullptr, c->d, st);
+            launch_scatter(t, 1, 0, c->yb, c->d, st);
             launch_tfeti_e(t, c->fi, c->fbeta, c->Cit, c->e, st);
             launch_small_gemm(c->n_alpha, 1, c->n_alpha, c->GG_inv, c->e, c->tcoef, 1.0, st);
             HIPCHK(hipMemsetAsync(c->lam0, 0, sizeof(double) * P.n_lambda, st));
@@ -732,6 +845,7 @@ KrylovOut run_pcg(feti_ctx* c, int prec, double eps0, double tol, int max_it, st
         o.iters = it + 1;
         o.eps = std::sqrt(std::max(rz_new, 0.0));
         hist.push_back(o.eps);
+        if (verbose()) fprintf(stderr, "[feti] pcg it %d prec %d eps/eps0 %.3e\n", it + 1, prec, o.eps / eps0);
         if (o.eps <= tol * eps0) break;
         const double beta = rz_new / rz;
         rz = rz_new;
@@ -759,6 +873,8 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
     if (o.eps <= tol * eps0) return o;
     project(c, kd, c->Zk);  // W_0 = P Z_0 (in place)
     int nb = 0;
+    double best = o.eps;
+    int it_best = 0;
     for (int it = 0; it < max_it && o.kept < n; ++it) {
         ensure_history(c, kd, nb + 1);
         double* Wn = (double*)c->WH[nb];
@@ -767,7 +883,8 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
         // Delta = Q^T W
         launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
         launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st);
-        launch_apply_T(n, kd, c->Tm, c->Zk, c->Qk, Wn, Qn, st);
+        launch_ts_gemm(n, kd, 1, c->zk_ptr, c->Tm, nullptr, Wn, 1.0, 0.0, st);
+        launch_ts_gemm(n, kd, 1, c->qk_ptr, c->Tm, nullptr, Qn, 1.0, 0.0, st);
         // gamma = W^T r
         launch_gram(n, kd, 1, c->WH_dev + nb, 1, c->r, c->part, c->gam, st);
         if (c->P.method == FETI_TFETI) {
@@ -786,7 +903,7 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
         project(c, kd, c->Zk);
         for (int pass = 0; pass < passes; ++pass) {
             launch_gram(n, kd, kd, c->QH_dev, nb, c->Zk, c->part, c->Psi, st);
-            launch_orth_update(n, kd, c->WH_dev, nb, c->Psi, c->Zk, st);
+            launch_ts_gemm(n, kd, nb, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st);
         }
         CHECK_LAUNCH();
         int rank = 0;
@@ -796,6 +913,9 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
         HIPCHK(hipStreamSynchronize(st));
         ranks.push_back(rank);
         o.iters = it + 1;
+        if (verbose())
+            fprintf(stderr, "[feti] sfeti it %d prec %d rank %d eps/eps0 %.3e\n", it + 1, prec, rank,
+                    std::sqrt(std::max(ez, 0.0)) / eps0);
         if (rank == 0) {
             o.status = FETI_EBREAKDOWN;
             break;
@@ -804,6 +924,15 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
         o.eps = std::sqrt(std::max(ez, 0.0));
         hist.push_back(o.eps);
         if (o.eps <= tol * eps0) break;
+        if (o.eps < 0.9 * best) {
+            best = o.eps;
+            it_best = it;
+        }
+        // a reduced-precision pass that diverges or stalls ends here; the caller restarts in FP64
+        if (prec != FETI_FP64 && (o.eps > 1e3 * best || it - it_best > 30)) {
+            o.status = FETI_ENOCONV;
+            break;
+        }
     }
     return o;
 }
@@ -823,9 +952,9 @@ void recover(feti_ctx* c, double* u) {
             if (P.n_lambda > 0) {
                 launch_flambda(t, FETI_FP64, 1, c->lam, c->sw64, nullptr, c->Ybuf, c->Tbuf, st);
                 launch_axpby(t.nc_tot, 1.0, c->fbar_s, 1.0, c->Tbuf, st);
-                launch_coarse(t, 1, 0, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->uc, st);
+                launch_coarse(t, 1, 0, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->uc, c->tcbuf, st);
             } else {
-                launch_coarse(t, 1, 0, c->fbar_s, nullptr, c->Kcc_inv, 1.0, c->uc, st);
+                launch_coarse(t, 1, 0, c->fbar_s, nullptr, c->Kcc_inv, 1.0, c->uc, c->tcbuf, st);
             }
         }
         launch_dp_ub(t, c->F64, c->S, c->g, c->xb, c->uc, c->ubeta, st);
@@ -856,7 +985,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
     std::vector<double> hist;
     std::vector<int> ranks;
     KrylovOut tot;
-    int refinements = 0;
+    int refinements = 0, fallback = 0;
     double eps0 = 0.0, true_rel = 0.0;
     int status = FETI_OK;
     if (n > 0) {
@@ -871,16 +1000,21 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         hist.push_back(eps0);
         const double tol = c->opts.tol > 0 ? c->opts.tol : 1e-8;
         int max_it = c->opts.max_it > 0 ? c->opts.max_it : n;
-        const int max_ref = prec == FETI_FP64 ? 0 : (c->opts.max_refine >= 0 ? c->opts.max_refine : 4);
+        const int max_ref = c->opts.max_refine >= 0 ? c->opts.max_refine : 4;
+        // Mixed precision: each pass runs the Krylov iteration with the reduced-precision
+        // operator on the current FP64 residual; a pass that breaks down, or whose FP64 true
+        // residual does not contract by 10x, hands over to the FP64 operator.
+        int cur = prec;
+        double prev_rel = 1.0;
         if (eps0 > 0.0) {
             for (int pass = 0;; ++pass) {
                 HIPCHK(hipMemsetAsync(c->lt, 0, sizeof(double) * n, st));
                 KrylovOut o;
                 const int left = max_it - tot.iters;
                 if (c->opts.krylov == FETI_PCG)
-                    o = run_pcg(c, prec, eps0, tol, left, hist);
+                    o = run_pcg(c, cur, eps0, tol, left, hist);
                 else
-                    o = run_sfeti(c, prec, kd, eps0, tol, left, hist, ranks);
+                    o = run_sfeti(c, cur, kd, eps0, tol, left, hist, ranks);
                 tot.iters += o.iters;
                 tot.kept += o.kept;
                 tot.eps = o.eps;
@@ -892,15 +1026,30 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
                 ddot(c, n, c->r, c->zv, 0);
                 const double et = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
                 true_rel = et / eps0;
-                if (o.status != FETI_OK) {
-                    status = o.status;
+                if (verbose())
+                    fprintf(stderr, "[feti] pass %d prec %d iters %d status %d true rel. residual %.3e\n", pass, cur,
+                            o.iters, o.status, true_rel);
+                if (true_rel <= tol) {
+                    status = FETI_OK;
                     break;
                 }
-                if (true_rel <= tol) break;
-                if (pass >= max_ref || tot.iters >= max_it) {
+                if (tot.iters >= max_it) {
+                    status = o.status != FETI_OK ? o.status : FETI_ENOCONV;
+                    break;
+                }
+                if (cur != FETI_FP64) {
+                    if (o.status != FETI_OK || !(true_rel < 0.1 * prev_rel) || refinements >= max_ref) {
+                        cur = FETI_FP64;
+                        ++fallback;
+                    }
+                } else if (o.status != FETI_OK) {
+                    status = o.status;
+                    break;
+                } else if (pass > max_ref + 1) {
                     status = FETI_ENOCONV;
                     break;
                 }
+                prev_rel = true_rel;
                 ++refinements;
             }
         }
@@ -919,6 +1068,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         info->eps = tot.eps;
         info->true_rel_res = true_rel;
         info->kept_directions = tot.kept;
+        info->fp64_fallback = fallback;
         if (info->res_hist && info->res_hist_cap > 0)
             for (int i = 0; i < (int)hist.size() && i < info->res_hist_cap; ++i) info->res_hist[i] = hist[i];
         if (info->rank_hist && info->res_hist_cap > 0)
@@ -1117,6 +1267,7 @@ feti_status feti_get_sizes(feti_ctx* c, feti_sizes* out) {
     z.sum_nb2 = P.sum_nb2();
     z.sum_nb_nc = P.sum_nb_nc();
     z.device_bytes = c->bytes;
+    z.n_fp64_subs = c->n_fp64_subs;
     *out = z;
     return FETI_OK;
 }
@@ -1124,11 +1275,13 @@ feti_status feti_get_sizes(feti_ctx* c, feti_sizes* out) {
 feti_status feti_apply_F(feti_ctx* c, int k, int precision, const double* Lambda, double* Q) {
     if (!c || !Lambda || !Q) return fail(FETI_EINVAL, "null argument");
     if (k < 1 || k > kMaxDirs) return fail(FETI_EINVAL, "k must lie in [1, 64]");
+    const bool pure = (precision & FETI_PURE) != 0;
+    precision &= ~FETI_PURE;
     if (precision != FETI_FP64 && precision != FETI_FP32 && precision != FETI_BF16X3)
         return fail(FETI_EINVAL, "unknown precision");
     return guarded([&]() -> feti_status {
         HIPCHK(hipEventRecord(c->ev[0], c->st));
-        apply_F(c, k, precision, Lambda, Q, true);
+        apply_F(c, k, precision, Lambda, Q, true, pure);
         HIPCHK(hipEventRecord(c->ev[1], c->st));
         HIPCHK(hipEventSynchronize(c->ev[1]));
         float a = 0, b = 0;
@@ -1197,7 +1350,7 @@ feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long 
                 nr = M.n_b;
                 nc = M.n_c;
                 for (int j = 0; j < M.n_b; ++j)
-                    for (int q = 0; q < M.n_c; ++q) v.push_back(F[(long long)(M.n_b + q) * M.ldF + j]);
+                    for (int q = 0; q < M.n_c; ++q) v.push_back(F[(long long)(M.rowT + q) * M.ldF + j]);
             }
         } else if (what == 1) {
             const SubMeta& M = c->hsubs[s];

@@ -11,7 +11,7 @@ namespace feti {
 constexpr int kGramRows = 32;   // rows staged per LDS step
 
 int gram_chunks(int n, int nblk) {
-    return std::max(1, std::min({256, 2048 / std::max(1, nblk), (n + 255) / 256}));
+    return std::max(1, std::min({256, 4096 / std::max(1, nblk), (n + 255) / 256}));
 }
 
 // part[(b*nchunk + c)][ka x kb] = A_b[rows of chunk c]^T B[rows of chunk c], ka, kb <= 64.
@@ -73,12 +73,144 @@ __global__ void k_gram_reduce(int nchunk, int nblk, int ka, int kb, const double
     out[idx] = v;
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Matrix-core (FP64 MFMA 16x16x4) tall-skinny products of the block Gram-Schmidt step.
+// Operand layouts of v_mfma_f64_16x16x4f64: A (16x4): lane l holds A[l%16][l/16];
+// B (4x16): lane l holds B[l/16][l%16]; D (16x16): lane l holds D[l/16 + 4v][l%16].
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+// part[(b*nchunk + c)][ka x kb] = A_b[rows of c]^T B[rows of c]. The chunk is walked in
+// 64-row tiles staged through LDS; the next tile is loaded into registers while the matrix
+// cores work on the current one. Wave w computes rows 16w..16w+15 of the ka x kb result.
+__global__ void __launch_bounds__(256) k_gram_mfma(int n, int ka, int kb, const double* const* __restrict__ Aptrs,
+                                                   const double* __restrict__ B, double* __restrict__ part) {
+    __shared__ double As[64][65];
+    __shared__ double Bs[64][65];
+    const int nchunk = gridDim.x, c = blockIdx.x, b = blockIdx.y;
+    const double* A = Aptrs[b];
+    const int rows_per = ((n + nchunk - 1) / nchunk + 63) & ~63;
+    const int r0 = c * rows_per, r1 = min(n, r0 + rows_per);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    v4d_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = v4d_t{0.0, 0.0, 0.0, 0.0};
+    double ra[16], rb[16];
+    auto load = [&](int t0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, rr = e >> 6, cc = e & 63;
+            const int row = t0 + rr;
+            ra[u] = (row < r1 && cc < ka) ? A[(long long)row * ka + cc] : 0.0;
+            rb[u] = (row < r1 && cc < kb) ? B[(long long)row * kb + cc] : 0.0;
+        }
+    };
+    if (r0 < r1) load(r0);
+    for (int t0 = r0; t0 < r1; t0 += 64) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, rr = e >> 6, cc = e & 63;
+            As[rr][cc] = ra[u];
+            Bs[rr][cc] = rb[u];
+        }
+        __syncthreads();
+        if (t0 + 64 < r1) load(t0 + 64);
+        if (16 * wave < ka) {
+#pragma unroll 4
+            for (int k0 = 0; k0 < 64; k0 += 4) {
+                const double a = As[k0 + (lane >> 4)][16 * wave + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double bv = Bs[k0 + (lane >> 4)][16 * j + (lane & 15)];
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    double* out = part + (long long)(b * nchunk + c) * ka * kb;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * wave + (lane >> 4) + 4 * v, jj = 16 * j + (lane & 15);
+            if (i < ka && jj < kb) out[i * kb + jj] = acc[j][v];
+        }
+}
+
+// out = beta C + alpha sum_b A_b M_b  (A_b: n x kd row-major via Aptrs, M_b = Mats + b*kd*kd,
+// C and out n x kd, out may alias C). Workgroup = 64 rows; A_b rows are staged through LDS
+// (transposed) so that the A operand is read conflict-free, and the next block is loaded into
+// registers while the matrix cores work on the current one; the accumulators stay in
+// registers across all blocks b.
+__global__ void __launch_bounds__(256) k_ts_gemm(int n, int kd, int nblk, const double* const* __restrict__ Aptrs,
+                                                 const double* __restrict__ Mats, const double* C, double* out,
+                                                 double alpha, double beta) {
+    __shared__ double As[64][65];   // As[col][row]
+    __shared__ double Ms[64][64];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r0 = blockIdx.x * 64;
+    v4d_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = v4d_t{0.0, 0.0, 0.0, 0.0};
+    double ra[16], rm[16];
+    auto load = [&](int b) {
+        const double* A = Aptrs[b];
+        const double* Mb = Mats + (long long)b * kd * kd;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, rr = e >> 6, cc = e & 63;
+            const int row = r0 + rr;
+            ra[u] = (row < n && cc < kd) ? A[(long long)row * kd + cc] : 0.0;
+            rm[u] = (rr < kd && cc < kd) ? Mb[rr * kd + cc] : 0.0;
+        }
+    };
+    if (nblk > 0) load(0);
+    for (int b = 0; b < nblk; ++b) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, rr = e >> 6, cc = e & 63;
+            As[cc][rr] = ra[u];
+            Ms[rr][cc] = rm[u];
+        }
+        __syncthreads();
+        if (b + 1 < nblk) load(b + 1);
+        for (int k0 = 0; k0 < kd; k0 += 4) {
+            const double a = As[k0 + (lane >> 4)][16 * wave + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double bv = Ms[k0 + (lane >> 4)][16 * j + (lane & 15)];
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = r0 + 16 * wave + (lane >> 4) + 4 * v, col = 16 * j + (lane & 15);
+            if (row < n && col < kd) {
+                const long long idx = (long long)row * kd + col;
+                out[idx] = (beta == 0.0 ? 0.0 : beta * C[idx]) + alpha * acc[j][v];
+            }
+        }
+}
+
+void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
+                    double* out, double alpha, double beta, hipStream_t st) {
+    if (n && nblk) k_ts_gemm<<<(n + 63) / 64, 256, 0, st>>>(n, kd, nblk, Aptrs, Mats, C, out, alpha, beta);
+}
+
 void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
                  double* out, hipStream_t st) {
     if (nblk == 0) return;
     const int nchunk = gram_chunks(n, nblk);
     if ((long long)nchunk * nblk * ka * kb > kGramPartCap) throw std::length_error("Gram partial buffer too small");
-    k_gram<<<dim3(nchunk, nblk), 256, 0, st>>>(n, ka, kb, Aptrs, B, part);
+    if (ka >= 16 && kb >= 16)
+        k_gram_mfma<<<dim3(nchunk, nblk), 256, 0, st>>>(n, ka, kb, Aptrs, B, part);
+    else
+        k_gram<<<dim3(nchunk, nblk), 256, 0, st>>>(n, ka, kb, Aptrs, B, part);
     const long long tot = (long long)ka * kb * nblk;
     k_gram_reduce<<<(int)((tot + 255) / 256), 256, 0, st>>>(nchunk, nblk, ka, kb, part, out);
 }

@@ -397,13 +397,13 @@ __global__ void __launch_bounds__(256) k_frc(const SubMeta* __restrict__ subs, c
         const int c = (int)(e / nb), j = (int)(e % nb);
         double v = 0.0;
         for (int q = 0; q < nb; ++q) v += S[(long long)(nb + c) * M.n_beta + q] * F[(long long)q * M.ldF + j];
-        F[(long long)(nb + c) * M.ldF + j] = v;
+        F[(long long)(M.rowT + c) * M.ldF + j] = v;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nc * nc; e += 256) {
         const int c = e / nc, c2 = e % nc;
         double v = S[(long long)(nb + c) * M.n_beta + nb + c2];
-        for (int j = 0; j < nb; ++j) v -= F[(long long)(nb + c) * M.ldF + j] * S[(long long)j * M.n_beta + nb + c2];
+        for (int j = 0; j < nb; ++j) v -= F[(long long)(M.rowT + c) * M.ldF + j] * S[(long long)j * M.n_beta + nb + c2];
         Kc[M.off_Kc + e] = v;
     }
 }
@@ -420,14 +420,14 @@ __global__ void k_swizzle(const SubMeta* __restrict__ subs, const double* __rest
     const SubMeta M = subs[s];
     const long long tot = (long long)M.rows_F * M.ldF;
     const int KQ = M.ldF / 16, KB = M.ldF / 32;
-    const int nrow = M.n_b + M.n_c;
+    auto live = [&](int row) { return row < M.n_b || (row >= M.rowT && row < M.rowT + M.n_c); };
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
         {
             const int q = (int)(e & 3), lane = (int)((e >> 2) & 63);
             const long long blk = e >> 8;
             const int rb = (int)(blk / KQ), kq = (int)(blk % KQ);
             const int row = 16 * rb + (lane & 15), col = 16 * kq + 4 * q + (lane >> 4);
-            const double v = (row < nrow && col < M.n_b) ? F64[M.off_F + (long long)row * M.ldF + col] : 0.0;
+            const double v = (live(row) && col < M.n_b) ? F64[M.off_F + (long long)row * M.ldF + col] : 0.0;
             sw64[M.off_Fsw + e] = v;
             sw32[M.off_Fsw + e] = (float)v;
         }
@@ -436,7 +436,7 @@ __global__ void k_swizzle(const SubMeta* __restrict__ subs, const double* __rest
             const long long blk = e >> 9;
             const int rb = (int)(blk / KB), kb = (int)(blk % KB);
             const int row = 16 * rb + (lane & 15), col = 32 * kb + 8 * (lane >> 4) + q;
-            const double v = (row < nrow && col < M.n_b) ? F64[M.off_F + (long long)row * M.ldF + col] : 0.0;
+            const double v = (live(row) && col < M.n_b) ? F64[M.off_F + (long long)row * M.ldF + col] : 0.0;
             const float vf = (float)v;
             const __hip_bfloat16 hi = __float2bfloat16(vf);
             const __hip_bfloat16 lo = __float2bfloat16(vf - __bfloat162float(hi));
@@ -541,6 +541,49 @@ __global__ void k_ggt_assemble(int n_sub, int nm, const SubMeta* __restrict__ su
     }
 }
 
+// dst[s] = round_P(F_s), leading n_b x n_b block of the augmented operator, ld n_b.
+__global__ void k_copy_F_rounded(const SubMeta* __restrict__ subs, const double* __restrict__ F64, int precision,
+                                 double* dst) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const long long nn = (long long)M.n_b * M.n_b;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / M.n_b), j = (int)(e % M.n_b);
+        const double v = F64[M.off_F + (long long)i * M.ldF + j];
+        double r = v;
+        if (precision == FETI_FP32) {
+            r = (double)(float)v;
+        } else if (precision == FETI_BF16X3) {
+            const float vf = (float)v;
+            const float hi = __bfloat162float(__float2bfloat16(vf));
+            const float lo = __bfloat162float(__float2bfloat16(vf - hi));
+            r = (double)hi + (double)lo;
+        }
+        dst[M.off_P + e] = r;
+    }
+}
+
+// Per-subdomain round-off test: largest relative change of a Cholesky pivot.
+__global__ void k_pivot_compare(const SubMeta* __restrict__ subs, const double* __restrict__ W1,
+                                const double* __restrict__ W2, const int* __restrict__ info2, double* dev) {
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    double m = 0.0;
+    for (int j = threadIdx.x; j < M.n_b; j += 256) {
+        const double a = W1[M.off_P + (long long)j * M.n_b + j], b = W2[M.off_P + (long long)j * M.n_b + j];
+        const double r = fabs((b * b) / (a * a) - 1.0);
+        m = fmax(m, r == r ? r : 1e300);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int u = 0; u < 256; ++u) v = fmax(v, red[u]);
+        dev[s] = info2[s] ? 1e300 : v;
+    }
+}
+
 __global__ void k_set_identity(double* A, int n, long long lda) {
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= (long long)n * n) return;
@@ -627,6 +670,15 @@ void launch_coarse_assemble(const DevTopo& t, const double* Kc, double* Kg, hipS
 void launch_ggt_assemble(const DevTopo& t, const double* Rb, double* GG, hipStream_t st) {
     k_ggt_assemble<<<(t.n_sub + 63) / 64, 64, 0, st>>>(t.n_sub, t.dim == 2 ? 3 : 6, t.subs, t.bg_ptr, t.bg_row,
                                                        t.bg_sg, t.row_s, t.row_j, t.row_sg, Rb, GG);
+}
+
+void launch_copy_F_rounded(const DevTopo& t, const double* F64, int precision, double* dst, hipStream_t st) {
+    k_copy_F_rounded<<<dim3(64, t.n_sub), 256, 0, st>>>(t.subs, F64, precision, dst);
+}
+
+void launch_pivot_compare(const DevTopo& t, const double* W1, const double* W2, const int* info2, double* dev,
+                          hipStream_t st) {
+    k_pivot_compare<<<t.n_sub, 256, 0, st>>>(t.subs, W1, W2, info2, dev);
 }
 
 void launch_set_identity(double* A, int n, long long lda, hipStream_t st) {

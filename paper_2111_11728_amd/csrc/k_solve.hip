@@ -155,7 +155,8 @@ __global__ void __launch_bounds__(256) k_local_F(const SubMeta* __restrict__ sub
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (row >= M.n_b + M.n_c) return;
     const long long ob = M.off_b + M.off_c;
-    const double* Fr = F64 + M.off_F + (long long)row * M.ldF;
+    const int prow = row < M.n_b ? row : M.rowT + row - M.n_b;   // physical row of F_rc^T entries
+    const double* Fr = F64 + M.off_F + (long long)prow * M.ldF;
     double v = 0.0;
     for (int j = lane; j < M.n_b; j += 64) v += Fr[j] * g[ob + j];
     v = warp_sum(v);

@@ -12,6 +12,14 @@
 
 namespace feti {
 
+// A list of 128-row tiles of the augmented local operators (subdomain, first row).
+struct TileList {
+    const int* sub = nullptr;
+    const int* row = nullptr;   // first row of the tile
+    const int* end = nullptr;   // one past the last row the tile may touch
+    int n = 0;
+};
+
 // Descriptors of batched dense operations (offsets in elements from a base pointer).
 struct GemmDesc {   // C[m x n] = beta C + alpha A^T B, A: k x m (lda), B: k x n (ldb), row-major
     long long a, b, c;
@@ -60,8 +68,11 @@ struct DevTopo {
     const int* cc_j = nullptr;
     const int* ax_first[3] = {nullptr, nullptr, nullptr};
     const int* ax_cnt[3] = {nullptr, nullptr, nullptr};
+    const int* gmap = nullptr;        // fixed-width gather map: gmap[q*gmap_R + t] = sign*(row+1), 0 unused
+    int gmap_R = 1;
     const int* m_tile_sub = nullptr;  // F*Lambda work list: subdomain of every 128-row tile
     const int* m_tile_row = nullptr;  // first row of the tile
+    const int* m_tile_end = nullptr;  // one past the last row of the tile
     int n_m_tiles = 0;
 };
 
@@ -90,14 +101,25 @@ void launch_set_identity(double* A, int n, long long lda, hipStream_t st);
 
 // ---- operator application (k_apply.hip) ----
 // Y/T outputs of the local products: Y [nb_tot x k], T [nc_tot x k], row-major, type by precision.
+// tl = nullptr: every tile of the topology; out_f64: write Y/T in FP64 whatever the precision
 void launch_flambda(const DevTopo& t, int precision, int k, const double* Lambda, const void* Fsw,
-                    const void* Fsw_lo, void* Y, void* T, hipStream_t st);
-// t = add + sum_s B_c^sT T_s (n_cg x k), v = scale * Kinv t
+                    const void* Fsw_lo, void* Y, void* T, hipStream_t st, const TileList* tl = nullptr,
+                    int out_f64 = 0);
+// Copy F_s (leading n_b x n_b block of the augmented operator) into dst (ld n_b), rounded to
+// the given precision (FP64: exact; FP32; BF16X3: hi + lo split) and back to FP64.
+void launch_copy_F_rounded(const DevTopo& t, const double* F64, int precision, double* dst, hipStream_t st);
+// dev[s] = max_j |L2_jj^2 / L1_jj^2 - 1| over the Cholesky factors L1 (exact) and L2 (rounded)
+// stored in W1 / W2 (infinite if info2[s] != 0)
+void launch_pivot_compare(const DevTopo& t, const double* W1, const double* W2, const int* info2, double* dev,
+                          hipStream_t st);
+// t = add + sum_s B_c^sT T_s (n_cg x k, in tbuf), v = scale * Kinv t
 void launch_coarse(const DevTopo& t, int k, int ytype_f32, const void* T, const double* add, const double* Kinv,
-                   double scale, double* v, hipStream_t st);
-// Q[row] = sum over sides sign * (Y[b] + F_rc[b,:] . v[corners])   (v may be null)
-void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, const double* F64, const double* v,
-                    double* Q, hipStream_t st);
+                   double scale, double* v, double* tbuf, hipStream_t st);
+// Y_s += F_rc^s v_s (coarse correction folded into the local products)
+void launch_fold_coarse(const DevTopo& t, int k, int ytype_f32, const double* F64, const double* v, void* Y,
+                        hipStream_t st);
+// Q[row] = sum over sides sign * Y[b]
+void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, double* Q, hipStream_t st);
 // x_s = B~^sT r gathered and multiplied: y_s = P_s x_s  (P_s FP64 or FP32)
 void launch_precond_local(const DevTopo& t, int use_f32, const double* r, const double* bg_w, const double* P64,
                           const float* P32, double* y, hipStream_t st);
@@ -117,7 +139,10 @@ void launch_proj_apply(const DevTopo& t, int k, const double* tcoef, const doubl
 void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
                  double* out, hipStream_t st);
 int gram_chunks(int n, int nblk);
-constexpr long long kGramPartCap = 2048ll * kMaxDirs * kMaxDirs;   // doubles in the partial-sum buffer
+constexpr long long kGramPartCap = 4096ll * kMaxDirs * kMaxDirs;   // doubles in the partial-sum buffer
+// out = beta C + alpha sum_b A_b M_b (FP64 matrix cores), A_b n x kd, M_b kd x kd
+void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
+                    double* out, double alpha, double beta, hipStream_t st);
 void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st);
 void launch_apply_T(int n, int k, const double* T, const double* W, const double* Q, double* Wo, double* Qo,
                     hipStream_t st);

@@ -22,6 +22,7 @@ FETI_MULT, FETI_KSCALE = 0, 1
 FETI_PCG, FETI_FO, FETI_SFETI = 0, 1, 2
 FETI_DIRICHLET, FETI_LUMPED = 0, 1
 FETI_FP64, FETI_FP32, FETI_BF16X3 = 0, 1, 2
+FETI_PURE = 16
 
 METHODS = {"tfeti": FETI_TFETI, "fetidp": FETI_DP}
 SCALINGS = {"mult": FETI_MULT, "k": FETI_KSCALE}
@@ -49,14 +50,14 @@ class feti_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("refinements", C.c_int), ("status", C.c_int), ("eps0", C.c_double),
                 ("eps", C.c_double), ("true_rel_res", C.c_double), ("kept_directions", C.c_int),
                 ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int), ("rank_hist", C.POINTER(C.c_int)),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("fp64_fallback", C.c_int)]
 
 
 class feti_sizes(C.Structure):
     _fields_ = [("n_sub", C.c_int), ("n_dof", C.c_int), ("n_el", C.c_int), ("n_lambda", C.c_int), ("n_cg", C.c_int),
                 ("n_alpha", C.c_int), ("n_groups", C.c_int), ("nb_max", C.c_int), ("nb_min", C.c_int),
                 ("n_loc_max", C.c_int), ("n_i_max", C.c_int), ("band_max", C.c_int), ("sum_nb2", C.c_longlong),
-                ("sum_nb_nc", C.c_longlong), ("device_bytes", C.c_longlong)]
+                ("sum_nb_nc", C.c_longlong), ("device_bytes", C.c_longlong), ("n_fp64_subs", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -214,16 +215,19 @@ class Context:
         n = min(hist_cap, info.iters + 1)
         return {"status": st, "iters": info.iters, "refinements": info.refinements, "eps0": info.eps0,
                 "eps": info.eps, "true_rel_res": info.true_rel_res, "kept_directions": info.kept_directions,
-                "history": hist[:n].copy(), "ranks": ranks[:info.iters].copy(), "t_solve_ms": info.t_solve_ms}
+                "history": hist[:n].copy(), "ranks": ranks[:info.iters].copy(), "t_solve_ms": info.t_solve_ms,
+                "fp64_fallback": info.fp64_fallback}
 
     def feti_compliance_and_grad(self, rho, f, c, dc, u=None):
         info = feti_info()
         st = _check(lib().feti_compliance_and_grad(self.handle, _ptr(rho), _ptr(f), _ptr(c), _ptr(dc), _ptr(u),
                                                    C.byref(info)), allow=(FETI_ENOCONV,))
-        return {"status": st, "iters": info.iters, "true_rel_res": info.true_rel_res}
+        return {"status": st, "iters": info.iters, "true_rel_res": info.true_rel_res,
+                "refinements": info.refinements, "fp64_fallback": info.fp64_fallback}
 
-    def feti_apply_F(self, k, precision, Lam, Q):
-        _check(lib().feti_apply_F(self.handle, k, PRECISIONS.get(precision, precision), _ptr(Lam), _ptr(Q)))
+    def feti_apply_F(self, k, precision, Lam, Q, pure=False):
+        p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)
+        _check(lib().feti_apply_F(self.handle, k, p, _ptr(Lam), _ptr(Q)))
 
     def feti_apply_precond(self, r, Z, one_column):
         _check(lib().feti_apply_precond(self.handle, _ptr(r), _ptr(Z), int(one_column)))
