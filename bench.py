@@ -121,19 +121,22 @@ def main():
     Q = torch.zeros_like(L)
     flops = flambda_work(sizes, k)
     fl = {}
-    for prec in ["fp64", "fp32", "bf16x3"]:
+    # pure: every row block in the named precision (the kernel rate); "fp32_solve": the form the
+    # mixed solve applies (FP32 where the round-off test allows, FP64 F_rc^T rows and the rest)
+    for name, prec, pure in [("fp64", "fp64", True), ("fp32", "fp32", True), ("bf16x3", "bf16x3", True),
+                             ("fp32_solve", "fp32", False)]:
         for _ in range(3):
-            ctx.feti_apply_F(k, prec, L, Q)
+            ctx.feti_apply_F(k, prec, L, Q, pure=pure)
         kern, tot = [], []
         for _ in range(args.flambda_reps):
-            ctx.feti_apply_F(k, prec, L, Q)
+            ctx.feti_apply_F(k, prec, L, Q, pure=pure)
             kern.append(ctx.feti_last_timing(0))
             tot.append(ctx.feti_last_timing(1))
         km, tm = float(np.mean(kern)), float(np.mean(tot))
-        log(f"F*Lambda {prec}: kernel {1e3 * km:.1f} us, total {1e3 * tm:.1f} us")
+        log(f"F*Lambda {name}: kernel {1e3 * km:.1f} us, total {1e3 * tm:.1f} us")
         elem = 8 if prec == "fp64" else 4
         bytes_ = elem * sizes["sum_nb2"] + 2 * 8 * n_l * k
-        fl[prec] = {"kernel_us": 1e3 * km, "total_us": 1e3 * tm,
+        fl[name] = {"kernel_us": 1e3 * km, "total_us": 1e3 * tm,
                     "gflops_kernel": flops / (km * 1e-3) / 1e9, "gflops_total": flops / (tm * 1e-3) / 1e9,
                     "frac_peak_kernel": flops / (km * 1e-3) / 1e12 / PEAK[prec],
                     "hbm_gbs_kernel": bytes_ / (km * 1e-3) / 1e9}

@@ -87,6 +87,11 @@ typedef struct {
                                  directions (1 or 2; 0 = 2) */
     int max_refine;           /* mixed precision: FP64 residual restarts with the reduced-precision
                                  operator after the first pass (< 0: 4); further passes use FP64 */
+    double relax;             /* mixed precision: an iteration applies the FP64 operator while
+                                 sqrt(r^T z) > relax * sqrt(r_0^T z_0) and the reduced-precision one
+                                 below it, so the large early steps carry no reduced-precision
+                                 error into lambda (<= 0: min(1, 0.1 tol / delta) with delta = 1e-5
+                                 for FETI_FP32 and 1e-3 for FETI_BF16X3) */
 } feti_opts;
 
 typedef struct {
@@ -103,6 +108,7 @@ typedef struct {
     double t_solve_ms;        /* wall time of feti_solve on the host clock */
     int fp64_fallback;        /* 1 if a reduced-precision pass broke down or stagnated and the
                                  solve was finished with the FP64 operator */
+    int reduced_iters;        /* iterations that applied the reduced-precision operator */
 } feti_info;
 
 typedef struct {

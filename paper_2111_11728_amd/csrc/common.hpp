@@ -21,8 +21,8 @@ struct SubMeta {
     int n_loc, n_i, n_b, n_c, n_beta, grp;
     int n_lines;        // block-tridiagonal blocks of K_ii (grid rows in 2D, planes in 3D)
     int ldF;            // leading dimension (columns) of the row-major F_s storage, n_b rounded up to 16
-    int rows_F;         // rows of the augmented operator [F_s; F_rc^T]: rowT + n_c rounded up to 16
-    int rowT;           // first row of F_rc^T (n_b rounded up to 16; rows n_b..rowT-1 are zero)
+    int rows_F;         // rows of the augmented operator [F_s; F_rc^T]: n_b + n_c rounded up to 16
+    int rowT;           // first row of F_rc^T (= n_b: the corner rows follow F_s directly)
     long long off_loc, off_i, off_b, off_c;   // prefix offsets of the per-DOF arrays
     long long line0;    // first entry of this subdomain in the line table
     long long off_L;    // block-tridiagonal factor storage (doubles)

@@ -153,9 +153,11 @@ struct feti_ctx {
     double* tcbuf = nullptr;            // coarse right-hand sides t (n_cg x k)
     // per-subdomain precision selection for the reduced-precision F*Lambda (FETI-DP)
     double* pivdev = nullptr;
-    int *tl_low_sub = nullptr, *tl_low_row = nullptr, *tl_low_end = nullptr;
-    int *tl_64_sub = nullptr, *tl_64_row = nullptr, *tl_64_end = nullptr;
-    TileList tl_low, tl_64;
+    // hybrid F*Lambda work lists: reduced rows where safe, and the FP64 rest (owned buffers)
+    FlTile* fl_hyb_red_dev = nullptr;
+    FlTile* fl_hyb_64_dev = nullptr;
+    int fl_hyb_red_cap = 0, fl_hyb_64_cap = 0;
+    FlTiles fl_hyb_red, fl_hyb_64;
     bool hybrid = false;
     int n_fp64_subs = 0;
     long long psi_cap = 0;
@@ -191,6 +193,8 @@ struct feti_ctx {
         if (WH_dev) hipFree(WH_dev);
         if (QH_dev) hipFree(QH_dev);
         if (Psi) hipFree(Psi);
+        if (fl_hyb_red_dev) hipFree(fl_hyb_red_dev);
+        if (fl_hyb_64_dev) hipFree(fl_hyb_64_dev);
         for (auto& e : ev)
             if (e) hipEventDestroy(e);
     }
@@ -198,37 +202,35 @@ struct feti_ctx {
 
 namespace {
 
-// XCD-aware list of 128-row tiles (subdomain s runs on XCD s % 8; dummy tiles pad the
-// interleaving). A subdomain contributes tiles over its F_s rows [0, rowT) and, when it has
-// corners, over its F_rc^T rows [rowT, rows_F); keep(s, is_T) selects which.
-template <typename Keep>
-void make_tiles(const feti_ctx* c, Keep keep, std::vector<int>& ts, std::vector<int>& tr, std::vector<int>& te) {
-    struct Tl { int s, r0, end; };
-    std::vector<std::vector<Tl>> bucket(8);
-    for (int s = 0; s < (int)c->hsubs.size(); ++s) {
-        const SubMeta& M = c->hsubs[s];
-        if (keep(s, false))
-            for (int r0 = 0; r0 < M.rowT; r0 += 128) bucket[s % 8].push_back({s, r0, M.rowT});
-        if (M.rows_F > M.rowT && keep(s, true))
-            for (int r0 = M.rowT; r0 < M.rows_F; r0 += 128) bucket[s % 8].push_back({s, r0, M.rows_F});
+// Packs per-subdomain row-block ranges into F*Lambda tiles. The tiles of subdomain s sit at
+// positions congruent to s mod 8 (workgroup i runs on XCD i mod 8), so the tiles that gather
+// the same X_s share one L2; uneven buckets are padded with empty slots.
+struct RbRange {
+    int red0, n_red, d0, n_d;
+};
+// max_d caps the FP64 row blocks of one tile (small tiles spread FP64 work over many CUs).
+std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, int max_d = kFlWaves) {
+    std::vector<std::vector<FlTile>> bucket(8);
+    for (int s = 0; s < (int)rr.size(); ++s) {
+        RbRange r = rr[s];
+        while (r.n_red > 0 || r.n_d > 0) {
+            FlTile T{s, r.red0, std::min(r.n_red, 2 * kFlWaves), r.d0, 0, flags, 0, 0};
+            T.n_d = std::min({r.n_d, max_d, kFlWaves - (T.n_red + 1) / 2});
+            r.red0 += T.n_red;
+            r.n_red -= T.n_red;
+            r.d0 += T.n_d;
+            r.n_d -= T.n_d;
+            bucket[s % 8].push_back(T);
+        }
     }
     size_t mx = 0;
     for (auto& b : bucket) mx = std::max(mx, b.size());
-    ts.clear();
-    tr.clear();
-    te.clear();
+    std::vector<FlTile> out;
     for (size_t i = 0; i < mx; ++i)
-        for (int x = 0; x < 8; ++x) {
-            const bool in = i < bucket[x].size();
-            ts.push_back(in ? bucket[x][i].s : -1);
-            tr.push_back(in ? bucket[x][i].r0 : 0);
-            te.push_back(in ? bucket[x][i].end : 0);
-        }
-    while (!ts.empty() && ts.back() < 0) {
-        ts.pop_back();
-        tr.pop_back();
-        te.pop_back();
-    }
+        for (int x = 0; x < 8; ++x)
+            out.push_back(i < bucket[x].size() ? bucket[x][i] : FlTile{-1, 0, 0, 0, 0, 0, 0, 0});
+    while (!out.empty() && out.back().s < 0) out.pop_back();
+    return out;
 }
 
 void build_layout(feti_ctx* c) {
@@ -252,8 +254,8 @@ void build_layout(feti_ctx* c) {
         M.n_beta = M.n_b + M.n_c;
         M.grp = P.grp[s];
         M.ldF = (int)rup(std::max(M.n_b, 1), 32);
-        M.rowT = (int)rup(std::max(M.n_b, 1), 16);
-        M.rows_F = M.rowT + (int)rup(M.n_c, 16);
+        M.rowT = M.n_b;
+        M.rows_F = (int)rup(std::max(M.n_b + M.n_c, 1), 16);
         M.off_loc = P.off_loc[s];
         M.off_i = P.off_i[s];
         M.off_b = P.off_b[s];
@@ -376,10 +378,14 @@ void build_layout(feti_ctx* c) {
     c->d_potrf_one = c->upload(std::vector<PotrfDesc>{PotrfDesc{0, nsmall, nsmall}});
     c->d_trsm_one = c->upload(std::vector<TrsmDesc>{TrsmDesc{0, 0, nsmall, nsmall, nsmall, nsmall}});
 
-    // F*Lambda work list: 128-row tiles of every subdomain's augmented operator
-    std::vector<int> ts, tr, te;
-    make_tiles(c, [](int, bool) { return true; }, ts, tr, te);
-    t.n_m_tiles = (int)ts.size();
+    // F*Lambda work lists: every row block in FP64, or every row block in the reduced precision
+    std::vector<RbRange> r64(ns), rred(ns);
+    for (int s = 0; s < ns; ++s) {
+        const int nrb = c->hsubs[s].rows_F / 16;
+        r64[s] = RbRange{0, 0, 0, nrb};
+        rred[s] = RbRange{0, nrb, 0, 0};
+    }
+    const std::vector<FlTile> tiles64 = pack_tiles(r64), tilesred = pack_tiles(rred);
 
     // topology arrays
     std::vector<int> bq_s(t.nb_tot);
@@ -424,15 +430,8 @@ void build_layout(feti_ctx* c) {
         t.ax_first[a] = c->upload(P.ax_first[a]);
         t.ax_cnt[a] = c->upload(P.ax_cnt[a]);
     }
-    t.m_tile_sub = c->upload(ts);
-    t.m_tile_row = c->upload(tr);
-    t.m_tile_end = c->upload(te);
-    c->tl_low_sub = c->alloc<int>(ts.size());
-    c->tl_low_row = c->alloc<int>(ts.size());
-    c->tl_low_end = c->alloc<int>(ts.size());
-    c->tl_64_sub = c->alloc<int>(ts.size());
-    c->tl_64_row = c->alloc<int>(ts.size());
-    c->tl_64_end = c->alloc<int>(ts.size());
+    t.fl64 = FlTiles{c->upload(tiles64), (int)tiles64.size()};
+    t.flred = FlTiles{c->upload(tilesred), (int)tilesred.size()};
     c->pivdev = c->alloc<double>(ns);
     std::vector<double> K0 = element_K0(P.dim, P.nu);
     c->K0dev = c->upload(K0);
@@ -517,21 +516,35 @@ void classify_precision(feti_ctx* c) {
         ok[s] = dev[s] <= 2e-2 ? 1 : 0;
         c->n_fp64_subs += 1 - ok[s];
     }
-    std::vector<int> ts, tr, te;
-    auto upload3 = [&](int* ds, int* dr, int* de) {
-        if (ts.empty()) return;
-        HIPCHK(hipMemcpyAsync(ds, ts.data(), sizeof(int) * ts.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(dr, tr.data(), sizeof(int) * tr.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(de, te.data(), sizeof(int) * te.size(), hipMemcpyHostToDevice, st));
+    if (verbose()) {
+        std::vector<double> d2 = dev;
+        std::sort(d2.begin(), d2.end());
+        fprintf(stderr, "[feti] round-off metric quantiles: 50%% %.2e 80%% %.2e 90%% %.2e 95%% %.2e max %.2e\n",
+                d2[d2.size() / 2], d2[d2.size() * 8 / 10], d2[d2.size() * 9 / 10], d2[d2.size() * 95 / 100], d2.back());
+    }
+    // Reduced precision: every row block of the subdomains that passed, without writing the
+    // F_rc^T rows. FP64, in a second launch of one-block tiles: the row blocks holding F_rc^T
+    // rows (the coarse right-hand side stays FP64: Kbar_cc^{-1} amplifies its errors) and all
+    // row blocks of the subdomains that failed, spread over many CUs.
+    std::vector<RbRange> rr(t.n_sub), rd(t.n_sub);
+    for (int s = 0; s < t.n_sub; ++s) {
+        const SubMeta& M = c->hsubs[s];
+        const int nrb = M.rows_F / 16, t0 = M.rowT / 16;
+        rr[s] = ok[s] ? RbRange{0, nrb, 0, 0} : RbRange{0, 0, 0, 0};
+        rd[s] = ok[s] ? (M.n_c > 0 ? RbRange{0, 0, t0, nrb - t0} : RbRange{0, 0, 0, 0}) : RbRange{0, 0, 0, nrb};
+    }
+    const std::vector<FlTile> tr = pack_tiles(rr, kFlNoT), td = pack_tiles(rd, kFlSplitK, 1);
+    auto put = [&](const std::vector<FlTile>& v, FlTile*& dev, int& cap, FlTiles& out) {
+        if ((int)v.size() > cap) {
+            if (dev) HIPCHK(hipFree(dev));
+            HIPCHK(hipMalloc(&dev, sizeof(FlTile) * v.size()));
+            cap = (int)v.size();
+        }
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(dev, v.data(), sizeof(FlTile) * v.size(), hipMemcpyHostToDevice, st));
+        out = FlTiles{dev, (int)v.size()};
     };
-    // reduced precision: F_s rows of the subdomains that passed; FP64: the others' F_s rows
-    // and every F_rc^T row (the coarse right-hand side stays FP64: Kbar_cc^{-1} amplifies its errors)
-    make_tiles(c, [&](int s, bool isT) { return !isT && ok[s]; }, ts, tr, te);
-    upload3(c->tl_low_sub, c->tl_low_row, c->tl_low_end);
-    c->tl_low = TileList{c->tl_low_sub, c->tl_low_row, c->tl_low_end, (int)ts.size()};
-    make_tiles(c, [&](int s, bool isT) { return isT || !ok[s]; }, ts, tr, te);
-    upload3(c->tl_64_sub, c->tl_64_row, c->tl_64_end);
-    c->tl_64 = TileList{c->tl_64_sub, c->tl_64_row, c->tl_64_end, (int)ts.size()};
+    put(tr, c->fl_hyb_red_dev, c->fl_hyb_red_cap, c->fl_hyb_red);
+    put(td, c->fl_hyb_64_dev, c->fl_hyb_64_cap, c->fl_hyb_64);
     HIPCHK(hipStreamSynchronize(st));
     c->hybrid = true;
 }
@@ -666,16 +679,16 @@ void numeric_setup(feti_ctx* c) {
 void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool time_it = false, bool pure = false) {
     DevTopo& t = c->t;
     hipStream_t st = c->st;
-    const void* A = prec == FETI_FP64 ? (const void*)c->sw64 : prec == FETI_FP32 ? (const void*)c->sw32 : (const void*)c->swhi;
+    const void* A = prec == FETI_FP32 ? (const void*)c->sw32 : prec == FETI_BF16X3 ? (const void*)c->swhi : nullptr;
     const bool hyb = prec != FETI_FP64 && !pure && c->hybrid && prec == c->opts.precision;
     const int f32 = prec != FETI_FP64 && !hyb;
     if (time_it) HIPCHK(hipEventRecord(c->ev[2], st));
     if (hyb) {
-        launch_flambda(t, FETI_FP64, k, Lam, c->sw64, nullptr, c->Ybuf, c->Tbuf, st, &c->tl_64, 1);
-        launch_flambda(t, prec, k, Lam, A, c->swlo, c->Ybuf, c->Tbuf, st, &c->tl_low, 1);
-    } else {
-        launch_flambda(t, prec, k, Lam, A, c->swlo, c->Ybuf, c->Tbuf, st);
+        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, c->Ybuf, c->Tbuf, st, &c->fl_hyb_red, 1);
+        launch_flambda(t, FETI_FP64, k, Lam, nullptr, nullptr, c->sw64, c->Ybuf, c->Tbuf, st, &c->fl_hyb_64, 1);
     }
+    else
+        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, c->Ybuf, c->Tbuf, st);
     CHECK_LAUNCH();
     if (time_it) HIPCHK(hipEventRecord(c->ev[3], st));
     if (c->P.method == FETI_DP && c->P.n_cg > 0) {
@@ -809,13 +822,24 @@ void ensure_history(feti_ctx* c, int kd, int need) {
 
 struct KrylovOut {
     int iters = 0;
+    int reduced = 0;   // iterations that applied the reduced-precision operator
     int kept = 0;
     double eps = 0;
     int status = FETI_OK;
 };
 
 // One pass of PCG on the correction: lt accumulates, r is the residual (updated).
-KrylovOut run_pcg(feti_ctx* c, int prec, double eps0, double tol, int max_it, std::vector<double>& hist) {
+// lambda of the current pass: out = lam + lt
+void current_iterate(feti_ctx* c, double* out) {
+    const int n = c->P.n_lambda;
+    HIPCHK(hipMemcpyAsync(out, c->lam, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+    launch_axpby(n, 1.0, c->lt, 1.0, out, c->st);
+    CHECK_LAUNCH();
+}
+
+// Mixed precision: iterations apply the FP64 operator while eps > sw * eps0 and the reduced-
+// precision one after that (relaxation of the operator accuracy as the residual decreases).
+KrylovOut run_pcg(feti_ctx* c, int prec, double sw, double eps0, double tol, int max_it, std::vector<double>& hist) {
     KrylovOut o;
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
@@ -827,8 +851,11 @@ KrylovOut run_pcg(feti_ctx* c, int prec, double eps0, double tol, int max_it, st
     double rz = read_scalar(c, c->scal);
     o.eps = std::sqrt(std::max(rz, 0.0));
     if (o.eps <= tol * eps0) return o;
+    bool replaced = false;
     for (int it = 0; it < max_it; ++it) {
-        apply_F(c, 1, prec, c->Zk, c->Qk);
+        const int p_it = (prec != FETI_FP64 && !replaced && o.eps <= sw * eps0) ? prec : FETI_FP64;
+        o.reduced += p_it != FETI_FP64;
+        apply_F(c, 1, p_it, c->Zk, c->Qk);
         ddot(c, n, c->Zk, c->Qk, 1);
         const double wq = read_scalar(c, c->scal + 1);
         if (!(wq > 0.0)) {
@@ -845,8 +872,24 @@ KrylovOut run_pcg(feti_ctx* c, int prec, double eps0, double tol, int max_it, st
         o.iters = it + 1;
         o.eps = std::sqrt(std::max(rz_new, 0.0));
         hist.push_back(o.eps);
-        if (verbose()) fprintf(stderr, "[feti] pcg it %d prec %d eps/eps0 %.3e\n", it + 1, prec, o.eps / eps0);
-        if (o.eps <= tol * eps0) break;
+        if (verbose()) fprintf(stderr, "[feti] pcg it %d prec %d eps/eps0 %.3e\n", it + 1, p_it, o.eps / eps0);
+        if (o.eps <= tol * eps0) {
+            if (o.reduced == 0 || replaced) break;
+            // residual replacement after reduced-precision products; PCG restarts from it
+            replaced = true;
+            current_iterate(c, c->tmpv);
+            true_residual(c, c->tmpv, c->r);
+            precondition(c, c->r, c->zv, 1, 0);
+            ddot(c, n, c->r, c->zv, 0);
+            rz = read_scalar(c, c->scal);
+            o.eps = std::sqrt(std::max(rz, 0.0));
+            if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
+            if (o.eps <= tol * eps0) break;
+            HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            project(c, 1, c->Zk);
+            CHECK_LAUNCH();
+            continue;
+        }
         const double beta = rz_new / rz;
         rz = rz_new;
         HIPCHK(hipMemcpyAsync(c->Qtmp, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
@@ -858,8 +901,8 @@ KrylovOut run_pcg(feti_ctx* c, int prec, double eps0, double tol, int max_it, st
 }
 
 // One pass of Algorithm 1 (simultaneous directions; kd = 1 is full orthogonalisation).
-KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int max_it, std::vector<double>& hist,
-                    std::vector<int>& ranks) {
+KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, double tol, int max_it,
+                    std::vector<double>& hist, std::vector<int>& ranks) {
     KrylovOut o;
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
@@ -875,11 +918,14 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
     int nb = 0;
     double best = o.eps;
     int it_best = 0;
+    bool replaced = false;
     for (int it = 0; it < max_it && o.kept < n; ++it) {
         ensure_history(c, kd, nb + 1);
         double* Wn = (double*)c->WH[nb];
         double* Qn = (double*)c->QH[nb];
-        apply_F(c, kd, prec, c->Zk, c->Qk);
+        const int p_it = (prec != FETI_FP64 && !replaced && o.eps <= sw * eps0) ? prec : FETI_FP64;
+        o.reduced += p_it != FETI_FP64;
+        apply_F(c, kd, p_it, c->Zk, c->Qk);
         // Delta = Q^T W
         launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
         launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st);
@@ -914,7 +960,7 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
         ranks.push_back(rank);
         o.iters = it + 1;
         if (verbose())
-            fprintf(stderr, "[feti] sfeti it %d prec %d rank %d eps/eps0 %.3e\n", it + 1, prec, rank,
+            fprintf(stderr, "[feti] sfeti it %d prec %d rank %d eps/eps0 %.3e\n", it + 1, p_it, rank,
                     std::sqrt(std::max(ez, 0.0)) / eps0);
         if (rank == 0) {
             o.status = FETI_EBREAKDOWN;
@@ -923,13 +969,35 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, int kd, double eps0, double tol, int 
         o.kept += rank;
         o.eps = std::sqrt(std::max(ez, 0.0));
         hist.push_back(o.eps);
-        if (o.eps <= tol * eps0) break;
+        if (o.eps <= tol * eps0) {
+            if (o.reduced == 0 || replaced) break;
+            // The recurrence converged on reduced-precision products: replace the recursive
+            // residual by the FP64 one of the current iterate and, if that misses the
+            // tolerance, go on in FP64 from it with the stored directions kept.
+            replaced = true;
+            current_iterate(c, c->tmpv);
+            true_residual(c, c->tmpv, c->r);
+            precondition(c, c->r, c->Zk, one, 0);
+            launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
+            o.eps = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
+            if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
+            if (o.eps <= tol * eps0) break;
+            project(c, kd, c->Zk);
+            for (int pass = 0; pass < passes; ++pass) {
+                launch_gram(n, kd, kd, c->QH_dev, nb, c->Zk, c->part, c->Psi, st);
+                launch_ts_gemm(n, kd, nb, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st);
+            }
+            CHECK_LAUNCH();
+            best = o.eps;
+            it_best = it;
+            continue;
+        }
         if (o.eps < 0.9 * best) {
             best = o.eps;
             it_best = it;
         }
         // a reduced-precision pass that diverges or stalls ends here; the caller restarts in FP64
-        if (prec != FETI_FP64 && (o.eps > 1e3 * best || it - it_best > 30)) {
+        if (p_it != FETI_FP64 && (o.eps > 1e3 * best || it - it_best > 30)) {
             o.status = FETI_ENOCONV;
             break;
         }
@@ -950,7 +1018,7 @@ void recover(feti_ctx* c, double* u) {
     if (P.method == FETI_DP) {
         if (P.n_cg > 0) {
             if (P.n_lambda > 0) {
-                launch_flambda(t, FETI_FP64, 1, c->lam, c->sw64, nullptr, c->Ybuf, c->Tbuf, st);
+                launch_flambda(t, FETI_FP64, 1, c->lam, nullptr, nullptr, c->sw64, c->Ybuf, c->Tbuf, st);
                 launch_axpby(t.nc_tot, 1.0, c->fbar_s, 1.0, c->Tbuf, st);
                 launch_coarse(t, 1, 0, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->uc, c->tcbuf, st);
             } else {
@@ -1006,16 +1074,19 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         // residual does not contract by 10x, hands over to the FP64 operator.
         int cur = prec;
         double prev_rel = 1.0;
+        double sw = c->opts.relax;
+        if (!(sw > 0.0)) sw = std::min(1.0, 0.1 * tol / (prec == FETI_BF16X3 ? 1e-3 : 1e-5));
         if (eps0 > 0.0) {
             for (int pass = 0;; ++pass) {
                 HIPCHK(hipMemsetAsync(c->lt, 0, sizeof(double) * n, st));
                 KrylovOut o;
                 const int left = max_it - tot.iters;
                 if (c->opts.krylov == FETI_PCG)
-                    o = run_pcg(c, cur, eps0, tol, left, hist);
+                    o = run_pcg(c, cur, sw, eps0, tol, left, hist);
                 else
-                    o = run_sfeti(c, cur, kd, eps0, tol, left, hist, ranks);
+                    o = run_sfeti(c, cur, sw, kd, eps0, tol, left, hist, ranks);
                 tot.iters += o.iters;
+                tot.reduced += o.reduced;
                 tot.kept += o.kept;
                 tot.eps = o.eps;
                 launch_axpby(n, 1.0, c->lt, 1.0, c->lam, st);
@@ -1069,6 +1140,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         info->true_rel_res = true_rel;
         info->kept_directions = tot.kept;
         info->fp64_fallback = fallback;
+        info->reduced_iters = tot.reduced;
         if (info->res_hist && info->res_hist_cap > 0)
             for (int i = 0; i < (int)hist.size() && i < info->res_hist_cap; ++i) info->res_hist[i] = hist[i];
         if (info->rank_hist && info->res_hist_cap > 0)

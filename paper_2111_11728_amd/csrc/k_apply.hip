@@ -3,10 +3,12 @@
 // TFETI projector.
 //
 // F * Lambda = sum_s B^s F_s B^sT Lambda runs in three launches:
-//   1. k_flambda: per (subdomain, 128-row tile) gather X_s = B^sT Lambda into LDS (in MFMA
-//      operand order) and multiply by the augmented operator A_s = [F_s; F_rc^sT] on the
-//      matrix cores; A_s streams from HBM in a pre-swizzled layout so that every wavefront
-//      load is one coalesced 16-byte access per lane with no LDS round trip.
+//   1. k_flambda: one workgroup per (subdomain, row tile) gathers X_s = B^sT Lambda into LDS
+//      (FP64, MFMA operand order, double-buffered 128-row chunks) and multiplies it by the
+//      augmented operator A_s = [F_s; F_rc^sT] on the matrix cores. A_s streams from HBM in a
+//      pre-swizzled layout (one coalesced 16-byte load per lane and MFMA step, prefetched one
+//      step ahead). Row blocks of 16 rows run either in the reduced precision (two per
+//      wavefront) or in FP64 (one per wavefront, same cost), both within one launch.
 //   2. k_coarse (FETI-DP): t = sum_s B_c^sT F_rc^sT X_s, v = Kbar_cc^{-1} t.
 //   3. k_scatter: owner-computes per lambda row, Q[row] = sum over the row's (one or two)
 //      subdomains of sign * (Y_s[j] + F_rc^s[j,:] v_s); no atomics, bit-reproducible.
@@ -18,13 +20,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int kKC = 64;        // rows of X staged per LDS chunk
-constexpr int kTileRows = 128; // rows of A_s per workgroup (4 wavefronts x 32 rows)
-
-template <int P> struct PrecTraits;
-template <> struct PrecTraits<FETI_FP64> { typedef double Elem; typedef double Out; };
-template <> struct PrecTraits<FETI_FP32> { typedef float Elem; typedef float Out; };
-template <> struct PrecTraits<FETI_BF16X3> { typedef __bf16 Elem; typedef float Out; };
+constexpr int kFLThreads = 64 * kFlWaves;
+constexpr int kXC = 128;                         // rows of X_s per LDS chunk (two chunks in flight)
+constexpr int kXPer = kXC * 64 / kFLThreads;     // gathered values per thread and chunk
 
 __device__ inline __bf16 to_bf16(float x) {
     __hip_bfloat16 h = __float2bfloat16(x);
@@ -32,204 +30,369 @@ __device__ inline __bf16 to_bf16(float x) {
 }
 __device__ inline float from_bf16(__bf16 x) { return __bfloat162float(*reinterpret_cast<__hip_bfloat16*>(&x)); }
 
-// Gather of X_s = B^sT Lambda rows through the fixed-width map gmap[q*R + t] = sign*(row+1)
-// (0: unused slot). Each thread owns kGatherPer (row, column) pairs of a 64-row chunk:
-// e = tid + kFLThreads*u, chunk row e/64, column e%64 (a wavefront shares the row: the map
-// load is a broadcast and the Lambda loads are one coalesced 512-byte access).
-constexpr int kFLThreads = 512;                  // 8 wavefronts x 16 rows = one 128-row tile
-constexpr int kGatherPer = kKC * 64 / kFLThreads;
+// Gather of X_s rows [kc0, kc0 + kXC) through the fixed-width map gmap[q*R + t] =
+// sign*(row+1) (0: unused slot). Value u of a thread is chunk row wave + 16 u, column lane:
+// the row is uniform over the wavefront, so its map entries come through scalar loads and
+// its Lambda row through one coalesced 512-byte load. gather_x only issues the loads of the
+// first copy (nothing waits on them until the chunk is stored, after the next chunk's
+// products); store_x applies the sign, adds further copies (rows shared by more than two
+// subdomains) and writes the LDS chunk.
+__device__ inline int fl_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-__device__ inline void gather_chunk(const SubMeta& M, int kc0, int kcn, int k, int R, const int* __restrict__ gmap,
-                                    const double* __restrict__ Lambda, double* vals) {
+__device__ inline void gather_x(const SubMeta& M, int kc0, int k, int R, const int* __restrict__ gmap,
+                                const double* __restrict__ Lambda, double* g, int* gv) {
+    const int wave = fl_wave();
+    const int c = min((int)(threadIdx.x & 63), k - 1);
 #pragma unroll
-    for (int u = 0; u < kGatherPer; ++u) {
-        const int e = threadIdx.x + kFLThreads * u;
-        const int jj = e >> 6, c = e & 63;
-        const int j = kc0 + jj;
-        double v = 0.0;
-        if (jj < kcn && j < M.n_b && c < k) {
-            const int* g = gmap + (M.off_b + j) * R;
-            for (int t = 0; t < R; ++t) {
-                const int gv = g[t];
-                if (gv > 0) v += Lambda[(long long)(gv - 1) * k + c];
-                else if (gv < 0) v -= Lambda[(long long)(-gv - 1) * k + c];
-            }
-        }
-        vals[u] = v;
+    for (int u = 0; u < kXPer; ++u) {
+        const int j = kc0 + wave + 16 * u;
+        gv[u] = j < M.n_b ? gmap[(M.off_b + j) * R] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kXPer; ++u) {
+        const int r = gv[u] > 0 ? gv[u] - 1 : (gv[u] < 0 ? -gv[u] - 1 : 0);
+        g[u] = Lambda[(long long)r * k + c];
     }
 }
 
-template <int P>
-__device__ inline void store_chunk(unsigned char* lds_raw, const double* vals) {
+// LDS chunk layout (B operand of the 16x16x4 MFMAs): element ((kq*4 + nb)*64 + l)*4 + q
+// holds X[16 kq + 4 q + l/16][16 nb + l%16], so a lane's operands for one 16-row step are
+// four consecutive doubles. Chunk row wave + 16 u has kq = u, q = wave/4, l/16 = wave%4.
+__device__ inline void store_x(double* Xb, const SubMeta& M, int kc0, int k, int R, const int* __restrict__ gmap,
+                               const double* __restrict__ Lambda, const double* g, const int* gv) {
+    const int wave = fl_wave();
+    const int lane = threadIdx.x & 63;
+    const int c = min(lane, k - 1);
 #pragma unroll
-    for (int u = 0; u < kGatherPer; ++u) {
-        const int e = threadIdx.x + kFLThreads * u;
-        const int jj = e >> 6, c = e & 63;
-        if constexpr (P != FETI_BF16X3) {
-            typedef typename PrecTraits<P>::Elem E;
-            E* X = reinterpret_cast<E*>(lds_raw);
-            const int kq = jj >> 4, q4 = (jj & 15) >> 2, lr = jj & 3;
-            const int l = lr * 16 + (c & 15), nb = c >> 4;
-            X[((kq * 4 + nb) * 64 + l) * 4 + q4] = (E)vals[u];
-        } else {
-            __bf16* Xh = reinterpret_cast<__bf16*>(lds_raw);
-            __bf16* Xl = Xh + 4096;
-            const int kb = jj >> 5, r32 = jj & 31, lg = r32 >> 3, q8 = r32 & 7;
-            const int l = lg * 16 + (c & 15), nb = c >> 4;
-            const float vf = (float)vals[u];
-            const __bf16 hi = to_bf16(vf);
-            const __bf16 lo = to_bf16(vf - from_bf16(hi));
-            const int idx = ((kb * 4 + nb) * 64 + l) * 8 + q8;
-            Xh[idx] = hi;
-            Xl[idx] = lo;
+    for (int u = 0; u < kXPer; ++u) {
+        double v = gv[u] > 0 ? g[u] : (gv[u] < 0 ? -g[u] : 0.0);
+        if (R > 1 && gv[u] != 0) {
+            const int* gm = gmap + (M.off_b + kc0 + wave + 16 * u) * R;
+            for (int t = 1; t < R; ++t) {
+                const int e = gm[t];
+                if (e > 0) v += Lambda[(long long)(e - 1) * k + c];
+                else if (e < 0) v -= Lambda[(long long)(-e - 1) * k + c];
+            }
         }
+        if (lane >= k) v = 0.0;
+        Xb[((u * 4 + (lane >> 4)) * 64 + (wave & 3) * 16 + (lane & 15)) * 4 + (wave >> 2)] = v;
     }
 }
 
-template <int P, typename Out>
-__global__ void __launch_bounds__(kFLThreads) k_flambda(const SubMeta* __restrict__ subs, const int* __restrict__ tile_sub,
-                                                        const int* __restrict__ tile_row, const int* __restrict__ tile_end,
-                                                        int k, const double* __restrict__ Lambda,
-                                                        const int* __restrict__ gmap, int R,
-                                                        const void* __restrict__ Fsw_, const void* __restrict__ Fsw_lo_,
-                                                        Out* __restrict__ Y, Out* __restrict__ T) {
-    constexpr bool kBF = P == FETI_BF16X3;
-    // FP32/FP64: 4 super-blocks of 16 k x 4 column blocks x 64 lanes x 4 values;
-    // BF16: 2 blocks of 32 k x 4 column blocks x 64 lanes x 8 values (hi and lo)
-    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[kBF ? 2 * 4096 * 2 : 4096 * sizeof(typename PrecTraits<P>::Elem)];
-    const int s = tile_sub[blockIdx.x];
-    if (s < 0) return;
-    const SubMeta M = subs[s];
-    const int row0 = tile_row[blockIdx.x];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int rbase = row0 + 16 * wave;     // first row of this wavefront (one 16-row block)
-    const int rb = rbase >> 4;
-    const bool rvalid = rb < (min(M.rows_F, tile_end[blockIdx.x]) >> 4);
+__device__ inline void split_bf16(double x, __bf16& hi, __bf16& lo) {
+    const float f = (float)x;
+    hi = to_bf16(f);
+    lo = to_bf16(f - from_bf16(hi));
+}
 
-    typedef typename std::conditional<P == FETI_FP64, v4d, v4f>::type Acc;
-    Acc acc[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[nb][v] = 0;
-
-    double vals[kGatherPer];
-    gather_chunk(M, 0, min(kKC, M.ldF), k, R, gmap, Lambda, vals);
-    for (int kc0 = 0; kc0 < M.ldF; kc0 += kKC) {
-        const int kcn = min(kKC, M.ldF - kc0);   // multiple of 32
-        store_chunk<P>(lds_raw, vals);
-        __syncthreads();
-        // prefetch the next chunk's gathered values while the matrix cores work on this one
-        if (kc0 + kKC < M.ldF) gather_chunk(M, kc0 + kKC, min(kKC, M.ldF - kc0 - kKC), k, R, gmap, Lambda, vals);
-        if (rvalid) {
-            if constexpr (P == FETI_FP64 || P == FETI_FP32) {
-                typedef typename PrecTraits<P>::Elem E;
-                const E* A = reinterpret_cast<const E*>(Fsw_) + M.off_Fsw;
-                const E* X = reinterpret_cast<const E*>(lds_raw);
-                const int KQ = M.ldF >> 4;
-                const int nkq = kcn >> 4;
-                E a[4][4];
-#pragma unroll
-                for (int kq = 0; kq < 4; ++kq) {
-                    const E* src = A + ((long long)(rb * KQ + (kc0 >> 4) + kq) * 64 + lane) * 4;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) a[kq][q] = kq < nkq ? src[q] : (E)0;
-                }
-#pragma unroll
-                for (int kq = 0; kq < 4; ++kq) {
-                    if (kq >= nkq) break;
-#pragma unroll
-                    for (int nb = 0; nb < 4; ++nb) {
-                        const E* bsrc = X + ((kq * 4 + nb) * 64 + lane) * 4;
-                        E bq[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) bq[q] = bsrc[q];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            if constexpr (P == FETI_FP64)
-                                acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kq][q], bq[q], acc[nb], 0, 0, 0);
-                            else
-                                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq][q], bq[q], acc[nb], 0, 0, 0);
-                        }
-                    }
-                }
-            } else {
-                const v8bf* Ah = reinterpret_cast<const v8bf*>(Fsw_) + (M.off_Fsw >> 3);
-                const v8bf* Al = reinterpret_cast<const v8bf*>(Fsw_lo_) + (M.off_Fsw >> 3);
-                const v8bf* Xh = reinterpret_cast<const v8bf*>(lds_raw);
-                const v8bf* Xl = Xh + 512;
-                const int KB = M.ldF >> 5;
-                const int nkb = kcn >> 5;
-                v8bf ah[2], al[2];
-#pragma unroll
-                for (int kb = 0; kb < 2; ++kb) {
-                    if (kb < nkb) {
-                        const long long idx = (long long)(rb * KB + (kc0 >> 5) + kb) * 64 + lane;
-                        ah[kb] = Ah[idx];
-                        al[kb] = Al[idx];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) { ah[kb][q] = to_bf16(0.f); al[kb][q] = to_bf16(0.f); }
-                    }
-                }
-#pragma unroll
-                for (int kb = 0; kb < 2; ++kb) {
-                    if (kb >= nkb) break;
-#pragma unroll
-                    for (int nb = 0; nb < 4; ++nb) {
-                        const int idx = (kb * 4 + nb) * 64 + lane;
-                        const v8bf bh = Xh[idx], bl = Xl[idx];
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kb], bh, acc[nb], 0, 0, 0);
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kb], bl, acc[nb], 0, 0, 0);
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[kb], bh, acc[nb], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (!rvalid) return;
-    // ---- store: in every 16x16 block the lane holds column lane%16 and rows
-    // 4*(lane/16)+v (FP32 accumulators) or lane/16+4*v (FP64 accumulators) ----
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+template <typename Out>
+__device__ inline void store_block(const SubMeta& M, int row0, int lane, int k, int nbk, bool f64_layout, bool storeT,
+                                   const float* accf, const double* accd, Out* __restrict__ Y, Out* __restrict__ T) {
+    // D layout of the 16x16 blocks: column lane%16; rows 4*(lane/16)+v (FP32 accumulators)
+    // or lane/16 + 4*v (FP64 accumulators)
+    for (int nb = 0; nb < nbk; ++nb) {
         const int col = nb * 16 + (lane & 15);
         if (col >= k) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int rin = P == FETI_FP64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
-            const int row = rbase + rin;
-            const Out val = (Out)acc[nb][v];
+            const int row = row0 + (f64_layout ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+            const Out val = f64_layout ? (Out)accd[nb * 4 + v] : (Out)accf[nb * 4 + v];
             if (row < M.n_b)
                 Y[(M.off_b + row) * k + col] = val;
-            else if (row >= M.rowT && row < M.rowT + M.n_c)
+            else if (storeT && row >= M.rowT && row < M.rowT + M.n_c)
                 T[(M.off_c + row - M.rowT) * k + col] = val;
         }
     }
 }
 
-void launch_flambda(const DevTopo& t, int precision, int k, const double* Lambda, const void* Fsw,
-                    const void* Fsw_lo, void* Y, void* T, hipStream_t st, const TileList* tl, int out_f64) {
-    const TileList all{t.m_tile_sub, t.m_tile_row, t.m_tile_end, t.n_m_tiles};
-    const TileList& L = tl ? *tl : all;
+// Each wavefront runs the whole chunk loop for its role; every role gathers its share of
+// the X_s chunks and meets the same nch + 1 workgroup barriers, so the roles' register
+// states never overlap.
+struct FlCtx {
+    const SubMeta& M;
+    int k, R, lane;
+    const int* gmap;
+    const double* Lambda;
+    double* Xs;   // two chunk buffers of kXC*64 doubles
+};
+
+__device__ inline int fl_nch(const SubMeta& M) { return (M.ldF + kXC - 1) / kXC; }
+
+template <typename Body>
+__device__ __forceinline__ void fl_chunks(const FlCtx& C, Body body) {
+    double g[kXPer];
+    int gv[kXPer];
+    gather_x(C.M, 0, C.k, C.R, C.gmap, C.Lambda, g, gv);
+    store_x(C.Xs, C.M, 0, C.k, C.R, C.gmap, C.Lambda, g, gv);
+    __syncthreads();
+    const int nch = fl_nch(C.M);
+    for (int ch = 0; ch < nch; ++ch) {
+        const int kc0 = ch * kXC;
+        if (ch + 1 < nch) gather_x(C.M, kc0 + kXC, C.k, C.R, C.gmap, C.Lambda, g, gv);
+        body(C.Xs + (ch & 1) * (kXC * 64), kc0, min(kXC, C.M.ldF - kc0));
+        if (ch + 1 < nch) store_x(C.Xs + ((ch + 1) & 1) * (kXC * 64), C.M, kc0 + kXC, C.k, C.R, C.gmap, C.Lambda, g, gv);
+        __syncthreads();
+    }
+}
+
+template <int NB, typename Out>
+__device__ __forceinline__ void fl_fp32(const FlCtx& C, const float* __restrict__ Ared, int rb0, int rb1, bool two,
+                                        bool storeT, Out* __restrict__ Y, Out* __restrict__ T) {
+    const SubMeta& M = C.M;
+    const int lane = C.lane, KQ = M.ldF >> 4;
+    const float* A = Ared + M.off_Fsw + lane * 4;
+    const float* p0 = A + (long long)rb0 * KQ * 256;
+    const float* p1 = A + (long long)rb1 * KQ * 256;
+    v4f acc0[NB], acc1[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc0[nb] = acc1[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    v4f n0 = *reinterpret_cast<const v4f*>(p0), n1 = *reinterpret_cast<const v4f*>(p1);
+    fl_chunks(C, [&](const double* Xb, int kc0, int kcn) {
+        for (int kql = 0; kql < (kcn >> 4); ++kql) {
+            const int gkq = (kc0 >> 4) + kql;
+            const v4f a0 = n0, a1 = n1;
+            if (gkq + 1 < KQ) {
+                n0 = *reinterpret_cast<const v4f*>(p0 + (gkq + 1) * 256);
+                n1 = *reinterpret_cast<const v4f*>(p1 + (gkq + 1) * 256);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float b = (float)xv[q];
+                    acc0[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], b, acc0[nb], 0, 0, 0);
+                    acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q], b, acc1[nb], 0, 0, 0);
+                }
+            }
+        }
+    });
+    float f[4 * NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f[nb * 4 + v] = acc0[nb][v];
+    store_block<Out>(M, 16 * rb0, lane, C.k, NB, false, storeT, f, nullptr, Y, T);
+    if (two) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) f[nb * 4 + v] = acc1[nb][v];
+        store_block<Out>(M, 16 * rb1, lane, C.k, NB, false, storeT, f, nullptr, Y, T);
+    }
+}
+
+template <int NB, typename Out>
+__device__ __forceinline__ void fl_bf16(const FlCtx& C, const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
+                                        int rb0, int rb1, bool two, bool storeT, Out* __restrict__ Y, Out* __restrict__ T) {
+    const SubMeta& M = C.M;
+    const int lane = C.lane, KB = M.ldF >> 5;
+    const v8bf* H = reinterpret_cast<const v8bf*>(Ahi) + (M.off_Fsw >> 3) + lane;
+    const v8bf* L = reinterpret_cast<const v8bf*>(Alo) + (M.off_Fsw >> 3) + lane;
+    const v8bf* h0p = H + (long long)rb0 * KB * 64;
+    const v8bf* h1p = H + (long long)rb1 * KB * 64;
+    const v8bf* l0p = L + (long long)rb0 * KB * 64;
+    const v8bf* l1p = L + (long long)rb1 * KB * 64;
+    v4f acc0[NB], acc1[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc0[nb] = acc1[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    v8bf nh0 = *h0p, nh1 = *h1p, nl0 = *l0p, nl1 = *l1p;
+    fl_chunks(C, [&](const double* Xb, int kc0, int kcn) {
+        for (int kbl = 0; kbl < (kcn >> 5); ++kbl) {
+            const int gkb = (kc0 >> 5) + kbl;
+            const v8bf h0 = nh0, h1 = nh1, l0 = nl0, l1 = nl1;
+            if (gkb + 1 < KB) {
+                nh0 = h0p[(gkb + 1) * 64];
+                nh1 = h1p[(gkb + 1) * 64];
+                nl0 = l0p[(gkb + 1) * 64];
+                nl1 = l1p[(gkb + 1) * 64];
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                // lane operand e = 4h + q is X row 32 kb + 16 h + 4 q + lane/16 (the A layout
+                // uses the same permutation of the contraction index)
+                const v4d x0 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl) * 4 + nb) * 64 + lane) * 4);
+                const v4d x1 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl + 1) * 4 + nb) * 64 + lane) * 4);
+                v8bf bh, bl;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    __bf16 hi, lo;
+                    split_bf16(x0[q], hi, lo);
+                    bh[q] = hi;
+                    bl[q] = lo;
+                    split_bf16(x1[q], hi, lo);
+                    bh[4 + q] = hi;
+                    bl[4 + q] = lo;
+                }
+                acc0[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h0, bh, acc0[nb], 0, 0, 0);
+                acc0[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h0, bl, acc0[nb], 0, 0, 0);
+                acc0[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l0, bh, acc0[nb], 0, 0, 0);
+                acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1, bh, acc1[nb], 0, 0, 0);
+                acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1, bl, acc1[nb], 0, 0, 0);
+                acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l1, bh, acc1[nb], 0, 0, 0);
+            }
+        }
+    });
+    float f[4 * NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f[nb * 4 + v] = acc0[nb][v];
+    store_block<Out>(M, 16 * rb0, lane, C.k, NB, false, storeT, f, nullptr, Y, T);
+    if (two) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) f[nb * 4 + v] = acc1[nb][v];
+        store_block<Out>(M, 16 * rb1, lane, C.k, NB, false, storeT, f, nullptr, Y, T);
+    }
+}
+
+template <int NB, typename Out>
+__device__ __forceinline__ void fl_fp64(const FlCtx& C, const double* __restrict__ A64, int rb0, Out* __restrict__ Y,
+                                        Out* __restrict__ T) {
+    const SubMeta& M = C.M;
+    const int lane = C.lane, KQ = M.ldF >> 4;
+    const double* p = A64 + M.off_Fsw + (long long)rb0 * KQ * 256 + lane * 4;
+    v4d acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = v4d{0.0, 0.0, 0.0, 0.0};
+    v4d n = *reinterpret_cast<const v4d*>(p);
+    fl_chunks(C, [&](const double* Xb, int kc0, int kcn) {
+        for (int kql = 0; kql < (kcn >> 4); ++kql) {
+            const int gkq = (kc0 >> 4) + kql;
+            const v4d a = n;
+            if (gkq + 1 < KQ) n = *reinterpret_cast<const v4d*>(p + (gkq + 1) * 256);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], xv[q], acc[nb], 0, 0, 0);
+            }
+        }
+    });
+    double d[4 * NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[nb * 4 + v] = acc[nb][v];
+    store_block<Out>(M, 16 * rb0, lane, C.k, NB, true, true, nullptr, d, Y, T);
+}
+
+// One FP64 row block with the contraction split over the wavefronts: wavefront w takes the
+// 16-column steps [w KQ/16, (w+1) KQ/16) while their X_s chunk is resident; the partial
+// blocks then meet in LDS and are summed in wavefront order (deterministic).
+template <int NB, typename Out>
+__device__ __forceinline__ void fl_fp64_splitk(const FlCtx& C, const double* __restrict__ A64, int rb0,
+                                               Out* __restrict__ Y, Out* __restrict__ T) {
+    const SubMeta& M = C.M;
+    const int lane = C.lane, wave = fl_wave(), KQ = M.ldF >> 4;
+    const int kq0 = wave * KQ / kFlWaves, kq1 = (wave + 1) * KQ / kFlWaves;
+    const double* p = A64 + M.off_Fsw + (long long)rb0 * KQ * 256 + lane * 4;
+    v4d acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = v4d{0.0, 0.0, 0.0, 0.0};
+    fl_chunks(C, [&](const double* Xb, int kc0, int kcn) {
+        const int c0 = kc0 >> 4;
+        const int lo = max(kq0, c0), hi = min(kq1, c0 + (kcn >> 4));
+        for (int gkq = lo; gkq < hi; ++gkq) {
+            const v4d a = *reinterpret_cast<const v4d*>(p + gkq * 256);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const v4d xv = *reinterpret_cast<const v4d*>(Xb + (((gkq - c0) * 4 + nb) * 64 + lane) * 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], xv[q], acc[nb], 0, 0, 0);
+            }
+        }
+    });
+    // partials: Xs[(w * 4 NB + nb * 4 + v) * 64 + lane] (the chunk buffers are free after the last barrier)
+    double* P = C.Xs;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[(wave * 4 * NB + nb * 4 + v) * 64 + lane] = acc[nb][v];
+    __syncthreads();
+    const int e = threadIdx.x;
+    if (e < 4 * NB * 64) {
+        double sum = 0.0;
+        for (int w = 0; w < kFlWaves; ++w) sum += P[w * 4 * NB * 64 + e];
+        const int nbv = e >> 6, l = e & 63, nb = nbv >> 2, v = nbv & 3;
+        const int row = 16 * rb0 + (l >> 4) + 4 * v, col = nb * 16 + (l & 15);
+        if (col < C.k) {
+            if (row < M.n_b)
+                Y[(M.off_b + row) * C.k + col] = (Out)sum;
+            else if (row >= M.rowT && row < M.rowT + M.n_c)
+                T[(M.off_c + row - M.rowT) * C.k + col] = (Out)sum;
+        }
+    }
+}
+
+// P: precision of the reduced row blocks (FETI_FP64: none); NB: 16-column blocks of the
+// direction block computed (1 for k <= 16, else 4).
+template <int P, int NB, typename Out>
+__global__ void __launch_bounds__(kFLThreads) k_flambda(const SubMeta* __restrict__ subs, const FlTile* __restrict__ tiles,
+                                                        int k, const double* __restrict__ Lambda,
+                                                        const int* __restrict__ gmap, int R,
+                                                        const void* __restrict__ Ared_, const void* __restrict__ Ared_lo_,
+                                                        const double* __restrict__ A64,
+                                                        Out* __restrict__ Y, Out* __restrict__ T) {
+    __shared__ __attribute__((aligned(16))) double Xs[2 * kXC * 64];
+    const FlTile tl = tiles[blockIdx.x];
+    if (tl.s < 0) return;
+    const SubMeta M = subs[tl.s];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const FlCtx C{M, k, R, lane, gmap, Lambda, Xs};
+    if (tl.flags & kFlSplitK) {
+        fl_fp64_splitk<NB, Out>(C, A64, tl.d0, Y, T);
+        return;
+    }
+    // wavefront role (uniform): two reduced row blocks, one FP64 row block, or gather only
+    const int nw_red = (tl.n_red + 1) >> 1;
+    if (P != FETI_FP64 && wave < nw_red) {
+        const int rb0 = tl.red0 + 2 * wave;
+        const bool two = 2 * wave + 1 < tl.n_red;
+        const int rb1 = two ? rb0 + 1 : rb0;
+        const bool storeT = !(tl.flags & kFlNoT);
+        if constexpr (P == FETI_FP32)
+            fl_fp32<NB, Out>(C, reinterpret_cast<const float*>(Ared_), rb0, rb1, two, storeT, Y, T);
+        else if constexpr (P == FETI_BF16X3)
+            fl_bf16<NB, Out>(C, reinterpret_cast<const __bf16*>(Ared_), reinterpret_cast<const __bf16*>(Ared_lo_), rb0,
+                             rb1, two, storeT, Y, T);
+    } else if (wave >= nw_red && wave - nw_red < tl.n_d) {
+        fl_fp64<NB, Out>(C, A64, tl.d0 + wave - nw_red, Y, T);
+    } else {
+        fl_chunks(C, [](const double*, int, int) {});
+    }
+}
+
+template <int P, typename Out>
+void launch_fl(const DevTopo& t, const FlTiles& L, int k, const double* Lambda, const void* Ared, const void* Ared_lo,
+               const double* A64, Out* Y, Out* T, hipStream_t st) {
+    if (k <= 16)
+        k_flambda<P, 1, Out><<<L.n, kFLThreads, 0, st>>>(t.subs, L.t, k, Lambda, t.gmap, t.gmap_R, Ared, Ared_lo, A64, Y, T);
+    else
+        k_flambda<P, 4, Out><<<L.n, kFLThreads, 0, st>>>(t.subs, L.t, k, Lambda, t.gmap, t.gmap_R, Ared, Ared_lo, A64, Y, T);
+}
+
+void launch_flambda(const DevTopo& t, int precision, int k, const double* Lambda, const void* Ared, const void* Ared_lo,
+                    const double* A64, void* Y, void* T, hipStream_t st, const FlTiles* tl, int out_f64) {
+    if (k < 1 || k > 64) throw std::invalid_argument("F*Lambda takes 1..64 directions");
+    if (t.n_lambda < 1) throw std::invalid_argument("F*Lambda without Lagrange multipliers");
+    const FlTiles& L = tl ? *tl : (precision == FETI_FP64 ? t.fl64 : t.flred);
     if (L.n == 0) return;
-    dim3 grid(L.n);
-    const int nt = kFLThreads;
-#define FL_ARGS t.subs, L.sub, L.row, L.end, k, Lambda, t.gmap, t.gmap_R
     if (precision == FETI_FP64) {
-        k_flambda<FETI_FP64, double><<<grid, nt, 0, st>>>(FL_ARGS, Fsw, nullptr, (double*)Y, (double*)T);
+        launch_fl<FETI_FP64, double>(t, L, k, Lambda, nullptr, nullptr, A64, (double*)Y, (double*)T, st);
     } else if (precision == FETI_FP32) {
         if (out_f64)
-            k_flambda<FETI_FP32, double><<<grid, nt, 0, st>>>(FL_ARGS, Fsw, nullptr, (double*)Y, (double*)T);
+            launch_fl<FETI_FP32, double>(t, L, k, Lambda, Ared, nullptr, A64, (double*)Y, (double*)T, st);
         else
-            k_flambda<FETI_FP32, float><<<grid, nt, 0, st>>>(FL_ARGS, Fsw, nullptr, (float*)Y, (float*)T);
+            launch_fl<FETI_FP32, float>(t, L, k, Lambda, Ared, nullptr, A64, (float*)Y, (float*)T, st);
     } else {
         if (out_f64)
-            k_flambda<FETI_BF16X3, double><<<grid, nt, 0, st>>>(FL_ARGS, Fsw, Fsw_lo, (double*)Y, (double*)T);
+            launch_fl<FETI_BF16X3, double>(t, L, k, Lambda, Ared, Ared_lo, A64, (double*)Y, (double*)T, st);
         else
-            k_flambda<FETI_BF16X3, float><<<grid, nt, 0, st>>>(FL_ARGS, Fsw, Fsw_lo, (float*)Y, (float*)T);
+            launch_fl<FETI_BF16X3, float>(t, L, k, Lambda, Ared, Ared_lo, A64, (float*)Y, (float*)T, st);
     }
-#undef FL_ARGS
 }
 
 // ---------------------------------------------------------------------------------------

@@ -432,10 +432,13 @@ __global__ void k_swizzle(const SubMeta* __restrict__ subs, const double* __rest
             sw32[M.off_Fsw + e] = (float)v;
         }
         {
+            // lane operand e = 4h + q of the 16x16x32 MFMA takes contraction index
+            // 32 kb + 16 h + 4 q + lane/16: the same permutation is applied to X_s, whose
+            // FP64 operand order then serves the BF16 products without a lane exchange
             const int q = (int)(e & 7), lane = (int)((e >> 3) & 63);
             const long long blk = e >> 9;
             const int rb = (int)(blk / KB), kb = (int)(blk % KB);
-            const int row = 16 * rb + (lane & 15), col = 32 * kb + 8 * (lane >> 4) + q;
+            const int row = 16 * rb + (lane & 15), col = 32 * kb + 16 * (q >> 2) + 4 * (q & 3) + (lane >> 4);
             const double v = (live(row) && col < M.n_b) ? F64[M.off_F + (long long)row * M.ldF + col] : 0.0;
             const float vf = (float)v;
             const __hip_bfloat16 hi = __float2bfloat16(vf);

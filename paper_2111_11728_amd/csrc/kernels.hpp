@@ -12,11 +12,17 @@
 
 namespace feti {
 
-// A list of 128-row tiles of the augmented local operators (subdomain, first row).
-struct TileList {
-    const int* sub = nullptr;
-    const int* row = nullptr;   // first row of the tile
-    const int* end = nullptr;   // one past the last row the tile may touch
+// F*Lambda work item: one workgroup per tile, all rows of one subdomain's augmented operator
+// A_s = [F_s; F_rc^sT] in 16-row blocks: n_red blocks from red0 in the reduced precision (two
+// per wavefront) and n_d blocks from d0 in FP64 (one per wavefront); (n_red+1)/2 + n_d <= 16.
+constexpr int kFlWaves = 16;   // wavefronts per F*Lambda workgroup
+struct FlTile {
+    int s, red0, n_red, d0, n_d, flags, pad1, pad2;   // s < 0: empty slot
+};
+constexpr int kFlNoT = 1;     // FlTile flag: reduced row blocks do not write the F_rc^T rows
+constexpr int kFlSplitK = 2;  // FlTile flag: one FP64 row block, contraction split over all wavefronts
+struct FlTiles {
+    const FlTile* t = nullptr;
     int n = 0;
 };
 
@@ -70,10 +76,8 @@ struct DevTopo {
     const int* ax_cnt[3] = {nullptr, nullptr, nullptr};
     const int* gmap = nullptr;        // fixed-width gather map: gmap[q*gmap_R + t] = sign*(row+1), 0 unused
     int gmap_R = 1;
-    const int* m_tile_sub = nullptr;  // F*Lambda work list: subdomain of every 128-row tile
-    const int* m_tile_row = nullptr;  // first row of the tile
-    const int* m_tile_end = nullptr;  // one past the last row of the tile
-    int n_m_tiles = 0;
+    FlTiles fl64;                     // F*Lambda work list with every row block in FP64
+    FlTiles flred;                    // ... with every row block in the reduced precision
 };
 
 // ---- setup (k_setup.hip) ----
@@ -101,10 +105,11 @@ void launch_set_identity(double* A, int n, long long lda, hipStream_t st);
 
 // ---- operator application (k_apply.hip) ----
 // Y/T outputs of the local products: Y [nb_tot x k], T [nc_tot x k], row-major, type by precision.
-// tl = nullptr: every tile of the topology; out_f64: write Y/T in FP64 whatever the precision
-void launch_flambda(const DevTopo& t, int precision, int k, const double* Lambda, const void* Fsw,
-                    const void* Fsw_lo, void* Y, void* T, hipStream_t st, const TileList* tl = nullptr,
-                    int out_f64 = 0);
+// Ared/Ared_lo: swizzled A_s in the reduced precision (BF16X3: hi and lo parts), A64: in FP64.
+// tl = nullptr: every row block in `precision`; out_f64: write Y/T in FP64 whatever the precision
+void launch_flambda(const DevTopo& t, int precision, int k, const double* Lambda, const void* Ared,
+                    const void* Ared_lo, const double* A64, void* Y, void* T, hipStream_t st,
+                    const FlTiles* tl = nullptr, int out_f64 = 0);
 // Copy F_s (leading n_b x n_b block of the augmented operator) into dst (ld n_b), rounded to
 // the given precision (FP64: exact; FP32; BF16X3: hi + lo split) and back to FP64.
 void launch_copy_F_rounded(const DevTopo& t, const double* F64, int precision, double* dst, hipStream_t st);

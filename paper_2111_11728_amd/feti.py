@@ -43,14 +43,15 @@ class feti_partition(C.Structure):
 class feti_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("scaling", C.c_int), ("krylov", C.c_int), ("precond", C.c_int),
                 ("precision", C.c_int), ("tol", C.c_double), ("max_it", C.c_int), ("rr_tol", C.c_double),
-                ("reorth", C.c_int), ("max_refine", C.c_int)]
+                ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double)]
 
 
 class feti_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("refinements", C.c_int), ("status", C.c_int), ("eps0", C.c_double),
                 ("eps", C.c_double), ("true_rel_res", C.c_double), ("kept_directions", C.c_int),
                 ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int), ("rank_hist", C.POINTER(C.c_int)),
-                ("t_solve_ms", C.c_double), ("fp64_fallback", C.c_int)]
+                ("t_solve_ms", C.c_double), ("fp64_fallback", C.c_int),
+                ("reduced_iters", C.c_int)]
 
 
 class feti_sizes(C.Structure):
@@ -127,7 +128,7 @@ class Spec:
     """ctypes views of a workloads.Problem (keeps the host arrays alive)."""
 
     def __init__(self, prob, method="fetidp", scaling="k", krylov="pcg", precond="dirichlet", precision="fp64",
-                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=2, max_refine=-1):
+                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=2, max_refine=-1, relax=0.0):
         self.prob = prob
         fixed = np.ascontiguousarray(prob.fixed_dofs(), dtype=np.int32)
         self._fixed = fixed
@@ -151,7 +152,7 @@ class Spec:
                 self.part.cuts[a] = C.POINTER(C.c_int)()
             self.part.group[a] = (prob.groups[a] if (prob.groups is not None and a < prob.dim) else 0)
         self.opts = feti_opts(METHODS[method], SCALINGS[scaling], KRYLOVS[krylov], PRECONDS[precond],
-                              PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine)
+                              PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax)
 
 
 def feti_plan_sizes(spec: Spec) -> dict:
@@ -216,14 +217,15 @@ class Context:
         return {"status": st, "iters": info.iters, "refinements": info.refinements, "eps0": info.eps0,
                 "eps": info.eps, "true_rel_res": info.true_rel_res, "kept_directions": info.kept_directions,
                 "history": hist[:n].copy(), "ranks": ranks[:info.iters].copy(), "t_solve_ms": info.t_solve_ms,
-                "fp64_fallback": info.fp64_fallback}
+                "fp64_fallback": info.fp64_fallback, "reduced_iters": info.reduced_iters}
 
     def feti_compliance_and_grad(self, rho, f, c, dc, u=None):
         info = feti_info()
         st = _check(lib().feti_compliance_and_grad(self.handle, _ptr(rho), _ptr(f), _ptr(c), _ptr(dc), _ptr(u),
                                                    C.byref(info)), allow=(FETI_ENOCONV,))
         return {"status": st, "iters": info.iters, "true_rel_res": info.true_rel_res,
-                "refinements": info.refinements, "fp64_fallback": info.fp64_fallback}
+                "refinements": info.refinements, "fp64_fallback": info.fp64_fallback,
+                "reduced_iters": info.reduced_iters}
 
     def feti_apply_F(self, k, precision, Lam, Q, pure=False):
         p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)
