@@ -84,7 +84,7 @@ typedef struct {
     double rr_tol;            /* rank-revealing pivot threshold on the Jacobi-scaled Gram matrix
                                  (<= 0: 1e-12) */
     int reorth;               /* passes of block classical Gram-Schmidt against the stored
-                                 directions (1 or 2; 0 = 2) */
+                                 directions (1 or 2; 0 = 1, the single pass of Algorithm 1) */
     int max_refine;           /* mixed precision: FP64 residual restarts with the reduced-precision
                                  operator after the first pass (< 0: 4); further passes use FP64 */
     double relax;             /* mixed precision: an iteration applies the FP64 operator while

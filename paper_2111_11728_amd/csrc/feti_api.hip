@@ -909,7 +909,7 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, doubl
     const int pf32 = prec != FETI_FP64;
     const int one = kd == 1;
     const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
-    const int passes = c->opts.reorth == 1 ? 1 : 2;
+    const int passes = c->opts.reorth == 2 ? 2 : 1;
     precondition(c, c->r, c->Zk, one, pf32);
     launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
     o.eps = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
@@ -932,7 +932,10 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, doubl
         launch_ts_gemm(n, kd, 1, c->zk_ptr, c->Tm, nullptr, Wn, 1.0, 0.0, st);
         launch_ts_gemm(n, kd, 1, c->qk_ptr, c->Tm, nullptr, Qn, 1.0, 0.0, st);
         // gamma = W^T r
-        launch_gram(n, kd, 1, c->WH_dev + nb, 1, c->r, c->part, c->gam, st);
+        if (kd == 64)
+            launch_gemv_t(n, kd, Wn, c->r, c->part, c->gam, st);
+        else
+            launch_gram(n, kd, 1, c->WH_dev + nb, 1, c->r, c->part, c->gam, st);
         if (c->P.method == FETI_TFETI) {
             launch_update_lr(n, kd, Wn, nullptr, c->gam, c->lt, nullptr, st);
             HIPCHK(hipMemsetAsync(c->tmpv, 0, sizeof(double) * n, st));

@@ -411,35 +411,39 @@ __global__ void k_coarse_t(int n_cg, int k, const TT* __restrict__ T, const doub
     t[idx] = val;
 }
 
+// v = scale * Kinv t (n_cg x n_cg by n_cg x k, k <= 64) on the FP64 matrix cores: workgroup =
+// 16 rows of v, wavefront w = columns 16w..16w+15. Step Q contracts q = 16Q + 4g + s, so lane
+// (m, g) reads Kinv[p0 + m][16Q + 4g .. +3] (one 32-byte load) and t[16Q + 4g + s][16w + m].
 __global__ void __launch_bounds__(256) k_coarse_v(int n_cg, int k, const double* __restrict__ t,
                                                   const double* __restrict__ Kinv, double scale, double* __restrict__ v) {
-    __shared__ double tc[64][17];
-    const int p0 = blockIdx.x * 32, c0 = blockIdx.y * 16;
-    const int tid = threadIdx.x;
-    const int pr = tid >> 3, cg2 = (tid & 7) * 2;   // row p0+pr, columns c0+cg2, +1
-    double acc0 = 0.0, acc1 = 0.0;
-    const int p = p0 + pr;
-    for (int q0 = 0; q0 < n_cg; q0 += 64) {
-        for (int e = tid; e < 64 * 16; e += 256) {
-            const int qq = e >> 4, c = e & 15;
-            const int q = q0 + qq, col = c0 + c;
-            tc[qq][c] = (q < n_cg && col < k) ? t[(long long)q * k + col] : 0.0;
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
+    const int p0 = blockIdx.x * 16, col = 16 * wave + m;
+    const int prow = p0 + m;
+    v4 acc = v4{0.0, 0.0, 0.0, 0.0};
+    const int nQ = (n_cg + 15) >> 4;
+    const bool vec = (n_cg & 3) == 0;
+    for (int Q = 0; Q < nQ; ++Q) {
+        const int q0 = 16 * Q + 4 * g;
+        double a[4], bq[4];
+        if (vec && prow < n_cg && q0 + 3 < n_cg) {
+            const v4 av = *reinterpret_cast<const v4*>(Kinv + (long long)prow * n_cg + q0);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) a[s2] = av[s2];
+        } else {
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) a[s2] = (prow < n_cg && q0 + s2 < n_cg) ? Kinv[(long long)prow * n_cg + q0 + s2] : 0.0;
         }
-        __syncthreads();
-        if (p < n_cg) {
-            const int qn = min(64, n_cg - q0);
-            const double* Kr = Kinv + (long long)p * n_cg + q0;
-            for (int qq = 0; qq < qn; ++qq) {
-                const double kv = Kr[qq];
-                acc0 += kv * tc[qq][cg2];
-                acc1 += kv * tc[qq][cg2 + 1];
-            }
-        }
-        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) bq[s2] = (q0 + s2 < n_cg && col < k) ? t[(long long)(q0 + s2) * k + col] : 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], bq[s2], acc, 0, 0, 0);
     }
-    if (p < n_cg) {
-        if (c0 + cg2 < k) v[(long long)p * k + c0 + cg2] = scale * acc0;
-        if (c0 + cg2 + 1 < k) v[(long long)p * k + c0 + cg2 + 1] = scale * acc1;
+    // D layout: rows g + 4 j, column m
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = p0 + g + 4 * j;
+        if (p < n_cg && col < k) v[(long long)p * k + col] = scale * acc[j];
     }
 }
 
@@ -453,7 +457,7 @@ void launch_coarse(const DevTopo& t, int k, int ytype_f32, const void* T, const 
     else
         k_coarse_t<double><<<(int)((n + 255) / 256), 256, 0, st>>>(t.n_cg, k, (const double*)T, add, t.cc_ptr,
                                                                    t.cc_s, t.cc_j, t.subs, tbuf);
-    k_coarse_v<<<dim3((t.n_cg + 31) / 32, (k + 15) / 16), 256, 0, st>>>(t.n_cg, k, tbuf, Kinv, scale, v);
+    k_coarse_v<<<(t.n_cg + 15) / 16, 256, 0, st>>>(t.n_cg, k, tbuf, Kinv, scale, v);
 }
 
 // Y_s[j][c] += sum_q F_rc^s[j][q] v[cg(s,q)][c]  (the coarse correction folded into the local
@@ -463,6 +467,7 @@ __global__ void __launch_bounds__(256) k_fold_coarse(const SubMeta* __restrict__
                                                      const int* __restrict__ c_glob, const double* __restrict__ v,
                                                      TY* __restrict__ Y) {
     __shared__ double vs[32][64];
+    __shared__ double Fs[32][64];   // Fs[q][jj] = F_rc^T[q][j0 + jj]
     const int s = blockIdx.y;
     const SubMeta M = subs[s];
     const int j0 = blockIdx.x * 64;
@@ -470,18 +475,24 @@ __global__ void __launch_bounds__(256) k_fold_coarse(const SubMeta* __restrict__
     for (int e = threadIdx.x; e < M.n_c * 64; e += 256) {
         const int q = e >> 6, c = e & 63;
         vs[q][c] = c < k ? v[(long long)c_glob[M.off_c + q] * k + c] : 0.0;
+        Fs[q][c] = j0 + c < M.n_b ? F64[M.off_F + (long long)(M.rowT + q) * M.ldF + j0 + c] : 0.0;
     }
     __syncthreads();
     const int c = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (c >= k) return;
-    for (int jj = wave; jj < 64; jj += 4) {
-        const int j = j0 + jj;
-        if (j >= M.n_b) break;
-        const double* Fr = F64 + M.off_F + (long long)M.rowT * M.ldF + j;
+    const int nj = min(64, M.n_b - j0);
+    TY y[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int jj = wave + 4 * i;
+        y[i] = jj < nj ? Y[(M.off_b + j0 + jj) * k + c] : (TY)0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int jj = wave + 4 * i;
         double acc = 0.0;
-        for (int q = 0; q < M.n_c; ++q) acc += Fr[(long long)q * M.ldF] * vs[q][c];
-        TY* y = Y + (M.off_b + j) * k + c;
-        *y = (TY)((double)*y + acc);
+        for (int q = 0; q < M.n_c; ++q) acc += Fs[q][jj] * vs[q][c];
+        if (jj < nj) Y[(M.off_b + j0 + jj) * k + c] = (TY)((double)y[i] + acc);
     }
 }
 
@@ -500,9 +511,9 @@ template <typename TY>
 __global__ void k_scatter(int n_lambda, int k, const int* __restrict__ row_s, const int* __restrict__ row_j,
                           const int8_t* __restrict__ row_sg, const SubMeta* __restrict__ subs,
                           const TY* __restrict__ Y, double* __restrict__ Q) {
-    const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (idx >= (long long)n_lambda * k) return;
-    const int row = (int)(idx / k), c = (int)(idx % k);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_lambda * k) return;
+    const int row = k == 64 ? idx >> 6 : idx / k, c = idx - row * k;
     double val = 0.0;
     for (int t = 0; t < 2; ++t) {
         const int s = row_s[2 * row + t];

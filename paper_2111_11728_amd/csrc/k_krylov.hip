@@ -197,14 +197,279 @@ __global__ void __launch_bounds__(256) k_ts_gemm(int n, int kd, int nblk, const 
         }
 }
 
+// ---------------------------------------------------------------------------------------
+// Register-direct FP64 matrix-core forms for blocks of 64 directions (the common case).
+// Both use the freedom to permute the contraction and output indices consistently so that
+// every lane reads 16 or 32 contiguous bytes of a row-major n x 64 operand straight from
+// HBM, with a ring of loads in flight; no LDS round trip for the streamed operands.
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+
+constexpr int kTsWaves = 8;   // 128 output rows per workgroup
+
+// out = beta C + alpha sum_b A_b Psi_b (A_b = Aptrs[b], n x 64; Psi_b = Mats + 4096 b).
+// Wavefront: 16 output rows x 64 columns. Step t = 4 b + q contracts columns 16q..16q+15 of
+// A_b: lane (m = lane%16, g = lane/16) supplies A_b[row m][16q + 4g + s] at sub-step s, i.e.
+// one 32-byte load per step, issued a whole block (four steps) ahead; Psi_b is staged in LDS
+// in the matching operand order ((q*4 + j)*64 + lane)*4 + s <- Psi_b[16q + 4g + s][16j + m],
+// double-buffered per block.
+__global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
+                                                        const double* __restrict__ Mats, const double* C, double* out,
+                                                        double alpha, double beta) {
+    __shared__ __attribute__((aligned(16))) double Ps[2][4096];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int rb0 = blockIdx.x * (16 * kTsWaves) + 16 * wave;
+    const int arow = rb0 + m;
+    const bool av = arow < n;
+    constexpr int kPer = 4096 / (64 * kTsWaves);
+    double pst[kPer];
+    auto load_psi = [&](int b) {
+        const double* P = Mats + (long long)b * 4096;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) pst[u] = P[tid + 64 * kTsWaves * u];
+    };
+    auto store_psi = [&](double* Pb) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 64 * kTsWaves * u, kr = e >> 6, kc = e & 63;
+            Pb[(((kr >> 4) * 4 + (kc >> 4)) * 64 + ((kr & 15) >> 2) * 16 + (kc & 15)) * 4 + (kr & 3)] = pst[u];
+        }
+    };
+    const int nst = 4 * nblk;
+    auto load_a = [&](int t) -> v4d_t {
+        if (!av || t >= nst) return v4d_t{0.0, 0.0, 0.0, 0.0};
+        const double* A = Aptrs[t >> 2];
+        return *reinterpret_cast<const v4d_t*>(A + (long long)arow * 64 + 16 * (t & 3) + 4 * g);
+    };
+    v4d_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = v4d_t{0.0, 0.0, 0.0, 0.0};
+    v4d_t ring[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ring[q] = load_a(q);
+    load_psi(0);
+    store_psi(Ps[0]);
+    __syncthreads();
+    for (int b = 0; b < nblk; ++b) {
+        if (b + 1 < nblk) load_psi(b + 1);
+        const double* Pb = Ps[b & 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const v4d_t a = ring[q];
+            ring[q] = load_a(4 * (b + 1) + q);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const v4d_t bv = *reinterpret_cast<const v4d_t*>(Pb + ((q * 4 + j) * 64 + lane) * 4);
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], bv[s2], acc[j], 0, 0, 0);
+            }
+        }
+        if (b + 1 < nblk) store_psi(Ps[(b + 1) & 1]);
+        __syncthreads();
+    }
+    // D layout: lane holds rows g + 4v, column m of each 16x16 block j
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = rb0 + g + 4 * v;
+        if (row >= n) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long idx = (long long)row * 64 + 16 * j + m;
+            out[idx] = (beta == 0.0 ? 0.0 : beta * C[idx]) + alpha * acc[j][v];
+        }
+    }
+}
+
+constexpr int kGrRing = 6;    // 4-row steps in flight per lane
+constexpr int kGrGroups = 256; // workgroups per round: one per CU
+
+// Gram products Psi_b = A_b^T B for 64 directions over all blocks b < nblk at once. The
+// nblk * nsteps 4-row steps (block-major) are split evenly over the G workgroups (G a
+// multiple of 256, so no range spans more than two blocks); within a workgroup the four
+// wavefronts split each block segment and every wavefront accumulates a full 64 x 64
+// result (sixteen 16x16 FP64 accumulators, one wavefront per SIMD, loads kGrRing steps
+// ahead). Rows/columns are permuted so that at step st lane (m, g) loads A[4 st + g][4m..4m+3]
+// and B[4 st + g][4m..4m+3]: accumulator row m' of block ib is A column 4 m' + ib, column n'
+// of block jb is B column 4 n' + jb. The wavefront results meet in LDS (fixed order) and each
+// segment writes part[(w*2 + slot)*4096 + i*64 + j], slot 0 for the block of the range start.
+__global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double* const* __restrict__ Aptrs,
+                                                   const double* __restrict__ B, double* __restrict__ part) {
+    __shared__ double red[4 * 4096];
+    const int G = gridDim.x, w = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const long long nsteps = (n + 3) >> 2, S = nsteps * nblk;
+    const long long s_lo = (long long)w * S / G, s_hi = (long long)(w + 1) * S / G;
+    for (int slot = 0; slot < 2; ++slot) {
+        const long long b_ll = s_lo / nsteps + slot;
+        if (b_ll >= nblk || b_ll * nsteps >= s_hi) break;
+        const int b = (int)b_ll;
+        const long long a0 = std::max(s_lo, b_ll * nsteps) - b_ll * nsteps;
+        const long long a1 = std::min(s_hi, (b_ll + 1) * nsteps) - b_ll * nsteps;
+        const int w0 = (int)(a0 + (a1 - a0) * wave / 4), w1 = (int)(a0 + (a1 - a0) * (wave + 1) / 4);
+        const double* A = Aptrs[b];
+        v4d_t acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = v4d_t{0.0, 0.0, 0.0, 0.0};
+        v4d_t ar[kGrRing], br[kGrRing];
+        auto ld = [&](int st, v4d_t& av, v4d_t& bv) {
+            const int r = 4 * st + g;
+            if (st < w1 && r < n) {
+                av = *reinterpret_cast<const v4d_t*>(A + (long long)r * 64 + 4 * m);
+                bv = *reinterpret_cast<const v4d_t*>(B + (long long)r * 64 + 4 * m);
+            } else {
+                av = v4d_t{0.0, 0.0, 0.0, 0.0};
+                bv = v4d_t{0.0, 0.0, 0.0, 0.0};
+            }
+        };
+#pragma unroll
+        for (int d = 0; d < kGrRing; ++d) ld(w0 + d, ar[d], br[d]);
+        for (int st = w0; st < w1; st += kGrRing) {
+#pragma unroll
+            for (int d = 0; d < kGrRing; ++d) {
+                if (st + d < w1) {
+#pragma unroll
+                    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                        for (int jb = 0; jb < 4; ++jb)
+                            acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[d][ib], br[d][jb], acc[ib][jb], 0, 0, 0);
+                    ld(st + d + kGrRing, ar[d], br[d]);
+                }
+            }
+        }
+        // D layout: lane holds rows g + 4v, column m of block (ib, jb)
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    red[wave * 4096 + (4 * (g + 4 * v) + ib) * 64 + 4 * m + jb] = acc[ib][jb][v];
+        __syncthreads();
+        double* out = part + ((long long)w * 2 + slot) * 4096;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u;
+            out[e] = ((red[e] + red[4096 + e]) + red[8192 + e]) + red[12288 + e];
+        }
+        __syncthreads();
+    }
+}
+
+// out[b][e] = sum, in workgroup order, of the segment partials of block b: workgroup = 64
+// consecutive entries of one block; its four wavefronts take every fourth contributing
+// workgroup and meet in LDS.
+__global__ void __launch_bounds__(256) k_gram64_reduce(int n, int nblk, int G, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    __shared__ double red[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = blockIdx.x >> 6, e = ((blockIdx.x & 63) << 6) + lane;
+    const long long nsteps = (n + 3) >> 2, S = nsteps * nblk;
+    const long long bs = (long long)b * nsteps, be = bs + nsteps;
+    // contributing workgroups wf..wl: [w S / G, (w+1) S / G) meets [bs, be); only wf can
+    // start before bs (its block-b partial is then in slot 1)
+    long long wf = bs * G / S;
+    while (wf > 0 && wf * S / G > bs) --wf;
+    while ((wf + 1) * S / G <= bs) ++wf;
+    long long wl = (be * G + S - 1) / S;
+    if (wl > G - 1) wl = G - 1;
+    while (wl > wf && wl * S / G >= be) --wl;
+    const int slot_f = wf * S / G < bs ? 1 : 0;
+    double v = 0.0;
+    for (long long ww = wf + wave; ww <= wl; ww += 4)
+        v += part[(ww * 2 + (ww == wf ? slot_f : 0)) * 4096 + e];
+    red[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0) out[(long long)b * 4096 + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// part[c][0..63] = sum over the chunk's rows of A[row][:] * x[row] (A: n x 64). Lane = column;
+// a wavefront covers 8 rows per pass, four wavefronts summed in LDS (fixed order).
+__global__ void __launch_bounds__(256) k_gemv_t64(int n, const double* __restrict__ A, const double* __restrict__ x,
+                                                  double* __restrict__ part) {
+    __shared__ double red[4][64];
+    const int c = blockIdx.x, nchunk = gridDim.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r0 = (int)((long long)c * n / nchunk), r1 = (int)((long long)(c + 1) * n / nchunk);
+    double acc = 0.0;
+    for (int rr = r0 + 8 * wave; rr < r1; rr += 32) {
+        double av[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int row = rr + u;
+            av[u] = row < r1 ? A[(long long)row * 64 + lane] : 0.0;
+            xv[u] = row < r1 ? x[row] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(av[u], xv[u], acc);
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) part[(long long)c * 64 + lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// lam += W g; r -= Q g for 64 directions: 16 lanes per row, 4 consecutive columns each.
+__global__ void __launch_bounds__(256) k_update_lr64(int n, const double* __restrict__ W, const double* __restrict__ Q,
+                                                     const double* __restrict__ gm, double* __restrict__ lam,
+                                                     double* __restrict__ r) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int row = (int)(t >> 4), p = (int)(t & 15);
+    const v4d_t gv = *reinterpret_cast<const v4d_t*>(gm + 4 * p);
+    double dl = 0.0, dr = 0.0;
+    if (row < n) {
+        const v4d_t w = *reinterpret_cast<const v4d_t*>(W + (long long)row * 64 + 4 * p);
+        dl = ((w[0] * gv[0] + w[1] * gv[1]) + w[2] * gv[2]) + w[3] * gv[3];
+        if (Q) {
+            const v4d_t q = *reinterpret_cast<const v4d_t*>(Q + (long long)row * 64 + 4 * p);
+            dr = ((q[0] * gv[0] + q[1] * gv[1]) + q[2] * gv[2]) + q[3] * gv[3];
+        }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        dl += __shfl_xor(dl, o, 16);
+        dr += __shfl_xor(dr, o, 16);
+    }
+    if (row < n && p == 0) {
+        lam[row] += dl;
+        if (Q) r[row] -= dr;
+    }
+}
+
+// part[block] = sum over rows of r[row] * sum_c Z[row][c] for 64 columns: 16 lanes per row.
+__global__ void __launch_bounds__(256) k_rowsum_dot64(int n, const double* __restrict__ r, const double* __restrict__ Z,
+                                                      double* __restrict__ part) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (long long t = blockIdx.x * 256LL + threadIdx.x; t < 16LL * n; t += 256LL * gridDim.x) {
+        const int row = (int)(t >> 4), p = (int)(t & 15);
+        const v4d_t z = *reinterpret_cast<const v4d_t*>(Z + (long long)row * 64 + 4 * p);
+        acc = fma(r[row], ((z[0] + z[1]) + z[2]) + z[3], acc);
+    }
+    acc = warp_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
                     double* out, double alpha, double beta, hipStream_t st) {
-    if (n && nblk) k_ts_gemm<<<(n + 63) / 64, 256, 0, st>>>(n, kd, nblk, Aptrs, Mats, C, out, alpha, beta);
+    if (!n || !nblk) return;
+    if (kd == 64)
+        k_ts64<<<(n + 16 * kTsWaves - 1) / (16 * kTsWaves), 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha,
+                                                                                    beta);
+    else
+        k_ts_gemm<<<(n + 63) / 64, 256, 0, st>>>(n, kd, nblk, Aptrs, Mats, C, out, alpha, beta);
 }
 
 void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
                  double* out, hipStream_t st) {
     if (nblk == 0) return;
+    if (ka == 64 && kb == 64 && n >= 64) {
+        const int G = kGrGroups * ((nblk + kGrGroups - 1) / kGrGroups);
+        if ((long long)G * 2 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
+        k_gram64<<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part);
+        k_gram64_reduce<<<nblk * 64, 256, 0, st>>>(n, nblk, G, part, out);
+        return;
+    }
     const int nchunk = gram_chunks(n, nblk);
     if ((long long)nchunk * nblk * ka * kb > kGramPartCap) throw std::length_error("Gram partial buffer too small");
     if (ka >= 16 && kb >= 16)
@@ -222,32 +487,102 @@ void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, co
 // complement diagonal, lowest index on ties), stopping when that pivot is <= rr_tol.
 // Output T = S^{-1/2} N^T [Ltilde^{-T}; 0] (k x k row-major, zero columns beyond the rank)
 // so that W T is F-orthonormal, and the rank.
+// a[p] for a wavefront-uniform p: a scalar branch to one register move (no LDS round trip)
+__device__ __forceinline__ double pick64(const double (&a)[64], int p) {
+    switch (p) {
+        case 0: return a[0];
+        case 1: return a[1];
+        case 2: return a[2];
+        case 3: return a[3];
+        case 4: return a[4];
+        case 5: return a[5];
+        case 6: return a[6];
+        case 7: return a[7];
+        case 8: return a[8];
+        case 9: return a[9];
+        case 10: return a[10];
+        case 11: return a[11];
+        case 12: return a[12];
+        case 13: return a[13];
+        case 14: return a[14];
+        case 15: return a[15];
+        case 16: return a[16];
+        case 17: return a[17];
+        case 18: return a[18];
+        case 19: return a[19];
+        case 20: return a[20];
+        case 21: return a[21];
+        case 22: return a[22];
+        case 23: return a[23];
+        case 24: return a[24];
+        case 25: return a[25];
+        case 26: return a[26];
+        case 27: return a[27];
+        case 28: return a[28];
+        case 29: return a[29];
+        case 30: return a[30];
+        case 31: return a[31];
+        case 32: return a[32];
+        case 33: return a[33];
+        case 34: return a[34];
+        case 35: return a[35];
+        case 36: return a[36];
+        case 37: return a[37];
+        case 38: return a[38];
+        case 39: return a[39];
+        case 40: return a[40];
+        case 41: return a[41];
+        case 42: return a[42];
+        case 43: return a[43];
+        case 44: return a[44];
+        case 45: return a[45];
+        case 46: return a[46];
+        case 47: return a[47];
+        case 48: return a[48];
+        case 49: return a[49];
+        case 50: return a[50];
+        case 51: return a[51];
+        case 52: return a[52];
+        case 53: return a[53];
+        case 54: return a[54];
+        case 55: return a[55];
+        case 56: return a[56];
+        case 57: return a[57];
+        case 58: return a[58];
+        case 59: return a[59];
+        case 60: return a[60];
+        case 61: return a[61];
+        case 62: return a[62];
+        case 63: return a[63];
+        default: return 0.0;
+    }
+}
+
 __global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict__ D, double rr_tol,
                                                 double* __restrict__ T, int* __restrict__ rank_out) {
-    __shared__ double A[64][65];
-    __shared__ double L[64][65];   // L[m][l]: column m of the factor, indexed by original index l
-    __shared__ double X[64][65];
+    // lane l keeps column l of the working matrix (a[]) and, after the factorisation, column l
+    // of Ltilde^{-1} (x[]) in registers; the factor columns go through LDS
+    __shared__ double Lm[64][64];   // Lm[m][l]: entry l of factor column m (original indexing)
     __shared__ int order[64];
     __shared__ double scs[64];
     const int l = threadIdx.x;
-    for (int i = 0; i < k; ++i)
-        if (l < k) A[i][l] = 0.5 * (D[i * k + l] + D[l * k + i]);
-    __syncthreads();
-    double dg = l < k ? A[l][l] : -1.0;
+    double a[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) a[i] = (l < k && i < k) ? 0.5 * (D[i * k + l] + D[l * k + i]) : 0.0;
+    const double dg = l < k ? 0.5 * (D[l * k + l] + D[l * k + l]) : -1.0;
     double dmax = dg;
     for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
     const bool live = l < k && dmax > 0.0 && dg > 1e-30 * dmax;
     const double sc = live ? 1.0 / sqrt(dg) : 0.0;
     scs[l] = sc;
     __syncthreads();
-    // scale: lane l owns column l
-    for (int i = 0; i < k; ++i)
-        if (l < k) A[i][l] = A[i][l] * scs[i] * sc;
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 64; ++i) a[i] = a[i] * scs[i] * sc;
+    double diag = dg * sc * sc;   // = a[l]
     bool rem = live;
     int m = 0;
     for (; m < k; ++m) {
-        double cand = rem ? A[l][l] : -1.0e300;
+        double cand = rem ? diag : -1.0e300;
         int ci = l;
         for (int o = 32; o > 0; o >>= 1) {
             const double ov = __shfl_xor(cand, o, 64);
@@ -255,34 +590,54 @@ __global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict_
             if (ov > cand || (ov == cand && oi < ci)) { cand = ov; ci = oi; }
         }
         if (!(cand > rr_tol)) break;
-        const int p = ci;
+        const int p = __builtin_amdgcn_readfirstlane(ci);
         const double piv = sqrt(cand);
-        const double lc = (l == p) ? piv : (rem ? A[l][p] / piv : 0.0);
+        const double ipiv = 1.0 / piv;
+        // A[l][p] = A[p][l] (symmetric among the remaining indices) = a[p] of lane l
+        const double lc = (l == p) ? piv : (rem ? pick64(a, p) * ipiv : 0.0);
         if (l == p) rem = false;
-        if (l < 64) L[m][l] = lc;
+        Lm[m][l] = lc;
         if (l == 0) order[m] = p;
         __syncthreads();
         // Schur-complement update of the remaining columns: A[i][l] -= lc_i lc_l
-        if (rem)
-            for (int i = 0; i < k; ++i) A[i][l] -= L[m][i] * lc;
-        __syncthreads();
-    }
-    const int rank = m;
-    // Ltilde[r][c] = L[c][order[r]] (rank x rank lower); X = Ltilde^{-1}, lane c owns column c
-    if (l < rank) {
-        for (int r = 0; r < rank; ++r) {
-            double v = (r == l) ? 1.0 : 0.0;
-            for (int q = 0; q < r; ++q) v -= L[q][order[r]] * X[q][l];
-            X[r][l] = v / L[r][order[r]];
+        if (rem) {
+#pragma unroll
+            for (int i = 0; i < 64; ++i) a[i] -= Lm[m][i] * lc;
+            diag -= lc * lc;
         }
     }
     __syncthreads();
-    for (int i = 0; i < k; ++i)
-        if (l < k) T[i * k + l] = 0.0;
-    __syncthreads();
-    // T[order[r]][c] = s[order[r]] * (Ltilde^{-T})[r][c] = s[order[r]] * X[c][r]
-    if (l < rank)
-        for (int r = 0; r < rank; ++r) T[order[r] * k + l] = scs[order[r]] * X[l][r];
+    const int rank = m;
+    // Ltilde[r][c] = Lm[c][order[r]] (rank x rank lower); lane c: column c of X = Ltilde^{-1}
+    double x[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) {
+        x[r] = 0.0;
+        if (r < rank && l < rank) {
+            const int orr = order[r];
+            double v0 = (r == l) ? 1.0 : 0.0, v1 = 0.0;
+#pragma unroll
+            for (int q = 0; q + 1 < r; q += 2) {
+                v0 -= Lm[q][orr] * x[q];
+                v1 -= Lm[q + 1][orr] * x[q + 1];
+            }
+            if (r & 1) v0 -= Lm[r - 1][orr] * x[r - 1];
+            x[r] = (v0 + v1) / Lm[r][orr];
+        }
+    }
+    // T[order[r]][c] = s[order[r]] (Ltilde^{-T})[r][c] = s[order[r]] X[c][r]: lane r writes row
+    // order[r]; rows of indices never taken as pivots are zero (written by their own lane)
+    if (l < k) {
+        if (!(live && !rem))
+            for (int j = 0; j < k; ++j) T[l * k + j] = 0.0;
+        if (l < rank) {
+            const int row = order[l];
+            const double s = scs[row];
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                if (j < k) T[row * k + j] = j < rank ? s * x[j] : 0.0;
+        }
+    }
     if (l == 0) *rank_out = rank;
 }
 
@@ -340,7 +695,18 @@ __global__ void k_update_lr(int n, int k, const double* __restrict__ W, const do
 
 void launch_update_lr(int n, int k, const double* W, const double* Q, const double* g, double* lam, double* r,
                       hipStream_t st) {
-    if (n) k_update_lr<<<(n + 255) / 256, 256, 0, st>>>(n, k, W, Q, g, lam, r);
+    if (!n) return;
+    if (k == 64)
+        k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, r);
+    else
+        k_update_lr<<<(n + 255) / 256, 256, 0, st>>>(n, k, W, Q, g, lam, r);
+}
+
+void launch_gemv_t(int n, int k, const double* A, const double* x, double* part, double* out, hipStream_t st) {
+    if (k != 64) throw std::invalid_argument("launch_gemv_t takes 64 columns");
+    const int nchunk = std::max(1, std::min(256, (n + 1023) / 1024));
+    k_gemv_t64<<<nchunk, 256, 0, st>>>(n, A, x, part);
+    k_gram_reduce<<<1, 64, 0, st>>>(nchunk, 1, 64, 1, part, out);
 }
 
 // W -= sum_b W_b Psi_b, Psi_b = Psi + b*k*k (k x k), W_b = Wptrs[b] (n x k).
@@ -411,7 +777,10 @@ __global__ void k_sum(int n, const double* __restrict__ part, double* __restrict
 
 void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st) {
     const int nb = std::max(1, std::min(256, (n + 255) / 256));
-    k_rowsum_dot<<<nb, 256, 0, st>>>(n, k, r, Z, part);
+    if (k == 64)
+        k_rowsum_dot64<<<nb, 256, 0, st>>>(n, r, Z, part);
+    else
+        k_rowsum_dot<<<nb, 256, 0, st>>>(n, k, r, Z, part);
     k_sum<<<1, 64, 0, st>>>(nb, part, out);
 }
 

@@ -128,7 +128,7 @@ class Spec:
     """ctypes views of a workloads.Problem (keeps the host arrays alive)."""
 
     def __init__(self, prob, method="fetidp", scaling="k", krylov="pcg", precond="dirichlet", precision="fp64",
-                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=2, max_refine=-1, relax=0.0):
+                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0):
         self.prob = prob
         fixed = np.ascontiguousarray(prob.fixed_dofs(), dtype=np.int32)
         self._fixed = fixed
