@@ -43,6 +43,7 @@ struct LineMeta {
     int pad_;
     long long off_diag; // n x n dense diagonal block (lower triangle holds L_kk after factorisation)
     long long off_sub;  // n x n_prev dense block coupling to the previous block (L_{k,k-1})
+    long long off_inv;  // n x n explicit L_kk^{-1} (lower triangle) in the inverse buffer
 };
 
 __device__ __forceinline__ double warp_sum(double v) {

@@ -123,7 +123,7 @@ struct feti_ctx {
     long long bytes = 0;
 
     // numeric state
-    double *rho = nullptr, *L = nullptr, *Z = nullptr, *S = nullptr, *diag = nullptr, *F64 = nullptr;
+    double *rho = nullptr, *L = nullptr, *Li = nullptr, *Z = nullptr, *S = nullptr, *diag = nullptr, *F64 = nullptr;
     double* sw64 = nullptr;
     float* sw32 = nullptr;
     __hip_bfloat16 *swhi = nullptr, *swlo = nullptr;
@@ -238,7 +238,7 @@ void build_layout(feti_ctx* c) {
     const int ns = P.n_sub;
     c->hsubs.assign(ns, SubMeta{});
     c->hlines.clear();
-    long long oL = 0, oZ = 0, oS = 0, oF = 0, oP = 0, oKc = 0, oR = 0;
+    long long oL = 0, oZ = 0, oS = 0, oF = 0, oP = 0, oKc = 0, oR = 0, oLi = 0;
     DevTopo& t = c->t;
     const int nrbm = P.method == FETI_TFETI ? (P.dim == 2 ? 3 : 6) : 0;
     for (int s = 0; s < ns; ++s) {
@@ -280,6 +280,8 @@ void build_layout(feti_ctx* c) {
             oL += (long long)n * n;
             Lm.off_sub = oL;
             oL += (long long)n * prev;
+            Lm.off_inv = oLi;
+            oLi += (long long)n * n;
             c->hlines.push_back(Lm);
             t.max_line = std::max(t.max_line, n);
             i0 += n;
@@ -308,6 +310,7 @@ void build_layout(feti_ctx* c) {
     }
     t.dim = P.dim;
     t.n_sub = ns;
+    t.n_lines_tot = (int)c->hlines.size();
     t.n_lambda = P.n_lambda;
     t.n_cg = P.n_cg;
     t.n_groups = P.n_groups;
@@ -325,6 +328,7 @@ void build_layout(feti_ctx* c) {
 
     // ---- device buffers ----
     c->L = c->alloc<double>(oL);
+    c->Li = c->alloc<double>(std::max(1LL, oLi));
     c->Z = c->alloc<double>(oZ);
     c->S = c->alloc<double>(oS);
     c->F64 = c->alloc<double>(oF);
@@ -626,6 +630,8 @@ void numeric_setup(feti_ctx* c) {
     launch_bt_factor(t, c->L, c->info, st);
     CHECK_LAUNCH();
     check_info(c, t.n_sub, "interior Cholesky");
+    launch_bt_invert(t, c->L, c->Li, st);
+    CHECK_LAUNCH();
     launch_bt_forward(t, c->L, c->Z, st);
     CHECK_LAUNCH();
     if (c->opts.precond == FETI_LUMPED) launch_copy_Sbb(t, c->S, c->P64, 0, st);
@@ -738,7 +744,7 @@ void compute_rhs(feti_ctx* c, const double* f) {
     c->have_f = true;
     launch_scatter_f(t, f, c->fi, c->fbeta, st);
     HIPCHK(hipMemcpyAsync(c->h, c->fi, sizeof(double) * std::max<long long>(1, t.ni_tot), hipMemcpyDeviceToDevice, st));
-    launch_bt_fsolve1(t, c->L, c->h, st);
+    launch_bt_fsolve1(t, c->L, c->Li, c->h, st);
     launch_zt_gemv(t, c->Z, c->h, c->fbeta, c->g, st);
     launch_local_F(t, c->F64, c->g, c->yb, c->yc, st);
     CHECK_LAUNCH();
@@ -1040,7 +1046,7 @@ void recover(feti_ctx* c, double* u) {
     }
     CHECK_LAUNCH();
     launch_z_gemv(t, c->Z, c->ubeta, c->h, c->ui, st);
-    launch_bt_bsolve1(t, c->L, c->ui, st);
+    launch_bt_bsolve1(t, c->L, c->Li, c->ui, st);
     launch_assemble_loc(t, c->ui, c->ubeta, c->Cit, alpha, c->uloc, st);
     launch_average(t, c->uloc, u, st);
     CHECK_LAUNCH();

@@ -3,6 +3,7 @@
 // d_r, fbar_c), recovery of the primal solution, averaging of the subdomain copies and
 // the compliance with its adjoint gradient.
 #include "kernels.hpp"
+#include "dense_wg.hpp"
 
 namespace feti {
 
@@ -98,12 +99,147 @@ __global__ void __launch_bounds__(64) k_bt_bsolve1(const SubMeta* __restrict__ s
     }
 }
 
-void launch_bt_fsolve1(const DevTopo& t, const double* L, double* h, hipStream_t st) {
-    k_bt_fsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, h);
+// Sweeps with the explicit diagonal inverses (every line <= kSweepMaxLine DOFs): per line
+// one product with the coupling block and one with L_kk^{-1}. The forward sweep stages both
+// blocks in LDS (stride n+1: conflict-free row reads); the backward sweep reads them by
+// columns, which is coalesced straight from HBM. One 256-thread workgroup per subdomain.
+constexpr int kSwT = 256;
+
+// rows x cols (cols <= 128) from HBM into LDS with stride cols + 1: two rows per pass of the
+// workgroup, eight passes of loads in flight before they are stored
+__device__ inline void stage_block(double* A, const double* __restrict__ g, int rows, int cols) {
+    const int c = threadIdx.x & 127, half = threadIdx.x >> 7;
+    for (int r0 = 0; r0 < rows; r0 += 16) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int r = r0 + 2 * u + half;
+            v[u] = (r < rows && c < cols) ? g[(long long)r * cols + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int r = r0 + 2 * u + half;
+            if (r < rows && c < cols) A[r * (cols + 1) + c] = v[u];
+        }
+    }
 }
 
-void launch_bt_bsolve1(const DevTopo& t, const double* L, double* x, hipStream_t st) {
-    k_bt_bsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, x);
+__global__ void __launch_bounds__(kSwT) k_bt_fsweep(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
+                                                    const double* __restrict__ Lbuf, const double* __restrict__ Li,
+                                                    double* h) {
+    __shared__ double A[kSweepMaxLine * (kSweepMaxLine + 1)];
+    __shared__ double xp[kSweepMaxLine], v[kSweepMaxLine];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int r = threadIdx.x;
+    double* hs = h + M.off_i;
+    for (int k = 0; k < M.n_lines; ++k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        // v = b_k - L_{k,k-1} x_{k-1}
+        if (Lk.n_prev > 0) stage_block(A, Lbuf + Lk.off_sub, Lk.n, Lk.n_prev);
+        __syncthreads();
+        if (r < Lk.n) {
+            double a = hs[Lk.i0 + r];
+            for (int q = 0; q < Lk.n_prev; ++q) a -= A[r * (Lk.n_prev + 1) + q] * xp[q];
+            v[r] = a;
+        }
+        __syncthreads();
+        // x_k = L_kk^{-1} v
+        stage_block(A, Li + Lk.off_inv, Lk.n, Lk.n);
+        __syncthreads();
+        if (r < Lk.n) {
+            double a = 0.0;
+            for (int c = 0; c <= r; ++c) a += A[r * (Lk.n + 1) + c] * v[c];
+            hs[Lk.i0 + r] = a;
+            xp[r] = a;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kSwT) k_bt_bsweep(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
+                                                    const double* __restrict__ Lbuf, const double* __restrict__ Li,
+                                                    double* x) {
+    __shared__ double xn[kSweepMaxLine], w[kSweepMaxLine];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int q = threadIdx.x;
+    double* xg = x + M.off_i;
+    for (int k = M.n_lines - 1; k >= 0; --k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        // w = t_k - L_{k+1,k}^T x_{k+1}  (L_{k+1,k}: n_next x n, row-major; column q by thread q;
+        // xn holds x_{k+1} whenever line k+1 is not empty)
+        const int n_next = k + 1 < M.n_lines ? lines[M.line0 + k + 1].n : 0;
+        if (q < Lk.n) {
+            double a = xg[Lk.i0 + q];
+            if (n_next > 0) {
+                const double* C = Lbuf + lines[M.line0 + k + 1].off_sub;
+                for (int r0 = 0; r0 < n_next; r0 += 8) {
+                    double cv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) cv[u] = r0 + u < n_next ? C[(long long)(r0 + u) * Lk.n + q] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (r0 + u < n_next) a -= cv[u] * xn[r0 + u];
+                }
+            }
+            w[q] = a;
+        }
+        __syncthreads();
+        // x_k = L_kk^{-T} w: x_q = sum_{r >= q} Li[r][q] w_r
+        double a = 0.0;
+        if (q < Lk.n) {
+            // every thread walks the rows in the same order (coalesced); L_kk^{-1} is zero
+            // above its diagonal
+            const double* Ib = Li + Lk.off_inv;
+            for (int r0 = 0; r0 < Lk.n; r0 += 8) {
+                double iv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) iv[u] = r0 + u < Lk.n ? Ib[(long long)(r0 + u) * Lk.n + q] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (r0 + u < Lk.n) a += iv[u] * w[r0 + u];
+            }
+        }
+        __syncthreads();
+        if (q < Lk.n) {
+            xg[Lk.i0 + q] = a;
+            xn[q] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// Li = L_kk^{-1} for every line block of every subdomain (identity, then L_kk^{-1} I).
+__global__ void __launch_bounds__(256) k_bt_invert(const LineMeta* __restrict__ lines, const double* __restrict__ Lbuf,
+                                                   double* Li) {
+    __shared__ double lds[kLdsDoubles];
+    const LineMeta Lk = lines[blockIdx.x];
+    if (Lk.n == 0) return;
+    double* X = Li + Lk.off_inv;
+    for (int e = threadIdx.x; e < Lk.n * Lk.n; e += 256) X[e] = (e / Lk.n == e % Lk.n) ? 1.0 : 0.0;
+    __syncthreads();
+    wg_trsm_lower(Lk.n, Lk.n, Lbuf + Lk.off_diag, Lk.n, X, Lk.n, 1, lds);
+}
+
+void launch_bt_invert(const DevTopo& t, const double* L, double* Li, hipStream_t st) {
+    if (t.max_line <= kSweepMaxLine && t.n_lines_tot > 0) k_bt_invert<<<t.n_lines_tot, 256, 0, st>>>(t.lines, L, Li);
+}
+
+void launch_bt_fsolve1(const DevTopo& t, const double* L, const double* Li, double* h, hipStream_t st) {
+    if (t.max_line <= kSweepMaxLine)
+        k_bt_fsweep<<<t.n_sub, kSwT, 0, st>>>(t.subs, t.lines, L, Li, h);
+    else
+        k_bt_fsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, h);
+}
+
+void launch_bt_bsolve1(const DevTopo& t, const double* L, const double* Li, double* x, hipStream_t st) {
+    if (t.max_line <= kSweepMaxLine)
+        k_bt_bsweep<<<t.n_sub, kSwT, 0, st>>>(t.subs, t.lines, L, Li, x);
+    else
+        k_bt_bsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, x);
 }
 
 // g = fbeta - Z^T h  (thread per interface column)

@@ -76,6 +76,7 @@ struct DevTopo {
     const int* ax_cnt[3] = {nullptr, nullptr, nullptr};
     const int* gmap = nullptr;        // fixed-width gather map: gmap[q*gmap_R + t] = sign*(row+1), 0 unused
     int gmap_R = 1;
+    int n_lines_tot = 0;              // interior line (2D) / plane (3D) blocks over all subdomains
     FlTiles fl64;                     // F*Lambda work list with every row block in FP64
     FlTiles flred;                    // ... with every row block in the reduced precision
 };
@@ -166,8 +167,12 @@ void launch_pcg_dir(int n, const double* sc, const double* z, double* w, hipStre
 
 // ---- solve-phase (k_solve.hip) ----
 void launch_scatter_f(const DevTopo& t, const double* f, double* fi, double* fbeta, hipStream_t st);
-void launch_bt_fsolve1(const DevTopo& t, const double* L, double* h, hipStream_t st);
-void launch_bt_bsolve1(const DevTopo& t, const double* L, double* x, hipStream_t st);
+// Li: explicit inverses of the diagonal Cholesky blocks (LineMeta::off_inv), used when every
+// line has at most kSweepMaxLine DOFs
+void launch_bt_fsolve1(const DevTopo& t, const double* L, const double* Li, double* h, hipStream_t st);
+void launch_bt_bsolve1(const DevTopo& t, const double* L, const double* Li, double* x, hipStream_t st);
+void launch_bt_invert(const DevTopo& t, const double* L, double* Li, hipStream_t st);
+constexpr int kSweepMaxLine = 128;
 void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g,
                     hipStream_t st);  // g = fbeta - Z^T h
 void launch_z_gemv(const DevTopo& t, const double* Z, const double* ubeta, const double* h, double* x,
