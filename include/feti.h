@@ -90,7 +90,7 @@ typedef struct {
     double relax;             /* mixed precision: an iteration applies the FP64 operator while
                                  sqrt(r^T z) > relax * sqrt(r_0^T z_0) and the reduced-precision one
                                  below it, so the large early steps carry no reduced-precision
-                                 error into lambda (<= 0: min(1, 0.1 tol / delta) with delta = 1e-5
+                                 error into lambda (<= 0: min(1, 0.1 tol / delta) with delta = 1e-4
                                  for FETI_FP32 and 1e-3 for FETI_BF16X3) */
 } feti_opts;
 

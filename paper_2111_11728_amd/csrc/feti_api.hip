@@ -208,21 +208,24 @@ namespace {
 struct RbRange {
     int red0, n_red, d0, n_d;
 };
-// max_d caps the FP64 row blocks of one tile (small tiles spread FP64 work over many CUs).
-std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, int max_d = kFlWaves) {
+// max_d caps the FP64 row blocks of one tile (small tiles spread FP64 work over many CUs);
+// xcd = false lists the tiles in order (no XCD grouping, no empty slots).
+std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, int max_d = kFlWaves, bool xcd = true) {
     std::vector<std::vector<FlTile>> bucket(8);
     for (int s = 0; s < (int)rr.size(); ++s) {
         RbRange r = rr[s];
         while (r.n_red > 0 || r.n_d > 0) {
             FlTile T{s, r.red0, std::min(r.n_red, 2 * kFlWaves), r.d0, 0, flags, 0, 0};
-            T.n_d = std::min({r.n_d, max_d, kFlWaves - (T.n_red + 1) / 2});
+            const int mixed = (flags & kFlSplitK) ? 0 : ((T.n_red & 1) && r.n_d > 0 ? 1 : 0);
+            T.n_d = std::min({r.n_d, max_d, kFlWaves - (T.n_red + 1) / 2 + mixed});
             r.red0 += T.n_red;
             r.n_red -= T.n_red;
             r.d0 += T.n_d;
             r.n_d -= T.n_d;
-            bucket[s % 8].push_back(T);
+            bucket[xcd ? s % 8 : 0].push_back(T);
         }
     }
+    if (!xcd) return bucket[0];
     size_t mx = 0;
     for (auto& b : bucket) mx = std::max(mx, b.size());
     std::vector<FlTile> out;
@@ -526,18 +529,18 @@ void classify_precision(feti_ctx* c) {
         fprintf(stderr, "[feti] round-off metric quantiles: 50%% %.2e 80%% %.2e 90%% %.2e 95%% %.2e max %.2e\n",
                 d2[d2.size() / 2], d2[d2.size() * 8 / 10], d2[d2.size() * 9 / 10], d2[d2.size() * 95 / 100], d2.back());
     }
-    // Reduced precision: every row block of the subdomains that passed, without writing the
-    // F_rc^T rows. FP64, in a second launch of one-block tiles: the row blocks holding F_rc^T
-    // rows (the coarse right-hand side stays FP64: Kbar_cc^{-1} amplifies its errors) and all
-    // row blocks of the subdomains that failed, spread over many CUs.
+    // Subdomains that passed: reduced precision for their F_s row blocks, FP64 for the blocks
+    // holding F_rc^T rows (the coarse right-hand side stays FP64: Kbar_cc^{-1} amplifies its
+    // errors), in the same tile. Subdomains that failed: FP64, in a second launch of split-
+    // contraction tiles of four row blocks, spread over many CUs.
     std::vector<RbRange> rr(t.n_sub), rd(t.n_sub);
     for (int s = 0; s < t.n_sub; ++s) {
         const SubMeta& M = c->hsubs[s];
-        const int nrb = M.rows_F / 16, t0 = M.rowT / 16;
-        rr[s] = ok[s] ? RbRange{0, nrb, 0, 0} : RbRange{0, 0, 0, 0};
-        rd[s] = ok[s] ? (M.n_c > 0 ? RbRange{0, 0, t0, nrb - t0} : RbRange{0, 0, 0, 0}) : RbRange{0, 0, 0, nrb};
+        const int nrb = M.rows_F / 16, t0 = M.n_c > 0 ? M.rowT / 16 : nrb;
+        rr[s] = ok[s] ? RbRange{0, t0, t0, nrb - t0} : RbRange{0, 0, 0, 0};
+        rd[s] = ok[s] ? RbRange{0, 0, 0, 0} : RbRange{0, 0, 0, nrb};
     }
-    const std::vector<FlTile> tr = pack_tiles(rr, kFlNoT), td = pack_tiles(rd, kFlSplitK, 1);
+    const std::vector<FlTile> tr = pack_tiles(rr, kFlNoT), td = pack_tiles(rd, kFlSplitK, 4, false);
     auto put = [&](const std::vector<FlTile>& v, FlTile*& dev, int& cap, FlTiles& out) {
         if ((int)v.size() > cap) {
             if (dev) HIPCHK(hipFree(dev));
@@ -1084,7 +1087,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         int cur = prec;
         double prev_rel = 1.0;
         double sw = c->opts.relax;
-        if (!(sw > 0.0)) sw = std::min(1.0, 0.1 * tol / (prec == FETI_BF16X3 ? 1e-3 : 1e-5));
+        if (!(sw > 0.0)) sw = std::min(1.0, 0.1 * tol / (prec == FETI_BF16X3 ? 1e-3 : 1e-4));
         if (eps0 > 0.0) {
             for (int pass = 0;; ++pass) {
                 HIPCHK(hipMemsetAsync(c->lt, 0, sizeof(double) * n, st));

@@ -279,31 +279,52 @@ __device__ __forceinline__ void fl_fp64(const FlCtx& C, const double* __restrict
     store_block<Out>(M, 16 * rb0, lane, C.k, NB, true, true, nullptr, d, Y, T);
 }
 
-// One FP64 row block with the contraction split over the wavefronts: wavefront w takes the
-// 16-column steps [w KQ/16, (w+1) KQ/16) while their X_s chunk is resident; the partial
-// blocks then meet in LDS and are summed in wavefront order (deterministic).
+// Up to four FP64 row blocks with the contraction split four ways: wavefront w takes row
+// block d0 + w/4 and, in every X_s chunk, the 16-column steps 8ch + (w%4) + 4j (j = 0, 1), whose
+// operands it loads one chunk ahead; the four partial blocks of each row block then meet in
+// LDS and are summed in slice order (deterministic).
 template <int NB, typename Out>
-__device__ __forceinline__ void fl_fp64_splitk(const FlCtx& C, const double* __restrict__ A64, int rb0,
+__device__ __forceinline__ void fl_fp64_splitk(const FlCtx& C, const double* __restrict__ A64, int d0, int n_d,
                                                Out* __restrict__ Y, Out* __restrict__ T) {
+    constexpr int S = 4;
+    static_assert(kXC == 128, "two steps per slice and chunk");
     const SubMeta& M = C.M;
     const int lane = C.lane, wave = fl_wave(), KQ = M.ldF >> 4;
-    const int kq0 = wave * KQ / kFlWaves, kq1 = (wave + 1) * KQ / kFlWaves;
-    const double* p = A64 + M.off_Fsw + (long long)rb0 * KQ * 256 + lane * 4;
+    const int ri = wave / S, sl = wave % S;
+    const bool act = ri < n_d;
+    const double* p = A64 + M.off_Fsw + (long long)(d0 + (act ? ri : 0)) * KQ * 256 + lane * 4;
+    auto ld = [&](int ch, v4d* a) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int kq = 8 * ch + sl + 4 * j;
+            a[j] = (act && kq < KQ) ? *reinterpret_cast<const v4d*>(p + kq * 256) : v4d{0.0, 0.0, 0.0, 0.0};
+        }
+    };
     v4d acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = v4d{0.0, 0.0, 0.0, 0.0};
+    v4d pre[2];
+    ld(0, pre);
+    int ch = 0;
     fl_chunks(C, [&](const double* Xb, int kc0, int kcn) {
-        const int c0 = kc0 >> 4;
-        const int lo = max(kq0, c0), hi = min(kq1, c0 + (kcn >> 4));
-        for (int gkq = lo; gkq < hi; ++gkq) {
-            const v4d a = *reinterpret_cast<const v4d*>(p + gkq * 256);
+        const v4d cur[2] = {pre[0], pre[1]};
+        ld(ch + 1, pre);
+        if (act) {
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const v4d xv = *reinterpret_cast<const v4d*>(Xb + (((gkq - c0) * 4 + nb) * 64 + lane) * 4);
+            for (int j = 0; j < 2; ++j) {
+                const int kql = sl + 4 * j;
+                if (kql < (kcn >> 4)) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], xv[q], acc[nb], 0, 0, 0);
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[j][q], xv[q], acc[nb], 0, 0, 0);
+                    }
+                }
             }
         }
+        ++ch;
     });
     // partials: Xs[(w * 4 NB + nb * 4 + v) * 64 + lane] (the chunk buffers are free after the last barrier)
     double* P = C.Xs;
@@ -312,12 +333,12 @@ __device__ __forceinline__ void fl_fp64_splitk(const FlCtx& C, const double* __r
 #pragma unroll
         for (int v = 0; v < 4; ++v) P[(wave * 4 * NB + nb * 4 + v) * 64 + lane] = acc[nb][v];
     __syncthreads();
-    const int e = threadIdx.x;
-    if (e < 4 * NB * 64) {
+    for (int e = threadIdx.x; e < n_d * 4 * NB * 64; e += kFLThreads) {
+        const int r = e / (4 * NB * 64), el = e - r * (4 * NB * 64);
         double sum = 0.0;
-        for (int w = 0; w < kFlWaves; ++w) sum += P[w * 4 * NB * 64 + e];
-        const int nbv = e >> 6, l = e & 63, nb = nbv >> 2, v = nbv & 3;
-        const int row = 16 * rb0 + (l >> 4) + 4 * v, col = nb * 16 + (l & 15);
+        for (int w = r * S; w < (r + 1) * S; ++w) sum += P[w * 4 * NB * 64 + el];
+        const int nbv = el >> 6, l = el & 63, nb = nbv >> 2, v = nbv & 3;
+        const int row = 16 * (d0 + r) + (l >> 4) + 4 * v, col = nb * 16 + (l & 15);
         if (col < C.k) {
             if (row < M.n_b)
                 Y[(M.off_b + row) * C.k + col] = (Out)sum;
@@ -325,6 +346,88 @@ __device__ __forceinline__ void fl_fp64_splitk(const FlCtx& C, const double* __r
                 T[(M.off_c + row - M.rowT) * C.k + col] = (Out)sum;
         }
     }
+}
+
+// One reduced-precision row block and one FP64 row block in the same wavefront (a tile whose
+// reduced row-block count is odd gives its last reduced wavefront the first FP64 block; both
+// together cost one FP32 pair).
+template <int P, int NB, typename Out>
+__device__ __forceinline__ void fl_mixed(const FlCtx& C, const void* __restrict__ Ared_, const void* __restrict__ Ared_lo_,
+                                         const double* __restrict__ A64, int rbr, int rbd, Out* __restrict__ Y,
+                                         Out* __restrict__ T) {
+    const SubMeta& M = C.M;
+    const int lane = C.lane, KQ = M.ldF >> 4, KB = M.ldF >> 5;
+    v4f accr[NB];
+    v4d accd[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        accr[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+        accd[nb] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    const double* pd = A64 + M.off_Fsw + (long long)rbd * KQ * 256 + lane * 4;
+    fl_chunks(C, [&](const double* Xb, int kc0, int kcn) {
+        if constexpr (P == FETI_FP32) {
+            const float* pf = reinterpret_cast<const float*>(Ared_) + M.off_Fsw + (long long)rbr * KQ * 256 + lane * 4;
+            for (int kql = 0; kql < (kcn >> 4); ++kql) {
+                const int gkq = (kc0 >> 4) + kql;
+                const v4f af = *reinterpret_cast<const v4f*>(pf + gkq * 256);
+                const v4d ad = *reinterpret_cast<const v4d*>(pd + gkq * 256);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        accr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q], (float)xv[q], accr[nb], 0, 0, 0);
+                        accd[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[q], xv[q], accd[nb], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            const v8bf* H = reinterpret_cast<const v8bf*>(Ared_) + (M.off_Fsw >> 3) + lane + (long long)rbr * KB * 64;
+            const v8bf* L = reinterpret_cast<const v8bf*>(Ared_lo_) + (M.off_Fsw >> 3) + lane + (long long)rbr * KB * 64;
+            for (int kbl = 0; kbl < (kcn >> 5); ++kbl) {
+                const int gkb = (kc0 >> 5) + kbl;
+                const v8bf h = H[gkb * 64], l = L[gkb * 64];
+                const v4d ad0 = *reinterpret_cast<const v4d*>(pd + (2 * gkb) * 256);
+                const v4d ad1 = *reinterpret_cast<const v4d*>(pd + (2 * gkb + 1) * 256);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const v4d x0 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl) * 4 + nb) * 64 + lane) * 4);
+                    const v4d x1 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl + 1) * 4 + nb) * 64 + lane) * 4);
+                    v8bf bh, bl;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        __bf16 hi, lo;
+                        split_bf16(x0[q], hi, lo);
+                        bh[q] = hi;
+                        bl[q] = lo;
+                        split_bf16(x1[q], hi, lo);
+                        bh[4 + q] = hi;
+                        bl[4 + q] = lo;
+                    }
+                    accr[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bh, accr[nb], 0, 0, 0);
+                    accr[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bl, accr[nb], 0, 0, 0);
+                    accr[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bh, accr[nb], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        accd[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad0[q], x0[q], accd[nb], 0, 0, 0);
+                        accd[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad1[q], x1[q], accd[nb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    });
+    float f[4 * NB];
+    double d[4 * NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            f[nb * 4 + v] = accr[nb][v];
+            d[nb * 4 + v] = accd[nb][v];
+        }
+    store_block<Out>(M, 16 * rbr, lane, C.k, NB, false, false, f, nullptr, Y, T);
+    store_block<Out>(M, 16 * rbd, lane, C.k, NB, true, true, nullptr, d, Y, T);
 }
 
 // P: precision of the reduced row blocks (FETI_FP64: none); NB: 16-column blocks of the
@@ -343,23 +446,32 @@ __global__ void __launch_bounds__(kFLThreads) k_flambda(const SubMeta* __restric
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const FlCtx C{M, k, R, lane, gmap, Lambda, Xs};
     if (tl.flags & kFlSplitK) {
-        fl_fp64_splitk<NB, Out>(C, A64, tl.d0, Y, T);
+        fl_fp64_splitk<NB, Out>(C, A64, tl.d0, tl.n_d, Y, T);
         return;
     }
-    // wavefront role (uniform): two reduced row blocks, one FP64 row block, or gather only
+    // wavefront role (uniform): two reduced row blocks; one reduced and one FP64 row block (the
+    // last reduced wavefront of an odd count, when FP64 blocks follow); one FP64 row block; or
+    // gather only
     const int nw_red = (tl.n_red + 1) >> 1;
+    const int mixed = P != FETI_FP64 && (tl.n_red & 1) && tl.n_d > 0;
     if (P != FETI_FP64 && wave < nw_red) {
         const int rb0 = tl.red0 + 2 * wave;
         const bool two = 2 * wave + 1 < tl.n_red;
         const int rb1 = two ? rb0 + 1 : rb0;
         const bool storeT = !(tl.flags & kFlNoT);
+        if constexpr (P != FETI_FP64) {
+            if (!two && mixed) {
+                fl_mixed<P, NB, Out>(C, Ared_, Ared_lo_, A64, rb0, tl.d0, Y, T);
+                return;
+            }
+        }
         if constexpr (P == FETI_FP32)
             fl_fp32<NB, Out>(C, reinterpret_cast<const float*>(Ared_), rb0, rb1, two, storeT, Y, T);
         else if constexpr (P == FETI_BF16X3)
             fl_bf16<NB, Out>(C, reinterpret_cast<const __bf16*>(Ared_), reinterpret_cast<const __bf16*>(Ared_lo_), rb0,
                              rb1, two, storeT, Y, T);
-    } else if (wave >= nw_red && wave - nw_red < tl.n_d) {
-        fl_fp64<NB, Out>(C, A64, tl.d0 + wave - nw_red, Y, T);
+    } else if (wave >= nw_red && wave - nw_red < tl.n_d - mixed) {
+        fl_fp64<NB, Out>(C, A64, tl.d0 + mixed + wave - nw_red, Y, T);
     } else {
         fl_chunks(C, [](const double*, int, int) {});
     }

@@ -14,7 +14,9 @@ namespace feti {
 
 // F*Lambda work item: one workgroup per tile, all rows of one subdomain's augmented operator
 // A_s = [F_s; F_rc^sT] in 16-row blocks: n_red blocks from red0 in the reduced precision (two
-// per wavefront) and n_d blocks from d0 in FP64 (one per wavefront); (n_red+1)/2 + n_d <= 16.
+// per wavefront) and n_d blocks from d0 in FP64 (one per wavefront; with an odd n_red the last
+// reduced wavefront also takes block d0): (n_red+1)/2 + n_d - (n_red odd && n_d > 0) <= 16.
+// kFlSplitK tiles hold n_d <= 4 FP64 blocks with the contraction split four ways.
 constexpr int kFlWaves = 16;   // wavefronts per F*Lambda workgroup
 struct FlTile {
     int s, red0, n_red, d0, n_d, flags, pad1, pad2;   // s < 0: empty slot
