@@ -558,11 +558,38 @@ __device__ __forceinline__ double pick64(const double (&a)[64], int p) {
     }
 }
 
+// max over the wavefront of a double: DPP within rows of 16 (xor 1, xor 2, rotate 4, rotate 8),
+// then the four row maxima through readlane (uniform result)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    const int nlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const int nhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)nhi << 32) | (unsigned int)nlo);
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_mov<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_mov<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_mov<0x124>(v));   // row_ror:4
+    v = fmax(v, dpp_mov<0x128>(v));   // row_ror:8
+    auto rl = [&](int lane) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    };
+    return fmax(fmax(rl(0), rl(16)), fmax(rl(32), rl(48)));
+}
+
 __global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict__ D, double rr_tol,
                                                 double* __restrict__ T, int* __restrict__ rank_out) {
     // lane l keeps column l of the working matrix (a[]) and, after the factorisation, column l
     // of Ltilde^{-1} (x[]) in registers; the factor columns go through LDS
-    __shared__ double Lm[64][64];   // Lm[m][l]: entry l of factor column m (original indexing)
+    __shared__ double Lm[64][65];   // Lm[m][l]: entry l of factor column m (odd stride: the
+                                    // column reads Lm[l][order[r]] below are conflict-free)
+    __shared__ __attribute__((aligned(16))) double Lt[64][66];   // Lt[r][q] = Lm[q][order[r]]
+    __shared__ double ipv[64];                                   // 1 / pivot of step m
     __shared__ int order[64];
     __shared__ double scs[64];
     const int l = threadIdx.x;
@@ -570,8 +597,7 @@ __global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict_
 #pragma unroll
     for (int i = 0; i < 64; ++i) a[i] = (l < k && i < k) ? 0.5 * (D[i * k + l] + D[l * k + i]) : 0.0;
     const double dg = l < k ? 0.5 * (D[l * k + l] + D[l * k + l]) : -1.0;
-    double dmax = dg;
-    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    const double dmax = wave_max(dg);
     const bool live = l < k && dmax > 0.0 && dg > 1e-30 * dmax;
     const double sc = live ? 1.0 / sqrt(dg) : 0.0;
     scs[l] = sc;
@@ -582,22 +608,22 @@ __global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict_
     bool rem = live;
     int m = 0;
     for (; m < k; ++m) {
-        double cand = rem ? diag : -1.0e300;
-        int ci = l;
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(cand, o, 64);
-            const int oi = __shfl_xor(ci, o, 64);
-            if (ov > cand || (ov == cand && oi < ci)) { cand = ov; ci = oi; }
-        }
-        if (!(cand > rr_tol)) break;
-        const int p = __builtin_amdgcn_readfirstlane(ci);
-        const double piv = sqrt(cand);
+        // largest remaining pivot, lowest index on ties
+        const double cand = rem ? diag : -1.0e300;
+        const double best = wave_max(cand);
+        if (!(best > rr_tol)) break;
+        const unsigned long long hit = __ballot(cand == best);
+        const int p = __builtin_amdgcn_readfirstlane(__ffsll((long long)hit) - 1);
+        const double piv = sqrt(best);
         const double ipiv = 1.0 / piv;
         // A[l][p] = A[p][l] (symmetric among the remaining indices) = a[p] of lane l
         const double lc = (l == p) ? piv : (rem ? pick64(a, p) * ipiv : 0.0);
         if (l == p) rem = false;
         Lm[m][l] = lc;
-        if (l == 0) order[m] = p;
+        if (l == 0) {
+            order[m] = p;
+            ipv[m] = ipiv;
+        }
         __syncthreads();
         // Schur-complement update of the remaining columns: A[i][l] -= lc_i lc_l
         if (rem) {
@@ -606,25 +632,28 @@ __global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict_
             diag -= lc * lc;
         }
     }
-    __syncthreads();
     const int rank = m;
-    // Ltilde[r][c] = Lm[c][order[r]] (rank x rank lower); lane c: column c of X = Ltilde^{-1}
-    double x[64];
-#pragma unroll
-    for (int r = 0; r < 64; ++r) {
-        x[r] = 0.0;
-        if (r < rank && l < rank) {
-            const int orr = order[r];
+    // Lt[r][q] = Ltilde[r][q] = Lm[q][order[r]] (lane q writes column q)
+    for (int r = 0; r < rank; ++r) Lt[r][l] = l < rank ? Lm[l][order[r]] : 0.0;
+    __syncthreads();
+    // lane c: column c of X = Ltilde^{-1} by forward substitution with two partial sums; X lives
+    // in LDS (column c is lane c's own, so no barrier is needed inside; rolled loops keep the
+    // code small: the kernel runs once per iteration with a cold instruction cache)
+    double* X = &Lm[0][0];   // reuse: X[q*65 + c]
+    if (l < rank) {
+        for (int r = 0; r < rank; ++r) {
+            const double* Lr = Lt[r];
             double v0 = (r == l) ? 1.0 : 0.0, v1 = 0.0;
-#pragma unroll
-            for (int q = 0; q + 1 < r; q += 2) {
-                v0 -= Lm[q][orr] * x[q];
-                v1 -= Lm[q + 1][orr] * x[q + 1];
+            int q = 0;
+            for (; q + 1 < r; q += 2) {
+                v0 -= Lr[q] * X[q * 65 + l];
+                v1 -= Lr[q + 1] * X[(q + 1) * 65 + l];
             }
-            if (r & 1) v0 -= Lm[r - 1][orr] * x[r - 1];
-            x[r] = (v0 + v1) / Lm[r][orr];
+            if (q < r) v0 -= Lr[q] * X[q * 65 + l];
+            X[r * 65 + l] = (v0 + v1) * ipv[r];
         }
     }
+    __syncthreads();
     // T[order[r]][c] = s[order[r]] (Ltilde^{-T})[r][c] = s[order[r]] X[c][r]: lane r writes row
     // order[r]; rows of indices never taken as pivots are zero (written by their own lane)
     if (l < k) {
@@ -633,9 +662,7 @@ __global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict_
         if (l < rank) {
             const int row = order[l];
             const double s = scs[row];
-#pragma unroll
-            for (int j = 0; j < 64; ++j)
-                if (j < k) T[row * k + j] = j < rank ? s * x[j] : 0.0;
+            for (int j = 0; j < k; ++j) T[row * k + j] = j < rank ? s * X[j * 65 + l] : 0.0;
         }
     }
     if (l == 0) *rank_out = rank;
@@ -706,7 +733,7 @@ void launch_gemv_t(int n, int k, const double* A, const double* x, double* part,
     if (k != 64) throw std::invalid_argument("launch_gemv_t takes 64 columns");
     const int nchunk = std::max(1, std::min(256, (n + 1023) / 1024));
     k_gemv_t64<<<nchunk, 256, 0, st>>>(n, A, x, part);
-    k_gram_reduce<<<1, 64, 0, st>>>(nchunk, 1, 64, 1, part, out);
+    k_colsum64<<<1, 256, 0, st>>>(nchunk, part, out);
 }
 
 // W -= sum_b W_b Psi_b, Psi_b = Psi + b*k*k (k x k), W_b = Wptrs[b] (n x k).
@@ -767,12 +794,29 @@ __global__ void __launch_bounds__(256) k_rowsum_dot(int n, int k, const double* 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void k_sum(int n, const double* __restrict__ part, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double v = 0.0;
-        for (int i = 0; i < n; ++i) v += part[i];
-        *out = v;
+// *out = sum of part[0..n) in a fixed order: 256 strided partial sums, then a fixed tree
+__global__ void __launch_bounds__(256) k_sum(int n, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += part[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// out[e] = sum_c part[c*64 + e] for e < 64: four wavefronts take c = w mod 4, fixed-order combine
+__global__ void __launch_bounds__(256) k_colsum64(int nchunk, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double red[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double v = 0.0;
+    for (int c = wave; c < nchunk; c += 4) v += part[(long long)c * 64 + lane];
+    red[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0) out[lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st) {
@@ -781,7 +825,7 @@ void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* p
         k_rowsum_dot64<<<nb, 256, 0, st>>>(n, r, Z, part);
     else
         k_rowsum_dot<<<nb, 256, 0, st>>>(n, k, r, Z, part);
-    k_sum<<<1, 64, 0, st>>>(nb, part, out);
+    k_sum<<<1, 256, 0, st>>>(nb, part, out);
 }
 
 __global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
