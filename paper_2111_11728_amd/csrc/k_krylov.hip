@@ -729,6 +729,8 @@ void launch_update_lr(int n, int k, const double* W, const double* Q, const doub
         k_update_lr<<<(n + 255) / 256, 256, 0, st>>>(n, k, W, Q, g, lam, r);
 }
 
+__global__ void k_colsum64(int nchunk, const double* __restrict__ part, double* __restrict__ out);
+
 void launch_gemv_t(int n, int k, const double* A, const double* x, double* part, double* out, hipStream_t st) {
     if (k != 64) throw std::invalid_argument("launch_gemv_t takes 64 columns");
     const int nchunk = std::max(1, std::min(256, (n + 1023) / 1024));
