@@ -5,3 +5,4 @@ The compute path is the HIP library libfeti.so (C ABI in include/feti.h); ``feti
 ctypes binding and ``autograd`` wraps compliance and its gradient for torch.
 """
 from . import feti  # noqa: F401
+from . import autograd  # noqa: F401

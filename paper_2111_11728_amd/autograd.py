@@ -1,0 +1,35 @@
+"""Compliance c(rho) = f^T u(rho) of the SIMP system (Sec. 1, Eq. 1-2) as a torch autograd
+function. The forward pass calls ``feti_compliance_and_grad``: it sets the context up for rho,
+solves with the FETI method of the context, and writes c together with the adjoint gradient
+dc/drho_e = -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e (compliance is self-adjoint). The backward
+pass scales that gradient; it does no extra solve. Argument marshalling only: all arithmetic
+runs in the HIP library.
+"""
+from __future__ import annotations
+
+import torch
+
+from .feti import Context
+
+
+class Compliance(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho: torch.Tensor, fctx: Context, f: torch.Tensor) -> torch.Tensor:
+        if rho.dtype != torch.float64 or f.dtype != torch.float64:
+            raise TypeError("rho and f must be float64")
+        rho_c = rho.detach().contiguous()
+        c = torch.zeros(1, dtype=torch.float64, device=rho.device)
+        g = torch.empty_like(rho_c)
+        fctx.feti_compliance_and_grad(rho_c, f.contiguous(), c, g)
+        ctx.save_for_backward(g)
+        return c[0]
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        (g,) = ctx.saved_tensors
+        return grad_c * g, None, None
+
+
+def compliance(rho: torch.Tensor, fctx: Context, f: torch.Tensor) -> torch.Tensor:
+    """c(rho) with autograd support (gradient w.r.t. rho only)."""
+    return Compliance.apply(rho, fctx, f)
