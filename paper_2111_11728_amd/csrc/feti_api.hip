@@ -635,7 +635,7 @@ void numeric_setup(feti_ctx* c) {
     check_info(c, t.n_sub, "interior Cholesky");
     launch_bt_invert(t, c->L, c->Li, st);
     CHECK_LAUNCH();
-    launch_bt_forward(t, c->L, c->Z, st);
+    launch_bt_forward_li(t, c->L, c->Li, c->Z, st);
     CHECK_LAUNCH();
     if (c->opts.precond == FETI_LUMPED) launch_copy_Sbb(t, c->S, c->P64, 0, st);
     launch_gemm_tn(c->d_syrk, t.n_sub, c->syrk_tiles, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);

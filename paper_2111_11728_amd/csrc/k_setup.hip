@@ -146,15 +146,150 @@ __global__ void __launch_bounds__(256) k_bt_forward(const SubMeta* __restrict__ 
     }
 }
 
+// Z <- L^{-1} Z for one 64-column chunk of Z = K_i,beta (row-major n_i x n_beta), with the
+// explicit inverses L_kk^{-1} (lines of at most 128 DOFs): per line T = Z_k - L_{k,k-1} Z_{k-1},
+// then Z_k = L_kk^{-1} T, both on the FP64 matrix cores. Z_{k-1} and then T stay in one LDS
+// buffer (128 x 68); wavefront w computes rows 32w..32w+31 of the line (two 16-row blocks x
+// four 16-column blocks). The contraction of step Q uses index 16Q + 4g + s for lane group g
+// and sub-step s, so a lane's four operands of A are consecutive.
+constexpr int kFwLd = 68;
+typedef double v4w __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256, 2) k_bt_forward_mfma(const SubMeta* __restrict__ subs,
+                                                            const LineMeta* __restrict__ lines,
+                                                            const double* __restrict__ Lbuf,
+                                                            const double* __restrict__ Li, double* Zbuf) {
+    __shared__ double buf[128 * kFwLd];
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int c0 = blockIdx.x * 64;
+    if (c0 >= M.n_beta || M.n_i == 0) return;
+    const int nc = min(64, M.n_beta - c0);
+    double* Z = Zbuf + M.off_Z + c0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int rw = 32 * wave;   // first row of the wavefront within the line
+    int n_prev = 0;
+    for (int k = 0; k < M.n_lines; ++k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) {
+            n_prev = 0;
+            continue;
+        }
+        const int n = Lk.n, np = Lk.n_prev;
+        double* Zk = Z + (long long)Lk.i0 * M.n_beta;
+        v4w acc[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = v4w{0.0, 0.0, 0.0, 0.0};
+        // acc = L_{k,k-1} Z_{k-1} (Z_{k-1} in buf, rows < np)
+        if (np > 0 && n_prev == np && rw < n) {
+            const double* C = Lbuf + Lk.off_sub;
+            for (int Q = 0; Q < (np + 15) / 16; ++Q) {
+                const int q0 = 16 * Q + 4 * g;
+                double a0[4], a1[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int q = q0 + e;
+                    const int r0 = rw + m, r1 = rw + 16 + m;
+                    a0[e] = (q < np && r0 < n) ? C[(long long)r0 * np + q] : 0.0;
+                    a1[e] = (q < np && r1 < n) ? C[(long long)r1 * np + q] : 0.0;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int q = q0 + e;
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const double bv = q < np ? buf[q * kFwLd + 16 * cb + m] : 0.0;
+                        acc[0][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[e], bv, acc[0][cb], 0, 0, 0);
+                        acc[1][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[e], bv, acc[1][cb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // T = Z_k - acc (D layout: rows g + 4v, column m of each block)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = rw + 16 * a + g + 4 * v, c = 16 * cb + m;
+                    const double zk = (r < n && c < nc) ? Zk[(long long)r * M.n_beta + c] : 0.0;
+                    acc[a][cb][v] = zk - acc[a][cb][v];
+                }
+        __syncthreads();   // every wavefront is done with Z_{k-1}
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) buf[(rw + 16 * a + g + 4 * v) * kFwLd + 16 * cb + m] = acc[a][cb][v];
+        __syncthreads();
+        // Z_k = L_kk^{-1} T (lower triangular: contraction index q <= row)
+        v4w z[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) z[a][b] = v4w{0.0, 0.0, 0.0, 0.0};
+        if (rw < n) {
+            const double* I = Li + Lk.off_inv;
+            const int qmax = min(n, rw + 32);
+            for (int Q = 0; Q < (qmax + 15) / 16; ++Q) {
+                const int q0 = 16 * Q + 4 * g;
+                double a0[4], a1[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int q = q0 + e;
+                    const int r0 = rw + m, r1 = rw + 16 + m;
+                    a0[e] = (q < n && r0 < n) ? I[(long long)r0 * n + q] : 0.0;
+                    a1[e] = (q < n && r1 < n) ? I[(long long)r1 * n + q] : 0.0;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int q = q0 + e;
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const double bv = q < n ? buf[q * kFwLd + 16 * cb + m] : 0.0;
+                        z[0][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[e], bv, z[0][cb], 0, 0, 0);
+                        z[1][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[e], bv, z[1][cb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // every wavefront is done with T
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = rw + 16 * a + g + 4 * v, c = 16 * cb + m;
+                    buf[r * kFwLd + c] = z[a][cb][v];
+                    if (r < n && c < nc) Zk[(long long)r * M.n_beta + c] = z[a][cb][v];
+                }
+        __syncthreads();
+        n_prev = n;
+    }
+}
+
 // ---------------------------------------------------------------------------------------
-// Batched C = beta C + alpha A^T B (A: k x m, B: k x n, row-major), 64x64 tiles per
-// workgroup. symmetric: only tiles on or below the diagonal are computed and each is
-// written to both (i, j) and (j, i) (requires A == B).
-__global__ void __launch_bounds__(256) k_gemm_tn(const GemmDesc* __restrict__ desc, const double* Abase,
-                                                 const double* Bbase, double* Cbase, double alpha,
-                                                 double beta, int symmetric) {
-    __shared__ double As[16 * 64];
-    __shared__ double Bs[16 * 64];
+// Batched C = beta C + alpha A^T B (A: k x m, B: k x n, row-major with leading dimensions
+// lda/ldb) on the FP64 matrix cores. Workgroup = one 64x64 tile of C; its four wavefronts
+// split the contraction and each accumulates the full tile (sixteen 16x16 accumulators, one
+// wavefront per SIMD, loads kGtRing steps ahead); the partial tiles meet in LDS and are summed
+// in wavefront order. Rows and columns of the tile are permuted so that at step st lane
+// (m, g) reads A[4 st + g][i0 + 4m .. +3] and B[4 st + g][j0 + 4m .. +3]: accumulator row m'
+// of block ib is tile row 4 m' + ib, column n' of block jb is tile column 4 n' + jb.
+// symmetric (A == B): only tiles on or below the diagonal are computed; off-diagonal tiles
+// are written to both (i, j) and (j, i).
+typedef double v4g __attribute__((ext_vector_type(4)));
+constexpr int kGtRing = 6;
+
+__global__ void __launch_bounds__(256, 1) k_gemm_tn(const GemmDesc* __restrict__ desc, const double* Abase,
+                                                    const double* Bbase, double* Cbase, double alpha, double beta,
+                                                    int symmetric) {
+    __shared__ double red[4 * 4096];
     const GemmDesc d = desc[blockIdx.y];
     const int tn = (d.n + 63) / 64;
     const int ti = blockIdx.x / tn, tj = blockIdx.x % tn;
@@ -164,48 +299,61 @@ __global__ void __launch_bounds__(256) k_gemm_tn(const GemmDesc* __restrict__ de
     const double* B = Bbase + d.b;
     double* C = Cbase + d.c;
     const int i0 = ti * 64, j0 = tj * 64;
-    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-    double acc[4][4];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int nsteps = (d.k + 3) >> 2;
+    const int w0 = nsteps * wave / 4, w1 = nsteps * (wave + 1) / 4;
+    const int ia = i0 + 4 * m, jb0 = j0 + 4 * m;
+    v4g acc[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-    for (int k0 = 0; k0 < d.k; k0 += 16) {
-        for (int e = tid; e < 16 * 64; e += 256) {
-            const int kk = e >> 6, ii = e & 63;
-            const bool kin = k0 + kk < d.k;
-            As[e] = (kin && i0 + ii < d.m) ? A[(long long)(k0 + kk) * d.lda + i0 + ii] : 0.0;
-            Bs[e] = (kin && j0 + ii < d.n) ? B[(long long)(k0 + kk) * d.ldb + j0 + ii] : 0.0;
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4g{0.0, 0.0, 0.0, 0.0};
+    v4g ar[kGtRing], br[kGtRing];
+    auto ld = [&](int st, v4g& av, v4g& bv) {
+        const int r = 4 * st + g;
+        const bool rv = st < w1 && r < d.k;
+        const double* Ar = A + (long long)r * d.lda;
+        const double* Br = B + (long long)r * d.ldb;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            av[e] = (rv && ia + e < d.m) ? Ar[ia + e] : 0.0;
+            bv[e] = (rv && jb0 + e < d.n) ? Br[jb0 + e] : 0.0;
         }
-        __syncthreads();
+    };
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], b[4];
+    for (int dd = 0; dd < kGtRing; ++dd) ld(w0 + dd, ar[dd], br[dd]);
+    for (int st = w0; st < w1; st += kGtRing) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk * 64 + tr * 4 + r];
+        for (int dd = 0; dd < kGtRing; ++dd) {
+            if (st + dd < w1) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = Bs[kk * 64 + tc * 4 + c];
+                for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = i0 + tr * 4 + r, j = j0 + tc * 4 + c;
-            if (i >= d.m || j >= d.n) continue;
-            if (symmetric && j > i) continue;
-            double* dst = C + (long long)i * d.ldc + j;
-            *dst = beta == 0.0 ? alpha * acc[r][c] : beta * *dst + alpha * acc[r][c];
-            if (symmetric && i != j) {
-                double* dt = C + (long long)j * d.ldc + i;
-                *dt = beta == 0.0 ? alpha * acc[r][c] : beta * *dt + alpha * acc[r][c];
+                    for (int jb = 0; jb < 4; ++jb)
+                        acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[dd][ib], br[dd][jb], acc[ib][jb], 0, 0, 0);
+                ld(st + dd + kGtRing, ar[dd], br[dd]);
             }
         }
+    }
+    // D layout: lane holds rows g + 4v, column m of block (ib, jb) -> tile (4(g+4v)+ib, 4m+jb)
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[wave * 4096 + (4 * (g + 4 * v) + ib) * 64 + 4 * m + jb] = acc[ib][jb][v];
+    __syncthreads();
+    for (int e = tid; e < 4096; e += 256) {
+        const int i = i0 + (e >> 6), j = j0 + (e & 63);
+        if (i >= d.m || j >= d.n) continue;
+        const double val = ((red[e] + red[4096 + e]) + red[8192 + e]) + red[12288 + e];
+        double* dst = C + (long long)i * d.ldc + j;
+        *dst = beta == 0.0 ? alpha * val : beta * *dst + alpha * val;
+        if (symmetric && ti != tj) {
+            double* dt = C + (long long)j * d.ldc + i;
+            *dt = beta == 0.0 ? alpha * val : beta * *dt + alpha * val;
+        }
+    }
 }
 
 // Batched in-place Cholesky (one workgroup per matrix).
@@ -615,6 +763,14 @@ void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st) {
 void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st) {
     dim3 grid((t.max_beta + 63) / 64, t.n_sub);
     k_bt_forward<<<grid, 256, 0, st>>>(t.subs, t.lines, L, Z);
+}
+
+void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, double* Z, hipStream_t st) {
+    if (t.max_line > 128) {
+        launch_bt_forward(t, L, Z, st);
+        return;
+    }
+    if (t.n_sub && t.max_beta) k_bt_forward_mfma<<<dim3((t.max_beta + 63) / 64, t.n_sub), 256, 0, st>>>(t.subs, t.lines, L, Li, Z);
 }
 
 void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* A, const double* B, double* C,
