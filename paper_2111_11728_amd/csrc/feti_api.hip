@@ -630,7 +630,7 @@ void numeric_setup(feti_ctx* c) {
     zero(c->info, (t.n_sub + 8) * 4);
     launch_assemble(t, c->rho, c->p, c->E0, c->Emin, c->L, c->Z, c->S, c->diag, st);
     CHECK_LAUNCH();
-    launch_bt_factor(t, c->L, c->info, st);
+    launch_bt_factor_li(t, c->L, c->Li, c->info, st);
     CHECK_LAUNCH();
     check_info(c, t.n_sub, "interior Cholesky");
     launch_bt_invert(t, c->L, c->Li, st);

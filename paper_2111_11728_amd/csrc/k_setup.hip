@@ -146,6 +146,171 @@ __global__ void __launch_bounds__(256) k_bt_forward(const SubMeta* __restrict__ 
     }
 }
 
+// Block-tridiagonal Cholesky of K_ii for lines of at most 128 DOFs, one workgroup per
+// subdomain, the line's diagonal block resident in LDS (stride 129):
+//   D_k -= C_k C_k^T           (FP64 matrix cores, lower 16x16 blocks; C_k = L_{k,k-1})
+//   D_k  = L_kk L_kk^T          (left-looking, two threads per row)
+//   L_kk^{-1}                   (in place, right to left over the columns)
+//   C_{k+1} = A_{k+1,k} L_kk^{-T}  (matrix cores, B operand from LDS, written over A_{k+1,k})
+// L_kk goes to its slot of L and L_kk^{-1} to the inverse buffer.
+constexpr int kBfLd = 129;
+typedef double v4w __attribute__((ext_vector_type(4)));
+
+__device__ inline void bf_syrk_update(double* A, const double* __restrict__ C, int n, int np) {
+    // lower 16x16 blocks (bi >= bj) of the n x n block, dealt round-robin to the wavefronts
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
+    const int nb = (n + 15) >> 4;
+    int idx = 0;
+    for (int bi = 0; bi < nb; ++bi)
+        for (int bj = 0; bj <= bi; ++bj, ++idx) {
+            if ((idx & 3) != wave) continue;
+            v4w acc = v4w{0.0, 0.0, 0.0, 0.0};
+            const int ra = 16 * bi + m, rb = 16 * bj + m;
+            for (int Q = 0; Q < (np + 15) / 16; ++Q) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int q = 16 * Q + 4 * g + e;
+                    const double a = (q < np && ra < n) ? C[(long long)ra * np + q] : 0.0;
+                    const double b = (q < np && rb < n) ? C[(long long)rb * np + q] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+            }
+            // D layout: rows g + 4v, column m
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * bi + g + 4 * v, j = 16 * bj + m;
+                if (i < n && j < n && j <= i) A[i * kBfLd + j] -= acc[v];
+            }
+        }
+}
+
+// left-looking Cholesky of the lower triangle of A (n <= 128); returns 0 or the failing
+// column + 1 (uniform)
+__device__ inline int bf_potrf(double* A, int n, double* colv) {
+    const int tid = threadIdx.x, row = tid >> 1, half = tid & 1;
+    for (int j = 0; j < n; ++j) {
+        // A[i][j] -= sum_{q<j} A[i][q] A[j][q] for i >= j (two threads per row, halves of q)
+        double part = 0.0;
+        if (row < n && row >= j) {
+            const double* Ai = A + row * kBfLd;
+            const double* Aj = A + j * kBfLd;
+            const int qh = (j + 1) >> 1, q0 = half ? qh : 0, q1 = half ? j : qh;
+            for (int q = q0; q < q1; ++q) part += Ai[q] * Aj[q];
+        }
+        part += __shfl_xor(part, 1, 64);
+        if (row < n && row >= j && half == 0) colv[row] = A[row * kBfLd + j] - part;
+        __syncthreads();
+        const double d = colv[j];
+        if (!(d > 0.0)) return j + 1;
+        const double piv = sqrt(d), inv = 1.0 / piv;
+        if (row < n && row >= j && half == 0) A[row * kBfLd + j] = row == j ? piv : colv[row] * inv;
+        __syncthreads();
+    }
+    return 0;
+}
+
+// in-place inverse of the lower-triangular L in A: columns right to left, column j from the
+// trailing inverse already in place and L's own column j (kept until all rows are done)
+__device__ inline void bf_trtri(double* A, int n, double* colv) {
+    const int tid = threadIdx.x, row = tid >> 1, half = tid & 1;
+    for (int j = n - 1; j >= 0; --j) {
+        const double djj = 1.0 / A[j * kBfLd + j];
+        double part = 0.0;
+        if (row < n && row > j) {
+            // X[row][j] = -(sum_{q=j+1}^{row} X[row][q] L[q][j]) / L[j][j]
+            const double* Xi = A + row * kBfLd;
+            const int len = row - j, qh = j + 1 + (len >> 1);
+            const int q0 = half ? qh : j + 1, q1 = half ? row + 1 : qh;
+            for (int q = q0; q < q1; ++q) part += Xi[q] * A[q * kBfLd + j];
+        }
+        part += __shfl_xor(part, 1, 64);
+        __syncthreads();   // every row has read column j of L
+        if (row < n && half == 0) {
+            if (row > j) A[row * kBfLd + j] = -part * djj;
+            else if (row == j) A[row * kBfLd + j] = djj;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bt_factor128(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
+                                                      double* Lbuf, double* Li, int* info) {
+    __shared__ double A[128 * kBfLd];
+    __shared__ double colv[128];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    for (int k = 0; k < M.n_lines; ++k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        const int n = Lk.n;
+        if (n == 0) continue;
+        double* D = Lbuf + Lk.off_diag;
+        for (int e = tid; e < n * n; e += 256) {
+            const int i = e / n, j = e - i * n;
+            A[i * kBfLd + j] = D[e];
+        }
+        __syncthreads();
+        if (Lk.n_prev > 0) {
+            bf_syrk_update(A, Lbuf + Lk.off_sub, n, Lk.n_prev);
+            __syncthreads();
+        }
+        const int r = bf_potrf(A, n, colv);
+        if (r) {
+            if (tid == 0) info[s] = Lk.i0 + r;
+            return;
+        }
+        for (int e = tid; e < n * n; e += 256) {
+            const int i = e / n, j = e - i * n;
+            D[e] = j <= i ? A[i * kBfLd + j] : 0.0;
+        }
+        __syncthreads();
+        bf_trtri(A, n, colv);
+        double* X = Li + Lk.off_inv;
+        for (int e = tid; e < n * n; e += 256) {
+            const int i = e / n, j = e - i * n;
+            X[e] = j <= i ? A[i * kBfLd + j] : 0.0;
+        }
+        if (k + 1 < M.n_lines) {
+            const LineMeta Ln = lines[M.line0 + k + 1];
+            if (Ln.n > 0) {
+                // C = A_{k+1,k} L_kk^{-T}: C[r][c] = sum_{q <= c} A[r][q] X[c][q]; wavefront = 16 rows
+                // x all columns, every row block read completely before it is overwritten
+                double* Ab = Lbuf + Ln.off_sub;   // n_next x n
+                const int nn = Ln.n, ncb = (n + 15) >> 4;
+                for (int rbk = wave; rbk < (nn + 15) / 16; rbk += 4) {
+                    v4w acc[8];
+#pragma unroll
+                    for (int cb = 0; cb < 8; ++cb) acc[cb] = v4w{0.0, 0.0, 0.0, 0.0};
+                    const int ra = 16 * rbk + m;
+                    for (int Q = 0; Q < (n + 15) / 16; ++Q) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int q = 16 * Q + 4 * g + e;
+                            const double a = (q < n && ra < nn) ? Ab[(long long)ra * n + q] : 0.0;
+#pragma unroll
+                            for (int cb = 0; cb < 8; ++cb) {
+                                if (cb < ncb) {
+                                    const int cc = 16 * cb + m;
+                                    const double b = (q < n && cc < n && q <= cc) ? A[cc * kBfLd + q] : 0.0;
+                                    acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int cb = 0; cb < 8; ++cb)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int rr = 16 * rbk + g + 4 * v, cc = 16 * cb + m;
+                            if (cb < ncb && rr < nn && cc < n) Ab[(long long)rr * n + cc] = acc[cb][v];
+                        }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Z <- L^{-1} Z for one 64-column chunk of Z = K_i,beta (row-major n_i x n_beta), with the
 // explicit inverses L_kk^{-1} (lines of at most 128 DOFs): per line T = Z_k - L_{k,k-1} Z_{k-1},
 // then Z_k = L_kk^{-1} T, both on the FP64 matrix cores. Z_{k-1} and then T stay in one LDS
@@ -153,7 +318,6 @@ __global__ void __launch_bounds__(256) k_bt_forward(const SubMeta* __restrict__ 
 // four 16-column blocks). The contraction of step Q uses index 16Q + 4g + s for lane group g
 // and sub-step s, so a lane's four operands of A are consecutive.
 constexpr int kFwLd = 68;
-typedef double v4w __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256, 2) k_bt_forward_mfma(const SubMeta* __restrict__ subs,
                                                             const LineMeta* __restrict__ lines,
@@ -763,6 +927,16 @@ void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st) {
 void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st) {
     dim3 grid((t.max_beta + 63) / 64, t.n_sub);
     k_bt_forward<<<grid, 256, 0, st>>>(t.subs, t.lines, L, Z);
+}
+
+// FP64 MFMA factorisation with the inverses for lines <= 128 DOFs, else the generic path
+// followed by the separate inverse kernel
+void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, hipStream_t st) {
+    if (t.max_line <= 128) {
+        if (t.n_sub) k_bt_factor128<<<t.n_sub, 256, 0, st>>>(t.subs, t.lines, L, Li, info);
+        return;
+    }
+    launch_bt_factor(t, L, info, st);
 }
 
 void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, double* Z, hipStream_t st) {

@@ -224,8 +224,10 @@ __global__ void __launch_bounds__(256) k_bt_invert(const LineMeta* __restrict__ 
     wg_trsm_lower(Lk.n, Lk.n, Lbuf + Lk.off_diag, Lk.n, X, Lk.n, 1, lds);
 }
 
+// (lines <= 128 DOFs get their inverses from the factorisation itself)
 void launch_bt_invert(const DevTopo& t, const double* L, double* Li, hipStream_t st) {
-    if (t.max_line <= kSweepMaxLine && t.n_lines_tot > 0) k_bt_invert<<<t.n_lines_tot, 256, 0, st>>>(t.lines, L, Li);
+    if (t.max_line > 128 && t.max_line <= kSweepMaxLine && t.n_lines_tot > 0)
+        k_bt_invert<<<t.n_lines_tot, 256, 0, st>>>(t.lines, L, Li);
 }
 
 void launch_bt_fsolve1(const DevTopo& t, const double* L, const double* Li, double* h, hipStream_t st) {

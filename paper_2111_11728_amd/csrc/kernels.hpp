@@ -88,6 +88,9 @@ void upload_K0(const double* K0, int n, hipStream_t st);
 void launch_assemble(const DevTopo& t, const double* rho, double p, double E0, double Emin, double* L, double* Z,
                      double* S, double* diag, hipStream_t st);
 void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st);
+// Block-tridiagonal Cholesky that also writes L_kk^{-1} (lines <= 128 DOFs; otherwise the
+// generic factorisation, and launch_bt_invert must follow)
+void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, hipStream_t st);
 // Z <- L^{-1} Z with the explicit diagonal inverses (matrix cores; lines <= 128 DOFs)
 void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, double* Z, hipStream_t st);
 void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st);
