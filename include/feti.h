@@ -87,11 +87,17 @@ typedef struct {
                                  directions (1 or 2; 0 = 1, the single pass of Algorithm 1) */
     int max_refine;           /* mixed precision: FP64 residual restarts with the reduced-precision
                                  operator after the first pass (< 0: 4); further passes use FP64 */
-    double relax;             /* mixed precision: an iteration applies the FP64 operator while
-                                 sqrt(r^T z) > relax * sqrt(r_0^T z_0) and the reduced-precision one
-                                 below it, so the large early steps carry no reduced-precision
-                                 error into lambda (<= 0: min(1, 0.1 tol / delta) with delta = 1e-4
-                                 for FETI_FP32 and 1e-3 for FETI_BF16X3) */
+    double relax;             /* mixed precision, switch level. > 0: an iteration applies the FP64
+                                 operator while eps = sqrt(r^T z) > relax * eps0 and the reduced-
+                                 precision one below it. <= 0 (default): measured switch. A reduced
+                                 iteration moves the true residual away from the recursive one by
+                                 about eta * eps, eta = ||(F_red - F) Z|| / ||F Z|| on the
+                                 iteration's own block Z, so the reduced operator is used only while
+                                 eta * eps <= 0.1 tol eps0. The first iteration that passes this test
+                                 (with the prior eta = 1e-4 for FETI_FP32, 1e-3 for FETI_BF16X3),
+                                 and every 16th reduced iteration after it, applies F in both
+                                 precisions, keeps the FP64 product and records eta (the largest
+                                 measurement is kept). */
 } feti_opts;
 
 typedef struct {
@@ -109,6 +115,8 @@ typedef struct {
     int fp64_fallback;        /* 1 if a reduced-precision pass broke down or stagnated and the
                                  solve was finished with the FP64 operator */
     int reduced_iters;        /* iterations that applied the reduced-precision operator */
+    int precision_probes;     /* iterations that applied F in both precisions to measure eta */
+    double reduced_rel_err;   /* largest eta measured (0 if never measured) */
 } feti_info;
 
 typedef struct {

@@ -846,14 +846,78 @@ void current_iterate(feti_ctx* c, double* out) {
     CHECK_LAUNCH();
 }
 
-// Mixed precision: iterations apply the FP64 operator while eps > sw * eps0 and the reduced-
-// precision one after that (relaxation of the operator accuracy as the residual decreases).
-KrylovOut run_pcg(feti_ctx* c, int prec, double sw, double eps0, double tol, int max_it, std::vector<double>& hist) {
+// Which operator an iteration applies (inexact Krylov: the operator accuracy may be relaxed as
+// the residual decreases). A reduced-precision product Q = F_red Z moves the true residual away
+// from the recursive one by about eta * |Delta r| <= eta * eps, with eta = |(F_red - F) Z| / |F Z|
+// on the iteration's own block: the relative error on the search directions, which grows as they
+// concentrate in the low modes of F and can far exceed the error on a generic block. With a
+// fixed level (relax > 0) the reduced operator is used once eps <= relax * eps0; otherwise while
+// eta * eps <= 0.1 tol eps0, with eta measured by probes (F applied in both precisions, the FP64
+// product kept) at the first iteration that passes the test under the prior and every
+// kProbeEvery-th reduced iteration after it; the largest measurement is kept.
+struct PrecGate {
+    static constexpr int kProbeEvery = 16;
+    enum { kFp64, kReduced, kProbe };
+    int prec = FETI_FP64;
+    double sw = 0.0;    // fixed switch level, 0 = measured
+    double eta = 0.0;   // prior until the first probe, then the largest measurement
+    double tol = 0.0;
+    bool measured = false;
+    int since = 0;      // reduced iterations since the last probe
+    int probes = 0;
+    PrecGate(int prec_, double relax, double tol_) : prec(prec_), tol(tol_) {
+        if (relax > 0.0)
+            sw = relax;
+        else
+            eta = prec == FETI_BF16X3 ? 1e-3 : 1e-4;
+    }
+    int choose(bool replaced, double eps, double eps0) {
+        if (prec == FETI_FP64 || replaced) return kFp64;
+        if (sw > 0.0) return eps <= sw * eps0 ? kReduced : kFp64;
+        if (!(eta * eps <= 0.1 * tol * eps0)) return kFp64;
+        if (!measured || since >= kProbeEvery) return kProbe;
+        ++since;
+        return kReduced;
+    }
+    void record(double e) {
+        eta = measured ? std::max(eta, e) : e;
+        measured = true;
+        since = 0;
+        ++probes;
+    }
+};
+
+// Q = F Z (k columns) with the operator the gate picks; returns the precision whose product Q holds.
+// A probe leaves the FP64 product in Q and records |F_red Z - F Z|_F / |F Z|_F (scratch: n x k).
+int gated_apply(feti_ctx* c, PrecGate& g, bool replaced, double eps, double eps0, int k, const double* Z,
+                double* Q, double* scratch) {
+    const int ch = g.choose(replaced, eps, eps0);
+    if (ch == PrecGate::kFp64) {
+        apply_F(c, k, FETI_FP64, Z, Q);
+        return FETI_FP64;
+    }
+    if (ch == PrecGate::kReduced) {
+        apply_F(c, k, g.prec, Z, Q);
+        return g.prec;
+    }
+    apply_F(c, k, FETI_FP64, Z, Q);
+    apply_F(c, k, g.prec, Z, scratch);
+    launch_diff_norms((long long)c->P.n_lambda * k, scratch, Q, c->part, c->scal + 4, c->st);
+    CHECK_LAUNCH();
+    double v[2] = {0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(v, c->scal + 4, sizeof(v), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const double e = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : 0.0;
+    g.record(e);
+    if (verbose()) fprintf(stderr, "[feti] precision probe: eta %.3e, eps/eps0 %.3e\n", e, eps / eps0);
+    return FETI_FP64;
+}
+
+KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it, std::vector<double>& hist) {
     KrylovOut o;
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
-    const int pf32 = prec != FETI_FP64;
-    precondition(c, c->r, c->zv, 1, pf32);
+    precondition(c, c->r, c->zv, 1, 0);
     HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     project(c, 1, c->Zk);  // w = P z
     ddot(c, n, c->r, c->zv, 0);
@@ -862,9 +926,8 @@ KrylovOut run_pcg(feti_ctx* c, int prec, double sw, double eps0, double tol, int
     if (o.eps <= tol * eps0) return o;
     bool replaced = false;
     for (int it = 0; it < max_it; ++it) {
-        const int p_it = (prec != FETI_FP64 && !replaced && o.eps <= sw * eps0) ? prec : FETI_FP64;
+        const int p_it = gated_apply(c, g, replaced, o.eps, eps0, 1, c->Zk, c->Qk, c->Qtmp);
         o.reduced += p_it != FETI_FP64;
-        apply_F(c, 1, p_it, c->Zk, c->Qk);
         ddot(c, n, c->Zk, c->Qk, 1);
         const double wq = read_scalar(c, c->scal + 1);
         if (!(wq > 0.0)) {
@@ -875,7 +938,7 @@ KrylovOut run_pcg(feti_ctx* c, int prec, double sw, double eps0, double tol, int
         launch_axpby(n, a, c->Zk, 1.0, c->lt, st);
         project(c, 1, c->Qk);
         launch_axpby(n, -a, c->Qk, 1.0, c->r, st);
-        precondition(c, c->r, c->zv, 1, pf32);
+        precondition(c, c->r, c->zv, 1, 0);
         ddot(c, n, c->r, c->zv, 0);
         const double rz_new = read_scalar(c, c->scal);
         o.iters = it + 1;
@@ -910,16 +973,15 @@ KrylovOut run_pcg(feti_ctx* c, int prec, double sw, double eps0, double tol, int
 }
 
 // One pass of Algorithm 1 (simultaneous directions; kd = 1 is full orthogonalisation).
-KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, double tol, int max_it,
+KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, int max_it,
                     std::vector<double>& hist, std::vector<int>& ranks) {
     KrylovOut o;
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
-    const int pf32 = prec != FETI_FP64;
     const int one = kd == 1;
     const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
     const int passes = c->opts.reorth == 2 ? 2 : 1;
-    precondition(c, c->r, c->Zk, one, pf32);
+    precondition(c, c->r, c->Zk, one, 0);
     launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
     o.eps = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
     if (o.eps <= tol * eps0) return o;
@@ -932,9 +994,8 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, doubl
         ensure_history(c, kd, nb + 1);
         double* Wn = (double*)c->WH[nb];
         double* Qn = (double*)c->QH[nb];
-        const int p_it = (prec != FETI_FP64 && !replaced && o.eps <= sw * eps0) ? prec : FETI_FP64;
+        const int p_it = gated_apply(c, g, replaced, o.eps, eps0, kd, c->Zk, c->Qk, c->Qtmp);
         o.reduced += p_it != FETI_FP64;
-        apply_F(c, kd, p_it, c->Zk, c->Qk);
         // Delta = Q^T W
         launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
         launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st);
@@ -956,7 +1017,7 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, doubl
         }
         CHECK_LAUNCH();
         ++nb;
-        precondition(c, c->r, c->Zk, one, pf32);
+        precondition(c, c->r, c->Zk, one, 0);
         launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
         project(c, kd, c->Zk);
         for (int pass = 0; pass < passes; ++pass) {
@@ -981,8 +1042,20 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, doubl
         o.kept += rank;
         o.eps = std::sqrt(std::max(ez, 0.0));
         hist.push_back(o.eps);
-        if (o.eps <= tol * eps0) {
-            if (o.reduced == 0 || replaced) break;
+        const bool conv = o.eps <= tol * eps0;
+        if (o.eps < 0.9 * best) {
+            best = o.eps;
+            it_best = it;
+        }
+        // A recurrence on reduced-precision products that diverges or stalls for 10 iterations
+        // ends the pass; the caller restarts in FP64 without the stored directions, whose
+        // products are then too inexact to orthogonalise against.
+        if (!conv && p_it != FETI_FP64 && (o.eps > 1e3 * best || it - it_best > 10)) {
+            o.status = FETI_ENOCONV;
+            break;
+        }
+        if (conv && (o.reduced == 0 || replaced)) break;
+        if (conv) {
             // The recurrence converged on reduced-precision products: replace the recursive
             // residual by the FP64 one of the current iterate and, if that misses the
             // tolerance, go on in FP64 from it with the stored directions kept.
@@ -1002,16 +1075,6 @@ KrylovOut run_sfeti(feti_ctx* c, int prec, double sw, int kd, double eps0, doubl
             CHECK_LAUNCH();
             best = o.eps;
             it_best = it;
-            continue;
-        }
-        if (o.eps < 0.9 * best) {
-            best = o.eps;
-            it_best = it;
-        }
-        // a reduced-precision pass that diverges or stalls ends here; the caller restarts in FP64
-        if (p_it != FETI_FP64 && (o.eps > 1e3 * best || it - it_best > 30)) {
-            o.status = FETI_ENOCONV;
-            break;
         }
     }
     return o;
@@ -1065,7 +1128,8 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
     std::vector<double> hist;
     std::vector<int> ranks;
     KrylovOut tot;
-    int refinements = 0, fallback = 0;
+    int refinements = 0, fallback = 0, probes = 0;
+    double eta_max = 0.0;
     double eps0 = 0.0, true_rel = 0.0;
     int status = FETI_OK;
     if (n > 0) {
@@ -1086,17 +1150,17 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         // residual does not contract by 10x, hands over to the FP64 operator.
         int cur = prec;
         double prev_rel = 1.0;
-        double sw = c->opts.relax;
-        if (!(sw > 0.0)) sw = std::min(1.0, 0.1 * tol / (prec == FETI_BF16X3 ? 1e-3 : 1e-4));
+        PrecGate gate(prec, c->opts.relax, tol);
         if (eps0 > 0.0) {
             for (int pass = 0;; ++pass) {
                 HIPCHK(hipMemsetAsync(c->lt, 0, sizeof(double) * n, st));
                 KrylovOut o;
                 const int left = max_it - tot.iters;
+                gate.prec = cur;
                 if (c->opts.krylov == FETI_PCG)
-                    o = run_pcg(c, cur, sw, eps0, tol, left, hist);
+                    o = run_pcg(c, gate, eps0, tol, left, hist);
                 else
-                    o = run_sfeti(c, cur, sw, kd, eps0, tol, left, hist, ranks);
+                    o = run_sfeti(c, gate, kd, eps0, tol, left, hist, ranks);
                 tot.iters += o.iters;
                 tot.reduced += o.reduced;
                 tot.kept += o.kept;
@@ -1136,6 +1200,8 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
                 ++refinements;
             }
         }
+        probes = gate.probes;
+        eta_max = gate.measured ? gate.eta : 0.0;
     }
     recover(c, u);
     HIPCHK(hipEventRecord(c->ev[1], st));
@@ -1153,6 +1219,8 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         info->kept_directions = tot.kept;
         info->fp64_fallback = fallback;
         info->reduced_iters = tot.reduced;
+        info->precision_probes = probes;
+        info->reduced_rel_err = eta_max;
         if (info->res_hist && info->res_hist_cap > 0)
             for (int i = 0; i < (int)hist.size() && i < info->res_hist_cap; ++i) info->res_hist[i] = hist[i];
         if (info->rank_hist && info->res_hist_cap > 0)

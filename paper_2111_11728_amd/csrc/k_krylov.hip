@@ -282,48 +282,54 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
 constexpr int kGrRing = 6;    // 4-row steps in flight per lane
 constexpr int kGrGroups = 256; // workgroups per round: one per CU
 
-// Gram products Psi_b = A_b^T B for 64 directions over all blocks b < nblk at once. The
-// nblk * nsteps 4-row steps (block-major) are split evenly over the G workgroups (G a
-// multiple of 256, so no range spans more than two blocks); within a workgroup the four
-// wavefronts split each block segment and every wavefront accumulates a full 64 x 64
-// result (sixteen 16x16 FP64 accumulators, one wavefront per SIMD, loads kGrRing steps
-// ahead). Rows/columns are permuted so that at step st lane (m, g) loads A[4 st + g][4m..4m+3]
-// and B[4 st + g][4m..4m+3]: accumulator row m' of block ib is A column 4 m' + ib, column n'
-// of block jb is B column 4 n' + jb. The wavefront results meet in LDS (fixed order) and each
-// segment writes part[(w*2 + slot)*4096 + i*64 + j], slot 0 for the block of the range start.
+// Gram products Psi_b = A_b^T B for 64 directions over all blocks b < nblk at once. Blocks
+// are taken in pairs (b = 2p, 2p+1) that share every load of B: the npair * nsteps 4-row steps
+// (pair-major) are split evenly over the G workgroups (G a multiple of 256, so no range spans
+// more than two pairs); within a workgroup the four wavefronts split each pair segment and
+// every wavefront accumulates two full 64 x 64 results (32 FP64 16x16 accumulators, one
+// wavefront per SIMD, loads kGrRing steps ahead). Rows/columns are permuted so that at step
+// st lane (m, g) loads A_b[4 st + g][4m..4m+3] and B[4 st + g][4m..4m+3]: accumulator row m'
+// of block ib is A column 4 m' + ib, column n' of block jb is B column 4 n' + jb. The
+// wavefront results meet in LDS (fixed order); segment slot t of workgroup w writes, for its
+// pair p, part[((w*2 + t)*2 + h)*4096 + i*64 + j] for block 2p + h.
 __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double* const* __restrict__ Aptrs,
                                                    const double* __restrict__ B, double* __restrict__ part) {
     __shared__ double red[4 * 4096];
     const int G = gridDim.x, w = blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
-    const long long nsteps = (n + 3) >> 2, S = nsteps * nblk;
+    const int npair = (nblk + 1) >> 1;
+    const long long nsteps = (n + 3) >> 2, S = nsteps * npair;
     const long long s_lo = (long long)w * S / G, s_hi = (long long)(w + 1) * S / G;
     for (int slot = 0; slot < 2; ++slot) {
-        const long long b_ll = s_lo / nsteps + slot;
-        if (b_ll >= nblk || b_ll * nsteps >= s_hi) break;
-        const int b = (int)b_ll;
-        const long long a0 = std::max(s_lo, b_ll * nsteps) - b_ll * nsteps;
-        const long long a1 = std::min(s_hi, (b_ll + 1) * nsteps) - b_ll * nsteps;
+        const long long p_ll = s_lo / nsteps + slot;
+        if (p_ll >= npair || p_ll * nsteps >= s_hi) break;
+        const int pr = (int)p_ll;
+        const long long a0 = std::max(s_lo, p_ll * nsteps) - p_ll * nsteps;
+        const long long a1 = std::min(s_hi, (p_ll + 1) * nsteps) - p_ll * nsteps;
         const int w0 = (int)(a0 + (a1 - a0) * wave / 4), w1 = (int)(a0 + (a1 - a0) * (wave + 1) / 4);
-        const double* A = Aptrs[b];
-        v4d_t acc[4][4];
+        const double* A0 = Aptrs[2 * pr];
+        const bool has1 = 2 * pr + 1 < nblk;
+        const double* A1 = has1 ? Aptrs[2 * pr + 1] : A0;
+        v4d_t acc[2][4][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = v4d_t{0.0, 0.0, 0.0, 0.0};
-        v4d_t ar[kGrRing], br[kGrRing];
-        auto ld = [&](int st, v4d_t& av, v4d_t& bv) {
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[h][i][j] = v4d_t{0.0, 0.0, 0.0, 0.0};
+        v4d_t ar0[kGrRing], ar1[kGrRing], br[kGrRing];
+        auto ld = [&](int st, v4d_t& av0, v4d_t& av1, v4d_t& bv) {
             const int r = 4 * st + g;
             if (st < w1 && r < n) {
-                av = *reinterpret_cast<const v4d_t*>(A + (long long)r * 64 + 4 * m);
+                av0 = *reinterpret_cast<const v4d_t*>(A0 + (long long)r * 64 + 4 * m);
+                av1 = *reinterpret_cast<const v4d_t*>(A1 + (long long)r * 64 + 4 * m);
                 bv = *reinterpret_cast<const v4d_t*>(B + (long long)r * 64 + 4 * m);
             } else {
-                av = v4d_t{0.0, 0.0, 0.0, 0.0};
-                bv = v4d_t{0.0, 0.0, 0.0, 0.0};
+                av0 = av1 = bv = v4d_t{0.0, 0.0, 0.0, 0.0};
             }
         };
 #pragma unroll
-        for (int d = 0; d < kGrRing; ++d) ld(w0 + d, ar[d], br[d]);
+        for (int d = 0; d < kGrRing; ++d) ld(w0 + d, ar0[d], ar1[d], br[d]);
         for (int st = w0; st < w1; st += kGrRing) {
 #pragma unroll
             for (int d = 0; d < kGrRing; ++d) {
@@ -331,43 +337,50 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
 #pragma unroll
                     for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-                        for (int jb = 0; jb < 4; ++jb)
-                            acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[d][ib], br[d][jb], acc[ib][jb], 0, 0, 0);
-                    ld(st + d + kGrRing, ar[d], br[d]);
+                        for (int jb = 0; jb < 4; ++jb) {
+                            acc[0][ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar0[d][ib], br[d][jb], acc[0][ib][jb], 0, 0, 0);
+                            acc[1][ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar1[d][ib], br[d][jb], acc[1][ib][jb], 0, 0, 0);
+                        }
+                    ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
                 }
             }
         }
-        // D layout: lane holds rows g + 4v, column m of block (ib, jb)
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib)
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !has1) break;
+            // D layout: lane holds rows g + 4v, column m of block (ib, jb)
 #pragma unroll
-            for (int jb = 0; jb < 4; ++jb)
+            for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    red[wave * 4096 + (4 * (g + 4 * v) + ib) * 64 + 4 * m + jb] = acc[ib][jb][v];
-        __syncthreads();
-        double* out = part + ((long long)w * 2 + slot) * 4096;
+                for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            out[e] = ((red[e] + red[4096 + e]) + red[8192 + e]) + red[12288 + e];
+                    for (int v = 0; v < 4; ++v)
+                        red[wave * 4096 + (4 * (g + 4 * v) + ib) * 64 + 4 * m + jb] = acc[h][ib][jb][v];
+            __syncthreads();
+            double* out = part + (((long long)w * 2 + slot) * 2 + h) * 4096;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + 256 * u;
+                out[e] = ((red[e] + red[4096 + e]) + red[8192 + e]) + red[12288 + e];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
-// out[b][e] = sum, in workgroup order, of the segment partials of block b: workgroup = 64
-// consecutive entries of one block; its four wavefronts take every fourth contributing
-// workgroup and meet in LDS.
+// out[b][e] = sum, in workgroup order, of the segment partials of block b (pair b/2, half
+// b%2): workgroup = 64 consecutive entries of one block; its four wavefronts take every fourth
+// contributing workgroup and meet in LDS.
 __global__ void __launch_bounds__(256) k_gram64_reduce(int n, int nblk, int G, const double* __restrict__ part,
                                                        double* __restrict__ out) {
     __shared__ double red[4][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = blockIdx.x >> 6, e = ((blockIdx.x & 63) << 6) + lane;
-    const long long nsteps = (n + 3) >> 2, S = nsteps * nblk;
-    const long long bs = (long long)b * nsteps, be = bs + nsteps;
+    const int pr = b >> 1, h = b & 1, npair = (nblk + 1) >> 1;
+    const long long nsteps = (n + 3) >> 2, S = nsteps * npair;
+    const long long bs = (long long)pr * nsteps, be = bs + nsteps;
     // contributing workgroups wf..wl: [w S / G, (w+1) S / G) meets [bs, be); only wf can
-    // start before bs (its block-b partial is then in slot 1)
+    // start before bs (its pair-pr partial is then in slot 1)
     long long wf = bs * G / S;
     while (wf > 0 && wf * S / G > bs) --wf;
     while ((wf + 1) * S / G <= bs) ++wf;
@@ -377,7 +390,8 @@ __global__ void __launch_bounds__(256) k_gram64_reduce(int n, int nblk, int G, c
     const int slot_f = wf * S / G < bs ? 1 : 0;
     double v = 0.0;
     for (long long ww = wf + wave; ww <= wl; ww += 4)
-        v += part[(ww * 2 + (ww == wf ? slot_f : 0)) * 4096 + e];
+        if ((ww + 1) * S / G > ww * S / G)   // a workgroup with an empty step range adds only zeros
+            v += part[((ww * 2 + (ww == wf ? slot_f : 0)) * 2 + h) * 4096 + e];
     red[wave][lane] = v;
     __syncthreads();
     if (wave == 0) out[(long long)b * 4096 + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
@@ -464,8 +478,9 @@ void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, co
                  double* out, hipStream_t st) {
     if (nblk == 0) return;
     if (ka == 64 && kb == 64 && n >= 64) {
-        const int G = kGrGroups * ((nblk + kGrGroups - 1) / kGrGroups);
-        if ((long long)G * 2 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
+        const int npair = (nblk + 1) / 2;
+        const int G = kGrGroups * ((npair + kGrGroups - 1) / kGrGroups);
+        if ((long long)G * 4 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
         k_gram64<<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part);
         k_gram64_reduce<<<nblk * 64, 256, 0, st>>>(n, nblk, G, part, out);
         return;
@@ -828,6 +843,37 @@ void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* p
     else
         k_rowsum_dot<<<nb, 256, 0, st>>>(n, k, r, Z, part);
     k_sum<<<1, 256, 0, st>>>(nb, part, out);
+}
+
+// part[blk] = sum of (a - b)^2, part[256 + blk] = sum of b^2 over the workgroup's grid-stride
+// share of the len entries (fixed order within the workgroup)
+__global__ void __launch_bounds__(256) k_diff_norms(long long len, const double* __restrict__ a,
+                                                    const double* __restrict__ b, double* __restrict__ part) {
+    __shared__ double red[2][4];
+    double d2 = 0.0, b2 = 0.0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < len; i += 256LL * gridDim.x) {
+        const double bv = b[i], dv = a[i] - bv;
+        d2 = fma(dv, dv, d2);
+        b2 = fma(bv, bv, b2);
+    }
+    d2 = warp_sum(d2);
+    b2 = warp_sum(b2);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = d2;
+        red[1][threadIdx.x >> 6] = b2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        part[256 + blockIdx.x] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+}
+
+void launch_diff_norms(long long len, const double* a, const double* b, double* part, double* out, hipStream_t st) {
+    const int nb = (int)std::max(1LL, std::min(256LL, (len + 255) / 256));
+    k_diff_norms<<<nb, 256, 0, st>>>(len, a, b, part);
+    k_sum<<<1, 256, 0, st>>>(nb, part, out);
+    k_sum<<<1, 256, 0, st>>>(nb, part + 256, out + 1);
 }
 
 __global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {

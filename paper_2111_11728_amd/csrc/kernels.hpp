@@ -167,6 +167,8 @@ void launch_orth_update(int n, int k, const double* const* Wptrs, int nblk, cons
 void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st);
 // out[0..63] = A^T x (A: n x 64 row-major), two-stage deterministic reduction through part
 void launch_gemv_t(int n, int k, const double* A, const double* x, double* part, double* out, hipStream_t st);
+void launch_diff_norms(long long len, const double* a, const double* b, double* part, double* out,
+                       hipStream_t st);  // out[0] = ||a - b||^2, out[1] = ||b||^2 (part: >= 512)
 void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st);  // y = a x + b y
 void launch_pcg_update(int n, const double* sc, const double* w, const double* q, double* lam, double* r,
                        hipStream_t st);

@@ -51,7 +51,7 @@ class feti_info(C.Structure):
                 ("eps", C.c_double), ("true_rel_res", C.c_double), ("kept_directions", C.c_int),
                 ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int), ("rank_hist", C.POINTER(C.c_int)),
                 ("t_solve_ms", C.c_double), ("fp64_fallback", C.c_int),
-                ("reduced_iters", C.c_int)]
+                ("reduced_iters", C.c_int), ("precision_probes", C.c_int), ("reduced_rel_err", C.c_double)]
 
 
 class feti_sizes(C.Structure):
@@ -217,7 +217,8 @@ class Context:
         return {"status": st, "iters": info.iters, "refinements": info.refinements, "eps0": info.eps0,
                 "eps": info.eps, "true_rel_res": info.true_rel_res, "kept_directions": info.kept_directions,
                 "history": hist[:n].copy(), "ranks": ranks[:info.iters].copy(), "t_solve_ms": info.t_solve_ms,
-                "fp64_fallback": info.fp64_fallback, "reduced_iters": info.reduced_iters}
+                "fp64_fallback": info.fp64_fallback, "reduced_iters": info.reduced_iters,
+                "precision_probes": info.precision_probes, "reduced_rel_err": info.reduced_rel_err}
 
     def feti_compliance_and_grad(self, rho, f, c, dc, u=None):
         info = feti_info()
@@ -225,7 +226,8 @@ class Context:
                                                    C.byref(info)), allow=(FETI_ENOCONV,))
         return {"status": st, "iters": info.iters, "true_rel_res": info.true_rel_res,
                 "refinements": info.refinements, "fp64_fallback": info.fp64_fallback,
-                "reduced_iters": info.reduced_iters}
+                "reduced_iters": info.reduced_iters, "precision_probes": info.precision_probes,
+                "reduced_rel_err": info.reduced_rel_err}
 
     def feti_apply_F(self, k, precision, Lam, Q, pure=False):
         p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)

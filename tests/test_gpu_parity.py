@@ -258,6 +258,13 @@ def test_mixed_precision_solve(precision):
     info = ctx.feti_solve(_t(prob.load()), u)
     assert info["true_rel_res"] <= 1e-8
     assert _rel(u.cpu().numpy(), fem.solve_problem(prob)) < 1e-6
+    # the switch to the reduced operator is measured: at least one probe, and reduced
+    # iterations only if the measured relative error allows them before the tolerance
+    assert info["precision_probes"] >= 1
+    eta = info["reduced_rel_err"]
+    assert 0.0 < eta < 1.0
+    if info["reduced_iters"] > 0:  # eta * eps <= 0.1 tol eps0 with eps >= tol eps0
+        assert eta <= 0.1
     ctx.close()
 
 
@@ -286,6 +293,28 @@ def test_c2_sfeti_fetidp():
             cross = lambda h: int(np.argmax(h <= 1e-8))
             assert abs(cross(hg) - cross(ho)) <= 2
         ctx.close()
+
+
+def test_sfeti_64_directions_small_interface():
+    """8x8 subdomains of 3x3 elements: 64 direction groups (the widest block of Algorithm 1)
+    with fewer than 1024 dual unknowns, so the Gram products over one stored block leave
+    workgroups without rows; the solve must still match the oracle."""
+    prob = workloads.cantilever_tfeti(4, nsub=(8, 8), m=3)
+    op = ofeti.FETIDP(prob, "dirichlet", "k")
+    res = okrylov.solve(op, "sfeti", tol=1e-10)
+    u_ref, _ = op.recover(res.lam)
+    print(f"case sfeti64 n_lambda={op.n_lambda}", flush=True)
+    assert op.n_lambda < 1024
+    ctx = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", tol=1e-10)
+    assert ctx.sizes["n_groups"] == 64 and ctx.sizes["n_lambda"] == op.n_lambda
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
+    info = ctx.feti_solve(_t(prob.load()), u)
+    assert _rel(u.cpu().numpy(), u_ref) < 1e-8
+    hg = np.asarray(info["history"]) / info["history"][0]
+    ho = np.asarray(res.history) / res.history[0]
+    cross = lambda h: int(np.argmax(h <= 1e-8)) if np.any(h <= 1e-8) else len(h)
+    assert abs(cross(hg) - cross(ho)) <= 1
+    ctx.close()
 
 
 def test_compliance_gradient_small():
