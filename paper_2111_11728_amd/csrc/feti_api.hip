@@ -147,7 +147,8 @@ struct feti_ctx {
     double *Ybuf = nullptr, *Tbuf = nullptr, *vbuf = nullptr, *Qtmp = nullptr, *Tsum = nullptr;
     double *Zk = nullptr, *Qk = nullptr, *Delta = nullptr, *Tm = nullptr, *gam = nullptr, *part = nullptr,
            *scal = nullptr, *Psi = nullptr, *tmpv = nullptr, *zv = nullptr, *K0dev = nullptr;
-    int* rank_dev = nullptr;
+    int* rank_dev = nullptr;         // inside scal (scal[8]), so one copy returns eps and rank
+    double* hpin = nullptr;          // pinned host mirror of scal
     const double** qk_ptr = nullptr;    // device table holding the single pointer Qk
     const double** zk_ptr = nullptr;    // device table holding the single pointer Zk
     double* tcbuf = nullptr;            // coarse right-hand sides t (n_cg x k)
@@ -190,6 +191,7 @@ struct feti_ctx {
         hipStreamSynchronize(st);
         for (void* p : allocs) hipFree(p);
         for (double* p : hist_chunks) hipFree(p);
+        if (hpin) hipHostFree(hpin);
         if (WH_dev) hipFree(WH_dev);
         if (QH_dev) hipFree(QH_dev);
         if (Psi) hipFree(Psi);
@@ -486,7 +488,8 @@ void build_layout(feti_ctx* c) {
     c->gam = c->alloc<double>(kMaxDirs);
     c->part = c->alloc<double>(kGramPartCap);
     c->scal = c->alloc<double>(16);
-    c->rank_dev = c->alloc<int>(4);
+    c->rank_dev = reinterpret_cast<int*>(c->scal + 8);
+    HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(double) * 16, hipHostMallocDefault));
     c->qk_ptr = c->upload(std::vector<const double*>{c->Qk});
     c->zk_ptr = c->upload(std::vector<const double*>{c->Zk});
     c->tcbuf = c->alloc<double>((long long)std::max(1, ncg) * kMaxDirs);
@@ -725,10 +728,20 @@ void precondition(feti_ctx* c, const double* r, double* Z, int one_column, int u
     CHECK_LAUNCH();
 }
 
+// Wait for the stream by polling: the Krylov loop waits once per iteration for a few scalars,
+// and a polling host resumes launching sooner than a blocking wait.
+void wait_poll(feti_ctx* c) {
+    hipError_t e;
+    while ((e = hipStreamQuery(c->st)) == hipErrorNotReady) {
+    }
+    HIPCHK(e);
+}
+
 double read_scalar(feti_ctx* c, const double* dptr) {
     double v = 0;
-    HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpyAsync(c->hpin, dptr, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    wait_poll(c);
+    v = c->hpin[0];
     return v;
 }
 
@@ -904,9 +917,9 @@ int gated_apply(feti_ctx* c, PrecGate& g, bool replaced, double eps, double eps0
     apply_F(c, k, g.prec, Z, scratch);
     launch_diff_norms((long long)c->P.n_lambda * k, scratch, Q, c->part, c->scal + 4, c->st);
     CHECK_LAUNCH();
-    double v[2] = {0.0, 0.0};
-    HIPCHK(hipMemcpyAsync(v, c->scal + 4, sizeof(v), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpyAsync(c->hpin, c->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    wait_poll(c);
+    const double v[2] = {c->hpin[0], c->hpin[1]};
     const double e = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : 0.0;
     g.record(e);
     if (verbose()) fprintf(stderr, "[feti] precision probe: eta %.3e, eps/eps0 %.3e\n", e, eps / eps0);
@@ -1025,11 +1038,12 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             launch_ts_gemm(n, kd, nb, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st);
         }
         CHECK_LAUNCH();
+        // eps^2 (scal[0]) and the rank (scal[8]) in one copy
+        HIPCHK(hipMemcpyAsync(c->hpin, c->scal, 9 * sizeof(double), hipMemcpyDeviceToHost, st));
+        wait_poll(c);
+        const double ez = c->hpin[0];
         int rank = 0;
-        double ez = 0;
-        HIPCHK(hipMemcpyAsync(&rank, c->rank_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(&ez, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        std::memcpy(&rank, c->hpin + 8, sizeof(int));
         ranks.push_back(rank);
         o.iters = it + 1;
         if (verbose())

@@ -597,94 +597,124 @@ __device__ __forceinline__ double wave_max(double v) {
     return fmax(fmax(rl(0), rl(16)), fmax(rl(32), rl(48)));
 }
 
-__global__ void __launch_bounds__(64) k_pivchol(int k, const double* __restrict__ D, double rr_tol,
-                                                double* __restrict__ T, int* __restrict__ rank_out) {
-    // lane l keeps column l of the working matrix (a[]) and, after the factorisation, column l
-    // of Ltilde^{-1} (x[]) in registers; the factor columns go through LDS
-    __shared__ double Lm[64][65];   // Lm[m][l]: entry l of factor column m (odd stride: the
-                                    // column reads Lm[l][order[r]] below are conflict-free)
-    __shared__ __attribute__((aligned(16))) double Lt[64][66];   // Lt[r][q] = Lm[q][order[r]]
-    __shared__ double ipv[64];                                   // 1 / pivot of step m
-    __shared__ int order[64];
+// a[p] = v for a wavefront-uniform p (scalar branch to one register move)
+#define FETI_PUT1(i) \
+    case i:          \
+        a[i] = v;    \
+        break;
+#define FETI_PUT8(i) FETI_PUT1(i) FETI_PUT1(i + 1) FETI_PUT1(i + 2) FETI_PUT1(i + 3) FETI_PUT1(i + 4) FETI_PUT1(i + 5) FETI_PUT1(i + 6) FETI_PUT1(i + 7)
+__device__ __forceinline__ void put64(double (&a)[64], int p, double v) {
+    switch (p) {
+        FETI_PUT8(0) FETI_PUT8(8) FETI_PUT8(16) FETI_PUT8(24) FETI_PUT8(32) FETI_PUT8(40) FETI_PUT8(48) FETI_PUT8(56)
+        default: break;
+    }
+}
+#undef FETI_PUT8
+#undef FETI_PUT1
+
+// The columns of Ltilde^{-T} are built during the factorisation, in the original index space:
+// with pivot p at step m, the direction t_m = N^T (Ltilde^{-T})[:, m] obeys
+//     t_m = (e_p - sum_{q<m} L_q[p] t_q) / piv_m,
+// L_q the factor column of step q (forward substitution for row m of Ltilde^{-1}), so the pivot
+// order is never needed; T[l][q] = s_l t_q[l]. Two wavefronts: wavefront 0 factorises (lane l
+// keeps column l of the working matrix in registers), wavefront 1 builds the t_q (lane l keeps
+// t_q[l]); they meet once per step at a barrier, both loops running the same number of
+// barriers (each leaves after reading the same stop mark p_s[m] < 0).
+__global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict__ D, double rr_tol,
+                                                 double* __restrict__ T, int* __restrict__ rank_out) {
+    __shared__ __attribute__((aligned(16))) double Lm[64][66];    // Lm[m][i]: entry i of factor column m
+    __shared__ __attribute__((aligned(16))) double LmT[64][66];   // LmT[i][m] = Lm[m][i]
     __shared__ double scs[64];
-    const int l = threadIdx.x;
-    double a[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) a[i] = (l < k && i < k) ? 0.5 * (D[i * k + l] + D[l * k + i]) : 0.0;
-    const double dg = l < k ? 0.5 * (D[l * k + l] + D[l * k + l]) : -1.0;
-    const double dmax = wave_max(dg);
-    const bool live = l < k && dmax > 0.0 && dg > 1e-30 * dmax;
-    const double sc = live ? 1.0 / sqrt(dg) : 0.0;
-    scs[l] = sc;
+    __shared__ double ipv_s[64];
+    __shared__ int p_s[64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    // D staged through LDS by coalesced rows
+    for (int i = 32 * w; i < 32 * w + 32; ++i) Lm[i][l] = (l < k && i < k) ? D[i * k + l] : 0.0;
     __syncthreads();
+    if (w == 0) {
+        double a[64];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) a[i] = a[i] * scs[i] * sc;
-    double diag = dg * sc * sc;   // = a[l]
-    bool rem = live;
-    int m = 0;
-    for (; m < k; ++m) {
-        // largest remaining pivot, lowest index on ties
-        const double cand = rem ? diag : -1.0e300;
-        const double best = wave_max(cand);
-        if (!(best > rr_tol)) break;
-        const unsigned long long hit = __ballot(cand == best);
-        const int p = __builtin_amdgcn_readfirstlane(__ffsll((long long)hit) - 1);
-        const double piv = sqrt(best);
-        const double ipiv = 1.0 / piv;
-        // A[l][p] = A[p][l] (symmetric among the remaining indices) = a[p] of lane l
-        const double lc = (l == p) ? piv : (rem ? pick64(a, p) * ipiv : 0.0);
-        if (l == p) rem = false;
-        Lm[m][l] = lc;
-        if (l == 0) {
-            order[m] = p;
-            ipv[m] = ipiv;
-        }
-        __syncthreads();
-        // Schur-complement update of the remaining columns: A[i][l] -= lc_i lc_l
-        if (rem) {
+        for (int i = 0; i < 64; ++i) a[i] = 0.5 * (Lm[i][l] + Lm[l][i]);
+        const double dg = l < k ? 0.5 * (Lm[l][l] + Lm[l][l]) : -1.0;
+        const double dmax = wave_max(dg);
+        const bool live = l < k && dmax > 0.0 && dg > 1e-30 * dmax;
+        const double sc = live ? 1.0 / sqrt(dg) : 0.0;
+        scs[l] = sc;
+        __syncthreads();   // (S) scs complete, Lm free, LmT zeroed
 #pragma unroll
-            for (int i = 0; i < 64; ++i) a[i] -= Lm[m][i] * lc;
-            diag -= lc * lc;
-        }
-    }
-    const int rank = m;
-    // Lt[r][q] = Ltilde[r][q] = Lm[q][order[r]] (lane q writes column q)
-    for (int r = 0; r < rank; ++r) Lt[r][l] = l < rank ? Lm[l][order[r]] : 0.0;
-    __syncthreads();
-    // lane c: column c of X = Ltilde^{-1} by forward substitution with two partial sums; X lives
-    // in LDS (column c is lane c's own, so no barrier is needed inside; rolled loops keep the
-    // code small: the kernel runs once per iteration with a cold instruction cache)
-    double* X = &Lm[0][0];   // reuse: X[q*65 + c]
-    if (l < rank) {
-        for (int r = 0; r < rank; ++r) {
-            const double* Lr = Lt[r];
-            double v0 = (r == l) ? 1.0 : 0.0, v1 = 0.0;
-            int q = 0;
-            for (; q + 1 < r; q += 2) {
-                v0 -= Lr[q] * X[q * 65 + l];
-                v1 -= Lr[q + 1] * X[(q + 1) * 65 + l];
+        for (int i = 0; i < 64; ++i) a[i] = a[i] * scs[i] * sc;
+        double diag = dg * sc * sc;   // = a[l]
+        bool rem = live;
+        for (int m = 0; m < k; ++m) {
+            // largest remaining pivot, lowest index on ties
+            const double cand = rem ? diag : -1.0e300;
+            const double best = wave_max(cand);
+            const bool go = best > rr_tol;
+            const unsigned long long hit = __ballot(cand == best);
+            const int p = go ? __builtin_amdgcn_readfirstlane(__ffsll((long long)hit) - 1) : -1;
+            double lc = 0.0;
+            if (go) {
+                const double piv = sqrt(best);
+                const double ipiv = 1.0 / piv;
+                // A[l][p] = A[p][l] (symmetric among the remaining indices) = a[p] of lane l
+                lc = (l == p) ? piv : (rem ? pick64(a, p) * ipiv : 0.0);
+                if (l == p) rem = false;
+                Lm[m][l] = lc;
+                LmT[l][m] = lc;
+                if (l == 0) ipv_s[m] = ipiv;
             }
-            if (q < r) v0 -= Lr[q] * X[q * 65 + l];
-            X[r * 65 + l] = (v0 + v1) * ipv[r];
+            if (l == 0) p_s[m] = p;
+            __syncthreads();   // (B_m)
+            if (!go) break;
+            // Schur-complement update of the remaining columns: A[i][l] -= lc_i lc_l
+            if (rem) {
+#pragma unroll
+                for (int i = 0; i < 64; i += 2) {
+                    const double2 c2 = *reinterpret_cast<const double2*>(&Lm[m][i]);
+                    a[i] -= c2.x * lc;
+                    a[i + 1] -= c2.y * lc;
+                }
+                diag -= lc * lc;
+            }
         }
-    }
-    __syncthreads();
-    // T[order[r]][c] = s[order[r]] (Ltilde^{-T})[r][c] = s[order[r]] X[c][r]: lane r writes row
-    // order[r]; rows of indices never taken as pivots are zero (written by their own lane)
-    if (l < k) {
-        if (!(live && !rem))
-            for (int j = 0; j < k; ++j) T[l * k + j] = 0.0;
-        if (l < rank) {
-            const int row = order[l];
-            const double s = scs[row];
-            for (int j = 0; j < k; ++j) T[row * k + j] = j < rank ? s * X[j * 65 + l] : 0.0;
+    } else {
+        double x[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) {
+            x[i] = 0.0;
+            LmT[l][i] = 0.0;
         }
+        __syncthreads();   // (S)
+        int m = 0;
+        for (; m < k; ++m) {
+            __syncthreads();   // (B_m)
+            const int p = p_s[m];
+            if (p < 0) break;
+            // LmT[p][q] = L_q[p] for q < m; entries q > m are zero (later steps write zeros
+            // into row p: index p is no longer a candidate) and x[m] is still zero
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 64; q += 2) {
+                const double2 b = *reinterpret_cast<const double2*>(&LmT[p][q]);
+                s0 = fma(b.x, x[q], s0);
+                s1 = fma(b.y, x[q + 1], s1);
+            }
+            put64(x, m, ((l == p ? 1.0 : 0.0) - (s0 + s1)) * ipv_s[m]);
+        }
+        const int rank = m;
+        // row l of T; components of indices never taken as pivots are exactly zero
+        if (l < k) {
+            const double s = scs[l];
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                if (j < k) T[l * k + j] = j < rank ? s * x[j] : 0.0;
+        }
+        if (l == 0) *rank_out = rank;
     }
-    if (l == 0) *rank_out = rank;
 }
 
 void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st) {
-    k_pivchol<<<1, 64, 0, st>>>(k, D, rr_tol, T, rank);
+    k_pivchol<<<1, 128, 0, st>>>(k, D, rr_tol, T, rank);
 }
 
 // Wo = W T, Qo = Q T (n x k by k x k), 4 rows x 64 columns per workgroup step.
