@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
             const int r = 4 * st + g;
             if (st < w1 && r < n) {
                 av0 = *reinterpret_cast<const v4d_t*>(A0 + (long long)r * 64 + 4 * m);
-                av1 = *reinterpret_cast<const v4d_t*>(A1 + (long long)r * 64 + 4 * m);
+                if (has1) av1 = *reinterpret_cast<const v4d_t*>(A1 + (long long)r * 64 + 4 * m);
                 bv = *reinterpret_cast<const v4d_t*>(B + (long long)r * 64 + 4 * m);
             } else {
                 av0 = av1 = bv = v4d_t{0.0, 0.0, 0.0, 0.0};
@@ -330,18 +330,38 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
         };
 #pragma unroll
         for (int d = 0; d < kGrRing; ++d) ld(w0 + d, ar0[d], ar1[d], br[d]);
-        for (int st = w0; st < w1; st += kGrRing) {
+        if (has1) {
+            for (int st = w0; st < w1; st += kGrRing) {
 #pragma unroll
-            for (int d = 0; d < kGrRing; ++d) {
-                if (st + d < w1) {
+                for (int d = 0; d < kGrRing; ++d) {
+                    if (st + d < w1) {
 #pragma unroll
-                    for (int ib = 0; ib < 4; ++ib)
+                        for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-                        for (int jb = 0; jb < 4; ++jb) {
-                            acc[0][ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar0[d][ib], br[d][jb], acc[0][ib][jb], 0, 0, 0);
-                            acc[1][ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar1[d][ib], br[d][jb], acc[1][ib][jb], 0, 0, 0);
-                        }
-                    ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
+                            for (int jb = 0; jb < 4; ++jb) {
+                                acc[0][ib][jb] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(ar0[d][ib], br[d][jb], acc[0][ib][jb], 0, 0, 0);
+                                acc[1][ib][jb] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(ar1[d][ib], br[d][jb], acc[1][ib][jb], 0, 0, 0);
+                            }
+                        ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
+                    }
+                }
+            }
+        } else {
+            // a single block (the last one of an odd count): half the products
+            for (int st = w0; st < w1; st += kGrRing) {
+#pragma unroll
+                for (int d = 0; d < kGrRing; ++d) {
+                    if (st + d < w1) {
+#pragma unroll
+                        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                            for (int jb = 0; jb < 4; ++jb)
+                                acc[0][ib][jb] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(ar0[d][ib], br[d][jb], acc[0][ib][jb], 0, 0, 0);
+                        ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
+                    }
                 }
             }
         }
