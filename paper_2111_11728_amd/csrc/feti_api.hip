@@ -1012,8 +1012,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         // Delta = Q^T W
         launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
         launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st);
-        launch_ts_gemm(n, kd, 1, c->zk_ptr, c->Tm, nullptr, Wn, 1.0, 0.0, st);
-        launch_ts_gemm(n, kd, 1, c->qk_ptr, c->Tm, nullptr, Qn, 1.0, 0.0, st);
+        launch_ts_pair(n, kd, c->zk_ptr, c->qk_ptr, c->Tm, Wn, Qn, st);
         // gamma = W^T r
         if (kd == 64)
             launch_gemv_t(n, kd, Wn, c->r, c->part, c->gam, st);

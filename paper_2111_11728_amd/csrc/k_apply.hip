@@ -526,36 +526,60 @@ __global__ void k_coarse_t(int n_cg, int k, const TT* __restrict__ T, const doub
 // v = scale * Kinv t (n_cg x n_cg by n_cg x k, k <= 64) on the FP64 matrix cores: workgroup =
 // 16 rows of v, wavefront w = columns 16w..16w+15. Step Q contracts q = 16Q + 4g + s, so lane
 // (m, g) reads Kinv[p0 + m][16Q + 4g .. +3] (one 32-byte load) and t[16Q + 4g + s][16w + m].
-__global__ void __launch_bounds__(256) k_coarse_v(int n_cg, int k, const double* __restrict__ t,
-                                                  const double* __restrict__ Kinv, double scale, double* __restrict__ v) {
+__global__ void __launch_bounds__(1024) k_coarse_v(int n_cg, int k, const double* __restrict__ t,
+                                                   const double* __restrict__ Kinv, double scale, double* __restrict__ v) {
+    // workgroup: 16 rows of v; wavefront (cg, ks) = (w mod 4, w / 4): columns 16 cg..16 cg + 15 and
+    // the 16-wide contraction slices Q = ks (mod 4), three slices of loads in flight; the four
+    // partial tiles are summed in LDS in a fixed order
     typedef double v4 __attribute__((ext_vector_type(4)));
+    __shared__ double red[4][16][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
-    const int p0 = blockIdx.x * 16, col = 16 * wave + m;
+    const int cg = wave & 3, ks = wave >> 2;
+    const int p0 = blockIdx.x * 16, col = 16 * cg + m;
     const int prow = p0 + m;
-    v4 acc = v4{0.0, 0.0, 0.0, 0.0};
     const int nQ = (n_cg + 15) >> 4;
     const bool vec = (n_cg & 3) == 0;
-    for (int Q = 0; Q < nQ; ++Q) {
+    auto ld = [&](int Q, double (&a)[4], double (&bq)[4]) {
         const int q0 = 16 * Q + 4 * g;
-        double a[4], bq[4];
-        if (vec && prow < n_cg && q0 + 3 < n_cg) {
+        if (Q < nQ && vec && prow < n_cg && q0 + 3 < n_cg) {
             const v4 av = *reinterpret_cast<const v4*>(Kinv + (long long)prow * n_cg + q0);
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) a[s2] = av[s2];
         } else {
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) a[s2] = (prow < n_cg && q0 + s2 < n_cg) ? Kinv[(long long)prow * n_cg + q0 + s2] : 0.0;
+            for (int s2 = 0; s2 < 4; ++s2)
+                a[s2] = (Q < nQ && prow < n_cg && q0 + s2 < n_cg) ? Kinv[(long long)prow * n_cg + q0 + s2] : 0.0;
         }
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) bq[s2] = (q0 + s2 < n_cg && col < k) ? t[(long long)(q0 + s2) * k + col] : 0.0;
+        for (int s2 = 0; s2 < 4; ++s2)
+            bq[s2] = (Q < nQ && q0 + s2 < n_cg && col < k) ? t[(long long)(q0 + s2) * k + col] : 0.0;
+    };
+    constexpr int R = 3;
+    double ar[R][4], br[R][4];
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], bq[s2], acc, 0, 0, 0);
+    for (int d = 0; d < R; ++d) ld(ks + 4 * d, ar[d], br[d]);
+    v4 acc = v4{0.0, 0.0, 0.0, 0.0};
+    for (int Q = ks; Q < nQ; Q += 4 * R) {
+#pragma unroll
+        for (int d = 0; d < R; ++d) {
+            if (Q + 4 * d < nQ) {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[d][s2], br[d][s2], acc, 0, 0, 0);
+                ld(Q + 4 * d + 4 * R, ar[d], br[d]);
+            }
+        }
     }
     // D layout: rows g + 4 j, column m
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int p = p0 + g + 4 * j;
-        if (p < n_cg && col < k) v[(long long)p * k + col] = scale * acc[j];
+    for (int j = 0; j < 4; ++j) red[ks][g + 4 * j][col] = acc[j];
+    __syncthreads();
+    if (ks == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = g + 4 * j, p = p0 + r;
+            if (p < n_cg && col < k)
+                v[(long long)p * k + col] = scale * (((red[0][r][col] + red[1][r][col]) + red[2][r][col]) + red[3][r][col]);
+        }
     }
 }
 
@@ -569,7 +593,7 @@ void launch_coarse(const DevTopo& t, int k, int ytype_f32, const void* T, const 
     else
         k_coarse_t<double><<<(int)((n + 255) / 256), 256, 0, st>>>(t.n_cg, k, (const double*)T, add, t.cc_ptr,
                                                                    t.cc_s, t.cc_j, t.subs, tbuf);
-    k_coarse_v<<<(t.n_cg + 15) / 16, 256, 0, st>>>(t.n_cg, k, tbuf, Kinv, scale, v);
+    k_coarse_v<<<(t.n_cg + 15) / 16, 1024, 0, st>>>(t.n_cg, k, tbuf, Kinv, scale, v);
 }
 
 // Y_s[j][c] += sum_q F_rc^s[j][q] v[cg(s,q)][c]  (the coarse correction folded into the local

@@ -214,7 +214,12 @@ constexpr int kTsWaves = 8;   // 128 output rows per workgroup
 // double-buffered per block.
 __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
                                                         const double* __restrict__ Mats, const double* C, double* out,
-                                                        double alpha, double beta) {
+                                                        double alpha, double beta, const double* const* Aptrs2,
+                                                        double* out2) {
+    if (blockIdx.y) {   // second job of a paired launch: same Mats, its own operands
+        Aptrs = Aptrs2;
+        out = out2;
+    }
     __shared__ __attribute__((aligned(16))) double Ps[2][4096];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
     const int rb0 = blockIdx.x * (16 * kTsWaves) + 16 * wave;
@@ -489,9 +494,21 @@ void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const d
     if (!n || !nblk) return;
     if (kd == 64)
         k_ts64<<<(n + 16 * kTsWaves - 1) / (16 * kTsWaves), 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha,
-                                                                                    beta);
+                                                                                    beta, nullptr, nullptr);
     else
         k_ts_gemm<<<(n + 63) / 64, 256, 0, st>>>(n, kd, nblk, Aptrs, Mats, C, out, alpha, beta);
+}
+
+void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* const* Aptrs2, const double* Mats,
+                    double* out, double* out2, hipStream_t st) {
+    if (!n) return;
+    if (kd == 64) {
+        k_ts64<<<dim3((n + 16 * kTsWaves - 1) / (16 * kTsWaves), 2), 64 * kTsWaves, 0, st>>>(
+            n, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, Aptrs2, out2);
+        return;
+    }
+    launch_ts_gemm(n, kd, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, st);
+    launch_ts_gemm(n, kd, 1, Aptrs2, Mats, nullptr, out2, 1.0, 0.0, st);
 }
 
 void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
@@ -794,13 +811,14 @@ void launch_update_lr(int n, int k, const double* W, const double* Q, const doub
         k_update_lr<<<(n + 255) / 256, 256, 0, st>>>(n, k, W, Q, g, lam, r);
 }
 
-__global__ void k_colsum64(int nchunk, const double* __restrict__ part, double* __restrict__ out);
+__global__ void __launch_bounds__(1024) k_colsum64(int nchunk, const double* __restrict__ part, double* __restrict__ out);
 
 void launch_gemv_t(int n, int k, const double* A, const double* x, double* part, double* out, hipStream_t st) {
     if (k != 64) throw std::invalid_argument("launch_gemv_t takes 64 columns");
-    const int nchunk = std::max(1, std::min(256, (n + 1023) / 1024));
+    // 64 rows per workgroup, up to 1024 workgroups: enough in flight to fill all CUs
+    const int nchunk = std::max(1, std::min(1024, (n + 63) / 64));
     k_gemv_t64<<<nchunk, 256, 0, st>>>(n, A, x, part);
-    k_colsum64<<<1, 256, 0, st>>>(nchunk, part, out);
+    k_colsum64<<<1, 1024, 0, st>>>(nchunk, part, out);
 }
 
 // W -= sum_b W_b Psi_b, Psi_b = Psi + b*k*k (k x k), W_b = Wptrs[b] (n x k).
@@ -875,19 +893,28 @@ __global__ void __launch_bounds__(256) k_sum(int n, const double* __restrict__ p
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// out[e] = sum_c part[c*64 + e] for e < 64: four wavefronts take c = w mod 4, fixed-order combine
-__global__ void __launch_bounds__(256) k_colsum64(int nchunk, const double* __restrict__ part, double* __restrict__ out) {
-    __shared__ double red[4][64];
+// out[e] = sum_c part[c*64 + e] for e < 64: sixteen wavefronts take c = w mod 16, each with four
+// running sums (c = w + 16(4i + u), sum u) so that four loads are in flight; fixed-order combine
+__global__ void __launch_bounds__(1024) k_colsum64(int nchunk, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double red[16][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double v = 0.0;
-    for (int c = wave; c < nchunk; c += 4) v += part[(long long)c * 64 + lane];
-    red[wave][lane] = v;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = wave; c < nchunk; c += 64)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c + 16 * u < nchunk) v[u] += part[(long long)(c + 16 * u) * 64 + lane];
+    red[wave][lane] = (v[0] + v[1]) + (v[2] + v[3]);
     __syncthreads();
-    if (wave == 0) out[lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (wave == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) t += red[w][lane];
+        out[lane] = t;
+    }
 }
 
 void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st) {
-    const int nb = std::max(1, std::min(256, (n + 255) / 256));
+    const int nb = k == 64 ? std::max(1, std::min(1024, (n + 63) / 64)) : std::max(1, std::min(256, (n + 255) / 256));
     if (k == 64)
         k_rowsum_dot64<<<nb, 256, 0, st>>>(n, r, Z, part);
     else

@@ -154,6 +154,9 @@ void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, co
 int gram_chunks(int n, int nblk);
 constexpr long long kGramPartCap = 4096ll * kMaxDirs * kMaxDirs;   // doubles in the partial-sum buffer
 // out = beta C + alpha sum_b A_b M_b (FP64 matrix cores), A_b n x kd, M_b kd x kd
+// out = A Mats and out2 = A2 Mats (one stored block each, n x kd; Mats kd x kd) in one launch
+void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* const* Aptrs2, const double* Mats,
+                    double* out, double* out2, hipStream_t st);
 void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
                     double* out, double alpha, double beta, hipStream_t st);
 void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st);
