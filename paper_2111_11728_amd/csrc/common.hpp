@@ -30,7 +30,9 @@ struct SubMeta {
     long long off_S;    // S = K_beta,beta - Z^T Z, row-major [n_beta x n_beta]
     long long off_F;    // [rows_F x ldF] row-major F_s and F_rc^T (FP64 master copy)
     long long off_Fsw;  // MFMA-swizzled copies (elements, same offset for every precision)
-    long long off_P;    // preconditioner block S~ [n_b x n_b] row-major; also work buffers of that size
+    long long off_P;    // work buffers of n_b x n_b, row-major
+    long long off_Pk;   // preconditioner block S~: upper triangle in 64x64 tiles (I <= J), tile (I, J) at
+                        // (J(J+1)/2 + I) * 4096, holding S~[64I + a][64J + b] at a*64 + b (zero past n_b)
     long long off_Kc;   // Kbar_cc^s [n_c x n_c]
     long long off_R;    // TFETI: R_b [n_b x n_rbm] row-major
 };

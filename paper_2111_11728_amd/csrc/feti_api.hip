@@ -127,8 +127,7 @@ struct feti_ctx {
     double* sw64 = nullptr;
     float* sw32 = nullptr;
     __hip_bfloat16 *swhi = nullptr, *swlo = nullptr;
-    double *P64 = nullptr, *W1 = nullptr, *W2 = nullptr;
-    float* P32 = nullptr;
+    double *Pk = nullptr, *W1 = nullptr, *W2 = nullptr, *ypart = nullptr;
     double *Kc = nullptr, *Kcc = nullptr, *Kcc_w = nullptr, *Kcc_inv = nullptr;
     double *Rb = nullptr, *Cit = nullptr, *tau = nullptr, *GG = nullptr, *GG_w = nullptr, *GG_inv = nullptr;
     double *w = nullptr, *bg_w = nullptr;
@@ -243,7 +242,7 @@ void build_layout(feti_ctx* c) {
     const int ns = P.n_sub;
     c->hsubs.assign(ns, SubMeta{});
     c->hlines.clear();
-    long long oL = 0, oZ = 0, oS = 0, oF = 0, oP = 0, oKc = 0, oR = 0, oLi = 0;
+    long long oL = 0, oZ = 0, oS = 0, oF = 0, oP = 0, oPk = 0, oKc = 0, oR = 0, oLi = 0;
     DevTopo& t = c->t;
     const int nrbm = P.method == FETI_TFETI ? (P.dim == 2 ? 3 : 6) : 0;
     for (int s = 0; s < ns; ++s) {
@@ -301,6 +300,8 @@ void build_layout(feti_ctx* c) {
         oF += (long long)M.rows_F * M.ldF;
         M.off_P = oP;
         oP += (long long)M.n_b * M.n_b;
+        M.off_Pk = oPk;
+        oPk += (long long)((M.n_b + 63) / 64) * ((M.n_b + 63) / 64 + 1) / 2 * 4096;
         M.off_Kc = oKc;
         oKc += (long long)M.n_c * M.n_c;
         M.off_R = oR;
@@ -341,8 +342,8 @@ void build_layout(feti_ctx* c) {
     c->sw32 = c->alloc<float>(oF);
     c->swhi = c->alloc<__hip_bfloat16>(oF);
     c->swlo = c->alloc<__hip_bfloat16>(oF);
-    c->P64 = c->alloc<double>(oP);
-    c->P32 = c->alloc<float>(oP);
+    c->Pk = c->alloc<double>(std::max(1LL, oPk));
+    c->ypart = c->alloc<double>(std::max<long long>(1, (long long)kPsMaxSplit * t.nb_tot));
     c->W1 = c->alloc<double>(oP);
     c->W2 = c->alloc<double>(oP);
     c->Kc = c->alloc<double>(oKc);
@@ -640,12 +641,10 @@ void numeric_setup(feti_ctx* c) {
     CHECK_LAUNCH();
     launch_bt_forward_li(t, c->L, c->Li, c->Z, st);
     CHECK_LAUNCH();
-    if (c->opts.precond == FETI_LUMPED) launch_copy_Sbb(t, c->S, c->P64, 0, st);
+    if (c->opts.precond == FETI_LUMPED) launch_pack_sym(t, c->S, c->Pk, st);
     launch_gemm_tn(c->d_syrk, t.n_sub, c->syrk_tiles, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
     CHECK_LAUNCH();
-    if (c->opts.precond == FETI_DIRICHLET) launch_copy_Sbb(t, c->S, c->P64, 0, st);
-    long long nP = H.empty() ? 0 : H.back().off_P + (long long)H.back().n_b * H.back().n_b;
-    launch_to_f32(c->P64, c->P32, nP, st);
+    if (c->opts.precond == FETI_DIRICHLET) launch_pack_sym(t, c->S, c->Pk, st);
     if (P.method == FETI_TFETI)
         launch_tfeti_rbm(t, c->S, c->Rb, c->Cit, c->tau, c->W1, st);
     else
@@ -723,7 +722,7 @@ void project(feti_ctx* c, int k, double* Y) {
 void precondition(feti_ctx* c, const double* r, double* Z, int one_column, int use_f32) {
     DevTopo& t = c->t;
     (void)use_f32;  // the preconditioner blocks stay FP64: FP32 rounding can make them indefinite
-    launch_precond_local(t, 0, r, c->bg_w, c->P64, c->P32, c->yb, c->st);
+    launch_precond_local(t, r, c->bg_w, c->Pk, c->ypart, c->yb, c->st);
     launch_precond_scatter(t, one_column, c->w, c->yb, Z, c->st);
     CHECK_LAUNCH();
 }
@@ -1518,9 +1517,25 @@ feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long 
                     for (int q = 0; q < M.n_c; ++q) v.push_back(F[(long long)(M.rowT + q) * M.ldF + j]);
             }
         } else if (what == 1) {
+            // the packed upper tiles, expanded to the full symmetric n_b x n_b block
             const SubMeta& M = c->hsubs[s];
             nr = nc = M.n_b;
-            fetch(c->P64 + M.off_P, (long long)M.n_b * M.n_b);
+            const int nT = (M.n_b + 63) / 64;
+            std::vector<double> pk;
+            pk.resize((size_t)nT * (nT + 1) / 2 * 4096);
+            if (!pk.empty())
+                HIPCHK(hipMemcpy(pk.data(), c->Pk + M.off_Pk, sizeof(double) * pk.size(), hipMemcpyDeviceToHost));
+            v.assign((size_t)M.n_b * M.n_b, 0.0);
+            for (int J = 0; J < nT; ++J)
+                for (int I = 0; I <= J; ++I)
+                    for (int a = 0; a < 64; ++a)
+                        for (int b = 0; b < 64; ++b) {
+                            const int row = 64 * I + a, col = 64 * J + b;
+                            if (row >= M.n_b || col >= M.n_b) continue;
+                            const double e = pk[((size_t)J * (J + 1) / 2 + I) * 4096 + a * 64 + b];
+                            v[(size_t)row * M.n_b + col] = e;
+                            v[(size_t)col * M.n_b + row] = e;
+                        }
         } else if (what == 3) {
             const SubMeta& M = c->hsubs[s];
             nr = nc = M.n_c;

@@ -672,41 +672,131 @@ void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, doubl
 
 // ---------------------------------------------------------------------------------------
 // Preconditioner (Sec. 3.1, Eq. 13): x_s = B~^sT r = B^sT W^s r, y_s = S~^s x_s.
-// One workgroup per (subdomain, 64 rows of S~^s); x_s is gathered whole into LDS.
-template <typename TP>
-__global__ void __launch_bounds__(256) k_precond_local(const SubMeta* __restrict__ subs, const int* __restrict__ bg_ptr,
-                                                       const int* __restrict__ bg_row, const int8_t* __restrict__ bg_sg,
-                                                       const double* __restrict__ bg_w, const double* __restrict__ r,
-                                                       const TP* __restrict__ P, double* __restrict__ y) {
-    extern __shared__ double xs[];
-    const int s = blockIdx.y;
-    const SubMeta M = subs[s];
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x * 256 >= M.n_b) return;
-    for (int q = threadIdx.x; q < M.n_b; q += 256) {
-        const long long g = M.off_b + q;
-        double v = 0.0;
-        for (int e = bg_ptr[g]; e < bg_ptr[g + 1]; ++e) v += bg_sg[e] * bg_w[e] * r[bg_row[e]];
-        xs[q] = v;
-    }
-    __syncthreads();
-    if (j >= M.n_b) return;
-    // S~ is symmetric: y[j] = sum_q S~[q][j] x[q] reads column j, coalesced across threads
-    const TP* Pc = P + M.off_P + j;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < M.n_b; ++q) acc += (double)Pc[(long long)q * M.n_b] * xs[q];
-    y[M.off_b + j] = acc;
+// S~^s is symmetric and stored as its upper triangle in 64x64 tiles, so every stored value is
+// read once: tile (I, J) adds S_IJ x_J to y_I (row part) and, for I < J, S_IJ^T x_I to y_J
+// (column part). Workgroup (g, s) takes tiles [g nt / G, (g+1) nt / G) of subdomain s in storage
+// order (column block J outer); thread (wave, lane) holds row i = 4 wave + lane/16 of a tile and
+// columns 4 (lane%16) .. +3 (one 32-byte load per tile, kPsRing tiles ahead). x_s and the partial
+// y_s live in LDS; the column part is summed over the tile rows in a fixed order when J changes.
+// G = 1 writes y_s; G > 1 writes partial g to ypart + g * nb_tot for k_precond_sum.
+constexpr int kPsRing = 4;
+typedef double ps4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int tri_col(int t) {   // J with J(J+1)/2 <= t < (J+1)(J+2)/2
+    int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    while (J * (J + 1) / 2 > t) --J;
+    return J;
 }
 
-void launch_precond_local(const DevTopo& t, int use_f32, const double* r, const double* bg_w, const double* P64,
-                          const float* P32, double* y, hipStream_t st) {
-    dim3 grid((t.max_nb + 255) / 256, t.n_sub);
-    const size_t sh = sizeof(double) * std::max(1, t.max_nb);
-    if (use_f32)
-        k_precond_local<float><<<grid, 256, sh, st>>>(t.subs, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, P32, y);
-    else
-        k_precond_local<double><<<grid, 256, sh, st>>>(t.subs, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, P64, y);
+__global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict__ subs, const int* __restrict__ bg_ptr,
+                                                      const int* __restrict__ bg_row, const int8_t* __restrict__ bg_sg,
+                                                      const double* __restrict__ bg_w, const double* __restrict__ r,
+                                                      const double* __restrict__ Pk, double* __restrict__ y,
+                                                      long long ystride, int cap) {
+    extern __shared__ double sh[];
+    double* xs = sh;             // cap
+    double* ys = sh + cap;       // cap
+    double* red = sh + 2 * cap;  // 16 x 64
+    const int g = blockIdx.x, G = gridDim.x, s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int nb = M.n_b, nT = (nb + 63) >> 6, nt = nT * (nT + 1) / 2;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = 4 * wave + (lane >> 4), jq = lane & 15;
+    for (int q = tid; q < nT * 64; q += 1024) {
+        double v = 0.0;
+        if (q < nb) {
+            const long long gq = M.off_b + q;
+            for (int e = bg_ptr[gq]; e < bg_ptr[gq + 1]; ++e) v += bg_sg[e] * bg_w[e] * r[bg_row[e]];
+        }
+        xs[q] = v;
+        ys[q] = 0.0;
+    }
+    __syncthreads();
+    const int t0 = (int)((long long)g * nt / G), t1 = (int)((long long)(g + 1) * nt / G);
+    const double* T = Pk + M.off_Pk + i * 64 + 4 * jq;
+    auto ld = [&](int t) -> ps4_t {
+        return t < t1 ? *reinterpret_cast<const ps4_t*>(T + (long long)t * 4096) : ps4_t{0.0, 0.0, 0.0, 0.0};
+    };
+    ps4_t ring[kPsRing];
+#pragma unroll
+    for (int d = 0; d < kPsRing; ++d) ring[d] = ld(t0 + d);
+    int J = t0 < t1 ? tri_col(t0) : 0, I = t0 - J * (J + 1) / 2;
+    double ca[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = t0; t < t1; t += kPsRing) {
+#pragma unroll
+        for (int d = 0; d < kPsRing; ++d) {
+            if (t + d < t1) {   // uniform over the workgroup
+                const ps4_t a = ring[d];
+                ring[d] = ld(t + d + kPsRing);
+                // row part: y_I[i] += sum_b S[i][b] x_J[b]
+                const ps4_t xj = *reinterpret_cast<const ps4_t*>(xs + 64 * J + 4 * jq);
+                double rp = ((a[0] * xj[0] + a[1] * xj[1]) + a[2] * xj[2]) + a[3] * xj[3];
+                rp += __shfl_xor(rp, 1);
+                rp += __shfl_xor(rp, 2);
+                rp += __shfl_xor(rp, 4);
+                rp += __shfl_xor(rp, 8);
+                if (jq == 0) ys[64 * I + i] += rp;
+                // column part: y_J[b] += S[i][b] x_I[i]
+                if (I < J) {
+                    const double xi = xs[64 * I + i];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) ca[b] = fma(a[b], xi, ca[b]);
+                }
+                if (I == J || t + d == t1 - 1) {
+                    // sum the column part over the 64 tile rows: lanes of equal jq, then wavefronts
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        ca[b] += __shfl_xor(ca[b], 16);
+                        ca[b] += __shfl_xor(ca[b], 32);
+                    }
+                    if (lane < 16)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) red[wave * 64 + 4 * lane + b] = ca[b];
+                    __syncthreads();
+                    if (tid < 64) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int w = 0; w < 16; ++w) v += red[w * 64 + tid];
+                        ys[64 * J + tid] += v;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) ca[b] = 0.0;
+                }
+                if (++I > J) {
+                    ++J;
+                    I = 0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double* yo = y + (long long)g * ystride + M.off_b;
+    for (int q = tid; q < nb; q += 1024) yo[q] = ys[q];
+}
+
+// y[q] = sum over g < G of ypart[g * n + q], in order
+__global__ void k_precond_sum(long long n, int G, const double* __restrict__ ypart, double* __restrict__ y) {
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    double v = 0.0;
+    for (int g = 0; g < G; ++g) v += ypart[g * n + q];
+    y[q] = v;
+}
+
+void launch_precond_local(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* ypart,
+                          double* y, hipStream_t st) {
+    if (t.nb_tot == 0) return;
+    // about 256 workgroups in all: subdomains split over up to kPsMaxSplit workgroups when few
+    const int G = std::max(1, std::min(kPsMaxSplit, 256 / std::max(1, t.n_sub)));
+    const int cap = (t.max_nb + 63) / 64 * 64;
+    const size_t sh = sizeof(double) * (2 * (size_t)cap + 16 * 64);
+    if (G == 1) {
+        k_precond_sym<<<dim3(1, t.n_sub), 1024, sh, st>>>(t.subs, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, y, 0, cap);
+    } else {
+        k_precond_sym<<<dim3(G, t.n_sub), 1024, sh, st>>>(t.subs, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, ypart,
+                                                          t.nb_tot, cap);
+        k_precond_sum<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, G, ypart, y);
+    }
 }
 
 // Z[row][c] = sum over the row's sides with g(s) == c of sign * w * y_s[j]  (kz = n_groups or 1).
@@ -716,7 +806,9 @@ __global__ void k_precond_scatter(int n_lambda, int kz, int one_column, const in
                                   const double* __restrict__ y, double* __restrict__ Z) {
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (idx >= (long long)n_lambda * kz) return;
-    const int row = (int)(idx / kz), c = (int)(idx % kz);
+    // row = idx / kz without a 64-bit division (kz = 64: one wavefront per row)
+    const int row = kz == 64 ? (int)(idx >> 6) : kz == 1 ? (int)idx : (int)((unsigned long long)idx / (unsigned)kz);
+    const int c = (int)(idx - (long long)row * kz);
     double val = 0.0;
     for (int t = 0; t < 2; ++t) {
         const int s = row_s[2 * row + t];
@@ -728,11 +820,51 @@ __global__ void k_precond_scatter(int n_lambda, int kz, int one_column, const in
     Z[idx] = val;
 }
 
+// kz = 64: a wavefront takes 64 rows; lane l first resolves row r0 + l (its one or two sides:
+// group and sign * w * y_s[j]), then the wavefront writes the 64 rows one after another, lane =
+// column (coalesced 512-byte rows), taking each row's values by shuffle. Same sums, same order.
+__global__ void __launch_bounds__(256) k_precond_scatter64(int n_lambda, const int* __restrict__ row_s,
+                                                           const int* __restrict__ row_j,
+                                                           const int8_t* __restrict__ row_sg,
+                                                           const SubMeta* __restrict__ subs, const double* __restrict__ w,
+                                                           const double* __restrict__ y, double* __restrict__ Z) {
+    const int lane = threadIdx.x & 63;
+    const int r0 = ((blockIdx.x * 256 + threadIdx.x) >> 6) * 64;
+    const int row = r0 + lane;
+    int ga = -1, gb = -1;
+    double va = 0.0, vb = 0.0;
+    if (row < n_lambda) {
+        const int s0 = row_s[2 * row], s1 = row_s[2 * row + 1];
+        if (s0 >= 0) {
+            ga = subs[s0].grp;
+            va = row_sg[2 * row] * w[2 * row] * y[subs[s0].off_b + row_j[2 * row]];
+        }
+        if (s1 >= 0) {
+            gb = subs[s1].grp;
+            vb = row_sg[2 * row + 1] * w[2 * row + 1] * y[subs[s1].off_b + row_j[2 * row + 1]];
+        }
+    }
+    const int nr = min(64, n_lambda - r0);
+    for (int i = 0; i < nr; ++i) {
+        const int gai = __shfl(ga, i), gbi = __shfl(gb, i);
+        const double vai = __shfl(va, i), vbi = __shfl(vb, i);
+        double v = 0.0;
+        if (lane == gai) v += vai;
+        if (lane == gbi) v += vbi;
+        Z[(long long)(r0 + i) * 64 + lane] = v;
+    }
+}
+
 void launch_precond_scatter(const DevTopo& t, int one_column, const double* w, const double* y, double* Z,
                             hipStream_t st) {
     const int kz = one_column ? 1 : t.n_groups;
     const long long n = (long long)t.n_lambda * kz;
     if (n == 0) return;
+    if (kz == 64) {
+        const int nw = (t.n_lambda + 63) / 64;   // wavefronts
+        k_precond_scatter64<<<(nw + 3) / 4, 256, 0, st>>>(t.n_lambda, t.row_s, t.row_j, t.row_sg, t.subs, w, y, Z);
+        return;
+    }
     k_precond_scatter<<<(int)((n + 255) / 256), 256, 0, st>>>(t.n_lambda, kz, one_column, t.row_s, t.row_j, t.row_sg,
                                                               t.subs, w, y, Z);
 }
@@ -791,7 +923,7 @@ __global__ void k_proj_apply(int n_lambda, int k, int nm, const int* __restrict_
                              double* __restrict__ Y) {
     const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (idx >= (long long)n_lambda * k) return;
-    const int row = (int)(idx / k), c = (int)(idx % k);
+    const int row = k == 64 ? (int)(idx >> 6) : (int)((unsigned long long)idx / (unsigned)k), c = (int)(idx - (long long)row * k);
     double val = 0.0;
     for (int t = 0; t < 2; ++t) {
         const int s = row_s[2 * row + t];

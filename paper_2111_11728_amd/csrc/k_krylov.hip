@@ -815,8 +815,8 @@ __global__ void __launch_bounds__(1024) k_colsum64(int nchunk, const double* __r
 
 void launch_gemv_t(int n, int k, const double* A, const double* x, double* part, double* out, hipStream_t st) {
     if (k != 64) throw std::invalid_argument("launch_gemv_t takes 64 columns");
-    // 64 rows per workgroup, up to 1024 workgroups: enough in flight to fill all CUs
-    const int nchunk = std::max(1, std::min(1024, (n + 63) / 64));
+    // at least 64 rows per workgroup, up to 256 workgroups (one per CU)
+    const int nchunk = std::max(1, std::min(256, (n + 63) / 64));
     k_gemv_t64<<<nchunk, 256, 0, st>>>(n, A, x, part);
     k_colsum64<<<1, 1024, 0, st>>>(nchunk, part, out);
 }

@@ -555,9 +555,22 @@ __global__ void k_copy_Sbb(const SubMeta* __restrict__ subs, const double* __res
     }
 }
 
-__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long long n) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
-        dst[e] = (float)src[e];
+// Pk[s]: the leading n_b x n_b block of S (ld n_beta) as its upper triangle in 64x64 tiles, tile
+// (I, J), I <= J, at (J(J+1)/2 + I) * 4096 with element (a, b) = S[64I + a][64J + b], zero past n_b
+__global__ void k_pack_sym(const SubMeta* __restrict__ subs, const double* __restrict__ Sbuf, double* __restrict__ Pk) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int nT = (M.n_b + 63) >> 6;
+    const long long ne = (long long)nT * (nT + 1) / 2 * 4096;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x) {
+        const int t = (int)(e >> 12), a = (int)((e >> 6) & 63), b = (int)(e & 63);
+        int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((J + 1) * (J + 2) / 2 <= t) ++J;
+        while (J * (J + 1) / 2 > t) --J;
+        const int I = t - J * (J + 1) / 2;
+        const int row = 64 * I + a, col = 64 * J + b;
+        Pk[M.off_Pk + e] = (row < M.n_b && col < M.n_b) ? Sbuf[M.off_S + (long long)row * M.n_beta + col] : 0.0;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -965,8 +978,8 @@ void launch_copy_Sbb(const DevTopo& t, const double* S, double* dst, int identit
     k_copy_Sbb<<<dim3(64, t.n_sub), 256, 0, st>>>(t.subs, S, dst, identity);
 }
 
-void launch_to_f32(const double* src, float* dst, long long n, hipStream_t st) {
-    if (n > 0) k_to_f32<<<(int)std::min<long long>((n + 255) / 256, 65535), 256, 0, st>>>(src, dst, n);
+void launch_pack_sym(const DevTopo& t, const double* S, double* Pk, hipStream_t st) {
+    k_pack_sym<<<dim3(64, t.n_sub), 256, 0, st>>>(t.subs, S, Pk);
 }
 
 void launch_tfeti_rbm(const DevTopo& t, const double* S, double* Rb, double* Cit, double* tau, double* W,

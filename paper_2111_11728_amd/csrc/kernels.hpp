@@ -99,7 +99,6 @@ void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* 
 void launch_potrf(const PotrfDesc* d, int nbatch, double* base, int* info, hipStream_t st);
 void launch_trsm(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st);
 void launch_copy_Sbb(const DevTopo& t, const double* S, double* dst, int identity, hipStream_t st);
-void launch_to_f32(const double* src, float* dst, long long n, hipStream_t st);
 void launch_tfeti_rbm(const DevTopo& t, const double* S, double* Rb, double* Cit, double* tau, double* W,
                       hipStream_t st);
 void launch_tfeti_fix(const DevTopo& t, const double* Rb, const double* tau, double* F64, hipStream_t st);
@@ -133,9 +132,13 @@ void launch_fold_coarse(const DevTopo& t, int k, int ytype_f32, const double* F6
                         hipStream_t st);
 // Q[row] = sum over sides sign * Y[b]
 void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, double* Q, hipStream_t st);
-// x_s = B~^sT r gathered and multiplied: y_s = P_s x_s  (P_s FP64 or FP32)
-void launch_precond_local(const DevTopo& t, int use_f32, const double* r, const double* bg_w, const double* P64,
-                          const float* P32, double* y, hipStream_t st);
+// x_s = B~^sT r gathered and multiplied: y_s = P_s x_s, P_s symmetric in packed 64x64 upper tiles;
+// ypart: kPsMaxSplit * nb_tot doubles of workspace (subdomains split over several workgroups)
+constexpr int kPsMaxSplit = 8;
+void launch_precond_local(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* ypart,
+                          double* y, hipStream_t st);
+// Pk (packed upper tiles) <- the leading n_b x n_b block of S (ld n_beta)
+void launch_pack_sym(const DevTopo& t, const double* S, double* Pk, hipStream_t st);
 // Z[row][g(s)] = sum over sides sign * w * y_s[j]; one_column sums into column 0
 void launch_precond_scatter(const DevTopo& t, int one_column, const double* w, const double* y, double* Z,
                             hipStream_t st);

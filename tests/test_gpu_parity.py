@@ -317,6 +317,26 @@ def test_sfeti_64_directions_small_interface():
     ctx.close()
 
 
+def test_pcg_256_subdomains():
+    """16x16 subdomains of 2x2 elements: one preconditioner workgroup per subdomain (the layout
+    of the large configurations) and 256 corner blocks; plain PCG against the oracle."""
+    prob = workloads.cantilever_tfeti(5, nsub=(16, 16), m=2)
+    op = ofeti.FETIDP(prob, "dirichlet", "k")
+    res = okrylov.solve(op, "pcg", tol=1e-10)
+    u_ref, _ = op.recover(res.lam)
+    print(f"case pcg256 n_lambda={op.n_lambda}", flush=True)
+    ctx = _ctx(prob, method="fetidp", scaling="k", krylov="pcg", tol=1e-10)
+    assert ctx.sizes["n_sub"] == 256
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
+    info = ctx.feti_solve(_t(prob.load()), u)
+    assert _rel(u.cpu().numpy(), u_ref) < 1e-8
+    hg = np.asarray(info["history"]) / info["history"][0]
+    ho = np.asarray(res.history) / res.history[0]
+    cross = lambda h: int(np.argmax(h <= 1e-8)) if np.any(h <= 1e-8) else len(h)
+    assert abs(cross(hg) - cross(ho)) <= 1
+    ctx.close()
+
+
 def test_compliance_gradient_small():
     prob = workloads.cantilever_tfeti(3, nsub=(2, 2), m=4)
     print("case compliance", flush=True)
