@@ -139,7 +139,7 @@ def cpu_baseline(prob, gpu_iters, budget_s=30.0):
     est_ms = 1e3 * per_it * scale * gpu_iters
     return {"value": est_ms, "unit": "ms", "cores": int(threads), "kind": "oracle",
             "sample": (f"oracle S-FETI-DP (k-scaling, Dirichlet) on a 4x4 block of the same 64x64-element "
-                       f"subdomains: setup {t_setup:.1f} s, {res.iters} iterations in {t_solve:.1f} s; "
+                       f"subdomains: setup {t_setup:.1f} s, {res.iters} iterations in {1e3 * t_solve:.1f} ms; "
                        f"value = per-iteration time x {scale:.0f} (subdomain ratio) x {gpu_iters} GPU iterations")}
 
 
