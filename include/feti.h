@@ -127,7 +127,17 @@ typedef struct {
     long long device_bytes;   /* device memory held by a context */
     int n_fp64_subs;          /* FETI-DP with a reduced precision: subdomains whose F_s failed the
                                  round-off test at the last setup and run in FP64 */
+    int n_designs;            /* independent designs held by the context (1 unless batched) */
 } feti_sizes;
+
+/* One design of a batched context: its ranges in the concatenated arrays. */
+typedef struct {
+    long long el0, n_el;      /* densities and gradient: [el0, el0 + n_el) */
+    long long dof0, n_dof;    /* loads and displacements: [dof0, dof0 + n_dof) */
+    int sub0, n_sub;          /* subdomains */
+    int lam0, n_lambda;       /* dual unknowns (rows of the multiplier vector) */
+    int n_groups;             /* S-FETI direction groups of this design */
+} feti_design;
 
 /* Builds the integer topology only (no device work) and reports the interface sizes.
  * Host-only; usable without a GPU. */
@@ -154,6 +164,27 @@ feti_status feti_setup(const feti_mesh* mesh, const feti_partition* part, const 
                        const double* rho, double p, double E0, double Emin,
                        void* stream, feti_ctx** out);
 
+/* Several independent designs in one context (their disjoint union as one decomposition):
+ * every launch of setup and of the Krylov loop covers all designs at once, the FETI-DP coarse
+ * matrix is block diagonal (one dense block per design) and the solve stops when every design
+ * has reached tol in its own relative preconditioned residual. meshes/parts: host arrays of
+ * n_designs entries (same dimension and Poisson ratio; FETI-DP only). rho, and the f, u,
+ * dc_drho of later calls, concatenate the designs in order (offsets: feti_design_layout);
+ * feti_compliance_and_grad writes one compliance per design (c: device [n_designs]).
+ * S-FETI uses the union of the designs' direction groups (64 at most): each design searches
+ * along its own groups, and since F couples no two designs the simultaneous directions of
+ * different designs stay F-orthogonal. */
+feti_status feti_setup_batched(int n_designs, const feti_mesh* meshes, const feti_partition* parts,
+                               const feti_opts* opts, const double* rho, double p, double E0, double Emin,
+                               void* stream, feti_ctx** out);
+
+/* Ranges of design d (0 <= d < n_designs) in the concatenated arrays. */
+feti_status feti_design_layout(feti_ctx* ctx, int d, feti_design* out);
+
+/* Host out[n_designs]: each design's true relative residual sqrt(r_d^T M r_d) / eps0_d after the
+ * last solve (r_d = the design's rows of d - F lambda, FP64). */
+feti_status feti_design_residuals(feti_ctx* ctx, double* out, int cap);
+
 /* Same topology, new densities: repeats assembly, factorisation and operator formation. */
 feti_status feti_update_rho(feti_ctx* ctx, const double* rho);
 
@@ -167,7 +198,8 @@ feti_status feti_solve(feti_ctx* ctx, const double* f, double* u, const double* 
                        feti_info* info);
 
 /* Compliance c = f^T u and its gradient dc/drho_e = -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e
- * (self-adjoint), after feti_update_rho(rho) and feti_solve(f).
+ * (self-adjoint), after feti_update_rho(rho) and feti_solve(f). A batched context writes one
+ * compliance per design (c: device [n_designs]).
  * rho: device [n_el] or NULL (keep the current densities); f: device [n_dof] or NULL
  * (reuse the last load); c: device scalar; dc_drho: device [n_el]; u: device [n_dof] or NULL. */
 feti_status feti_compliance_and_grad(feti_ctx* ctx, const double* rho, const double* f,
@@ -206,7 +238,8 @@ feti_status feti_rhs(feti_ctx* ctx, const double* f, double* d, double* lambda0)
 /* Copies one local matrix of subdomain s to host memory (for checking against the
  * oracle). what: 0 = F_s [n_b x n_b]; 1 = S~^s preconditioner block [n_b x n_b];
  * 2 = F_rc^s [n_b x n_c]; 3 = Kbar_cc^s [n_c x n_c]; 4 = scaling weight of every lambda row on
- * each side [n_lambda x 2] (s ignored); 5 = global Kbar_cc [n_cg x n_cg] (s ignored);
+ * each side [n_lambda x 2] (s ignored); 5 = the assembled Kbar_cc of design s [n_cg x n_cg of that
+ * design] (s = 0 for a single design: the whole coarse matrix);
  * 6 = diagonal of K^s [n_loc]. out: host, capacity cap doubles; rows/cols: host, receive the shape. */
 feti_status feti_get_local(feti_ctx* ctx, int s, int what, double* out, long long cap,
                            int* rows, int* cols);

@@ -33,3 +33,32 @@ class Compliance(torch.autograd.Function):
 def compliance(rho: torch.Tensor, fctx: Context, f: torch.Tensor) -> torch.Tensor:
     """c(rho) with autograd support (gradient w.r.t. rho only)."""
     return Compliance.apply(rho, fctx, f)
+
+
+class BatchedCompliance(torch.autograd.Function):
+    """Compliances c_d(rho) of the designs of a batched context (one entry per design); rho and
+    the gradient concatenate the designs. Backward scales each design's gradient block by its
+    own upstream gradient."""
+
+    @staticmethod
+    def forward(ctx, rho: torch.Tensor, fctx, f: torch.Tensor) -> torch.Tensor:
+        if rho.dtype != torch.float64 or f.dtype != torch.float64:
+            raise TypeError("rho and f must be float64")
+        rho_c = rho.detach().contiguous()
+        nd = len(fctx.layout)
+        c = torch.zeros(nd, dtype=torch.float64, device=rho.device)
+        g = torch.empty_like(rho_c)
+        fctx.feti_compliance_and_grad(rho_c, f.contiguous(), c, g)
+        counts = torch.tensor([lay["n_el"] for lay in fctx.layout], device=rho.device)
+        ctx.save_for_backward(g, counts)
+        return c
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        g, counts = ctx.saved_tensors
+        return torch.repeat_interleave(grad_c, counts) * g, None, None
+
+
+def batched_compliance(rho: torch.Tensor, fctx, f: torch.Tensor) -> torch.Tensor:
+    """[c_d(rho)] over the designs of a BatchedContext, with autograd support."""
+    return BatchedCompliance.apply(rho, fctx, f)

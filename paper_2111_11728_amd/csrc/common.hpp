@@ -23,6 +23,8 @@ struct SubMeta {
     int ldF;            // leading dimension (columns) of the row-major F_s storage, n_b rounded up to 16
     int rows_F;         // rows of the augmented operator [F_s; F_rc^T]: n_b + n_c rounded up to 16
     int rowT;           // first row of F_rc^T (= n_b: the corner rows follow F_s directly)
+    int nelx, nely;     // element grid of the subdomain's design (its global element numbering)
+    long long el0;      // first element of the subdomain's design in the density array
     long long off_loc, off_i, off_b, off_c;   // prefix offsets of the per-DOF arrays
     long long line0;    // first entry of this subdomain in the line table
     long long off_L;    // block-tridiagonal factor storage (doubles)

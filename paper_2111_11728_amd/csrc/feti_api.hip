@@ -129,6 +129,13 @@ struct feti_ctx {
     __hip_bfloat16 *swhi = nullptr, *swlo = nullptr;
     double *Pk = nullptr, *W1 = nullptr, *W2 = nullptr, *ypart = nullptr;
     double *Kc = nullptr, *Kcc = nullptr, *Kcc_w = nullptr, *Kcc_inv = nullptr;
+    // designs held by the context (one, or several independent ones as a disjoint union)
+    std::vector<DesignMeta> designs;
+    std::vector<CoarseBlk> hcblk;
+    GemmDesc* d_cc_gemm = nullptr;
+    PotrfDesc* d_cc_potrf = nullptr;
+    TrsmDesc* d_cc_trsm = nullptr;
+    std::vector<double> eps0_d, true_d;   // per design: initial and last true preconditioned residual
     double *Rb = nullptr, *Cit = nullptr, *tau = nullptr, *GG = nullptr, *GG_w = nullptr, *GG_inv = nullptr;
     double *w = nullptr, *bg_w = nullptr;
     int* info = nullptr;
@@ -240,6 +247,26 @@ std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, in
 void build_layout(feti_ctx* c) {
     Plan& P = c->P;
     const int ns = P.n_sub;
+    if (c->designs.empty()) {   // a single design: the whole plan
+        DesignMeta D;
+        D.n_sub = ns;
+        D.n_el = P.n_el;
+        D.n_nodes = P.n_nodes;
+        D.n_dof = P.n_dof;
+        D.n_lambda = P.n_lambda;
+        D.n_cg = P.n_cg;
+        D.n_groups = P.n_groups;
+        for (int a = 0; a < 3; ++a) {
+            D.nel[a] = P.nel[a];
+            D.nsub[a] = P.nsub[a];
+            D.ax_first[a] = P.ax_first[a];
+            D.ax_cnt[a] = P.ax_cnt[a];
+        }
+        c->designs.push_back(D);
+    }
+    std::vector<int> sub_design(ns, 0);
+    for (int d = 0; d < (int)c->designs.size(); ++d)
+        for (int s = 0; s < c->designs[d].n_sub; ++s) sub_design[c->designs[d].sub0 + s] = d;
     c->hsubs.assign(ns, SubMeta{});
     c->hlines.clear();
     long long oL = 0, oZ = 0, oS = 0, oF = 0, oP = 0, oPk = 0, oKc = 0, oR = 0, oLi = 0;
@@ -250,6 +277,12 @@ void build_layout(feti_ctx* c) {
         for (int a = 0; a < 3; ++a) {
             M.lo[a] = P.lo[3 * s + a];
             M.nn[a] = P.nn[3 * s + a];
+        }
+        {
+            const DesignMeta& D = c->designs[sub_design[s]];
+            M.nelx = D.nel[0];
+            M.nely = D.nel[1];
+            M.el0 = D.el0;
         }
         M.n_loc = P.n_loc[s];
         M.n_i = P.n_i[s];
@@ -354,9 +387,47 @@ void build_layout(feti_ctx* c) {
     c->rho = c->alloc<double>(P.n_el);
     c->info = c->alloc<int>(ns + 8);
     const int ncg = P.n_cg;
-    c->Kcc = c->alloc<double>((long long)ncg * ncg);
-    c->Kcc_w = c->alloc<double>((long long)ncg * ncg);
-    c->Kcc_inv = c->alloc<double>((long long)ncg * ncg);
+    // Kbar_cc: one dense block per design, 16-row tiles for the coarse solve
+    long long kcc_sz = 0;
+    c->hcblk.clear();
+    std::vector<int> cg_blk(std::max(1, ncg), 0);
+    std::vector<CoarseTile> ctiles;
+    for (const DesignMeta& D : c->designs) {
+        if (D.n_cg == 0) continue;
+        const int b = (int)c->hcblk.size();
+        c->hcblk.push_back(CoarseBlk{D.cg0, D.n_cg, kcc_sz});
+        kcc_sz += (long long)D.n_cg * D.n_cg;
+        for (int q = 0; q < D.n_cg; ++q) cg_blk[D.cg0 + q] = b;
+        for (int r0 = 0; r0 < D.n_cg; r0 += 16) ctiles.push_back(CoarseTile{b, r0});
+    }
+    c->Kcc = c->alloc<double>(std::max(1LL, kcc_sz));
+    c->Kcc_w = c->alloc<double>(std::max(1LL, kcc_sz));
+    c->Kcc_inv = c->alloc<double>(std::max(1LL, kcc_sz));
+    if (!c->hcblk.empty()) {
+        std::vector<GemmDesc> gd;
+        std::vector<PotrfDesc> pd;
+        std::vector<TrsmDesc> td;
+        for (const CoarseBlk& B : c->hcblk) {
+            gd.push_back(GemmDesc{B.off, B.off, B.off, B.n, B.n, B.n, B.n, B.n, B.n});
+            pd.push_back(PotrfDesc{B.off, B.n, B.n});
+            td.push_back(TrsmDesc{B.off, B.off, B.n, B.n, B.n, B.n});
+        }
+        c->d_cc_gemm = c->upload(gd);
+        c->d_cc_potrf = c->upload(pd);
+        c->d_cc_trsm = c->upload(td);
+        t.cblk = c->upload(c->hcblk);
+        t.ctiles = c->upload(ctiles);
+        t.n_ctiles = (int)ctiles.size();
+    }
+    t.cg_blk = c->upload(cg_blk);
+    {
+        std::vector<int> seg;
+        for (const DesignMeta& D : c->designs) {
+            seg.push_back(D.lam0);
+            seg.push_back(D.n_lambda);
+        }
+        t.seg = c->upload(seg);
+    }
     const int na = c->n_alpha;
     c->GG = c->alloc<double>((long long)na * na);
     c->GG_w = c->alloc<double>((long long)na * na);
@@ -440,6 +511,24 @@ void build_layout(feti_ctx* c) {
         t.ax_first[a] = c->upload(P.ax_first[a]);
         t.ax_cnt[a] = c->upload(P.ax_cnt[a]);
     }
+    t.dsg.clear();
+    for (const DesignMeta& D : c->designs) {
+        DesignDev E;
+        E.sub0 = D.sub0;
+        E.lam0 = D.lam0;
+        E.n_lambda = D.n_lambda;
+        E.el0 = D.el0;
+        E.n_el = D.n_el;
+        E.dof0 = D.dof0;
+        E.n_dof = D.n_dof;
+        for (int a = 0; a < 3; ++a) {
+            E.nel[a] = D.nel[a];
+            E.nsub[a] = D.nsub[a];
+            E.axf[a] = c->upload(D.ax_first[a]);
+            E.axc[a] = c->upload(D.ax_cnt[a]);
+        }
+        t.dsg.push_back(E);
+    }
     t.fl64 = FlTiles{c->upload(tiles64), (int)tiles64.size()};
     t.flred = FlTiles{c->upload(tilesred), (int)tilesred.size()};
     c->pivdev = c->alloc<double>(ns);
@@ -488,9 +577,12 @@ void build_layout(feti_ctx* c) {
     c->Tm = c->alloc<double>(kMaxDirs * kMaxDirs);
     c->gam = c->alloc<double>(kMaxDirs);
     c->part = c->alloc<double>(kGramPartCap);
-    c->scal = c->alloc<double>(16);
+    const int nd = (int)c->designs.size();
+    c->scal = c->alloc<double>(16 + nd);   // [16 + d]: per-design dots (several designs)
     c->rank_dev = reinterpret_cast<int*>(c->scal + 8);
-    HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(double) * 16, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(double) * (16 + nd), hipHostMallocDefault));
+    c->eps0_d.assign(nd, 0.0);
+    c->true_d.assign(nd, 0.0);
     c->qk_ptr = c->upload(std::vector<const double*>{c->Qk});
     c->zk_ptr = c->upload(std::vector<const double*>{c->Zk});
     c->tcbuf = c->alloc<double>((long long)std::max(1, ncg) * kMaxDirs);
@@ -607,6 +699,29 @@ void dense_spd_inverse(feti_ctx* c, int n, const double* A, double* work, double
     HIPCHK(hipMemcpyAsync(Ainv, work, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c->st));
 }
 
+// Kbar_cc^{-1}, block by block (one dense block per design): Cholesky, L^{-1} by a triangular
+// solve on the identity, then L^{-T} L^{-1}, each step one batched launch over the blocks.
+void coarse_inverse(feti_ctx* c) {
+    const std::vector<CoarseBlk>& B = c->hcblk;
+    const int nb = (int)B.size();
+    if (nb == 0) return;
+    const long long sz = B.back().off + (long long)B.back().n * B.back().n;
+    int maxn = 0;
+    for (const CoarseBlk& b : B) maxn = std::max(maxn, b.n);
+    hipStream_t st = c->st;
+    HIPCHK(hipMemcpyAsync(c->Kcc_w, c->Kcc, sizeof(double) * sz, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * nb, st));
+    launch_potrf(c->d_cc_potrf, nb, c->Kcc_w, c->info, st);
+    CHECK_LAUNCH();
+    check_info(c, nb, "coarse Cholesky");
+    for (const CoarseBlk& b : B) launch_set_identity(c->Kcc_inv + b.off, b.n, b.n, st);
+    launch_trsm(c->d_cc_trsm, nb, maxn, c->Kcc_w, c->Kcc_inv, st);
+    launch_gemm_tn(c->d_cc_gemm, nb, ((maxn + 63) / 64) * ((maxn + 63) / 64), c->Kcc_inv, c->Kcc_inv, c->Kcc_w, 1.0,
+                   0.0, 1, st);
+    CHECK_LAUNCH();
+    HIPCHK(hipMemcpyAsync(c->Kcc_inv, c->Kcc_w, sizeof(double) * sz, hipMemcpyDeviceToDevice, st));
+}
+
 // Assembly, factorisation and explicit local operators for the current densities.
 void numeric_setup(feti_ctx* c) {
     Timer tm(c, 2);
@@ -668,10 +783,11 @@ void numeric_setup(feti_ctx* c) {
     CHECK_LAUNCH();
     classify_precision(c);
     if (P.method == FETI_DP && P.n_cg > 0) {
-        zero(c->Kcc, (long long)P.n_cg * P.n_cg * 8);
+        const CoarseBlk& last = c->hcblk.back();
+        zero(c->Kcc, (last.off + (long long)last.n * last.n) * 8);
         launch_coarse_assemble(t, c->Kc, c->Kcc, st);
         CHECK_LAUNCH();
-        dense_spd_inverse(c, P.n_cg, c->Kcc, c->Kcc_w, c->Kcc_inv, "coarse Cholesky");
+        coarse_inverse(c);
     }
     if (P.method == FETI_TFETI && c->n_alpha > 0) {
         zero(c->GG, (long long)c->n_alpha * c->n_alpha * 8);
@@ -742,6 +858,25 @@ double read_scalar(feti_ctx* c, const double* dptr) {
     wait_poll(c);
     v = c->hpin[0];
     return v;
+}
+
+// scal[0 .. 16 + designs) to the host; returns scal[0]
+double read_scalars(feti_ctx* c) {
+    HIPCHK(hipMemcpyAsync(c->hpin, c->scal, sizeof(double) * (16 + c->designs.size()), hipMemcpyDeviceToHost, c->st));
+    wait_poll(c);
+    return c->hpin[0];
+}
+
+// Convergence with several designs is per design: each ratio sqrt(r_d^T z_d) / eps0_d (from
+// the segmented dots in scal[16 + d], read by the last read_scalars) must reach tol; with one
+// design it is the plain eps <= tol eps0.
+bool converged(feti_ctx* c, double eps, double eps0, double tol) {
+    if (c->designs.size() <= 1) return eps <= tol * eps0;
+    for (size_t d = 0; d < c->designs.size(); ++d) {
+        const double e0 = c->eps0_d[d];
+        if (e0 > 0.0 && !(std::sqrt(std::max(c->hpin[16 + d], 0.0)) <= tol * e0)) return false;
+    }
+    return true;
 }
 
 // dot(a, b) of n-vectors into c->scal[slot]
@@ -933,9 +1068,10 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
     HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     project(c, 1, c->Zk);  // w = P z
     ddot(c, n, c->r, c->zv, 0);
-    double rz = read_scalar(c, c->scal);
+    launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+    double rz = read_scalars(c);
     o.eps = std::sqrt(std::max(rz, 0.0));
-    if (o.eps <= tol * eps0) return o;
+    if (converged(c, o.eps, eps0, tol)) return o;
     bool replaced = false;
     for (int it = 0; it < max_it; ++it) {
         const int p_it = gated_apply(c, g, replaced, o.eps, eps0, 1, c->Zk, c->Qk, c->Qtmp);
@@ -952,12 +1088,13 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
         launch_axpby(n, -a, c->Qk, 1.0, c->r, st);
         precondition(c, c->r, c->zv, 1, 0);
         ddot(c, n, c->r, c->zv, 0);
-        const double rz_new = read_scalar(c, c->scal);
+        launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+        const double rz_new = read_scalars(c);
         o.iters = it + 1;
         o.eps = std::sqrt(std::max(rz_new, 0.0));
         hist.push_back(o.eps);
         if (verbose()) fprintf(stderr, "[feti] pcg it %d prec %d eps/eps0 %.3e\n", it + 1, p_it, o.eps / eps0);
-        if (o.eps <= tol * eps0) {
+        if (converged(c, o.eps, eps0, tol)) {
             if (o.reduced == 0 || replaced) break;
             // residual replacement after reduced-precision products; PCG restarts from it
             replaced = true;
@@ -965,10 +1102,11 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
             true_residual(c, c->tmpv, c->r);
             precondition(c, c->r, c->zv, 1, 0);
             ddot(c, n, c->r, c->zv, 0);
-            rz = read_scalar(c, c->scal);
+            launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+            rz = read_scalars(c);
             o.eps = std::sqrt(std::max(rz, 0.0));
             if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
-            if (o.eps <= tol * eps0) break;
+            if (converged(c, o.eps, eps0, tol)) break;
             HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
             project(c, 1, c->Zk);
             CHECK_LAUNCH();
@@ -991,13 +1129,26 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
     const int one = kd == 1;
+    const bool multi = c->designs.size() > 1 && kd == c->P.n_groups;
     const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
     const int passes = c->opts.reorth == 2 ? 2 : 1;
     precondition(c, c->r, c->Zk, one, 0);
     launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
-    o.eps = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
-    if (o.eps <= tol * eps0) return o;
+    launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
+    o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
+    if (converged(c, o.eps, eps0, tol)) return o;
     project(c, kd, c->Zk);  // W_0 = P Z_0 (in place)
+    // several designs: each stops searching (its direction columns are zeroed) once it has
+    // converged or its kept directions span its own dual space, as a single design would
+    const int nds = (int)c->designs.size();
+    std::vector<unsigned long long> gmask(nds, 0);
+    std::vector<int> kept_d(nds, 0);
+    unsigned long long all_mask = 0, frozen = 0;
+    if (multi)
+        for (int d = 0; d < nds; ++d) {
+            for (int g = 0; g < c->designs[d].n_groups; ++g) gmask[d] |= 1ull << (c->designs[d].grp0 + g);
+            all_mask |= gmask[d];
+        }
     int nb = 0;
     double best = o.eps;
     int it_best = 0;
@@ -1010,7 +1161,8 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         o.reduced += p_it != FETI_FP64;
         // Delta = Q^T W
         launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
-        launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st);
+        launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st,
+                       multi ? reinterpret_cast<unsigned long long*>(c->scal + 9) : nullptr);
         launch_ts_pair(n, kd, c->zk_ptr, c->qk_ptr, c->Tm, Wn, Qn, st);
         // gamma = W^T r
         if (kd == 64)
@@ -1030,6 +1182,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         ++nb;
         precondition(c, c->r, c->Zk, one, 0);
         launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
+        launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
         project(c, kd, c->Zk);
         for (int pass = 0; pass < passes; ++pass) {
             launch_gram(n, kd, kd, c->QH_dev, nb, c->Zk, c->part, c->Psi, st);
@@ -1037,7 +1190,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         }
         CHECK_LAUNCH();
         // eps^2 (scal[0]) and the rank (scal[8]) in one copy
-        HIPCHK(hipMemcpyAsync(c->hpin, c->scal, 9 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(c->hpin, c->scal, (16 + c->designs.size()) * sizeof(double), hipMemcpyDeviceToHost, st));
         wait_poll(c);
         const double ez = c->hpin[0];
         int rank = 0;
@@ -1054,7 +1207,20 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         o.kept += rank;
         o.eps = std::sqrt(std::max(ez, 0.0));
         hist.push_back(o.eps);
-        const bool conv = o.eps <= tol * eps0;
+        if (multi) {
+            unsigned long long km = 0;
+            std::memcpy(&km, c->hpin + 9, sizeof(km));
+            for (int d = 0; d < nds; ++d) {
+                if (frozen & gmask[d]) continue;
+                kept_d[d] += __builtin_popcountll(km & gmask[d]);
+                const bool cd = !(c->eps0_d[d] > 0.0) ||
+                                std::sqrt(std::max(c->hpin[16 + d], 0.0)) <= tol * c->eps0_d[d];
+                if (cd || kept_d[d] >= c->designs[d].n_lambda) frozen |= gmask[d];
+            }
+            if (frozen == all_mask && !converged(c, o.eps, eps0, tol)) break;   // every design done
+            launch_zero_cols(n, kd, frozen, c->Zk, st);
+        }
+        const bool conv = converged(c, o.eps, eps0, tol);
         if (o.eps < 0.9 * best) {
             best = o.eps;
             it_best = it;
@@ -1076,9 +1242,10 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             true_residual(c, c->tmpv, c->r);
             precondition(c, c->r, c->Zk, one, 0);
             launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
-            o.eps = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
+            launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
+            o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
             if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
-            if (o.eps <= tol * eps0) break;
+            if (converged(c, o.eps, eps0, tol)) break;
             project(c, kd, c->Zk);
             for (int pass = 0; pass < passes; ++pass) {
                 launch_gram(n, kd, kd, c->QH_dev, nb, c->Zk, c->part, c->Psi, st);
@@ -1152,7 +1319,10 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         // eps0 = sqrt(r0^T z0) with the FP64 preconditioner
         precondition(c, c->r, c->zv, 1, 0);
         ddot(c, n, c->r, c->zv, 0);
-        eps0 = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
+        launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+        eps0 = std::sqrt(std::max(read_scalars(c), 0.0));
+        for (size_t d = 0; d < c->designs.size(); ++d)
+            c->eps0_d[d] = c->designs.size() > 1 ? std::sqrt(std::max(c->hpin[16 + d], 0.0)) : eps0;
         hist.push_back(eps0);
         const double tol = c->opts.tol > 0 ? c->opts.tol : 1e-8;
         int max_it = c->opts.max_it > 0 ? c->opts.max_it : n;
@@ -1183,8 +1353,18 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
                 true_residual(c, c->lam, c->r);
                 precondition(c, c->r, c->zv, 1, 0);
                 ddot(c, n, c->r, c->zv, 0);
-                const double et = std::sqrt(std::max(read_scalar(c, c->scal), 0.0));
+                launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+                const double et = std::sqrt(std::max(read_scalars(c), 0.0));
                 true_rel = et / eps0;
+                if (c->designs.size() > 1) {   // the worst design
+                    true_rel = 0.0;
+                    for (size_t d = 0; d < c->designs.size(); ++d) {
+                        c->true_d[d] = std::sqrt(std::max(c->hpin[16 + d], 0.0));
+                        if (c->eps0_d[d] > 0.0) true_rel = std::max(true_rel, c->true_d[d] / c->eps0_d[d]);
+                    }
+                } else {
+                    c->true_d[0] = et;
+                }
                 if (verbose())
                     fprintf(stderr, "[feti] pass %d prec %d iters %d status %d true rel. residual %.3e\n", pass, cur,
                             o.iters, o.status, true_rel);
@@ -1374,6 +1554,63 @@ feti_status feti_setup(const feti_mesh* mesh, const feti_partition* part, const 
     return FETI_OK;
 }
 
+feti_status feti_setup_batched(int n_designs, const feti_mesh* meshes, const feti_partition* parts,
+                               const feti_opts* opts, const double* rho, double p, double E0, double Emin,
+                               void* stream, feti_ctx** out) {
+    if (!out) return fail(FETI_EINVAL, "null output");
+    *out = nullptr;
+    if (n_designs < 1 || !meshes || !parts) return fail(FETI_EINVAL, "need at least one design");
+    feti_status vs = validate_opts(opts);
+    if (vs != FETI_OK) return vs;
+    if (opts->method != FETI_DP) return fail(FETI_EINVAL, "batched designs need FETI-DP");
+    if (!(p >= 1.0) || !(E0 > 0.0) || !(Emin > 0.0) || !(Emin < E0))
+        return fail(FETI_EINVAL, "need p >= 1 and 0 < Emin < E0");
+    if (!rho) return fail(FETI_EINVAL, "null density array");
+    std::unique_ptr<feti_ctx> c(new feti_ctx());
+    std::string err = build_plan_batched(n_designs, meshes, parts, opts, c->P, c->designs);
+    if (!err.empty()) return fail(FETI_EINVAL, err);
+    if (opts->krylov == FETI_SFETI && c->P.n_groups > kMaxDirs)
+        return fail(FETI_EINVAL, "more than 64 simultaneous directions over all designs: set partition.group");
+    c->opts = *opts;
+    c->p = p;
+    c->E0 = E0;
+    c->Emin = Emin;
+    c->st = (hipStream_t)stream;
+    feti_status rs = guarded([&]() -> feti_status {
+        build_layout(c.get());
+        HIPCHK(hipMemcpyAsync(c->rho, rho, sizeof(double) * c->P.n_el, hipMemcpyDeviceToDevice, c->st));
+        numeric_setup(c.get());
+        return FETI_OK;
+    });
+    if (rs != FETI_OK) return rs;
+    *out = c.release();
+    return FETI_OK;
+}
+
+feti_status feti_design_layout(feti_ctx* c, int d, feti_design* out) {
+    if (!c || !out) return fail(FETI_EINVAL, "null argument");
+    if (d < 0 || d >= (int)c->designs.size()) return fail(FETI_EINVAL, "design index out of range");
+    const DesignMeta& D = c->designs[d];
+    out->el0 = D.el0;
+    out->n_el = D.n_el;
+    out->dof0 = D.dof0;
+    out->n_dof = D.n_dof;
+    out->sub0 = D.sub0;
+    out->n_sub = D.n_sub;
+    out->lam0 = D.lam0;
+    out->n_lambda = D.n_lambda;
+    out->n_groups = D.n_groups;
+    return FETI_OK;
+}
+
+feti_status feti_design_residuals(feti_ctx* c, double* out, int cap) {
+    if (!c || !out) return fail(FETI_EINVAL, "null argument");
+    if (cap < (int)c->designs.size()) return fail(FETI_EINVAL, "output smaller than the number of designs");
+    for (size_t d = 0; d < c->designs.size(); ++d)
+        out[d] = c->eps0_d[d] > 0.0 ? c->true_d[d] / c->eps0_d[d] : 0.0;
+    return FETI_OK;
+}
+
 feti_status feti_update_rho(feti_ctx* c, const double* rho) {
     if (!c || !rho) return fail(FETI_EINVAL, "null argument");
     return guarded([&]() -> feti_status {
@@ -1432,6 +1669,7 @@ feti_status feti_get_sizes(feti_ctx* c, feti_sizes* out) {
     z.sum_nb_nc = P.sum_nb_nc();
     z.device_bytes = c->bytes;
     z.n_fp64_subs = c->n_fp64_subs;
+    z.n_designs = (int)c->designs.size();
     *out = z;
     return FETI_OK;
 }
@@ -1545,8 +1783,14 @@ feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long 
             nc = 2;
             fetch(c->w, 2ll * P.n_lambda);
         } else if (what == 5) {
-            nr = nc = P.n_cg;
-            fetch(c->Kcc, (long long)P.n_cg * P.n_cg);
+            // the coarse matrix of design s (its dense diagonal block)
+            if (s >= (int)c->designs.size()) throw std::invalid_argument("design index out of range");
+            const DesignMeta& D = c->designs[s];
+            nr = nc = D.n_cg;
+            long long off = 0;
+            for (const CoarseBlk& b : c->hcblk)
+                if (b.cg0 == D.cg0 && b.n == D.n_cg) off = b.off;
+            fetch(c->Kcc + off, (long long)D.n_cg * D.n_cg);
         } else if (what == 6) {
             const SubMeta& M = c->hsubs[s];
             nr = M.n_loc;

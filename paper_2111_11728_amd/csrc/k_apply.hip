@@ -526,16 +526,24 @@ __global__ void k_coarse_t(int n_cg, int k, const TT* __restrict__ T, const doub
 // v = scale * Kinv t (n_cg x n_cg by n_cg x k, k <= 64) on the FP64 matrix cores: workgroup =
 // 16 rows of v, wavefront w = columns 16w..16w+15. Step Q contracts q = 16Q + 4g + s, so lane
 // (m, g) reads Kinv[p0 + m][16Q + 4g .. +3] (one 32-byte load) and t[16Q + 4g + s][16w + m].
-__global__ void __launch_bounds__(1024) k_coarse_v(int n_cg, int k, const double* __restrict__ t,
-                                                   const double* __restrict__ Kinv, double scale, double* __restrict__ v) {
-    // workgroup: 16 rows of v; wavefront (cg, ks) = (w mod 4, w / 4): columns 16 cg..16 cg + 15 and
-    // the 16-wide contraction slices Q = ks (mod 4), three slices of loads in flight; the four
-    // partial tiles are summed in LDS in a fixed order
+__global__ void __launch_bounds__(1024) k_coarse_v(const CoarseTile* __restrict__ tiles,
+                                                   const CoarseBlk* __restrict__ blks, int k, const double* __restrict__ tg,
+                                                   const double* __restrict__ Kg, double scale, double* __restrict__ vg) {
+    // workgroup: 16 rows of v inside one design's block (v_B = Kbar_B^{-1} t_B); wavefront
+    // (cg, ks) = (w mod 4, w / 4): columns 16 cg..16 cg + 15 and the 16-wide contraction slices
+    // Q = ks (mod 4), three slices of loads in flight; the four partial tiles are summed in LDS in
+    // a fixed order
     typedef double v4 __attribute__((ext_vector_type(4)));
     __shared__ double red[4][16][64];
+    const CoarseTile T = tiles[blockIdx.x];
+    const CoarseBlk B = blks[T.blk];
+    const int n_cg = B.n;
+    const double* __restrict__ Kinv = Kg + B.off;
+    const double* __restrict__ t = tg + (long long)B.cg0 * k;
+    double* __restrict__ v = vg + (long long)B.cg0 * k;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
     const int cg = wave & 3, ks = wave >> 2;
-    const int p0 = blockIdx.x * 16, col = 16 * cg + m;
+    const int p0 = T.r0, col = 16 * cg + m;
     const int prow = p0 + m;
     const int nQ = (n_cg + 15) >> 4;
     const bool vec = (n_cg & 3) == 0;
@@ -593,7 +601,7 @@ void launch_coarse(const DevTopo& t, int k, int ytype_f32, const void* T, const 
     else
         k_coarse_t<double><<<(int)((n + 255) / 256), 256, 0, st>>>(t.n_cg, k, (const double*)T, add, t.cc_ptr,
                                                                    t.cc_s, t.cc_j, t.subs, tbuf);
-    k_coarse_v<<<(t.n_cg + 15) / 16, 1024, 0, st>>>(t.n_cg, k, tbuf, Kinv, scale, v);
+    k_coarse_v<<<t.n_ctiles, 1024, 0, st>>>(t.ctiles, t.cblk, k, tbuf, Kinv, scale, v);
 }
 
 // Y_s[j][c] += sum_q F_rc^s[j][q] v[cg(s,q)][c]  (the coarse correction folded into the local

@@ -658,7 +658,8 @@ __device__ __forceinline__ void put64(double (&a)[64], int p, double v) {
 // t_q[l]); they meet once per step at a barrier, both loops running the same number of
 // barriers (each leaves after reading the same stop mark p_s[m] < 0).
 __global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict__ D, double rr_tol,
-                                                 double* __restrict__ T, int* __restrict__ rank_out) {
+                                                 double* __restrict__ T, int* __restrict__ rank_out,
+                                                 unsigned long long* __restrict__ mask_out) {
     __shared__ __attribute__((aligned(16))) double Lm[64][66];    // Lm[m][i]: entry i of factor column m
     __shared__ __attribute__((aligned(16))) double LmT[64][66];   // LmT[i][m] = Lm[m][i]
     __shared__ double scs[64];
@@ -746,12 +747,32 @@ __global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict
             for (int j = 0; j < 64; ++j)
                 if (j < k) T[l * k + j] = j < rank ? s * x[j] : 0.0;
         }
-        if (l == 0) *rank_out = rank;
+        if (l == 0) {
+            *rank_out = rank;
+            if (mask_out) {   // bit j: column j was taken as a pivot (kept)
+                unsigned long long msk = 0;
+                for (int q = 0; q < rank; ++q) msk |= 1ull << p_s[q];
+                *mask_out = msk;
+            }
+        }
     }
 }
 
-void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st) {
-    k_pivchol<<<1, 128, 0, st>>>(k, D, rr_tol, T, rank);
+void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st,
+                    unsigned long long* kept_mask) {
+    k_pivchol<<<1, 128, 0, st>>>(k, D, rr_tol, T, rank, kept_mask);
+}
+
+// Z[row][c] = 0 for every column c with bit c of mask set (n x k, k <= 64)
+__global__ void k_zero_cols(long long n, int k, unsigned long long mask, double* __restrict__ Z) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= n * k) return;
+    const int c = (int)(e % k);
+    if ((mask >> c) & 1ull) Z[e] = 0.0;
+}
+
+void launch_zero_cols(long long n, int k, unsigned long long mask, double* Z, hipStream_t st) {
+    if (mask && n) k_zero_cols<<<(int)((n * k + 255) / 256), 256, 0, st>>>(n, k, mask, Z);
 }
 
 // Wo = W T, Qo = Q T (n x k by k x k), 4 rows x 64 columns per workgroup step.
@@ -951,6 +972,32 @@ void launch_diff_norms(long long len, const double* a, const double* b, double* 
     k_diff_norms<<<nb, 256, 0, st>>>(len, a, b, part);
     k_sum<<<1, 256, 0, st>>>(nb, part, out);
     k_sum<<<1, 256, 0, st>>>(nb, part + 256, out + 1);
+}
+
+// out[d] = sum over the rows of design d of r[row] * sum_c Z[row][c]; one workgroup per design,
+// fixed order (thread-strided partial sums, then a fixed tree)
+__global__ void __launch_bounds__(256) k_seg_dot(const int* __restrict__ seg, int k, const double* __restrict__ r,
+                                                 const double* __restrict__ Z, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int d = blockIdx.x, r0 = seg[2 * d], nr = seg[2 * d + 1];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nr; i += 256) {
+        const long long row = r0 + i;
+        double z = 0.0;
+        for (int c = 0; c < k; ++c) z += Z[row * k + c];
+        v += r[row] * z;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[d] = red[0];
+}
+
+void launch_seg_dot(const DevTopo& t, int k, const double* r, const double* Z, double* out, hipStream_t st) {
+    if (t.dsg.size() > 1) k_seg_dot<<<(int)t.dsg.size(), 256, 0, st>>>(t.seg, k, r, Z, out);
 }
 
 __global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {

@@ -16,7 +16,7 @@ __constant__ double c_K0[24 * 24];
 //   (i, beta) -> Z (becomes L^{-1} K_i,beta), (beta, beta) -> S (becomes the Schur complement),
 //   diagonal -> diag (k-scaling). Each entry has exactly one writer: no atomics.
 __global__ void k_assemble(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines, int dim,
-                           int nelx, int nely, const double* __restrict__ rho, double p, double E0,
+                           const double* __restrict__ rho, double p, double E0,
                            double Emin, const int8_t* __restrict__ lcls, const int* __restrict__ lidx,
                            double* __restrict__ Lbuf, double* __restrict__ Zbuf, double* __restrict__ Sbuf,
                            double* __restrict__ diag) {
@@ -48,8 +48,8 @@ __global__ void k_assemble(const SubMeta* __restrict__ subs, const LineMeta* __r
                         for (int ex = ex0; ex <= ex1; ++ex) {
                             const int ca = (ax - ex) + 2 * (ay - ey) + (dim == 3 ? 4 * (az - ez) : 0);
                             const int cb = (bx - ex) + 2 * (by - ey) + (dim == 3 ? 4 * (bz - ez) : 0);
-                            const long long ge = (long long)(M.lo[0] + ex) +
-                                                 (long long)nelx * ((M.lo[1] + ey) + (long long)nely * (M.lo[2] + ez));
+                            const long long ge = M.el0 + (long long)(M.lo[0] + ex) +
+                                                 (long long)M.nelx * ((M.lo[1] + ey) + (long long)M.nely * (M.lo[2] + ez));
                             const double E = Emin + pow(rho[ge], p) * (E0 - Emin);
                             for (int ci = 0; ci < dpn; ++ci)
                                 for (int cj = 0; cj < dpn; ++cj)
@@ -827,16 +827,20 @@ __global__ void k_bg_weights(long long nb_tot, const int* __restrict__ bq_s, con
 
 // Coarse matrix Kbar_cc = sum_s B_c^sT Kbar_cc^s B_c^s (Sec. 2.2), one thread per global
 // corner row (owner computes, fixed summation order).
+// Row p of Kbar_cc, inside its design's dense block (corners of one design couple only among
+// themselves): one thread per corner, each entry written by its row's thread only.
 __global__ void k_coarse_assemble(int n_cg, const int* __restrict__ cc_ptr, const int* __restrict__ cc_s,
                                   const int* __restrict__ cc_j, const SubMeta* __restrict__ subs,
-                                  const int* __restrict__ c_glob, const double* __restrict__ Kc, double* Kg) {
+                                  const int* __restrict__ c_glob, const int* __restrict__ cg_blk,
+                                  const CoarseBlk* __restrict__ blks, const double* __restrict__ Kc, double* Kg) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_cg) return;
+    const CoarseBlk B = blks[cg_blk[p]];
+    double* row = Kg + B.off + (long long)(p - B.cg0) * B.n - B.cg0;
     for (int e = cc_ptr[p]; e < cc_ptr[p + 1]; ++e) {
         const int s = cc_s[e], jc = cc_j[e];
         const SubMeta& M = subs[s];
-        for (int c2 = 0; c2 < M.n_c; ++c2)
-            Kg[(long long)p * n_cg + c_glob[M.off_c + c2]] += Kc[M.off_Kc + jc * M.n_c + c2];
+        for (int c2 = 0; c2 < M.n_c; ++c2) row[c_glob[M.off_c + c2]] += Kc[M.off_Kc + jc * M.n_c + c2];
     }
 }
 
@@ -929,7 +933,7 @@ void upload_K0(const double* K0, int n, hipStream_t st) {
 void launch_assemble(const DevTopo& t, const double* rho, double p, double E0, double Emin, double* L, double* Z,
                      double* S, double* diag, hipStream_t st) {
     dim3 grid((t.max_nodes + 255) / 256, t.n_sub);
-    k_assemble<<<grid, 256, 0, st>>>(t.subs, t.lines, t.dim, t.nel[0], t.nel[1], rho, p, E0, Emin, t.lcls, t.lidx,
+    k_assemble<<<grid, 256, 0, st>>>(t.subs, t.lines, t.dim, rho, p, E0, Emin, t.lcls, t.lidx,
                                      L, Z, S, diag);
 }
 
@@ -1010,7 +1014,7 @@ void launch_weights(const DevTopo& t, int kscale, const double* diag, double* w,
 
 void launch_coarse_assemble(const DevTopo& t, const double* Kc, double* Kg, hipStream_t st) {
     if (t.n_cg) k_coarse_assemble<<<(t.n_cg + 255) / 256, 256, 0, st>>>(t.n_cg, t.cc_ptr, t.cc_s, t.cc_j, t.subs,
-                                                                          t.c_glob, Kc, Kg);
+                                                                          t.c_glob, t.cg_blk, t.cblk, Kc, Kg);
 }
 
 void launch_ggt_assemble(const DevTopo& t, const double* Rb, double* GG, hipStream_t st) {

@@ -503,9 +503,12 @@ __global__ void k_average(long long n_dof, int dim, int nx, int ny, int nsx, int
 }
 
 void launch_average(const DevTopo& t, const double* uloc, double* u, hipStream_t st) {
-    k_average<<<(int)((t.n_dof + 255) / 256), 256, 0, st>>>(t.n_dof, t.dim, t.nel[0], t.nel[1], t.nsub[0], t.nsub[1],
-                                                           t.ax_first[0], t.ax_cnt[0], t.ax_first[1], t.ax_cnt[1],
-                                                           t.ax_first[2], t.ax_cnt[2], t.subs, uloc, u);
+    // one launch per design: the subdomain of a node follows from that design's grid
+    for (const DesignDev& D : t.dsg)
+        if (D.n_dof)
+            k_average<<<(int)((D.n_dof + 255) / 256), 256, 0, st>>>(
+                D.n_dof, t.dim, D.nel[0], D.nel[1], D.nsub[0], D.nsub[1], D.axf[0], D.axc[0], D.axf[1], D.axc[1],
+                D.axf[2], D.axc[2], t.subs + D.sub0, uloc, u + D.dof0);
 }
 
 // Compliance c = f^T u (two-stage reduction) and gradient
@@ -553,13 +556,15 @@ __global__ void k_grad(long long n_el, int dim, int nx, int ny, const double* __
 
 void launch_compliance(const DevTopo& t, const double* f, const double* u, const double* rho, double p, double E0,
                        double Emin, double* part, double* c, double* g, hipStream_t st) {
-    // part must hold 256 doubles; t.K0dev holds the unit element matrix
-    k_dot_part<<<256, 256, 0, st>>>(t.n_dof, f, u, part);
-    k_sum_parts<<<1, 64, 0, st>>>(256, part, c);
-    if (g) {
-        const long long n_el = (long long)t.nel[0] * t.nel[1] * (t.dim == 3 ? t.nel[2] : 1);
-        k_grad<<<(int)((n_el + 255) / 256), 256, 0, st>>>(n_el, t.dim, t.nel[0], t.nel[1], t.K0dev, u, rho, p, E0,
-                                                          Emin, g);
+    // part must hold 256 doubles; t.K0dev holds the unit element matrix. One compliance c[d] and
+    // one gradient block per design.
+    for (size_t d = 0; d < t.dsg.size(); ++d) {
+        const DesignDev& D = t.dsg[d];
+        k_dot_part<<<256, 256, 0, st>>>(D.n_dof, f + D.dof0, u + D.dof0, part);
+        k_sum_parts<<<1, 64, 0, st>>>(256, part, c + d);
+        if (g && D.n_el)
+            k_grad<<<(int)((D.n_el + 255) / 256), 256, 0, st>>>(D.n_el, t.dim, D.nel[0], D.nel[1], t.K0dev,
+                                                                u + D.dof0, rho + D.el0, p, E0, Emin, g + D.el0);
     }
 }
 

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 #include <cstdint>
 
 #include "common.hpp"
@@ -42,12 +43,38 @@ struct TrsmDesc {   // B <- L^{-1} B, L: n x n (ldl), B: n x ncols (ldb), row-ma
     int n, ldl, ncols, ldb;
 };
 
+// FETI-DP coarse matrix Kbar_cc of several independent designs is block diagonal: one dense
+// block per design (corners cg0 .. cg0 + n - 1, row-major at off in the block buffer).
+struct CoarseBlk {
+    int cg0, n;
+    long long off;
+};
+struct CoarseTile {   // 16 rows r0 .. r0 + 15 (block-local) of block blk
+    int blk, r0;
+};
+// Host-side launch parameters of one design inside a context holding several (a single design
+// has one entry with zero offsets).
+struct DesignDev {
+    int sub0 = 0, lam0 = 0, n_lambda = 0;
+    long long el0 = 0, n_el = 0, dof0 = 0, n_dof = 0;
+    int nel[3] = {1, 1, 1}, nsub[3] = {1, 1, 1};
+    const int* axf[3] = {nullptr, nullptr, nullptr};
+    const int* axc[3] = {nullptr, nullptr, nullptr};
+};
+
 // Device copies of the topology (pointers into one device allocation).
 struct DevTopo {
     int dim = 2, n_sub = 0, n_lambda = 0, n_cg = 0, n_groups = 0, n_rbm = 0;
     int nel[3] = {0, 0, 0}, nsub[3] = {1, 1, 1};
     int max_nodes = 0, max_beta = 0, max_nb = 0, max_rows_F = 0, max_nloc = 0, max_nc = 0, max_ni = 0;
     int max_line = 0;
+    // coarse blocks (one per design) and the 16-row tiles of the coarse solve
+    const int* cg_blk = nullptr;
+    const CoarseBlk* cblk = nullptr;
+    const CoarseTile* ctiles = nullptr;
+    int n_ctiles = 0;
+    std::vector<DesignDev> dsg;   // host side: per-design ranges for the per-design launches
+    const int* seg = nullptr;     // device: (first lambda row, rows) per design
     const double* K0dev = nullptr;    // unit-modulus element matrix (row-major)
     long long nb_tot = 0, nc_tot = 0, ni_tot = 0, nloc_tot = 0, n_dof = 0;
     const SubMeta* subs = nullptr;
@@ -162,7 +189,10 @@ void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* con
                     double* out, double* out2, hipStream_t st);
 void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
                     double* out, double alpha, double beta, hipStream_t st);
-void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st);
+void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st,
+                    unsigned long long* kept_mask = nullptr);   // kept_mask: bit j set when column j was kept
+// Z[:, c] = 0 for the columns c set in mask (n x k row-major)
+void launch_zero_cols(long long n, int k, unsigned long long mask, double* Z, hipStream_t st);
 void launch_apply_T(int n, int k, const double* T, const double* W, const double* Q, double* Wo, double* Qo,
                     hipStream_t st);
 // lam += W g; r -= Qg_scale * Q g  (Q may be null)
@@ -171,6 +201,8 @@ void launch_update_lr(int n, int k, const double* W, const double* Q, const doub
 void launch_orth_update(int n, int k, const double* const* Wptrs, int nblk, const double* Psi, double* W,
                         hipStream_t st);
 void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st);
+// out[d] = sum over the lambda rows of design d of r[row] * sum_c Z[row][c] (k columns), fixed order
+void launch_seg_dot(const DevTopo& t, int k, const double* r, const double* Z, double* out, hipStream_t st);
 // out[0..63] = A^T x (A: n x 64 row-major), two-stage deterministic reduction through part
 void launch_gemv_t(int n, int k, const double* A, const double* x, double* part, double* out, hipStream_t st);
 void launch_diff_norms(long long len, const double* a, const double* b, double* part, double* out,

@@ -389,4 +389,123 @@ std::string build_plan(const feti_mesh* mesh, const feti_partition* part, const 
     return "";
 }
 
+std::string build_plan_batched(int nd, const feti_mesh* meshes, const feti_partition* parts, const feti_opts* opts,
+                               Plan& U, std::vector<DesignMeta>& D) {
+    if (nd < 1 || !meshes || !parts) return "need at least one design";
+    U = Plan();
+    D.assign(nd, DesignMeta{});
+    U.off_loc.assign(1, 0);
+    U.off_i.assign(1, 0);
+    U.off_b.assign(1, 0);
+    U.off_c.assign(1, 0);
+    U.sh_ptr.assign(1, 0);
+    U.bg_ptr.assign(1, 0);
+    U.cc_ptr.assign(1, 0);
+    int n_sh = 0;
+    for (int d = 0; d < nd; ++d) {
+        Plan P;
+        std::string err = build_plan(&meshes[d], &parts[d], opts, P);
+        if (!err.empty()) return "design " + std::to_string(d) + ": " + err;
+        if (d == 0) {
+            U.dim = P.dim;
+            U.dpn = P.dpn;
+            U.method = P.method;
+            U.nu = P.nu;
+            U.n_rbm = P.n_rbm;
+        } else if (P.dim != U.dim) {
+            return "all designs must have the same dimension";
+        } else if (P.nu != U.nu) {
+            return "all designs must have the same Poisson ratio";
+        }
+        DesignMeta& M = D[d];
+        M.sub0 = U.n_sub;
+        M.n_sub = P.n_sub;
+        M.el0 = U.n_el;
+        M.n_el = P.n_el;
+        M.node0 = U.n_nodes;
+        M.n_nodes = P.n_nodes;
+        M.dof0 = U.n_dof;
+        M.n_dof = P.n_dof;
+        M.lam0 = U.n_lambda;
+        M.n_lambda = P.n_lambda;
+        M.cg0 = U.n_cg;
+        M.n_cg = P.n_cg;
+        M.grp0 = U.n_groups;
+        M.n_groups = P.n_groups;
+        for (int a = 0; a < 3; ++a) {
+            M.nel[a] = P.nel[a];
+            M.nsub[a] = P.nsub[a];
+            M.ax_first[a] = P.ax_first[a];
+            M.ax_cnt[a] = P.ax_cnt[a];
+        }
+        const int64_t loc0 = U.off_loc.back(), i0 = U.off_i.back(), b0 = U.off_b.back(), c0 = U.off_c.back();
+        for (int s = 0; s < P.n_sub; ++s) {
+            for (int a = 0; a < 3; ++a) {
+                U.lo.push_back(P.lo[3 * s + a]);
+                U.nn.push_back(P.nn[3 * s + a]);
+            }
+            U.n_loc.push_back(P.n_loc[s]);
+            U.n_i.push_back(P.n_i[s]);
+            U.n_b.push_back(P.n_b[s]);
+            U.n_c.push_back(P.n_c[s]);
+            U.band.push_back(P.band[s]);
+            U.grp.push_back(P.grp[s] + M.grp0);
+            U.off_loc.push_back(loc0 + P.off_loc[s + 1]);
+            U.off_i.push_back(i0 + P.off_i[s + 1]);
+            U.off_b.push_back(b0 + P.off_b[s + 1]);
+            U.off_c.push_back(c0 + P.off_c[s + 1]);
+        }
+        U.lcls.insert(U.lcls.end(), P.lcls.begin(), P.lcls.end());
+        U.lidx.insert(U.lidx.end(), P.lidx.begin(), P.lidx.end());
+        U.lown.insert(U.lown.end(), P.lown.begin(), P.lown.end());
+        for (int g : P.lglob) U.lglob.push_back(g + (int)M.dof0);
+        U.i_loc.insert(U.i_loc.end(), P.i_loc.begin(), P.i_loc.end());
+        U.b_loc.insert(U.b_loc.end(), P.b_loc.begin(), P.b_loc.end());
+        U.c_loc.insert(U.c_loc.end(), P.c_loc.begin(), P.c_loc.end());
+        for (int g : P.c_glob) U.c_glob.push_back(g + M.cg0);
+        for (int r = 0; r < P.n_lambda; ++r) {
+            for (int t = 0; t < 2; ++t) {
+                const int s = P.row_s[2 * r + t];
+                U.row_s.push_back(s >= 0 ? s + M.sub0 : -1);
+                U.row_j.push_back(P.row_j[2 * r + t]);
+                U.row_sg.push_back(P.row_sg[2 * r + t]);
+            }
+            U.row_sh.push_back(P.row_sh[r] >= 0 ? P.row_sh[r] + n_sh : -1);
+        }
+        const int sh_base = U.sh_ptr.back();
+        for (size_t q = 1; q < P.sh_ptr.size(); ++q) U.sh_ptr.push_back(sh_base + P.sh_ptr[q]);
+        for (int s : P.sh_s) U.sh_s.push_back(s + M.sub0);
+        U.sh_l.insert(U.sh_l.end(), P.sh_l.begin(), P.sh_l.end());
+        n_sh += (int)P.sh_ptr.size() - 1;
+        const int bg_base = U.bg_ptr.back();
+        for (size_t q = 1; q < P.bg_ptr.size(); ++q) U.bg_ptr.push_back(bg_base + P.bg_ptr[q]);
+        for (int r : P.bg_row) U.bg_row.push_back(r + M.lam0);
+        U.bg_sg.insert(U.bg_sg.end(), P.bg_sg.begin(), P.bg_sg.end());
+        for (int g : P.corner_dofs) U.corner_dofs.push_back(g + (int)M.dof0);
+        const int cc_base = U.cc_ptr.back();
+        for (size_t q = 1; q < P.cc_ptr.size(); ++q) U.cc_ptr.push_back(cc_base + P.cc_ptr[q]);
+        for (int s : P.cc_s) U.cc_s.push_back(s + M.sub0);
+        U.cc_j.insert(U.cc_j.end(), P.cc_j.begin(), P.cc_j.end());
+        U.n_sub += P.n_sub;
+        U.n_el += P.n_el;
+        U.n_nodes += P.n_nodes;
+        U.n_dof += P.n_dof;
+        U.n_lambda += P.n_lambda;
+        U.n_cg += P.n_cg;
+        U.n_groups += P.n_groups;
+        U.n_alpha += P.n_alpha;
+    }
+    if (nd == 1) {
+        for (int a = 0; a < 3; ++a) {
+            U.nel[a] = D[0].nel[a];
+            U.nsub[a] = D[0].nsub[a];
+            U.ax_first[a] = D[0].ax_first[a];
+            U.ax_cnt[a] = D[0].ax_cnt[a];
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) U.nel[a] = U.nsub[a] = 0;
+    }
+    return "";
+}
+
 }  // namespace feti

@@ -71,4 +71,21 @@ struct Plan {
 std::string build_plan(const feti_mesh* mesh, const feti_partition* part, const feti_opts* opts,
                        Plan& P);
 
+// One design inside a plan that holds several independent designs (their disjoint union):
+// the ranges of its subdomains, elements, nodes, DOFs, lambda rows, corners and S-FETI
+// direction groups in the union's numbering, and its own structured grid.
+struct DesignMeta {
+    int sub0 = 0, n_sub = 0;
+    int64_t el0 = 0, n_el = 0, node0 = 0, n_nodes = 0, dof0 = 0, n_dof = 0;
+    int lam0 = 0, n_lambda = 0, cg0 = 0, n_cg = 0, grp0 = 0, n_groups = 0;
+    int nel[3] = {1, 1, 1}, nsub[3] = {1, 1, 1};
+    std::vector<int> ax_first[3], ax_cnt[3];
+};
+
+// The union of nd designs (same dimension, method and options) as one decomposition: the
+// per-design plans concatenated with offsets. The union's nel/nsub/ax_* are those of design 0
+// when nd == 1 and unused otherwise (per-design data is in D).
+std::string build_plan_batched(int nd, const feti_mesh* meshes, const feti_partition* parts, const feti_opts* opts,
+                               Plan& U, std::vector<DesignMeta>& D);
+
 }  // namespace feti

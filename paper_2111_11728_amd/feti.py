@@ -54,11 +54,21 @@ class feti_info(C.Structure):
                 ("reduced_iters", C.c_int), ("precision_probes", C.c_int), ("reduced_rel_err", C.c_double)]
 
 
+class feti_design(C.Structure):
+    _fields_ = [("el0", C.c_longlong), ("n_el", C.c_longlong), ("dof0", C.c_longlong), ("n_dof", C.c_longlong),
+                ("sub0", C.c_int), ("n_sub", C.c_int), ("lam0", C.c_int), ("n_lambda", C.c_int),
+                ("n_groups", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class feti_sizes(C.Structure):
     _fields_ = [("n_sub", C.c_int), ("n_dof", C.c_int), ("n_el", C.c_int), ("n_lambda", C.c_int), ("n_cg", C.c_int),
                 ("n_alpha", C.c_int), ("n_groups", C.c_int), ("nb_max", C.c_int), ("nb_min", C.c_int),
                 ("n_loc_max", C.c_int), ("n_i_max", C.c_int), ("band_max", C.c_int), ("sum_nb2", C.c_longlong),
-                ("sum_nb_nc", C.c_longlong), ("device_bytes", C.c_longlong), ("n_fp64_subs", C.c_int)]
+                ("sum_nb_nc", C.c_longlong), ("device_bytes", C.c_longlong), ("n_fp64_subs", C.c_int),
+                ("n_designs", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +104,10 @@ def lib():
             "feti_rhs": (I, [P, P, P, P]),
             "feti_get_local": (I, [P, I, I, C.POINTER(D), LL, C.POINTER(I), C.POINTER(I)]),
             "feti_last_timing": (I, [P, I, C.POINTER(D)]),
+            "feti_setup_batched": (I, [I, C.POINTER(feti_mesh), C.POINTER(feti_partition), C.POINTER(feti_opts), P,
+                                       D, D, D, P, C.POINTER(P)]),
+            "feti_design_layout": (I, [P, I, C.POINTER(feti_design)]),
+            "feti_design_residuals": (I, [P, C.POINTER(D), I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -254,3 +268,36 @@ class Context:
         ms = C.c_double(0)
         _check(lib().feti_last_timing(self.handle, what, C.byref(ms)))
         return ms.value
+
+
+class BatchedContext(Context):
+    """Several independent designs in one feti_ctx (feti_setup_batched): rho, f, u and the
+    gradient concatenate the designs in order; the compliance has one entry per design."""
+
+    def __init__(self, specs, rho, p=None, E0=None, Emin=None):
+        if not specs:
+            raise ValueError("need at least one design")
+        prob = specs[0].prob
+        self.spec = specs[0]
+        self.specs = list(specs)
+        self.p = prob.p if p is None else p
+        self.E0 = prob.E0 if E0 is None else E0
+        self.Emin = prob.Emin if Emin is None else Emin
+        nd = len(specs)
+        meshes = (feti_mesh * nd)(*[s.mesh for s in specs])
+        parts = (feti_partition * nd)(*[s.part for s in specs])
+        self.handle = C.c_void_p()
+        _check(lib().feti_setup_batched(nd, meshes, parts, C.byref(specs[0].opts), _ptr(rho), self.p, self.E0,
+                                        self.Emin, _stream(), C.byref(self.handle)))
+        self.sizes = self.feti_get_sizes()
+        self.layout = [self.feti_design_layout(d) for d in range(nd)]
+
+    def feti_design_layout(self, d) -> dict:
+        out = feti_design()
+        _check(lib().feti_design_layout(self.handle, d, C.byref(out)))
+        return out.as_dict()
+
+    def feti_design_residuals(self) -> np.ndarray:
+        out = np.zeros(len(self.specs))
+        _check(lib().feti_design_residuals(self.handle, out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        return out

@@ -152,13 +152,13 @@ def modular_3d(seed: int = 0, nsub=(4, 4, 4), m: int = 12, Emin: float = 1e-6) -
                    Emin=Emin, name=f"modular3d_{nsub[0]}x{nsub[1]}x{nsub[2]}_of_{m}")
 
 
-def uneven_design(seed: int, d: int) -> Problem:
-    """One design of the batched workload: gx, gy ~ U{4..8} subdomains per axis,
-    per-column widths and per-row heights ~ U{16..48} elements, modular 0/1 rho."""
+def uneven_design(seed: int, d: int, g=(4, 8), w=(16, 48)) -> Problem:
+    """One design of the batched workload: gx, gy ~ U{g0..g1} subdomains per axis (4..8),
+    per-column widths and per-row heights ~ U{w0..w1} elements (16..48), modular 0/1 rho."""
     rng = np.random.default_rng([seed, d])
-    gx, gy = int(rng.integers(4, 9)), int(rng.integers(4, 9))
-    wx = rng.integers(16, 49, gx)
-    wy = rng.integers(16, 49, gy)
+    gx, gy = int(rng.integers(g[0], g[1] + 1)), int(rng.integers(g[0], g[1] + 1))
+    wx = rng.integers(w[0], w[1] + 1, gx)
+    wy = rng.integers(w[0], w[1] + 1, gy)
     cx = [0] + list(np.cumsum(wx).astype(int))
     cy = [0] + list(np.cumsum(wy).astype(int))
     nel = (cx[-1], cy[-1])
