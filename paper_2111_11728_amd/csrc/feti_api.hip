@@ -131,6 +131,7 @@ struct feti_ctx {
     double *Kc = nullptr, *Kcc = nullptr, *Kcc_w = nullptr, *Kcc_inv = nullptr;
     // designs held by the context (one, or several independent ones as a disjoint union)
     std::vector<DesignMeta> designs;
+    bool segmented = false;   // several designs, each with its own S-FETI directions
     std::vector<CoarseBlk> hcblk;
     GemmDesc* d_cc_gemm = nullptr;
     PotrfDesc* d_cc_potrf = nullptr;
@@ -254,6 +255,7 @@ void build_layout(feti_ctx* c) {
         D.n_nodes = P.n_nodes;
         D.n_dof = P.n_dof;
         D.n_lambda = P.n_lambda;
+        D.n_rows = P.n_lambda;
         D.n_cg = P.n_cg;
         D.n_groups = P.n_groups;
         for (int a = 0; a < 3; ++a) {
@@ -428,6 +430,18 @@ void build_layout(feti_ctx* c) {
         }
         t.seg = c->upload(seg);
     }
+    t.hkseg.clear();
+    if (c->segmented) {
+        std::vector<int> rb((size_t)std::max(1, P.n_lambda / 256), 0);
+        for (int d = 0; d < (int)c->designs.size(); ++d) {
+            const DesignMeta& D = c->designs[d];
+            const int base = std::max(1, (int)std::llround(256.0 * D.n_rows / std::max(1, P.n_lambda)));
+            t.hkseg.push_back(KrySeg{D.lam0, D.n_rows, base});
+            for (int q = D.lam0 / 256; q < (D.lam0 + D.n_rows) / 256; ++q) rb[q] = d;
+        }
+        t.kseg = c->upload(t.hkseg);
+        t.rb_design = c->upload(rb);
+    }
     const int na = c->n_alpha;
     c->GG = c->alloc<double>((long long)na * na);
     c->GG_w = c->alloc<double>((long long)na * na);
@@ -573,14 +587,16 @@ void build_layout(feti_ctx* c) {
     c->Qtmp = c->alloc<double>(nl * kMaxDirs);
     c->Zk = c->alloc<double>(nl * kMaxDirs);
     c->Qk = c->alloc<double>(nl * kMaxDirs);
-    c->Delta = c->alloc<double>(kMaxDirs * kMaxDirs);
-    c->Tm = c->alloc<double>(kMaxDirs * kMaxDirs);
-    c->gam = c->alloc<double>(kMaxDirs);
+    const int nsegd = c->segmented ? (int)c->designs.size() : 1;   // per-design k x k blocks
+    c->Delta = c->alloc<double>((long long)nsegd * kMaxDirs * kMaxDirs);
+    c->Tm = c->alloc<double>((long long)nsegd * kMaxDirs * kMaxDirs);
+    c->gam = c->alloc<double>((long long)nsegd * kMaxDirs);
     c->part = c->alloc<double>(kGramPartCap);
     const int nd = (int)c->designs.size();
-    c->scal = c->alloc<double>(16 + nd);   // [16 + d]: per-design dots (several designs)
+    // [16 + d]: per-design dots; segmented: [16 + nd + d] kept-column masks, [16 + 2 nd + d] ranks
+    c->scal = c->alloc<double>(16 + 3 * nd);
     c->rank_dev = reinterpret_cast<int*>(c->scal + 8);
-    HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(double) * (16 + nd), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(double) * (16 + 3 * nd), hipHostMallocDefault));
     c->eps0_d.assign(nd, 0.0);
     c->true_d.assign(nd, 0.0);
     c->qk_ptr = c->upload(std::vector<const double*>{c->Qk});
@@ -965,7 +981,7 @@ void ensure_history(feti_ctx* c, int kd, int need) {
     }
     c->WH_dev = wdev;
     c->QH_dev = qdev;
-    const long long pc = (long long)newcap * kd * kd;
+    const long long pc = (long long)newcap * kd * kd * (c->segmented ? (long long)c->designs.size() : 1);
     if (pc > c->psi_cap) {
         if (c->Psi) {
             hipStreamSynchronize(c->st);
@@ -1129,7 +1145,18 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
     const int one = kd == 1;
-    const bool multi = c->designs.size() > 1 && kd == c->P.n_groups;
+    const bool seg = c->segmented && kd == kMaxDirs;
+    const bool multi = c->designs.size() > 1 && !c->segmented && kd == c->P.n_groups;
+    // orthogonalisation of Zk against the stored blocks (per design when segmented)
+    auto orth = [&](int nb_) {
+        if (seg) {
+            launch_gram_seg(c->t, n, c->QH_dev, nb_, c->Zk, c->part, c->Psi, st);
+            launch_ts_seg(c->t, n, nb_, c->WH_dev, c->Psi, (long long)nb_ * 4096, c->Zk, c->Zk, -1.0, 1.0, st);
+        } else {
+            launch_gram(n, kd, kd, c->QH_dev, nb_, c->Zk, c->part, c->Psi, st);
+            launch_ts_gemm(n, kd, nb_, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st);
+        }
+    };
     const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
     const int passes = c->opts.reorth == 2 ? 2 : 1;
     precondition(c, c->r, c->Zk, one, 0);
@@ -1149,6 +1176,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             for (int g = 0; g < c->designs[d].n_groups; ++g) gmask[d] |= 1ull << (c->designs[d].grp0 + g);
             all_mask |= gmask[d];
         }
+    if (seg) all_mask = nds >= 64 ? ~0ull : (1ull << nds) - 1;   // bit d: design d
     int nb = 0;
     double best = o.eps;
     int it_best = 0;
@@ -1159,6 +1187,15 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         double* Qn = (double*)c->QH[nb];
         const int p_it = gated_apply(c, g, replaced, o.eps, eps0, kd, c->Zk, c->Qk, c->Qtmp);
         o.reduced += p_it != FETI_FP64;
+        if (seg) {
+            // per design: Delta_d = Q_d^T W_d, its pivoted Cholesky, W, Q, gamma_d = W_d^T r_d
+            launch_gram_seg(c->t, n, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
+            launch_pivchol_seg(nds, c->Delta, rr_tol, c->Tm, reinterpret_cast<int*>(c->scal + 16 + 2 * nds),
+                               reinterpret_cast<unsigned long long*>(c->scal + 16 + nds), st);
+            launch_ts_pair_seg(c->t, n, c->zk_ptr, c->qk_ptr, c->Tm, Wn, Qn, st);
+            launch_gemv_t_seg(c->t, n, Wn, c->r, c->part, c->gam, st);
+            launch_update_lr_seg(c->t, n, Wn, Qn, c->gam, c->lt, c->r, st);
+        } else {
         // Delta = Q^T W
         launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
         launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st,
@@ -1178,23 +1215,28 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         } else {
             launch_update_lr(n, kd, Wn, Qn, c->gam, c->lt, c->r, st);
         }
+        }
         CHECK_LAUNCH();
         ++nb;
         precondition(c, c->r, c->Zk, one, 0);
         launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
         launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
         project(c, kd, c->Zk);
-        for (int pass = 0; pass < passes; ++pass) {
-            launch_gram(n, kd, kd, c->QH_dev, nb, c->Zk, c->part, c->Psi, st);
-            launch_ts_gemm(n, kd, nb, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st);
-        }
+        for (int pass = 0; pass < passes; ++pass) orth(nb);
         CHECK_LAUNCH();
-        // eps^2 (scal[0]) and the rank (scal[8]) in one copy
-        HIPCHK(hipMemcpyAsync(c->hpin, c->scal, (16 + c->designs.size()) * sizeof(double), hipMemcpyDeviceToHost, st));
+        // eps^2 (scal[0]), the rank (scal[8]) and the per-design values in one copy
+        HIPCHK(hipMemcpyAsync(c->hpin, c->scal, (16 + 3 * c->designs.size()) * sizeof(double), hipMemcpyDeviceToHost,
+                              st));
         wait_poll(c);
         const double ez = c->hpin[0];
         int rank = 0;
         std::memcpy(&rank, c->hpin + 8, sizeof(int));
+        std::vector<int> rank_d(seg ? nds : 0, 0);
+        if (seg) {
+            std::memcpy(rank_d.data(), c->hpin + 16 + 2 * nds, sizeof(int) * nds);
+            rank = 0;
+            for (int d = 0; d < nds; ++d) rank += rank_d[d];
+        }
         ranks.push_back(rank);
         o.iters = it + 1;
         if (verbose())
@@ -1219,6 +1261,18 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             }
             if (frozen == all_mask && !converged(c, o.eps, eps0, tol)) break;   // every design done
             launch_zero_cols(n, kd, frozen, c->Zk, st);
+        } else if (seg) {
+            std::vector<unsigned long long> km(nds, 0);
+            std::memcpy(km.data(), c->hpin + 16 + nds, sizeof(unsigned long long) * nds);
+            for (int d = 0; d < nds; ++d) {
+                if ((frozen >> d) & 1ull) continue;
+                kept_d[d] += __builtin_popcountll(km[d]);
+                const bool cd = !(c->eps0_d[d] > 0.0) ||
+                                std::sqrt(std::max(c->hpin[16 + d], 0.0)) <= tol * c->eps0_d[d];
+                if (cd || kept_d[d] >= c->designs[d].n_lambda) frozen |= 1ull << d;
+            }
+            if (frozen == all_mask && !converged(c, o.eps, eps0, tol)) break;   // every design done
+            launch_zero_rows(c->t, n, frozen, c->Zk, st);
         }
         const bool conv = converged(c, o.eps, eps0, tol);
         if (o.eps < 0.9 * best) {
@@ -1247,10 +1301,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
             if (converged(c, o.eps, eps0, tol)) break;
             project(c, kd, c->Zk);
-            for (int pass = 0; pass < passes; ++pass) {
-                launch_gram(n, kd, kd, c->QH_dev, nb, c->Zk, c->part, c->Psi, st);
-                launch_ts_gemm(n, kd, nb, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st);
-            }
+            for (int pass = 0; pass < passes; ++pass) orth(nb);
             CHECK_LAUNCH();
             best = o.eps;
             it_best = it;
@@ -1567,10 +1618,14 @@ feti_status feti_setup_batched(int n_designs, const feti_mesh* meshes, const fet
         return fail(FETI_EINVAL, "need p >= 1 and 0 < Emin < E0");
     if (!rho) return fail(FETI_EINVAL, "null density array");
     std::unique_ptr<feti_ctx> c(new feti_ctx());
-    std::string err = build_plan_batched(n_designs, meshes, parts, opts, c->P, c->designs);
+    // S-FETI: every design searches along its own direction groups in the same 64 columns
+    c->segmented = opts->krylov == FETI_SFETI && n_designs > 1;
+    if (c->segmented && n_designs > 64) return fail(FETI_EINVAL, "at most 64 designs per batched S-FETI context");
+    std::string err = build_plan_batched(n_designs, meshes, parts, opts, c->P, c->designs, c->segmented);
     if (!err.empty()) return fail(FETI_EINVAL, err);
     if (opts->krylov == FETI_SFETI && c->P.n_groups > kMaxDirs)
-        return fail(FETI_EINVAL, "more than 64 simultaneous directions over all designs: set partition.group");
+        return fail(FETI_EINVAL, "more than 64 simultaneous directions in one design: set partition.group");
+    if (c->segmented) c->P.n_groups = kMaxDirs;   // 64 columns; a design's unused ones stay zero
     c->opts = *opts;
     c->p = p;
     c->E0 = E0;

@@ -215,11 +215,14 @@ constexpr int kTsWaves = 8;   // 128 output rows per workgroup
 __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
                                                         const double* __restrict__ Mats, const double* C, double* out,
                                                         double alpha, double beta, const double* const* Aptrs2,
-                                                        double* out2) {
+                                                        double* out2, const int* __restrict__ rb_design,
+                                                        long long mstride) {
     if (blockIdx.y) {   // second job of a paired launch: same Mats, its own operands
         Aptrs = Aptrs2;
         out = out2;
     }
+    // several designs: the matrices of the design owning this workgroup's rows (a 256-row block)
+    if (rb_design) Mats += (long long)rb_design[(blockIdx.x * (16 * kTsWaves)) >> 8] * mstride;
     __shared__ __attribute__((aligned(16))) double Ps[2][4096];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
     const int rb0 = blockIdx.x * (16 * kTsWaves) + 16 * wave;
@@ -297,12 +300,39 @@ constexpr int kGrGroups = 256; // workgroups per round: one per CU
 // of block ib is A column 4 m' + ib, column n' of block jb is B column 4 n' + jb. The
 // wavefront results meet in LDS (fixed order); segment slot t of workgroup w writes, for its
 // pair p, part[((w*2 + t)*2 + h)*4096 + i*64 + j] for block 2p + h.
+// Several designs (segs != null): design d owns max(npair, segs[d].base) consecutive
+// workgroups, which split its own rows in the same way; partials keep the global workgroup index.
+__device__ __forceinline__ int gram_seg_find(const KrySeg* segs, int nseg, int npair, int wg, int& w, int& G) {
+    int acc = 0;
+    for (int d = 0; d < nseg; ++d) {
+        const int Gd = max(npair, segs[d].base);
+        if (wg < acc + Gd) {
+            w = wg - acc;
+            G = Gd;
+            return d;
+        }
+        acc += Gd;
+    }
+    w = 0;
+    G = 1;
+    return nseg - 1;
+}
+
 __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double* const* __restrict__ Aptrs,
-                                                   const double* __restrict__ B, double* __restrict__ part) {
+                                                   const double* __restrict__ B, double* __restrict__ part,
+                                                   const KrySeg* __restrict__ segs, int nseg) {
     __shared__ double red[4 * 4096];
-    const int G = gridDim.x, w = blockIdx.x;
+    const int wg = blockIdx.x;
+    int G = gridDim.x, w = blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
     const int npair = (nblk + 1) >> 1;
+    long long arow0 = 0;   // first element of this workgroup's design in every n x 64 block
+    if (segs) {
+        const int d = gram_seg_find(segs, nseg, npair, wg, w, G);
+        arow0 = (long long)segs[d].row0 * 64;
+        n = segs[d].nrows;
+        B += arow0;
+    }
     const long long nsteps = (n + 3) >> 2, S = nsteps * npair;
     const long long s_lo = (long long)w * S / G, s_hi = (long long)(w + 1) * S / G;
     for (int slot = 0; slot < 2; ++slot) {
@@ -312,9 +342,9 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
         const long long a0 = std::max(s_lo, p_ll * nsteps) - p_ll * nsteps;
         const long long a1 = std::min(s_hi, (p_ll + 1) * nsteps) - p_ll * nsteps;
         const int w0 = (int)(a0 + (a1 - a0) * wave / 4), w1 = (int)(a0 + (a1 - a0) * (wave + 1) / 4);
-        const double* A0 = Aptrs[2 * pr];
+        const double* A0 = Aptrs[2 * pr] + arow0;
         const bool has1 = 2 * pr + 1 < nblk;
-        const double* A1 = has1 ? Aptrs[2 * pr + 1] : A0;
+        const double* A1 = has1 ? Aptrs[2 * pr + 1] + arow0 : A0;
         v4d_t acc[2][4][4];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -382,7 +412,7 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
                     for (int v = 0; v < 4; ++v)
                         red[wave * 4096 + (4 * (g + 4 * v) + ib) * 64 + 4 * m + jb] = acc[h][ib][jb][v];
             __syncthreads();
-            double* out = part + (((long long)w * 2 + slot) * 2 + h) * 4096;
+            double* out = part + (((long long)wg * 2 + slot) * 2 + h) * 4096;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int e = tid + 256 * u;
@@ -397,11 +427,22 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
 // b%2): workgroup = 64 consecutive entries of one block; its four wavefronts take every fourth
 // contributing workgroup and meet in LDS.
 __global__ void __launch_bounds__(256) k_gram64_reduce(int n, int nblk, int G, const double* __restrict__ part,
-                                                       double* __restrict__ out) {
+                                                       double* __restrict__ out, const KrySeg* __restrict__ segs,
+                                                       int nseg) {
     __shared__ double red[4][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int b = blockIdx.x >> 6, e = ((blockIdx.x & 63) << 6) + lane;
-    const int pr = b >> 1, h = b & 1, npair = (nblk + 1) >> 1;
+    int bid = blockIdx.x, wbase = 0;
+    const int npair = (nblk + 1) >> 1;
+    if (segs) {   // workgroup = (design, block, 64 entries); that design's workgroups only
+        const int d = bid / (nblk * 64);
+        bid -= d * nblk * 64;
+        for (int q = 0; q < d; ++q) wbase += max(npair, segs[q].base);
+        G = max(npair, segs[d].base);
+        n = segs[d].nrows;
+        out += (long long)d * nblk * 4096;
+    }
+    const int b = bid >> 6, e = ((bid & 63) << 6) + lane;
+    const int pr = b >> 1, h = b & 1;
     const long long nsteps = (n + 3) >> 2, S = nsteps * npair;
     const long long bs = (long long)pr * nsteps, be = bs + nsteps;
     // contributing workgroups wf..wl: [w S / G, (w+1) S / G) meets [bs, be); only wf can
@@ -416,7 +457,7 @@ __global__ void __launch_bounds__(256) k_gram64_reduce(int n, int nblk, int G, c
     double v = 0.0;
     for (long long ww = wf + wave; ww <= wl; ww += 4)
         if ((ww + 1) * S / G > ww * S / G)   // a workgroup with an empty step range adds only zeros
-            v += part[((ww * 2 + (ww == wf ? slot_f : 0)) * 2 + h) * 4096 + e];
+            v += part[(((wbase + ww) * 2 + (ww == wf ? slot_f : 0)) * 2 + h) * 4096 + e];
     red[wave][lane] = v;
     __syncthreads();
     if (wave == 0) out[(long long)b * 4096 + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
@@ -449,9 +490,12 @@ __global__ void __launch_bounds__(256) k_gemv_t64(int n, const double* __restric
 // lam += W g; r -= Q g for 64 directions: 16 lanes per row, 4 consecutive columns each.
 __global__ void __launch_bounds__(256) k_update_lr64(int n, const double* __restrict__ W, const double* __restrict__ Q,
                                                      const double* __restrict__ gm, double* __restrict__ lam,
-                                                     double* __restrict__ r) {
+                                                     double* __restrict__ r,
+                                                     const int* __restrict__ rb_design) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int row = (int)(t >> 4), p = (int)(t & 15);
+    // several designs: the gamma of the row's design
+    if (rb_design && row < n) gm += rb_design[row >> 8] * 64;
     const v4d_t gv = *reinterpret_cast<const v4d_t*>(gm + 4 * p);
     double dl = 0.0, dr = 0.0;
     if (row < n) {
@@ -494,7 +538,7 @@ void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const d
     if (!n || !nblk) return;
     if (kd == 64)
         k_ts64<<<(n + 16 * kTsWaves - 1) / (16 * kTsWaves), 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha,
-                                                                                    beta, nullptr, nullptr);
+                                                                                    beta, nullptr, nullptr, nullptr, 0);
     else
         k_ts_gemm<<<(n + 63) / 64, 256, 0, st>>>(n, kd, nblk, Aptrs, Mats, C, out, alpha, beta);
 }
@@ -504,7 +548,7 @@ void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* con
     if (!n) return;
     if (kd == 64) {
         k_ts64<<<dim3((n + 16 * kTsWaves - 1) / (16 * kTsWaves), 2), 64 * kTsWaves, 0, st>>>(
-            n, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, Aptrs2, out2);
+            n, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, Aptrs2, out2, nullptr, 0);
         return;
     }
     launch_ts_gemm(n, kd, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, st);
@@ -518,8 +562,8 @@ void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, co
         const int npair = (nblk + 1) / 2;
         const int G = kGrGroups * ((npair + kGrGroups - 1) / kGrGroups);
         if ((long long)G * 4 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
-        k_gram64<<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part);
-        k_gram64_reduce<<<nblk * 64, 256, 0, st>>>(n, nblk, G, part, out);
+        k_gram64<<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
+        k_gram64_reduce<<<nblk * 64, 256, 0, st>>>(n, nblk, G, part, out, nullptr, 0);
         return;
     }
     const int nchunk = gram_chunks(n, nblk);
@@ -665,6 +709,11 @@ __global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict
     __shared__ double scs[64];
     __shared__ double ipv_s[64];
     __shared__ int p_s[64];
+    // one workgroup per design in the segmented form (grid = designs)
+    D += (long long)blockIdx.x * k * k;
+    T += (long long)blockIdx.x * k * k;
+    rank_out += blockIdx.x;
+    if (mask_out) mask_out += blockIdx.x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     // D staged through LDS by coalesced rows
     for (int i = 32 * w; i < 32 * w + 32; ++i) Lm[i][l] = (l < k && i < k) ? D[i * k + l] : 0.0;
@@ -763,6 +812,83 @@ void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank,
     k_pivchol<<<1, 128, 0, st>>>(k, D, rr_tol, T, rank, kept_mask);
 }
 
+// ---- segmented forms (several designs, each with its own directions in the 64 columns) ----
+void launch_gram_seg(const DevTopo& t, int n, const double* const* Aptrs, int nblk, const double* B, double* part,
+                     double* out, hipStream_t st) {
+    if (nblk == 0) return;
+    const int nseg = (int)t.hkseg.size();
+    const int npair = (nblk + 1) / 2;
+    int G = 0;
+    for (const KrySeg& q : t.hkseg) G += std::max(npair, q.base);
+    if ((long long)G * 4 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
+    (void)n;
+    k_gram64<<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
+    k_gram64_reduce<<<nseg * nblk * 64, 256, 0, st>>>(0, nblk, G, part, out, t.kseg, nseg);
+}
+
+void launch_ts_seg(const DevTopo& t, int n, int nblk, const double* const* Aptrs, const double* Mats, long long mstride,
+                   const double* C, double* out, double alpha, double beta, hipStream_t st) {
+    if (!n || !nblk) return;
+    k_ts64<<<(n + 16 * kTsWaves - 1) / (16 * kTsWaves), 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha, beta,
+                                                                                nullptr, nullptr, t.rb_design, mstride);
+}
+
+void launch_ts_pair_seg(const DevTopo& t, int n, const double* const* Aptrs, const double* const* Aptrs2,
+                        const double* Mats, double* out, double* out2, hipStream_t st) {
+    if (!n) return;
+    k_ts64<<<dim3((n + 16 * kTsWaves - 1) / (16 * kTsWaves), 2), 64 * kTsWaves, 0, st>>>(
+        n, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, Aptrs2, out2, t.rb_design, 4096);
+}
+
+// out[d*64 + e] = sum of the 256-row chunk partials of design d, in chunk order (16 wavefronts,
+// fixed-order combine)
+__global__ void __launch_bounds__(1024) k_colsum64_seg(const KrySeg* __restrict__ segs, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    __shared__ double red[16][64];
+    const int d = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c0 = segs[d].row0 >> 8, c1 = (segs[d].row0 + segs[d].nrows) >> 8;
+    double v = 0.0;
+    for (int c = c0 + wave; c < c1; c += 16) v += part[(long long)c * 64 + lane];
+    red[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0) {
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) tot += red[w][lane];
+        out[(long long)d * 64 + lane] = tot;
+    }
+}
+
+void launch_gemv_t_seg(const DevTopo& t, int n, const double* A, const double* x, double* part, double* out,
+                       hipStream_t st) {
+    if (!n) return;
+    const int nchunk = n / 256;   // 256-row chunks: each lies in one design
+    k_gemv_t64<<<nchunk, 256, 0, st>>>(n, A, x, part);
+    k_colsum64_seg<<<(int)t.hkseg.size(), 1024, 0, st>>>(t.kseg, part, out);
+}
+
+void launch_update_lr_seg(const DevTopo& t, int n, const double* W, const double* Q, const double* g, double* lam,
+                          double* r, hipStream_t st) {
+    if (n) k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, r, t.rb_design);
+}
+
+void launch_pivchol_seg(int nseg, const double* D, double rr_tol, double* T, int* rank, unsigned long long* kept_mask,
+                        hipStream_t st) {
+    k_pivchol<<<nseg, 128, 0, st>>>(64, D, rr_tol, T, rank, kept_mask);
+}
+
+// Z[row][:] = 0 for the rows of the designs set in frozen (bit d = design d)
+__global__ void k_zero_rows(long long n, const int* __restrict__ rb_design, unsigned long long frozen,
+                            double* __restrict__ Z) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= n * 64) return;
+    if ((frozen >> rb_design[(e >> 6) >> 8]) & 1ull) Z[e] = 0.0;
+}
+
+void launch_zero_rows(const DevTopo& t, int n, unsigned long long frozen, double* Z, hipStream_t st) {
+    if (frozen && n) k_zero_rows<<<(int)((64LL * n + 255) / 256), 256, 0, st>>>(n, t.rb_design, frozen, Z);
+}
+
 // Z[row][c] = 0 for every column c with bit c of mask set (n x k, k <= 64)
 __global__ void k_zero_cols(long long n, int k, unsigned long long mask, double* __restrict__ Z) {
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -827,7 +953,7 @@ void launch_update_lr(int n, int k, const double* W, const double* Q, const doub
                       hipStream_t st) {
     if (!n) return;
     if (k == 64)
-        k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, r);
+        k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, r, nullptr);
     else
         k_update_lr<<<(n + 255) / 256, 256, 0, st>>>(n, k, W, Q, g, lam, r);
 }

@@ -52,6 +52,13 @@ struct CoarseBlk {
 struct CoarseTile {   // 16 rows r0 .. r0 + 15 (block-local) of block blk
     int blk, r0;
 };
+// One design's rows in a segmented Krylov block (several designs, each with its own search
+// directions in the same 64 columns): rows row0 .. row0 + nrows - 1 (nrows a multiple of 256;
+// every 256-row block belongs to one design), base = its share of the Gram workgroups.
+struct KrySeg {
+    int row0, nrows, base;
+};
+
 // Host-side launch parameters of one design inside a context holding several (a single design
 // has one entry with zero offsets).
 struct DesignDev {
@@ -75,6 +82,11 @@ struct DevTopo {
     int n_ctiles = 0;
     std::vector<DesignDev> dsg;   // host side: per-design ranges for the per-design launches
     const int* seg = nullptr;     // device: (first lambda row, rows) per design
+    // segmented Krylov (several designs with their own directions): per-design row ranges and
+    // the design of every 256-row block; null / empty for one design
+    const KrySeg* kseg = nullptr;
+    std::vector<KrySeg> hkseg;
+    const int* rb_design = nullptr;
     const double* K0dev = nullptr;    // unit-modulus element matrix (row-major)
     long long nb_tot = 0, nc_tot = 0, ni_tot = 0, nloc_tot = 0, n_dof = 0;
     const SubMeta* subs = nullptr;
@@ -182,8 +194,25 @@ void launch_proj_apply(const DevTopo& t, int k, const double* tcoef, const doubl
 void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
                  double* out, hipStream_t st);
 int gram_chunks(int n, int nblk);
-constexpr long long kGramPartCap = 4096ll * kMaxDirs * kMaxDirs;   // doubles in the partial-sum buffer
+constexpr long long kGramPartCap = 4 * 4096ll * kMaxDirs * kMaxDirs;   // doubles in the partial-sum buffer
 // out = beta C + alpha sum_b A_b M_b (FP64 matrix cores), A_b n x kd, M_b kd x kd
+// Segmented forms (kd = 64, several designs): Gram products per design (out[(d*nblk + b)*4096]),
+// products whose 64x64 matrix is the row's design's (Mats + design * mstride), gamma per design,
+// lambda/r update with each row's design's gamma, one pivoted Cholesky per design, rows of
+// frozen designs zeroed.
+void launch_gram_seg(const DevTopo& t, int n, const double* const* Aptrs, int nblk, const double* B, double* part,
+                     double* out, hipStream_t st);
+void launch_ts_seg(const DevTopo& t, int n, int nblk, const double* const* Aptrs, const double* Mats, long long mstride,
+                   const double* C, double* out, double alpha, double beta, hipStream_t st);
+void launch_ts_pair_seg(const DevTopo& t, int n, const double* const* Aptrs, const double* const* Aptrs2,
+                        const double* Mats, double* out, double* out2, hipStream_t st);
+void launch_gemv_t_seg(const DevTopo& t, int n, const double* A, const double* x, double* part, double* out,
+                       hipStream_t st);
+void launch_update_lr_seg(const DevTopo& t, int n, const double* W, const double* Q, const double* g, double* lam,
+                          double* r, hipStream_t st);
+void launch_pivchol_seg(int nseg, const double* D, double rr_tol, double* T, int* rank, unsigned long long* kept_mask,
+                        hipStream_t st);
+void launch_zero_rows(const DevTopo& t, int n, unsigned long long frozen, double* Z, hipStream_t st);
 // out = A Mats and out2 = A2 Mats (one stored block each, n x kd; Mats kd x kd) in one launch
 void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* const* Aptrs2, const double* Mats,
                     double* out, double* out2, hipStream_t st);

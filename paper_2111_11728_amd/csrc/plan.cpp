@@ -390,7 +390,7 @@ std::string build_plan(const feti_mesh* mesh, const feti_partition* part, const 
 }
 
 std::string build_plan_batched(int nd, const feti_mesh* meshes, const feti_partition* parts, const feti_opts* opts,
-                               Plan& U, std::vector<DesignMeta>& D) {
+                               Plan& U, std::vector<DesignMeta>& D, bool segmented) {
     if (nd < 1 || !meshes || !parts) return "need at least one design";
     U = Plan();
     D.assign(nd, DesignMeta{});
@@ -430,7 +430,7 @@ std::string build_plan_batched(int nd, const feti_mesh* meshes, const feti_parti
         M.n_lambda = P.n_lambda;
         M.cg0 = U.n_cg;
         M.n_cg = P.n_cg;
-        M.grp0 = U.n_groups;
+        M.grp0 = segmented ? 0 : U.n_groups;
         M.n_groups = P.n_groups;
         for (int a = 0; a < 3; ++a) {
             M.nel[a] = P.nel[a];
@@ -491,8 +491,22 @@ std::string build_plan_batched(int nd, const feti_mesh* meshes, const feti_parti
         U.n_nodes += P.n_nodes;
         U.n_dof += P.n_dof;
         U.n_lambda += P.n_lambda;
+        M.n_rows = P.n_lambda;
+        if (segmented) {   // empty rows up to a multiple of 256
+            const int pad = (256 - P.n_lambda % 256) % 256;
+            for (int q = 0; q < pad; ++q) {
+                for (int t = 0; t < 2; ++t) {
+                    U.row_s.push_back(-1);
+                    U.row_j.push_back(0);
+                    U.row_sg.push_back(0);
+                }
+                U.row_sh.push_back(-1);
+            }
+            U.n_lambda += pad;
+            M.n_rows += pad;
+        }
         U.n_cg += P.n_cg;
-        U.n_groups += P.n_groups;
+        U.n_groups = segmented ? std::max(U.n_groups, P.n_groups) : U.n_groups + P.n_groups;
         U.n_alpha += P.n_alpha;
     }
     if (nd == 1) {

@@ -78,6 +78,7 @@ struct DesignMeta {
     int sub0 = 0, n_sub = 0;
     int64_t el0 = 0, n_el = 0, node0 = 0, n_nodes = 0, dof0 = 0, n_dof = 0;
     int lam0 = 0, n_lambda = 0, cg0 = 0, n_cg = 0, grp0 = 0, n_groups = 0;
+    int n_rows = 0;   // lambda rows reserved for the design (n_lambda, padded when segmented)
     int nel[3] = {1, 1, 1}, nsub[3] = {1, 1, 1};
     std::vector<int> ax_first[3], ax_cnt[3];
 };
@@ -85,7 +86,9 @@ struct DesignMeta {
 // The union of nd designs (same dimension, method and options) as one decomposition: the
 // per-design plans concatenated with offsets. The union's nel/nsub/ax_* are those of design 0
 // when nd == 1 and unused otherwise (per-design data is in D).
+// segmented: every design keeps its own direction groups (numbered from 0; the union's n_groups
+// is their maximum) and its lambda rows are padded with empty rows (no side) to a multiple of 256.
 std::string build_plan_batched(int nd, const feti_mesh* meshes, const feti_partition* parts, const feti_opts* opts,
-                               Plan& U, std::vector<DesignMeta>& D);
+                               Plan& U, std::vector<DesignMeta>& D, bool segmented = false);
 
 }  // namespace feti
