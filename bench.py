@@ -248,6 +248,10 @@ def main():
     ctx = make("fp32")
     sizes = ctx.sizes
     n_l = sizes["n_lambda"]
+    # tile shapes of the in-solve F*Lambda chosen on the device (no cache: tuned every run)
+    tune = ctx.feti_autotune(reps=5)
+    log(f"autotune: max_red {tune['max_red']}, max_d {tune['max_d']}, xcd {tune['xcd']}, split_d {tune['split_d']}: "
+        f"{tune['us']:.1f} us (default shapes {tune['us_default']:.1f} us)")
 
     # ---- F*Lambda microbenchmark (k = 64 directions) ----
     k = 64
@@ -343,7 +347,7 @@ def main():
         "setup_ms": setup_m, "iters": gpu_iters, "refinements": info_m["refinements"],
         "fp64_fallback": info_m["fp64_fallback"],
         "true_rel_res": info_m["true_rel_res"], "fp64": res64,
-        "flambda": fl, "roofline": roof,
+        "flambda": fl, "roofline": roof, "autotune": tune,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a 4x4-subdomain sample)")

@@ -178,6 +178,27 @@ feti_status feti_setup_batched(int n_designs, const feti_mesh* meshes, const fet
                                const feti_opts* opts, const double* rho, double p, double E0, double Emin,
                                void* stream, feti_ctx** out);
 
+/* F*Lambda tile shapes. */
+typedef struct {
+    int max_red;              /* reduced-precision row blocks (of 16 rows) per tile, 1..32 */
+    int max_d;                /* FP64 row blocks per tile, 1..16 */
+    int xcd;                  /* 1: the tiles of one subdomain are placed on one XCD (shared L2) */
+    int split_d;              /* FP64 row blocks per split-contraction tile (hybrid precision,
+                                 subdomains that failed the round-off test), 1..4 */
+    double us;                /* in-solve F*Lambda kernel time with these shapes, microseconds */
+    double us_default;        /* the same with the default shapes (32, 16, 1, 4) */
+    int from_cache;           /* 1: read from the cache file, not timed */
+} feti_tuning;
+
+/* Autotuner of the F*Lambda tile shapes: times the context's in-solve F*Lambda (k = 64 columns,
+ * the context's precision, hybrid lists included) over reps launches for every candidate in
+ * max_red {32, 16} x max_d {16, 8, 4} x xcd {1, 0} x split_d {4, 2}, keeps the fastest (a
+ * change from the defaults must gain 2%) and applies it to every tile list of the context. cache_path (host string, optional): a JSON
+ * file of earlier results keyed by (subdomains, n_b bucket of 32, precision, hybrid); a hit is
+ * applied without timing, a miss is timed and written back. out: host, optional. Results of
+ * F*Lambda do not depend on the tile shapes (each row's contraction order is fixed). */
+feti_status feti_autotune(feti_ctx* ctx, int reps, const char* cache_path, feti_tuning* out);
+
 /* Ranges of design d (0 <= d < n_designs) in the concatenated arrays. */
 feti_status feti_design_layout(feti_ctx* ctx, int d, feti_design* out);
 

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -132,6 +133,12 @@ struct feti_ctx {
     // designs held by the context (one, or several independent ones as a disjoint union)
     std::vector<DesignMeta> designs;
     bool segmented = false;   // several designs, each with its own S-FETI directions
+    // F*Lambda tile shapes (chosen by feti_autotune, defaults otherwise) and the per-subdomain
+    // round-off verdicts of the hybrid lists
+    feti_tuning tune{2 * kFlWaves, kFlWaves, 1, 4, 0.0, 0.0, 0};
+    std::vector<int> sub_ok;
+    FlTile *fl64_dev = nullptr, *flred_dev = nullptr;
+    int fl64_cap = 0, flred_cap = 0;
     std::vector<CoarseBlk> hcblk;
     GemmDesc* d_cc_gemm = nullptr;
     PotrfDesc* d_cc_potrf = nullptr;
@@ -203,6 +210,8 @@ struct feti_ctx {
         if (QH_dev) hipFree(QH_dev);
         if (Psi) hipFree(Psi);
         if (fl_hyb_red_dev) hipFree(fl_hyb_red_dev);
+        if (fl64_dev) hipFree(fl64_dev);
+        if (flred_dev) hipFree(flred_dev);
         if (fl_hyb_64_dev) hipFree(fl_hyb_64_dev);
         for (auto& e : ev)
             if (e) hipEventDestroy(e);
@@ -219,12 +228,13 @@ struct RbRange {
 };
 // max_d caps the FP64 row blocks of one tile (small tiles spread FP64 work over many CUs);
 // xcd = false lists the tiles in order (no XCD grouping, no empty slots).
-std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, int max_d = kFlWaves, bool xcd = true) {
+std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, int max_d = kFlWaves, bool xcd = true,
+                               int max_red = 2 * kFlWaves) {
     std::vector<std::vector<FlTile>> bucket(8);
     for (int s = 0; s < (int)rr.size(); ++s) {
         RbRange r = rr[s];
         while (r.n_red > 0 || r.n_d > 0) {
-            FlTile T{s, r.red0, std::min(r.n_red, 2 * kFlWaves), r.d0, 0, flags, 0, 0};
+            FlTile T{s, r.red0, std::min({r.n_red, 2 * kFlWaves, max_red}), r.d0, 0, flags, 0, 0};
             const int mixed = (flags & kFlSplitK) ? 0 : ((T.n_red & 1) && r.n_d > 0 ? 1 : 0);
             T.n_d = std::min({r.n_d, max_d, kFlWaves - (T.n_red + 1) / 2 + mixed});
             r.red0 += T.n_red;
@@ -243,6 +253,51 @@ std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, in
             out.push_back(i < bucket[x].size() ? bucket[x][i] : FlTile{-1, 0, 0, 0, 0, 0, 0, 0});
     while (!out.empty() && out.back().s < 0) out.pop_back();
     return out;
+}
+
+// F*Lambda work lists for the context's tile shapes (c->tune): every row block in FP64, every
+// row block in the reduced precision, and, after the round-off test, the hybrid lists:
+// subdomains that passed get reduced precision for their F_s row blocks and FP64 for the blocks
+// holding F_rc^T rows (the coarse right-hand side stays FP64: Kbar_cc^{-1} amplifies its errors)
+// in the same tile; subdomains that failed run in FP64, in a second launch of split-contraction
+// tiles spread over many CUs.
+void build_fl_tiles(feti_ctx* c) {
+    DevTopo& t = c->t;
+    const int ns = c->P.n_sub;
+    const feti_tuning& q = c->tune;
+    auto put = [&](const std::vector<FlTile>& v, FlTile*& dev, int& cap, FlTiles& out) {
+        if ((int)v.size() > cap) {
+            if (dev) {
+                HIPCHK(hipStreamSynchronize(c->st));
+                HIPCHK(hipFree(dev));
+            }
+            HIPCHK(hipMalloc(&dev, sizeof(FlTile) * std::max<size_t>(1, v.size())));
+            cap = (int)v.size();
+        }
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(dev, v.data(), sizeof(FlTile) * v.size(), hipMemcpyHostToDevice, c->st));
+        out = FlTiles{dev, (int)v.size()};
+    };
+    std::vector<RbRange> r64(ns), rred(ns);
+    for (int s = 0; s < ns; ++s) {
+        const int nrb = c->hsubs[s].rows_F / 16;
+        r64[s] = RbRange{0, 0, 0, nrb};
+        rred[s] = RbRange{0, nrb, 0, 0};
+    }
+    put(pack_tiles(r64, 0, q.max_d, q.xcd != 0), c->fl64_dev, c->fl64_cap, t.fl64);
+    put(pack_tiles(rred, 0, q.max_d, q.xcd != 0, q.max_red), c->flred_dev, c->flred_cap, t.flred);
+    if (c->hybrid && (int)c->sub_ok.size() == ns) {
+        std::vector<RbRange> rr(ns), rd(ns);
+        for (int s = 0; s < ns; ++s) {
+            const SubMeta& M = c->hsubs[s];
+            const int nrb = M.rows_F / 16, t0 = M.n_c > 0 ? M.rowT / 16 : nrb;
+            rr[s] = c->sub_ok[s] ? RbRange{0, t0, t0, nrb - t0} : RbRange{0, 0, 0, 0};
+            rd[s] = c->sub_ok[s] ? RbRange{0, 0, 0, 0} : RbRange{0, 0, 0, nrb};
+        }
+        put(pack_tiles(rr, kFlNoT, q.max_d, q.xcd != 0, q.max_red), c->fl_hyb_red_dev, c->fl_hyb_red_cap,
+            c->fl_hyb_red);
+        put(pack_tiles(rd, kFlSplitK, q.split_d, false), c->fl_hyb_64_dev, c->fl_hyb_64_cap, c->fl_hyb_64);
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
 }
 
 void build_layout(feti_ctx* c) {
@@ -473,14 +528,6 @@ void build_layout(feti_ctx* c) {
     c->d_potrf_one = c->upload(std::vector<PotrfDesc>{PotrfDesc{0, nsmall, nsmall}});
     c->d_trsm_one = c->upload(std::vector<TrsmDesc>{TrsmDesc{0, 0, nsmall, nsmall, nsmall, nsmall}});
 
-    // F*Lambda work lists: every row block in FP64, or every row block in the reduced precision
-    std::vector<RbRange> r64(ns), rred(ns);
-    for (int s = 0; s < ns; ++s) {
-        const int nrb = c->hsubs[s].rows_F / 16;
-        r64[s] = RbRange{0, 0, 0, nrb};
-        rred[s] = RbRange{0, nrb, 0, 0};
-    }
-    const std::vector<FlTile> tiles64 = pack_tiles(r64), tilesred = pack_tiles(rred);
 
     // topology arrays
     std::vector<int> bq_s(t.nb_tot);
@@ -543,8 +590,7 @@ void build_layout(feti_ctx* c) {
         }
         t.dsg.push_back(E);
     }
-    t.fl64 = FlTiles{c->upload(tiles64), (int)tiles64.size()};
-    t.flred = FlTiles{c->upload(tilesred), (int)tilesred.size()};
+    build_fl_tiles(c);
     c->pivdev = c->alloc<double>(ns);
     std::vector<double> K0 = element_K0(P.dim, P.nu);
     c->K0dev = c->upload(K0);
@@ -630,7 +676,8 @@ void classify_precision(feti_ctx* c) {
     std::vector<double> dev(t.n_sub);
     HIPCHK(hipMemcpyAsync(dev.data(), c->pivdev, sizeof(double) * t.n_sub, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    std::vector<int> ok(t.n_sub);
+    std::vector<int>& ok = c->sub_ok;
+    ok.assign(t.n_sub, 0);
     for (int s = 0; s < t.n_sub; ++s) {
         ok[s] = dev[s] <= 2e-2 ? 1 : 0;
         c->n_fp64_subs += 1 - ok[s];
@@ -641,31 +688,8 @@ void classify_precision(feti_ctx* c) {
         fprintf(stderr, "[feti] round-off metric quantiles: 50%% %.2e 80%% %.2e 90%% %.2e 95%% %.2e max %.2e\n",
                 d2[d2.size() / 2], d2[d2.size() * 8 / 10], d2[d2.size() * 9 / 10], d2[d2.size() * 95 / 100], d2.back());
     }
-    // Subdomains that passed: reduced precision for their F_s row blocks, FP64 for the blocks
-    // holding F_rc^T rows (the coarse right-hand side stays FP64: Kbar_cc^{-1} amplifies its
-    // errors), in the same tile. Subdomains that failed: FP64, in a second launch of split-
-    // contraction tiles of four row blocks, spread over many CUs.
-    std::vector<RbRange> rr(t.n_sub), rd(t.n_sub);
-    for (int s = 0; s < t.n_sub; ++s) {
-        const SubMeta& M = c->hsubs[s];
-        const int nrb = M.rows_F / 16, t0 = M.n_c > 0 ? M.rowT / 16 : nrb;
-        rr[s] = ok[s] ? RbRange{0, t0, t0, nrb - t0} : RbRange{0, 0, 0, 0};
-        rd[s] = ok[s] ? RbRange{0, 0, 0, 0} : RbRange{0, 0, 0, nrb};
-    }
-    const std::vector<FlTile> tr = pack_tiles(rr, kFlNoT), td = pack_tiles(rd, kFlSplitK, 4, false);
-    auto put = [&](const std::vector<FlTile>& v, FlTile*& dev, int& cap, FlTiles& out) {
-        if ((int)v.size() > cap) {
-            if (dev) HIPCHK(hipFree(dev));
-            HIPCHK(hipMalloc(&dev, sizeof(FlTile) * v.size()));
-            cap = (int)v.size();
-        }
-        if (!v.empty()) HIPCHK(hipMemcpyAsync(dev, v.data(), sizeof(FlTile) * v.size(), hipMemcpyHostToDevice, st));
-        out = FlTiles{dev, (int)v.size()};
-    };
-    put(tr, c->fl_hyb_red_dev, c->fl_hyb_red_cap, c->fl_hyb_red);
-    put(td, c->fl_hyb_64_dev, c->fl_hyb_64_cap, c->fl_hyb_64);
-    HIPCHK(hipStreamSynchronize(st));
     c->hybrid = true;
+    build_fl_tiles(c);
 }
 
 struct Timer {
@@ -1640,6 +1664,103 @@ feti_status feti_setup_batched(int n_designs, const feti_mesh* meshes, const fet
     if (rs != FETI_OK) return rs;
     *out = c.release();
     return FETI_OK;
+}
+
+namespace {
+// Cache of tuned tile shapes: a JSON object with one entry per line,
+//   "key": {"max_red": 32, "max_d": 16, "xcd": 1, "split_d": 4, "us": 96.5},
+std::map<std::string, feti_tuning> read_tune_cache(const char* path) {
+    std::map<std::string, feti_tuning> out;
+    FILE* f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+        const char* q0 = std::strchr(line, '"');
+        const char* q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char* br = q1 ? std::strchr(q1, '{') : nullptr;
+        if (!br) continue;
+        feti_tuning t{};
+        if (std::sscanf(br, "{\"max_red\": %d, \"max_d\": %d, \"xcd\": %d, \"split_d\": %d, \"us\": %lf", &t.max_red,
+                        &t.max_d, &t.xcd, &t.split_d, &t.us) == 5)
+            out[std::string(q0 + 1, q1)] = t;
+    }
+    std::fclose(f);
+    return out;
+}
+
+void write_tune_cache(const char* path, const std::map<std::string, feti_tuning>& m) {
+    FILE* f = std::fopen(path, "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m) {
+        const feti_tuning& t = kv.second;
+        std::fprintf(f, " \"%s\": {\"max_red\": %d, \"max_d\": %d, \"xcd\": %d, \"split_d\": %d, \"us\": %.2f}%s\n",
+                     kv.first.c_str(), t.max_red, t.max_d, t.xcd, t.split_d, t.us, ++i < m.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+}
+
+// in-solve F*Lambda kernel time (ms, mean over reps after one warm-up) with the current shapes
+double time_flambda(feti_ctx* c, int reps) {
+    apply_F(c, 64, c->opts.precision, c->Zk, c->Qtmp, true);
+    double tot = 0.0;
+    for (int r = 0; r < reps; ++r) {
+        apply_F(c, 64, c->opts.precision, c->Zk, c->Qtmp, true);
+        HIPCHK(hipEventSynchronize(c->ev[3]));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+        tot += ms;
+    }
+    return tot / std::max(1, reps);
+}
+}  // namespace
+
+feti_status feti_autotune(feti_ctx* c, int reps, const char* cache_path, feti_tuning* out) {
+    if (!c) return fail(FETI_EINVAL, "null context");
+    if (c->P.n_lambda == 0) return fail(FETI_EINVAL, "no dual unknowns to tune for");
+    return guarded([&]() -> feti_status {
+        char key[256];
+        std::snprintf(key, sizeof(key), "flambda nsub=%d nb32=%d prec=%d hybrid=%d fp64subs=%d", c->P.n_sub,
+                      (c->t.max_nb + 31) / 32, c->opts.precision, c->hybrid ? 1 : 0, c->n_fp64_subs);
+        std::map<std::string, feti_tuning> cache = read_tune_cache(cache_path);
+        auto hit = cache.find(key);
+        if (hit != cache.end()) {
+            c->tune = hit->second;
+            c->tune.from_cache = 1;
+            build_fl_tiles(c);
+            if (out) *out = c->tune;
+            return FETI_OK;
+        }
+        // Zk, Qtmp: n_lambda x 64 work buffers; their contents do not change the timing
+        HIPCHK(hipMemsetAsync(c->Zk, 0, sizeof(double) * c->P.n_lambda * kMaxDirs, c->st));
+        const int rp = std::max(1, reps);
+        feti_tuning best{2 * kFlWaves, kFlWaves, 1, 4, 0.0, 0.0, 0};
+        c->tune = best;
+        build_fl_tiles(c);
+        const double t_def = time_flambda(c, rp);
+        best.us = 1e3 * t_def;
+        for (int mr : {32, 16})
+            for (int md : {16, 8, 4})
+                for (int xc : {1, 0})
+                    for (int sd : {4, 2}) {
+                        c->tune = feti_tuning{mr, md, xc, sd, 0.0, 0.0, 0};
+                        build_fl_tiles(c);
+                        const double tm = 1e3 * time_flambda(c, rp);
+                        // a change of shapes must gain at least 2% (timing noise keeps the defaults)
+                        if (tm < 0.98 * best.us) best = feti_tuning{mr, md, xc, sd, tm, 0.0, 0};
+                    }
+        best.us_default = 1e3 * t_def;
+        c->tune = best;
+        build_fl_tiles(c);
+        if (cache_path) {
+            cache[key] = best;
+            write_tune_cache(cache_path, cache);
+        }
+        if (out) *out = best;
+        return FETI_OK;
+    });
 }
 
 feti_status feti_design_layout(feti_ctx* c, int d, feti_design* out) {

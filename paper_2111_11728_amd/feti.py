@@ -63,6 +63,14 @@ class feti_design(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class feti_tuning(C.Structure):
+    _fields_ = [("max_red", C.c_int), ("max_d", C.c_int), ("xcd", C.c_int), ("split_d", C.c_int),
+                ("us", C.c_double), ("us_default", C.c_double), ("from_cache", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class feti_sizes(C.Structure):
     _fields_ = [("n_sub", C.c_int), ("n_dof", C.c_int), ("n_el", C.c_int), ("n_lambda", C.c_int), ("n_cg", C.c_int),
                 ("n_alpha", C.c_int), ("n_groups", C.c_int), ("nb_max", C.c_int), ("nb_min", C.c_int),
@@ -108,6 +116,7 @@ def lib():
                                        D, D, D, P, C.POINTER(P)]),
             "feti_design_layout": (I, [P, I, C.POINTER(feti_design)]),
             "feti_design_residuals": (I, [P, C.POINTER(D), I]),
+            "feti_autotune": (I, [P, I, C.c_char_p, C.POINTER(feti_tuning)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -263,6 +272,11 @@ class Context:
         _check(lib().feti_get_local(self.handle, s, what, buf.ctypes.data_as(C.POINTER(C.c_double)), cap,
                                     C.byref(r), C.byref(c)))
         return buf[:r.value * c.value].reshape(r.value, c.value).copy()
+
+    def feti_autotune(self, reps=5, cache=None) -> dict:
+        out = feti_tuning()
+        _check(lib().feti_autotune(self.handle, reps, None if cache is None else str(cache).encode(), C.byref(out)))
+        return out.as_dict()
 
     def feti_last_timing(self, what):
         ms = C.c_double(0)

@@ -418,6 +418,37 @@ def test_batched_designs_oracle_and_fd(dens):
     ctx.close()
 
 
+def test_autotune_shapes_and_cache(tmp_path):
+    """F*Lambda tile-shape autotuner on the 8x4 modular design in mixed precision: the tuned
+    shapes leave the product unchanged bit for bit (each row's contraction order does not
+    depend on the tiling), the chosen time is not worse than the default's, and a second call
+    with the same cache file applies the stored shapes without timing."""
+    prob = workloads.modular_2d(0)
+    print("case autotune", flush=True)
+    ctx = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", precision="fp32", tol=1e-8)
+    n = ctx.sizes["n_lambda"]
+    g = torch.Generator(device=DEV)
+    g.manual_seed(3)
+    L = torch.randn(n, 32, generator=g, dtype=torch.float64, device=DEV)
+    Q0 = torch.zeros_like(L)
+    Q1 = torch.zeros_like(L)
+    for prec in ("fp32", "fp64"):
+        ctx.feti_apply_F(32, prec, L, Q0)
+        cache = tmp_path / "tune.json"
+        t1 = ctx.feti_autotune(reps=3, cache=cache)
+        assert t1["from_cache"] == 0 and t1["us"] <= t1["us_default"]
+        assert 1 <= t1["max_red"] <= 32 and 1 <= t1["max_d"] <= 16 and 1 <= t1["split_d"] <= 4
+        ctx.feti_apply_F(32, prec, L, Q1)
+        assert torch.equal(Q0, Q1), prec
+        t2 = ctx.feti_autotune(reps=3, cache=cache)
+        assert t2["from_cache"] == 1
+        assert (t2["max_red"], t2["max_d"], t2["xcd"], t2["split_d"]) == (t1["max_red"], t1["max_d"], t1["xcd"],
+                                                                          t1["split_d"])
+        ctx.close()
+        ctx = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", precision="fp64", tol=1e-8)
+    ctx.close()
+
+
 def test_compliance_gradient_small():
     prob = workloads.cantilever_tfeti(3, nsub=(2, 2), m=4)
     print("case compliance", flush=True)
