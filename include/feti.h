@@ -98,6 +98,11 @@ typedef struct {
                                  and every 16th reduced iteration after it, applies F in both
                                  precisions, keeps the FP64 product and records eta (the largest
                                  measurement is kept). */
+    int graphs;               /* S-FETI: 1 = replay the per-iteration operator sequences (F*Lambda
+                                 with the coarse correction, fold and scatter; the preconditioner
+                                 with the residual dots) as captured hipGraphs, one per precision,
+                                 recaptured after a setup or an autotune. Needs a non-null stream
+                                 (capture is not allowed on the null stream); 0 = direct launches. */
 } feti_opts;
 
 typedef struct {

@@ -137,6 +137,20 @@ struct feti_ctx {
     // round-off verdicts of the hybrid lists
     feti_tuning tune{2 * kFlWaves, kFlWaves, 1, 4, 0.0, 0.0, 0};
     std::vector<int> sub_ok;
+    // captured per-iteration sequences (opts.graphs): F*Lambda per precision, preconditioner
+    struct GraphSlot {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t e = nullptr;
+        int key = -1;
+    };
+    GraphSlot g_apply[3], g_prec;
+    void drop_graphs() {
+        for (GraphSlot* gs : {&g_apply[0], &g_apply[1], &g_apply[2], &g_prec}) {
+            if (gs->e) hipGraphExecDestroy(gs->e);
+            if (gs->g) hipGraphDestroy(gs->g);
+            *gs = GraphSlot{};
+        }
+    }
     FlTile *fl64_dev = nullptr, *flred_dev = nullptr;
     int fl64_cap = 0, flred_cap = 0;
     std::vector<CoarseBlk> hcblk;
@@ -203,6 +217,7 @@ struct feti_ctx {
     }
     ~feti_ctx() {
         hipStreamSynchronize(st);
+        drop_graphs();
         for (void* p : allocs) hipFree(p);
         for (double* p : hist_chunks) hipFree(p);
         if (hpin) hipHostFree(hpin);
@@ -262,6 +277,7 @@ std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, in
 // in the same tile; subdomains that failed run in FP64, in a second launch of split-contraction
 // tiles spread over many CUs.
 void build_fl_tiles(feti_ctx* c) {
+    c->drop_graphs();   // captured launches refer to the old tile lists
     DevTopo& t = c->t;
     const int ns = c->P.n_sub;
     const feti_tuning& q = c->tune;
@@ -764,6 +780,7 @@ void coarse_inverse(feti_ctx* c) {
 
 // Assembly, factorisation and explicit local operators for the current densities.
 void numeric_setup(feti_ctx* c) {
+    c->drop_graphs();
     Timer tm(c, 2);
     const Plan& P = c->P;
     DevTopo& t = c->t;
@@ -864,6 +881,27 @@ void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool ti
     }
     launch_scatter(t, k, f32, c->Ybuf, Q, st);
     CHECK_LAUNCH();
+}
+
+// body() as a captured graph replayed on c->st (opts.graphs and a non-null stream), captured on
+// first use for the given key; otherwise body() is launched directly.
+template <class F>
+void run_graph(feti_ctx* c, feti_ctx::GraphSlot& gs, int key, F&& body) {
+    if (!c->opts.graphs || c->st == nullptr) {
+        body();
+        return;
+    }
+    if (!gs.e || gs.key != key) {
+        if (gs.e) HIPCHK(hipGraphExecDestroy(gs.e));
+        if (gs.g) HIPCHK(hipGraphDestroy(gs.g));
+        gs = feti_ctx::GraphSlot{};
+        HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+        body();
+        HIPCHK(hipStreamEndCapture(c->st, &gs.g));
+        HIPCHK(hipGraphInstantiate(&gs.e, gs.g, nullptr, nullptr, 0));
+        gs.key = key;
+    }
+    HIPCHK(hipGraphLaunch(gs.e, c->st));
 }
 
 void project(feti_ctx* c, int k, double* Y) {
@@ -1079,12 +1117,19 @@ struct PrecGate {
 int gated_apply(feti_ctx* c, PrecGate& g, bool replaced, double eps, double eps0, int k, const double* Z,
                 double* Q, double* scratch) {
     const int ch = g.choose(replaced, eps, eps0);
+    // the search block's product (Zk -> Qk) replays a captured graph per precision (opts.graphs)
+    auto apply = [&](int prec) {
+        if (Z == c->Zk && Q == c->Qk && prec >= 0 && prec < 3)
+            run_graph(c, c->g_apply[prec], k, [&] { apply_F(c, k, prec, Z, Q); });
+        else
+            apply_F(c, k, prec, Z, Q);
+    };
     if (ch == PrecGate::kFp64) {
-        apply_F(c, k, FETI_FP64, Z, Q);
+        apply(FETI_FP64);
         return FETI_FP64;
     }
     if (ch == PrecGate::kReduced) {
-        apply_F(c, k, g.prec, Z, Q);
+        apply(g.prec);
         return g.prec;
     }
     apply_F(c, k, FETI_FP64, Z, Q);
@@ -1242,10 +1287,12 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         }
         CHECK_LAUNCH();
         ++nb;
-        precondition(c, c->r, c->Zk, one, 0);
-        launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
-        launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
-        project(c, kd, c->Zk);
+        run_graph(c, c->g_prec, kd, [&] {
+            precondition(c, c->r, c->Zk, one, 0);
+            launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
+            launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
+            project(c, kd, c->Zk);
+        });
         for (int pass = 0; pass < passes; ++pass) orth(nb);
         CHECK_LAUNCH();
         // eps^2 (scal[0]), the rank (scal[8]) and the per-design values in one copy

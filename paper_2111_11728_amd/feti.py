@@ -43,7 +43,7 @@ class feti_partition(C.Structure):
 class feti_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("scaling", C.c_int), ("krylov", C.c_int), ("precond", C.c_int),
                 ("precision", C.c_int), ("tol", C.c_double), ("max_it", C.c_int), ("rr_tol", C.c_double),
-                ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double)]
+                ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double), ("graphs", C.c_int)]
 
 
 class feti_info(C.Structure):
@@ -151,7 +151,7 @@ class Spec:
     """ctypes views of a workloads.Problem (keeps the host arrays alive)."""
 
     def __init__(self, prob, method="fetidp", scaling="k", krylov="pcg", precond="dirichlet", precision="fp64",
-                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0):
+                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0, graphs=0):
         self.prob = prob
         fixed = np.ascontiguousarray(prob.fixed_dofs(), dtype=np.int32)
         self._fixed = fixed
@@ -175,7 +175,7 @@ class Spec:
                 self.part.cuts[a] = C.POINTER(C.c_int)()
             self.part.group[a] = (prob.groups[a] if (prob.groups is not None and a < prob.dim) else 0)
         self.opts = feti_opts(METHODS[method], SCALINGS[scaling], KRYLOVS[krylov], PRECONDS[precond],
-                              PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax)
+                              PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax, graphs)
 
 
 def feti_plan_sizes(spec: Spec) -> dict:
