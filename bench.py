@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--flambda-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64-solve", action="store_true")
+    ap.add_argument("--orth-fp32", action="store_true",
+                    help="opt-in: FP32 Gram-Schmidt against the stored directions on reduced iterations")
     ap.add_argument("--max-it", type=int, default=1000)
     ap.add_argument("--flambda-only", action="store_true",
                     help="only the F*Lambda microbenchmark and a calibration copy (for counter runs)")
@@ -238,7 +240,7 @@ def main():
 
     def make(precision):
         spec = feti.Spec(prob, method="fetidp", scaling="k", krylov="sfeti", precond="dirichlet",
-                         precision=precision, tol=args.tol, max_it=args.max_it)
+                         precision=precision, tol=args.tol, max_it=args.max_it, orth_fp32=int(args.orth_fp32))
         t0 = time.perf_counter()
         cx = feti.Context(spec, rho)
         log(f"setup {precision}: {time.perf_counter() - t0:.2f} s, {cx.sizes['device_bytes'] / 2**30:.1f} GiB")
@@ -304,7 +306,9 @@ def main():
             info = cx.feti_compliance_and_grad(rho, f, c, g, u)
             rec.append((cx.feti_last_timing(2), cx.feti_last_timing(3), info))
             log(f"step {i}: setup {rec[-1][0]:.1f} ms, solve {rec[-1][1]:.1f} ms, {info['iters']} iterations, "
-                f"true rel. residual {info['true_rel_res']:.2e}, fp64 fallback {info['fp64_fallback']}")
+                f"true rel. residual {info['true_rel_res']:.2e}, fp64 fallback {info['fp64_fallback']}, "
+                f"reduced {info['reduced_iters']}, eta {info['reduced_rel_err']:.2e} "
+                f"(orth {info['reduced_orth_err']:.2e})")
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / max(1, nsteps)
         return wall, rec
@@ -345,7 +349,9 @@ def main():
                    "n_dof": prob.n_dof, "n_lambda": n_l, "n_cg": sizes["n_cg"], "directions": sizes["n_groups"],
                    "tol": args.tol},
         "setup_ms": setup_m, "iters": gpu_iters, "refinements": info_m["refinements"],
-        "fp64_fallback": info_m["fp64_fallback"],
+        "fp64_fallback": info_m["fp64_fallback"], "reduced_iters": info_m["reduced_iters"],
+        "precision_probes": info_m["precision_probes"], "reduced_rel_err": info_m["reduced_rel_err"],
+        "reduced_orth_err": info_m["reduced_orth_err"], "orth_fp32": int(args.orth_fp32),
         "true_rel_res": info_m["true_rel_res"], "fp64": res64,
         "flambda": fl, "roofline": roof, "autotune": tune,
     }

@@ -103,6 +103,14 @@ typedef struct {
                                  with the residual dots) as captured hipGraphs, one per precision,
                                  recaptured after a setup or an autotune. Needs a non-null stream
                                  (capture is not allowed on the null stream); 0 = direct launches. */
+    int orth_fp32;            /* S-FETI with 64 directions and a reduced precision, opt-in: 1 = an
+                                 iteration on the reduced-precision operator also runs the block
+                                 Gram-Schmidt against the stored directions on the FP32 matrix
+                                 cores (FP64 history, FP64 update); probe iterations run both
+                                 forms and keep the FP64 one. Its error is amplified by about
+                                 sqrt(kappa(F)) in the F-inner product, so on strongly
+                                 heterogeneous designs it stalls the reduced pass and the solve
+                                 ends in FP64. 0 (default): FP64 on every iteration. */
 } feti_opts;
 
 typedef struct {
@@ -122,6 +130,8 @@ typedef struct {
     int reduced_iters;        /* iterations that applied the reduced-precision operator */
     int precision_probes;     /* iterations that applied F in both precisions to measure eta */
     double reduced_rel_err;   /* largest eta measured (0 if never measured) */
+    double reduced_orth_err;  /* orth_fp32: largest |Z_32 - Z_64| / |Z_64| of the orthogonalised
+                                 block on probe iterations (0 if never measured) */
 } feti_info;
 
 typedef struct {

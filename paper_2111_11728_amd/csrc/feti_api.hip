@@ -1110,6 +1110,10 @@ struct PrecGate {
         since = 0;
         ++probes;
     }
+    // relative error of the FP32 orthogonalisation on probe iterations (opt-in form; reported,
+    // not a gate input: see orth_gated)
+    double eta_orth = 0.0;
+    void record_orth(double e) { eta_orth = std::max(eta_orth, e); }
 };
 
 // Q = F Z (k columns) with the operator the gate picks; returns the precision whose product Q holds.
@@ -1216,18 +1220,45 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
     const int one = kd == 1;
     const bool seg = c->segmented && kd == kMaxDirs;
     const bool multi = c->designs.size() > 1 && !c->segmented && kd == c->P.n_groups;
-    // orthogonalisation of Zk against the stored blocks (per design when segmented)
-    auto orth = [&](int nb_) {
-        if (seg) {
-            launch_gram_seg(c->t, n, c->QH_dev, nb_, c->Zk, c->part, c->Psi, st);
-            launch_ts_seg(c->t, n, nb_, c->WH_dev, c->Psi, (long long)nb_ * 4096, c->Zk, c->Zk, -1.0, 1.0, st);
+    const int passes = c->opts.reorth == 2 ? 2 : 1;
+    // block classical Gram-Schmidt of Z against the stored blocks (per design when segmented),
+    // in FP64 or with the FP32 matrix-core forms (64 directions)
+    auto orth = [&](int nb_, bool f32, double* Z) {
+        for (int pass = 0; pass < passes; ++pass) {
+            if (seg) {
+                launch_gram_seg(c->t, n, c->QH_dev, nb_, Z, c->part, c->Psi, st, f32);
+                launch_ts_seg(c->t, n, nb_, c->WH_dev, c->Psi, (long long)nb_ * 4096, Z, Z, -1.0, 1.0, st, f32);
+            } else {
+                launch_gram(n, kd, kd, c->QH_dev, nb_, Z, c->part, c->Psi, st, f32);
+                launch_ts_gemm(n, kd, nb_, c->WH_dev, c->Psi, Z, Z, -1.0, 1.0, st, f32);
+            }
+        }
+    };
+    // Opt-in (orth_fp32): iterations on the reduced-precision operator also orthogonalise with the
+    // FP32 forms. Their error tilts the new block against the stored ones in the F-inner product:
+    // a Gram error of u |Q_j| |Z| is a cosine error of about u sqrt(kappa(F)) there, which the
+    // later directions cannot remove; on strongly heterogeneous designs that stalls the reduced
+    // pass (the caller's FP64 restart then finishes the solve), so FP64 is the default. A probe
+    // iteration runs both forms on a copy, keeps the FP64 one and reports |Z_32 - Z_64| / |Z_64|
+    // (a Euclidean diagnostic that does not see the F-inner-product amplification).
+    const bool orth_red_ok = kd == 64 && c->opts.orth_fp32 && g.prec != FETI_FP64;
+    auto orth_gated = [&](int nb_, int p_it, bool probed) {
+        if (orth_red_ok && probed) {
+            HIPCHK(hipMemcpyAsync(c->Qtmp, c->Zk, sizeof(double) * n * kd, hipMemcpyDeviceToDevice, st));
+            orth(nb_, false, c->Zk);
+            orth(nb_, true, c->Qtmp);
+            launch_diff_norms((long long)n * kd, c->Qtmp, c->Zk, c->part, c->scal + 4, st);
+            CHECK_LAUNCH();
+            HIPCHK(hipMemcpyAsync(c->hpin, c->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            wait_poll(c);
+            const double e = c->hpin[1] > 0.0 ? std::sqrt(c->hpin[0] / c->hpin[1]) : 0.0;
+            g.record_orth(e);
+            if (verbose()) fprintf(stderr, "[feti] orthogonalisation probe: eta %.3e\n", e);
         } else {
-            launch_gram(n, kd, kd, c->QH_dev, nb_, c->Zk, c->part, c->Psi, st);
-            launch_ts_gemm(n, kd, nb_, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st);
+            orth(nb_, orth_red_ok && p_it != FETI_FP64, c->Zk);
         }
     };
     const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
-    const int passes = c->opts.reorth == 2 ? 2 : 1;
     precondition(c, c->r, c->Zk, one, 0);
     launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
     launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
@@ -1254,7 +1285,9 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         ensure_history(c, kd, nb + 1);
         double* Wn = (double*)c->WH[nb];
         double* Qn = (double*)c->QH[nb];
+        const int probes_before = g.probes;
         const int p_it = gated_apply(c, g, replaced, o.eps, eps0, kd, c->Zk, c->Qk, c->Qtmp);
+        const bool probed = g.probes != probes_before;
         o.reduced += p_it != FETI_FP64;
         if (seg) {
             // per design: Delta_d = Q_d^T W_d, its pivoted Cholesky, W, Q, gamma_d = W_d^T r_d
@@ -1293,7 +1326,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
             project(c, kd, c->Zk);
         });
-        for (int pass = 0; pass < passes; ++pass) orth(nb);
+        orth_gated(nb, p_it, probed);
         CHECK_LAUNCH();
         // eps^2 (scal[0]), the rank (scal[8]) and the per-design values in one copy
         HIPCHK(hipMemcpyAsync(c->hpin, c->scal, (16 + 3 * c->designs.size()) * sizeof(double), hipMemcpyDeviceToHost,
@@ -1372,7 +1405,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
             if (converged(c, o.eps, eps0, tol)) break;
             project(c, kd, c->Zk);
-            for (int pass = 0; pass < passes; ++pass) orth(nb);
+            orth(nb, false, c->Zk);
             CHECK_LAUNCH();
             best = o.eps;
             it_best = it;
@@ -1430,7 +1463,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
     std::vector<int> ranks;
     KrylovOut tot;
     int refinements = 0, fallback = 0, probes = 0;
-    double eta_max = 0.0;
+    double eta_max = 0.0, eta_orth = 0.0;
     double eps0 = 0.0, true_rel = 0.0;
     int status = FETI_OK;
     if (n > 0) {
@@ -1516,6 +1549,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         }
         probes = gate.probes;
         eta_max = gate.measured ? gate.eta : 0.0;
+        eta_orth = gate.eta_orth;
     }
     recover(c, u);
     HIPCHK(hipEventRecord(c->ev[1], st));
@@ -1535,6 +1569,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         info->reduced_iters = tot.reduced;
         info->precision_probes = probes;
         info->reduced_rel_err = eta_max;
+        info->reduced_orth_err = eta_orth;
         if (info->res_hist && info->res_hist_cap > 0)
             for (int i = 0; i < (int)hist.size() && i < info->res_hist_cap; ++i) info->res_hist[i] = hist[i];
         if (info->rank_hist && info->res_hist_cap > 0)

@@ -206,12 +206,37 @@ typedef double v2d_t __attribute__((ext_vector_type(2)));
 
 constexpr int kTsWaves = 8;   // 128 output rows per workgroup
 
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+// The 16x16x4 matrix-core step in the two arithmetic types the orthogonalisation runs in. The
+// FP32 form reads the same FP64 operands and rounds them in registers; its accumulator rows are
+// 4*(lane/16) + v where the FP64 form's are lane/16 + 4v (column lane%16 in both).
+template <bool F32> struct MfmaT;
+template <> struct MfmaT<false> {
+    typedef double T;
+    typedef v4d_t V;
+    static __device__ __forceinline__ V step(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+};
+template <> struct MfmaT<true> {
+    typedef float T;
+    typedef v4f_t V;
+    static __device__ __forceinline__ V step(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+};
+
 // out = beta C + alpha sum_b A_b Psi_b (A_b = Aptrs[b], n x 64; Psi_b = Mats + 4096 b).
 // Wavefront: 16 output rows x 64 columns. Step t = 4 b + q contracts columns 16q..16q+15 of
 // A_b: lane (m = lane%16, g = lane/16) supplies A_b[row m][16q + 4g + s] at sub-step s, i.e.
 // one 32-byte load per step, issued a whole block (four steps) ahead; Psi_b is staged in LDS
 // in the matching operand order ((q*4 + j)*64 + lane)*4 + s <- Psi_b[16q + 4g + s][16j + m],
-// double-buffered per block.
+// double-buffered per block. F32: products on the FP32 matrix cores (Psi_b staged rounded to
+// FP32, A_b rounded as it is loaded), sums in FP32 per row, the update C + alpha acc in FP64.
+template <bool F32>
 __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
                                                         const double* __restrict__ Mats, const double* C, double* out,
                                                         double alpha, double beta, const double* const* Aptrs2,
@@ -223,19 +248,21 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
     }
     // several designs: the matrices of the design owning this workgroup's rows (a 256-row block)
     if (rb_design) Mats += (long long)rb_design[(blockIdx.x * (16 * kTsWaves)) >> 8] * mstride;
-    __shared__ __attribute__((aligned(16))) double Ps[2][4096];
+    typedef typename MfmaT<F32>::T T;
+    typedef typename MfmaT<F32>::V V;
+    __shared__ __attribute__((aligned(16))) T Ps[2][4096];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
     const int rb0 = blockIdx.x * (16 * kTsWaves) + 16 * wave;
     const int arow = rb0 + m;
     const bool av = arow < n;
     constexpr int kPer = 4096 / (64 * kTsWaves);
-    double pst[kPer];
+    T pst[kPer];
     auto load_psi = [&](int b) {
         const double* P = Mats + (long long)b * 4096;
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) pst[u] = P[tid + 64 * kTsWaves * u];
+        for (int u = 0; u < kPer; ++u) pst[u] = (T)P[tid + 64 * kTsWaves * u];
     };
-    auto store_psi = [&](double* Pb) {
+    auto store_psi = [&](T* Pb) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int e = tid + 64 * kTsWaves * u, kr = e >> 6, kc = e & 63;
@@ -248,9 +275,9 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
         const double* A = Aptrs[t >> 2];
         return *reinterpret_cast<const v4d_t*>(A + (long long)arow * 64 + 16 * (t & 3) + 4 * g);
     };
-    v4d_t acc[4];
+    V acc[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = v4d_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[j] = V{0, 0, 0, 0};
     v4d_t ring[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ring[q] = load_a(q);
@@ -259,30 +286,30 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
     __syncthreads();
     for (int b = 0; b < nblk; ++b) {
         if (b + 1 < nblk) load_psi(b + 1);
-        const double* Pb = Ps[b & 1];
+        const T* Pb = Ps[b & 1];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const v4d_t a = ring[q];
             ring[q] = load_a(4 * (b + 1) + q);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const v4d_t bv = *reinterpret_cast<const v4d_t*>(Pb + ((q * 4 + j) * 64 + lane) * 4);
+                const V bv = *reinterpret_cast<const V*>(Pb + ((q * 4 + j) * 64 + lane) * 4);
 #pragma unroll
-                for (int s2 = 0; s2 < 4; ++s2) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], bv[s2], acc[j], 0, 0, 0);
+                for (int s2 = 0; s2 < 4; ++s2) acc[j] = MfmaT<F32>::step(a[s2], bv[s2], acc[j]);
             }
         }
         if (b + 1 < nblk) store_psi(Ps[(b + 1) & 1]);
         __syncthreads();
     }
-    // D layout: lane holds rows g + 4v, column m of each 16x16 block j
+    // D layout: lane holds rows MfmaT::row(g, v), column m of each 16x16 block j
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int row = rb0 + g + 4 * v;
+        const int row = rb0 + MfmaT<F32>::row(g, v);
         if (row >= n) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const long long idx = (long long)row * 64 + 16 * j + m;
-            out[idx] = (beta == 0.0 ? 0.0 : beta * C[idx]) + alpha * acc[j][v];
+            out[idx] = (beta == 0.0 ? 0.0 : beta * C[idx]) + alpha * (double)acc[j][v];
         }
     }
 }
@@ -295,7 +322,8 @@ constexpr int kGrGroups = 256; // workgroups per round: one per CU
 // (pair-major) are split evenly over the G workgroups (G a multiple of 256, so no range spans
 // more than two pairs); within a workgroup the four wavefronts split each pair segment and
 // every wavefront accumulates two full 64 x 64 results (32 FP64 16x16 accumulators, one
-// wavefront per SIMD, loads kGrRing steps ahead). Rows/columns are permuted so that at step
+// wavefront per SIMD, loads kGrRing steps ahead; F32: FP32 matrix cores on the operands rounded
+// in registers, FP32 sums over the wavefront's rows). Rows/columns are permuted so that at step
 // st lane (m, g) loads A_b[4 st + g][4m..4m+3] and B[4 st + g][4m..4m+3]: accumulator row m'
 // of block ib is A column 4 m' + ib, column n' of block jb is B column 4 n' + jb. The
 // wavefront results meet in LDS (fixed order); segment slot t of workgroup w writes, for its
@@ -318,6 +346,7 @@ __device__ __forceinline__ int gram_seg_find(const KrySeg* segs, int nseg, int n
     return nseg - 1;
 }
 
+template <bool F32>
 __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double* const* __restrict__ Aptrs,
                                                    const double* __restrict__ B, double* __restrict__ part,
                                                    const KrySeg* __restrict__ segs, int nseg) {
@@ -345,13 +374,14 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
         const double* A0 = Aptrs[2 * pr] + arow0;
         const bool has1 = 2 * pr + 1 < nblk;
         const double* A1 = has1 ? Aptrs[2 * pr + 1] + arow0 : A0;
-        v4d_t acc[2][4][4];
+        typedef typename MfmaT<F32>::V V;
+        V acc[2][4][4];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[h][i][j] = v4d_t{0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < 4; ++j) acc[h][i][j] = V{0, 0, 0, 0};
         v4d_t ar0[kGrRing], ar1[kGrRing], br[kGrRing];
         auto ld = [&](int st, v4d_t& av0, v4d_t& av1, v4d_t& bv) {
             const int r = 4 * st + g;
@@ -374,10 +404,8 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
                         for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
                             for (int jb = 0; jb < 4; ++jb) {
-                                acc[0][ib][jb] =
-                                    __builtin_amdgcn_mfma_f64_16x16x4f64(ar0[d][ib], br[d][jb], acc[0][ib][jb], 0, 0, 0);
-                                acc[1][ib][jb] =
-                                    __builtin_amdgcn_mfma_f64_16x16x4f64(ar1[d][ib], br[d][jb], acc[1][ib][jb], 0, 0, 0);
+                                acc[0][ib][jb] = MfmaT<F32>::step(ar0[d][ib], br[d][jb], acc[0][ib][jb]);
+                                acc[1][ib][jb] = MfmaT<F32>::step(ar1[d][ib], br[d][jb], acc[1][ib][jb]);
                             }
                         ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
                     }
@@ -393,8 +421,7 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
                         for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
                             for (int jb = 0; jb < 4; ++jb)
-                                acc[0][ib][jb] =
-                                    __builtin_amdgcn_mfma_f64_16x16x4f64(ar0[d][ib], br[d][jb], acc[0][ib][jb], 0, 0, 0);
+                                acc[0][ib][jb] = MfmaT<F32>::step(ar0[d][ib], br[d][jb], acc[0][ib][jb]);
                         ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
                     }
                 }
@@ -403,14 +430,15 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && !has1) break;
-            // D layout: lane holds rows g + 4v, column m of block (ib, jb)
+            // D layout: lane holds rows MfmaT::row(g, v), column m of block (ib, jb)
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        red[wave * 4096 + (4 * (g + 4 * v) + ib) * 64 + 4 * m + jb] = acc[h][ib][jb][v];
+                        red[wave * 4096 + (4 * MfmaT<F32>::row(g, v) + ib) * 64 + 4 * m + jb] =
+                            (double)acc[h][ib][jb][v];
             __syncthreads();
             double* out = part + (((long long)wg * 2 + slot) * 2 + h) * 4096;
 #pragma unroll
@@ -534,11 +562,15 @@ __global__ void __launch_bounds__(256) k_rowsum_dot64(int n, const double* __res
 }
 
 void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
-                    double* out, double alpha, double beta, hipStream_t st) {
+                    double* out, double alpha, double beta, hipStream_t st, bool f32) {
     if (!n || !nblk) return;
-    if (kd == 64)
-        k_ts64<<<(n + 16 * kTsWaves - 1) / (16 * kTsWaves), 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha,
-                                                                                    beta, nullptr, nullptr, nullptr, 0);
+    const int nwg = (n + 16 * kTsWaves - 1) / (16 * kTsWaves);
+    if (kd == 64 && f32)
+        k_ts64<true><<<nwg, 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha, beta, nullptr, nullptr, nullptr,
+                                                    0);
+    else if (kd == 64)
+        k_ts64<false><<<nwg, 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha, beta, nullptr, nullptr,
+                                                     nullptr, 0);
     else
         k_ts_gemm<<<(n + 63) / 64, 256, 0, st>>>(n, kd, nblk, Aptrs, Mats, C, out, alpha, beta);
 }
@@ -547,7 +579,7 @@ void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* con
                     double* out, double* out2, hipStream_t st) {
     if (!n) return;
     if (kd == 64) {
-        k_ts64<<<dim3((n + 16 * kTsWaves - 1) / (16 * kTsWaves), 2), 64 * kTsWaves, 0, st>>>(
+        k_ts64<false><<<dim3((n + 16 * kTsWaves - 1) / (16 * kTsWaves), 2), 64 * kTsWaves, 0, st>>>(
             n, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, Aptrs2, out2, nullptr, 0);
         return;
     }
@@ -556,13 +588,16 @@ void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* con
 }
 
 void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
-                 double* out, hipStream_t st) {
+                 double* out, hipStream_t st, bool f32) {
     if (nblk == 0) return;
     if (ka == 64 && kb == 64 && n >= 64) {
         const int npair = (nblk + 1) / 2;
         const int G = kGrGroups * ((npair + kGrGroups - 1) / kGrGroups);
         if ((long long)G * 4 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
-        k_gram64<<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
+        if (f32)
+            k_gram64<true><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
+        else
+            k_gram64<false><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
         k_gram64_reduce<<<nblk * 64, 256, 0, st>>>(n, nblk, G, part, out, nullptr, 0);
         return;
     }
@@ -814,7 +849,7 @@ void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank,
 
 // ---- segmented forms (several designs, each with its own directions in the 64 columns) ----
 void launch_gram_seg(const DevTopo& t, int n, const double* const* Aptrs, int nblk, const double* B, double* part,
-                     double* out, hipStream_t st) {
+                     double* out, hipStream_t st, bool f32) {
     if (nblk == 0) return;
     const int nseg = (int)t.hkseg.size();
     const int npair = (nblk + 1) / 2;
@@ -822,21 +857,29 @@ void launch_gram_seg(const DevTopo& t, int n, const double* const* Aptrs, int nb
     for (const KrySeg& q : t.hkseg) G += std::max(npair, q.base);
     if ((long long)G * 4 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
     (void)n;
-    k_gram64<<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
+    if (f32)
+        k_gram64<true><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
+    else
+        k_gram64<false><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
     k_gram64_reduce<<<nseg * nblk * 64, 256, 0, st>>>(0, nblk, G, part, out, t.kseg, nseg);
 }
 
 void launch_ts_seg(const DevTopo& t, int n, int nblk, const double* const* Aptrs, const double* Mats, long long mstride,
-                   const double* C, double* out, double alpha, double beta, hipStream_t st) {
+                   const double* C, double* out, double alpha, double beta, hipStream_t st, bool f32) {
     if (!n || !nblk) return;
-    k_ts64<<<(n + 16 * kTsWaves - 1) / (16 * kTsWaves), 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha, beta,
-                                                                                nullptr, nullptr, t.rb_design, mstride);
+    const int nwg = (n + 16 * kTsWaves - 1) / (16 * kTsWaves);
+    if (f32)
+        k_ts64<true><<<nwg, 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha, beta, nullptr, nullptr,
+                                                    t.rb_design, mstride);
+    else
+        k_ts64<false><<<nwg, 64 * kTsWaves, 0, st>>>(n, nblk, Aptrs, Mats, C, out, alpha, beta, nullptr, nullptr,
+                                                     t.rb_design, mstride);
 }
 
 void launch_ts_pair_seg(const DevTopo& t, int n, const double* const* Aptrs, const double* const* Aptrs2,
                         const double* Mats, double* out, double* out2, hipStream_t st) {
     if (!n) return;
-    k_ts64<<<dim3((n + 16 * kTsWaves - 1) / (16 * kTsWaves), 2), 64 * kTsWaves, 0, st>>>(
+    k_ts64<false><<<dim3((n + 16 * kTsWaves - 1) / (16 * kTsWaves), 2), 64 * kTsWaves, 0, st>>>(
         n, 1, Aptrs, Mats, nullptr, out, 1.0, 0.0, Aptrs2, out2, t.rb_design, 4096);
 }
 

@@ -190,20 +190,23 @@ void launch_proj_apply(const DevTopo& t, int k, const double* tcoef, const doubl
 
 // ---- Krylov (k_krylov.hip) ----
 // partial Gram: for every block b < nblk (A_b = Aptrs[b]) and row chunk c:
-// part[(b*nchunk + c)][ka x kb] = A_b[rows of c]^T B[rows of c]
+// part[(b*nchunk + c)][ka x kb] = A_b[rows of c]^T B[rows of c]. f32 (ka = kb = 64 only): the
+// products on the FP32 matrix cores from the FP64 operands rounded in registers, FP32 partial sums
+// over each wavefront's rows, FP64 beyond.
 void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, const double* B, double* part,
-                 double* out, hipStream_t st);
+                 double* out, hipStream_t st, bool f32 = false);
 int gram_chunks(int n, int nblk);
 constexpr long long kGramPartCap = 4 * 4096ll * kMaxDirs * kMaxDirs;   // doubles in the partial-sum buffer
-// out = beta C + alpha sum_b A_b M_b (FP64 matrix cores), A_b n x kd, M_b kd x kd
+// out = beta C + alpha sum_b A_b M_b (FP64 matrix cores; f32 with kd = 64: the sum on the FP32
+// matrix cores, the update in FP64), A_b n x kd, M_b kd x kd
 // Segmented forms (kd = 64, several designs): Gram products per design (out[(d*nblk + b)*4096]),
 // products whose 64x64 matrix is the row's design's (Mats + design * mstride), gamma per design,
 // lambda/r update with each row's design's gamma, one pivoted Cholesky per design, rows of
 // frozen designs zeroed.
 void launch_gram_seg(const DevTopo& t, int n, const double* const* Aptrs, int nblk, const double* B, double* part,
-                     double* out, hipStream_t st);
+                     double* out, hipStream_t st, bool f32 = false);
 void launch_ts_seg(const DevTopo& t, int n, int nblk, const double* const* Aptrs, const double* Mats, long long mstride,
-                   const double* C, double* out, double alpha, double beta, hipStream_t st);
+                   const double* C, double* out, double alpha, double beta, hipStream_t st, bool f32 = false);
 void launch_ts_pair_seg(const DevTopo& t, int n, const double* const* Aptrs, const double* const* Aptrs2,
                         const double* Mats, double* out, double* out2, hipStream_t st);
 void launch_gemv_t_seg(const DevTopo& t, int n, const double* A, const double* x, double* part, double* out,
@@ -217,7 +220,7 @@ void launch_zero_rows(const DevTopo& t, int n, unsigned long long frozen, double
 void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* const* Aptrs2, const double* Mats,
                     double* out, double* out2, hipStream_t st);
 void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
-                    double* out, double alpha, double beta, hipStream_t st);
+                    double* out, double alpha, double beta, hipStream_t st, bool f32 = false);
 void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st,
                     unsigned long long* kept_mask = nullptr);   // kept_mask: bit j set when column j was kept
 // Z[:, c] = 0 for the columns c set in mask (n x k row-major)

@@ -43,7 +43,8 @@ class feti_partition(C.Structure):
 class feti_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("scaling", C.c_int), ("krylov", C.c_int), ("precond", C.c_int),
                 ("precision", C.c_int), ("tol", C.c_double), ("max_it", C.c_int), ("rr_tol", C.c_double),
-                ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double), ("graphs", C.c_int)]
+                ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double), ("graphs", C.c_int),
+                ("orth_fp32", C.c_int)]
 
 
 class feti_info(C.Structure):
@@ -51,7 +52,8 @@ class feti_info(C.Structure):
                 ("eps", C.c_double), ("true_rel_res", C.c_double), ("kept_directions", C.c_int),
                 ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int), ("rank_hist", C.POINTER(C.c_int)),
                 ("t_solve_ms", C.c_double), ("fp64_fallback", C.c_int),
-                ("reduced_iters", C.c_int), ("precision_probes", C.c_int), ("reduced_rel_err", C.c_double)]
+                ("reduced_iters", C.c_int), ("precision_probes", C.c_int), ("reduced_rel_err", C.c_double),
+                ("reduced_orth_err", C.c_double)]
 
 
 class feti_design(C.Structure):
@@ -151,7 +153,7 @@ class Spec:
     """ctypes views of a workloads.Problem (keeps the host arrays alive)."""
 
     def __init__(self, prob, method="fetidp", scaling="k", krylov="pcg", precond="dirichlet", precision="fp64",
-                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0, graphs=0):
+                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0, graphs=0, orth_fp32=0):
         self.prob = prob
         fixed = np.ascontiguousarray(prob.fixed_dofs(), dtype=np.int32)
         self._fixed = fixed
@@ -175,7 +177,8 @@ class Spec:
                 self.part.cuts[a] = C.POINTER(C.c_int)()
             self.part.group[a] = (prob.groups[a] if (prob.groups is not None and a < prob.dim) else 0)
         self.opts = feti_opts(METHODS[method], SCALINGS[scaling], KRYLOVS[krylov], PRECONDS[precond],
-                              PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax, graphs)
+                              PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax, graphs,
+                              orth_fp32)
 
 
 def feti_plan_sizes(spec: Spec) -> dict:
@@ -241,7 +244,8 @@ class Context:
                 "eps": info.eps, "true_rel_res": info.true_rel_res, "kept_directions": info.kept_directions,
                 "history": hist[:n].copy(), "ranks": ranks[:info.iters].copy(), "t_solve_ms": info.t_solve_ms,
                 "fp64_fallback": info.fp64_fallback, "reduced_iters": info.reduced_iters,
-                "precision_probes": info.precision_probes, "reduced_rel_err": info.reduced_rel_err}
+                "precision_probes": info.precision_probes, "reduced_rel_err": info.reduced_rel_err,
+                "reduced_orth_err": info.reduced_orth_err}
 
     def feti_compliance_and_grad(self, rho, f, c, dc, u=None):
         info = feti_info()
@@ -250,7 +254,7 @@ class Context:
         return {"status": st, "iters": info.iters, "true_rel_res": info.true_rel_res,
                 "refinements": info.refinements, "fp64_fallback": info.fp64_fallback,
                 "reduced_iters": info.reduced_iters, "precision_probes": info.precision_probes,
-                "reduced_rel_err": info.reduced_rel_err}
+                "reduced_rel_err": info.reduced_rel_err, "reduced_orth_err": info.reduced_orth_err}
 
     def feti_apply_F(self, k, precision, Lam, Q, pure=False):
         p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)

@@ -268,6 +268,37 @@ def test_mixed_precision_solve(precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mixed_orthogonalisation_fp32(precision):
+    """64 directions, opt-in orth_fp32: iterations on the reduced-precision operator also run
+    the block Gram-Schmidt against the stored directions on the FP32 matrix cores. On this
+    moderately conditioned cantilever, compared with the default (FP64 Gram-Schmidt): both reach
+    the tolerance, the iteration counts are within 1, both solutions match the direct solve to
+    the mixed-precision bound, and the FP32 step's error on probe iterations is reported."""
+    prob = workloads.cantilever_tfeti(3, nsub=(8, 8), m=16)
+    u_ref = fem.solve_problem(prob)
+    out = {}
+    for of in (1, 0):
+        print(f"case orth32 {precision} orth_fp32={of}", flush=True)
+        ctx = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", precision=precision, tol=1e-8, orth_fp32=of)
+        assert ctx.sizes["n_groups"] == 64
+        u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
+        info = ctx.feti_solve(_t(prob.load()), u)
+        ctx.close()
+        err = _rel(u.cpu().numpy(), u_ref)
+        print(f"  iters {info['iters']} reduced {info['reduced_iters']} probes {info['precision_probes']} "
+              f"eta {info['reduced_rel_err']:.2e} orth {info['reduced_orth_err']:.2e} "
+              f"true {info['true_rel_res']:.2e} u err {err:.2e}", flush=True)
+        assert info["true_rel_res"] <= 1e-8
+        assert err < 1e-6
+        out[of] = info
+    a, b = out[1], out[0]
+    assert a["reduced_iters"] > 0 and a["fp64_fallback"] == 0
+    assert abs(a["iters"] - b["iters"]) <= 1
+    assert 0.0 < a["reduced_orth_err"] < 1e-5   # FP32 rounding of the operands, Euclidean
+    assert b["reduced_orth_err"] == 0.0
+
+
 def test_c2_sfeti_fetidp():
     """Modular 8x4 design of 32x32 modules (contrast 1e-6): S-FETI-DP with k-scaling.
 
