@@ -229,6 +229,22 @@ template <> struct MfmaT<true> {
     static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
 };
 
+// Streamed operands go through buffer resources covering exactly the rows a wavefront owns:
+// a load past num_records returns zeros without touching memory, so the loads of the ring
+// are unconditional (no per-lane branches, no zero fill) and the compiler can count them.
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const double* base, int nbytes) {
+    // wavefront-uniform by construction; readfirstlane keeps the descriptor in scalar registers
+    // (a per-lane copy would turn every load into a loop over distinct descriptors)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
+                                             __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
+}
+__device__ __forceinline__ v4d_t load4d(__amdgpu_buffer_rsrc_t r, int off) {
+    const v2d_t lo = __builtin_bit_cast(v2d_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const v2d_t hi = __builtin_bit_cast(v2d_t, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
+    return v4d_t{lo[0], lo[1], hi[0], hi[1]};
+}
+
 // out = beta C + alpha sum_b A_b Psi_b (A_b = Aptrs[b], n x 64; Psi_b = Mats + 4096 b).
 // Wavefront: 16 output rows x 64 columns. Step t = 4 b + q contracts columns 16q..16q+15 of
 // A_b: lane (m = lane%16, g = lane/16) supplies A_b[row m][16q + 4g + s] at sub-step s, i.e.
@@ -251,10 +267,11 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
     typedef typename MfmaT<F32>::T T;
     typedef typename MfmaT<F32>::V V;
     __shared__ __attribute__((aligned(16))) T Ps[2][4096];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rb0 = blockIdx.x * (16 * kTsWaves) + 16 * wave;
-    const int arow = rb0 + m;
-    const bool av = arow < n;
+    const int nbytes = max(0, min(16, n - rb0)) * 512;   // this wavefront's rows of every A_b
+    const int aoff = m * 512 + 32 * g;                     // + 128 q for column block q
     constexpr int kPer = 4096 / (64 * kTsWaves);
     T pst[kPer];
     auto load_psi = [&](int b) {
@@ -269,28 +286,28 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
             Pb[(((kr >> 4) * 4 + (kc >> 4)) * 64 + ((kr & 15) >> 2) * 16 + (kc & 15)) * 4 + (kr & 3)] = pst[u];
         }
     };
-    const int nst = 4 * nblk;
-    auto load_a = [&](int t) -> v4d_t {
-        if (!av || t >= nst) return v4d_t{0.0, 0.0, 0.0, 0.0};
-        const double* A = Aptrs[t >> 2];
-        return *reinterpret_cast<const v4d_t*>(A + (long long)arow * 64 + 16 * (t & 3) + 4 * g);
+    // block b's rows of this wavefront (no bytes past the last block)
+    auto rsrc_of = [&](int b) {
+        return rows_rsrc(Aptrs[min(b, nblk - 1)] + (long long)rb0 * 64, b < nblk ? nbytes : 0);
     };
     V acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = V{0, 0, 0, 0};
     v4d_t ring[4];
+    __amdgpu_buffer_rsrc_t ra = rsrc_of(0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ring[q] = load_a(q);
+    for (int q = 0; q < 4; ++q) ring[q] = load4d(ra, aoff + 128 * q);
     load_psi(0);
     store_psi(Ps[0]);
     __syncthreads();
     for (int b = 0; b < nblk; ++b) {
         if (b + 1 < nblk) load_psi(b + 1);
         const T* Pb = Ps[b & 1];
+        ra = rsrc_of(b + 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const v4d_t a = ring[q];
-            ring[q] = load_a(4 * (b + 1) + q);
+            ring[q] = load4d(ra, aoff + 128 * q);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const V bv = *reinterpret_cast<const V*>(Pb + ((q * 4 + j) * 64 + lane) * 4);
@@ -353,7 +370,8 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
     __shared__ double red[4 * 4096];
     const int wg = blockIdx.x;
     int G = gridDim.x, w = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int npair = (nblk + 1) >> 1;
     long long arow0 = 0;   // first element of this workgroup's design in every n x 64 block
     if (segs) {
@@ -383,47 +401,52 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[h][i][j] = V{0, 0, 0, 0};
         v4d_t ar0[kGrRing], ar1[kGrRing], br[kGrRing];
+        // rows [4 w0, min(4 w1, n)) of the three operands
+        const long long row_lo = 4LL * w0;
+        const int nbytes = (int)std::max(0LL, std::min((long long)n, 4LL * w1) - row_lo) * 512;
+        const __amdgpu_buffer_rsrc_t rA0 = rows_rsrc(A0 + row_lo * 64, nbytes);
+        const __amdgpu_buffer_rsrc_t rA1 = rows_rsrc(A1 + row_lo * 64, has1 ? nbytes : 0);
+        const __amdgpu_buffer_rsrc_t rB = rows_rsrc(B + row_lo * 64, nbytes);
         auto ld = [&](int st, v4d_t& av0, v4d_t& av1, v4d_t& bv) {
-            const int r = 4 * st + g;
-            if (st < w1 && r < n) {
-                av0 = *reinterpret_cast<const v4d_t*>(A0 + (long long)r * 64 + 4 * m);
-                if (has1) av1 = *reinterpret_cast<const v4d_t*>(A1 + (long long)r * 64 + 4 * m);
-                bv = *reinterpret_cast<const v4d_t*>(B + (long long)r * 64 + 4 * m);
-            } else {
-                av0 = av1 = bv = v4d_t{0.0, 0.0, 0.0, 0.0};
-            }
+            const int off = ((st - w0) * 4 + g) * 512 + 32 * m;
+            av0 = load4d(rA0, off);
+            av1 = load4d(rA1, off);
+            bv = load4d(rB, off);
         };
 #pragma unroll
         for (int d = 0; d < kGrRing; ++d) ld(w0 + d, ar0[d], ar1[d], br[d]);
+        auto prod2 = [&](int d) {
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    acc[0][ib][jb] = MfmaT<F32>::step(ar0[d][ib], br[d][jb], acc[0][ib][jb]);
+                    acc[1][ib][jb] = MfmaT<F32>::step(ar1[d][ib], br[d][jb], acc[1][ib][jb]);
+                }
+        };
+        auto prod1 = [&](int d) {   // a single block (the last one of an odd count)
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    acc[0][ib][jb] = MfmaT<F32>::step(ar0[d][ib], br[d][jb], acc[0][ib][jb]);
+        };
+        // whole rings without guards: steps past the range load zeros and add nothing, so the
+        // last ring runs in full (at most kGrRing - 1 idle steps per wavefront)
         if (has1) {
             for (int st = w0; st < w1; st += kGrRing) {
 #pragma unroll
                 for (int d = 0; d < kGrRing; ++d) {
-                    if (st + d < w1) {
-#pragma unroll
-                        for (int ib = 0; ib < 4; ++ib)
-#pragma unroll
-                            for (int jb = 0; jb < 4; ++jb) {
-                                acc[0][ib][jb] = MfmaT<F32>::step(ar0[d][ib], br[d][jb], acc[0][ib][jb]);
-                                acc[1][ib][jb] = MfmaT<F32>::step(ar1[d][ib], br[d][jb], acc[1][ib][jb]);
-                            }
-                        ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
-                    }
+                    prod2(d);
+                    ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
                 }
             }
         } else {
-            // a single block (the last one of an odd count): half the products
             for (int st = w0; st < w1; st += kGrRing) {
 #pragma unroll
                 for (int d = 0; d < kGrRing; ++d) {
-                    if (st + d < w1) {
-#pragma unroll
-                        for (int ib = 0; ib < 4; ++ib)
-#pragma unroll
-                            for (int jb = 0; jb < 4; ++jb)
-                                acc[0][ib][jb] = MfmaT<F32>::step(ar0[d][ib], br[d][jb], acc[0][ib][jb]);
-                        ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
-                    }
+                    prod1(d);
+                    ld(st + d + kGrRing, ar0[d], ar1[d], br[d]);
                 }
             }
         }
