@@ -55,9 +55,19 @@ __device__ inline void gather_x(const SubMeta& M, int kc0, int k, int R, const i
     }
 }
 
-// LDS chunk layout (B operand of the 16x16x4 MFMAs): element ((kq*4 + nb)*64 + l)*4 + q
-// holds X[16 kq + 4 q + l/16][16 nb + l%16], so a lane's operands for one 16-row step are
-// four consecutive doubles. Chunk row wave + 16 u has kq = u, q = wave/4, l/16 = wave%4.
+// LDS chunk layout (B operand of the 16x16x4 MFMAs): X[16 kq + 4 q + l/16][16 nb + l%16] is
+// element (((kq*4 + nb)*2 + q/2)*64 + l)*2 + q%2: a lane's four operands of one 16-row step are
+// two 16-byte pairs in two planes, so every 16-byte read has a 16-byte lane stride (no bank
+// conflicts). Chunk row wave + 16 u has kq = u, q = wave/4, l/16 = wave%4.
+__device__ __forceinline__ int x_index(int kq, int nb, int l, int q) {
+    return (((kq * 4 + nb) * 2 + (q >> 1)) * 64 + l) * 2 + (q & 1);
+}
+__device__ __forceinline__ v4d ld_x(const double* Xb, int kq, int nb, int lane) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 lo = *reinterpret_cast<const v2*>(Xb + x_index(kq, nb, lane, 0));
+    const v2 hi = *reinterpret_cast<const v2*>(Xb + x_index(kq, nb, lane, 2));
+    return v4d{lo[0], lo[1], hi[0], hi[1]};
+}
 __device__ inline void store_x(double* Xb, const SubMeta& M, int kc0, int k, int R, const int* __restrict__ gmap,
                                const double* __restrict__ Lambda, const double* g, const int* gv) {
     const int wave = fl_wave();
@@ -75,7 +85,7 @@ __device__ inline void store_x(double* Xb, const SubMeta& M, int kc0, int k, int
             }
         }
         if (lane >= k) v = 0.0;
-        Xb[((u * 4 + (lane >> 4)) * 64 + (wave & 3) * 16 + (lane & 15)) * 4 + (wave >> 2)] = v;
+        Xb[x_index(u, lane >> 4, (wave & 3) * 16 + (lane & 15), wave >> 2)] = v;
     }
 }
 
@@ -157,7 +167,7 @@ __device__ __forceinline__ void fl_fp32(const FlCtx& C, const float* __restrict_
             }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+                const v4d xv = ld_x(Xb, kql, nb, lane);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const float b = (float)xv[q];
@@ -211,8 +221,8 @@ __device__ __forceinline__ void fl_bf16(const FlCtx& C, const __bf16* __restrict
             for (int nb = 0; nb < NB; ++nb) {
                 // lane operand e = 4h + q is X row 32 kb + 16 h + 4 q + lane/16 (the A layout
                 // uses the same permutation of the contraction index)
-                const v4d x0 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl) * 4 + nb) * 64 + lane) * 4);
-                const v4d x1 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl + 1) * 4 + nb) * 64 + lane) * 4);
+                const v4d x0 = ld_x(Xb, 2 * kbl, nb, lane);
+                const v4d x1 = ld_x(Xb, 2 * kbl + 1, nb, lane);
                 v8bf bh, bl;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -265,7 +275,7 @@ __device__ __forceinline__ void fl_fp64(const FlCtx& C, const double* __restrict
             if (gkq + 1 < KQ) n = *reinterpret_cast<const v4d*>(p + (gkq + 1) * 256);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+                const v4d xv = ld_x(Xb, kql, nb, lane);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], xv[q], acc[nb], 0, 0, 0);
             }
@@ -316,7 +326,7 @@ __device__ __forceinline__ void fl_fp64_splitk(const FlCtx& C, const double* __r
                 if (kql < (kcn >> 4)) {
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
-                        const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+                        const v4d xv = ld_x(Xb, kql, nb, lane);
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[j][q], xv[q], acc[nb], 0, 0, 0);
@@ -374,7 +384,7 @@ __device__ __forceinline__ void fl_mixed(const FlCtx& C, const void* __restrict_
                 const v4d ad = *reinterpret_cast<const v4d*>(pd + gkq * 256);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const v4d xv = *reinterpret_cast<const v4d*>(Xb + ((kql * 4 + nb) * 64 + lane) * 4);
+                    const v4d xv = ld_x(Xb, kql, nb, lane);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         accr[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q], (float)xv[q], accr[nb], 0, 0, 0);
@@ -392,8 +402,8 @@ __device__ __forceinline__ void fl_mixed(const FlCtx& C, const void* __restrict_
                 const v4d ad1 = *reinterpret_cast<const v4d*>(pd + (2 * gkb + 1) * 256);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const v4d x0 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl) * 4 + nb) * 64 + lane) * 4);
-                    const v4d x1 = *reinterpret_cast<const v4d*>(Xb + (((2 * kbl + 1) * 4 + nb) * 64 + lane) * 4);
+                    const v4d x0 = ld_x(Xb, 2 * kbl, nb, lane);
+                    const v4d x1 = ld_x(Xb, 2 * kbl + 1, nb, lane);
                     v8bf bh, bl;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {

@@ -249,11 +249,14 @@ __device__ __forceinline__ v4d_t load4d(__amdgpu_buffer_rsrc_t r, int off) {
 // Wavefront: 16 output rows x 64 columns. Step t = 4 b + q contracts columns 16q..16q+15 of
 // A_b: lane (m = lane%16, g = lane/16) supplies A_b[row m][16q + 4g + s] at sub-step s, i.e.
 // one 32-byte load per step, issued a whole block (four steps) ahead; Psi_b is staged in LDS
-// in the matching operand order ((q*4 + j)*64 + lane)*4 + s <- Psi_b[16q + 4g + s][16j + m],
+// in the matching operand order (FP32: ((q*4 + j)*64 + lane)*4 + s; FP64: (((q*4 + j)*2 + s/2)*64
+// + lane)*2 + s%2, so that each 16-byte read has a 16-byte lane stride) <- Psi_b[16q + 4g + s][16j + m],
 // double-buffered per block. F32: products on the FP32 matrix cores (Psi_b staged rounded to
 // FP32, A_b rounded as it is loaded), sums in FP32 per row, the update C + alpha acc in FP64.
+// (at most 128 VGPRs: four wavefronts per SIMD, two workgroups per CU)
 template <bool F32>
-__global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
+__global__ void __launch_bounds__(64 * kTsWaves) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
                                                         const double* __restrict__ Mats, const double* C, double* out,
                                                         double alpha, double beta, const double* const* Aptrs2,
                                                         double* out2, const int* __restrict__ rb_design,
@@ -283,7 +286,11 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int e = tid + 64 * kTsWaves * u, kr = e >> 6, kc = e & 63;
-            Pb[(((kr >> 4) * 4 + (kc >> 4)) * 64 + ((kr & 15) >> 2) * 16 + (kc & 15)) * 4 + (kr & 3)] = pst[u];
+            const int qj = (kr >> 4) * 4 + (kc >> 4), ln = ((kr & 15) >> 2) * 16 + (kc & 15), sub = kr & 3;
+            if constexpr (F32)   // one 16-byte operand group per lane
+                Pb[(qj * 64 + ln) * 4 + sub] = pst[u];
+            else   // sub-steps {0,1} and {2,3} in separate planes: 16-byte lane stride, no bank conflicts
+                Pb[((qj * 2 + (sub >> 1)) * 64 + ln) * 2 + (sub & 1)] = pst[u];
         }
     };
     // block b's rows of this wavefront (no bytes past the last block)
@@ -310,7 +317,14 @@ __global__ void __launch_bounds__(64 * kTsWaves) k_ts64(int n, int nblk, const d
             ring[q] = load4d(ra, aoff + 128 * q);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const V bv = *reinterpret_cast<const V*>(Pb + ((q * 4 + j) * 64 + lane) * 4);
+                V bv;
+                if constexpr (F32) {
+                    bv = *reinterpret_cast<const V*>(Pb + ((q * 4 + j) * 64 + lane) * 4);
+                } else {
+                    const v2d_t b0 = *reinterpret_cast<const v2d_t*>(Pb + (((q * 4 + j) * 2) * 64 + lane) * 2);
+                    const v2d_t b1 = *reinterpret_cast<const v2d_t*>(Pb + (((q * 4 + j) * 2 + 1) * 64 + lane) * 2);
+                    bv = V{b0[0], b0[1], b1[0], b1[1]};
+                }
 #pragma unroll
                 for (int s2 = 0; s2 < 4; ++s2) acc[j] = MfmaT<F32>::step(a[s2], bv[s2], acc[j]);
             }
@@ -474,13 +488,15 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
     }
 }
 
-// out[b][e] = sum, in workgroup order, of the segment partials of block b (pair b/2, half
-// b%2): workgroup = 64 consecutive entries of one block; its four wavefronts take every fourth
-// contributing workgroup and meet in LDS.
-__global__ void __launch_bounds__(256) k_gram64_reduce(int n, int nblk, int G, const double* __restrict__ part,
-                                                       double* __restrict__ out, const KrySeg* __restrict__ segs,
-                                                       int nseg) {
-    __shared__ double red[4][64];
+// out[b][e] = sum of the segment partials of block b (pair b/2, half b%2): workgroup = 64
+// consecutive entries of one block; its W wavefronts take every W-th contributing workgroup
+// (loads independent, in flight together) and meet in LDS in a fixed order. W = 16 when a
+// block has many contributors (few stored blocks), 4 otherwise.
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_gram64_reduce(int n, int nblk, int G, const double* __restrict__ part,
+                                                          double* __restrict__ out, const KrySeg* __restrict__ segs,
+                                                          int nseg) {
+    __shared__ double red[W][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int bid = blockIdx.x, wbase = 0;
     const int npair = (nblk + 1) >> 1;
@@ -505,13 +521,31 @@ __global__ void __launch_bounds__(256) k_gram64_reduce(int n, int nblk, int G, c
     if (wl > G - 1) wl = G - 1;
     while (wl > wf && wl * S / G >= be) --wl;
     const int slot_f = wf * S / G < bs ? 1 : 0;
+    // with at least as many steps as workgroups every range is non-empty; otherwise a
+    // workgroup with an empty range wrote nothing and adds nothing
+    const bool dense = S >= G;
     double v = 0.0;
-    for (long long ww = wf + wave; ww <= wl; ww += 4)
-        if ((ww + 1) * S / G > ww * S / G)   // a workgroup with an empty step range adds only zeros
+#pragma unroll 4
+    for (long long ww = wf + wave; ww <= wl; ww += W)
+        if (dense || (ww + 1) * S / G > ww * S / G)
             v += part[(((wbase + ww) * 2 + (ww == wf ? slot_f : 0)) * 2 + h) * 4096 + e];
     red[wave][lane] = v;
     __syncthreads();
-    if (wave == 0) out[(long long)b * 4096 + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (wave == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) t += red[q][lane];
+        out[(long long)b * 4096 + e] = t;
+    }
+}
+
+// contrib: about how many workgroup partials each entry sums
+static void launch_gram64_reduce(int nwg, int contrib, int n, int nblk, int G, const double* part, double* out,
+                                 const KrySeg* segs, int nseg, hipStream_t st) {
+    if (contrib >= 32)
+        k_gram64_reduce<16><<<nwg, 64 * 16, 0, st>>>(n, nblk, G, part, out, segs, nseg);
+    else
+        k_gram64_reduce<4><<<nwg, 64 * 4, 0, st>>>(n, nblk, G, part, out, segs, nseg);
 }
 
 // part[c][0..63] = sum over the chunk's rows of A[row][:] * x[row] (A: n x 64). Lane = column;
@@ -621,7 +655,7 @@ void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, co
             k_gram64<true><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
         else
             k_gram64<false><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
-        k_gram64_reduce<<<nblk * 64, 256, 0, st>>>(n, nblk, G, part, out, nullptr, 0);
+        launch_gram64_reduce(nblk * 64, G / npair, n, nblk, G, part, out, nullptr, 0, st);
         return;
     }
     const int nchunk = gram_chunks(n, nblk);
@@ -884,7 +918,7 @@ void launch_gram_seg(const DevTopo& t, int n, const double* const* Aptrs, int nb
         k_gram64<true><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
     else
         k_gram64<false><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
-    k_gram64_reduce<<<nseg * nblk * 64, 256, 0, st>>>(0, nblk, G, part, out, t.kseg, nseg);
+    launch_gram64_reduce(nseg * nblk * 64, G / (nseg * npair), 0, nblk, G, part, out, t.kseg, nseg, st);
 }
 
 void launch_ts_seg(const DevTopo& t, int n, int nblk, const double* const* Aptrs, const double* Mats, long long mstride,
