@@ -183,10 +183,9 @@ struct feti_ctx {
     // per-subdomain precision selection for the reduced-precision F*Lambda (FETI-DP)
     double* pivdev = nullptr;
     // hybrid F*Lambda work lists: reduced rows where safe, and the FP64 rest (owned buffers)
-    FlTile* fl_hyb_red_dev = nullptr;
-    FlTile* fl_hyb_64_dev = nullptr;
-    int fl_hyb_red_cap = 0, fl_hyb_64_cap = 0;
-    FlTiles fl_hyb_red, fl_hyb_64;
+    FlTile* fl_hyb_dev = nullptr;
+    int fl_hyb_cap = 0;
+    FlTiles fl_hyb;   // in-solve reduced-precision form: reduced tiles, then FP64 split-contraction tiles
     bool hybrid = false;
     int n_fp64_subs = 0;
     long long psi_cap = 0;
@@ -224,10 +223,9 @@ struct feti_ctx {
         if (WH_dev) hipFree(WH_dev);
         if (QH_dev) hipFree(QH_dev);
         if (Psi) hipFree(Psi);
-        if (fl_hyb_red_dev) hipFree(fl_hyb_red_dev);
+        if (fl_hyb_dev) hipFree(fl_hyb_dev);
         if (fl64_dev) hipFree(fl64_dev);
         if (flred_dev) hipFree(flred_dev);
-        if (fl_hyb_64_dev) hipFree(fl_hyb_64_dev);
         for (auto& e : ev)
             if (e) hipEventDestroy(e);
     }
@@ -309,9 +307,12 @@ void build_fl_tiles(feti_ctx* c) {
             rr[s] = c->sub_ok[s] ? RbRange{0, t0, t0, nrb - t0} : RbRange{0, 0, 0, 0};
             rd[s] = c->sub_ok[s] ? RbRange{0, 0, 0, 0} : RbRange{0, 0, 0, nrb};
         }
-        put(pack_tiles(rr, kFlNoT, q.max_d, q.xcd != 0, q.max_red), c->fl_hyb_red_dev, c->fl_hyb_red_cap,
-            c->fl_hyb_red);
-        put(pack_tiles(rd, kFlSplitK, q.split_d, false), c->fl_hyb_64_dev, c->fl_hyb_64_cap, c->fl_hyb_64);
+        // one launch: the FP64 split-contraction tiles follow the reduced ones and fill the CUs
+        // those leave free (the kernel dispatches a tile by its flags, whatever the precision)
+        std::vector<FlTile> hyb = pack_tiles(rr, kFlNoT, q.max_d, q.xcd != 0, q.max_red);
+        const std::vector<FlTile> h64 = pack_tiles(rd, kFlSplitK, q.split_d, false);
+        hyb.insert(hyb.end(), h64.begin(), h64.end());
+        put(hyb, c->fl_hyb_dev, c->fl_hyb_cap, c->fl_hyb);
     }
     HIPCHK(hipStreamSynchronize(c->st));
 }
@@ -868,8 +869,7 @@ void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool ti
     const int f32 = prec != FETI_FP64 && !hyb;
     if (time_it) HIPCHK(hipEventRecord(c->ev[2], st));
     if (hyb) {
-        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, c->Ybuf, c->Tbuf, st, &c->fl_hyb_red, 1);
-        launch_flambda(t, FETI_FP64, k, Lam, nullptr, nullptr, c->sw64, c->Ybuf, c->Tbuf, st, &c->fl_hyb_64, 1);
+        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, c->Ybuf, c->Tbuf, st, &c->fl_hyb, 1);
     }
     else
         launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, c->Ybuf, c->Tbuf, st);
