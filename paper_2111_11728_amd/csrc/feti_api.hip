@@ -973,7 +973,7 @@ void compute_rhs(feti_ctx* c, const double* f) {
     launch_scatter_f(t, f, c->fi, c->fbeta, st);
     HIPCHK(hipMemcpyAsync(c->h, c->fi, sizeof(double) * std::max<long long>(1, t.ni_tot), hipMemcpyDeviceToDevice, st));
     launch_bt_fsolve1(t, c->L, c->Li, c->h, st);
-    launch_zt_gemv(t, c->Z, c->h, c->fbeta, c->g, st);
+    launch_zt_gemv(t, c->Z, c->h, c->fbeta, c->g, c->part, st);
     launch_local_F(t, c->F64, c->g, c->yb, c->yc, st);
     CHECK_LAUNCH();
     if (P.n_lambda > 0) {

@@ -3,6 +3,8 @@
 // d_r, fbar_c), recovery of the primal solution, averaging of the subdomain copies and
 // the compliance with its adjoint gradient.
 #include "kernels.hpp"
+
+#include <stdexcept>
 #include "dense_wg.hpp"
 
 namespace feti {
@@ -245,44 +247,85 @@ void launch_bt_bsolve1(const DevTopo& t, const double* L, const double* Li, doub
 }
 
 // g = fbeta - Z^T h  (thread per interface column)
-__global__ void k_zt_gemv(const SubMeta* __restrict__ subs, const double* __restrict__ Z, const double* __restrict__ h,
-                          const double* __restrict__ fbeta, double* g) {
+// g = fbeta - Z^T h in two passes. Pass 1: workgroup (slice sp, subdomain s) sums rows
+// [i0, i1) of Z_s (n_i / kZtSplit each) for every column (thread = columns j, j + 256, ...),
+// eight rows in flight, into part[sp * stride + ob + j]; each workgroup streams one contiguous
+// block of Z_s. Pass 2 adds the slices in order (deterministic).
+constexpr int kZtSplit = 8;
+__global__ void __launch_bounds__(256) k_zt_part(const SubMeta* __restrict__ subs, const double* __restrict__ Z,
+                                                 const double* __restrict__ h, double* __restrict__ part,
+                                                 long long stride) {
+    const int s = blockIdx.y, sp = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int i0 = (int)((long long)M.n_i * sp / kZtSplit), i1 = (int)((long long)M.n_i * (sp + 1) / kZtSplit);
+    const long long ob = M.off_b + M.off_c;
+    const double* hs = h + M.off_i;
+    for (int j = threadIdx.x; j < M.n_beta; j += 256) {
+        const double* Zc = Z + M.off_Z + j;
+        double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int i = i0;
+        for (; i + 8 <= i1; i += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = fma(Zc[(long long)(i + u) * M.n_beta], hs[i + u], v[u]);
+        }
+        for (int u = 0; i < i1; ++i, ++u) v[u] = fma(Zc[(long long)i * M.n_beta], hs[i], v[u]);
+        part[sp * stride + ob + j] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
+}
+
+__global__ void k_zt_sum(const SubMeta* __restrict__ subs, const double* __restrict__ part, long long stride,
+                         const double* __restrict__ fbeta, double* __restrict__ g) {
     const int s = blockIdx.y;
     const SubMeta M = subs[s];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M.n_beta) return;
     const long long ob = M.off_b + M.off_c;
-    double v = fbeta[ob + j];
-    const double* Zs = Z + M.off_Z + j;
-    const double* hs = h + M.off_i;
-    for (int i = 0; i < M.n_i; ++i) v -= Zs[(long long)i * M.n_beta] * hs[i];
-    g[ob + j] = v;
+    double v = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < kZtSplit; ++sp) v += part[sp * stride + ob + j];
+    g[ob + j] = fbeta[ob + j] - v;
 }
 
-void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g,
+void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g, double* part,
                     hipStream_t st) {
-    k_zt_gemv<<<dim3((t.max_beta + 255) / 256, t.n_sub), 256, 0, st>>>(t.subs, Z, h, fbeta, g);
+    const long long stride = t.nb_tot + t.nc_tot;
+    if (kZtSplit * stride > kGramPartCap) throw std::length_error("Z^T h partial buffer too small");
+    k_zt_part<<<dim3(kZtSplit, t.n_sub), 256, 0, st>>>(t.subs, Z, h, part, stride);
+    k_zt_sum<<<dim3((t.max_beta + 255) / 256, t.n_sub), 256, 0, st>>>(t.subs, part, stride, fbeta, g);
 }
 
-// x = h - Z ubeta  (wavefront per interior row)
+// x = h - Z ubeta: wavefront per four interior rows (their loads in flight together), each row
+// reduced over the wavefront
+constexpr int kZRows = 4;
 __global__ void __launch_bounds__(256) k_z_gemv(const SubMeta* __restrict__ subs, const double* __restrict__ Z,
                                                 const double* __restrict__ ubeta, const double* __restrict__ h,
                                                 double* x) {
     const int s = blockIdx.y;
     const SubMeta M = subs[s];
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (i >= M.n_i) return;
+    const int i0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kZRows, lane = threadIdx.x & 63;
+    if (i0 >= M.n_i) return;
     const long long ob = M.off_b + M.off_c;
-    const double* Zr = Z + M.off_Z + (long long)i * M.n_beta;
-    double v = 0.0;
-    for (int j = lane; j < M.n_beta; j += 64) v += Zr[j] * ubeta[ob + j];
-    v = warp_sum(v);
-    if (lane == 0) x[M.off_i + i] = h[M.off_i + i] - v;
+    double v[kZRows];
+#pragma unroll
+    for (int r = 0; r < kZRows; ++r) v[r] = 0.0;
+    for (int j = lane; j < M.n_beta; j += 64) {
+        const double u = ubeta[ob + j];
+#pragma unroll
+        for (int r = 0; r < kZRows; ++r) {
+            const int i = min(i0 + r, M.n_i - 1);
+            v[r] = fma(Z[M.off_Z + (long long)i * M.n_beta + j], u, v[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kZRows; ++r) {
+        const double t = warp_sum(v[r]);
+        if (lane == 0 && i0 + r < M.n_i) x[M.off_i + i0 + r] = h[M.off_i + i0 + r] - t;
+    }
 }
 
 void launch_z_gemv(const DevTopo& t, const double* Z, const double* ubeta, const double* h, double* x,
                    hipStream_t st) {
-    k_z_gemv<<<dim3((t.max_ni + 3) / 4, t.n_sub), 256, 0, st>>>(t.subs, Z, ubeta, h, x);
+    k_z_gemv<<<dim3((t.max_ni + 4 * kZRows - 1) / (4 * kZRows), t.n_sub), 256, 0, st>>>(t.subs, Z, ubeta, h, x);
 }
 
 // y = [F_s; F_rc^sT] g_b (FP64), wavefront per row

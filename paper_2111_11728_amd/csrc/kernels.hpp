@@ -252,8 +252,9 @@ void launch_bt_fsolve1(const DevTopo& t, const double* L, const double* Li, doub
 void launch_bt_bsolve1(const DevTopo& t, const double* L, const double* Li, double* x, hipStream_t st);
 void launch_bt_invert(const DevTopo& t, const double* L, double* Li, hipStream_t st);
 constexpr int kSweepMaxLine = 128;
-void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g,
-                    hipStream_t st);  // g = fbeta - Z^T h
+// g = fbeta - Z^T h; part: scratch of 8 (nb_tot + nc_tot) doubles
+void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g, double* part,
+                    hipStream_t st);
 void launch_z_gemv(const DevTopo& t, const double* Z, const double* ubeta, const double* h, double* x,
                    hipStream_t st);   // x = h - Z ubeta
 void launch_local_F(const DevTopo& t, const double* F64, const double* g, double* yb, double* yc, hipStream_t st);
