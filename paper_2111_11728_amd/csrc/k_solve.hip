@@ -102,115 +102,130 @@ __global__ void __launch_bounds__(64) k_bt_bsolve1(const SubMeta* __restrict__ s
 }
 
 // Sweeps with the explicit diagonal inverses (every line <= kSweepMaxLine DOFs): per line
-// one product with the coupling block and one with L_kk^{-1}. The forward sweep stages both
-// blocks in LDS (stride n+1: conflict-free row reads); the backward sweep reads them by
-// columns, which is coalesced straight from HBM. One 256-thread workgroup per subdomain.
-constexpr int kSwT = 256;
+// one product with the coupling block and one with L_kk^{-1}. One 1024-thread workgroup per
+// subdomain: wavefront w takes rows w, w + 16, ... of a block and lane l its columns l and
+// l + 64, so every load reads 512 contiguous bytes of a row, and all sixteen loads of a lane
+// are in flight before the first is used. L_kk^{-1} is lower triangular: its zero upper part
+// is not read. The forward sweep sums each row over its wavefront; the backward sweep (the
+// transposed products) keeps per-lane column sums and adds the sixteen wavefronts' sums in
+// LDS in a fixed order.
+constexpr int kSwW = 16, kSwT = 64 * kSwW, kSwP = kSweepMaxLine / kSwW;   // rows per wavefront
 
-// rows x cols (cols <= 128) from HBM into LDS with stride cols + 1: two rows per pass of the
-// workgroup, eight passes of loads in flight before they are stored
-__device__ inline void stage_block(double* A, const double* __restrict__ g, int rows, int cols) {
-    const int c = threadIdx.x & 127, half = threadIdx.x >> 7;
-    for (int r0 = 0; r0 < rows; r0 += 16) {
-        double v[8];
+// a[p][h] = A[w + 16 p][l + 64 h] (rows < nr, columns < nc and <= row when lower), 0 elsewhere
+__device__ __forceinline__ void sweep_load(double (&a)[kSwP][2], const double* __restrict__ A, int nr, int nc,
+                                           bool lower) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int r = r0 + 2 * u + half;
-            v[u] = (r < rows && c < cols) ? g[(long long)r * cols + c] : 0.0;
-        }
+    for (int p = 0; p < kSwP; ++p)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int r = r0 + 2 * u + half;
-            if (r < rows && c < cols) A[r * (cols + 1) + c] = v[u];
+        for (int h = 0; h < 2; ++h) {
+            const int r = w + kSwW * p, q = l + 64 * h;
+            a[p][h] = (r < nr && q < nc && (!lower || q <= r)) ? A[(long long)r * nc + q] : 0.0;
         }
+}
+
+// y[r] = sum_q A[r][q] x[q] for the rows of this wavefront (result valid in every lane)
+__device__ __forceinline__ void sweep_rows(const double (&a)[kSwP][2], const double* x, double (&y)[kSwP]) {
+    const int l = threadIdx.x & 63;
+    const double x0 = x[l], x1 = x[l + 64];
+#pragma unroll
+    for (int p = 0; p < kSwP; ++p) y[p] = warp_sum(a[p][0] * x0 + a[p][1] * x1);
+}
+
+// y[q] = sum_r A[r][q] x[r] over all rows (red: kSwW x 128 doubles of LDS; y in LDS, size 128)
+__device__ __forceinline__ void sweep_cols(const double (&a)[kSwP][2], const double* x, double* red, double* y,
+                                           int nc) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < kSwP; ++p) {
+        const double xr = x[w + kSwW * p];
+        c0 = fma(a[p][0], xr, c0);
+        c1 = fma(a[p][1], xr, c1);
+    }
+    red[w * kSweepMaxLine + l] = c0;
+    red[w * kSweepMaxLine + l + 64] = c1;
+    __syncthreads();
+    if (threadIdx.x < kSweepMaxLine && (int)threadIdx.x < nc) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSwW; ++q) t += red[q * kSweepMaxLine + threadIdx.x];
+        y[threadIdx.x] = t;
     }
 }
 
 __global__ void __launch_bounds__(kSwT) k_bt_fsweep(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
                                                     const double* __restrict__ Lbuf, const double* __restrict__ Li,
                                                     double* h) {
-    __shared__ double A[kSweepMaxLine * (kSweepMaxLine + 1)];
     __shared__ double xp[kSweepMaxLine], v[kSweepMaxLine];
     const int s = blockIdx.x;
     const SubMeta M = subs[s];
-    const int r = threadIdx.x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     double* hs = h + M.off_i;
+    if (threadIdx.x < kSweepMaxLine) xp[threadIdx.x] = 0.0;
+    double a[kSwP][2], y[kSwP];
     for (int k = 0; k < M.n_lines; ++k) {
         const LineMeta Lk = lines[M.line0 + k];
         if (Lk.n == 0) continue;
         // v = b_k - L_{k,k-1} x_{k-1}
-        if (Lk.n_prev > 0) stage_block(A, Lbuf + Lk.off_sub, Lk.n, Lk.n_prev);
-        __syncthreads();
-        if (r < Lk.n) {
-            double a = hs[Lk.i0 + r];
-            for (int q = 0; q < Lk.n_prev; ++q) a -= A[r * (Lk.n_prev + 1) + q] * xp[q];
-            v[r] = a;
+        sweep_load(a, Lbuf + Lk.off_sub, Lk.n, Lk.n_prev, false);
+        __syncthreads();   // xp of the previous line complete
+        sweep_rows(a, xp, y);
+#pragma unroll
+        for (int p = 0; p < kSwP; ++p) {
+            const int r = w + kSwW * p;
+            if (l == 0 && r < Lk.n) v[r] = hs[Lk.i0 + r] - y[p];
         }
-        __syncthreads();
+        if (threadIdx.x >= (unsigned)Lk.n && threadIdx.x < kSweepMaxLine) v[threadIdx.x] = 0.0;
         // x_k = L_kk^{-1} v
-        stage_block(A, Li + Lk.off_inv, Lk.n, Lk.n);
-        __syncthreads();
-        if (r < Lk.n) {
-            double a = 0.0;
-            for (int c = 0; c <= r; ++c) a += A[r * (Lk.n + 1) + c] * v[c];
-            hs[Lk.i0 + r] = a;
-            xp[r] = a;
+        sweep_load(a, Li + Lk.off_inv, Lk.n, Lk.n, true);
+        __syncthreads();   // v complete, xp free
+        sweep_rows(a, v, y);
+#pragma unroll
+        for (int p = 0; p < kSwP; ++p) {
+            const int r = w + kSwW * p;
+            if (l == 0 && r < Lk.n) {
+                hs[Lk.i0 + r] = y[p];
+                xp[r] = y[p];
+            }
         }
-        __syncthreads();
+        if (threadIdx.x >= (unsigned)Lk.n && threadIdx.x < kSweepMaxLine) xp[threadIdx.x] = 0.0;
     }
 }
 
 __global__ void __launch_bounds__(kSwT) k_bt_bsweep(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
                                                     const double* __restrict__ Lbuf, const double* __restrict__ Li,
                                                     double* x) {
-    __shared__ double xn[kSweepMaxLine], w[kSweepMaxLine];
+    __shared__ double xn[kSweepMaxLine], wv[kSweepMaxLine], cs[kSweepMaxLine];
+    __shared__ double red[kSwW * kSweepMaxLine];
     const int s = blockIdx.x;
     const SubMeta M = subs[s];
-    const int q = threadIdx.x;
     double* xg = x + M.off_i;
+    if (threadIdx.x < kSweepMaxLine) xn[threadIdx.x] = 0.0;
+    double a[kSwP][2];
     for (int k = M.n_lines - 1; k >= 0; --k) {
         const LineMeta Lk = lines[M.line0 + k];
         if (Lk.n == 0) continue;
-        // w = t_k - L_{k+1,k}^T x_{k+1}  (L_{k+1,k}: n_next x n, row-major; column q by thread q;
-        // xn holds x_{k+1} whenever line k+1 is not empty)
+        // w = t_k - L_{k+1,k}^T x_{k+1}  (L_{k+1,k}: n_next x n, row-major)
         const int n_next = k + 1 < M.n_lines ? lines[M.line0 + k + 1].n : 0;
-        if (q < Lk.n) {
-            double a = xg[Lk.i0 + q];
-            if (n_next > 0) {
-                const double* C = Lbuf + lines[M.line0 + k + 1].off_sub;
-                for (int r0 = 0; r0 < n_next; r0 += 8) {
-                    double cv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) cv[u] = r0 + u < n_next ? C[(long long)(r0 + u) * Lk.n + q] : 0.0;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (r0 + u < n_next) a -= cv[u] * xn[r0 + u];
-                }
-            }
-            w[q] = a;
-        }
-        __syncthreads();
+        const long long off_c = n_next > 0 ? lines[M.line0 + k + 1].off_sub : 0;
+        sweep_load(a, Lbuf + off_c, n_next, Lk.n, false);
+        __syncthreads();   // xn of the previous line complete, red free
+        sweep_cols(a, xn, red, cs, Lk.n);
+        __syncthreads();   // cs complete
+        if (threadIdx.x < (unsigned)Lk.n) wv[threadIdx.x] = xg[Lk.i0 + threadIdx.x] - cs[threadIdx.x];
+        else if (threadIdx.x < kSweepMaxLine) wv[threadIdx.x] = 0.0;
         // x_k = L_kk^{-T} w: x_q = sum_{r >= q} Li[r][q] w_r
-        double a = 0.0;
-        if (q < Lk.n) {
-            // every thread walks the rows in the same order (coalesced); L_kk^{-1} is zero
-            // above its diagonal
-            const double* Ib = Li + Lk.off_inv;
-            for (int r0 = 0; r0 < Lk.n; r0 += 8) {
-                double iv[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) iv[u] = r0 + u < Lk.n ? Ib[(long long)(r0 + u) * Lk.n + q] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (r0 + u < Lk.n) a += iv[u] * w[r0 + u];
-            }
+        sweep_load(a, Li + Lk.off_inv, Lk.n, Lk.n, true);
+        __syncthreads();   // wv complete, red free
+        sweep_cols(a, wv, red, cs, Lk.n);
+        __syncthreads();   // cs complete
+        if (threadIdx.x < (unsigned)Lk.n) {
+            xg[Lk.i0 + threadIdx.x] = cs[threadIdx.x];
+            xn[threadIdx.x] = cs[threadIdx.x];
+        } else if (threadIdx.x < kSweepMaxLine) {
+            xn[threadIdx.x] = 0.0;
         }
-        __syncthreads();
-        if (q < Lk.n) {
-            xg[Lk.i0 + q] = a;
-            xn[q] = a;
-        }
-        __syncthreads();
     }
 }
 
@@ -246,7 +261,6 @@ void launch_bt_bsolve1(const DevTopo& t, const double* L, const double* Li, doub
         k_bt_bsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, x);
 }
 
-// g = fbeta - Z^T h  (thread per interface column)
 // g = fbeta - Z^T h in two passes. Pass 1: workgroup (slice sp, subdomain s) sums rows
 // [i0, i1) of Z_s (n_i / kZtSplit each) for every column (thread = columns j, j + 256, ...),
 // eight rows in flight, into part[sp * stride + ob + j]; each workgroup streams one contiguous
