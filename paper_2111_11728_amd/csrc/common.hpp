@@ -55,4 +55,31 @@ __device__ __forceinline__ double warp_sum(double v) {
     return v;
 }
 
+// v of the lane CTRL selects within its row of 16 (a DPP move of both halves of a double)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    const int nlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const int nhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)nhi << 32) | (unsigned int)nlo);
+}
+
+// sum over a full wavefront without LDS: DPP within rows of 16 (xor 1, xor 2, rotate 4,
+// rotate 8 leave every lane with its row's sum), then the four row sums through readlane in a
+// fixed order (uniform result; every lane must be active)
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x124>(v);   // row_ror:4
+    v += dpp_mov<0x128>(v);   // row_ror:8
+    auto rl = [&](int lane) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    };
+    return (rl(0) + rl(16)) + (rl(32) + rl(48));
+}
+
 }  // namespace feti

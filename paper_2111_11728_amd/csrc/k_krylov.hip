@@ -746,16 +746,8 @@ __device__ __forceinline__ double pick64(const double (&a)[64], int p) {
     }
 }
 
-// max over the wavefront of a double: DPP within rows of 16 (xor 1, xor 2, rotate 4, rotate 8),
-// then the four row maxima through readlane (uniform result)
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-    const int nlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
-    const int nhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)nhi << 32) | (unsigned int)nlo);
-}
+// max over the wavefront of a double: DPP within rows of 16 (xor 1, xor 2, rotate 4, rotate 8;
+// dpp_mov), then the four row maxima through readlane (uniform result)
 __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp_mov<0xB1>(v));    // quad_perm [1,0,3,2]
     v = fmax(v, dpp_mov<0x4E>(v));    // quad_perm [2,3,0,1]

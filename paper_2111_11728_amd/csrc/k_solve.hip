@@ -129,7 +129,7 @@ __device__ __forceinline__ void sweep_rows(const double (&a)[kSwP][2], const dou
     const int l = threadIdx.x & 63;
     const double x0 = x[l], x1 = x[l + 64];
 #pragma unroll
-    for (int p = 0; p < kSwP; ++p) y[p] = warp_sum(a[p][0] * x0 + a[p][1] * x1);
+    for (int p = 0; p < kSwP; ++p) y[p] = wave_sum_dpp(a[p][0] * x0 + a[p][1] * x1);
 }
 
 // y[q] = sum_r A[r][q] x[r] over all rows (red: kSwW x 128 doubles of LDS; y in LDS, size 128)
@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(256) k_z_gemv(const SubMeta* __restrict__ subs
     }
 #pragma unroll
     for (int r = 0; r < kZRows; ++r) {
-        const double t = warp_sum(v[r]);
+        const double t = wave_sum_dpp(v[r]);
         if (lane == 0 && i0 + r < M.n_i) x[M.off_i + i0 + r] = h[M.off_i + i0 + r] - t;
     }
 }
