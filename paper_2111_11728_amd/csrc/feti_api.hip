@@ -564,6 +564,12 @@ void build_layout(feti_ctx* c) {
     t.row_s = c->upload(P.row_s);
     t.row_j = c->upload(P.row_j);
     t.row_sg = c->upload(P.row_sg);
+    {   // absolute Y row of each (row, side): the scatter's loads need no subdomain lookup
+        std::vector<long long> yo(P.row_s.size());
+        for (size_t e = 0; e < yo.size(); ++e)
+            yo[e] = P.row_s[e] >= 0 ? c->hsubs[P.row_s[e]].off_b + P.row_j[e] : -1;
+        t.row_yo = c->upload(yo);
+    }
     t.row_sh = c->upload(P.row_sh);
     t.sh_ptr = c->upload(P.sh_ptr);
     t.sh_s = c->upload(P.sh_s);

@@ -662,17 +662,16 @@ void launch_fold_coarse(const DevTopo& t, int k, int ytype_f32, const double* F6
 
 // Q[row][c] = sum over the row's (one or two) sides of sign * Y_s[j][c].
 template <typename TY>
-__global__ void k_scatter(int n_lambda, int k, const int* __restrict__ row_s, const int* __restrict__ row_j,
-                          const int8_t* __restrict__ row_sg, const SubMeta* __restrict__ subs,
+__global__ void k_scatter(int n_lambda, int k, const long long* __restrict__ row_yo, const int8_t* __restrict__ row_sg,
                           const TY* __restrict__ Y, double* __restrict__ Q) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_lambda * k) return;
     const int row = k == 64 ? idx >> 6 : idx / k, c = idx - row * k;
     double val = 0.0;
+#pragma unroll
     for (int t = 0; t < 2; ++t) {
-        const int s = row_s[2 * row + t];
-        if (s < 0) continue;
-        val += row_sg[2 * row + t] * (double)Y[(subs[s].off_b + row_j[2 * row + t]) * k + c];
+        const long long yo = row_yo[2 * row + t];
+        if (yo >= 0) val += row_sg[2 * row + t] * (double)Y[yo * k + c];
     }
     Q[idx] = val;
 }
@@ -682,10 +681,9 @@ void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, doubl
     if (n == 0) return;
     const int grid = (int)((n + 255) / 256);
     if (ytype_f32)
-        k_scatter<float><<<grid, 256, 0, st>>>(t.n_lambda, k, t.row_s, t.row_j, t.row_sg, t.subs, (const float*)Y, Q);
+        k_scatter<float><<<grid, 256, 0, st>>>(t.n_lambda, k, t.row_yo, t.row_sg, (const float*)Y, Q);
     else
-        k_scatter<double><<<grid, 256, 0, st>>>(t.n_lambda, k, t.row_s, t.row_j, t.row_sg, t.subs, (const double*)Y,
-                                                Q);
+        k_scatter<double><<<grid, 256, 0, st>>>(t.n_lambda, k, t.row_yo, t.row_sg, (const double*)Y, Q);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -103,6 +103,7 @@ struct DevTopo {
     const int* row_s = nullptr;
     const int* row_j = nullptr;
     const int8_t* row_sg = nullptr;
+    const long long* row_yo = nullptr;   // [2 n_lambda]: off_b + row_j of each side (-1: none)
     const int* row_sh = nullptr;
     const int* sh_ptr = nullptr;
     const int* sh_s = nullptr;
