@@ -65,14 +65,21 @@ __device__ __forceinline__ double dpp_mov(double v) {
     return __longlong_as_double(((long long)nhi << 32) | (unsigned int)nlo);
 }
 
-// sum over a full wavefront without LDS: DPP within rows of 16 (xor 1, xor 2, rotate 4,
-// rotate 8 leave every lane with its row's sum), then the four row sums through readlane in a
-// fixed order (uniform result; every lane must be active)
-__device__ __forceinline__ double wave_sum_dpp(double v) {
+// sum over the lane's row of 16 lanes, left in every lane of the row (DPP: xor 1, xor 2,
+// rotate 4, rotate 8; every lane of the row must be active)
+__device__ __forceinline__ double row16_sum_dpp(double v) {
     v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
     v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
     v += dpp_mov<0x124>(v);   // row_ror:4
     v += dpp_mov<0x128>(v);   // row_ror:8
+    return v;
+}
+
+// sum over a full wavefront without LDS: DPP within rows of 16 (xor 1, xor 2, rotate 4,
+// rotate 8 leave every lane with its row's sum), then the four row sums through readlane in a
+// fixed order (uniform result; every lane must be active)
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v = row16_sum_dpp(v);
     auto rl = [&](int lane) {
         const long long b = __double_as_longlong(v);
         const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);

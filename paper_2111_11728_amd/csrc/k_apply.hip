@@ -717,6 +717,15 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
     const SubMeta M = subs[s];
     const int nb = M.n_b, nT = (nb + 63) >> 6, nt = nT * (nT + 1) / 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = 4 * wave + (lane >> 4), jq = lane & 15;
+    // the first tiles' loads go out before the gather of x (they do not depend on it)
+    const int t0 = (int)((long long)g * nt / G), t1 = (int)((long long)(g + 1) * nt / G);
+    const double* T = Pk + M.off_Pk + i * 64 + 4 * jq;
+    auto ld = [&](int t) -> ps4_t {
+        return t < t1 ? *reinterpret_cast<const ps4_t*>(T + (long long)t * 4096) : ps4_t{0.0, 0.0, 0.0, 0.0};
+    };
+    ps4_t ring[kPsRing];
+#pragma unroll
+    for (int d = 0; d < kPsRing; ++d) ring[d] = ld(t0 + d);
     for (int q = tid; q < nT * 64; q += 1024) {
         double v = 0.0;
         if (q < nb) {
@@ -727,14 +736,6 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
         ys[q] = 0.0;
     }
     __syncthreads();
-    const int t0 = (int)((long long)g * nt / G), t1 = (int)((long long)(g + 1) * nt / G);
-    const double* T = Pk + M.off_Pk + i * 64 + 4 * jq;
-    auto ld = [&](int t) -> ps4_t {
-        return t < t1 ? *reinterpret_cast<const ps4_t*>(T + (long long)t * 4096) : ps4_t{0.0, 0.0, 0.0, 0.0};
-    };
-    ps4_t ring[kPsRing];
-#pragma unroll
-    for (int d = 0; d < kPsRing; ++d) ring[d] = ld(t0 + d);
     int J = t0 < t1 ? tri_col(t0) : 0, I = t0 - J * (J + 1) / 2;
     double ca[4] = {0.0, 0.0, 0.0, 0.0};
     for (int t = t0; t < t1; t += kPsRing) {
@@ -745,11 +746,8 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
                 ring[d] = ld(t + d + kPsRing);
                 // row part: y_I[i] += sum_b S[i][b] x_J[b]
                 const ps4_t xj = *reinterpret_cast<const ps4_t*>(xs + 64 * J + 4 * jq);
-                double rp = ((a[0] * xj[0] + a[1] * xj[1]) + a[2] * xj[2]) + a[3] * xj[3];
-                rp += __shfl_xor(rp, 1);
-                rp += __shfl_xor(rp, 2);
-                rp += __shfl_xor(rp, 4);
-                rp += __shfl_xor(rp, 8);
+                const double rp =
+                    row16_sum_dpp(((a[0] * xj[0] + a[1] * xj[1]) + a[2] * xj[2]) + a[3] * xj[3]);   // over jq
                 if (jq == 0) ys[64 * I + i] += rp;
                 // column part: y_J[b] += S[i][b] x_I[i]
                 if (I < J) {
