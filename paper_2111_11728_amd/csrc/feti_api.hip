@@ -1163,7 +1163,7 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
     HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     project(c, 1, c->Zk);  // w = P z
     ddot(c, n, c->r, c->zv, 0);
-    launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+    launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
     double rz = read_scalars(c);
     o.eps = std::sqrt(std::max(rz, 0.0));
     if (converged(c, o.eps, eps0, tol)) return o;
@@ -1183,7 +1183,7 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
         launch_axpby(n, -a, c->Qk, 1.0, c->r, st);
         precondition(c, c->r, c->zv, 1, 0);
         ddot(c, n, c->r, c->zv, 0);
-        launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+        launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
         const double rz_new = read_scalars(c);
         o.iters = it + 1;
         o.eps = std::sqrt(std::max(rz_new, 0.0));
@@ -1197,7 +1197,7 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
             true_residual(c, c->tmpv, c->r);
             precondition(c, c->r, c->zv, 1, 0);
             ddot(c, n, c->r, c->zv, 0);
-            launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+            launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
             rz = read_scalars(c);
             o.eps = std::sqrt(std::max(rz, 0.0));
             if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
@@ -1267,7 +1267,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
     const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
     precondition(c, c->r, c->Zk, one, 0);
     launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
-    launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
+    launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
     o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
     if (converged(c, o.eps, eps0, tol)) return o;
     project(c, kd, c->Zk);  // W_0 = P Z_0 (in place)
@@ -1329,7 +1329,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         run_graph(c, c->g_prec, kd, [&] {
             precondition(c, c->r, c->Zk, one, 0);
             launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
-            launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
+            launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
             project(c, kd, c->Zk);
         });
         orth_gated(nb, p_it, probed);
@@ -1406,7 +1406,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             true_residual(c, c->tmpv, c->r);
             precondition(c, c->r, c->Zk, one, 0);
             launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
-            launch_seg_dot(c->t, kd, c->r, c->Zk, c->scal + 16, st);
+            launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
             o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
             if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
             if (converged(c, o.eps, eps0, tol)) break;
@@ -1480,7 +1480,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         // eps0 = sqrt(r0^T z0) with the FP64 preconditioner
         precondition(c, c->r, c->zv, 1, 0);
         ddot(c, n, c->r, c->zv, 0);
-        launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+        launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
         eps0 = std::sqrt(std::max(read_scalars(c), 0.0));
         for (size_t d = 0; d < c->designs.size(); ++d)
             c->eps0_d[d] = c->designs.size() > 1 ? std::sqrt(std::max(c->hpin[16 + d], 0.0)) : eps0;
@@ -1514,7 +1514,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
                 true_residual(c, c->lam, c->r);
                 precondition(c, c->r, c->zv, 1, 0);
                 ddot(c, n, c->r, c->zv, 0);
-                launch_seg_dot(c->t, 1, c->r, c->zv, c->scal + 16, st);
+                launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
                 const double et = std::sqrt(std::max(read_scalars(c), 0.0));
                 true_rel = et / eps0;
                 if (c->designs.size() > 1) {   // the worst design

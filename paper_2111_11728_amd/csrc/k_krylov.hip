@@ -345,6 +345,7 @@ k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
     }
 }
 
+constexpr int kMaxSegs = 256;  // designs of a segmented Gram product (the setup allows 64)
 constexpr int kGrRing = 6;    // 4-row steps in flight per lane
 constexpr int kGrGroups = 256; // workgroups per round: one per CU
 
@@ -361,10 +362,15 @@ constexpr int kGrGroups = 256; // workgroups per round: one per CU
 // pair p, part[((w*2 + t)*2 + h)*4096 + i*64 + j] for block 2p + h.
 // Several designs (segs != null): design d owns max(npair, segs[d].base) consecutive
 // workgroups, which split its own rows in the same way; partials keep the global workgroup index.
-__device__ __forceinline__ int gram_seg_find(const KrySeg* segs, int nseg, int npair, int wg, int& w, int& G) {
+// gq[d] = max(npair, segs[d].base) for d < nseg (at most kMaxSegs designs), one load per
+// thread; the caller synchronises before reading gq
+__device__ __forceinline__ void seg_groups(const KrySeg* segs, int nseg, int npair, int* gq) {
+    for (int d = threadIdx.x; d < nseg; d += blockDim.x) gq[d] = max(npair, segs[d].base);
+}
+__device__ __forceinline__ int gram_seg_find(const int* gq, int nseg, int wg, int& w, int& G) {
     int acc = 0;
     for (int d = 0; d < nseg; ++d) {
-        const int Gd = max(npair, segs[d].base);
+        const int Gd = gq[d];
         if (wg < acc + Gd) {
             w = wg - acc;
             G = Gd;
@@ -389,7 +395,10 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
     const int npair = (nblk + 1) >> 1;
     long long arow0 = 0;   // first element of this workgroup's design in every n x 64 block
     if (segs) {
-        const int d = gram_seg_find(segs, nseg, npair, wg, w, G);
+        __shared__ int gq[kMaxSegs];
+        seg_groups(segs, nseg, npair, gq);
+        __syncthreads();
+        const int d = gram_seg_find(gq, nseg, wg, w, G);
         arow0 = (long long)segs[d].row0 * 64;
         n = segs[d].nrows;
         B += arow0;
@@ -501,10 +510,13 @@ __global__ void __launch_bounds__(64 * W) k_gram64_reduce(int n, int nblk, int G
     int bid = blockIdx.x, wbase = 0;
     const int npair = (nblk + 1) >> 1;
     if (segs) {   // workgroup = (design, block, 64 entries); that design's workgroups only
+        __shared__ int gq[kMaxSegs];
+        seg_groups(segs, nseg, npair, gq);
+        __syncthreads();
         const int d = bid / (nblk * 64);
         bid -= d * nblk * 64;
-        for (int q = 0; q < d; ++q) wbase += max(npair, segs[q].base);
-        G = max(npair, segs[d].base);
+        for (int q = 0; q < d; ++q) wbase += gq[q];
+        G = gq[d];
         n = segs[d].nrows;
         out += (long long)d * nblk * 4096;
     }
@@ -1194,28 +1206,52 @@ void launch_diff_norms(long long len, const double* a, const double* b, double* 
 
 // out[d] = sum over the rows of design d of r[row] * sum_c Z[row][c]; one workgroup per design,
 // fixed order (thread-strided partial sums, then a fixed tree)
+// out[d] = r_d^T (Z_d 1) over design d's rows [seg[2d], seg[2d] + seg[2d+1]): kSegDotSplit
+// workgroups per design, each over a contiguous slice of its rows (k = 64: wavefront per row,
+// lane per column, coalesced; otherwise thread per row), then the slices in order.
+constexpr int kSegDotSplit = 8;
 __global__ void __launch_bounds__(256) k_seg_dot(const int* __restrict__ seg, int k, const double* __restrict__ r,
-                                                 const double* __restrict__ Z, double* __restrict__ out) {
-    __shared__ double red[256];
-    const int d = blockIdx.x, r0 = seg[2 * d], nr = seg[2 * d + 1];
+                                                 const double* __restrict__ Z, double* __restrict__ part) {
+    __shared__ double red[4];
+    const int d = blockIdx.y, sp = blockIdx.x, r0 = seg[2 * d], nr = seg[2 * d + 1];
+    const int i0 = (int)((long long)nr * sp / kSegDotSplit), i1 = (int)((long long)nr * (sp + 1) / kSegDotSplit);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     double v = 0.0;
-    for (int i = threadIdx.x; i < nr; i += 256) {
-        const long long row = r0 + i;
-        double z = 0.0;
-        for (int c = 0; c < k; ++c) z += Z[row * k + c];
-        v += r[row] * z;
+    if (k == 64) {
+#pragma unroll 4
+        for (int i = i0 + wave; i < i1; i += 4) {
+            const long long row = r0 + i;
+            v = fma(Z[row * 64 + lane], r[row], v);
+        }
+    } else {
+        for (int i = i0 + tid; i < i1; i += 256) {
+            const long long row = r0 + i;
+            double z = 0.0;
+            for (int c = 0; c < k; ++c) z += Z[row * k + c];
+            v = fma(r[row], z, v);
+        }
     }
-    red[threadIdx.x] = v;
+    v = wave_sum_dpp(v);
+    if (lane == 0) red[wave] = v;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[d] = red[0];
+    if (tid == 0) part[d * kSegDotSplit + sp] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-void launch_seg_dot(const DevTopo& t, int k, const double* r, const double* Z, double* out, hipStream_t st) {
-    if (t.dsg.size() > 1) k_seg_dot<<<(int)t.dsg.size(), 256, 0, st>>>(t.seg, k, r, Z, out);
+__global__ void k_seg_dot_sum(int nseg, const double* __restrict__ part, double* __restrict__ out) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= nseg) return;
+    double v = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < kSegDotSplit; ++sp) v += part[d * kSegDotSplit + sp];
+    out[d] = v;
+}
+
+void launch_seg_dot(const DevTopo& t, int k, const double* r, const double* Z, double* part, double* out,
+                    hipStream_t st) {
+    const int nseg = (int)t.dsg.size();
+    if (nseg <= 1) return;
+    k_seg_dot<<<dim3(kSegDotSplit, nseg), 256, 0, st>>>(t.seg, k, r, Z, part);
+    k_seg_dot_sum<<<(nseg + 63) / 64, 64, 0, st>>>(nseg, part, out);
 }
 
 __global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {

@@ -235,7 +235,8 @@ void launch_orth_update(int n, int k, const double* const* Wptrs, int nblk, cons
                         hipStream_t st);
 void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st);
 // out[d] = sum over the lambda rows of design d of r[row] * sum_c Z[row][c] (k columns), fixed order
-void launch_seg_dot(const DevTopo& t, int k, const double* r, const double* Z, double* out, hipStream_t st);
+void launch_seg_dot(const DevTopo& t, int k, const double* r, const double* Z, double* part, double* out,
+                    hipStream_t st);   // part: scratch of 8 doubles per design
 // out[0..63] = A^T x (A: n x 64 row-major), two-stage deterministic reduction through part
 void launch_gemv_t(int n, int k, const double* A, const double* x, double* part, double* out, hipStream_t st);
 void launch_diff_norms(long long len, const double* a, const double* b, double* part, double* out,
