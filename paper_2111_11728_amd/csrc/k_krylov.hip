@@ -345,7 +345,6 @@ k_ts64(int n, int nblk, const double* const* __restrict__ Aptrs,
     }
 }
 
-constexpr int kMaxSegs = 256;  // designs of a segmented Gram product (the setup allows 64)
 constexpr int kGrRing = 6;    // 4-row steps in flight per lane
 constexpr int kGrGroups = 256; // workgroups per round: one per CU
 
@@ -362,31 +361,18 @@ constexpr int kGrGroups = 256; // workgroups per round: one per CU
 // pair p, part[((w*2 + t)*2 + h)*4096 + i*64 + j] for block 2p + h.
 // Several designs (segs != null): design d owns max(npair, segs[d].base) consecutive
 // workgroups, which split its own rows in the same way; partials keep the global workgroup index.
-// gq[d] = max(npair, segs[d].base) for d < nseg (at most kMaxSegs designs), one load per
-// thread; the caller synchronises before reading gq
-__device__ __forceinline__ void seg_groups(const KrySeg* segs, int nseg, int npair, int* gq) {
-    for (int d = threadIdx.x; d < nseg; d += blockDim.x) gq[d] = max(npair, segs[d].base);
-}
-__device__ __forceinline__ int gram_seg_find(const int* gq, int nseg, int wg, int& w, int& G) {
-    int acc = 0;
-    for (int d = 0; d < nseg; ++d) {
-        const int Gd = gq[d];
-        if (wg < acc + Gd) {
-            w = wg - acc;
-            G = Gd;
-            return d;
-        }
-        acc += Gd;
-    }
-    w = 0;
-    G = 1;
-    return nseg - 1;
+// The design of workgroup wg: w[d] <= wg < w[d + 1] (w: first workgroup of each design, built on
+// the host per launch and passed by value)
+__device__ __forceinline__ int seg_of(const SegBases& sb, int nseg, int wg) {
+    int d = 0;
+    while (d + 1 < nseg && sb.w[d + 1] <= wg) ++d;
+    return d;
 }
 
 template <bool F32>
 __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double* const* __restrict__ Aptrs,
                                                    const double* __restrict__ B, double* __restrict__ part,
-                                                   const KrySeg* __restrict__ segs, int nseg) {
+                                                   const KrySeg* __restrict__ segs, int nseg, SegBases sb) {
     __shared__ double red[4 * 4096];
     const int wg = blockIdx.x;
     int G = gridDim.x, w = blockIdx.x;
@@ -395,10 +381,9 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
     const int npair = (nblk + 1) >> 1;
     long long arow0 = 0;   // first element of this workgroup's design in every n x 64 block
     if (segs) {
-        __shared__ int gq[kMaxSegs];
-        seg_groups(segs, nseg, npair, gq);
-        __syncthreads();
-        const int d = gram_seg_find(gq, nseg, wg, w, G);
+        const int d = seg_of(sb, nseg, wg);
+        w = wg - sb.w[d];
+        G = sb.w[d + 1] - sb.w[d];
         arow0 = (long long)segs[d].row0 * 64;
         n = segs[d].nrows;
         B += arow0;
@@ -504,19 +489,16 @@ __global__ void __launch_bounds__(256, 1) k_gram64(int n, int nblk, const double
 template <int W>
 __global__ void __launch_bounds__(64 * W) k_gram64_reduce(int n, int nblk, int G, const double* __restrict__ part,
                                                           double* __restrict__ out, const KrySeg* __restrict__ segs,
-                                                          int nseg) {
+                                                          int nseg, SegBases sb) {
     __shared__ double red[W][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int bid = blockIdx.x, wbase = 0;
     const int npair = (nblk + 1) >> 1;
     if (segs) {   // workgroup = (design, block, 64 entries); that design's workgroups only
-        __shared__ int gq[kMaxSegs];
-        seg_groups(segs, nseg, npair, gq);
-        __syncthreads();
         const int d = bid / (nblk * 64);
         bid -= d * nblk * 64;
-        for (int q = 0; q < d; ++q) wbase += gq[q];
-        G = gq[d];
+        wbase = sb.w[d];
+        G = sb.w[d + 1] - sb.w[d];
         n = segs[d].nrows;
         out += (long long)d * nblk * 4096;
     }
@@ -553,11 +535,11 @@ __global__ void __launch_bounds__(64 * W) k_gram64_reduce(int n, int nblk, int G
 
 // contrib: about how many workgroup partials each entry sums
 static void launch_gram64_reduce(int nwg, int contrib, int n, int nblk, int G, const double* part, double* out,
-                                 const KrySeg* segs, int nseg, hipStream_t st) {
+                                 const KrySeg* segs, int nseg, const SegBases& sb, hipStream_t st) {
     if (contrib >= 32)
-        k_gram64_reduce<16><<<nwg, 64 * 16, 0, st>>>(n, nblk, G, part, out, segs, nseg);
+        k_gram64_reduce<16><<<nwg, 64 * 16, 0, st>>>(n, nblk, G, part, out, segs, nseg, sb);
     else
-        k_gram64_reduce<4><<<nwg, 64 * 4, 0, st>>>(n, nblk, G, part, out, segs, nseg);
+        k_gram64_reduce<4><<<nwg, 64 * 4, 0, st>>>(n, nblk, G, part, out, segs, nseg, sb);
 }
 
 // part[c][0..63] = sum over the chunk's rows of A[row][:] * x[row] (A: n x 64). Lane = column;
@@ -663,11 +645,12 @@ void launch_gram(int n, int ka, int kb, const double* const* Aptrs, int nblk, co
         const int npair = (nblk + 1) / 2;
         const int G = kGrGroups * ((npair + kGrGroups - 1) / kGrGroups);
         if ((long long)G * 4 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
+        const SegBases none{};
         if (f32)
-            k_gram64<true><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
+            k_gram64<true><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0, none);
         else
-            k_gram64<false><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0);
-        launch_gram64_reduce(nblk * 64, G / npair, n, nblk, G, part, out, nullptr, 0, st);
+            k_gram64<false><<<G, 256, 0, st>>>(n, nblk, Aptrs, B, part, nullptr, 0, none);
+        launch_gram64_reduce(nblk * 64, G / npair, n, nblk, G, part, out, nullptr, 0, none, st);
         return;
     }
     const int nchunk = gram_chunks(n, nblk);
@@ -914,15 +897,17 @@ void launch_gram_seg(const DevTopo& t, int n, const double* const* Aptrs, int nb
     if (nblk == 0) return;
     const int nseg = (int)t.hkseg.size();
     const int npair = (nblk + 1) / 2;
-    int G = 0;
-    for (const KrySeg& q : t.hkseg) G += std::max(npair, q.base);
+    if (nseg > kMaxSegDesigns) throw std::length_error("too many designs for a segmented Gram product");
+    SegBases sb{};
+    for (int d = 0; d < nseg; ++d) sb.w[d + 1] = sb.w[d] + std::max(npair, t.hkseg[d].base);
+    const int G = sb.w[nseg];
     if ((long long)G * 4 * 4096 > kGramPartCap) throw std::length_error("Gram partial buffer too small");
     (void)n;
     if (f32)
-        k_gram64<true><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
+        k_gram64<true><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg, sb);
     else
-        k_gram64<false><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg);
-    launch_gram64_reduce(nseg * nblk * 64, G / (nseg * npair), 0, nblk, G, part, out, t.kseg, nseg, st);
+        k_gram64<false><<<G, 256, 0, st>>>(0, nblk, Aptrs, B, part, t.kseg, nseg, sb);
+    launch_gram64_reduce(nseg * nblk * 64, G / (nseg * npair), 0, nblk, G, part, out, t.kseg, nseg, sb, st);
 }
 
 void launch_ts_seg(const DevTopo& t, int n, int nblk, const double* const* Aptrs, const double* Mats, long long mstride,

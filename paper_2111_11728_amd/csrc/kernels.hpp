@@ -43,6 +43,11 @@ struct TrsmDesc {   // B <- L^{-1} B, L: n x n (ldl), B: n x ncols (ldb), row-ma
     int n, ldl, ncols, ldb;
 };
 
+// first Gram workgroup of each design of a segmented product (w[nseg] = total), by value
+constexpr int kMaxSegDesigns = 64;
+struct SegBases {
+    int w[kMaxSegDesigns + 1];
+};
 // FETI-DP coarse matrix Kbar_cc of several independent designs is block diagonal: one dense
 // block per design (corners cg0 .. cg0 + n - 1, row-major at off in the block buffer).
 struct CoarseBlk {
