@@ -1440,14 +1440,14 @@ void recover(feti_ctx* c, double* u) {
                 launch_coarse(t, 1, 0, c->fbar_s, nullptr, c->Kcc_inv, 1.0, c->uc, c->tcbuf, st);
             }
         }
-        launch_dp_ub(t, c->F64, c->S, c->g, c->xb, c->uc, c->ubeta, st);
+        launch_dp_ub(t, c->F64, c->S, c->g, c->xb, c->uc, c->ubeta, c->part, st);
     } else {
         // alpha = (G G^T)^{-1} G (d - F lambda)
         apply_F(c, 1, FETI_FP64, c->lam, c->Qtmp);
         launch_axpby(P.n_lambda, 1.0, c->d, -1.0, c->Qtmp, st);
         launch_proj_G(t, 1, c->Qtmp, c->Rb, c->GY, st);
         launch_small_gemm(c->n_alpha, 1, c->n_alpha, c->GG_inv, c->GY, c->alpha, 1.0, st);
-        launch_tfeti_ub(t, c->F64, c->g, c->xb, c->ubeta, st);
+        launch_tfeti_ub(t, c->F64, c->g, c->xb, c->ubeta, c->part, st);
         alpha = c->alpha;
     }
     CHECK_LAUNCH();

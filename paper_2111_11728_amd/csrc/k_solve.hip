@@ -394,47 +394,64 @@ void launch_gather_B(const DevTopo& t, const double* lam, double* xb, hipStream_
     if (t.nb_tot) k_gather_B<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, t.bg_ptr, t.bg_row, t.bg_sg, lam, xb);
 }
 
-// Interface displacements: u_b = F_s (g_b - S_bc u_c^s - (B^sT lambda)_b), u_beta = [u_b; u_c^s]
-// (FETI-DP; for TFETI n_c = 0 and F_s is the pseudo-inverse block).
-__global__ void __launch_bounds__(256) k_interface_u(const SubMeta* __restrict__ subs, const double* __restrict__ F64,
-                                                     const double* __restrict__ S, const double* __restrict__ g,
-                                                     const double* __restrict__ xb, const double* __restrict__ uc,
-                                                     const int* __restrict__ c_glob, double* ubeta) {
-    extern __shared__ double sh[];
-    const int s = blockIdx.x;
+// Interface displacements of the recovery: u_b = F_s (g_b - S_bc u_c^s - (B^sT lambda)_b) and
+// u_beta = [u_b; u_c^s] (FETI-DP; in TFETI n_c = 0 and F_s is the pseudo-inverse block), in two
+// passes. k_ub_rhs: gh_s = g_b - x_b - S_bc u_c (thread per interface row, x_b = (B^sT lambda)_b)
+// into scratch indexed like x_b. k_ub_gemv: u_b = F_s gh_s, a wavefront per row and 16 rows per
+// workgroup (many workgroups per subdomain), then the corner values behind the interface rows.
+__global__ void __launch_bounds__(256) k_ub_rhs(const SubMeta* __restrict__ subs, const double* __restrict__ S,
+                                                const double* __restrict__ g, const double* __restrict__ xb,
+                                                const double* __restrict__ uc, const int* __restrict__ c_glob,
+                                                double* __restrict__ gh) {
+    const int s = blockIdx.y;
     const SubMeta M = subs[s];
-    double* ucs = sh;              // n_c
-    double* gh = sh + M.n_c;       // n_b
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M.n_b) return;
     const long long ob = M.off_b + M.off_c;
-    for (int c = threadIdx.x; c < M.n_c; c += 256) ucs[c] = uc[c_glob[M.off_c + c]];
-    __syncthreads();
-    for (int j = threadIdx.x; j < M.n_b; j += 256) {
-        double v = g[ob + j] - xb[M.off_b + j];
-        for (int c = 0; c < M.n_c; ++c) v -= S[M.off_S + (long long)j * M.n_beta + M.n_b + c] * ucs[c];
-        gh[j] = v;
-    }
-    __syncthreads();
+    double v = g[ob + j] - xb[M.off_b + j];
+    if (S)
+        for (int c = 0; c < M.n_c; ++c)
+            v -= S[M.off_S + (long long)j * M.n_beta + M.n_b + c] * uc[c_glob[M.off_c + c]];
+    gh[M.off_b + j] = v;
+}
+
+constexpr int kUbRows = 16;
+__global__ void __launch_bounds__(256) k_ub_gemv(const SubMeta* __restrict__ subs, const double* __restrict__ F64,
+                                                 const double* __restrict__ gh, const double* __restrict__ uc,
+                                                 const int* __restrict__ c_glob, double* __restrict__ ubeta) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int row = wave; row < M.n_b; row += 4) {
+    const long long ob = M.off_b + M.off_c;
+    const double* gs = gh + M.off_b;
+    for (int rr = wave; rr < kUbRows; rr += 4) {
+        const int row = blockIdx.x * kUbRows + rr;
+        if (row >= M.n_b) break;   // uniform over the wavefront
         const double* Fr = F64 + M.off_F + (long long)row * M.ldF;
-        double v = 0.0;
-        for (int j = lane; j < M.n_b; j += 64) v += Fr[j] * gh[j];
-        v = warp_sum(v);
+        double v0 = 0.0, v1 = 0.0;
+        int j = lane;
+        for (; j + 64 < M.n_b; j += 128) {
+            v0 = fma(Fr[j], gs[j], v0);
+            v1 = fma(Fr[j + 64], gs[j + 64], v1);
+        }
+        if (j < M.n_b) v0 = fma(Fr[j], gs[j], v0);
+        const double v = wave_sum_dpp(v0 + v1);
         if (lane == 0) ubeta[ob + row] = v;
     }
-    for (int c = threadIdx.x; c < M.n_c; c += 256) ubeta[ob + M.n_b + c] = ucs[c];
+    if (blockIdx.x == 0 && uc)
+        for (int c = threadIdx.x; c < M.n_c; c += 256) ubeta[ob + M.n_b + c] = uc[c_glob[M.off_c + c]];
 }
 
 void launch_dp_ub(const DevTopo& t, const double* F64, const double* S, const double* g, const double* xb,
-                  const double* uc, double* ubeta, hipStream_t st) {
-    k_interface_u<<<t.n_sub, 256, sizeof(double) * (t.max_nb + t.max_nc + 1), st>>>(t.subs, F64, S, g, xb, uc,
-                                                                                   t.c_glob, ubeta);
+                  const double* uc, double* ubeta, double* scratch, hipStream_t st) {
+    k_ub_rhs<<<dim3((t.max_nb + 255) / 256, t.n_sub), 256, 0, st>>>(t.subs, S, g, xb, uc, t.c_glob, scratch);
+    k_ub_gemv<<<dim3((t.max_nb + kUbRows - 1) / kUbRows, t.n_sub), 256, 0, st>>>(t.subs, F64, scratch, uc, t.c_glob,
+                                                                                ubeta);
 }
 
 void launch_tfeti_ub(const DevTopo& t, const double* F64, const double* g, const double* xb, double* ubeta,
-                     hipStream_t st) {
-    k_interface_u<<<t.n_sub, 256, sizeof(double) * (t.max_nb + 1), st>>>(t.subs, F64, nullptr, g, xb, nullptr,
-                                                                        t.c_glob, ubeta);
+                     double* scratch, hipStream_t st) {
+    launch_dp_ub(t, F64, nullptr, g, xb, nullptr, ubeta, scratch, st);
 }
 
 // ---- rigid-body modes of a local DOF (same basis as the setup kernels) ----

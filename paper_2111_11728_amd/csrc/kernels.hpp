@@ -267,10 +267,11 @@ void launch_z_gemv(const DevTopo& t, const double* Z, const double* ubeta, const
 void launch_local_F(const DevTopo& t, const double* F64, const double* g, double* yb, double* yc, hipStream_t st);
 void launch_fbar(const DevTopo& t, const double* g, const double* yc, double* fbar_s, hipStream_t st);
 void launch_gather_B(const DevTopo& t, const double* lam, double* xb, hipStream_t st);   // xb = B^T lam per subdomain
+// scratch: nb_tot doubles
 void launch_dp_ub(const DevTopo& t, const double* F64, const double* S, const double* g, const double* xb,
-                  const double* uc, double* ubeta, hipStream_t st);
+                  const double* uc, double* ubeta, double* scratch, hipStream_t st);
 void launch_tfeti_ub(const DevTopo& t, const double* F64, const double* g, const double* xb, double* ubeta,
-                     hipStream_t st);
+                     double* scratch, hipStream_t st);
 void launch_tfeti_e(const DevTopo& t, const double* fi, const double* fbeta, const double* Cit, double* e,
                     hipStream_t st);
 void launch_assemble_loc(const DevTopo& t, const double* ui, const double* ubeta, const double* Cit,
