@@ -229,6 +229,160 @@ __global__ void __launch_bounds__(kSwT) k_bt_bsweep(const SubMeta* __restrict__ 
     }
 }
 
+// Sweeps for lines of up to kSweepBigLine DOFs (3D plane blocks), on the same 1024-thread
+// layout over 128 x 128 tiles: a tile's sixteen loads per lane are in flight together, the
+// forward sweep accumulates a row tile over its column tiles before one wavefront sum per row,
+// the backward sweep a column tile over its row tiles before one LDS reduction; the zero tiles
+// above the diagonal of L_kk^{-1} are skipped.
+constexpr int kSweepBigLine = 512;
+
+// a[p][h] = A[r0 + w + 16 p][c0 + l + 64 h] (row-major, ld columns; rows < nr, columns < nc and,
+// when lower, column <= row), 0 elsewhere
+__device__ __forceinline__ void sweep_tile(double (&a)[kSwP][2], const double* __restrict__ A, int ld, int r0, int c0,
+                                           int nr, int nc, bool lower) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < kSwP; ++p)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = r0 + w + kSwW * p, q = c0 + l + 64 * h;
+            a[p][h] = (r < nr && q < nc && (!lower || q <= r)) ? A[(long long)r * ld + q] : 0.0;
+        }
+}
+
+// y[r] = sum_q A[r][q] x[q] for the rows of row tile rt (all column tiles), valid in every lane
+__device__ __forceinline__ void big_rows(const double* __restrict__ A, int n, int nc, int rt, const double* x, bool lower,
+                                         double (&y)[kSwP]) {
+    const int l = threadIdx.x & 63;
+    double part[kSwP];
+#pragma unroll
+    for (int p = 0; p < kSwP; ++p) part[p] = 0.0;
+    const int ct_end = lower ? rt + 1 : (nc + kSweepMaxLine - 1) / kSweepMaxLine;
+    for (int ct = 0; ct < ct_end; ++ct) {
+        double a[kSwP][2];
+        sweep_tile(a, A, nc, rt * kSweepMaxLine, ct * kSweepMaxLine, n, nc, lower);
+        const double x0 = x[ct * kSweepMaxLine + l], x1 = x[ct * kSweepMaxLine + l + 64];
+#pragma unroll
+        for (int p = 0; p < kSwP; ++p) part[p] = fma(a[p][1], x1, fma(a[p][0], x0, part[p]));
+    }
+#pragma unroll
+    for (int p = 0; p < kSwP; ++p) y[p] = wave_sum_dpp(part[p]);
+}
+
+// y[ct*128 + t] = sum_r A[r][ct*128 + t] x[r] over the rows r >= row of the diagonal when lower
+// (red: kSwW x 128 doubles; y written by threads < 128; ends with a barrier)
+__device__ __forceinline__ void big_cols(const double* __restrict__ A, int nr, int nc, int ct, const double* x,
+                                         bool lower, double* red, double* y) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double c0 = 0.0, c1 = 0.0;
+    const int rt_end = (nr + kSweepMaxLine - 1) / kSweepMaxLine;
+    for (int rt = lower ? ct : 0; rt < rt_end; ++rt) {
+        double a[kSwP][2];
+        sweep_tile(a, A, nc, rt * kSweepMaxLine, ct * kSweepMaxLine, nr, nc, lower);
+#pragma unroll
+        for (int p = 0; p < kSwP; ++p) {
+            const double xr = x[rt * kSweepMaxLine + w + kSwW * p];
+            c0 = fma(a[p][0], xr, c0);
+            c1 = fma(a[p][1], xr, c1);
+        }
+    }
+    red[w * kSweepMaxLine + l] = c0;
+    red[w * kSweepMaxLine + l + 64] = c1;
+    __syncthreads();
+    if (threadIdx.x < kSweepMaxLine) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSwW; ++q) t += red[q * kSweepMaxLine + threadIdx.x];
+        y[ct * kSweepMaxLine + threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kSwT) k_bt_fsweep_big(const SubMeta* __restrict__ subs,
+                                                        const LineMeta* __restrict__ lines,
+                                                        const double* __restrict__ Lbuf, const double* __restrict__ Li,
+                                                        double* h) {
+    __shared__ double xp[kSweepBigLine], v[kSweepBigLine];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double* hs = h + M.off_i;
+    for (int q = threadIdx.x; q < kSweepBigLine; q += kSwT) xp[q] = 0.0;
+    double y[kSwP];
+    for (int k = 0; k < M.n_lines; ++k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        const int nt = (Lk.n + kSweepMaxLine - 1) / kSweepMaxLine;
+        __syncthreads();   // xp of the previous line complete
+        // v = b_k - L_{k,k-1} x_{k-1}
+        for (int rt = 0; rt < nt; ++rt) {
+            if (Lk.n_prev > 0) {
+                big_rows(Lbuf + Lk.off_sub, Lk.n, Lk.n_prev, rt, xp, false, y);
+            } else {
+#pragma unroll
+                for (int p = 0; p < kSwP; ++p) y[p] = 0.0;
+            }
+#pragma unroll
+            for (int p = 0; p < kSwP; ++p) {
+                const int r = rt * kSweepMaxLine + w + kSwW * p;
+                if (l == 0 && r < Lk.n) v[r] = hs[Lk.i0 + r] - y[p];
+            }
+        }
+        for (int q = Lk.n + threadIdx.x; q < kSweepBigLine; q += kSwT) v[q] = 0.0;
+        __syncthreads();   // v complete, xp free
+        // x_k = L_kk^{-1} v
+        for (int rt = 0; rt < nt; ++rt) {
+            big_rows(Li + Lk.off_inv, Lk.n, Lk.n, rt, v, true, y);
+#pragma unroll
+            for (int p = 0; p < kSwP; ++p) {
+                const int r = rt * kSweepMaxLine + w + kSwW * p;
+                if (l == 0 && r < Lk.n) {
+                    hs[Lk.i0 + r] = y[p];
+                    xp[r] = y[p];
+                }
+            }
+        }
+        for (int q = Lk.n + threadIdx.x; q < kSweepBigLine; q += kSwT) xp[q] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kSwT) k_bt_bsweep_big(const SubMeta* __restrict__ subs,
+                                                        const LineMeta* __restrict__ lines,
+                                                        const double* __restrict__ Lbuf, const double* __restrict__ Li,
+                                                        double* x) {
+    __shared__ double xn[kSweepBigLine], wv[kSweepBigLine], cs[kSweepBigLine];
+    __shared__ double red[kSwW * kSweepMaxLine];
+    const int s = blockIdx.x;
+    const SubMeta M = subs[s];
+    double* xg = x + M.off_i;
+    for (int q = threadIdx.x; q < kSweepBigLine; q += kSwT) xn[q] = 0.0;
+    for (int k = M.n_lines - 1; k >= 0; --k) {
+        const LineMeta Lk = lines[M.line0 + k];
+        if (Lk.n == 0) continue;
+        const int nt = (Lk.n + kSweepMaxLine - 1) / kSweepMaxLine;
+        // w = t_k - L_{k+1,k}^T x_{k+1}  (L_{k+1,k}: n_next x n, row-major)
+        const int n_next = k + 1 < M.n_lines ? lines[M.line0 + k + 1].n : 0;
+        __syncthreads();   // xn of the previous line complete
+        if (n_next > 0) {
+            const double* C = Lbuf + lines[M.line0 + k + 1].off_sub;
+            for (int ct = 0; ct < nt; ++ct) big_cols(C, n_next, Lk.n, ct, xn, false, red, cs);
+        }
+        for (int q = threadIdx.x; q < kSweepBigLine; q += kSwT)
+            wv[q] = q < Lk.n ? xg[Lk.i0 + q] - (n_next > 0 ? cs[q] : 0.0) : 0.0;
+        __syncthreads();   // wv complete
+        // x_k = L_kk^{-T} w: x_q = sum_{r >= q} Li[r][q] w_r
+        for (int ct = 0; ct < nt; ++ct) big_cols(Li + Lk.off_inv, Lk.n, Lk.n, ct, wv, true, red, cs);
+        for (int q = threadIdx.x; q < kSweepBigLine; q += kSwT) {
+            if (q < Lk.n) {
+                xg[Lk.i0 + q] = cs[q];
+                xn[q] = cs[q];
+            } else {
+                xn[q] = 0.0;
+            }
+        }
+    }
+}
+
 // Li = L_kk^{-1} for every line block of every subdomain (identity, then L_kk^{-1} I).
 __global__ void __launch_bounds__(256) k_bt_invert(const LineMeta* __restrict__ lines, const double* __restrict__ Lbuf,
                                                    double* Li) {
@@ -241,15 +395,18 @@ __global__ void __launch_bounds__(256) k_bt_invert(const LineMeta* __restrict__ 
     wg_trsm_lower(Lk.n, Lk.n, Lbuf + Lk.off_diag, Lk.n, X, Lk.n, 1, lds);
 }
 
-// (lines <= 128 DOFs get their inverses from the factorisation itself)
+// (lines <= 128 DOFs get their inverses from the factorisation itself; longer lines, up to
+// kSweepBigLine, from this kernel)
 void launch_bt_invert(const DevTopo& t, const double* L, double* Li, hipStream_t st) {
-    if (t.max_line > 128 && t.max_line <= kSweepMaxLine && t.n_lines_tot > 0)
+    if (t.max_line > kSweepMaxLine && t.max_line <= kSweepBigLine && t.n_lines_tot > 0)
         k_bt_invert<<<t.n_lines_tot, 256, 0, st>>>(t.lines, L, Li);
 }
 
 void launch_bt_fsolve1(const DevTopo& t, const double* L, const double* Li, double* h, hipStream_t st) {
     if (t.max_line <= kSweepMaxLine)
         k_bt_fsweep<<<t.n_sub, kSwT, 0, st>>>(t.subs, t.lines, L, Li, h);
+    else if (t.max_line <= kSweepBigLine)
+        k_bt_fsweep_big<<<t.n_sub, kSwT, 0, st>>>(t.subs, t.lines, L, Li, h);
     else
         k_bt_fsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, h);
 }
@@ -257,6 +414,8 @@ void launch_bt_fsolve1(const DevTopo& t, const double* L, const double* Li, doub
 void launch_bt_bsolve1(const DevTopo& t, const double* L, const double* Li, double* x, hipStream_t st) {
     if (t.max_line <= kSweepMaxLine)
         k_bt_bsweep<<<t.n_sub, kSwT, 0, st>>>(t.subs, t.lines, L, Li, x);
+    else if (t.max_line <= kSweepBigLine)
+        k_bt_bsweep_big<<<t.n_sub, kSwT, 0, st>>>(t.subs, t.lines, L, Li, x);
     else
         k_bt_bsolve1<<<t.n_sub, 64, sizeof(double) * std::max(1, t.max_line), st>>>(t.subs, t.lines, L, x);
 }
