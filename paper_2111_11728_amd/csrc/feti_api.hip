@@ -1,10 +1,12 @@
 // C ABI of the FETI library: context, setup pipeline, Krylov drivers, recovery.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <cstdlib>
 #include <map>
 #include <memory>
@@ -233,18 +235,28 @@ struct feti_ctx {
 
 namespace {
 
-// Packs per-subdomain row-block ranges into F*Lambda tiles. The tiles of subdomain s sit at
-// positions congruent to s mod 8 (workgroup i runs on XCD i mod 8), so the tiles that gather
-// the same X_s share one L2; uneven buckets are padded with empty slots.
+// Packs per-subdomain row-block ranges into F*Lambda tiles. Workgroup i runs on XCD i mod 8,
+// so the tiles of one subdomain, which gather the same X_s, are kept in one XCD's bucket (one
+// L2). A tile's time is taken as its contraction length ldF times the wavefronts its busiest
+// SIMD runs; an XCD's 32 CUs take its tiles longest first, each tile going to the CU that
+// frees first. Subdomains are placed largest first, each on the XCD whose finishing time so
+// modelled grows least (ties: the least work), and every bucket lists its tiles longest
+// first. Uneven buckets are padded with empty slots.
 struct RbRange {
     int red0, n_red, d0, n_d;
 };
 // max_d caps the FP64 row blocks of one tile (small tiles spread FP64 work over many CUs);
 // xcd = false lists the tiles in order (no XCD grouping, no empty slots).
-std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, int max_d = kFlWaves, bool xcd = true,
-                               int max_red = 2 * kFlWaves) {
-    std::vector<std::vector<FlTile>> bucket(8);
-    for (int s = 0; s < (int)rr.size(); ++s) {
+std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, const std::vector<int>& ld, int flags = 0,
+                               int max_d = kFlWaves, bool xcd = true, int max_red = 2 * kFlWaves) {
+    const int ns = (int)rr.size();
+    std::vector<std::vector<FlTile>> per(ns);
+    std::vector<double> cost(ns, 0.0);
+    auto tile_cost = [&](const FlTile& T) {
+        const int waves = (T.n_red + 1) / 2 + T.n_d;
+        return (double)ld[T.s] * ((waves + 3) / 4);
+    };
+    for (int s = 0; s < ns; ++s) {
         RbRange r = rr[s];
         while (r.n_red > 0 || r.n_d > 0) {
             FlTile T{s, r.red0, std::min({r.n_red, 2 * kFlWaves, max_red}), r.d0, 0, flags, 0, 0};
@@ -254,10 +266,51 @@ std::vector<FlTile> pack_tiles(const std::vector<RbRange>& rr, int flags = 0, in
             r.n_red -= T.n_red;
             r.d0 += T.n_d;
             r.n_d -= T.n_d;
-            bucket[xcd ? s % 8 : 0].push_back(T);
+            per[s].push_back(T);
+            cost[s] += tile_cost(T);
         }
     }
-    if (!xcd) return bucket[0];
+    if (!xcd) {
+        std::vector<FlTile> out;
+        for (auto& v : per) out.insert(out.end(), v.begin(), v.end());
+        return out;
+    }
+    std::vector<int> order(ns);
+    for (int s = 0; s < ns; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    constexpr int kCuPerXcd = 32;
+    std::vector<std::vector<FlTile>> bucket(8);
+    std::vector<std::vector<double>> cu(8, std::vector<double>(kCuPerXcd, 0.0));   // min-heaps
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto place = [&](std::vector<double>& h, const std::vector<FlTile>& tiles) {
+        double end = 0.0;
+        for (const FlTile& T : tiles) {   // tiles of one subdomain: equal or decreasing cost
+            std::pop_heap(h.begin(), h.end(), std::greater<double>());
+            h.back() += tile_cost(T);
+            end = std::max(end, h.back());
+            std::push_heap(h.begin(), h.end(), std::greater<double>());
+        }
+        return end;
+    };
+    for (int s : order) {
+        if (per[s].empty()) continue;
+        std::sort(per[s].begin(), per[s].end(), [&](const FlTile& a, const FlTile& c) { return tile_cost(a) > tile_cost(c); });
+        int best = 0;
+        double best_end = 0.0;
+        for (int x = 0; x < 8; ++x) {
+            std::vector<double> h = cu[x];
+            const double end = std::max(*std::max_element(h.begin(), h.end()), place(h, per[s]));
+            if (x == 0 || end < best_end || (end == best_end && load[x] < load[best])) {
+                best = x;
+                best_end = end;
+            }
+        }
+        place(cu[best], per[s]);
+        load[best] += cost[s];
+        bucket[best].insert(bucket[best].end(), per[s].begin(), per[s].end());
+    }
+    for (auto& b : bucket)
+        std::stable_sort(b.begin(), b.end(), [&](const FlTile& a, const FlTile& c) { return tile_cost(a) > tile_cost(c); });
     size_t mx = 0;
     for (auto& b : bucket) mx = std::max(mx, b.size());
     std::vector<FlTile> out;
@@ -292,13 +345,15 @@ void build_fl_tiles(feti_ctx* c) {
         out = FlTiles{dev, (int)v.size()};
     };
     std::vector<RbRange> r64(ns), rred(ns);
+    std::vector<int> ld(ns);
     for (int s = 0; s < ns; ++s) {
+        ld[s] = c->hsubs[s].ldF;
         const int nrb = c->hsubs[s].rows_F / 16;
         r64[s] = RbRange{0, 0, 0, nrb};
         rred[s] = RbRange{0, nrb, 0, 0};
     }
-    put(pack_tiles(r64, 0, q.max_d, q.xcd != 0), c->fl64_dev, c->fl64_cap, t.fl64);
-    put(pack_tiles(rred, 0, q.max_d, q.xcd != 0, q.max_red), c->flred_dev, c->flred_cap, t.flred);
+    put(pack_tiles(r64, ld, 0, q.max_d, q.xcd != 0), c->fl64_dev, c->fl64_cap, t.fl64);
+    put(pack_tiles(rred, ld, 0, q.max_d, q.xcd != 0, q.max_red), c->flred_dev, c->flred_cap, t.flred);
     if (c->hybrid && (int)c->sub_ok.size() == ns) {
         std::vector<RbRange> rr(ns), rd(ns);
         for (int s = 0; s < ns; ++s) {
@@ -309,8 +364,8 @@ void build_fl_tiles(feti_ctx* c) {
         }
         // one launch: the FP64 split-contraction tiles follow the reduced ones and fill the CUs
         // those leave free (the kernel dispatches a tile by its flags, whatever the precision)
-        std::vector<FlTile> hyb = pack_tiles(rr, kFlNoT, q.max_d, q.xcd != 0, q.max_red);
-        const std::vector<FlTile> h64 = pack_tiles(rd, kFlSplitK, q.split_d, false);
+        std::vector<FlTile> hyb = pack_tiles(rr, ld, kFlNoT, q.max_d, q.xcd != 0, q.max_red);
+        const std::vector<FlTile> h64 = pack_tiles(rd, ld, kFlSplitK, q.split_d, false);
         hyb.insert(hyb.end(), h64.begin(), h64.end());
         put(hyb, c->fl_hyb_dev, c->fl_hyb_cap, c->fl_hyb);
     }
