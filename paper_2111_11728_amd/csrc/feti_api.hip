@@ -640,6 +640,38 @@ void build_layout(feti_ctx* c) {
         t.gmap_R = R;
     }
     if (t.max_nc > 32) throw std::runtime_error("more than 32 corner DOFs in one subdomain");
+    {   // preconditioner workgroups: at most one per CU in all; parts go one at a time to the
+        // subdomain with the most packed tiles per workgroup (at most kPsMaxSplit parts each)
+        std::vector<int> G(ns, 1), nt(ns);
+        for (int s = 0; s < ns; ++s) {
+            const int nT = (c->hsubs[s].n_b + 63) / 64;
+            nt[s] = nT * (nT + 1) / 2;
+        }
+        int total = ns;
+        while (total < 256) {
+            int best = -1;
+            for (int s = 0; s < ns; ++s)
+                if (G[s] < kPsMaxSplit && nt[s] > G[s] &&
+                    (best < 0 || (long long)nt[s] * G[best] > (long long)nt[best] * G[s]))
+                    best = s;
+            if (best < 0) break;
+            ++G[best];
+            ++total;
+        }
+        std::vector<int4> wk;
+        t.ps_maxG = 1;
+        for (int s = 0; s < ns; ++s) {
+            t.ps_maxG = std::max(t.ps_maxG, G[s]);
+            for (int g = 0; g < G[s]; ++g) wk.push_back(int4{s, g, G[s], 0});
+        }
+        // longest parts first
+        std::stable_sort(wk.begin(), wk.end(), [&](const int4& a, const int4& b) {
+            return (long long)nt[a.x] * b.z > (long long)nt[b.x] * a.z;
+        });
+        t.ps_work = c->upload(wk);
+        t.ps_G = c->upload(G);
+        t.ps_nwg = (int)wk.size();
+    }
     t.bg_ptr = c->upload(P.bg_ptr);
     t.bg_row = c->upload(P.bg_row);
     t.bg_sg = c->upload(P.bg_sg);

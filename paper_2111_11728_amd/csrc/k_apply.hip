@@ -690,11 +690,12 @@ void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, doubl
 // Preconditioner (Sec. 3.1, Eq. 13): x_s = B~^sT r = B^sT W^s r, y_s = S~^s x_s.
 // S~^s is symmetric and stored as its upper triangle in 64x64 tiles, so every stored value is
 // read once: tile (I, J) adds S_IJ x_J to y_I (row part) and, for I < J, S_IJ^T x_I to y_J
-// (column part). Workgroup (g, s) takes tiles [g nt / G, (g+1) nt / G) of subdomain s in storage
-// order (column block J outer); thread (wave, lane) holds row i = 4 wave + lane/16 of a tile and
-// columns 4 (lane%16) .. +3 (one 32-byte load per tile, kPsRing tiles ahead). x_s and the partial
-// y_s live in LDS; the column part is summed over the tile rows in a fixed order when J changes.
-// G = 1 writes y_s; G > 1 writes partial g to ypart + g * nb_tot for k_precond_sum.
+// (column part). Subdomain s is split into G_s parts (work[blockIdx.x] = (s, g, G_s)): part g
+// takes tiles [g nt / G_s, (g+1) nt / G_s) in storage order (column block J outer); thread
+// (wave, lane) holds row i = 4 wave + lane/16 of a tile and columns 4 (lane%16) .. +3 (one
+// 32-byte load per tile, kPsRing tiles ahead). x_s and the partial y_s live in LDS; the column
+// part is summed over the tile rows in a fixed order when J changes. With every G_s = 1 the
+// parts write y_s; otherwise part g writes ypart + g * nb_tot for k_precond_sum.
 constexpr int kPsRing = 4;
 typedef double ps4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int tri_col(int t) {   // J with J(J+1)/2 <= t < (J+1)(J+2)/2
@@ -704,7 +705,8 @@ __device__ __forceinline__ int tri_col(int t) {   // J with J(J+1)/2 <= t < (J+1
     return J;
 }
 
-__global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict__ subs, const int* __restrict__ bg_ptr,
+__global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict__ subs, const int4* __restrict__ work,
+                                                      const int* __restrict__ bg_ptr,
                                                       const int* __restrict__ bg_row, const int8_t* __restrict__ bg_sg,
                                                       const double* __restrict__ bg_w, const double* __restrict__ r,
                                                       const double* __restrict__ Pk, double* __restrict__ y,
@@ -713,7 +715,8 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
     double* xs = sh;             // cap
     double* ys = sh + cap;       // cap
     double* red = sh + 2 * cap;  // 16 x 64
-    const int g = blockIdx.x, G = gridDim.x, s = blockIdx.y;
+    const int4 wk = work[blockIdx.x];
+    const int s = wk.x, g = wk.y, G = wk.z;
     const SubMeta M = subs[s];
     const int nb = M.n_b, nT = (nb + 63) >> 6, nt = nT * (nT + 1) / 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = 4 * wave + (lane >> 4), jq = lane & 15;
@@ -788,10 +791,12 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
     for (int q = tid; q < nb; q += 1024) yo[q] = ys[q];
 }
 
-// y[q] = sum over g < G of ypart[g * n + q], in order
-__global__ void k_precond_sum(long long n, int G, const double* __restrict__ ypart, double* __restrict__ y) {
+// y[q] = sum over g < G_s of ypart[g * n + q], in order (s: the subdomain of b DOF q)
+__global__ void k_precond_sum(long long n, const int* __restrict__ bq_s, const int* __restrict__ ps_G,
+                              const double* __restrict__ ypart, double* __restrict__ y) {
     const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (q >= n) return;
+    const int G = ps_G[bq_s[q]];
     double v = 0.0;
     for (int g = 0; g < G; ++g) v += ypart[g * n + q];
     y[q] = v;
@@ -799,17 +804,15 @@ __global__ void k_precond_sum(long long n, int G, const double* __restrict__ ypa
 
 void launch_precond_local(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* ypart,
                           double* y, hipStream_t st) {
-    if (t.nb_tot == 0) return;
-    // about 256 workgroups in all: subdomains split over up to kPsMaxSplit workgroups when few
-    const int G = std::max(1, std::min(kPsMaxSplit, 256 / std::max(1, t.n_sub)));
+    if (t.nb_tot == 0 || t.ps_nwg == 0) return;
     const int cap = (t.max_nb + 63) / 64 * 64;
     const size_t sh = sizeof(double) * (2 * (size_t)cap + 16 * 64);
-    if (G == 1) {
-        k_precond_sym<<<dim3(1, t.n_sub), 1024, sh, st>>>(t.subs, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, y, 0, cap);
+    if (t.ps_maxG == 1) {
+        k_precond_sym<<<t.ps_nwg, 1024, sh, st>>>(t.subs, t.ps_work, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, y, 0, cap);
     } else {
-        k_precond_sym<<<dim3(G, t.n_sub), 1024, sh, st>>>(t.subs, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, ypart,
-                                                          t.nb_tot, cap);
-        k_precond_sum<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, G, ypart, y);
+        k_precond_sym<<<t.ps_nwg, 1024, sh, st>>>(t.subs, t.ps_work, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, ypart,
+                                                  t.nb_tot, cap);
+        k_precond_sum<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, t.bq_s, t.ps_G, ypart, y);
     }
 }
 

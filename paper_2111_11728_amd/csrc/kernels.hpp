@@ -121,6 +121,9 @@ struct DevTopo {
     const int* cc_j = nullptr;
     const int* ax_first[3] = {nullptr, nullptr, nullptr};
     const int* ax_cnt[3] = {nullptr, nullptr, nullptr};
+    const int4* ps_work = nullptr;    // preconditioner workgroups: (subdomain, part g, parts G_s, 0)
+    const int* ps_G = nullptr;        // parts G_s of every subdomain
+    int ps_nwg = 0, ps_maxG = 1;
     const int* gmap = nullptr;        // fixed-width gather map: gmap[q*gmap_R + t] = sign*(row+1), 0 unused
     int gmap_R = 1;
     int n_lines_tot = 0;              // interior line (2D) / plane (3D) blocks over all subdomains
