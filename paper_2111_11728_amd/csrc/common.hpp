@@ -89,4 +89,23 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
     return (rl(0) + rl(16)) + (rl(32) + rl(48));
 }
 
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+// Streamed operands go through buffer resources covering exactly the rows a wavefront owns:
+// a load past num_records returns zeros without touching memory, so the loads of the ring
+// are unconditional (no per-lane branches, no zero fill) and the compiler can count them.
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const double* base, int nbytes) {
+    // wavefront-uniform by construction; readfirstlane keeps the descriptor in scalar registers
+    // (a per-lane copy would turn every load into a loop over distinct descriptors)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
+                                             __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
+}
+__device__ __forceinline__ v4d_t load4d(__amdgpu_buffer_rsrc_t r, int off) {
+    const v2d_t lo = __builtin_bit_cast(v2d_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const v2d_t hi = __builtin_bit_cast(v2d_t, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
+    return v4d_t{lo[0], lo[1], hi[0], hi[1]};
+}
+
 }  // namespace feti

@@ -696,7 +696,7 @@ void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, doubl
 // 32-byte load per tile, kPsRing tiles ahead). x_s and the partial y_s live in LDS; the column
 // part is summed over the tile rows in a fixed order when J changes. With every G_s = 1 the
 // parts write y_s; otherwise part g writes ypart + g * nb_tot for k_precond_sum.
-constexpr int kPsRing = 4;
+constexpr int kPsRing = 8;
 typedef double ps4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int tri_col(int t) {   // J with J(J+1)/2 <= t < (J+1)(J+2)/2
     int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -722,10 +722,11 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = 4 * wave + (lane >> 4), jq = lane & 15;
     // the first tiles' loads go out before the gather of x (they do not depend on it)
     const int t0 = (int)((long long)g * nt / G), t1 = (int)((long long)(g + 1) * nt / G);
-    const double* T = Pk + M.off_Pk + i * 64 + 4 * jq;
-    auto ld = [&](int t) -> ps4_t {
-        return t < t1 ? *reinterpret_cast<const ps4_t*>(T + (long long)t * 4096) : ps4_t{0.0, 0.0, 0.0, 0.0};
-    };
+    // the part's tiles through a buffer resource: loads past its last tile return zeros, so the
+    // ring's loads are unconditional and their waits counted, not drained
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc(Pk + M.off_Pk + (long long)t0 * 4096, (t1 - t0) * 32768);
+    const int toff = (i * 64 + 4 * jq) * 8;
+    auto ld = [&](int t) -> ps4_t { return load4d(rs, toff + (t - t0) * 32768); };
     ps4_t ring[kPsRing];
 #pragma unroll
     for (int d = 0; d < kPsRing; ++d) ring[d] = ld(t0 + d);
@@ -744,9 +745,9 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
     for (int t = t0; t < t1; t += kPsRing) {
 #pragma unroll
         for (int d = 0; d < kPsRing; ++d) {
+            const ps4_t a = ring[d];
+            ring[d] = ld(t + d + kPsRing);
             if (t + d < t1) {   // uniform over the workgroup
-                const ps4_t a = ring[d];
-                ring[d] = ld(t + d + kPsRing);
                 // row part: y_I[i] += sum_b S[i][b] x_J[b]
                 const ps4_t xj = *reinterpret_cast<const ps4_t*>(xs + 64 * J + 4 * jq);
                 const double rp =

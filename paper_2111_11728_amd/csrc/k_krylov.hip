@@ -78,7 +78,6 @@ __global__ void k_gram_reduce(int nchunk, int nblk, int ka, int kb, const double
 // Matrix-core (FP64 MFMA 16x16x4) tall-skinny products of the block Gram-Schmidt step.
 // Operand layouts of v_mfma_f64_16x16x4f64: A (16x4): lane l holds A[l%16][l/16];
 // B (4x16): lane l holds B[l/16][l%16]; D (16x16): lane l holds D[l/16 + 4v][l%16].
-typedef double v4d_t __attribute__((ext_vector_type(4)));
 
 // part[(b*nchunk + c)][ka x kb] = A_b[rows of c]^T B[rows of c]. The chunk is walked in
 // 64-row tiles staged through LDS; the next tile is loaded into registers while the matrix
@@ -202,7 +201,6 @@ __global__ void __launch_bounds__(256) k_ts_gemm(int n, int kd, int nblk, const 
 // Both use the freedom to permute the contraction and output indices consistently so that
 // every lane reads 16 or 32 contiguous bytes of a row-major n x 64 operand straight from
 // HBM, with a ring of loads in flight; no LDS round trip for the streamed operands.
-typedef double v2d_t __attribute__((ext_vector_type(2)));
 
 constexpr int kTsWaves = 8;   // 128 output rows per workgroup
 
@@ -229,21 +227,6 @@ template <> struct MfmaT<true> {
     static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
 };
 
-// Streamed operands go through buffer resources covering exactly the rows a wavefront owns:
-// a load past num_records returns zeros without touching memory, so the loads of the ring
-// are unconditional (no per-lane branches, no zero fill) and the compiler can count them.
-typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const double* base, int nbytes) {
-    // wavefront-uniform by construction; readfirstlane keeps the descriptor in scalar registers
-    // (a per-lane copy would turn every load into a loop over distinct descriptors)
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
-                                             __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
-}
-__device__ __forceinline__ v4d_t load4d(__amdgpu_buffer_rsrc_t r, int off) {
-    const v2d_t lo = __builtin_bit_cast(v2d_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-    const v2d_t hi = __builtin_bit_cast(v2d_t, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
-    return v4d_t{lo[0], lo[1], hi[0], hi[1]};
-}
 
 // out = beta C + alpha sum_b A_b Psi_b (A_b = Aptrs[b], n x 64; Psi_b = Mats + 4096 b).
 // Wavefront: 16 output rows x 64 columns. Step t = 4 b + q contracts columns 16q..16q+15 of
