@@ -777,8 +777,19 @@ __global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict
     rank_out += blockIdx.x;
     if (mask_out) mask_out += blockIdx.x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    // D staged through LDS by coalesced rows
-    for (int i = 32 * w; i < 32 * w + 32; ++i) Lm[i][l] = (l < k && i < k) ? D[i * k + l] : 0.0;
+    // D staged through LDS by coalesced rows; all 32 loads of a lane are in flight together
+    // (entries outside the k x k matrix read as zeros from the buffer resource)
+    {
+        const __amdgpu_buffer_rsrc_t rd = rows_rsrc(D, k * k * 8);
+        double v[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int i = 32 * w + u;
+            v[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rd, l < k ? (i * k + l) * 8 : k * k * 8, 0, 0));
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) Lm[32 * w + u][l] = v[u];
+    }
     __syncthreads();
     if (w == 0) {
         double a[64];
