@@ -67,6 +67,22 @@ def schur_on(Ks, b_idx, active_idx):
     return Kbb - Kib.T @ X
 
 
+def fetidp_local(Ks, r, c, bpos):
+    """Local FETI-DP operators of one subdomain (Sec. 2.2, Eq. 11-12): with Y = K_rr^{-1} [E_b, K_rc]
+    (E_b the unit columns of the interface positions bpos within r), F_s = (K_rr^{-1})_bb,
+    F_rc^s = (K_rr^{-1} K_rc)_b and Kbar_cc^s = K_cc - K_cr K_rr^{-1} K_rc. Returns
+    (F_s, F_rc^s, Kbar_cc^s, K_rc, LU of K_rr)."""
+    Krr = Ks[r][:, r].tocsc()
+    Krc = Ks[r][:, c].toarray()
+    Kcc = Ks[c][:, c].toarray()
+    lu = _LU(Krr)
+    Eb = np.zeros((r.size, bpos.size))
+    Eb[bpos, np.arange(bpos.size)] = 1.0
+    Y = lu.solve(np.hstack([Eb, Krc]))
+    Yc = Y[:, bpos.size:]
+    return Y[bpos, :bpos.size], Yc[bpos], Kcc - Krc.T @ Yc, Krc, lu
+
+
 class _Common:
     """Weights, preconditioner and direction groups shared by both methods."""
 
@@ -188,19 +204,11 @@ class FETIDP(_Common):
         d_r = np.zeros(self.cons.n_rows)
         for s in range(n_sub):
             r, c = self.split.r[s], self.split.c[s]
-            Ks = self.K[s]
-            Krr = Ks[r][:, r].tocsc()
-            Krc = Ks[r][:, c].toarray()
-            Kcc = Ks[c][:, c].toarray()
-            lu = _LU(Krr)
             bpos = self.cons.bset[s]                 # positions in r
-            Eb = np.zeros((r.size, bpos.size))
-            Eb[bpos, np.arange(bpos.size)] = 1.0
-            Y = lu.solve(np.hstack([Eb, Krc]))
-            self.F_local.append(Y[bpos, :bpos.size])
-            Yc = Y[:, bpos.size:]
-            self.Frc.append(Yc[bpos])
-            self.Kcc_bar.append(Kcc - Krc.T @ Yc)
+            Fs, Frc, Kcc_bar, Krc, lu = fetidp_local(self.K[s], r, c, bpos)
+            self.F_local.append(Fs)
+            self.Frc.append(Frc)
+            self.Kcc_bar.append(Kcc_bar)
             self.Krc.append(Krc)
             self.lu.append(lu)
             self.b_local.append(r[bpos])
