@@ -1,0 +1,119 @@
+"""Parity of the HIP path at the full sizes of the 2D headline workload (16x16 subdomains of 64^2
+elements, 2.1 M DOFs, Beta(0.3, 0.3) density, contrast 1e-9) and of the 3D workload (4x4x4
+subdomains of 12^3 elements), in the configuration the benchmark times: FETI-DP, k-scaling,
+Dirichlet preconditioner, S-FETI with one direction per 2x2 subdomain group, F*Lambda in FP32
+where the rounding test allows.
+
+The oracle cannot run whole at these sizes, so the checks take samples it can compute one by
+one:
+* the local operators F_s, F_rc^s, Kbar_cc^s and the Dirichlet S_s of sampled subdomains, each
+  from the oracle's sparse LU of that subdomain alone; bound max(1e-11, 2 sqrt(n) eps kappa)
+  with kappa the condition number of the factorised block (as in the small-case tests);
+* the displacement u at 4096 seeded DOFs against the global direct solution stored by
+  tests/golden/make_c3_u_sample.py (oracle only).
+"""
+import pathlib
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads
+from oracle import fem, topology
+from oracle import feti as ofeti
+
+torch = pytest.importorskip("torch")
+feti = pytest.importorskip("paper_2111_11728_amd.feti")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+EPS = np.finfo(np.float64).eps
+GOLDEN = pathlib.Path(__file__).with_name("golden") / "c3_u_sample.npz"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def _bound(A):
+    """max(1e-11, 2 sqrt(n) eps kappa(A)) for a sparse SPD block A."""
+    lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = spla.eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    return max(1e-11, 2.0 * np.sqrt(A.shape[0]) * EPS * lmax / lmin)
+
+
+def _spec(prob, **kw):
+    opts = dict(method="fetidp", scaling="k", krylov="sfeti", precond="dirichlet", precision="fp32", tol=1e-6)
+    opts.update(kw)
+    return feti.Spec(prob, **opts)
+
+
+MAKE = {"c3": lambda: workloads.beta_2d(0), "c5": lambda: workloads.modular_3d(0)}
+_TOPO = {}
+
+
+def _topology(name):
+    if name not in _TOPO:
+        prob = MAKE[name]()
+        dec = topology.decompose(prob)
+        split, cons = topology.fetidp_split(dec)
+        E = fem.simp_modulus(prob.rho, prob.p, prob.E0, prob.Emin)
+        K0 = fem.element_stiffness(prob.dim, prob.nu)
+        _TOPO[name] = (prob, dec, split, cons, E, K0)
+    return _TOPO[name]
+
+
+# clamped corner, interior and far corner subdomains (2D); interior and far corner (3D)
+@pytest.mark.parametrize("name,s", [("c3", 0), ("c3", 136), ("c3", 255), ("c5", 21), ("c5", 63)])
+def test_full_size_local_operators(name, s):
+    prob, dec, split, cons, E, K0 = _topology(name)
+    print(f"case full-size local operators {name} subdomain {s}", flush=True)
+    ctx = feti.Context(_spec(prob), _t(prob.rho))
+    Ks = ofeti.subdomain_stiffness(prob, dec.subs[s], E, K0)
+    r, c, bpos = split.r[s], split.c[s], cons.bset[s]
+    Fs, Frc, Kcc_bar, _, _ = ofeti.fetidp_local(Ks, r, c, bpos)
+    tol = _bound(Ks[r][:, r].tocsc())
+    e_F = _rel(ctx.feti_get_local(s, 0), Fs)
+    print(f"  n_b {bpos.size}, bound {tol:.1e}, F_s {e_F:.1e}", flush=True)
+    assert e_F < tol
+    if Frc.size:
+        assert _rel(ctx.feti_get_local(s, 2), Frc) < tol
+        assert _rel(ctx.feti_get_local(s, 3), Kcc_bar) < tol
+    # Dirichlet S_s = K_bb - K_bi K_ii^{-1} K_ib over the subdomain's r set
+    b = r[bpos]
+    S = ofeti.schur_on(Ks, b, r)
+    i_idx = np.setdiff1d(r, b)
+    e_S = _rel(ctx.feti_get_local(s, 1), S)
+    tol_s = _bound(Ks[i_idx][:, i_idx].tocsc())
+    print(f"  S_s {e_S:.1e} (bound {tol_s:.1e})", flush=True)
+    assert e_S < tol_s
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-10, 1e-8), ("fp32", 1e-8, 1e-6)])
+def test_full_size_c3_displacements(precision, tol, bound):
+    """u at 4096 seeded DOFs of the 2.1 M-DOF headline workload against the global direct
+    solution; FP64 F*Lambda to 1e-8 and the mixed form to 1e-6, each solved to a residual
+    tolerance that reaches those errors at this contrast."""
+    if not GOLDEN.exists():
+        pytest.skip("tests/golden/c3_u_sample.npz not generated")
+    g = np.load(GOLDEN)
+    prob = workloads.beta_2d(0)
+    assert int(g["n_dof"]) == prob.n_dof
+    print(f"case full-size c3 displacements {precision} tol {tol}", flush=True)
+    ctx = feti.Context(_spec(prob, precision=precision, tol=tol, max_it=1000), _t(prob.rho))
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
+    info = ctx.feti_solve(_t(prob.load()), u)
+    un = u.cpu().numpy()
+    e = _rel(un[g["idx"]], g["u"])
+    print(f"  iters {info['iters']}, true rel. residual {info['true_rel_res']:.2e}, sampled u error {e:.2e}, "
+          f"norm error {abs(np.linalg.norm(un) - float(g['norm'])) / float(g['norm']):.2e}", flush=True)
+    assert info["true_rel_res"] <= tol
+    assert e <= bound
+    assert abs(np.linalg.norm(un) - float(g["norm"])) <= bound * float(g["norm"])
+    ctx.close()
