@@ -195,6 +195,70 @@ def run_c4(args):
     print(json.dumps(line))
 
 
+def run_c5(args):
+    """3D workload: Hex8 elasticity on 4x4x4 subdomains of 12^3 elements, seeded 0/1 modular
+    density, contrast 1e-6; S-FETI-DP with k-scaling and the Dirichlet preconditioner, F*Lambda
+    mixed FP32/FP64 (--c5-precision fp64 for the plain form); one step = compliance and gradient
+    (setup, solve, recovery, adjoint). Also times F*Lambda at k = 64 in FP64 and FP32. Prints its
+    own JSON line (not the headline metric)."""
+    import torch
+
+    import workloads
+    from paper_2111_11728_amd import feti
+
+    dev = torch.device("cuda:0")
+    prob = workloads.modular_3d(0)
+    spec = feti.Spec(prob, method="fetidp", scaling="k", krylov="sfeti", precond="dirichlet",
+                     precision=args.c5_precision, tol=args.tol, max_it=args.max_it)
+    rho = torch.tensor(prob.rho, device=dev)
+    f = torch.tensor(prob.load(), device=dev)
+    t0 = time.perf_counter()
+    cx = feti.Context(spec, rho)
+    torch.cuda.synchronize()
+    log(f"c5 setup: {time.perf_counter() - t0:.2f} s, n_lambda {cx.sizes['n_lambda']}, "
+        f"{cx.sizes['n_fp64_subs']} subdomains kept in FP64")
+    fl = {}
+    k = 64
+    L = torch.randn(cx.sizes["n_lambda"], k, device=dev, dtype=torch.float64)
+    Q = torch.zeros_like(L)
+    for prec in ("fp64", "fp32"):
+        for _ in range(3):
+            cx.feti_apply_F(k, prec, L, Q, pure=True)
+        ts = []
+        for _ in range(args.flambda_reps):
+            cx.feti_apply_F(k, prec, L, Q, pure=True)
+            ts.append(cx.feti_last_timing(0))
+        fl[prec] = float(np.mean(ts)) * 1e3
+        log(f"c5 F*Lambda {prec}, k = {k}: kernel {fl[prec]:.1f} us")
+    c = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(prob.n_el, dtype=torch.float64, device=dev)
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        cx.feti_compliance_and_grad(rho, f, c, g, u)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        info = cx.feti_compliance_and_grad(rho, f, c, g, u)
+        rec.append((cx.feti_last_timing(2), cx.feti_last_timing(3), info))
+        log(f"c5 step {i}: setup {rec[-1][0]:.1f} ms, solve {rec[-1][1]:.1f} ms, {info['iters']} iterations "
+            f"({info['reduced_iters']} reduced), true rel. residual {info['true_rel_res']:.2e}")
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
+    line = {"metric": f"3D FETI-DP solve time to rel.res {args.tol} (S-FETI, k-scaling)",
+            "value": float(np.mean([r[1] for r in rec])), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": wall, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64" if args.c5_precision == "fp64" else "f32+f64", "data": "synthetic",
+            "config": {"workload": "3D Hex8, 4x4x4 subdomains of 12^3 elements, modular 0/1 rho, contrast 1e-6",
+                       "n_dof": prob.n_dof, "n_lambda": cx.sizes["n_lambda"], "n_cg": cx.sizes["n_cg"],
+                       "directions": cx.sizes["n_groups"]},
+            "setup_ms": float(np.mean([r[0] for r in rec])), "iters": rec[-1][2]["iters"],
+            "reduced_iters": rec[-1][2]["reduced_iters"], "true_rel_res": rec[-1][2]["true_rel_res"],
+            "flambda_k64_us": fl, "compliance": float(c.item())}
+    cx.close()
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +279,8 @@ def main():
     ap.add_argument("--c4", action="store_true", help="the batched multi-design workload instead of the headline")
     ap.add_argument("--c4-designs", type=int, default=64)
     ap.add_argument("--c4-precision", default="fp64")
+    ap.add_argument("--c5", action="store_true", help="the 3D workload instead of the headline")
+    ap.add_argument("--c5-precision", default="fp32")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
@@ -226,6 +292,9 @@ def main():
 
     if args.c4:
         run_c4(args)
+        return
+    if args.c5:
+        run_c5(args)
         return
 
     import torch
