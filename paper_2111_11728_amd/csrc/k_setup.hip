@@ -710,21 +710,58 @@ __global__ void k_tfeti_fix(const SubMeta* __restrict__ subs, int nm, const doub
 
 // FETI-DP: F_rc^T = S_cb F_s (rows n_b.. of the augmented operator) and
 // Kbar_cc^s = S_cc - S_cb F_s S_bc (eliminating b after i from the interface Schur complement).
+// Pass 1: workgroup (x, s) takes columns j = 256 x + t of F_s; a thread keeps the n_c (<= 32)
+// outputs of its column in registers and streams its column of F_s once (coalesced over the
+// workgroup), with S_cb staged through LDS in slices of kFrcSlice columns (zero rows past n_c).
+constexpr int kFrcSlice = 64;
 __global__ void __launch_bounds__(256) k_frc(const SubMeta* __restrict__ subs, const double* __restrict__ Sbuf,
-                                             double* F64, double* Kc) {
+                                             double* F64) {
+    __shared__ __attribute__((aligned(16))) double Sc[kFrcSlice][32];   // Sc[q][c] = S_cb[c][q0 + q]
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int nb = M.n_b, nc = M.n_c;
+    if (nc == 0 || blockIdx.x * 256 >= nb) return;   // uniform over the workgroup
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const double* S = Sbuf + M.off_S;
+    double* F = F64 + M.off_F;
+    double v[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) v[c] = 0.0;
+    for (int q0 = 0; q0 < nb; q0 += kFrcSlice) {
+        const int qn = min(kFrcSlice, nb - q0);
+        __syncthreads();   // the previous slice is consumed
+        for (int e = threadIdx.x; e < kFrcSlice * 32; e += 256) {
+            const int q = e % kFrcSlice, c = e / kFrcSlice;
+            Sc[q][c] = (q < qn && c < nc) ? S[(long long)(nb + c) * M.n_beta + q0 + q] : 0.0;
+        }
+        __syncthreads();
+        if (j < nb) {
+#pragma unroll 4
+            for (int q = 0; q < qn; ++q) {
+                const double f = F[(long long)(q0 + q) * M.ldF + j];
+#pragma unroll
+                for (int c = 0; c < 32; c += 2) {
+                    const double2 sc = *reinterpret_cast<const double2*>(&Sc[q][c]);
+                    v[c] = fma(sc.x, f, v[c]);
+                    v[c + 1] = fma(sc.y, f, v[c + 1]);
+                }
+            }
+        }
+    }
+    if (j < nb)
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+            if (c < nc) F[(long long)(M.rowT + c) * M.ldF + j] = v[c];
+}
+
+// Pass 2: Kbar_cc^s = S_cc - F_rc^T S_bc, one workgroup per subdomain, one thread per entry.
+__global__ void __launch_bounds__(256) k_frc_kc(const SubMeta* __restrict__ subs, const double* __restrict__ Sbuf,
+                                                const double* __restrict__ F64, double* Kc) {
     const int s = blockIdx.x;
     const SubMeta M = subs[s];
     const int nb = M.n_b, nc = M.n_c;
-    if (nc == 0) return;
     const double* S = Sbuf + M.off_S;
-    double* F = F64 + M.off_F;
-    for (long long e = threadIdx.x; e < (long long)nc * nb; e += 256) {
-        const int c = (int)(e / nb), j = (int)(e % nb);
-        double v = 0.0;
-        for (int q = 0; q < nb; ++q) v += S[(long long)(nb + c) * M.n_beta + q] * F[(long long)q * M.ldF + j];
-        F[(long long)(M.rowT + c) * M.ldF + j] = v;
-    }
-    __syncthreads();
+    const double* F = F64 + M.off_F;
     for (int e = threadIdx.x; e < nc * nc; e += 256) {
         const int c = e / nc, c2 = e % nc;
         double v = S[(long long)(nb + c) * M.n_beta + nb + c2];
@@ -996,7 +1033,9 @@ void launch_tfeti_fix(const DevTopo& t, const double* Rb, const double* tau, dou
 }
 
 void launch_frc(const DevTopo& t, const double* S, double* F64, double* Kc, hipStream_t st) {
-    k_frc<<<t.n_sub, 256, 0, st>>>(t.subs, S, F64, Kc);
+    if (t.n_sub == 0 || t.max_nb == 0) return;
+    k_frc<<<dim3((t.max_nb + 255) / 256, t.n_sub), 256, 0, st>>>(t.subs, S, F64);
+    k_frc_kc<<<t.n_sub, 256, 0, st>>>(t.subs, S, F64, Kc);
 }
 
 void launch_swizzle(const DevTopo& t, const double* F64, double* sw64, float* sw32, __hip_bfloat16* hi,
