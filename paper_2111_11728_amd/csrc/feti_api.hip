@@ -776,11 +776,11 @@ void classify_precision(feti_ctx* c) {
     launch_copy_F_rounded(t, c->F64, FETI_FP64, c->W1, st);
     launch_copy_F_rounded(t, c->F64, c->opts.precision, c->W2, st);
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * (t.n_sub + 8), st));
-    launch_potrf(c->d_potrf, t.n_sub, c->W1, c->info, st);
+    launch_potrf(c->d_potrf, t.n_sub, t.max_nb, c->W1, c->info, st);
     CHECK_LAUNCH();
     check_info(c, t.n_sub, "Cholesky of F_s");
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * (t.n_sub + 8), st));
-    launch_potrf(c->d_potrf, t.n_sub, c->W2, c->info, st);
+    launch_potrf(c->d_potrf, t.n_sub, t.max_nb, c->W2, c->info, st);
     launch_pivot_compare(t, c->W1, c->W2, c->info, c->pivdev, st);
     CHECK_LAUNCH();
     std::vector<double> dev(t.n_sub);
@@ -838,7 +838,7 @@ void dense_spd_inverse(feti_ctx* c, int n, const double* A, double* work, double
     HIPCHK(hipMemcpyAsync(c->d_trsm_one, td.data(), sizeof(TrsmDesc), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(work, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int), c->st));
-    launch_potrf(c->d_potrf_one, 1, work, c->info, c->st);
+    launch_potrf(c->d_potrf_one, 1, n, work, c->info, c->st);
     CHECK_LAUNCH();
     check_info(c, 1, what);
     launch_set_identity(Ainv, n, n, c->st);
@@ -861,7 +861,7 @@ void coarse_inverse(feti_ctx* c) {
     hipStream_t st = c->st;
     HIPCHK(hipMemcpyAsync(c->Kcc_w, c->Kcc, sizeof(double) * sz, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * nb, st));
-    launch_potrf(c->d_cc_potrf, nb, c->Kcc_w, c->info, st);
+    launch_potrf(c->d_cc_potrf, nb, maxn, c->Kcc_w, c->info, st);
     CHECK_LAUNCH();
     check_info(c, nb, "coarse Cholesky");
     for (const CoarseBlk& b : B) launch_set_identity(c->Kcc_inv + b.off, b.n, b.n, st);
@@ -917,7 +917,7 @@ void numeric_setup(feti_ctx* c) {
         launch_copy_Sbb(t, c->S, c->W1, 0, st);
     CHECK_LAUNCH();
     zero(c->info, (t.n_sub + 8) * 4);
-    launch_potrf(c->d_potrf, t.n_sub, c->W1, c->info, st);
+    launch_potrf(c->d_potrf, t.n_sub, t.max_nb, c->W1, c->info, st);
     CHECK_LAUNCH();
     check_info(c, t.n_sub, "interface Schur complement Cholesky");
     launch_copy_Sbb(t, c->S, c->W2, 1, st);

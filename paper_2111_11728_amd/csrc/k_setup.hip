@@ -528,6 +528,110 @@ __global__ void __launch_bounds__(256) k_potrf(const PotrfDesc* __restrict__ des
     if (threadIdx.x == 0) info[blockIdx.x] = r;
 }
 
+// Blocked batched Cholesky for large matrices, three launches per panel of kPfB columns
+// starting at p0 (every matrix of the batch advances in step; matrices already finished, or
+// with a failed pivot, skip):
+//   k_potrf_diag:  A11 = L11 L11^T in place, one workgroup per matrix;
+//   k_potrf_panel: L21 = A21 L11^{-T}, kPfRows rows per workgroup (one thread per row,
+//                  substitution against L11 in LDS);
+//   k_potrf_syrk:  A22 -= L21 L21^T on the lower 64x64 tiles of the trailing matrix, one
+//                  workgroup per tile (4x4 outputs per thread, operands in LDS).
+// info[b]: 0, or 1 + the column of the first non-positive pivot (as the one-workgroup form).
+constexpr int kPfB = 64, kPfRows = 128;
+__global__ void __launch_bounds__(256) k_potrf_diag(const PotrfDesc* __restrict__ desc, int p0, double* base,
+                                                    int* info) {
+    __shared__ double lds[kLdsDoubles];
+    const PotrfDesc d = desc[blockIdx.x];
+    if (p0 >= d.n || (p0 > 0 && info[blockIdx.x] != 0)) return;   // uniform
+    const int b = min(kPfB, d.n - p0);
+    const int r = wg_potrf(b, base + d.a + (long long)p0 * d.lda + p0, d.lda, lds);
+    if (threadIdx.x == 0 && (r || p0 == 0)) info[blockIdx.x] = r ? p0 + r : 0;
+}
+
+__global__ void __launch_bounds__(256) k_potrf_panel(const PotrfDesc* __restrict__ desc, int p0, double* base,
+                                                     const int* __restrict__ info) {
+    __shared__ double Ls[kPfB][kPfB + 1];
+    __shared__ double Xs[kPfRows][kPfB + 1];
+    const PotrfDesc d = desc[blockIdx.y];
+    if (p0 >= d.n) return;
+    const int b = min(kPfB, d.n - p0);
+    const int r0 = p0 + b + blockIdx.x * kPfRows;
+    if (r0 >= d.n || info[blockIdx.y] != 0) return;   // uniform
+    const int nr = min(kPfRows, d.n - r0);
+    double* A = base + d.a;
+    for (int e = threadIdx.x; e < kPfB * kPfB; e += 256) {
+        const int i = e / kPfB, j = e % kPfB;
+        Ls[i][j] = (i < b && j <= i) ? A[(long long)(p0 + i) * d.lda + p0 + j] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kPfRows * kPfB; e += 256) {
+        const int i = e / kPfB, j = e % kPfB;
+        Xs[i][j] = (i < nr && j < b) ? A[(long long)(r0 + i) * d.lda + p0 + j] : 0.0;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nr) {
+        const int i = threadIdx.x;
+        for (int j = 0; j < b; ++j) {
+            double v = Xs[i][j];
+            for (int k = 0; k < j; ++k) v -= Xs[i][k] * Ls[j][k];
+            Xs[i][j] = v / Ls[j][j];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kPfRows * kPfB; e += 256) {
+        const int i = e / kPfB, j = e % kPfB;
+        if (i < nr && j < b) A[(long long)(r0 + i) * d.lda + p0 + j] = Xs[i][j];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_potrf_syrk(const PotrfDesc* __restrict__ desc, int p0, double* base,
+                                                    const int* __restrict__ info) {
+    __shared__ double Ai[64][kPfB + 1];
+    __shared__ double Aj[64][kPfB + 1];
+    const PotrfDesc d = desc[blockIdx.y];
+    if (p0 >= d.n) return;
+    const int b = min(kPfB, d.n - p0), q0 = p0 + b;
+    const int nt = (d.n - q0 + 63) / 64;
+    const int t = blockIdx.x;
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    if (I >= nt || info[blockIdx.y] != 0) return;   // uniform
+    double* A = base + d.a;
+    const int ri = q0 + 64 * I, rj = q0 + 64 * J;
+    for (int e = threadIdx.x; e < 64 * kPfB; e += 256) {
+        const int i = e / kPfB, k = e % kPfB;
+        Ai[i][k] = (ri + i < d.n && k < b) ? A[(long long)(ri + i) * d.lda + p0 + k] : 0.0;
+        Aj[i][k] = (rj + i < d.n && k < b) ? A[(long long)(rj + i) * d.lda + p0 + k] : 0.0;
+    }
+    __syncthreads();
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < b; ++k) {
+        double x[4], y[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = Ai[4 * tr + r][k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) y[c] = Aj[4 * tc + c][k];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = fma(x[r], y[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ri + 4 * tr + r, j = rj + 4 * tc + c;
+            if (i < d.n && j <= i) A[(long long)i * d.lda + j] -= acc[r][c];
+        }
+}
+
 // Batched B <- L^{-1} B, one workgroup per (matrix, chunk of 64 columns of B).
 __global__ void __launch_bounds__(256) k_trsm(const TrsmDesc* __restrict__ desc, const double* Lbase,
                                               double* Bbase) {
@@ -1007,8 +1111,20 @@ void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* 
     k_gemm_tn<<<dim3(max_tiles, nbatch), 256, 0, st>>>(d, A, B, C, alpha, beta, symmetric);
 }
 
-void launch_potrf(const PotrfDesc* d, int nbatch, double* base, int* info, hipStream_t st) {
-    if (nbatch) k_potrf<<<nbatch, 256, 0, st>>>(d, base, info);
+void launch_potrf(const PotrfDesc* d, int nbatch, int max_n, double* base, int* info, hipStream_t st) {
+    if (nbatch == 0) return;
+    if (max_n <= 512) {   // one workgroup per matrix
+        k_potrf<<<nbatch, 256, 0, st>>>(d, base, info);
+        return;
+    }
+    for (int p0 = 0; p0 < max_n; p0 += kPfB) {
+        k_potrf_diag<<<nbatch, 256, 0, st>>>(d, p0, base, info);
+        const int rest = max_n - p0 - kPfB;
+        if (rest <= 0) break;
+        k_potrf_panel<<<dim3((rest + kPfRows - 1) / kPfRows, nbatch), 256, 0, st>>>(d, p0, base, info);
+        const int nt = (rest + 63) / 64;
+        k_potrf_syrk<<<dim3(nt * (nt + 1) / 2, nbatch), 256, 0, st>>>(d, p0, base, info);
+    }
 }
 
 void launch_trsm(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st) {
