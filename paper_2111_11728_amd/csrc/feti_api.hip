@@ -842,7 +842,7 @@ void dense_spd_inverse(feti_ctx* c, int n, const double* A, double* work, double
     CHECK_LAUNCH();
     check_info(c, 1, what);
     launch_set_identity(Ainv, n, n, c->st);
-    launch_trsm(c->d_trsm_one, 1, n, work, Ainv, c->st);
+    launch_trsm_identity(c->d_trsm_one, 1, n, work, Ainv, c->st);
     // Ainv currently holds X = L^{-1}; form X^T X into work, then copy
     launch_gemm_tn(c->d_one, 1, ((n + 63) / 64) * ((n + 63) / 64), Ainv, Ainv, work, 1.0, 0.0, 1, c->st);
     CHECK_LAUNCH();
@@ -865,7 +865,7 @@ void coarse_inverse(feti_ctx* c) {
     CHECK_LAUNCH();
     check_info(c, nb, "coarse Cholesky");
     for (const CoarseBlk& b : B) launch_set_identity(c->Kcc_inv + b.off, b.n, b.n, st);
-    launch_trsm(c->d_cc_trsm, nb, maxn, c->Kcc_w, c->Kcc_inv, st);
+    launch_trsm_identity(c->d_cc_trsm, nb, maxn, c->Kcc_w, c->Kcc_inv, st);
     launch_gemm_tn(c->d_cc_gemm, nb, ((maxn + 63) / 64) * ((maxn + 63) / 64), c->Kcc_inv, c->Kcc_inv, c->Kcc_w, 1.0,
                    0.0, 1, st);
     CHECK_LAUNCH();
@@ -921,7 +921,7 @@ void numeric_setup(feti_ctx* c) {
     CHECK_LAUNCH();
     check_info(c, t.n_sub, "interface Schur complement Cholesky");
     launch_copy_Sbb(t, c->S, c->W2, 1, st);
-    launch_trsm(c->d_trsm, t.n_sub, c->max_nb_cols, c->W1, c->W2, st);
+    launch_trsm_identity(c->d_trsm, t.n_sub, c->max_nb_cols, c->W1, c->W2, st);
     launch_gemm_tn(c->d_F, t.n_sub, c->F_tiles, c->W2, c->W2, c->F64, 1.0, 0.0, 1, st);
     CHECK_LAUNCH();
     if (P.method == FETI_TFETI)

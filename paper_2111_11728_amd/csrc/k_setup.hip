@@ -632,15 +632,19 @@ __global__ void __launch_bounds__(256) k_potrf_syrk(const PotrfDesc* __restrict_
         }
 }
 
-// Batched B <- L^{-1} B, one workgroup per (matrix, chunk of 64 columns of B).
+// Batched B <- L^{-1} B for B holding the identity on entry (the explicit inverse of a
+// Cholesky factor), one workgroup per (matrix, chunk of 64 columns of B). Rows above the chunk's
+// first column are zero in B and stay zero in L^{-1} B (L lower triangular), so the chunk's
+// substitution starts at that row, on the trailing block of L.
 __global__ void __launch_bounds__(256) k_trsm(const TrsmDesc* __restrict__ desc, const double* Lbase,
                                               double* Bbase) {
     __shared__ double lds[kLdsDoubles];
     const TrsmDesc d = desc[blockIdx.y];
     const int c0 = blockIdx.x * 64;
-    if (c0 >= d.ncols) return;
+    if (c0 >= d.ncols || c0 >= d.n) return;
     const int nc = min(64, d.ncols - c0);
-    wg_trsm_lower(d.n, nc, Lbase + d.l, d.ldl, Bbase + d.b + c0, d.ldb, 1, lds);
+    wg_trsm_lower(d.n - c0, nc, Lbase + d.l + (long long)c0 * d.ldl + c0, d.ldl, Bbase + d.b + (long long)c0 * d.ldb + c0,
+                  d.ldb, 1, lds);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1127,7 +1131,7 @@ void launch_potrf(const PotrfDesc* d, int nbatch, int max_n, double* base, int* 
     }
 }
 
-void launch_trsm(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st) {
+void launch_trsm_identity(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st) {
     if (nbatch && max_cols) k_trsm<<<dim3((max_cols + 63) / 64, nbatch), 256, 0, st>>>(d, L, B);
 }
 

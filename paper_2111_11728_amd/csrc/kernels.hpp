@@ -146,7 +146,8 @@ void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* 
                     double alpha, double beta, int symmetric, hipStream_t st);
 // max_n: the largest n of the batch (above 512 the blocked multi-workgroup form runs)
 void launch_potrf(const PotrfDesc* d, int nbatch, int max_n, double* base, int* info, hipStream_t st);
-void launch_trsm(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st);
+// B <- L^{-1} B with B the identity on entry (B = L^{-1} on exit)
+void launch_trsm_identity(const TrsmDesc* d, int nbatch, int max_cols, const double* L, double* B, hipStream_t st);
 void launch_copy_Sbb(const DevTopo& t, const double* S, double* dst, int identity, hipStream_t st);
 void launch_tfeti_rbm(const DevTopo& t, const double* S, double* Rb, double* Cit, double* tau, double* W,
                       hipStream_t st);
