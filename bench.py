@@ -229,7 +229,12 @@ def run_c5(args):
             cx.feti_apply_F(k, prec, L, Q, pure=True)
             ts.append(cx.feti_last_timing(0))
         fl[prec] = float(np.mean(ts)) * 1e3
-        log(f"c5 F*Lambda {prec}, k = {k}: kernel {fl[prec]:.1f} us")
+        log(f"c5 F*Lambda {prec}, k = {k}: kernel {fl[prec]:.1f} us (default tile shapes)")
+    # tile shapes of the in-solve F*Lambda chosen on the device for the solve (no cache: tuned
+    # every run); they apply to every tile list, so the pure-precision timings above come first
+    tune = cx.feti_autotune(reps=3)
+    log(f"c5 autotune: max_red {tune['max_red']}, max_d {tune['max_d']}, xcd {tune['xcd']}, split_d {tune['split_d']}: "
+        f"{tune['us']:.1f} us (default shapes {tune['us_default']:.1f} us)")
     c = torch.zeros(1, dtype=torch.float64, device=dev)
     g = torch.zeros(prob.n_el, dtype=torch.float64, device=dev)
     u = torch.zeros(prob.n_dof, dtype=torch.float64, device=dev)
@@ -254,7 +259,7 @@ def run_c5(args):
                        "directions": cx.sizes["n_groups"]},
             "setup_ms": float(np.mean([r[0] for r in rec])), "iters": rec[-1][2]["iters"],
             "reduced_iters": rec[-1][2]["reduced_iters"], "true_rel_res": rec[-1][2]["true_rel_res"],
-            "flambda_k64_us": fl, "compliance": float(c.item())}
+            "flambda_k64_us": fl, "tuning": tune, "compliance": float(c.item())}
     cx.close()
     print(json.dumps(line))
 

@@ -207,7 +207,7 @@ typedef struct {
 
 /* Autotuner of the F*Lambda tile shapes: times the context's in-solve F*Lambda (k = 64 columns,
  * the context's precision, hybrid lists included) over reps launches for every candidate in
- * max_red {32, 16} x max_d {16, 8, 4} x xcd {1, 0} x split_d {4, 2}, keeps the fastest (a
+ * max_red {32, 16} x max_d {16, 14, 12, 10, 8, 4} x xcd {1, 0} x split_d {4, 2}, keeps the fastest (a
  * change from the defaults must gain 2%) and applies it to every tile list of the context. cache_path (host string, optional): a JSON
  * file of earlier results keyed by (subdomains, n_b bucket of 32, precision, hybrid); a hit is
  * applied without timing, a miss is timed and written back. out: host, optional. Results of

@@ -1917,7 +1917,7 @@ feti_status feti_autotune(feti_ctx* c, int reps, const char* cache_path, feti_tu
         const double t_def = time_flambda(c, rp);
         best.us = 1e3 * t_def;
         for (int mr : {32, 16})
-            for (int md : {16, 8, 4})
+            for (int md : {16, 14, 12, 10, 8, 4})
                 for (int xc : {1, 0})
                     for (int sd : {4, 2}) {
                         c->tune = feti_tuning{mr, md, xc, sd, 0.0, 0.0, 0};
