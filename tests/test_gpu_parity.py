@@ -165,16 +165,19 @@ def test_apply_F_fp64(oracle_cache, name, method, k):
     ctx.close()
 
 
+@pytest.mark.parametrize("k", [64, 16])
 @pytest.mark.parametrize("precision,u", [("fp32", 2.0 ** -24), ("bf16x3", 2.0 ** -16)])
 @pytest.mark.parametrize("name", ["c1", "uneven", "3d"])
-def test_apply_F_mixed(oracle_cache, name, precision, u):
+def test_apply_F_mixed(oracle_cache, name, precision, u, k):
+    """Every row block in the reduced precision (an FP64 context has no hybrid lists), for the
+    64-column and the 16-column forms of the kernel."""
     prob, op = _oracle(oracle_cache, name, "fetidp", "dirichlet", "mult")
-    print(f"case {name} {precision}", flush=True)
+    print(f"case {name} {precision} k={k}", flush=True)
     ctx = _ctx(prob, method="fetidp", scaling="mult")
     n = op.n_lambda
-    L = np.random.default_rng(3).standard_normal((n, 64))
-    Q = torch.zeros((n, 64), dtype=torch.float64, device=DEV)
-    ctx.feti_apply_F(64, precision, _t(L), Q)
+    L = np.random.default_rng(3).standard_normal((n, k))
+    Q = torch.zeros((n, k), dtype=torch.float64, device=DEV)
+    ctx.feti_apply_F(k, precision, _t(L), Q)
     nb = max(b.size for b in op.cons.bset)
     bound = 4.0 * np.sqrt(nb) * u * _abs_apply(op, L) + _tol_fp64(op) * np.abs(op.apply_F(L)).max()
     err = np.abs(Q.cpu().numpy() - op.apply_F(L))
