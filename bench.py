@@ -324,11 +324,6 @@ def main():
     ctx = make("fp32")
     sizes = ctx.sizes
     n_l = sizes["n_lambda"]
-    # tile shapes of the in-solve F*Lambda chosen on the device (no cache: tuned every run)
-    tune = ctx.feti_autotune(reps=5)
-    log(f"autotune: max_red {tune['max_red']}, max_d {tune['max_d']}, xcd {tune['xcd']}, split_d {tune['split_d']}: "
-        f"{tune['us']:.1f} us (default shapes {tune['us_default']:.1f} us)")
-
     # ---- F*Lambda microbenchmark (k = 64 directions) ----
     k = 64
     gen = torch.Generator(device=dev).manual_seed(0)
@@ -336,10 +331,18 @@ def main():
     Q = torch.zeros_like(L)
     flops = flambda_work(sizes, k)
     fl = {}
-    # pure: every row block in the named precision (the kernel rate); "fp32_solve": the form the
-    # mixed solve applies (FP32 where the round-off test allows, FP64 F_rc^T rows and the rest)
+    # pure: every row block in the named precision (the kernel rate, on the default tile shapes);
+    # "fp32_solve": the form the mixed solve applies (FP32 where the round-off test allows, FP64
+    # F_rc^T rows and the rest), on the shapes the autotuner then picks for it
+    tune = None
     for name, prec, pure in [("fp64", "fp64", True), ("fp32", "fp32", True), ("bf16x3", "bf16x3", True),
                              ("fp32_solve", "fp32", False)]:
+        if not pure and tune is None:
+            # tile shapes of the in-solve F*Lambda chosen on the device (no cache: tuned every run);
+            # they apply to every tile list, so the pure-precision timings come first
+            tune = ctx.feti_autotune(reps=5)
+            log(f"autotune: max_red {tune['max_red']}, max_d {tune['max_d']}, xcd {tune['xcd']}, "
+                f"split_d {tune['split_d']}: {tune['us']:.1f} us (default shapes {tune['us_default']:.1f} us)")
         for _ in range(3):
             ctx.feti_apply_F(k, prec, L, Q, pure=pure)
         kern, tot = [], []
