@@ -373,22 +373,24 @@ def test_pcg_256_subdomains():
 
 @pytest.mark.parametrize("case,method,krylov,precision,tol,bound",
                          [("tiled", "fetidp", "pcg", "fp64", 1e-11, 1e-7), ("generic", "fetidp", "pcg", "fp64", 1e-11, 1e-7),
-                          ("tiled", "fetidp", "sfeti", "fp32", 1e-9, 1e-6), ("tiled", "tfeti", "pcg", "fp64", 1e-11, 1e-7)])
-def test_3d_long_line_sweeps(case, method, krylov, precision, tol, bound):
-    """Interior solves of 3D subdomains with long plane blocks: 2x2x2 subdomains of 8^3 elements
+                          ("tiled", "fetidp", "sfeti", "fp32", 1e-9, 1e-6), ("tiled", "tfeti", "pcg", "fp64", 1e-11, 1e-7),
+                          ("2d", "fetidp", "pcg", "fp64", 1e-11, 1e-7)])
+def test_long_line_sweeps(case, method, krylov, precision, tol, bound):
+    """Interior solves of subdomains with long line blocks: 2x2 subdomains of 80^2 elements (2D
+    grid lines of about 160 interior DOFs: the tiled sweeps); 2x2x2 subdomains of 8^3 elements
     (up to 192 interior DOFs per plane: the tiled 1024-thread sweeps over explicit inverses of
     the diagonal blocks) and of 16x16x2 elements (more than 512 per plane: one wavefront per
     subdomain, substitutions with L_kk). Planes without interior DOFs (on the interface) occur in
     both. FETI-DP PCG in FP64, S-FETI (one direction per subdomain) with F*Lambda in FP32 where
     the rounding test allows, and TFETI PCG (floating subdomains), against the global direct
     solve."""
-    nel = (16, 16, 16) if case == "tiled" else (32, 32, 4)
+    nel = {"tiled": (16, 16, 16), "generic": (32, 32, 4), "2d": (160, 160)}[case]
     rng = np.random.default_rng(11)
     rho = np.where(rng.random(int(np.prod(nel))) < 0.5, 1.0, 0.0)
-    prob = workloads.Problem(3, nel, tuple(workloads.uniform_cuts(n, 2) for n in nel), rho, Emin=1e-2,
+    prob = workloads.Problem(len(nel), nel, tuple(workloads.uniform_cuts(n, 2) for n in nel), rho, Emin=1e-2,
                              name=f"slab3d_{case}")
     u_ref = fem.solve_problem(prob)
-    print(f"case 3d long lines {case} {method} {krylov} {precision}", flush=True)
+    print(f"case long lines {case} {method} {krylov} {precision}", flush=True)
     ctx = _ctx(prob, method=method, scaling="k", krylov=krylov, precision=precision, tol=tol)
     u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
     info = ctx.feti_solve(_t(prob.load()), u)
