@@ -291,8 +291,8 @@ def main():
         ingest_pmc(*args.ingest_pmc)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build measures one GPU's share at "
-              f"its real shape; sharding the subdomains over several GPUs is not implemented", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): it measures one GPU's share of the "
+              f"subdomains at its real shape; sharding them over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.c4:
