@@ -278,3 +278,28 @@ def test_3d_fetidp_small():
     res = krylov.solve(op, "sfeti", tol=1e-12)
     u, _ = op.recover(res.lam)
     assert res.converged and _rel(u, fem.solve_problem(prob)) < 1e-8
+
+
+def test_fetidp_local_against_dense_inverse():
+    """One subdomain's F_s, F_rc^s and Kbar_cc^s (Sec. 2.2, Eq. 11-12) against their definitions
+    written with a dense inverse of K_rr (no LU, no right-hand-side blocking): F_s = (K_rr^{-1})_bb,
+    F_rc^s = (K_rr^{-1} K_rc)_b, Kbar_cc^s = K_cc - K_rc^T K_rr^{-1} K_rc; plus symmetry and
+    positive definiteness of F_s."""
+    prob = workloads.cantilever_tfeti(3, nsub=(3, 2), m=4)
+    dec = topology.decompose(prob)
+    split, cons = topology.fetidp_split(dec)
+    E = fem.simp_modulus(prob.rho, prob.p, prob.E0, prob.Emin)
+    K0 = fem.element_stiffness(prob.dim, prob.nu)
+    for s in range(len(dec.subs)):
+        Ks = feti.subdomain_stiffness(prob, dec.subs[s], E, K0).toarray()
+        r, c, bpos = split.r[s], split.c[s], cons.bset[s]
+        Fs, Frc, Kcc_bar, _, _ = feti.fetidp_local(sp.csr_matrix(Ks), r, c, bpos)
+        Kinv = np.linalg.inv(Ks[np.ix_(r, r)])
+        Krc = Ks[np.ix_(r, c)]
+        assert np.allclose(Fs, Kinv[np.ix_(bpos, bpos)], rtol=1e-10, atol=1e-12 * np.abs(Kinv).max())
+        if c.size:
+            assert np.allclose(Frc, (Kinv @ Krc)[bpos], rtol=1e-10, atol=1e-12 * np.abs(Kinv @ Krc).max())
+            ref = Ks[np.ix_(c, c)] - Krc.T @ Kinv @ Krc
+            assert np.allclose(Kcc_bar, ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
+        assert np.allclose(Fs, Fs.T, atol=1e-12 * np.abs(Fs).max())
+        assert np.linalg.eigvalsh(0.5 * (Fs + Fs.T)).min() > 0.0
