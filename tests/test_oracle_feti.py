@@ -303,3 +303,41 @@ def test_fetidp_local_against_dense_inverse():
             assert np.allclose(Kcc_bar, ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
         assert np.allclose(Fs, Fs.T, atol=1e-12 * np.abs(Fs).max())
         assert np.linalg.eigvalsh(0.5 * (Fs + Fs.T)).min() > 0.0
+
+
+@pytest.mark.parametrize("method", ["tfeti", "fetidp"])
+def test_dirichlet_schur_is_harmonic_extension_energy(method):
+    """The Dirichlet block S^s of the preconditioner (Sec. 3.1, Eq. 13) against the energy
+    characterisation of a Schur complement, written without its block formula: for a trace x_b on
+    the interface, the least strain energy x^T K_A x over all interior completions x_i is x_b^T S x_b
+    (K_A = K^s on the active DOFs: all local DOFs in TFETI, the remainder set r in FETI-DP, Sec. 2.2).
+    The minimiser (the harmonic extension) solves K_ii x_i = -K_ib x_b; it is computed here with a
+    dense solve, the energy with the full active matrix, and S_ref = X^T K_A X with the unit traces
+    as columns. Any other completion has more energy. TFETI: rigid-body traces carry no energy,
+    S R_b = 0 on every (floating) subdomain. Heterogeneous densities (U(0, 1), contrast 1e-6)."""
+    prob = workloads.cantilever_tfeti(7, nsub=(3, 2), m=4)
+    op = feti.TFETI(prob, "dirichlet", "mult") if method == "tfeti" else feti.FETIDP(prob, "dirichlet", "mult")
+    rng = np.random.default_rng(3)
+    for s, sd in enumerate(op.dec.subs):
+        K = op.K[s].toarray()
+        active = np.arange(sd.n_loc) if method == "tfeti" else op.split.r[s]
+        b = np.asarray(op.b_local[s])
+        i = np.setdiff1d(active, b)
+        X = np.zeros((sd.n_loc, b.size))
+        X[b, np.arange(b.size)] = 1.0
+        X[i] = np.linalg.solve(K[np.ix_(i, i)], -K[np.ix_(i, b)])
+        S_ref = X.T @ K @ X
+        S = op.S[s]
+        assert np.abs(S - S_ref).max() <= 1e-10 * np.abs(S_ref).max(), s
+        # minimality: a perturbed interior raises the energy of a random trace
+        xb = rng.standard_normal(b.size)
+        x = X @ xb
+        e0 = x @ K @ x
+        assert abs(xb @ S @ xb - e0) <= 1e-10 * e0
+        for _ in range(3):
+            y = x.copy()
+            y[i] += 1e-3 * rng.standard_normal(i.size) * np.abs(x).max()
+            assert y @ K @ y > e0
+        if method == "tfeti":
+            Rb = op.R[s][b]
+            assert np.abs(S @ Rb).max() <= 1e-10 * np.abs(S).max() * np.abs(Rb).max(), s
