@@ -143,6 +143,8 @@ typedef struct {
     int n_fp64_subs;          /* FETI-DP with a reduced precision: subdomains whose F_s failed the
                                  round-off test at the last setup and run in FP64 */
     int n_designs;            /* independent designs held by the context (1 unless batched) */
+    long long sum_nb2_fp64;   /* sum of n_b^2 over the subdomains counted by n_fp64_subs (their F_s
+                                 products run on the FP64 matrix cores inside a reduced-precision solve) */
 } feti_sizes;
 
 /* One design of a batched context: its ranges in the concatenated arrays. */
@@ -221,7 +223,12 @@ feti_status feti_design_layout(feti_ctx* ctx, int d, feti_design* out);
  * last solve (r_d = the design's rows of d - F lambda, FP64). */
 feti_status feti_design_residuals(feti_ctx* ctx, double* out, int cap);
 
-/* Same topology, new densities: repeats assembly, factorisation and operator formation. */
+/* New densities rho on the same mesh and partition (the SIMP law of Sec. 1, Eq. 1, re-evaluated
+ * per element): repeats the setup of feti_setup from the assembly of every K^s (Sec. 2, Eq. 2-3)
+ * through the factorisations, the local dual operators (Sec. 2.1 Eq. 7 / Sec. 2.2 Eq. 12), the
+ * preconditioner blocks and scaling weights (Sec. 3.1, Eq. 13-15) and the coarse problem.
+ * rho: device [n_el] in [0, 1]. Errors: FETI_EINVAL (null rho), FETI_ENOTSPD (a non-positive
+ * pivot; the context must then be set up again before use). */
 feti_status feti_update_rho(feti_ctx* ctx, const double* rho);
 
 /* Solves K u = f (Eq. 2) by the configured FETI variant.
@@ -233,8 +240,12 @@ feti_status feti_update_rho(feti_ctx* ctx, const double* rho);
 feti_status feti_solve(feti_ctx* ctx, const double* f, double* u, const double* lambda_init,
                        feti_info* info);
 
-/* Compliance c = f^T u and its gradient dc/drho_e = -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e
- * (self-adjoint), after feti_update_rho(rho) and feti_solve(f). A batched context writes one
+/* Compliance c = f^T u of the SIMP system (Sec. 1, Eq. 1-2: E_e = Emin + rho_e^p (E0 - Emin),
+ * K(rho) u = f solved by the context's FETI variant, Sec. 2) and its gradient
+ * dc/drho_e = -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e (compliance is self-adjoint, so no second
+ * solve), after feti_update_rho(rho) and feti_solve(f). Returns FETI_ENOCONV with c and dc
+ * still written when the solve stopped at the iteration cap; callers that need a converged
+ * gradient must check the status. A batched context writes one
  * compliance per design (c: device [n_designs]).
  * rho: device [n_el] or NULL (keep the current densities); f: device [n_dof] or NULL
  * (reuse the last load); c: device scalar; dc_drho: device [n_el]; u: device [n_dof] or NULL. */

@@ -2,8 +2,9 @@
 function. The forward pass calls ``feti_compliance_and_grad``: it sets the context up for rho,
 solves with the FETI method of the context, and writes c together with the adjoint gradient
 dc/drho_e = -p rho_e^(p-1) (E0 - Emin) u_e^T K0 u_e (compliance is self-adjoint). The backward
-pass scales that gradient; it does no extra solve. Argument marshalling only: all arithmetic
-runs in the HIP library.
+pass scales that gradient; it does no extra solve. A solve that misses its tolerance raises
+``FetiError`` in the forward pass, so no compliance or gradient of an unconverged solve reaches
+autograd. Argument marshalling only: all arithmetic runs in the HIP library.
 """
 from __future__ import annotations
 

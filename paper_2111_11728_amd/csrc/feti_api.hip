@@ -2021,6 +2021,10 @@ feti_status feti_get_sizes(feti_ctx* c, feti_sizes* out) {
     z.device_bytes = c->bytes;
     z.n_fp64_subs = c->n_fp64_subs;
     z.n_designs = (int)c->designs.size();
+    z.sum_nb2_fp64 = 0;
+    if (c->hybrid)
+        for (int s = 0; s < P.n_sub; ++s)
+            if (!c->sub_ok[s]) z.sum_nb2_fp64 += (long long)P.n_b[s] * P.n_b[s];
     *out = z;
     return FETI_OK;
 }

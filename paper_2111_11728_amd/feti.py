@@ -78,7 +78,7 @@ class feti_sizes(C.Structure):
                 ("n_alpha", C.c_int), ("n_groups", C.c_int), ("nb_max", C.c_int), ("nb_min", C.c_int),
                 ("n_loc_max", C.c_int), ("n_i_max", C.c_int), ("band_max", C.c_int), ("sum_nb2", C.c_longlong),
                 ("sum_nb_nc", C.c_longlong), ("device_bytes", C.c_longlong), ("n_fp64_subs", C.c_int),
-                ("n_designs", C.c_int)]
+                ("n_designs", C.c_int), ("sum_nb2_fp64", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -247,14 +247,22 @@ class Context:
                 "precision_probes": info.precision_probes, "reduced_rel_err": info.reduced_rel_err,
                 "reduced_orth_err": info.reduced_orth_err}
 
-    def feti_compliance_and_grad(self, rho, f, c, dc, u=None):
+    def feti_compliance_and_grad(self, rho, f, c, dc, u=None, allow_noconv=False, hist_cap=4096):
+        """Raises FetiError unless the solve reached its tolerance; with allow_noconv, a solve that
+        stopped at the iteration cap (FETI_ENOCONV) returns its status and still writes c and dc."""
         info = feti_info()
+        hist = np.zeros(hist_cap)
+        info.res_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
+        info.res_hist_cap = hist_cap
+        allow = (FETI_ENOCONV,) if allow_noconv else ()
         st = _check(lib().feti_compliance_and_grad(self.handle, _ptr(rho), _ptr(f), _ptr(c), _ptr(dc), _ptr(u),
-                                                   C.byref(info)), allow=(FETI_ENOCONV,))
+                                                   C.byref(info)), allow=allow)
+        n = min(hist_cap, info.iters + 1)
         return {"status": st, "iters": info.iters, "true_rel_res": info.true_rel_res,
                 "refinements": info.refinements, "fp64_fallback": info.fp64_fallback,
                 "reduced_iters": info.reduced_iters, "precision_probes": info.precision_probes,
-                "reduced_rel_err": info.reduced_rel_err, "reduced_orth_err": info.reduced_orth_err}
+                "reduced_rel_err": info.reduced_rel_err, "reduced_orth_err": info.reduced_orth_err,
+                "history": hist[:n].copy(), "eps0": info.eps0}
 
     def feti_apply_F(self, k, precision, Lam, Q, pure=False):
         p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)

@@ -1,0 +1,192 @@
+"""Writes the oracle's full-size Krylov records that the GPU tests compare against.
+
+Calls only the oracle (``oracle.feti``, ``oracle.krylov``, ``oracle.fem``) on the seeded inputs of
+``workloads``. One file per workload, each with the oracle's wall-clock record (setup and solve
+seconds, threads, CPU model):
+
+* ``c3_sfeti.npz`` - 2D, 16x16 subdomains of 64x64 Q4 elements, rho ~ Beta(0.3, 0.3) (seed 0),
+  Emin/E0 = 1e-9. FETI-DP, k-scaling, Dirichlet preconditioner, simultaneous directions
+  (Sec. 3.3, Algorithm 1) with 64 (2x2 subdomain groups) and 32 (4x2 groups) directions, relative
+  tolerance 1e-6: iteration count, eps per iterate, rank per iteration, the recovered u at the
+  4096 DOFs of ``c3_u_sample.npz``, the compliance and the gradient at 20 seeded elements.
+  About 25 minutes and 12 GB on 8 cores.
+* ``c5_sfeti.npz`` - 3D, 4x4x4 subdomains of 12^3 Hex8 elements, modular 0/1 (seed 0), Emin 1e-6.
+  The global direct solution (sampled at 4096 seeded DOFs, with its norm, compliance and the
+  gradient at 20 seeded elements) and the same S-FETI-DP run with 64 directions at 1e-6.
+* ``c2_variants.npz`` - 2D, 8x4 subdomains of 32x32, modular 0/1 (seed 0), Emin 1e-6. FETI-DP with
+  the Dirichlet preconditioner, {multiplicity, k-scaling} x {PCG, full orthogonalisation}, at
+  1e-6 with the iteration cap n_lambda: converged flag, iteration count and eps per iterate; and
+  the same four runs on the oracle's operator evaluated through its explicit dense F (the same
+  operator in another rounding order), whose iteration counts measure how far round-off alone
+  moves the oracle's own count.
+
+* ``c3_cpu_sample.json`` - wall-clock of the bounded CPU sample that ``bench.py`` times on the
+  host of the GPU (the oracle's setup and 12 S-FETI-DP iterations on the 4x4-subdomain block of the
+  c3 design, ``workloads.beta_2d_block``), taken on the machine and thread count of the c3 record,
+  so that the sample's ratio between the two hosts carries the full-size record over.
+
+Usage: python tests/golden/make_krylov_goldens.py c3|c5|c2|c3cal
+"""
+import os
+import pathlib
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = pathlib.Path(__file__).resolve().parents[2]
+sys.path.insert(0, str(ROOT))
+
+import workloads  # noqa: E402
+from oracle import fem, feti, krylov  # noqa: E402
+
+HERE = pathlib.Path(__file__).resolve().parent
+
+
+def _cpu():
+    model = platform.processor()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return model, int(threads), os.cpu_count()
+
+
+def _el_sample(prob, n=20, seed=2111):
+    return np.sort(np.random.default_rng(seed).choice(prob.n_el, n, replace=False))
+
+
+def _dof_sample(prob, n=4096, seed=2111):
+    return np.sort(np.random.default_rng(seed).choice(prob.n_dof, n, replace=False))
+
+
+def _run(op, prob, krylov_kind, tol, idx, eidx):
+    t0 = time.perf_counter()
+    res = krylov.solve(op, krylov_kind, tol=tol)
+    t_solve = time.perf_counter() - t0
+    u, _ = op.recover(res.lam)
+    g = fem.compliance_gradient(prob, u)
+    print(f"  {krylov_kind}: {res.iters} iterations, converged {res.converged}, solve {t_solve:.1f} s", flush=True)
+    return dict(iters=res.iters, converged=res.converged, history=np.asarray(res.history),
+                ranks=np.asarray(res.ranks, dtype=np.int64), u=u[idx], u_norm=np.linalg.norm(u),
+                c=fem.compliance(prob.load(), u), g=g[eidx], t_solve=t_solve)
+
+
+def c3():
+    prob = workloads.beta_2d(0)
+    idx, eidx = _dof_sample(prob), _el_sample(prob)
+    t0 = time.perf_counter()
+    op = feti.FETIDP(prob, "dirichlet", "k")
+    t_setup = time.perf_counter() - t0
+    print(f"c3 setup {t_setup:.1f} s, n_lambda {op.n_lambda}", flush=True)
+    out = dict(idx=idx, el_idx=eidx, t_setup=t_setup, n_lambda=op.n_lambda)
+    for k, groups in [(64, (2, 2)), (32, (4, 2))]:
+        op.group = workloads.group_of_subdomains(prob.nsub, groups)
+        op.n_groups = int(op.group.max()) + 1
+        assert op.n_groups == k
+        r = _run(op, prob, "sfeti", 1e-6, idx, eidx)
+        out.update({f"k{k}_{key}": v for key, v in r.items()})
+    model, threads, ncpu = _cpu()
+    np.savez(HERE / "c3_sfeti.npz", cpu_model=model, threads=threads, cpu_count=ncpu, **out)
+
+
+def cpu_sample(it_cap=12):
+    """The bounded oracle sample shared with bench.py: setup and it_cap S-FETI-DP iterations on the
+    4x4-subdomain block of the c3 design. Returns (setup s, solve s, iterations)."""
+    sub = workloads.beta_2d_block(0)
+    t0 = time.perf_counter()
+    op = feti.FETIDP(sub, "dirichlet", "k")
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = krylov.simultaneous(op, tol=1e-6, max_it=it_cap)
+    return t_setup, time.perf_counter() - t0, res.iters
+
+
+def c3cal():
+    import json
+    runs = [cpu_sample() for _ in range(3)]
+    model, threads, ncpu = _cpu()
+    rec = {"setup_s": min(r[0] for r in runs), "solve_s": min(r[1] for r in runs), "iters": runs[0][2],
+           "cpu_model": model, "threads": threads, "cpu_count": ncpu,
+           "what": "oracle FETI-DP setup and 12 S-FETI-DP iterations (k-scaling, Dirichlet, 2x2 groups) on "
+                   "workloads.beta_2d_block(0), best of 3"}
+    (HERE / "c3_cpu_sample.json").write_text(json.dumps(rec, indent=1) + "\n")
+    print(rec)
+
+
+def c5():
+    prob = workloads.modular_3d(0)
+    idx, eidx = _dof_sample(prob), _el_sample(prob)
+    t0 = time.perf_counter()
+    u_star = fem.solve_problem(prob)
+    t_direct = time.perf_counter() - t0
+    g_star = fem.compliance_gradient(prob, u_star)
+    print(f"c5 direct solve {t_direct:.1f} s", flush=True)
+    t0 = time.perf_counter()
+    op = feti.FETIDP(prob, "dirichlet", "k")
+    t_setup = time.perf_counter() - t0
+    print(f"c5 setup {t_setup:.1f} s, n_lambda {op.n_lambda}", flush=True)
+    r = _run(op, prob, "sfeti", 1e-6, idx, eidx)
+    model, threads, ncpu = _cpu()
+    np.savez(HERE / "c5_sfeti.npz", idx=idx, el_idx=eidx, u_star=u_star[idx], u_star_norm=np.linalg.norm(u_star),
+             c_star=fem.compliance(prob.load(), u_star), g_star=g_star[eidx], t_direct=t_direct,
+             t_setup=t_setup, n_lambda=op.n_lambda, cpu_model=model, threads=threads, cpu_count=ncpu,
+             **{f"k64_{key}": v for key, v in r.items()})
+
+
+class DenseF:
+    """An oracle operator evaluated through its explicit dense F (symmetrised)."""
+
+    def __init__(self, op):
+        self.op = op
+        F = op.apply_F(np.eye(op.n_lambda))
+        self.F = 0.5 * (F + F.T)
+        self.n_lambda = op.n_lambda
+        self.d = op.d
+
+    def apply_F(self, L):
+        return self.F @ L
+
+    def project(self, Y):
+        return self.op.project(Y)
+
+    def lambda0(self):
+        return self.op.lambda0()
+
+    def precondition(self, r, one_column=False):
+        return self.op.precondition(r, one_column)
+
+
+def c2():
+    prob = workloads.modular_2d(0)
+    out = {}
+    for scaling in ["mult", "k"]:
+        op = feti.FETIDP(prob, "dirichlet", scaling)
+        dop = DenseF(op)
+        out["n_lambda"] = op.n_lambda
+        for kr in ["pcg", "fo"]:
+            t0 = time.perf_counter()
+            res = krylov.solve(op, kr, tol=1e-6)
+            dt = time.perf_counter() - t0
+            rd = krylov.solve(dop, kr, tol=1e-6)
+            print(f"c2 {scaling} {kr}: {res.iters} iterations (dense F: {rd.iters}), converged {res.converged} "
+                  f"({rd.converged}), {dt:.1f} s", flush=True)
+            key = f"{scaling}_{kr}"
+            out[f"{key}_iters"] = res.iters
+            out[f"{key}_converged"] = res.converged
+            out[f"{key}_history"] = np.asarray(res.history)
+            out[f"{key}_t_solve"] = dt
+            out[f"{key}_iters_dense"] = rd.iters
+            out[f"{key}_converged_dense"] = rd.converged
+            out[f"{key}_history_dense"] = np.asarray(rd.history)
+    model, threads, ncpu = _cpu()
+    np.savez(HERE / "c2_variants.npz", cpu_model=model, threads=threads, cpu_count=ncpu, **out)
+
+
+if __name__ == "__main__":
+    {"c3": c3, "c5": c5, "c2": c2, "c3cal": c3cal}[sys.argv[1]]()

@@ -161,7 +161,49 @@ def test_apply_F_fp64(oracle_cache, name, method, k):
         ref = op.project(op.apply_F(op.project(L)))
     else:
         ref = op.apply_F(L)
-    assert _rel(Q.cpu().numpy(), ref) < _tol_fp64(op)
+    err = _rel(Q.cpu().numpy(), ref)
+    print(f"  error {err:.2e} (bound {_tol_fp64(op):.2e})", flush=True)
+    assert err < _tol_fp64(op)
+    ctx.close()
+
+
+WELL = {
+    "2d": lambda: workloads.cantilever_tfeti(0, nsub=(4, 2), m=4),
+    "3d": lambda: workloads.modular_3d(1, nsub=(2, 2, 2), m=3),
+}
+
+
+@pytest.mark.parametrize("name", ["2d", "3d"])
+@pytest.mark.parametrize("method", ["fetidp", "tfeti"])
+@pytest.mark.parametrize("k", [1, 7, 64])
+def test_apply_F_fp64_well_conditioned(name, method, k):
+    """F*Lambda in FP64 held to 1e-12 of the oracle: homogeneous material (rho = 1) on small
+    subdomains, where the matrices the setup factorises have condition numbers of about 1e2 to
+    1e3, so a defect in the gathers, the local products, the coarse correction or the scatter
+    far below the heterogeneous tests' conditioning bounds still fails here."""
+    prob = WELL[name]()
+    prob.rho = np.ones_like(prob.rho)
+    precond = "dirichlet" if method == "fetidp" else "lumped"
+    op = (ofeti.FETIDP if method == "fetidp" else ofeti.TFETI)(prob, precond, "k")
+    assert _tol_fp64(op) < 1e-11
+    print(f"case well-conditioned {name} {method} k={k}", flush=True)
+    ctx = _ctx(prob, method=method, scaling="k", precond=precond)
+    L = np.random.default_rng(k + 17).standard_normal((op.n_lambda, k))
+    Q = torch.zeros((op.n_lambda, k), dtype=torch.float64, device=DEV)
+    if method == "tfeti":
+        # TFETI: only the projected operator P F P is independent of the generalised inverse
+        L = op.project(L)
+    ctx.feti_apply_F(k, "fp64", _t(L), Q)
+    ref = op.apply_F(L)
+    if method == "tfeti":
+        ctx.feti_project(k, Q)
+        ref = op.project(ref)
+    err = _rel(Q.cpu().numpy(), ref)
+    print(f"  error {err:.2e}", flush=True)
+    assert err < 1e-12
+    if method == "fetidp":
+        for s in range(prob.n_sub):
+            assert _rel(ctx.feti_get_local(s, 0), op.F_local[s]) < 1e-12, s
     ctx.close()
 
 
@@ -219,34 +261,63 @@ def test_preconditioner_and_rhs(oracle_cache, name, method):
     ctx.close()
 
 
+class _DenseF:
+    """The oracle's operator evaluated through its explicit dense F (symmetrised): the same
+    operator with a different rounding order, to measure how far round-off alone moves the
+    oracle's own iteration count."""
+
+    def __init__(self, op):
+        self.op = op
+        F = op.apply_F(np.eye(op.n_lambda))
+        self.F = 0.5 * (F + F.T)
+        self.n_lambda = op.n_lambda
+        self.d = op.d
+
+    def apply_F(self, L):
+        return self.F @ L
+
+    def project(self, Y):
+        return self.op.project(Y)
+
+    def lambda0(self):
+        return self.op.lambda0()
+
+    def precondition(self, r, one_column=False):
+        return self.op.precondition(r, one_column)
+
+
 @pytest.mark.parametrize("method", ["tfeti", "fetidp"])
 @pytest.mark.parametrize("scaling", ["mult", "k"])
 @pytest.mark.parametrize("kr", ["pcg", "fo", "sfeti"])
 def test_twelve_variants_c1(method, scaling, kr):
-    """Every variant of the paper's comparison on the 4x2 cantilever (FP64)."""
+    """Every variant of the paper's comparison on the 4x2 cantilever (FP64), tol 1e-8 of the
+    configuration: u against the oracle and the direct solve, and the iteration at which the
+    relative eps_r (Eq. 16) first drops below 1e-8 against the oracle's.
+
+    The allowed difference is 1, or the oracle's own round-off spread where that is larger: the
+    oracle run on its explicit dense F (same operator, other rounding order) crosses 1e-8 at
+    70 vs 64 iterations for plain TFETI PCG with multiplicity scaling and 56 vs 54 with
+    k-scaling (a lumped preconditioner loses orthogonality quickly there); every other variant
+    crosses at the same iteration in both forms."""
     prob = workloads.cantilever_tfeti(0)
     precond = "lumped" if method == "tfeti" else "dirichlet"
-    print(f"case c1 {method} {scaling} {kr}", flush=True)
     cls = ofeti.TFETI if method == "tfeti" else ofeti.FETIDP
     op = cls(prob, precond, scaling)
     res = okrylov.solve(op, kr, tol=1e-10)
+    res_dense = okrylov.solve(_DenseF(op), kr, tol=1e-10)
     u_ref, _ = op.recover(res.lam)
     ctx = _ctx(prob, method=method, scaling=scaling, krylov=kr, precond=precond, tol=1e-10)
     u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
     info = ctx.feti_solve(_t(prob.load()), u)
     assert _rel(u.cpu().numpy(), u_ref) < 1e-8
     assert _rel(u.cpu().numpy(), fem.solve_problem(prob)) < 1e-8
-    # iteration counts: the first iterate whose relative eps_r drops below 1e-8 (below that
-    # the measure oscillates at round-off level and even two equivalent pseudo-inverses of
-    # K^s in the oracle differ by a few iterations at 1e-10)
-    hg = np.asarray(info["history"]) / info["history"][0]
-    ho = np.asarray(res.history) / res.history[0]
+    rel = lambda h: np.asarray(h) / h[0]
     cross = lambda h: int(np.argmax(h <= 1e-8)) if np.any(h <= 1e-8) else len(h)
-    # plain TFETI PCG (lumped preconditioner) loses orthogonality: its count moves by a few
-    # iterations under any change of round-off (the oracle with two equivalent
-    # pseudo-inverses of K^s already differs by 2 at 1e-10); FETI-DP PCG must agree to 1.
-    band = 1 if (kr == "pcg" and method == "fetidp") else max(2, cross(ho) // 10)
-    assert abs(cross(hg) - cross(ho)) <= band
+    hg, ho, hd = rel(info["history"]), rel(res.history), rel(res_dense.history)
+    spread = abs(cross(hd) - cross(ho))
+    print(f"case c1 {method} {scaling} {kr}: crossing 1e-8 at gpu {cross(hg)}, oracle {cross(ho)}, "
+          f"oracle dense-F {cross(hd)}", flush=True)
+    assert abs(cross(hg) - cross(ho)) <= max(1, spread)
     m = min(5, len(hg), len(ho))
     assert np.allclose(hg[:m], ho[:m], rtol=1e-7)
     ctx.close()
@@ -618,4 +689,26 @@ def test_autograd_compliance_fd_and_oracle():
         cm = float(compliance(_t(rm), ctx, f).cpu())
         fd = (cp - cm) / (2 * h)
         assert abs(fd - g[e]) <= 1e-5 * gmax + 1e-7, (e, fd, g[e])
+    ctx.close()
+
+
+def test_unconverged_solve_raises_in_compliance_and_autograd():
+    """A solve stopped by the iteration cap (status FETI_ENOCONV) must not hand a compliance or
+    gradient to autograd: the binding and the autograd forward raise, and only an explicit
+    allow_noconv returns the status with c and dc written."""
+    from paper_2111_11728_amd.autograd import compliance
+    prob = workloads.cantilever_tfeti(5, nsub=(2, 2), m=4)
+    print("case unconverged compliance", flush=True)
+    ctx = _ctx(prob, method="fetidp", scaling="k", krylov="pcg", tol=1e-14, max_it=2)
+    f = _t(prob.load())
+    c = torch.zeros(1, dtype=torch.float64, device=DEV)
+    g = torch.zeros(prob.n_el, dtype=torch.float64, device=DEV)
+    with pytest.raises(feti.FetiError) as ei:
+        ctx.feti_compliance_and_grad(_t(prob.rho), f, c, g)
+    assert ei.value.status == feti.FETI_ENOCONV
+    with pytest.raises(feti.FetiError):
+        compliance(_t(prob.rho).requires_grad_(True), ctx, f)
+    info = ctx.feti_compliance_and_grad(_t(prob.rho), f, c, g, allow_noconv=True)
+    assert info["status"] == feti.FETI_ENOCONV and info["iters"] == 2
+    assert float(c.cpu()) != 0.0
     ctx.close()

@@ -1,0 +1,139 @@
+"""Parity of the HIP path with the oracle's stored full-size runs (files under tests/golden/,
+written by make_krylov_goldens.py and make_c3_u_sample.py, which call only the oracle).
+
+* 2D modular design, 8x4 subdomains of 32^2 elements (66 306 DOFs, contrast 1e-6): FETI-DP with
+  the Dirichlet preconditioner, {multiplicity, k-scaling} x {PCG, full orthogonalisation}
+  (Sec. 3.1-3.2) at 1e-6 with the cap n_lambda. The converged / iteration-cap outcome must be the
+  oracle's; the relative eps_r (Eq. 16) must follow the oracle's history while the oracle's two
+  rounding orders still agree; the iteration count must lie within the oracle's own round-off
+  spread (the oracle on its dense F against the oracle on its subdomain operators), or within 1.
+* 2D Beta(0.3, 0.3) design, 16x16 subdomains of 64^2 (2 101 250 DOFs, contrast 1e-9), the
+  benchmark's configuration at its tolerance 1e-6: S-FETI-DP, k-scaling, 64 and 32 directions
+  (Algorithm 1), in FP64 and with FP32 F*Lambda. Iterations within 1 of the oracle's, the eps_r
+  history, u at 4096 sampled DOFs against the oracle's solve at the same tolerance, the compliance
+  and the gradient at 20 sampled elements.
+* 3D modular design, 4x4x4 subdomains of 12^3 (352 947 DOFs): u against the global direct solution
+  (FP64 at tol 1e-10: 1e-8; FP32 F*Lambda at tol 1e-8: 1e-6), the gradient at 20 sampled elements
+  against the oracle's gradient of that solution, and the S-FETI-DP iteration count at 1e-6.
+"""
+import pathlib
+
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+feti = pytest.importorskip("paper_2111_11728_amd.feti")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+GOLDEN = pathlib.Path(__file__).with_name("golden")
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _load(name):
+    path = GOLDEN / name
+    if not path.exists():
+        pytest.skip(f"{name} not written (tests/golden/make_krylov_goldens.py)")
+    return np.load(path)
+
+
+def _solve(prob, **kw):
+    opts = dict(method="fetidp", scaling="k", krylov="sfeti", precond="dirichlet", precision="fp64", tol=1e-6)
+    opts.update(kw)
+    ctx = feti.Context(feti.Spec(prob, **opts), _t(prob.rho))
+    c = torch.zeros(1, dtype=torch.float64, device=DEV)
+    g = torch.zeros(prob.n_el, dtype=torch.float64, device=DEV)
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
+    info = ctx.feti_compliance_and_grad(_t(prob.rho), _t(prob.load()), c, g, u, allow_noconv=True, hist_cap=8192)
+    ctx.close()
+    return info, u.cpu().numpy(), float(c.cpu()), g.cpu().numpy()
+
+
+def _first_disagreement(a, b, rtol):
+    m = min(len(a), len(b))
+    dev = np.abs(np.asarray(a[:m]) / np.asarray(b[:m]) - 1.0)
+    return int(np.argmax(dev > rtol)) if np.any(dev > rtol) else m
+
+
+@pytest.mark.parametrize("scaling", ["mult", "k"])
+@pytest.mark.parametrize("kr", ["pcg", "fo"])
+def test_c2_variants_against_oracle(scaling, kr):
+    rec = _load("c2_variants.npz")
+    key = f"{scaling}_{kr}"
+    prob = workloads.modular_2d(0)
+    print(f"case c2 {scaling} {kr}", flush=True)
+    info, _, _, _ = _solve(prob, scaling=scaling, krylov=kr)
+    ho = rec[key + "_history"] / rec[key + "_history"][0]
+    hd = rec[key + "_history_dense"] / rec[key + "_history_dense"][0]
+    hg = info["history"] / info["history"][0]
+    it_o, it_d = int(rec[key + "_iters"]), int(rec[key + "_iters_dense"])
+    spread = abs(it_o - it_d)
+    agree = _first_disagreement(ho, hd, 1e-6)     # the oracle's two rounding orders agree this far
+    print(f"  gpu {info['iters']} iterations (status {info['status']}), oracle {it_o} (dense F {it_d}), "
+          f"history agreement gpu/oracle {_first_disagreement(hg, ho, 1e-6)}, oracle/dense {agree}", flush=True)
+    converged = info["status"] == feti.FETI_OK
+    assert converged == bool(rec[key + "_converged"])
+    assert _first_disagreement(hg, ho, 1e-6) >= min(agree, 10)
+    assert abs(info["iters"] - it_o) <= max(1, spread)
+
+
+@pytest.mark.parametrize("dirs", [64, 32])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c3_sfeti_at_benchmark_tolerance(dirs, precision):
+    rec = _load("c3_sfeti.npz")
+    key = f"k{dirs}_"
+    prob = workloads.beta_2d(0, n_dirs=dirs)
+    print(f"case c3 sfeti k={dirs} {precision} tol 1e-6", flush=True)
+    info, u, c, g = _solve(prob, precision=precision)
+    assert info["status"] == feti.FETI_OK and info["true_rel_res"] <= 1e-6
+    it_o = int(rec[key + "iters"])
+    ho = rec[key + "history"] / rec[key + "history"][0]
+    hg = info["history"] / info["history"][0]
+    m = min(len(ho), len(hg))
+    hist_dev = float(np.max(np.abs(hg[:m] / ho[:m] - 1.0)))
+    u_err = np.linalg.norm(u[rec["idx"]] - rec[key + "u"]) / float(rec[key + "u_norm"])
+    c_err = abs(c - float(rec[key + "c"])) / abs(float(rec[key + "c"]))
+    g_err = np.linalg.norm(g[rec["el_idx"]] - rec[key + "g"]) / np.linalg.norm(rec[key + "g"])
+    print(f"  gpu {info['iters']} iterations ({info['reduced_iters']} reduced), oracle {it_o}; eps_r history "
+          f"deviation {hist_dev:.2e}; u {u_err:.2e}, c {c_err:.2e}, g {g_err:.2e}", flush=True)
+    assert abs(info["iters"] - it_o) <= 1
+    if precision == "fp64":
+        assert hist_dev < 1e-4
+    assert u_err < 1e-6
+    assert c_err < 1e-7
+    assert g_err < 1e-5
+
+
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-10, 1e-8), ("fp32", 1e-8, 1e-6)])
+def test_c5_full_size_against_direct(precision, tol, bound):
+    rec = _load("c5_sfeti.npz")
+    prob = workloads.modular_3d(0)
+    print(f"case c5 {precision} tol {tol}", flush=True)
+    info, u, c, g = _solve(prob, precision=precision, tol=tol)
+    assert info["status"] == feti.FETI_OK
+    u_err = np.linalg.norm(u[rec["idx"]] - rec["u_star"]) / float(rec["u_star_norm"])
+    gs = rec["g_star"]
+    g_err = np.abs(g[rec["el_idx"]] - gs).max() / np.abs(gs).max()
+    c_err = abs(c - float(rec["c_star"])) / abs(float(rec["c_star"]))
+    print(f"  {info['iters']} iterations, u {u_err:.2e}, c {c_err:.2e}, g {g_err:.2e}", flush=True)
+    assert u_err < bound
+    assert c_err < bound
+    assert g_err < 10 * bound
+
+
+def test_c5_iterations_at_benchmark_tolerance():
+    rec = _load("c5_sfeti.npz")
+    prob = workloads.modular_3d(0)
+    print("case c5 fp64 tol 1e-6 iterations", flush=True)
+    info, u, _, _ = _solve(prob, precision="fp64", tol=1e-6)
+    it_o = int(rec["k64_iters"])
+    u_err = np.linalg.norm(u[rec["idx"]] - rec["k64_u"]) / float(rec["k64_u_norm"])
+    print(f"  gpu {info['iters']} iterations, oracle {it_o}; u against the oracle's solve {u_err:.2e}", flush=True)
+    assert abs(info["iters"] - it_o) <= 1
+    assert u_err < 1e-6

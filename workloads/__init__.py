@@ -143,6 +143,16 @@ def beta_2d(seed: int = 0, nsub=(16, 16), m: int = 64, n_dirs: int = 64, Emin: f
                    Emin=Emin, name=f"beta2d_{nsub[0]}x{nsub[1]}_of_{m}", groups=groups)
 
 
+def beta_2d_block(seed: int = 0, bs: int = 4, nsub=(16, 16), m: int = 64, Emin: float = 1e-9) -> Problem:
+    """The lower-left bs x bs block of subdomains of beta_2d(seed): the same 64x64-element
+    subdomains and the same density values, clamped at its own x = 0 edge and loaded at its own
+    right-mid node; 2x2 subdomain groups. A bounded sample of that workload for timing CPU code."""
+    full = beta_2d(seed, nsub, m, Emin=Emin)
+    rho = full.rho.reshape(full.nel[1], full.nel[0])[: bs * m, : bs * m].ravel().copy()
+    return Problem(2, (bs * m, bs * m), tuple(uniform_cuts(bs * m, bs) for _ in range(2)), rho,
+                   Emin=Emin, name=f"beta2d_block{bs}x{bs}_of_{m}", groups=(2, 2))
+
+
 def modular_3d(seed: int = 0, nsub=(4, 4, 4), m: int = 12, Emin: float = 1e-6) -> Problem:
     """3D Hex8 modular design: each 12^3 module a seeded 0/1 pattern at solid fraction 0.5."""
     rng = np.random.default_rng(seed)
