@@ -48,7 +48,8 @@ typedef enum {
 enum { FETI_TFETI = 0, FETI_DP = 1 };                       /* Sec. 2.1 / Sec. 2.2 */
 enum { FETI_MULT = 0, FETI_KSCALE = 1 };                    /* Sec. 3.1 */
 enum { FETI_PCG = 0, FETI_FO = 1, FETI_SFETI = 2 };         /* Sec. 2, Sec. 3.2, Sec. 3.3 */
-enum { FETI_DIRICHLET = 0, FETI_LUMPED = 1 };               /* Sec. 3.1, Eq. (13) */
+enum { FETI_DIRICHLET = 0, FETI_LUMPED = 1, FETI_SUPERLUMPED = 2 };   /* Sec. 3.1, Eq. (13): S~^s =
+                                                                       S^s, K_bb or diag K_bb */
 enum { FETI_FP64 = 0, FETI_FP32 = 1, FETI_BF16X3 = 2 };     /* arithmetic of the F*Lambda product */
 enum { FETI_PURE = 16 };   /* or-ed into feti_apply_F's precision: no per-subdomain FP64 fallback */
 
@@ -75,7 +76,7 @@ typedef struct {
     int method;               /* FETI_TFETI or FETI_DP */
     int scaling;              /* FETI_MULT or FETI_KSCALE */
     int krylov;               /* FETI_PCG, FETI_FO or FETI_SFETI */
-    int precond;              /* FETI_DIRICHLET or FETI_LUMPED */
+    int precond;              /* FETI_DIRICHLET, FETI_LUMPED or FETI_SUPERLUMPED */
     int precision;            /* FETI_FP64, FETI_FP32 or FETI_BF16X3: arithmetic of F*Lambda inside
                                  the Krylov loop; Gram products, the coarse problem and the
                                  true residual stay FP64 */

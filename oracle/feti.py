@@ -11,7 +11,8 @@ of Eq. (12), u_c = Kbar_cc^{-1} (fbar_c + F_rc^T lambda), leaves the lambda-only
 system (F_rr + F_rc Kbar_cc^{-1} F_rc^T) lambda = d_r - F_rc Kbar_cc^{-1} fbar_c.
 
 Preconditioner (Sec. 3.1, Eq. 13): sum_s B~^s S~^s B~^sT with B~^s = W^s B^s and
-S~^s the Dirichlet Schur complement K_bb - K_bi K_ii^{-1} K_ib or the lumped K_bb;
+S~^s the Dirichlet Schur complement K_bb - K_bi K_ii^{-1} K_ib, the lumped K_bb or the
+super-lumped diag K_bb;
 in FETI-DP the sets i and b are subsets of r. For simultaneous directions the
 contribution of subdomain s goes to column g(s) of Z (Algorithm 1).
 
@@ -96,6 +97,8 @@ class _Common:
                 self.S.append(schur_on(self.K[s], b_loc, active_sets[s]))
             elif precond == "lumped":
                 self.S.append(self.K[s][b_loc][:, b_loc].toarray())
+            elif precond == "superlumped":
+                self.S.append(np.diag(self.K[s][b_loc][:, b_loc].diagonal()))
             else:
                 raise ValueError(precond)
         col_to_local = self.col_to_local

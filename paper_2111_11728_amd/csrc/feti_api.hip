@@ -172,13 +172,16 @@ struct feti_ctx {
     // solve buffers
     double *f_last = nullptr, *fi = nullptr, *fbeta = nullptr, *h = nullptr, *g = nullptr, *yb = nullptr,
            *yc = nullptr, *fbar_s = nullptr, *d = nullptr, *lam0 = nullptr, *lam = nullptr, *lt = nullptr,
-           *r = nullptr, *xb = nullptr, *ubeta = nullptr, *ui = nullptr, *uloc = nullptr, *uc = nullptr,
+           *lt2 = nullptr, *r = nullptr, *xb = nullptr, *ubeta = nullptr, *ui = nullptr, *uloc = nullptr, *uc = nullptr,
            *alpha = nullptr, *e = nullptr, *GY = nullptr, *tcoef = nullptr, *u_int = nullptr;
     double *Ybuf = nullptr, *Tbuf = nullptr, *vbuf = nullptr, *Qtmp = nullptr, *Tsum = nullptr;
     double *Zk = nullptr, *Qk = nullptr, *Delta = nullptr, *Tm = nullptr, *gam = nullptr, *part = nullptr,
            *scal = nullptr, *Psi = nullptr, *tmpv = nullptr, *zv = nullptr, *K0dev = nullptr;
     int* rank_dev = nullptr;         // inside scal (scal[8]), so one copy returns eps and rank
     double* hpin = nullptr;          // pinned host mirror of scal
+    // one-ahead S-FETI loop: per-iteration copies of scal (two slots) and their completion events
+    double* hslot[2] = {nullptr, nullptr};
+    hipEvent_t evr[2] = {nullptr, nullptr};
     const double** qk_ptr = nullptr;    // device table holding the single pointer Qk
     const double** zk_ptr = nullptr;    // device table holding the single pointer Zk
     double* tcbuf = nullptr;            // coarse right-hand sides t (n_cg x k)
@@ -222,6 +225,10 @@ struct feti_ctx {
         for (void* p : allocs) hipFree(p);
         for (double* p : hist_chunks) hipFree(p);
         if (hpin) hipHostFree(hpin);
+        for (int q = 0; q < 2; ++q) {
+            if (hslot[q]) hipHostFree(hslot[q]);
+            if (evr[q]) hipEventDestroy(evr[q]);
+        }
         if (WH_dev) hipFree(WH_dev);
         if (QH_dev) hipFree(QH_dev);
         if (Psi) hipFree(Psi);
@@ -625,6 +632,32 @@ void build_layout(feti_ctx* c) {
             yo[e] = P.row_s[e] >= 0 ? c->hsubs[P.row_s[e]].off_b + P.row_j[e] : -1;
         t.row_yo = c->upload(yo);
     }
+    if (P.method == FETI_DP && P.n_cg > 0 && P.n_lambda > 0) {
+        // coarse fold entries of every lambda row (values follow at each setup: launch_fold_rows)
+        int W = 0;
+        for (int r = 0; r < P.n_lambda; ++r) {
+            int ne = 0;
+            for (int e = 0; e < 2; ++e)
+                if (P.row_s[2 * r + e] >= 0) ne += c->hsubs[P.row_s[2 * r + e]].n_c;
+            W = std::max(W, ne);
+        }
+        W = std::max(W, 1);
+        std::vector<int> fn(P.n_lambda, 0), fc((size_t)P.n_lambda * W, 0);
+        for (int r = 0; r < P.n_lambda; ++r) {
+            int ne = 0;
+            for (int e = 0; e < 2; ++e) {
+                const int s = P.row_s[2 * r + e];
+                if (s < 0) continue;
+                const SubMeta& M = c->hsubs[s];
+                for (int q = 0; q < M.n_c; ++q) fc[(size_t)r * W + ne++] = P.c_glob[M.off_c + q];
+            }
+            fn[r] = ne;
+        }
+        t.fr_w = W;
+        t.fr_n = c->upload(fn);
+        t.fr_col = c->upload(fc);
+        t.fr_val = c->alloc<double>((long long)P.n_lambda * W);
+    }
     t.row_sh = c->upload(P.row_sh);
     t.sh_ptr = c->upload(P.sh_ptr);
     t.sh_s = c->upload(P.sh_s);
@@ -724,6 +757,7 @@ void build_layout(feti_ctx* c) {
     c->lam0 = c->alloc<double>(nl);
     c->lam = c->alloc<double>(nl);
     c->lt = c->alloc<double>(nl);
+    c->lt2 = c->alloc<double>(nl);
     c->r = c->alloc<double>(nl);
     c->zv = c->alloc<double>(nl);
     c->tmpv = c->alloc<double>(nl);
@@ -753,6 +787,10 @@ void build_layout(feti_ctx* c) {
     c->scal = c->alloc<double>(16 + 3 * nd);
     c->rank_dev = reinterpret_cast<int*>(c->scal + 8);
     HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(double) * (16 + 3 * nd), hipHostMallocDefault));
+    for (int q = 0; q < 2; ++q) {
+        HIPCHK(hipHostMalloc((void**)&c->hslot[q], sizeof(double) * (16 + 3 * nd), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&c->evr[q], hipEventDisableTiming));
+    }
     c->eps0_d.assign(nd, 0.0);
     c->true_d.assign(nd, 0.0);
     c->qk_ptr = c->upload(std::vector<const double*>{c->Qk});
@@ -907,7 +945,8 @@ void numeric_setup(feti_ctx* c) {
     CHECK_LAUNCH();
     launch_bt_forward_li(t, c->L, c->Li, c->Z, st);
     CHECK_LAUNCH();
-    if (c->opts.precond == FETI_LUMPED) launch_pack_sym(t, c->S, c->Pk, st);
+    if (c->opts.precond == FETI_LUMPED || c->opts.precond == FETI_SUPERLUMPED) launch_pack_sym(t, c->S, c->Pk, st);
+    if (c->opts.precond == FETI_SUPERLUMPED) launch_pk_diag_only(t, c->Pk, st);
     launch_gemm_tn(c->d_syrk, t.n_sub, c->syrk_tiles, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
     CHECK_LAUNCH();
     if (c->opts.precond == FETI_DIRICHLET) launch_pack_sym(t, c->S, c->Pk, st);
@@ -926,8 +965,10 @@ void numeric_setup(feti_ctx* c) {
     CHECK_LAUNCH();
     if (P.method == FETI_TFETI)
         launch_tfeti_fix(t, c->Rb, c->tau, c->F64, st);
-    else
+    else {
         launch_frc(t, c->S, c->F64, c->Kc, st);
+        launch_fold_rows(t, c->F64, st);
+    }
     CHECK_LAUNCH();
     launch_swizzle(t, c->F64, c->sw64, c->sw32, c->swhi, c->swlo, st);
     launch_weights(t, c->opts.scaling == FETI_KSCALE, c->diag, c->w, c->bg_w, st);
@@ -970,9 +1011,10 @@ void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool ti
     if (time_it) HIPCHK(hipEventRecord(c->ev[3], st));
     if (c->P.method == FETI_DP && c->P.n_cg > 0) {
         launch_coarse(t, k, f32, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->vbuf, c->tcbuf, st);
-        launch_fold_coarse(t, k, f32, c->F64, c->vbuf, c->Ybuf, st);
+        launch_scatter_fold(t, k, f32, c->Ybuf, c->vbuf, Q, st);
+    } else {
+        launch_scatter(t, k, f32, c->Ybuf, Q, st);
     }
-    launch_scatter(t, k, f32, c->Ybuf, Q, st);
     CHECK_LAUNCH();
 }
 
@@ -1009,7 +1051,10 @@ void project(feti_ctx* c, int k, double* Y) {
 void precondition(feti_ctx* c, const double* r, double* Z, int one_column, int use_f32) {
     DevTopo& t = c->t;
     (void)use_f32;  // the preconditioner blocks stay FP64: FP32 rounding can make them indefinite
-    launch_precond_local(t, r, c->bg_w, c->Pk, c->ypart, c->yb, c->st);
+    if (c->opts.precond == FETI_SUPERLUMPED)
+        launch_precond_diag(t, r, c->bg_w, c->Pk, c->yb, c->st);
+    else
+        launch_precond_local(t, r, c->bg_w, c->Pk, c->ypart, c->yb, c->st);
     launch_precond_scatter(t, one_column, c->w, c->yb, Z, c->st);
     CHECK_LAUNCH();
 }
@@ -1189,10 +1234,11 @@ struct PrecGate {
         else
             eta = prec == FETI_BF16X3 ? 1e-3 : 1e-4;
     }
+    bool pending = false;   // a probe's norms are not read back yet (one-ahead loop): no reduced product
     int choose(bool replaced, double eps, double eps0) {
         if (prec == FETI_FP64 || replaced) return kFp64;
         if (sw > 0.0) return eps <= sw * eps0 ? kReduced : kFp64;
-        if (!(eta * eps <= 0.1 * tol * eps0)) return kFp64;
+        if (pending || !(eta * eps <= 0.1 * tol * eps0)) return kFp64;
         if (!measured || since >= kProbeEvery) return kProbe;
         ++since;
         return kReduced;
@@ -1507,6 +1553,198 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
     return o;
 }
 
+// Waits for an event by polling (the Krylov loop waits once per iteration).
+void wait_event(hipEvent_t e) {
+    hipError_t r;
+    while ((r = hipEventQuery(e)) == hipErrorNotReady) {
+    }
+    HIPCHK(r);
+}
+
+// One pass of Algorithm 1 for a single design with the host one iteration behind the device:
+// iteration i+1 is enqueued before the scalars of iteration i (eps, rank, a probe's norms) are
+// read back, so the device runs the iterations back to back and never waits for the host.
+// Iteration i+1 reads the lambda correction of i from one of two buffers and writes its own into
+// the other, and stores its directions in the next history slot; when iteration i ends the pass
+// (tolerance, rank 0, a stalled reduced recurrence, the dual space exhausted), i+1 is dropped:
+// the history count and the correction buffer of i are kept, and every later step (residual
+// replacement, the FP64 true residual, recovery) recomputes r and Z from lambda. The precision gate
+// chooses from the last eps read back, one iteration older than in the synchronous loop, and
+// takes no reduced product while a probe's norms are still on their way.
+KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, int max_it,
+                          std::vector<double>& hist, std::vector<int>& ranks) {
+    KrylovOut o;
+    const int n = c->P.n_lambda;
+    hipStream_t st = c->st;
+    const int one = kd == 1;
+    const int passes = c->opts.reorth == 2 ? 2 : 1;
+    const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
+    const size_t nsc = 16 + 3 * c->designs.size();
+    auto orth = [&](int nb_) {
+        for (int pass = 0; pass < passes; ++pass) {
+            launch_gram(n, kd, kd, c->QH_dev, nb_, c->Zk, c->part, c->Psi, st, false);
+            launch_ts_gemm(n, kd, nb_, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st, false);
+        }
+    };
+    auto residual_dots = [&] {
+        launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
+        launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
+    };
+    precondition(c, c->r, c->Zk, one, 0);
+    residual_dots();
+    o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
+    if (converged(c, o.eps, eps0, tol) || max_it < 1) return o;
+    project(c, kd, c->Zk);   // W_0 = P Z_0 (in place)
+    // lambda correction buffers: buf(head) is the output of the last iteration enqueued
+    int head = 0;
+    auto buf = [&](int i) { return i == 0 ? c->lt : c->lt2; };
+    struct Step {
+        int p_it = FETI_FP64;
+        bool probed = false;
+        int out = 0, slot = 0;
+    };
+    int nb = 0;
+    double eps_seen = o.eps, best = o.eps;
+    int it_best = 0;
+    bool replaced = false;
+    auto enqueue = [&](int it) {
+        Step sp;
+        ensure_history(c, kd, nb + 1);
+        double* Wn = (double*)c->WH[nb];
+        double* Qn = (double*)c->QH[nb];
+        const int ch = g.choose(replaced, eps_seen, eps0);
+        if (ch == PrecGate::kProbe) {
+            apply_F(c, kd, FETI_FP64, c->Zk, c->Qk);
+            apply_F(c, kd, g.prec, c->Zk, c->Qtmp);
+            launch_diff_norms((long long)n * kd, c->Qtmp, c->Qk, c->part, c->scal + 4, st);
+            sp.probed = true;
+            g.pending = true;
+        } else {
+            sp.p_it = ch == PrecGate::kReduced ? g.prec : FETI_FP64;
+            run_graph(c, c->g_apply[sp.p_it], kd, [&] { apply_F(c, kd, sp.p_it, c->Zk, c->Qk); });
+        }
+        // Delta = Q^T W, its pivoted Cholesky, W <- W T, Q <- Q T, gamma = W^T r
+        launch_gram(n, kd, kd, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
+        launch_pivchol(kd, c->Delta, rr_tol, c->Tm, c->rank_dev, st, nullptr);
+        launch_ts_pair(n, kd, c->zk_ptr, c->qk_ptr, c->Tm, Wn, Qn, st);
+        if (kd == 64)
+            launch_gemv_t(n, kd, Wn, c->r, c->part, c->gam, st);
+        else
+            launch_gram(n, kd, 1, c->WH_dev + nb, 1, c->r, c->part, c->gam, st);
+        double* lin = buf(head);
+        double* lout = buf(1 - head);
+        if (c->P.method == FETI_TFETI) {
+            launch_update_lr(n, kd, Wn, nullptr, c->gam, lin, nullptr, st, lout);
+            HIPCHK(hipMemsetAsync(c->tmpv, 0, sizeof(double) * n, st));
+            launch_update_lr(n, kd, Qn, nullptr, c->gam, c->tmpv, nullptr, st);
+            project(c, 1, c->tmpv);
+            launch_axpby(n, -1.0, c->tmpv, 1.0, c->r, st);
+        } else {
+            launch_update_lr(n, kd, Wn, Qn, c->gam, lin, c->r, st, lout);
+        }
+        head = 1 - head;
+        sp.out = head;
+        ++nb;
+        run_graph(c, c->g_prec, kd, [&] {
+            precondition(c, c->r, c->Zk, one, 0);
+            residual_dots();
+            project(c, kd, c->Zk);
+        });
+        orth(nb);
+        sp.slot = it & 1;
+        HIPCHK(hipMemcpyAsync(c->hslot[sp.slot], c->scal, nsc * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(c->evr[sp.slot], st));
+        CHECK_LAUNCH();
+        return sp;
+    };
+    Step cur = enqueue(0);
+    for (int it = 0;; ++it) {
+        Step nxt;
+        bool have_nxt = false;
+        if (it + 1 < max_it) {
+            nxt = enqueue(it + 1);
+            have_nxt = true;
+        }
+        wait_event(c->evr[cur.slot]);
+        const double* hs = c->hslot[cur.slot];
+        if (cur.probed) {
+            const double e = hs[5] > 0.0 ? std::sqrt(hs[4] / hs[5]) : 0.0;
+            g.record(e);
+            g.pending = false;
+            if (verbose()) fprintf(stderr, "[feti] precision probe: eta %.3e\n", e);
+        }
+        int rank = 0;
+        std::memcpy(&rank, hs + 8, sizeof(int));
+        const double ez = hs[0];
+        ranks.push_back(rank);
+        o.iters = it + 1;
+        if (verbose())
+            fprintf(stderr, "[feti] sfeti it %d prec %d rank %d eps/eps0 %.3e\n", it + 1, cur.p_it, rank,
+                    std::sqrt(std::max(ez, 0.0)) / eps0);
+        auto drop_next = [&] {
+            if (!have_nxt) return;
+            --nb;
+            head = cur.out;
+            if (nxt.probed) g.pending = false;
+            have_nxt = false;
+        };
+        if (rank == 0) {
+            o.status = FETI_EBREAKDOWN;
+            drop_next();
+            break;
+        }
+        o.reduced += cur.p_it != FETI_FP64;
+        o.kept += rank;
+        o.eps = std::sqrt(std::max(ez, 0.0));
+        eps_seen = o.eps;
+        hist.push_back(o.eps);
+        const bool conv = converged(c, o.eps, eps0, tol);
+        if (o.eps < 0.9 * best) {
+            best = o.eps;
+            it_best = it;
+        }
+        if (!conv && cur.p_it != FETI_FP64 && (o.eps > 1e3 * best || it - it_best > 10)) {
+            o.status = FETI_ENOCONV;
+            drop_next();
+            break;
+        }
+        if ((conv && (o.reduced == 0 || replaced)) || o.kept >= n) {
+            drop_next();
+            break;
+        }
+        if (conv) {
+            // residual replacement after reduced-precision products (as in the synchronous loop)
+            drop_next();
+            if (head == 1) {
+                std::swap(c->lt, c->lt2);
+                head = 0;
+            }
+            replaced = true;
+            current_iterate(c, c->tmpv);
+            true_residual(c, c->tmpv, c->r);
+            precondition(c, c->r, c->Zk, one, 0);
+            residual_dots();
+            o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
+            eps_seen = o.eps;
+            if (verbose()) fprintf(stderr, "[feti] residual replacement: eps/eps0 %.3e\n", o.eps / eps0);
+            if (converged(c, o.eps, eps0, tol)) break;
+            project(c, kd, c->Zk);
+            orth(nb);
+            CHECK_LAUNCH();
+            best = o.eps;
+            it_best = it;
+            if (it + 1 >= max_it) break;
+            nxt = enqueue(it + 1);
+            have_nxt = true;
+        }
+        if (!have_nxt) break;
+        cur = nxt;
+    }
+    // the pass's lambda correction is read from c->lt
+    if (head == 1) std::swap(c->lt, c->lt2);
+    return o;
+}
+
 // recovery of u from lambda (c->lam)
 void recover(feti_ctx* c, double* u) {
     DevTopo& t = c->t;
@@ -1589,6 +1827,8 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
                 gate.prec = cur;
                 if (c->opts.krylov == FETI_PCG)
                     o = run_pcg(c, gate, eps0, tol, left, hist);
+                else if (c->designs.size() == 1 && !c->opts.orth_fp32)
+                    o = run_sfeti_ahead(c, gate, kd, eps0, tol, left, hist, ranks);
                 else
                     o = run_sfeti(c, gate, kd, eps0, tol, left, hist, ranks);
                 tot.iters += o.iters;
@@ -1679,7 +1919,8 @@ feti_status validate_opts(const feti_opts* o) {
     if (!o) return fail(FETI_EINVAL, "null options");
     if (o->scaling != FETI_MULT && o->scaling != FETI_KSCALE) return fail(FETI_EINVAL, "unknown scaling");
     if (o->krylov != FETI_PCG && o->krylov != FETI_FO && o->krylov != FETI_SFETI) return fail(FETI_EINVAL, "unknown krylov");
-    if (o->precond != FETI_DIRICHLET && o->precond != FETI_LUMPED) return fail(FETI_EINVAL, "unknown preconditioner");
+    if (o->precond != FETI_DIRICHLET && o->precond != FETI_LUMPED && o->precond != FETI_SUPERLUMPED)
+        return fail(FETI_EINVAL, "unknown preconditioner");
     if (o->precision != FETI_FP64 && o->precision != FETI_FP32 && o->precision != FETI_BF16X3)
         return fail(FETI_EINVAL, "unknown precision");
     if (!(o->tol >= 0.0)) return fail(FETI_EINVAL, "tol must be >= 0");

@@ -686,6 +686,79 @@ void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, doubl
         k_scatter<double><<<grid, 256, 0, st>>>(t.n_lambda, k, t.row_yo, t.row_sg, (const double*)Y, Q);
 }
 
+// Entries of B_r F_rc B_c (Sec. 2.2, Eq. 12) per lambda row: side t of the row (subdomain s,
+// interface position j, sign) contributes sign * F_rc^s[j][q] for each of the subdomain's corner
+// DOFs q, read from the F_rc^T rows of the augmented operator. One thread per row.
+__global__ void k_fold_rows(int n_lambda, int W, const int* __restrict__ row_s, const int* __restrict__ row_j,
+                            const int8_t* __restrict__ row_sg, const SubMeta* __restrict__ subs,
+                            const double* __restrict__ F64, double* __restrict__ fr_val) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_lambda) return;
+    int e = 0;
+    for (int t = 0; t < 2; ++t) {
+        const int s = row_s[2 * r + t];
+        if (s < 0) continue;
+        const SubMeta M = subs[s];
+        const int j = row_j[2 * r + t];
+        const double sg = (double)row_sg[2 * r + t];
+        for (int q = 0; q < M.n_c && e < W; ++q, ++e)
+            fr_val[(long long)r * W + e] = sg * F64[M.off_F + (long long)(M.rowT + q) * M.ldF + j];
+    }
+}
+
+void launch_fold_rows(const DevTopo& t, const double* F64, hipStream_t st) {
+    if (t.n_cg == 0 || t.n_lambda == 0 || t.fr_w == 0) return;
+    k_fold_rows<<<(t.n_lambda + 255) / 256, 256, 0, st>>>(t.n_lambda, t.fr_w, t.row_s, t.row_j, t.row_sg, t.subs,
+                                                          F64, t.fr_val);
+}
+
+// Q[row][c] = sum over the row's sides of sign * Y_s[j][c] + sum_e fr_val[row][e] v[fr_col[row][e]][c]:
+// the owner-computes scatter and the coarse fold Y_s += F_rc^s B_c^s v in one pass, so the local
+// products are read once and never rewritten. With k = 64 a wavefront is one row: its map entries
+// are wavefront-uniform scalar loads, v rows are 512-byte lines (L2-resident: n_cg x k).
+template <typename TY>
+__global__ void __launch_bounds__(256) k_scatter_fold(int n_lambda, int k, int W, const long long* __restrict__ row_yo,
+                                                      const int8_t* __restrict__ row_sg, const TY* __restrict__ Y,
+                                                      const int* __restrict__ fr_n, const int* __restrict__ fr_col,
+                                                      const double* __restrict__ fr_val, const double* __restrict__ v,
+                                                      double* __restrict__ Q) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_lambda * k) return;
+    int row = k == 64 ? idx >> 6 : idx / k;
+    if (k == 64) row = __builtin_amdgcn_readfirstlane(row);
+    const int c = idx - row * k;
+    double val = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const long long yo = row_yo[2 * row + t];
+        if (yo >= 0) val += row_sg[2 * row + t] * (double)Y[yo * k + c];
+    }
+    const int ne = fr_n[row];
+    const int* __restrict__ fc = fr_col + (long long)row * W;
+    const double* __restrict__ fv = fr_val + (long long)row * W;
+    double acc0 = 0.0, acc1 = 0.0;
+    int e = 0;
+    for (; e + 1 < ne; e += 2) {
+        acc0 = fma(fv[e], v[(long long)fc[e] * k + c], acc0);
+        acc1 = fma(fv[e + 1], v[(long long)fc[e + 1] * k + c], acc1);
+    }
+    if (e < ne) acc0 = fma(fv[e], v[(long long)fc[e] * k + c], acc0);
+    Q[idx] = val + (acc0 + acc1);
+}
+
+void launch_scatter_fold(const DevTopo& t, int k, int ytype_f32, const void* Y, const double* v, double* Q,
+                         hipStream_t st) {
+    const long long n = (long long)t.n_lambda * k;
+    if (n == 0) return;
+    const int grid = (int)((n + 255) / 256);
+    if (ytype_f32)
+        k_scatter_fold<float><<<grid, 256, 0, st>>>(t.n_lambda, k, t.fr_w, t.row_yo, t.row_sg, (const float*)Y, t.fr_n,
+                                                    t.fr_col, t.fr_val, v, Q);
+    else
+        k_scatter_fold<double><<<grid, 256, 0, st>>>(t.n_lambda, k, t.fr_w, t.row_yo, t.row_sg, (const double*)Y,
+                                                     t.fr_n, t.fr_col, t.fr_val, v, Q);
+}
+
 // ---------------------------------------------------------------------------------------
 // Preconditioner (Sec. 3.1, Eq. 13): x_s = B~^sT r = B^sT W^s r, y_s = S~^s x_s.
 // S~^s is symmetric and stored as its upper triangle in 64x64 tiles, so every stored value is
@@ -871,6 +944,50 @@ __global__ void __launch_bounds__(256) k_precond_scatter64(int n_lambda, const i
         if (lane == gbi) v += vbi;
         Z[(long long)(r0 + i) * 64 + lane] = v;
     }
+}
+
+// Super-lumped preconditioner (Sec. 3.1: S~^s = diag K_bb): y_q = (K_bb)_qq x_q with
+// x_q = sum over the multiplier rows of interface DOF q of sign * weight * r_row; one thread per
+// interface DOF, the diagonal read from the packed block (diagonal tiles, entry a * 65).
+__global__ void __launch_bounds__(256) k_precond_diag(long long nb_tot, const int* __restrict__ bq_s,
+                                                      const SubMeta* __restrict__ subs, const int* __restrict__ bg_ptr,
+                                                      const int* __restrict__ bg_row, const int8_t* __restrict__ bg_sg,
+                                                      const double* __restrict__ bg_w, const double* __restrict__ r,
+                                                      const double* __restrict__ Pk, double* __restrict__ y) {
+    const long long gq = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (gq >= nb_tot) return;
+    const SubMeta& M = subs[bq_s[gq]];
+    const int q = (int)(gq - M.off_b), J = q >> 6, a = q & 63;
+    const double d = Pk[M.off_Pk + ((long long)J * (J + 1) / 2 + J) * 4096 + a * 65];
+    double v = 0.0;
+    for (int e = bg_ptr[gq]; e < bg_ptr[gq + 1]; ++e) v += bg_sg[e] * bg_w[e] * r[bg_row[e]];
+    y[gq] = d * v;
+}
+
+void launch_precond_diag(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* y,
+                         hipStream_t st) {
+    if (t.nb_tot == 0) return;
+    k_precond_diag<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, t.bq_s, t.subs, t.bg_ptr, t.bg_row,
+                                                                    t.bg_sg, bg_w, r, Pk, y);
+}
+
+// Keeps only the diagonal of every packed preconditioner block (super-lumped: diag K_bb); one
+// workgroup per subdomain over its packed tiles.
+__global__ void __launch_bounds__(256) k_pk_diag_only(const SubMeta* __restrict__ subs, double* __restrict__ Pk) {
+    const SubMeta& M = subs[blockIdx.x];
+    const int nT = (M.n_b + 63) >> 6;
+    const long long ne = (long long)nT * (nT + 1) / 2 * 4096;
+    for (long long e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int tile = (int)(e >> 12), w = (int)(e & 4095);
+        int J = 0;
+        while ((J + 1) * (J + 2) / 2 <= tile) ++J;
+        const int I = tile - J * (J + 1) / 2;
+        if (I != J || (w >> 6) != (w & 63)) Pk[M.off_Pk + e] = 0.0;
+    }
+}
+
+void launch_pk_diag_only(const DevTopo& t, double* Pk, hipStream_t st) {
+    if (t.n_sub) k_pk_diag_only<<<t.n_sub, 256, 0, st>>>(t.subs, Pk);
 }
 
 void launch_precond_scatter(const DevTopo& t, int one_column, const double* w, const double* y, double* Z,

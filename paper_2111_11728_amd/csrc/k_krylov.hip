@@ -550,9 +550,10 @@ __global__ void __launch_bounds__(256) k_gemv_t64(int n, const double* __restric
 }
 
 // lam += W g; r -= Q g for 64 directions: 16 lanes per row, 4 consecutive columns each.
+// lam_out = lam + W gamma and r -= Q gamma (lam_out may be lam itself)
 __global__ void __launch_bounds__(256) k_update_lr64(int n, const double* __restrict__ W, const double* __restrict__ Q,
-                                                     const double* __restrict__ gm, double* __restrict__ lam,
-                                                     double* __restrict__ r,
+                                                     const double* __restrict__ gm, const double* lam,
+                                                     double* lam_out, double* __restrict__ r,
                                                      const int* __restrict__ rb_design) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int row = (int)(t >> 4), p = (int)(t & 15);
@@ -574,7 +575,7 @@ __global__ void __launch_bounds__(256) k_update_lr64(int n, const double* __rest
         dr += __shfl_xor(dr, o, 16);
     }
     if (row < n && p == 0) {
-        lam[row] += dl;
+        lam_out[row] = lam[row] + dl;
         if (Q) r[row] -= dr;
     }
 }
@@ -952,7 +953,7 @@ void launch_gemv_t_seg(const DevTopo& t, int n, const double* A, const double* x
 
 void launch_update_lr_seg(const DevTopo& t, int n, const double* W, const double* Q, const double* g, double* lam,
                           double* r, hipStream_t st) {
-    if (n) k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, r, t.rb_design);
+    if (n) k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, lam, r, t.rb_design);
 }
 
 void launch_pivchol_seg(int nseg, const double* D, double rr_tol, double* T, int* rank, unsigned long long* kept_mask,
@@ -1020,7 +1021,7 @@ void launch_apply_T(int n, int k, const double* T, const double* W, const double
 
 // lam += W g; r -= Q g (one thread per row).
 __global__ void k_update_lr(int n, int k, const double* __restrict__ W, const double* __restrict__ Q,
-                            const double* __restrict__ g, double* __restrict__ lam, double* __restrict__ r) {
+                            const double* __restrict__ g, const double* lam, double* lam_out, double* __restrict__ r) {
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= n) return;
     double dl = 0.0, dr = 0.0;
@@ -1028,17 +1029,18 @@ __global__ void k_update_lr(int n, int k, const double* __restrict__ W, const do
         dl += W[(long long)row * k + q] * g[q];
         if (Q) dr += Q[(long long)row * k + q] * g[q];
     }
-    lam[row] += dl;
+    lam_out[row] = lam[row] + dl;
     if (Q) r[row] -= dr;
 }
 
 void launch_update_lr(int n, int k, const double* W, const double* Q, const double* g, double* lam, double* r,
-                      hipStream_t st) {
+                      hipStream_t st, double* lam_out) {
     if (!n) return;
+    if (!lam_out) lam_out = lam;
     if (k == 64)
-        k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, r, nullptr);
+        k_update_lr64<<<(int)((16LL * n + 255) / 256), 256, 0, st>>>(n, W, Q, g, lam, lam_out, r, nullptr);
     else
-        k_update_lr<<<(n + 255) / 256, 256, 0, st>>>(n, k, W, Q, g, lam, r);
+        k_update_lr<<<(n + 255) / 256, 256, 0, st>>>(n, k, W, Q, g, lam, lam_out, r);
 }
 
 __global__ void __launch_bounds__(1024) k_colsum64(int nchunk, const double* __restrict__ part, double* __restrict__ out);

@@ -126,6 +126,12 @@ struct DevTopo {
     int ps_nwg = 0, ps_maxG = 1;
     const int* gmap = nullptr;        // fixed-width gather map: gmap[q*gmap_R + t] = sign*(row+1), 0 unused
     int gmap_R = 1;
+    // FETI-DP coarse fold of every lambda row, fixed width fr_w: the row's entries of
+    // B_r F_rc B_c (n_lambda x n_cg, at most two subdomains' corners), sign included
+    const int* fr_n = nullptr;        // entries of each row
+    const int* fr_col = nullptr;      // [n_lambda x fr_w] global corner DOF
+    double* fr_val = nullptr;         // [n_lambda x fr_w] values (set up with F_rc)
+    int fr_w = 0;
     int n_lines_tot = 0;              // interior line (2D) / plane (3D) blocks over all subdomains
     FlTiles fl64;                     // F*Lambda work list with every row block in FP64
     FlTiles flred;                    // ... with every row block in the reduced precision
@@ -182,9 +188,18 @@ void launch_fold_coarse(const DevTopo& t, int k, int ytype_f32, const double* F6
                         hipStream_t st);
 // Q[row] = sum over sides sign * Y[b]
 void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, double* Q, hipStream_t st);
+// fr_val from the F_rc^T rows of the augmented operators (after launch_frc)
+void launch_fold_rows(const DevTopo& t, const double* F64, hipStream_t st);
+// Q = sum_s B_s Y_s + (B_r F_rc B_c) v: the scatter with the coarse fold of F*Lambda in one pass
+void launch_scatter_fold(const DevTopo& t, int k, int ytype_f32, const void* Y, const double* v, double* Q,
+                         hipStream_t st);
 // x_s = B~^sT r gathered and multiplied: y_s = P_s x_s, P_s symmetric in packed 64x64 upper tiles;
 // ypart: kPsMaxSplit * nb_tot doubles of workspace (subdomains split over several workgroups)
 constexpr int kPsMaxSplit = 8;
+// super-lumped preconditioner: y = diag(K_bb) B~^T r per interface DOF; Pk reduced to its diagonal
+void launch_precond_diag(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* y,
+                         hipStream_t st);
+void launch_pk_diag_only(const DevTopo& t, double* Pk, hipStream_t st);
 void launch_precond_local(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* ypart,
                           double* y, hipStream_t st);
 // Pk (packed upper tiles) <- the leading n_b x n_b block of S (ld n_beta)
@@ -239,8 +254,9 @@ void launch_zero_cols(long long n, int k, unsigned long long mask, double* Z, hi
 void launch_apply_T(int n, int k, const double* T, const double* W, const double* Q, double* Wo, double* Qo,
                     hipStream_t st);
 // lam += W g; r -= Qg_scale * Q g  (Q may be null)
+// lam_out = lam + W g (lam_out = nullptr: in place), r -= Q g (Q = nullptr: r untouched)
 void launch_update_lr(int n, int k, const double* W, const double* Q, const double* g, double* lam, double* r,
-                      hipStream_t st);
+                      hipStream_t st, double* lam_out = nullptr);
 void launch_orth_update(int n, int k, const double* const* Wptrs, int nblk, const double* Psi, double* W,
                         hipStream_t st);
 void launch_rowsum_dot(int n, int k, const double* r, const double* Z, double* part, double* out, hipStream_t st);

@@ -20,14 +20,14 @@ FETI_OK, FETI_EINVAL, FETI_ENOMEM, FETI_EHIP, FETI_ENOTSPD, FETI_ENOCONV, FETI_E
 FETI_TFETI, FETI_DP = 0, 1
 FETI_MULT, FETI_KSCALE = 0, 1
 FETI_PCG, FETI_FO, FETI_SFETI = 0, 1, 2
-FETI_DIRICHLET, FETI_LUMPED = 0, 1
+FETI_DIRICHLET, FETI_LUMPED, FETI_SUPERLUMPED = 0, 1, 2
 FETI_FP64, FETI_FP32, FETI_BF16X3 = 0, 1, 2
 FETI_PURE = 16
 
 METHODS = {"tfeti": FETI_TFETI, "fetidp": FETI_DP}
 SCALINGS = {"mult": FETI_MULT, "k": FETI_KSCALE}
 KRYLOVS = {"pcg": FETI_PCG, "fo": FETI_FO, "sfeti": FETI_SFETI}
-PRECONDS = {"dirichlet": FETI_DIRICHLET, "lumped": FETI_LUMPED}
+PRECONDS = {"dirichlet": FETI_DIRICHLET, "lumped": FETI_LUMPED, "superlumped": FETI_SUPERLUMPED}
 PRECISIONS = {"fp64": FETI_FP64, "fp32": FETI_FP32, "bf16x3": FETI_BF16X3}
 
 

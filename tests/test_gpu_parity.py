@@ -712,3 +712,35 @@ def test_unconverged_solve_raises_in_compliance_and_autograd():
     assert info["status"] == feti.FETI_ENOCONV and info["iters"] == 2
     assert float(c.cpu()) != 0.0
     ctx.close()
+
+
+@pytest.mark.parametrize("method", ["fetidp", "tfeti"])
+@pytest.mark.parametrize("kr", ["pcg", "fo", "sfeti"])
+def test_superlumped_c1(method, kr):
+    """Super-lumped preconditioner (S~^s = diag K_bb, Sec. 3.1) with k-scaling on the 4x2
+    cantilever: the preconditioned residual of a random vector against the oracle's, u against the
+    oracle and the direct solve, and the iteration at which eps_r first drops below 1e-8."""
+    prob = workloads.cantilever_tfeti(0)
+    cls = ofeti.TFETI if method == "tfeti" else ofeti.FETIDP
+    op = cls(prob, "superlumped", "k")
+    print(f"case superlumped {method} {kr}", flush=True)
+    ctx = _ctx(prob, method=method, scaling="k", krylov=kr, precond="superlumped", tol=1e-10)
+    r = np.random.default_rng(5).standard_normal(op.n_lambda)
+    z = torch.zeros(op.n_lambda, dtype=torch.float64, device=DEV)
+    ctx.feti_apply_precond(_t(r), z, 1)
+    assert _rel(z.cpu().numpy(), op.precondition(r, one_column=True)[:, 0]) < 1e-13
+    for s in range(prob.n_sub):
+        assert _rel(ctx.feti_get_local(s, 1), op.S[s]) < 1e-14
+    res = okrylov.solve(op, kr, tol=1e-10)
+    u = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
+    info = ctx.feti_solve(_t(prob.load()), u)
+    u_ref, _ = op.recover(res.lam)
+    assert _rel(u.cpu().numpy(), u_ref) < 1e-8
+    assert _rel(u.cpu().numpy(), fem.solve_problem(prob)) < 1e-8
+    rel = lambda h: np.asarray(h) / h[0]
+    cross = lambda h: int(np.argmax(h <= 1e-8)) if np.any(h <= 1e-8) else len(h)
+    hd = rel(okrylov.solve(_DenseF(op), kr, tol=1e-10).history)
+    hg, ho = rel(info["history"]), rel(res.history)
+    print(f"  crossing 1e-8 at gpu {cross(hg)}, oracle {cross(ho)}, oracle dense-F {cross(hd)}", flush=True)
+    assert abs(cross(hg) - cross(ho)) <= max(1, abs(cross(hd) - cross(ho)))
+    ctx.close()

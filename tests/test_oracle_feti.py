@@ -341,3 +341,37 @@ def test_dirichlet_schur_is_harmonic_extension_energy(method):
         if method == "tfeti":
             Rb = op.R[s][b]
             assert np.abs(S @ Rb).max() <= 1e-10 * np.abs(S).max() * np.abs(Rb).max(), s
+
+
+def test_superlumped_preconditioner_closed_form_and_convergence(c1):
+    """Super-lumped preconditioner (Sec. 3.1: S~^s = diag K_bb). On a homogeneous unit-modulus
+    grid, a multiplier row on an interface edge (not a cross point) glues two subdomains whose
+    copies of the DOF each sit in two elements, so each K^s_jj = 2 K0_11 and, with weights 1/2,
+    (M e_row)_row = 2 (1/2)^2 2 K0_11 = K0_11 = (3 - nu) / (6 (1 - nu^2)) for an x-DOF. With
+    heterogeneous densities every variant still reaches the direct solution."""
+    prob = workloads.cantilever_tfeti(0, nsub=(2, 1), m=4)
+    prob.rho = np.ones_like(prob.rho)
+    op = feti.FETIDP(prob, "superlumped", "mult")
+    nu = prob.nu
+    k11 = (3 - nu) / (6 * (1 - nu ** 2))
+    rows = [r for r in range(op.n_lambda) if sum(1 for s in range(len(op.K)) if op.cons.Bb[s][r].nnz) == 2]
+    assert rows
+    for r in rows:
+        e = np.zeros(op.n_lambda)
+        e[r] = 1.0
+        z = op.precondition(e, one_column=True)[:, 0]
+        # x- and y-DOFs of an edge node: K0_11 and K0_22 are equal for the unit square
+        assert z[r] == pytest.approx(k11, rel=1e-12)
+        # diagonal blocks: no coupling to the neighbouring nodes' rows (the lumped K_bb has it)
+        assert np.count_nonzero(z) == 1
+    lumped = feti.FETIDP(prob, "lumped", "mult")
+    e = np.zeros(op.n_lambda)
+    e[rows[0]] = 1.0
+    assert np.count_nonzero(lumped.precondition(e, one_column=True)[:, 0]) > 1
+    prob, ustar = c1
+    for method in ["fetidp", "tfeti"]:
+        op = (feti.FETIDP if method == "fetidp" else feti.TFETI)(prob, "superlumped", "k")
+        for kr in ["pcg", "sfeti"]:
+            res = krylov.solve(op, kr, tol=1e-12)
+            assert res.converged
+            assert _rel(op.recover(res.lam)[0], ustar) < 1e-8
