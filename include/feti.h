@@ -270,6 +270,17 @@ feti_status feti_get_sizes(feti_ctx* ctx, feti_sizes* out);
  * or-ing FETI_PURE forces every subdomain to the reduced precision. 1 <= k <= 64. */
 feti_status feti_apply_F(feti_ctx* ctx, int k, int precision, const double* Lambda, double* Q);
 
+/* The product of feti_apply_F (same arguments, same kernels, bit-identical Q) for callers that
+ * cannot allocate device memory or wait on the device: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. It calls no allocation routine and does not
+ * synchronise or time: the work is only enqueued on the context's stream. Its work buffers (the
+ * local products, the corner rows and the coarse vectors: 8 * k * (sum n_b + sum n_c + 2 n_cg)
+ * bytes, each part rounded up to 256) live in a fixed 16 MiB device array that every GPU holds
+ * once for the life of the process; a larger request returns FETI_EINVAL and enqueues nothing.
+ * All calls on one GPU share that array, so calls that overlap in time on one GPU (other
+ * streams, other contexts, other host threads) race; serialise them. */
+feti_status feti_apply_F_noalloc(feti_ctx* ctx, int k, int precision, const double* Lambda, double* Q);
+
 /* Z = [.., B~^s S~^s B~^sT r, ..] (Sec. 3.1 Eq. 13, Algorithm 1): r device [n_lambda];
  * Z device [n_lambda x n_groups] (one_column = 0) or [n_lambda] summed (one_column = 1). */
 feti_status feti_apply_precond(feti_ctx* ctx, const double* r, double* Z, int one_column);

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -40,6 +41,29 @@ struct HipError {
     } while (0)
 
 #define CHECK_LAUNCH() HIPCHK(hipGetLastError())
+
+// Workspace of feti_apply_F_noalloc: the local products Y_s, the corner rows T_s and the coarse
+// vectors t and v of one F*Lambda. Every GPU the library runs on holds its own copy until the
+// process ends; calls on one GPU share it, so such calls must not overlap in time.
+constexpr long long kNoAllocScratchBytes = 16LL << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of this GPU's copy of scratch, looked up once per device with that device
+// current (host code never passes the array's name itself to a kernel or a copy).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) throw HipError{"device ordinal out of range for the no-allocation workspace"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
 
 // Unit-modulus element stiffness by full Gauss quadrature on the unit square / cube
 // (bilinear / trilinear shape functions, corners x fastest, DOFs interleaved).
@@ -153,6 +177,7 @@ struct feti_ctx {
             *gs = GraphSlot{};
         }
     }
+    void* scratch = nullptr;   // this device's no-allocation workspace (scratch_address)
     FlTile *fl64_dev = nullptr, *flred_dev = nullptr;
     int fl64_cap = 0, flred_cap = 0;
     std::vector<CoarseBlk> hcblk;
@@ -381,6 +406,9 @@ void build_fl_tiles(feti_ctx* c) {
 
 void build_layout(feti_ctx* c) {
     Plan& P = c->P;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    c->scratch = scratch_address(dev);
     const int ns = P.n_sub;
     if (c->designs.empty()) {   // a single design: the whole plan
         DesignMeta D;
@@ -995,7 +1023,38 @@ void numeric_setup(feti_ctx* c) {
 // Q = F Lambda (n_lambda x k) in the given precision. A reduced precision uses the
 // per-subdomain selection of the setup (FP64 tiles for the subdomains that failed the
 // round-off test, FP64 outputs) unless `pure` forces every tile to the reduced precision.
-void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool time_it = false, bool pure = false) {
+// Work buffers of one F*Lambda: local products Y (nb_tot x k), corner rows T (nc_tot x k), the
+// coarse right-hand sides t and the coarse solution v (n_cg x k each).
+struct FlBufs {
+    void *Y, *T;
+    double *v, *tc;
+};
+
+// Bytes of FlBufs for k columns laid out back to back, each part 256-byte aligned.
+long long fl_bufs_bytes(const DevTopo& t, int k) {
+    auto up = [](long long b) { return (b + 255) / 256 * 256; };
+    const long long ncg = std::max(1, t.n_cg);
+    return up(8LL * std::max<long long>(1, t.nb_tot) * k) + up(8LL * std::max<long long>(1, t.nc_tot) * k) +
+           2 * up(8LL * ncg * k);
+}
+
+FlBufs fl_bufs_in(const DevTopo& t, int k, void* base) {
+    auto up = [](long long b) { return (b + 255) / 256 * 256; };
+    const long long ncg = std::max(1, t.n_cg);
+    unsigned char* p = static_cast<unsigned char*>(base);
+    FlBufs b;
+    b.Y = p;
+    p += up(8LL * std::max<long long>(1, t.nb_tot) * k);
+    b.T = p;
+    p += up(8LL * std::max<long long>(1, t.nc_tot) * k);
+    b.tc = reinterpret_cast<double*>(p);
+    p += up(8LL * ncg * k);
+    b.v = reinterpret_cast<double*>(p);
+    return b;
+}
+
+void apply_F_with(feti_ctx* c, int k, int prec, const double* Lam, double* Q, const FlBufs& b, bool time_it,
+                  bool pure) {
     DevTopo& t = c->t;
     hipStream_t st = c->st;
     const void* A = prec == FETI_FP32 ? (const void*)c->sw32 : prec == FETI_BF16X3 ? (const void*)c->swhi : nullptr;
@@ -1003,19 +1062,23 @@ void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool ti
     const int f32 = prec != FETI_FP64 && !hyb;
     if (time_it) HIPCHK(hipEventRecord(c->ev[2], st));
     if (hyb) {
-        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, c->Ybuf, c->Tbuf, st, &c->fl_hyb, 1);
+        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, b.Y, b.T, st, &c->fl_hyb, 1);
     }
     else
-        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, c->Ybuf, c->Tbuf, st);
+        launch_flambda(t, prec, k, Lam, A, c->swlo, c->sw64, b.Y, b.T, st);
     CHECK_LAUNCH();
     if (time_it) HIPCHK(hipEventRecord(c->ev[3], st));
     if (c->P.method == FETI_DP && c->P.n_cg > 0) {
-        launch_coarse(t, k, f32, c->Tbuf, nullptr, c->Kcc_inv, 1.0, c->vbuf, c->tcbuf, st);
-        launch_scatter_fold(t, k, f32, c->Ybuf, c->vbuf, Q, st);
+        launch_coarse(t, k, f32, b.T, nullptr, c->Kcc_inv, 1.0, b.v, b.tc, st);
+        launch_scatter_fold(t, k, f32, b.Y, b.v, Q, st);
     } else {
-        launch_scatter(t, k, f32, c->Ybuf, Q, st);
+        launch_scatter(t, k, f32, b.Y, Q, st);
     }
     CHECK_LAUNCH();
+}
+
+void apply_F(feti_ctx* c, int k, int prec, const double* Lam, double* Q, bool time_it = false, bool pure = false) {
+    apply_F_with(c, k, prec, Lam, Q, FlBufs{c->Ybuf, c->Tbuf, c->vbuf, c->tcbuf}, time_it, pure);
 }
 
 // body() as a captured graph replayed on c->st (opts.graphs and a non-null stream), captured on
@@ -1937,6 +2000,8 @@ feti_status guarded(F&& fn) {
         return fail(FETI_ENOMEM, "host allocation failed");
     } catch (const std::length_error& e) {
         return fail(FETI_ENOMEM, e.what());
+    } catch (const std::logic_error& e) {
+        return fail(FETI_EINVAL, e.what());
     } catch (const std::runtime_error& e) {
         return fail(FETI_ENOTSPD, e.what());
     }
@@ -2287,6 +2352,25 @@ feti_status feti_apply_F(feti_ctx* c, int k, int precision, const double* Lambda
         HIPCHK(hipEventElapsedTime(&b, c->ev[0], c->ev[1]));
         c->last_ms[0] = a;
         c->last_ms[1] = b;
+        return FETI_OK;
+    });
+}
+
+feti_status feti_apply_F_noalloc(feti_ctx* c, int k, int precision, const double* Lambda, double* Q) {
+    if (!c || !Lambda || !Q) return fail(FETI_EINVAL, "null argument");
+    if (k < 1 || k > kMaxDirs) return fail(FETI_EINVAL, "k must lie in [1, 64]");
+    const bool pure = (precision & FETI_PURE) != 0;
+    precision &= ~FETI_PURE;
+    if (precision != FETI_FP64 && precision != FETI_FP32 && precision != FETI_BF16X3)
+        return fail(FETI_EINVAL, "unknown precision");
+    const long long need = fl_bufs_bytes(c->t, k);
+    if (need > kNoAllocScratchBytes)
+        return fail(FETI_EINVAL, "feti_apply_F_noalloc: the workspace of this F*Lambda needs " + std::to_string(need) +
+                                     " bytes, more than the fixed " + std::to_string(kNoAllocScratchBytes) +
+                                     " (use feti_apply_F or fewer columns)");
+    if (!c->scratch) return fail(FETI_EHIP, "no-allocation workspace address not set up");
+    return guarded([&]() -> feti_status {
+        apply_F_with(c, k, precision, Lambda, Q, fl_bufs_in(c->t, k, c->scratch), false, pure);
         return FETI_OK;
     });
 }

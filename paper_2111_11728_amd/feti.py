@@ -109,6 +109,7 @@ def lib():
             "feti_last_error": (C.c_char_p, []),
             "feti_get_sizes": (I, [P, C.POINTER(feti_sizes)]),
             "feti_apply_F": (I, [P, I, I, P, P]),
+            "feti_apply_F_noalloc": (I, [P, I, I, P, P]),
             "feti_apply_precond": (I, [P, P, P, I]),
             "feti_project": (I, [P, I, P]),
             "feti_rhs": (I, [P, P, P, P]),
@@ -267,6 +268,10 @@ class Context:
     def feti_apply_F(self, k, precision, Lam, Q, pure=False):
         p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)
         _check(lib().feti_apply_F(self.handle, k, p, _ptr(Lam), _ptr(Q)))
+
+    def feti_apply_F_noalloc(self, k, precision, Lam, Q, pure=False):
+        p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)
+        _check(lib().feti_apply_F_noalloc(self.handle, k, p, _ptr(Lam), _ptr(Q)))
 
     def feti_apply_precond(self, r, Z, one_column):
         _check(lib().feti_apply_precond(self.handle, _ptr(r), _ptr(Z), int(one_column)))
