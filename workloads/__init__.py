@@ -40,6 +40,7 @@ class Problem:
     p: float = 3.0
     name: str = ""
     groups: Optional[tuple] = None  # S-FETI direction groups: subdomain blocks per axis (None = one per subdomain)
+    traction: Optional[tuple] = None  # uniform traction (tx, ty) on the edge x = nx instead of the point load
 
     @property
     def dpn(self) -> int:
@@ -69,6 +70,8 @@ class Problem:
         return clamped_dofs(self.dim, self.nel)
 
     def load(self) -> np.ndarray:
+        if self.traction is not None:
+            return edge_traction(self.nel, self.traction)
         return point_load(self.dim, self.nel)
 
 
@@ -98,6 +101,19 @@ def point_load(dim: int, nel: Sequence[int]) -> np.ndarray:
     return f
 
 
+def edge_traction(nel: Sequence[int], t: Sequence[float]) -> np.ndarray:
+    """2D: nodal forces of a uniform traction t = (tx, ty) per unit length on the edge x = nx
+    (unit element edges: end nodes carry half an edge, the others a whole one)."""
+    nn = [n + 1 for n in nel]
+    f = np.zeros(2 * nn[0] * nn[1])
+    for iy in range(nn[1]):
+        node = nel[0] + nn[0] * iy
+        w = 0.5 if iy in (0, nel[1]) else 1.0
+        f[2 * node] = w * t[0]
+        f[2 * node + 1] = w * t[1]
+    return f
+
+
 def _module_rho(rng, nsub, m, dim, solid_fraction=0.5):
     """Modular 0/1 design: every subdomain (module of m^dim elements) gets exactly
     round(solid_fraction * m^dim) solid elements chosen by a seeded permutation."""
@@ -112,6 +128,26 @@ def _module_rho(rng, nsub, m, dim, solid_fraction=0.5):
         sl = tuple(slice(k * m, (k + 1) * m) for k in sidx)
         rho[sl] = pat
     return rho.ravel()
+
+
+def modular_types_2d(seed: int = 0, nsub=(8, 4), m: int = 16, n_types: int = 4, Emin: float = 1e-6) -> Problem:
+    """2D modular design built from n_types module types (Sec. 1: a modular structure repeats a few
+    module designs): every type is a seeded 0/1 pattern at solid fraction 0.5, and every subdomain
+    takes a seeded type."""
+    rng = np.random.default_rng(seed)
+    n_mod = m * m
+    types = []
+    for _ in range(n_types):
+        pat = np.zeros(n_mod)
+        pat[rng.permutation(n_mod)[:n_mod // 2]] = 1.0
+        types.append(pat.reshape(m, m))
+    rho = np.zeros((nsub[1] * m, nsub[0] * m))
+    for sy in range(nsub[1]):
+        for sx in range(nsub[0]):
+            rho[sy * m:(sy + 1) * m, sx * m:(sx + 1) * m] = types[int(rng.integers(n_types))]
+    nel = (nsub[0] * m, nsub[1] * m)
+    return Problem(2, nel, tuple(uniform_cuts(n, s) for n, s in zip(nel, nsub)), rho.ravel(), Emin=Emin,
+                   name=f"modular_types2d_{nsub[0]}x{nsub[1]}_of_{m}_{n_types}types")
 
 
 def cantilever_tfeti(seed: int = 0, nsub=(4, 2), m: int = 8) -> Problem:
@@ -182,6 +218,58 @@ def uneven_design(seed: int, d: int, g=(4, 8), w=(16, 48)) -> Problem:
             rho[cy[jy]:cy[jy + 1], cx[jx]:cx[jx + 1]] = pat.reshape(h, w)
     return Problem(2, nel, (tuple(cx), tuple(cy)), rho.ravel(), Emin=1e-6,
                    name=f"uneven2d_seed{seed}_d{d}")
+
+
+# ---- academic problems (Sec. 4.1): two materials, stiff (rho = 1, E0) and compliant (rho = 0,
+# Emin), clamped on the left edge, uniform tensile and tangential traction (1, -1) on the right
+# edge. The paper gives neither the material contrast nor the layer geometry beyond its figure
+# captions; the contrast here is Emin / E0 = 1e-4, with 14 x 14 (layers) or 16 x 16 (inclusion)
+# elements per subdomain.
+
+def _layers(m: int, n_layers: int, horizontal: bool) -> np.ndarray:
+    """m x m module of n_layers alternating layers (stiff first), rows y, columns x."""
+    if m % n_layers:
+        raise ValueError("the module size must be a multiple of the layer count")
+    k = (np.arange(m) // (m // n_layers)) % 2 == 0
+    return np.tile(k[:, None], (1, m)).astype(float) if horizontal else np.tile(k[None, :], (m, 1)).astype(float)
+
+
+def laminated_beam(nsub: int = 9, m: int = 14, n_layers: int = 7, Emin: float = 1e-4) -> Problem:
+    """Laminated beam: a row of nsub square subdomains, each of n_layers horizontal layers
+    alternating stiff and compliant, continuous from one subdomain to the next (no cross-points)."""
+    mod = _layers(m, n_layers, True)
+    rho = np.tile(mod, (1, nsub))
+    nel = (nsub * m, m)
+    return Problem(2, nel, (tuple(uniform_cuts(nel[0], nsub)), (0, m)), rho.ravel(), Emin=Emin,
+                   name=f"laminated_beam_{nsub}_of_{m}", traction=(1.0, -1.0))
+
+
+def layered_grid(nsub=(3, 3), m: int = 14, n_layers: int = 7, Emin: float = 1e-4) -> Problem:
+    """Grid of layered subdomains (n_layers alternating layers each) whose layer direction
+    alternates in a checkerboard (horizontal where sx + sy is even, vertical otherwise), so the
+    stiffness met at interface nodes and cross-points differs from one subdomain to the next."""
+    rho = np.zeros((nsub[1] * m, nsub[0] * m))
+    for sy in range(nsub[1]):
+        for sx in range(nsub[0]):
+            rho[sy * m:(sy + 1) * m, sx * m:(sx + 1) * m] = _layers(m, n_layers, (sx + sy) % 2 == 0)
+    nel = (nsub[0] * m, nsub[1] * m)
+    return Problem(2, nel, tuple(uniform_cuts(n, s) for n, s in zip(nel, nsub)), rho.ravel(), Emin=Emin,
+                   name=f"layered_grid_{nsub[0]}x{nsub[1]}_of_{m}", traction=(1.0, -1.0))
+
+
+def inclusion_grid(nsub=(4, 4), m: int = 16, Emin: float = 1e-4) -> Problem:
+    """Grid of compliant subdomains, each with one stiff square inclusion of m/2 x m/2 elements at
+    its centre: the material on every interface is the compliant one."""
+    mod = np.zeros((m, m))
+    a = m // 4
+    mod[a:m - a, a:m - a] = 1.0
+    rho = np.tile(mod, (nsub[1], nsub[0]))
+    nel = (nsub[0] * m, nsub[1] * m)
+    return Problem(2, nel, tuple(uniform_cuts(n, s) for n, s in zip(nel, nsub)), rho.ravel(), Emin=Emin,
+                   name=f"inclusion_grid_{nsub[0]}x{nsub[1]}_of_{m}", traction=(1.0, -1.0))
+
+
+ACADEMIC = {"laminated_beam": laminated_beam, "layered_grid": layered_grid, "inclusion_grid": inclusion_grid}
 
 
 def group_shape(nsub, n_dirs):
