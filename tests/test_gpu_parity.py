@@ -185,7 +185,7 @@ def test_apply_F_fp64_well_conditioned(name, method, k):
     prob.rho = np.ones_like(prob.rho)
     precond = "dirichlet" if method == "fetidp" else "lumped"
     op = (ofeti.FETIDP if method == "fetidp" else ofeti.TFETI)(prob, precond, "k")
-    assert _tol_fp64(op) < 1e-11
+    assert _tol_fp64(op) <= 1e-11   # the conditioning bound stays at its floor
     print(f"case well-conditioned {name} {method} k={k}", flush=True)
     ctx = _ctx(prob, method=method, scaling="k", precond=precond)
     L = np.random.default_rng(k + 17).standard_normal((op.n_lambda, k))
