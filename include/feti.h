@@ -70,6 +70,12 @@ typedef struct {
                                  NULL = uniform (nel[a] must then be divisible by nsub[a]) */
     int group[3];             /* S-FETI: subdomain blocks per axis forming one direction
                                  (0 or all 1 = one direction per subdomain) */
+    int n_primal;             /* FETI-DP: nodes enforced in primal variables besides the corners
+                                 (Sec. 2.2 Eq. 8-9 with the primal set enlarged as in Sec. 6, item i);
+                                 0 = corners only */
+    const int* primal_nodes;  /* host: n_primal global node numbers, each shared by two or more
+                                 subdomains and carrying a free DOF (FETI_EINVAL otherwise); at
+                                 most 32 primal DOFs per subdomain */
 } feti_partition;
 
 typedef struct {
@@ -112,6 +118,17 @@ typedef struct {
                                  sqrt(kappa(F)) in the F-inner product, so on strongly
                                  heterogeneous designs it stalls the reduced pass and the solve
                                  ends in FP64. 0 (default): FP64 on every iteration. */
+    int warm_start;           /* 1 = a solve without lambda_init starts from the multipliers of the
+                                 context's last solve, made feasible for the new load (lambda_0 +
+                                 P lambda_prev; FETI-DP: lambda_prev), e.g. across the design
+                                 iterations of a SIMP loop; its tolerance stays relative to the
+                                 residual of the cold start lambda_0. Single design only; 0 = off */
+    int recycle;              /* 1 = factorisation recycling over module types (Sec. 1; Sec. 2.1): at
+                                 every setup, subdomains with the same local layout and bit-identical
+                                 densities are found (a device hash per subdomain, then an element-by-
+                                 element check) and only one of each group is factorised and gets its
+                                 local operators, which the others then use. Results are bit-identical
+                                 to a setup without recycling. Single design only; 0 = off */
 } feti_opts;
 
 typedef struct {
@@ -146,6 +163,8 @@ typedef struct {
     int n_designs;            /* independent designs held by the context (1 unless batched) */
     long long sum_nb2_fp64;   /* sum of n_b^2 over the subdomains counted by n_fp64_subs (their F_s
                                  products run on the FP64 matrix cores inside a reduced-precision solve) */
+    int n_setup_subs;         /* subdomains factorised at the last setup (n_sub unless opts.recycle
+                                 found repeated module types) */
 } feti_sizes;
 
 /* One design of a batched context: its ranges in the concatenated arrays. */
@@ -161,6 +180,20 @@ typedef struct {
  * Host-only; usable without a GPU. */
 feti_status feti_plan_sizes(const feti_mesh* mesh, const feti_partition* part,
                             const feti_opts* opts, feti_sizes* out);
+
+/* Host-only: an adaptive choice of further FETI-DP primal nodes (Sec. 6, item i: compatibility
+ * enforced in primal variables at nodes other than the corners), to pass in
+ * feti_partition.primal_nodes. 2D: along every edge shared by two subdomains (its end vertices
+ * excluded), a node's stiffness is the sum of the moduli Emin + rho_e^p (E0 - Emin) of its
+ * elements (Sec. 1, Eq. 1), in lexicographic element order; the nodes whose stiffness is at least
+ * theta times the edge's largest form runs of consecutive nodes, and the cap runs of largest total
+ * stiffness (the earlier run on ties) each give their middle node ((first + last) / 2), unless it
+ * carries no free DOF. 3D: no nodes. rho: host [n_el]. nodes: host, capacity nodes_cap, sorted
+ * global node numbers (may be NULL to query the count in *n_out). cap <= 3 keeps a 2D subdomain
+ * within the 32 primal DOFs of feti_partition. */
+feti_status feti_adaptive_primal(const feti_mesh* mesh, const feti_partition* part, const double* rho, double p,
+                                 double E0, double Emin, double theta, int cap, int* nodes, int nodes_cap,
+                                 int* n_out);
 
 /* Host-only export of the topology, for checking it against an independent
  * construction. what: 0 = per lambda row [side0 subdomain, side0 local DOF, side0 sign,
@@ -202,15 +235,19 @@ typedef struct {
     int max_d;                /* FP64 row blocks per tile, 1..16 */
     int xcd;                  /* 1: the tiles of one subdomain are placed on one XCD (shared L2) */
     int split_d;              /* FP64 row blocks per split-contraction tile (hybrid precision,
-                                 subdomains that failed the round-off test), 1..4 */
+                                 subdomains that failed the round-off test), 1..4; 0 = no split
+                                 contraction: plain FP64 tiles of up to max_d row blocks */
     double us;                /* in-solve F*Lambda kernel time with these shapes, microseconds */
     double us_default;        /* the same with the default shapes (32, 16, 1, 4) */
     int from_cache;           /* 1: read from the cache file, not timed */
+    int fp64_first;           /* hybrid lists: 1 = the FP64 tiles of the subdomains that failed the
+                                 round-off test lead the launch, 0 = they follow the reduced tiles */
 } feti_tuning;
 
 /* Autotuner of the F*Lambda tile shapes: times the context's in-solve F*Lambda (k = 64 columns,
  * the context's precision, hybrid lists included) over reps launches for every candidate in
- * max_red {32, 16} x max_d {16, 14, 12, 10, 8, 4} x xcd {1, 0} x split_d {4, 2}, keeps the fastest (a
+ * max_red {32, 16} x max_d {16, 14, 12, 10, 8, 4} x xcd {1, 0} x split_d {4, 2} (hybrid lists:
+ * split_d {4, 2, 1, 0} x fp64_first {0, 1}), keeps the fastest (a
  * change from the defaults must gain 2%) and applies it to every tile list of the context. cache_path (host string, optional): a JSON
  * file of earlier results keyed by (subdomains, n_b bucket of 32, precision, hybrid); a hit is
  * applied without timing, a miss is timed and written back. out: host, optional. Results of
@@ -252,6 +289,25 @@ feti_status feti_solve(feti_ctx* ctx, const double* f, double* u, const double* 
  * (reuse the last load); c: device scalar; dc_drho: device [n_el]; u: device [n_dof] or NULL. */
 feti_status feti_compliance_and_grad(feti_ctx* ctx, const double* rho, const double* f,
                                      double* c, double* dc_drho, double* u, feti_info* info);
+
+/* The Lagrange multipliers lambda of the context's last solve (Sec. 2: the interface forces),
+ * for a later warm start (feti_solve's lambda_init). lambda: device [n_lambda] output. FETI_EINVAL
+ * before the first solve. */
+feti_status feti_get_lambda(feti_ctx* ctx, double* lambda);
+
+/* One design update of the SIMP problem of Sec. 1 (minimum compliance c(rho) = f^T u under a bound
+ * on the material volume, unit element volumes) by optimality criteria: with B_e(L) =
+ * max(0, -dc_e) / L,
+ *     rho_new_e = min(min(1, rho_e + move), max(max(rho_min, rho_e - move), rho_e B_e(L)^eta)),
+ * and the multiplier L > 0 chosen so that sum_e rho_new_e = volfrac * n_el: the volume is
+ * non-increasing in L, which is bracketed by 0 and max|dc| (doubled until the volume there is at
+ * most the target) and bisected to a relative width of 1e-14 on per-workgroup partial volumes
+ * summed on the host in a fixed order. rho, dc: device [n_el] (dc from feti_compliance_and_grad);
+ * rho_new: device [n_el] output (may alias neither input); lagrange: host, optional, receives L.
+ * Single-design contexts; needs 0 <= rho_min < volfrac <= 1, move > 0, eta > 0 (FETI_EINVAL
+ * otherwise). Synchronises the context's stream once per bisection step. */
+feti_status feti_oc_update(feti_ctx* ctx, const double* rho, const double* dc, double volfrac, double move,
+                           double eta, double rho_min, double* rho_new, double* lagrange);
 
 feti_status feti_destroy(feti_ctx* ctx);
 

@@ -190,9 +190,9 @@ class TFETI(_Common):
 class FETIDP(_Common):
     """FETI-DP operators (Sec. 2.2) with u_c condensed out."""
 
-    def __init__(self, prob, precond="dirichlet", scaling="mult"):
+    def __init__(self, prob, precond="dirichlet", scaling="mult", primal_nodes=None):
         self.prob = prob
-        self.dec = topology.decompose(prob)
+        self.dec = topology.decompose(prob, primal_nodes)
         self.split, self.cons = topology.fetidp_split(self.dec)
         E = fem.simp_modulus(prob.rho, prob.p, prob.E0, prob.Emin)
         K0 = fem.element_stiffness(prob.dim, prob.nu)

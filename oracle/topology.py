@@ -23,6 +23,7 @@ gluing row the lower-numbered subdomain carries +1, the other -1.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -65,7 +66,66 @@ def subdomain_grid_index(prob, s):
     return idx
 
 
-def decompose(prob) -> Decomposition:
+def adaptive_primal_nodes(prob, theta=0.2, cap=3):
+    """Adaptive choice of further primal nodes for FETI-DP (the paper's Sec. 6, item i: nodes
+    other than the corners whose compatibility is enforced in primal variables). 2D only (3D: no
+    further nodes). A node's stiffness is the sum of the Young moduli E_e = Emin + rho_e^p (E0 -
+    Emin) of the elements containing it, taken in lexicographic element order. Along every edge
+    shared by two subdomains (its end vertices excluded), the nodes whose stiffness is at least
+    theta times the edge's largest form runs of consecutive nodes; the cap runs of largest total
+    stiffness (earlier run first on ties) each contribute their middle node ((first + last) // 2),
+    unless that node carries no free DOF. Returns the sorted global node numbers."""
+    if prob.dim != 2:
+        return np.zeros(0, dtype=np.int64)
+    nx, ny = prob.nel
+    # libm pow per element, so that the threshold decisions are taken on the same values as in any
+    # other implementation that calls it
+    E = [prob.Emin + math.pow(float(r), prob.p) * (prob.E0 - prob.Emin) for r in prob.rho]
+
+    def stiffness(x, y):
+        k = 0.0
+        for ey in (y - 1, y):
+            for ex in (x - 1, x):
+                if 0 <= ex < nx and 0 <= ey < ny:
+                    k += E[ex + nx * ey]
+        return k
+
+    fixed = np.zeros(prob.n_dof, dtype=bool)
+    fixed[prob.fixed_dofs()] = True
+    cx, cy = prob.cuts
+    edges = []
+    for i in range(1, len(cx) - 1):
+        for j in range(len(cy) - 1):
+            edges.append([(cx[i], y) for y in range(cy[j] + 1, cy[j + 1])])
+    for j in range(1, len(cy) - 1):
+        for i in range(len(cx) - 1):
+            edges.append([(x, cy[j]) for x in range(cx[i] + 1, cx[i + 1])])
+    out = set()
+    for e in edges:
+        if not e:
+            continue
+        k = [stiffness(x, y) for (x, y) in e]
+        kmax = max(k)
+        if not kmax > 0.0:
+            continue
+        runs, a = [], None
+        for t in range(len(e) + 1):
+            stiff = t < len(e) and k[t] >= theta * kmax
+            if stiff and a is None:
+                a = t
+            elif not stiff and a is not None:
+                runs.append((a, t - 1, sum(k[a:t])))
+                a = None
+        runs.sort(key=lambda r: (-r[2], r[0]))
+        for a, b, _ in runs[:cap]:
+            x, y = e[(a + b) // 2]
+            nd = x + (nx + 1) * y
+            if not (fixed[2 * nd] and fixed[2 * nd + 1]):
+                out.add(nd)
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def decompose(prob, primal_nodes=None) -> Decomposition:
     dim, nel, cuts = prob.dim, prob.nel, prob.cuts
     nn = fem.node_shape(nel)
     strides = [int(np.prod(nn[:d])) for d in range(dim)]
@@ -115,6 +175,12 @@ def decompose(prob) -> Decomposition:
         if all(coord[a] in cut_sets[a] for a in range(dim)):
             if not all(fixed[dim * nd + c] for c in range(dim)):
                 corner[nd] = True
+    # further primal nodes (FETI-DP with an enlarged primal set): shared, with a free DOF
+    for nd in ([] if primal_nodes is None else primal_nodes):
+        nd = int(nd)
+        if nd not in node_subs or all(fixed[dim * nd + c] for c in range(dim)):
+            raise ValueError(f"primal node {nd} is not a shared node with a free DOF")
+        corner[nd] = True
     return Decomposition(prob, subs, node_subs, fixed, corner, g2l, fixed_node_subs)
 
 

@@ -177,7 +177,26 @@ struct feti_ctx {
             *gs = GraphSlot{};
         }
     }
+    // module types (opts.recycle): subdomains with the same local layout (structural key) and the
+    // same densities share one setup; rep_of[s] is the subdomain whose operators s uses
+    std::vector<unsigned long long> skey;
+    std::vector<int> rep_of;
+    std::vector<SubMeta> hsubs_act;   // what t.subs holds: operator offsets of each representative
+    int n_setup_subs = 0;
+    bool aliased = false;
+    SubMeta* subs_dev = nullptr;      // t.subs, writable
+    SubMeta* subs_rep = nullptr;      // representatives' own SubMeta, compacted
+    GemmDesc *d_syrk_r = nullptr, *d_F_r = nullptr;
+    PotrfDesc* d_potrf_r = nullptr;
+    TrsmDesc* d_trsm_r = nullptr;
+    std::vector<GemmDesc> h_dsy, h_dF;
+    std::vector<PotrfDesc> h_dpo;
+    std::vector<TrsmDesc> h_dtr;
+    unsigned long long* hash_dev = nullptr;
+    int *pair_dev = nullptr, *flag_dev = nullptr, *map_dev = nullptr;
+    double* rbm_tmp = nullptr;        // compacted Total FETI per-subdomain results before expansion
     void* scratch = nullptr;   // this device's no-allocation workspace (scratch_address)
+    bool have_lam = false;     // lam_prev holds the multipliers of the last solve (warm start)
     FlTile *fl64_dev = nullptr, *flred_dev = nullptr;
     int fl64_cap = 0, flred_cap = 0;
     std::vector<CoarseBlk> hcblk;
@@ -197,7 +216,7 @@ struct feti_ctx {
     // solve buffers
     double *f_last = nullptr, *fi = nullptr, *fbeta = nullptr, *h = nullptr, *g = nullptr, *yb = nullptr,
            *yc = nullptr, *fbar_s = nullptr, *d = nullptr, *lam0 = nullptr, *lam = nullptr, *lt = nullptr,
-           *lt2 = nullptr, *r = nullptr, *xb = nullptr, *ubeta = nullptr, *ui = nullptr, *uloc = nullptr, *uc = nullptr,
+           *lt2 = nullptr, *lam_prev = nullptr, *r = nullptr, *xb = nullptr, *ubeta = nullptr, *ui = nullptr, *uloc = nullptr, *uc = nullptr,
            *alpha = nullptr, *e = nullptr, *GY = nullptr, *tcoef = nullptr, *u_int = nullptr;
     double *Ybuf = nullptr, *Tbuf = nullptr, *vbuf = nullptr, *Qtmp = nullptr, *Tsum = nullptr;
     double *Zk = nullptr, *Qk = nullptr, *Delta = nullptr, *Tm = nullptr, *gam = nullptr, *part = nullptr,
@@ -396,9 +415,15 @@ void build_fl_tiles(feti_ctx* c) {
         }
         // one launch: the FP64 split-contraction tiles follow the reduced ones and fill the CUs
         // those leave free (the kernel dispatches a tile by its flags, whatever the precision)
+        // (split_d = 0: the failed subdomains as plain FP64 tiles of up to max_d row blocks, one per
+        // wavefront; fp64_first: their tiles lead the launch instead of following it)
         std::vector<FlTile> hyb = pack_tiles(rr, ld, kFlNoT, q.max_d, q.xcd != 0, q.max_red);
-        const std::vector<FlTile> h64 = pack_tiles(rd, ld, kFlSplitK, q.split_d, false);
-        hyb.insert(hyb.end(), h64.begin(), h64.end());
+        const std::vector<FlTile> h64 =
+            q.split_d > 0 ? pack_tiles(rd, ld, kFlSplitK, q.split_d, false) : pack_tiles(rd, ld, 0, q.max_d, false);
+        if (q.fp64_first)
+            hyb.insert(hyb.begin(), h64.begin(), h64.end());
+        else
+            hyb.insert(hyb.end(), h64.begin(), h64.end());
         put(hyb, c->fl_hyb_dev, c->fl_hyb_cap, c->fl_hyb);
     }
     HIPCHK(hipStreamSynchronize(c->st));
@@ -630,6 +655,46 @@ void build_layout(feti_ctx* c) {
     c->d_F = c->upload(dF);
     c->d_potrf = c->upload(dpo);
     c->d_trsm = c->upload(dtr);
+    c->rep_of.resize(ns);
+    for (int s = 0; s < ns; ++s) c->rep_of[s] = s;
+    c->n_setup_subs = ns;
+    if (c->opts.recycle && c->designs.size() == 1) {
+        c->h_dsy = dsy;
+        c->h_dF = dF;
+        c->h_dpo = dpo;
+        c->h_dtr = dtr;
+        c->d_syrk_r = c->alloc<GemmDesc>(ns);
+        c->d_F_r = c->alloc<GemmDesc>(ns);
+        c->d_potrf_r = c->alloc<PotrfDesc>(ns);
+        c->d_trsm_r = c->alloc<TrsmDesc>(ns);
+        c->subs_rep = c->alloc<SubMeta>(ns);
+        c->hash_dev = c->alloc<unsigned long long>(ns);
+        c->pair_dev = c->alloc<int>(2LL * ns);
+        c->flag_dev = c->alloc<int>(ns);
+        c->map_dev = c->alloc<int>(ns);
+        c->rbm_tmp = c->alloc<double>(37LL * ns);
+        // structural key: local grid, class sizes and the class and class index of every local
+        // DOF (which fixes the interface order, the line blocks and the corner set)
+        c->skey.assign(ns, 0);
+        for (int s = 0; s < ns; ++s) {
+            unsigned long long h = 1469598103934665603ull;
+            auto put = [&](long long v) {
+                h ^= (unsigned long long)v;
+                h *= 1099511628211ull;
+            };
+            for (int a = 0; a < 3; ++a) put(P.nn[3 * s + a]);
+            put(P.n_loc[s]);
+            put(P.n_i[s]);
+            put(P.n_b[s]);
+            put(P.n_c[s]);
+            put(P.band[s]);
+            for (long long q = P.off_loc[s]; q < P.off_loc[s + 1]; ++q) {
+                put(P.lcls[q]);
+                put(P.lidx[q]);
+            }
+            c->skey[s] = h;
+        }
+    }
     const int nsmall = std::max(ncg, na);
     c->d_one = c->upload(std::vector<GemmDesc>{GemmDesc{0, 0, 0, nsmall, nsmall, nsmall, nsmall, nsmall, nsmall}});
     c->d_potrf_one = c->upload(std::vector<PotrfDesc>{PotrfDesc{0, nsmall, nsmall}});
@@ -640,7 +705,9 @@ void build_layout(feti_ctx* c) {
     std::vector<int> bq_s(t.nb_tot);
     for (int s = 0; s < ns; ++s)
         for (long long q = P.off_b[s]; q < P.off_b[s + 1]; ++q) bq_s[q] = s;
-    t.subs = c->upload(c->hsubs);
+    c->subs_dev = c->upload(c->hsubs);
+    t.subs = c->subs_dev;
+    c->hsubs_act = c->hsubs;
     t.lines = c->upload(c->hlines);
     t.lcls = c->upload(P.lcls);
     t.lidx = c->upload(P.lidx);
@@ -654,12 +721,10 @@ void build_layout(feti_ctx* c) {
     t.row_s = c->upload(P.row_s);
     t.row_j = c->upload(P.row_j);
     t.row_sg = c->upload(P.row_sg);
-    {   // absolute Y row of each (row, side): the scatter's loads need no subdomain lookup
-        std::vector<long long> yo(P.row_s.size());
-        for (size_t e = 0; e < yo.size(); ++e)
-            yo[e] = P.row_s[e] >= 0 ? c->hsubs[P.row_s[e]].off_b + P.row_j[e] : -1;
-        t.row_yo = c->upload(yo);
-    }
+    // absolute Y row of each (row, side): the scatter's loads need no subdomain lookup
+    std::vector<long long> yo(P.row_s.size());
+    for (size_t e = 0; e < yo.size(); ++e) yo[e] = P.row_s[e] >= 0 ? c->hsubs[P.row_s[e]].off_b + P.row_j[e] : -1;
+    t.row_yo = c->upload(yo);
     if (P.method == FETI_DP && P.n_cg > 0 && P.n_lambda > 0) {
         // coarse fold entries of every lambda row (values follow at each setup: launch_fold_rows)
         int W = 0;
@@ -685,6 +750,50 @@ void build_layout(feti_ctx* c) {
         t.fr_n = c->upload(fn);
         t.fr_col = c->upload(fc);
         t.fr_val = c->alloc<double>((long long)P.n_lambda * W);
+        // rows grouped by their pair of subdomains: each group's corner DOFs (the union over both
+        // sides) are staged once, and fr_pos places every fold entry in that union
+        std::map<std::pair<int, int>, std::vector<int>> groups;
+        for (int r = 0; r < P.n_lambda; ++r) groups[{P.row_s[2 * r], P.row_s[2 * r + 1]}].push_back(r);
+        std::vector<int> pr_ptr{0}, pr_rows, pu_ptr{0}, pu_cg, fpos((size_t)P.n_lambda * W, 0), pfn, ipos(P.n_lambda);
+        std::vector<long long> pyo;
+        std::vector<int8_t> psg;
+        int maxu = 0;
+        for (auto& g : groups) {
+            std::vector<int> U;
+            for (int r : g.second)
+                for (int e = 0; e < fn[r]; ++e) U.push_back(fc[(size_t)r * W + e]);
+            std::sort(U.begin(), U.end());
+            U.erase(std::unique(U.begin(), U.end()), U.end());
+            maxu = std::max(maxu, (int)U.size());
+            for (int r : g.second) {
+                const size_t i = pr_rows.size();
+                ipos[r] = (int)i;
+                pr_rows.push_back(r);
+                pfn.push_back(fn[r]);
+                for (int t2 = 0; t2 < 2; ++t2) {
+                    pyo.push_back(yo[2 * (size_t)r + t2]);
+                    psg.push_back(P.row_sg[2 * (size_t)r + t2]);
+                }
+                for (int e = 0; e < fn[r]; ++e)
+                    fpos[i * W + e] = (int)(std::lower_bound(U.begin(), U.end(), fc[(size_t)r * W + e]) - U.begin());
+            }
+            pr_ptr.push_back((int)pr_rows.size());
+            pu_cg.insert(pu_cg.end(), U.begin(), U.end());
+            pu_ptr.push_back((int)pu_cg.size());
+        }
+        if (maxu <= kFoldPairMaxU) {
+            t.n_pairs = (int)groups.size();
+            t.pr_ptr = c->upload(pr_ptr);
+            t.pr_rows = c->upload(pr_rows);
+            t.pu_ptr = c->upload(pu_ptr);
+            t.pu_cg = c->upload(pu_cg);
+            t.fr_pos = c->upload(fpos);
+            t.pr_yo = c->upload(pyo);
+            t.pr_sg = c->upload(psg);
+            t.pr_fn = c->upload(pfn);
+            t.pr_ipos = c->upload(ipos);
+            t.pr_fval = c->alloc<double>((long long)P.n_lambda * W);
+        }
     }
     t.row_sh = c->upload(P.row_sh);
     t.sh_ptr = c->upload(P.sh_ptr);
@@ -786,6 +895,7 @@ void build_layout(feti_ctx* c) {
     c->lam = c->alloc<double>(nl);
     c->lt = c->alloc<double>(nl);
     c->lt2 = c->alloc<double>(nl);
+    c->lam_prev = c->alloc<double>(nl);
     c->r = c->alloc<double>(nl);
     c->zv = c->alloc<double>(nl);
     c->tmpv = c->alloc<double>(nl);
@@ -833,29 +943,32 @@ void check_info(feti_ctx* c, int n, const char* what);
 // rounding to the context's precision in FP64; a subdomain keeps the reduced precision only
 // if every Cholesky pivot agrees to 2 percent (otherwise rounding has reached the smallest
 // eigenvalues of F_s and its tiles run in FP64).
-void classify_precision(feti_ctx* c) {
-    DevTopo& t = c->t;
+// ts / dpo: the subdomains set up (all, or the representatives of the module types); ci[s]:
+// the position in ts of subdomain s's representative.
+void classify_precision(feti_ctx* c, const DevTopo& ts, const PotrfDesc* dpo, const std::vector<int>& ci) {
+    const DevTopo& t = c->t;
     hipStream_t st = c->st;
     c->hybrid = false;
     c->n_fp64_subs = 0;
     if (c->opts.precision == FETI_FP64 || c->P.method != FETI_DP) return;
-    launch_copy_F_rounded(t, c->F64, FETI_FP64, c->W1, st);
-    launch_copy_F_rounded(t, c->F64, c->opts.precision, c->W2, st);
+    const int nr = ts.n_sub;
+    launch_copy_F_rounded(ts, c->F64, FETI_FP64, c->W1, st);
+    launch_copy_F_rounded(ts, c->F64, c->opts.precision, c->W2, st);
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * (t.n_sub + 8), st));
-    launch_potrf(c->d_potrf, t.n_sub, t.max_nb, c->W1, c->info, st);
+    launch_potrf(dpo, nr, t.max_nb, c->W1, c->info, st);
     CHECK_LAUNCH();
-    check_info(c, t.n_sub, "Cholesky of F_s");
+    check_info(c, nr, "Cholesky of F_s");
     HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * (t.n_sub + 8), st));
-    launch_potrf(c->d_potrf, t.n_sub, t.max_nb, c->W2, c->info, st);
-    launch_pivot_compare(t, c->W1, c->W2, c->info, c->pivdev, st);
+    launch_potrf(dpo, nr, t.max_nb, c->W2, c->info, st);
+    launch_pivot_compare(ts, c->W1, c->W2, c->info, c->pivdev, st);
     CHECK_LAUNCH();
-    std::vector<double> dev(t.n_sub);
-    HIPCHK(hipMemcpyAsync(dev.data(), c->pivdev, sizeof(double) * t.n_sub, hipMemcpyDeviceToHost, st));
+    std::vector<double> dev(nr);
+    HIPCHK(hipMemcpyAsync(dev.data(), c->pivdev, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     std::vector<int>& ok = c->sub_ok;
     ok.assign(t.n_sub, 0);
     for (int s = 0; s < t.n_sub; ++s) {
-        ok[s] = dev[s] <= 2e-2 ? 1 : 0;
+        ok[s] = dev[ci[s]] <= 2e-2 ? 1 : 0;
         c->n_fp64_subs += 1 - ok[s];
     }
     if (verbose()) {
@@ -938,6 +1051,51 @@ void coarse_inverse(feti_ctx* c) {
     HIPCHK(hipMemcpyAsync(c->Kcc_inv, c->Kcc_w, sizeof(double) * sz, hipMemcpyDeviceToDevice, st));
 }
 
+// Module types (opts.recycle, single design): subdomains with the same structural key and the
+// same densities share their factorisation and local operators, as the paper's modular designs
+// recycle one factorisation per module type (Sec. 1; Sec. 2.1). Densities are compared through a
+// device hash per subdomain, and every candidate pair element by element. Returns the
+// representatives (ascending); rep_of[s] names each subdomain's.
+std::vector<int> find_modules(feti_ctx* c) {
+    const int ns = c->P.n_sub;
+    std::vector<int>& rep = c->rep_of;
+    rep.resize(ns);
+    for (int s = 0; s < ns; ++s) rep[s] = s;
+    if (c->opts.recycle && c->designs.size() == 1 && ns > 1) {
+        hipStream_t st = c->st;
+        launch_rho_hash(c->t, c->rho, c->hash_dev, st);
+        CHECK_LAUNCH();
+        std::vector<unsigned long long> h(ns);
+        HIPCHK(hipMemcpyAsync(h.data(), c->hash_dev, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::map<std::pair<unsigned long long, unsigned long long>, int> first;
+        std::vector<int> pairs;
+        for (int s = 0; s < ns; ++s) {
+            auto it = first.emplace(std::make_pair(c->skey[s], h[s]), s).first;
+            if (it->second != s) {
+                pairs.push_back(s);
+                pairs.push_back(it->second);
+            }
+        }
+        const int np = (int)pairs.size() / 2;
+        if (np > 0) {
+            HIPCHK(hipMemcpyAsync(c->pair_dev, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice, st));
+            launch_rho_match(c->t, c->rho, c->pair_dev, np, c->flag_dev, st);
+            CHECK_LAUNCH();
+            std::vector<int> flag(np);
+            HIPCHK(hipMemcpyAsync(flag.data(), c->flag_dev, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int q = 0; q < np; ++q)
+                if (!flag[q]) rep[pairs[2 * q]] = pairs[2 * q + 1];
+        }
+    }
+    std::vector<int> reps;
+    for (int s = 0; s < ns; ++s)
+        if (rep[s] == s) reps.push_back(s);
+    c->n_setup_subs = (int)reps.size();
+    return reps;
+}
+
 // Assembly, factorisation and explicit local operators for the current densities.
 void numeric_setup(feti_ctx* c) {
     c->drop_graphs();
@@ -946,6 +1104,7 @@ void numeric_setup(feti_ctx* c) {
     DevTopo& t = c->t;
     hipStream_t st = c->st;
     const auto& H = c->hsubs;
+    const int ns = P.n_sub;
     auto zero = [&](void* p, long long bytes) {
         if (bytes > 0) HIPCHK(hipMemsetAsync(p, 0, bytes, st));
     };
@@ -958,50 +1117,124 @@ void numeric_setup(feti_ctx* c) {
         nS = Ml.off_S + (long long)Ml.n_beta * Ml.n_beta;
         nF = Ml.off_F + (long long)Ml.rows_F * Ml.ldF;
     }
+    // every subdomain back on its own storage before the assembly
+    if (c->aliased) {
+        HIPCHK(hipMemcpyAsync(c->subs_dev, H.data(), sizeof(SubMeta) * ns, hipMemcpyHostToDevice, st));
+        c->hsubs_act = H;
+        c->aliased = false;
+    }
     zero(c->L, nL * 8);
     zero(c->Z, nZ * 8);
     zero(c->S, nS * 8);
     zero(c->F64, nF * 8);
     zero(c->diag, t.nloc_tot * 8);
     zero(c->info, (t.n_sub + 8) * 4);
+    // every subdomain is assembled (its diagonal feeds the scaling weights); the factorisation
+    // and the local operators are formed for the representatives only (ts, nr)
     launch_assemble(t, c->rho, c->p, c->E0, c->Emin, c->L, c->Z, c->S, c->diag, st);
     CHECK_LAUNCH();
-    launch_bt_factor_li(t, c->L, c->Li, c->info, st);
+    const std::vector<int> reps = find_modules(c);
+    const int nr = (int)reps.size();
+    DevTopo ts = t;
+    const GemmDesc *dsy = c->d_syrk, *dF = c->d_F;
+    const PotrfDesc* dpo = c->d_potrf;
+    const TrsmDesc* dtr = c->d_trsm;
+    if (nr < ns) {
+        std::vector<SubMeta> hr(nr);
+        std::vector<GemmDesc> a(nr), b(nr);
+        std::vector<PotrfDesc> pp(nr);
+        std::vector<TrsmDesc> tt(nr);
+        for (int i = 0; i < nr; ++i) {
+            hr[i] = H[reps[i]];
+            a[i] = c->h_dsy[reps[i]];
+            b[i] = c->h_dF[reps[i]];
+            pp[i] = c->h_dpo[reps[i]];
+            tt[i] = c->h_dtr[reps[i]];
+        }
+        HIPCHK(hipMemcpyAsync(c->subs_rep, hr.data(), sizeof(SubMeta) * nr, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->d_syrk_r, a.data(), sizeof(GemmDesc) * nr, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->d_F_r, b.data(), sizeof(GemmDesc) * nr, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->d_potrf_r, pp.data(), sizeof(PotrfDesc) * nr, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(c->d_trsm_r, tt.data(), sizeof(TrsmDesc) * nr, hipMemcpyHostToDevice, st));
+        ts.subs = c->subs_rep;
+        ts.n_sub = nr;
+        dsy = c->d_syrk_r;
+        dF = c->d_F_r;
+        dpo = c->d_potrf_r;
+        dtr = c->d_trsm_r;
+    }
+    launch_bt_factor_li(ts, c->L, c->Li, c->info, st);
     CHECK_LAUNCH();
-    check_info(c, t.n_sub, "interior Cholesky");
+    check_info(c, nr, "interior Cholesky");
     launch_bt_invert(t, c->L, c->Li, st);
     CHECK_LAUNCH();
-    launch_bt_forward_li(t, c->L, c->Li, c->Z, st);
+    launch_bt_forward_li(ts, c->L, c->Li, c->Z, st);
     CHECK_LAUNCH();
-    if (c->opts.precond == FETI_LUMPED || c->opts.precond == FETI_SUPERLUMPED) launch_pack_sym(t, c->S, c->Pk, st);
-    if (c->opts.precond == FETI_SUPERLUMPED) launch_pk_diag_only(t, c->Pk, st);
-    launch_gemm_tn(c->d_syrk, t.n_sub, c->syrk_tiles, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
+    if (c->opts.precond == FETI_LUMPED || c->opts.precond == FETI_SUPERLUMPED) launch_pack_sym(ts, c->S, c->Pk, st);
+    if (c->opts.precond == FETI_SUPERLUMPED) launch_pk_diag_only(ts, c->Pk, st);
+    launch_gemm_tn(dsy, nr, c->syrk_tiles, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
     CHECK_LAUNCH();
-    if (c->opts.precond == FETI_DIRICHLET) launch_pack_sym(t, c->S, c->Pk, st);
+    if (c->opts.precond == FETI_DIRICHLET) launch_pack_sym(ts, c->S, c->Pk, st);
     if (P.method == FETI_TFETI)
-        launch_tfeti_rbm(t, c->S, c->Rb, c->Cit, c->tau, c->W1, st);
+        launch_tfeti_rbm(ts, c->S, c->Rb, c->Cit, c->tau, c->W1, st);
     else
-        launch_copy_Sbb(t, c->S, c->W1, 0, st);
+        launch_copy_Sbb(ts, c->S, c->W1, 0, st);
     CHECK_LAUNCH();
     zero(c->info, (t.n_sub + 8) * 4);
-    launch_potrf(c->d_potrf, t.n_sub, t.max_nb, c->W1, c->info, st);
+    launch_potrf(dpo, nr, t.max_nb, c->W1, c->info, st);
     CHECK_LAUNCH();
-    check_info(c, t.n_sub, "interface Schur complement Cholesky");
-    launch_copy_Sbb(t, c->S, c->W2, 1, st);
-    launch_trsm_identity(c->d_trsm, t.n_sub, c->max_nb_cols, c->W1, c->W2, st);
-    launch_gemm_tn(c->d_F, t.n_sub, c->F_tiles, c->W2, c->W2, c->F64, 1.0, 0.0, 1, st);
+    check_info(c, nr, "interface Schur complement Cholesky");
+    launch_copy_Sbb(ts, c->S, c->W2, 1, st);
+    launch_trsm_identity(dtr, nr, c->max_nb_cols, c->W1, c->W2, st);
+    launch_gemm_tn(dF, nr, c->F_tiles, c->W2, c->W2, c->F64, 1.0, 0.0, 1, st);
     CHECK_LAUNCH();
     if (P.method == FETI_TFETI)
-        launch_tfeti_fix(t, c->Rb, c->tau, c->F64, st);
-    else {
-        launch_frc(t, c->S, c->F64, c->Kc, st);
-        launch_fold_rows(t, c->F64, st);
-    }
+        launch_tfeti_fix(ts, c->Rb, c->tau, c->F64, st);
+    else
+        launch_frc(ts, c->S, c->F64, c->Kc, st);
     CHECK_LAUNCH();
-    launch_swizzle(t, c->F64, c->sw64, c->sw32, c->swhi, c->swlo, st);
+    launch_swizzle(ts, c->F64, c->sw64, c->sw32, c->swhi, c->swlo, st);
+    CHECK_LAUNCH();
+    std::vector<int> ci(ns, 0);   // compacted index of each subdomain's representative
+    {
+        std::vector<int> pos(ns, -1);
+        for (int i = 0; i < nr; ++i) pos[reps[i]] = i;
+        for (int s = 0; s < ns; ++s) ci[s] = pos[c->rep_of[s]];
+    }
+    if (nr < ns) {
+        // members take their representative's operator storage; the per-subdomain Total FETI
+        // results written by compacted index are spread to every subdomain
+        std::vector<SubMeta>& A = c->hsubs_act;
+        A = H;
+        for (int s = 0; s < ns; ++s) {
+            const SubMeta& R = H[c->rep_of[s]];
+            SubMeta& M = A[s];
+            M.line0 = R.line0;
+            M.off_L = R.off_L;
+            M.off_Z = R.off_Z;
+            M.off_S = R.off_S;
+            M.off_F = R.off_F;
+            M.off_Fsw = R.off_Fsw;
+            M.off_P = R.off_P;
+            M.off_Pk = R.off_Pk;
+            M.off_Kc = R.off_Kc;
+            M.off_R = R.off_R;
+        }
+        HIPCHK(hipMemcpyAsync(c->subs_dev, A.data(), sizeof(SubMeta) * ns, hipMemcpyHostToDevice, st));
+        c->aliased = true;
+        if (P.method == FETI_TFETI) {
+            HIPCHK(hipMemcpyAsync(c->map_dev, ci.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(c->rbm_tmp, c->Cit, sizeof(double) * 36 * nr, hipMemcpyDeviceToDevice, st));
+            launch_gather_rows(ns, 36, c->map_dev, c->rbm_tmp, c->Cit, st);
+            HIPCHK(hipMemcpyAsync(c->rbm_tmp, c->tau, sizeof(double) * nr, hipMemcpyDeviceToDevice, st));
+            launch_gather_rows(ns, 1, c->map_dev, c->rbm_tmp, c->tau, st);
+            CHECK_LAUNCH();
+        }
+    }
+    if (P.method == FETI_DP) launch_fold_rows(t, c->F64, st);
     launch_weights(t, c->opts.scaling == FETI_KSCALE, c->diag, c->w, c->bg_w, st);
     CHECK_LAUNCH();
-    classify_precision(c);
+    classify_precision(c, ts, dpo, ci);
     if (P.method == FETI_DP && P.n_cg > 0) {
         const CoarseBlk& last = c->hcblk.back();
         zero(c->Kcc, (last.off + (long long)last.n * last.n) * 8);
@@ -1861,7 +2094,26 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
     double eps0 = 0.0, true_rel = 0.0;
     int status = FETI_OK;
     if (n > 0) {
-        HIPCHK(hipMemcpyAsync(c->lam, lam_init ? lam_init : c->lam0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        // warm start (single design): the multipliers of the last solve, made feasible for this
+        // load, lambda_0 + P lambda_prev (TFETI: lambda_0 the minimum-norm solution of G lambda = e,
+        // P the projector onto ker G; FETI-DP: lambda_prev itself). The tolerance stays relative to
+        // the residual of the cold start lambda_0, so a warm start ends earlier instead of later.
+        const bool warm = !lam_init && c->opts.warm_start && c->have_lam && c->designs.size() == 1;
+        double eps_cold = 0.0;
+        if (warm) {
+            HIPCHK(hipMemcpyAsync(c->lam, c->lam0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            true_residual(c, c->lam, c->r);
+            precondition(c, c->r, c->zv, 1, 0);
+            ddot(c, n, c->r, c->zv, 0);
+            launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
+            eps_cold = std::sqrt(std::max(read_scalars(c), 0.0));
+            HIPCHK(hipMemcpyAsync(c->lam, c->lam_prev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            project(c, 1, c->lam);
+            launch_axpby(n, 1.0, c->lam0, 1.0, c->lam, st);
+            CHECK_LAUNCH();
+        } else {
+            HIPCHK(hipMemcpyAsync(c->lam, lam_init ? lam_init : c->lam0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        }
         true_residual(c, c->lam, c->r);
         const int prec = c->opts.precision;
         const int kd = c->opts.krylov == FETI_SFETI ? P.n_groups : 1;
@@ -1870,6 +2122,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         ddot(c, n, c->r, c->zv, 0);
         launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
         eps0 = std::sqrt(std::max(read_scalars(c), 0.0));
+        if (warm) eps0 = std::max(eps_cold, eps0);
         for (size_t d = 0; d < c->designs.size(); ++d)
             c->eps0_d[d] = c->designs.size() > 1 ? std::sqrt(std::max(c->hpin[16 + d], 0.0)) : eps0;
         hist.push_back(eps0);
@@ -1948,6 +2201,10 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         eta_orth = gate.eta_orth;
     }
     recover(c, u);
+    if (n > 0 && (status == FETI_OK || status == FETI_ENOCONV)) {
+        HIPCHK(hipMemcpyAsync(c->lam_prev, c->lam, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        c->have_lam = true;
+    }
     HIPCHK(hipEventRecord(c->ev[1], st));
     HIPCHK(hipEventSynchronize(c->ev[1]));
     float ms = 0;
@@ -2037,6 +2294,26 @@ feti_status feti_plan_sizes(const feti_mesh* mesh, const feti_partition* part, c
         z.sum_nb2 = P.sum_nb2();
         z.sum_nb_nc = P.sum_nb_nc();
         *out = z;
+        return FETI_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(FETI_ENOMEM, "host allocation failed");
+    }
+}
+
+feti_status feti_adaptive_primal(const feti_mesh* mesh, const feti_partition* part, const double* rho, double p,
+                                 double E0, double Emin, double theta, int cap, int* nodes, int nodes_cap,
+                                 int* n_out) {
+    if (!n_out) return fail(FETI_EINVAL, "null output");
+    if (!(theta > 0.0) || cap < 0) return fail(FETI_EINVAL, "need theta > 0 and cap >= 0");
+    try {
+        std::vector<int> out;
+        std::string err = adaptive_primal(mesh, part, rho, p, E0, Emin, theta, cap, out);
+        if (!err.empty()) return fail(FETI_EINVAL, err);
+        *n_out = (int)out.size();
+        if (nodes) {
+            if (nodes_cap < (int)out.size()) return fail(FETI_EINVAL, "output capacity too small");
+            std::copy(out.begin(), out.end(), nodes);
+        }
         return FETI_OK;
     } catch (const std::bad_alloc&) {
         return fail(FETI_ENOMEM, "host allocation failed");
@@ -2161,8 +2438,8 @@ std::map<std::string, feti_tuning> read_tune_cache(const char* path) {
         const char* br = q1 ? std::strchr(q1, '{') : nullptr;
         if (!br) continue;
         feti_tuning t{};
-        if (std::sscanf(br, "{\"max_red\": %d, \"max_d\": %d, \"xcd\": %d, \"split_d\": %d, \"us\": %lf", &t.max_red,
-                        &t.max_d, &t.xcd, &t.split_d, &t.us) == 5)
+        if (std::sscanf(br, "{\"max_red\": %d, \"max_d\": %d, \"xcd\": %d, \"split_d\": %d, \"fp64_first\": %d, \"us\": %lf",
+                        &t.max_red, &t.max_d, &t.xcd, &t.split_d, &t.fp64_first, &t.us) == 6)
             out[std::string(q0 + 1, q1)] = t;
     }
     std::fclose(f);
@@ -2176,8 +2453,11 @@ void write_tune_cache(const char* path, const std::map<std::string, feti_tuning>
     size_t i = 0;
     for (const auto& kv : m) {
         const feti_tuning& t = kv.second;
-        std::fprintf(f, " \"%s\": {\"max_red\": %d, \"max_d\": %d, \"xcd\": %d, \"split_d\": %d, \"us\": %.2f}%s\n",
-                     kv.first.c_str(), t.max_red, t.max_d, t.xcd, t.split_d, t.us, ++i < m.size() ? "," : "");
+        std::fprintf(f,
+                     " \"%s\": {\"max_red\": %d, \"max_d\": %d, \"xcd\": %d, \"split_d\": %d, \"fp64_first\": %d, "
+                     "\"us\": %.2f}%s\n",
+                     kv.first.c_str(), t.max_red, t.max_d, t.xcd, t.split_d, t.fp64_first, t.us,
+                     ++i < m.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
     std::fclose(f);
@@ -2217,21 +2497,25 @@ feti_status feti_autotune(feti_ctx* c, int reps, const char* cache_path, feti_tu
         // Zk, Qtmp: n_lambda x 64 work buffers; their contents do not change the timing
         HIPCHK(hipMemsetAsync(c->Zk, 0, sizeof(double) * c->P.n_lambda * kMaxDirs, c->st));
         const int rp = std::max(1, reps);
-        feti_tuning best{2 * kFlWaves, kFlWaves, 1, 4, 0.0, 0.0, 0};
+        feti_tuning best{2 * kFlWaves, kFlWaves, 1, 4, 0.0, 0.0, 0, 0};
         c->tune = best;
         build_fl_tiles(c);
         const double t_def = time_flambda(c, rp);
         best.us = 1e3 * t_def;
+        // the placement of the FP64 tiles (split_d 0, fp64_first) only matters for hybrid lists
+        const std::vector<int> sds = c->hybrid ? std::vector<int>{4, 2, 1, 0} : std::vector<int>{4, 2};
+        const std::vector<int> ffs = c->hybrid ? std::vector<int>{0, 1} : std::vector<int>{0};
         for (int mr : {32, 16})
             for (int md : {16, 14, 12, 10, 8, 4})
                 for (int xc : {1, 0})
-                    for (int sd : {4, 2}) {
-                        c->tune = feti_tuning{mr, md, xc, sd, 0.0, 0.0, 0};
-                        build_fl_tiles(c);
-                        const double tm = 1e3 * time_flambda(c, rp);
-                        // a change of shapes must gain at least 2% (timing noise keeps the defaults)
-                        if (tm < 0.98 * best.us) best = feti_tuning{mr, md, xc, sd, tm, 0.0, 0};
-                    }
+                    for (int sd : sds)
+                        for (int ff : ffs) {
+                            c->tune = feti_tuning{mr, md, xc, sd, 0.0, 0.0, 0, ff};
+                            build_fl_tiles(c);
+                            const double tm = 1e3 * time_flambda(c, rp);
+                            // a change of shapes must gain at least 2% (timing noise keeps the defaults)
+                            if (tm < 0.98 * best.us) best = feti_tuning{mr, md, xc, sd, tm, 0.0, 0, ff};
+                        }
         best.us_default = 1e3 * t_def;
         c->tune = best;
         build_fl_tiles(c);
@@ -2300,6 +2584,54 @@ feti_status feti_compliance_and_grad(feti_ctx* c, const double* rho, const doubl
     });
 }
 
+feti_status feti_get_lambda(feti_ctx* c, double* lambda) {
+    if (!c || !lambda) return fail(FETI_EINVAL, "null argument");
+    if (!c->have_lam) return fail(FETI_EINVAL, "no solve has run on this context");
+    return guarded([&]() -> feti_status {
+        if (c->P.n_lambda > 0)
+            HIPCHK(hipMemcpyAsync(lambda, c->lam_prev, sizeof(double) * c->P.n_lambda, hipMemcpyDeviceToDevice,
+                                  c->st));
+        return FETI_OK;
+    });
+}
+
+feti_status feti_oc_update(feti_ctx* c, const double* rho, const double* dc, double volfrac, double move, double eta,
+                           double rho_min, double* rho_new, double* lagrange) {
+    if (!c || !rho || !dc || !rho_new) return fail(FETI_EINVAL, "null argument");
+    if (c->designs.size() != 1) return fail(FETI_EINVAL, "the design update takes one design per context");
+    if (!(rho_min >= 0.0 && rho_min < 1.0) || !(volfrac > rho_min && volfrac <= 1.0) || !(move > 0.0) || !(eta > 0.0))
+        return fail(FETI_EINVAL, "need 0 <= rho_min < volfrac <= 1, move > 0 and eta > 0");
+    return guarded([&]() -> feti_status {
+        const long long n = c->P.n_el;
+        const int nwg = (int)std::min<long long>(1024, std::max<long long>(1, (n + 255) / 256));
+        std::vector<double> hp(nwg);
+        auto reduce = [&](double lam, int mode) {
+            launch_oc_reduce(n, rho, dc, lam, move, eta, rho_min, mode, nwg, c->part, c->st);
+            CHECK_LAUNCH();
+            HIPCHK(hipMemcpyAsync(hp.data(), c->part, sizeof(double) * nwg, hipMemcpyDeviceToHost, c->st));
+            HIPCHK(hipStreamSynchronize(c->st));
+            double a = 0.0;
+            for (int i = 0; i < nwg; ++i) a = mode == 0 ? a + hp[i] : std::max(a, hp[i]);
+            return a;
+        };
+        const double target = volfrac * (double)n;
+        double lo = 0.0, hi = reduce(0.0, 1);
+        if (!(hi > 0.0)) hi = 1.0;
+        for (int k = 0; k < 200 && reduce(hi, 0) > target; ++k) hi *= 2.0;
+        for (int k = 0; k < 200 && hi - lo > 1e-14 * hi; ++k) {
+            const double mid = 0.5 * (lo + hi);
+            if (reduce(mid, 0) <= target)
+                hi = mid;
+            else
+                lo = mid;
+        }
+        launch_oc_apply(n, rho, dc, hi, move, eta, rho_min, rho_new, c->st);
+        CHECK_LAUNCH();
+        if (lagrange) *lagrange = hi;
+        return FETI_OK;
+    });
+}
+
 feti_status feti_destroy(feti_ctx* c) {
     if (!c) return FETI_OK;
     delete c;
@@ -2327,6 +2659,7 @@ feti_status feti_get_sizes(feti_ctx* c, feti_sizes* out) {
     z.device_bytes = c->bytes;
     z.n_fp64_subs = c->n_fp64_subs;
     z.n_designs = (int)c->designs.size();
+    z.n_setup_subs = c->n_setup_subs;
     z.sum_nb2_fp64 = 0;
     if (c->hybrid)
         for (int s = 0; s < P.n_sub; ++s)
@@ -2419,7 +2752,7 @@ feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long 
             if (n) HIPCHK(hipMemcpy(v.data(), src, sizeof(double) * n, hipMemcpyDeviceToHost));
         };
         if (what == 0 || what == 2) {
-            const SubMeta& M = c->hsubs[s];
+            const SubMeta& M = c->hsubs_act[s];
             std::vector<double> F;
             const long long n = (long long)M.rows_F * M.ldF;
             F.resize(n);
@@ -2436,7 +2769,7 @@ feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long 
             }
         } else if (what == 1) {
             // the packed upper tiles, expanded to the full symmetric n_b x n_b block
-            const SubMeta& M = c->hsubs[s];
+            const SubMeta& M = c->hsubs_act[s];
             nr = nc = M.n_b;
             const int nT = (M.n_b + 63) / 64;
             std::vector<double> pk;
@@ -2455,7 +2788,7 @@ feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long 
                             v[(size_t)col * M.n_b + row] = e;
                         }
         } else if (what == 3) {
-            const SubMeta& M = c->hsubs[s];
+            const SubMeta& M = c->hsubs_act[s];
             nr = nc = M.n_c;
             fetch(c->Kc + M.off_Kc, (long long)M.n_c * M.n_c);
         } else if (what == 4) {
@@ -2472,7 +2805,7 @@ feti_status feti_get_local(feti_ctx* c, int s, int what, double* out, long long 
                 if (b.cg0 == D.cg0 && b.n == D.n_cg) off = b.off;
             fetch(c->Kcc + off, (long long)D.n_cg * D.n_cg);
         } else if (what == 6) {
-            const SubMeta& M = c->hsubs[s];
+            const SubMeta& M = c->hsubs_act[s];
             nr = M.n_loc;
             nc = 1;
             fetch(c->diag + M.off_loc, M.n_loc);

@@ -689,11 +689,14 @@ void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, doubl
 // Entries of B_r F_rc B_c (Sec. 2.2, Eq. 12) per lambda row: side t of the row (subdomain s,
 // interface position j, sign) contributes sign * F_rc^s[j][q] for each of the subdomain's corner
 // DOFs q, read from the F_rc^T rows of the augmented operator. One thread per row.
+// (fr_val2, when given: the same values at the row's position ipos[r] in the pair-grouped order)
 __global__ void k_fold_rows(int n_lambda, int W, const int* __restrict__ row_s, const int* __restrict__ row_j,
                             const int8_t* __restrict__ row_sg, const SubMeta* __restrict__ subs,
-                            const double* __restrict__ F64, double* __restrict__ fr_val) {
+                            const double* __restrict__ F64, double* __restrict__ fr_val,
+                            const int* __restrict__ ipos, double* __restrict__ fr_val2) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_lambda) return;
+    const long long r2 = fr_val2 ? (long long)ipos[r] * W : 0;
     int e = 0;
     for (int t = 0; t < 2; ++t) {
         const int s = row_s[2 * r + t];
@@ -701,15 +704,18 @@ __global__ void k_fold_rows(int n_lambda, int W, const int* __restrict__ row_s, 
         const SubMeta M = subs[s];
         const int j = row_j[2 * r + t];
         const double sg = (double)row_sg[2 * r + t];
-        for (int q = 0; q < M.n_c && e < W; ++q, ++e)
-            fr_val[(long long)r * W + e] = sg * F64[M.off_F + (long long)(M.rowT + q) * M.ldF + j];
+        for (int q = 0; q < M.n_c && e < W; ++q, ++e) {
+            const double val = sg * F64[M.off_F + (long long)(M.rowT + q) * M.ldF + j];
+            fr_val[(long long)r * W + e] = val;
+            if (fr_val2) fr_val2[r2 + e] = val;
+        }
     }
 }
 
 void launch_fold_rows(const DevTopo& t, const double* F64, hipStream_t st) {
     if (t.n_cg == 0 || t.n_lambda == 0 || t.fr_w == 0) return;
     k_fold_rows<<<(t.n_lambda + 255) / 256, 256, 0, st>>>(t.n_lambda, t.fr_w, t.row_s, t.row_j, t.row_sg, t.subs,
-                                                          F64, t.fr_val);
+                                                          F64, t.fr_val, t.pr_ipos, t.n_pairs ? t.pr_fval : nullptr);
 }
 
 // Q[row][c] = sum over the row's sides of sign * Y_s[j][c] + sum_e fr_val[row][e] v[fr_col[row][e]][c]:
@@ -746,10 +752,85 @@ __global__ void __launch_bounds__(256) k_scatter_fold(int n_lambda, int k, int W
     Q[idx] = val + (acc0 + acc1);
 }
 
+// The same per pair of subdomains, for blocks of 32 or more columns: workgroup g stages the
+// coarse solution rows of its group's corner union (at most 64 x 64) in LDS once; its sixteen
+// wavefronts then take the group's rows two at a time, a lane per column. Every per-row array is
+// stored in the group order, so a row's loads depend on nothing but its position, and a row's
+// fold entries (at most 64) come in with one vector load per table, lane e holding entry e, and
+// are broadcast by readlane: no memory load waits inside the fold loop.
+__device__ __forceinline__ double bcast_lane(double v, int e) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), e);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), e);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename TY>
+__global__ void __launch_bounds__(1024) k_scatter_fold_pair(int k, int W, const int* __restrict__ pr_ptr,
+                                                            const int* __restrict__ pr_row,
+                                                            const long long* __restrict__ pr_yo,
+                                                            const int8_t* __restrict__ pr_sg,
+                                                            const int* __restrict__ pr_fn,
+                                                            const int* __restrict__ pr_fpos,
+                                                            const double* __restrict__ pr_fval,
+                                                            const int* __restrict__ pu_ptr, const int* __restrict__ pu_cg,
+                                                            const TY* __restrict__ Y, const double* __restrict__ v,
+                                                            double* __restrict__ Q) {
+    __shared__ double vs[kFoldPairMaxU][64];
+    const int g = blockIdx.x;
+    const int u0 = pu_ptr[g], nu = pu_ptr[g + 1] - u0;
+    for (int e = threadIdx.x; e < nu * 64; e += 1024) {
+        const int u = e >> 6, c = e & 63;
+        vs[u][c] = c < k ? v[(long long)pu_cg[u0 + u] * k + c] : 0.0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, c = threadIdx.x & 63;
+    const bool col = c < k;
+    const int i1 = pr_ptr[g + 1];
+    for (int i = pr_ptr[g] + wave; i < i1; i += 32) {
+        const bool two = i + 16 < i1;
+        const int ib = two ? i + 16 : i;
+        // both rows' loads issued before any use
+        const long long ya0 = pr_yo[2 * i], ya1 = pr_yo[2 * i + 1], yb0 = pr_yo[2 * ib], yb1 = pr_yo[2 * ib + 1];
+        const int nea = pr_fn[i], neb = pr_fn[ib];
+        const int fpa = c < nea ? pr_fpos[(long long)i * W + c] : 0;
+        const int fpb = c < neb ? pr_fpos[(long long)ib * W + c] : 0;
+        const double fva = c < nea ? pr_fval[(long long)i * W + c] : 0.0;
+        const double fvb = c < neb ? pr_fval[(long long)ib * W + c] : 0.0;
+        double va = 0.0, vb = 0.0;
+        if (col) {
+            if (ya0 >= 0) va += pr_sg[2 * i] * (double)Y[ya0 * k + c];
+            if (ya1 >= 0) va += pr_sg[2 * i + 1] * (double)Y[ya1 * k + c];
+            if (yb0 >= 0) vb += pr_sg[2 * ib] * (double)Y[yb0 * k + c];
+            if (yb1 >= 0) vb += pr_sg[2 * ib + 1] * (double)Y[yb1 * k + c];
+        }
+        double aa = 0.0, ab = 0.0;
+        for (int e = 0; e < nea; ++e)
+            aa = fma(bcast_lane(fva, e), vs[__builtin_amdgcn_readlane(fpa, e)][c], aa);
+        for (int e = 0; e < neb; ++e)
+            ab = fma(bcast_lane(fvb, e), vs[__builtin_amdgcn_readlane(fpb, e)][c], ab);
+        if (col) {
+            Q[(long long)pr_row[i] * k + c] = va + aa;
+            if (two) Q[(long long)pr_row[ib] * k + c] = vb + ab;
+        }
+    }
+}
+
 void launch_scatter_fold(const DevTopo& t, int k, int ytype_f32, const void* Y, const double* v, double* Q,
                          hipStream_t st) {
     const long long n = (long long)t.n_lambda * k;
     if (n == 0) return;
+    if (k >= 32 && t.n_pairs > 0) {
+        if (ytype_f32)
+            k_scatter_fold_pair<float><<<t.n_pairs, 1024, 0, st>>>(k, t.fr_w, t.pr_ptr, t.pr_rows, t.pr_yo, t.pr_sg,
+                                                                   t.pr_fn, t.fr_pos, t.pr_fval, t.pu_ptr, t.pu_cg,
+                                                                   (const float*)Y, v, Q);
+        else
+            k_scatter_fold_pair<double><<<t.n_pairs, 1024, 0, st>>>(k, t.fr_w, t.pr_ptr, t.pr_rows, t.pr_yo, t.pr_sg,
+                                                                    t.pr_fn, t.fr_pos, t.pr_fval, t.pu_ptr, t.pu_cg,
+                                                                    (const double*)Y, v, Q);
+        return;
+    }
     const int grid = (int)((n + 255) / 256);
     if (ytype_f32)
         k_scatter_fold<float><<<grid, 256, 0, st>>>(t.n_lambda, k, t.fr_w, t.row_yo, t.row_sg, (const float*)Y, t.fr_n,

@@ -1075,6 +1075,77 @@ void upload_K0(const double* K0, int n, hipStream_t st) {
     hipMemcpyToSymbolAsync(HIP_SYMBOL(c_K0), K0, sizeof(double) * n * n, 0, hipMemcpyHostToDevice, st);
 }
 
+// ---- module types (factorisation recycling) ----
+// Element e of subdomain s in local lexicographic order (x fastest), as its global index.
+__device__ __forceinline__ long long sub_element(const SubMeta& M, int dim, int e) {
+    const int nx = M.nn[0] - 1, ny = M.nn[1] - 1;
+    const int ex = e % nx, ey = (e / nx) % ny, ez = dim == 3 ? e / (nx * ny) : 0;
+    return M.el0 + (long long)(M.lo[0] + ex) + (long long)M.nelx * ((M.lo[1] + ey) + (long long)M.nely * (M.lo[2] + ez));
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// out[s] = XOR over the subdomain's elements of mix64(bits(rho_e) + mix64(local index)): equal
+// density patterns give equal values (order-independent, so deterministic); unequal ones almost
+// surely do not, and the host checks candidates element by element (k_rho_match).
+__global__ void __launch_bounds__(256) k_rho_hash(const SubMeta* __restrict__ subs, int dim, const double* __restrict__ rho,
+                                                  unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[4];
+    const SubMeta M = subs[blockIdx.x];
+    const int nel = (M.nn[0] - 1) * (M.nn[1] - 1) * (dim == 3 ? M.nn[2] - 1 : 1);
+    unsigned long long h = 0;
+    for (int e = threadIdx.x; e < nel; e += 256)
+        h ^= mix64((unsigned long long)__double_as_longlong(rho[sub_element(M, dim, e)]) + mix64((unsigned long long)e));
+    for (int o = 32; o > 0; o >>= 1) h ^= __shfl_xor(h, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = h;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
+}
+
+// flag[q] = 1 if the densities of subdomain pairs[2q] differ anywhere from those of pairs[2q+1]
+// (same local layout), else 0
+__global__ void __launch_bounds__(256) k_rho_match(const SubMeta* __restrict__ subs, int dim, const double* __restrict__ rho,
+                                                   const int* __restrict__ pairs, int* __restrict__ flag) {
+    __shared__ int any;
+    const SubMeta A = subs[pairs[2 * blockIdx.x]], B = subs[pairs[2 * blockIdx.x + 1]];
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int nel = (A.nn[0] - 1) * (A.nn[1] - 1) * (dim == 3 ? A.nn[2] - 1 : 1);
+    int d = 0;
+    for (int e = threadIdx.x; e < nel; e += 256)
+        d |= __double_as_longlong(rho[sub_element(A, dim, e)]) != __double_as_longlong(rho[sub_element(B, dim, e)]);
+    if (d) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) flag[blockIdx.x] = any;
+}
+
+// dst[i * w + j] = src[map[i] * w + j], i < n
+__global__ void k_gather_rows(int n, int w, const int* __restrict__ map, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)n * w) return;
+    const int i = (int)(e / w), j = (int)(e % w);
+    dst[e] = src[(long long)map[i] * w + j];
+}
+
+void launch_rho_hash(const DevTopo& t, const double* rho, unsigned long long* out, hipStream_t st) {
+    if (t.n_sub) k_rho_hash<<<t.n_sub, 256, 0, st>>>(t.subs, t.dim, rho, out);
+}
+
+void launch_rho_match(const DevTopo& t, const double* rho, const int* pairs, int npairs, int* flag, hipStream_t st) {
+    if (npairs) k_rho_match<<<npairs, 256, 0, st>>>(t.subs, t.dim, rho, pairs, flag);
+}
+
+void launch_gather_rows(int n, int w, const int* map, const double* src, double* dst, hipStream_t st) {
+    const long long m = (long long)n * w;
+    if (m) k_gather_rows<<<(int)((m + 255) / 256), 256, 0, st>>>(n, w, map, src, dst);
+}
+
 void launch_assemble(const DevTopo& t, const double* rho, double p, double E0, double Emin, double* L, double* Z,
                      double* S, double* diag, hipStream_t st) {
     dim3 grid((t.max_nodes + 255) / 256, t.n_sub);

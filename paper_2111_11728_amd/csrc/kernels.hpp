@@ -132,6 +132,22 @@ struct DevTopo {
     const int* fr_col = nullptr;      // [n_lambda x fr_w] global corner DOF
     double* fr_val = nullptr;         // [n_lambda x fr_w] values (set up with F_rc)
     int fr_w = 0;
+    // the same rows grouped by their pair of subdomains (n_pairs = 0: not built): rows
+    // pr_rows[pr_ptr[g] .. pr_ptr[g+1]), the union of their corner DOFs pu_cg[pu_ptr[g] .. ),
+    // and the position of every fold entry in its group's union
+    int n_pairs = 0;
+    const int* pr_ptr = nullptr;
+    const int* pr_rows = nullptr;
+    const int* pu_ptr = nullptr;
+    const int* pu_cg = nullptr;
+    const int* fr_pos = nullptr;      // [pair position x fr_w], in the group order
+    // per row in the group order: the scatter sides (off_b + j or -1, sign), the fold entry count
+    // and values; pr_ipos[row] = the row's position
+    const long long* pr_yo = nullptr;
+    const int8_t* pr_sg = nullptr;
+    const int* pr_fn = nullptr;
+    double* pr_fval = nullptr;
+    const int* pr_ipos = nullptr;
     int n_lines_tot = 0;              // interior line (2D) / plane (3D) blocks over all subdomains
     FlTiles fl64;                     // F*Lambda work list with every row block in FP64
     FlTiles flred;                    // ... with every row block in the reduced precision
@@ -188,6 +204,12 @@ void launch_fold_coarse(const DevTopo& t, int k, int ytype_f32, const double* F6
                         hipStream_t st);
 // Q[row] = sum over sides sign * Y[b]
 void launch_scatter(const DevTopo& t, int k, int ytype_f32, const void* Y, double* Q, hipStream_t st);
+// module types: per-subdomain density hashes, element-wise comparison of (member, representative)
+// pairs, and rows gathered by a map (per-subdomain setup results of representatives)
+void launch_rho_hash(const DevTopo& t, const double* rho, unsigned long long* out, hipStream_t st);
+void launch_rho_match(const DevTopo& t, const double* rho, const int* pairs, int npairs, int* flag, hipStream_t st);
+void launch_gather_rows(int n, int w, const int* map, const double* src, double* dst, hipStream_t st);
+constexpr int kFoldPairMaxU = 64;   // corner DOFs of two subdomains staged per group
 // fr_val from the F_rc^T rows of the augmented operators (after launch_frc)
 void launch_fold_rows(const DevTopo& t, const double* F64, hipStream_t st);
 // Q = sum_s B_s Y_s + (B_r F_rc B_c) v: the scatter with the coarse fold of F*Lambda in one pass
@@ -253,6 +275,12 @@ void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank,
 void launch_zero_cols(long long n, int k, unsigned long long mask, double* Z, hipStream_t st);
 void launch_apply_T(int n, int k, const double* T, const double* W, const double* Q, double* Wo, double* Qo,
                     hipStream_t st);
+// SIMP optimality-criteria step: partial volumes sum rho_e(L) (mode 0) or maxima of |dc| (mode 1)
+// per workgroup into part[nwg]; then rho_new = rho(L)
+void launch_oc_reduce(long long n, const double* rho, const double* dc, double lam, double move, double eta,
+                      double rho_min, int mode, int nwg, double* part, hipStream_t st);
+void launch_oc_apply(long long n, const double* rho, const double* dc, double lam, double move, double eta,
+                     double rho_min, double* out, hipStream_t st);
 // lam += W g; r -= Qg_scale * Q g  (Q may be null)
 // lam_out = lam + W g (lam_out = nullptr: in place), r -= Q g (Q = nullptr: r untouched)
 void launch_update_lr(int n, int k, const double* W, const double* Q, const double* g, double* lam, double* r,

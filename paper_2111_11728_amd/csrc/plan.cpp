@@ -170,6 +170,22 @@ std::string build_plan(const feti_mesh* mesh, const feti_partition* part, const 
     P.off_c.assign(n_sub + 1, 0);
     std::vector<uint8_t> corner_node(P.n_nodes, 0);
     for (int nd = 0; nd < P.n_nodes; ++nd) corner_node[nd] = is_corner_node(nd) ? 1 : 0;
+    // further primal nodes (Sec. 6, item i: compatibility enforced in primal variables at nodes
+    // other than the corners): each must be shared by two or more subdomains and carry a free DOF
+    if (part->n_primal < 0 || (part->n_primal > 0 && !part->primal_nodes)) return "bad primal node list";
+    if (part->n_primal > 0 && P.method != FETI_DP) return "primal nodes need FETI-DP";
+    for (int k = 0; k < part->n_primal; ++k) {
+        const int nd = part->primal_nodes[k];
+        if (nd < 0 || nd >= P.n_nodes) return fmt("primal node %lld out of range", nd);
+        int x[3];
+        node_coords(nd, x);
+        if (P.ax_cnt[0][x[0]] * P.ax_cnt[1][x[1]] * P.ax_cnt[2][x[2]] < 2)
+            return fmt("primal node %lld is not shared by two subdomains", nd);
+        bool free_dof = false;
+        for (int c = 0; c < dim; ++c) free_dof = free_dof || !fixed[dim * nd + c];
+        if (!free_dof) return fmt("primal node %lld has no free DOF", nd);
+        corner_node[nd] = 1;
+    }
 
     for (int s = 0; s < n_sub; ++s) {
         int k[3] = {s % P.nsub[0], (s / P.nsub[0]) % P.nsub[1], s / (P.nsub[0] * P.nsub[1])};
@@ -386,6 +402,90 @@ std::string build_plan(const feti_mesh* mesh, const feti_partition* part, const 
         for (int s = 0; s < n_sub; ++s)
             if (P.n_b[s] == 0) return "TFETI needs every subdomain to touch a constraint";
     }
+    return "";
+}
+
+std::string adaptive_primal(const feti_mesh* mesh, const feti_partition* part, const double* rho, double p,
+                            double E0, double Emin, double theta, int cap, std::vector<int>& out) {
+    out.clear();
+    if (!mesh || !part || !rho) return "null mesh, partition or densities";
+    if (mesh->dim == 3) return "";
+    if (mesh->dim != 2) return "dim must be 2 or 3";
+    const int nx = mesh->nel[0], ny = mesh->nel[1];
+    if (nx < 1 || ny < 1) return "bad grid";
+    std::vector<int> cuts[2];
+    for (int a = 0; a < 2; ++a) {
+        const int ns = part->nsub[a], ne = mesh->nel[a];
+        if (ns < 1 || ns > ne) return fmt("nsub[%lld] out of range", a);
+        cuts[a].resize(ns + 1);
+        for (int k = 0; k <= ns; ++k) cuts[a][k] = part->cuts[a] ? part->cuts[a][k] : k * (ne / ns);
+        if (cuts[a][0] != 0 || cuts[a][ns] != ne) return fmt("cuts[%lld] must run from 0 to nel", a);
+    }
+    const int nnx = nx + 1;
+    const long long n_dof = 2LL * nnx * (ny + 1);
+    std::vector<uint8_t> fixed(n_dof, 0);
+    for (int k = 0; k < mesh->n_fixed; ++k)
+        if (mesh->fixed_dofs[k] >= 0 && mesh->fixed_dofs[k] < n_dof) fixed[mesh->fixed_dofs[k]] = 1;
+    auto modulus = [&](int e) { return Emin + std::pow(rho[e], p) * (E0 - Emin); };
+    auto stiffness = [&](int x, int y) {   // elements containing the node, lexicographic order
+        double k = 0.0;
+        for (int ey = y - 1; ey <= y; ++ey)
+            for (int ex = x - 1; ex <= x; ++ex)
+                if (ex >= 0 && ex < nx && ey >= 0 && ey < ny) k += modulus(ex + nx * ey);
+        return k;
+    };
+    std::vector<std::vector<std::pair<int, int>>> edges;
+    for (size_t i = 1; i + 1 < cuts[0].size(); ++i)
+        for (size_t j = 0; j + 1 < cuts[1].size(); ++j) {
+            std::vector<std::pair<int, int>> e;
+            for (int y = cuts[1][j] + 1; y < cuts[1][j + 1]; ++y) e.push_back({cuts[0][i], y});
+            edges.push_back(e);
+        }
+    for (size_t j = 1; j + 1 < cuts[1].size(); ++j)
+        for (size_t i = 0; i + 1 < cuts[0].size(); ++i) {
+            std::vector<std::pair<int, int>> e;
+            for (int x = cuts[0][i] + 1; x < cuts[0][i + 1]; ++x) e.push_back({x, cuts[1][j]});
+            edges.push_back(e);
+        }
+    std::vector<int> nodes;
+    for (const auto& e : edges) {
+        if (e.empty()) continue;
+        std::vector<double> k(e.size());
+        double kmax = 0.0;
+        for (size_t t = 0; t < e.size(); ++t) {
+            k[t] = stiffness(e[t].first, e[t].second);
+            kmax = std::max(kmax, k[t]);
+        }
+        if (!(kmax > 0.0)) continue;
+        struct Run {
+            int a, b;
+            double w;
+        };
+        std::vector<Run> runs;
+        int a = -1;
+        for (size_t t = 0; t <= e.size(); ++t) {
+            const bool stiff = t < e.size() && k[t] >= theta * kmax;
+            if (stiff && a < 0) {
+                a = (int)t;
+            } else if (!stiff && a >= 0) {
+                double w = 0.0;
+                for (int q = a; q < (int)t; ++q) w += k[q];
+                runs.push_back({a, (int)t - 1, w});
+                a = -1;
+            }
+        }
+        std::stable_sort(runs.begin(), runs.end(), [](const Run& u, const Run& v) {
+            return u.w > v.w || (u.w == v.w && u.a < v.a);
+        });
+        for (int r = 0; r < (int)runs.size() && r < cap; ++r) {
+            const auto& xy = e[(runs[r].a + runs[r].b) / 2];
+            const int nd = xy.first + nnx * xy.second;
+            if (!(fixed[2LL * nd] && fixed[2LL * nd + 1])) nodes.push_back(nd);
+        }
+    }
+    std::sort(nodes.begin(), nodes.end());
+    nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+    out = nodes;
     return "";
 }
 

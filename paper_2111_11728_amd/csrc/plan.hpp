@@ -71,6 +71,13 @@ struct Plan {
 std::string build_plan(const feti_mesh* mesh, const feti_partition* part, const feti_opts* opts,
                        Plan& P);
 
+// Adaptive choice of further FETI-DP primal nodes from the densities (2D; 3D: none): along every
+// edge shared by two subdomains (end vertices excluded), runs of nodes whose stiffness (sum of the
+// moduli Emin + rho^p (E0 - Emin) of their elements) is at least theta times the edge's largest;
+// the cap runs of largest total stiffness give their middle nodes. out: sorted global nodes.
+std::string adaptive_primal(const feti_mesh* mesh, const feti_partition* part, const double* rho, double p,
+                            double E0, double Emin, double theta, int cap, std::vector<int>& out);
+
 // One design inside a plan that holds several independent designs (their disjoint union):
 // the ranges of its subdomains, elements, nodes, DOFs, lambda rows, corners and S-FETI
 // direction groups in the union's numbering, and its own structured grid.

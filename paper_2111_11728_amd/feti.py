@@ -37,14 +37,15 @@ class feti_mesh(C.Structure):
 
 
 class feti_partition(C.Structure):
-    _fields_ = [("nsub", C.c_int * 3), ("cuts", C.POINTER(C.c_int) * 3), ("group", C.c_int * 3)]
+    _fields_ = [("nsub", C.c_int * 3), ("cuts", C.POINTER(C.c_int) * 3), ("group", C.c_int * 3),
+                ("n_primal", C.c_int), ("primal_nodes", C.POINTER(C.c_int))]
 
 
 class feti_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("scaling", C.c_int), ("krylov", C.c_int), ("precond", C.c_int),
                 ("precision", C.c_int), ("tol", C.c_double), ("max_it", C.c_int), ("rr_tol", C.c_double),
                 ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double), ("graphs", C.c_int),
-                ("orth_fp32", C.c_int)]
+                ("orth_fp32", C.c_int), ("warm_start", C.c_int), ("recycle", C.c_int)]
 
 
 class feti_info(C.Structure):
@@ -67,7 +68,7 @@ class feti_design(C.Structure):
 
 class feti_tuning(C.Structure):
     _fields_ = [("max_red", C.c_int), ("max_d", C.c_int), ("xcd", C.c_int), ("split_d", C.c_int),
-                ("us", C.c_double), ("us_default", C.c_double), ("from_cache", C.c_int)]
+                ("us", C.c_double), ("us_default", C.c_double), ("from_cache", C.c_int), ("fp64_first", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -78,7 +79,7 @@ class feti_sizes(C.Structure):
                 ("n_alpha", C.c_int), ("n_groups", C.c_int), ("nb_max", C.c_int), ("nb_min", C.c_int),
                 ("n_loc_max", C.c_int), ("n_i_max", C.c_int), ("band_max", C.c_int), ("sum_nb2", C.c_longlong),
                 ("sum_nb_nc", C.c_longlong), ("device_bytes", C.c_longlong), ("n_fp64_subs", C.c_int),
-                ("n_designs", C.c_int), ("sum_nb2_fp64", C.c_longlong)]
+                ("n_designs", C.c_int), ("sum_nb2_fp64", C.c_longlong), ("n_setup_subs", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +110,10 @@ def lib():
             "feti_last_error": (C.c_char_p, []),
             "feti_get_sizes": (I, [P, C.POINTER(feti_sizes)]),
             "feti_apply_F": (I, [P, I, I, P, P]),
+            "feti_get_lambda": (I, [P, P]),
+            "feti_oc_update": (I, [P, P, P, D, D, D, D, P, C.POINTER(C.c_double)]),
+            "feti_adaptive_primal": (I, [C.POINTER(feti_mesh), C.POINTER(feti_partition), P, D, D, D, D, I,
+                                         C.POINTER(C.c_int), I, C.POINTER(C.c_int)]),
             "feti_apply_F_noalloc": (I, [P, I, I, P, P]),
             "feti_apply_precond": (I, [P, P, P, I]),
             "feti_project": (I, [P, I, P]),
@@ -154,7 +159,8 @@ class Spec:
     """ctypes views of a workloads.Problem (keeps the host arrays alive)."""
 
     def __init__(self, prob, method="fetidp", scaling="k", krylov="pcg", precond="dirichlet", precision="fp64",
-                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0, graphs=0, orth_fp32=0):
+                 tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0, graphs=0, orth_fp32=0,
+                 primal_nodes=None, warm_start=0, recycle=0):
         self.prob = prob
         fixed = np.ascontiguousarray(prob.fixed_dofs(), dtype=np.int32)
         self._fixed = fixed
@@ -177,15 +183,34 @@ class Spec:
                 self.part.nsub[a] = 1
                 self.part.cuts[a] = C.POINTER(C.c_int)()
             self.part.group[a] = (prob.groups[a] if (prob.groups is not None and a < prob.dim) else 0)
+        self._primal = np.ascontiguousarray(np.asarray([] if primal_nodes is None else primal_nodes), dtype=np.int32)
+        self.part.n_primal = self._primal.size
+        self.part.primal_nodes = (self._primal.ctypes.data_as(C.POINTER(C.c_int)) if self._primal.size
+                                  else C.POINTER(C.c_int)())
         self.opts = feti_opts(METHODS[method], SCALINGS[scaling], KRYLOVS[krylov], PRECONDS[precond],
                               PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax, graphs,
-                              orth_fp32)
+                              orth_fp32, warm_start, recycle)
 
 
 def feti_plan_sizes(spec: Spec) -> dict:
     out = feti_sizes()
     _check(lib().feti_plan_sizes(C.byref(spec.mesh), C.byref(spec.part), C.byref(spec.opts), C.byref(out)))
     return out.as_dict()
+
+
+def feti_adaptive_primal(spec: Spec, theta=0.2, cap=3) -> np.ndarray:
+    """Host-only: the library's adaptive choice of further FETI-DP primal nodes for spec's
+    problem (its densities and SIMP parameters)."""
+    prob = spec.prob
+    rho = np.ascontiguousarray(prob.rho, dtype=np.float64)
+    n = C.c_int(0)
+    rp = C.c_void_p(rho.ctypes.data)
+    _check(lib().feti_adaptive_primal(C.byref(spec.mesh), C.byref(spec.part), rp, prob.p, prob.E0, prob.Emin,
+                                      theta, cap, None, 0, C.byref(n)))
+    buf = np.zeros(max(1, n.value), dtype=np.int32)
+    _check(lib().feti_adaptive_primal(C.byref(spec.mesh), C.byref(spec.part), rp, prob.p, prob.E0, prob.Emin,
+                                      theta, cap, buf.ctypes.data_as(C.POINTER(C.c_int)), buf.size, C.byref(n)))
+    return buf[:n.value].astype(np.int64)
 
 
 def feti_plan_export(spec: Spec, what: int) -> np.ndarray:
@@ -264,6 +289,16 @@ class Context:
                 "reduced_iters": info.reduced_iters, "precision_probes": info.precision_probes,
                 "reduced_rel_err": info.reduced_rel_err, "reduced_orth_err": info.reduced_orth_err,
                 "history": hist[:n].copy(), "eps0": info.eps0}
+
+    def feti_get_lambda(self, lam):
+        _check(lib().feti_get_lambda(self.handle, _ptr(lam)))
+
+    def feti_oc_update(self, rho, dc, rho_new, volfrac, move=0.2, eta=0.5, rho_min=1e-3):
+        """Returns the multiplier L of the volume bound."""
+        L = C.c_double(0.0)
+        _check(lib().feti_oc_update(self.handle, _ptr(rho), _ptr(dc), volfrac, move, eta, rho_min, _ptr(rho_new),
+                                    C.byref(L)))
+        return L.value
 
     def feti_apply_F(self, k, precision, Lam, Q, pure=False):
         p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)

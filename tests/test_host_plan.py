@@ -30,8 +30,8 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
-def _oracle_rows(prob, method):
-    dec = topology.decompose(prob)
+def _oracle_rows(prob, method, primal_nodes=None):
+    dec = topology.decompose(prob, primal_nodes)
     if method == "tfeti":
         cons = topology.tfeti_constraints(dec)
         rows = [[(s, j, sg) for (s, j, sg) in row] for row in cons.rows]
@@ -103,3 +103,58 @@ def test_invalid_inputs_are_rejected():
     spec.part.cuts[0] = type(spec.part.cuts[0])()
     with pytest.raises(feti.FetiError):
         feti.feti_plan_sizes(spec)
+
+
+PRIMAL_CASES = [
+    ("c2", lambda: workloads.modular_2d(0), 0.2, 3),
+    ("c3-block", lambda: workloads.beta_2d_block(1), 0.2, 3),
+    ("layered", lambda: workloads.layered_grid(), 0.2, 3),
+    ("inclusion", lambda: workloads.inclusion_grid(), 0.5, 2),
+    ("uneven", lambda: workloads.uneven_design(0, 3), 0.1, 1),
+]
+
+
+@pytest.mark.parametrize("name,make,theta,cap", PRIMAL_CASES)
+def test_adaptive_primal_nodes_match_oracle(name, make, theta, cap):
+    """The library's adaptive choice of further primal nodes equals the oracle's (integer output,
+    bit-exact), and the FETI-DP topology with the enlarged primal set equals the oracle's."""
+    _lib_or_skip()
+    prob = make()
+    spec = feti.Spec(prob, method="fetidp")
+    got = feti.feti_adaptive_primal(spec, theta, cap)
+    want = topology.adaptive_primal_nodes(prob, theta, cap)
+    assert np.array_equal(got, want)
+    assert got.size > 0
+    # every chosen node lies strictly inside a shared subdomain edge
+    nx = prob.nel[0]
+    for nd in got:
+        x, y = nd % (nx + 1), nd // (nx + 1)
+        assert (x in prob.cuts[0][1:-1]) != (y in prob.cuts[1][1:-1]), nd
+    spec = feti.Spec(prob, method="fetidp", primal_nodes=got)
+    sizes = feti.feti_plan_sizes(spec)
+    cons, rows, split, dec = _oracle_rows(prob, "fetidp", want)
+    base = feti.feti_plan_sizes(feti.Spec(prob, method="fetidp"))
+    assert sizes["n_cg"] == split.corner_dofs.size == base["n_cg"] + 2 * got.size
+    assert sizes["n_lambda"] == cons.n_rows == base["n_lambda"] - 2 * got.size
+    assert np.array_equal(feti.feti_plan_export(spec, 2), split.corner_dofs)
+    per = feti.feti_plan_export(spec, 1).reshape(-1, 5)
+    assert np.array_equal(per[:, 2], [b.size for b in cons.bset])
+    assert np.array_equal(per[:, 3], [c.size for c in split.c])
+    assert per[:, 3].max() <= 32
+    ex = feti.feti_plan_export(spec, 0).reshape(-1, 2, 3)
+    for k, row in enumerate(rows):
+        got_row = [tuple(int(v) for v in ex[k, t]) for t in range(2) if ex[k, t, 0] >= 0]
+        assert got_row == [(s, j, int(sg)) for (s, j, sg) in row], k
+
+
+def test_primal_nodes_rejected_when_invalid():
+    _lib_or_skip()
+    prob = workloads.cantilever_tfeti(0)
+    for bad in ([5], [0], [10 ** 7]):        # interior node, clamped node, out of range
+        with pytest.raises(feti.FetiError) as e:
+            feti.feti_plan_sizes(feti.Spec(prob, method="fetidp", primal_nodes=bad))
+        assert e.value.status == feti.FETI_EINVAL
+    with pytest.raises(feti.FetiError):
+        feti.feti_plan_sizes(feti.Spec(prob, method="tfeti", primal_nodes=[8 + 33 * 4]))
+    with pytest.raises(ValueError):
+        topology.decompose(prob, [5])
