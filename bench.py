@@ -59,7 +59,7 @@ def log(msg):
 
 
 ROOF_KERNEL = "k_flambda<1, 4, double>"  # in-solve F*Lambda, 64 directions: FP32 rows + FP64 rows, FP64 outputs
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flambda_fp32_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flambda_insolve_c3_traffic.json")
 COPY_BYTES = 1 << 30                     # calibration copy for the HBM byte counters
 
 
@@ -97,26 +97,30 @@ def ingest_pmc(fetch_dir, write_dir):
         if not dbs:
             raise SystemExit(f"no rocpd database under {d}")
         con = sqlite3.connect(dbs[0])
-        rows = con.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+        rows = con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection").fetchall()
         out = {}
-        for name, cname, val in rows:
+        for disp, name, cname, val in rows:
             if cname != counter:
                 continue
-            out.setdefault(name, []).append(float(val))
+            out.setdefault(name, []).append((int(disp), float(val)))
         return out
 
     f = per_kernel(fetch_dir, "FETCH_SIZE")
     w = per_kernel(write_dir, "WRITE_SIZE")
 
-    def pick(tab, key, largest=False):
-        vals = [v for n, vs in tab.items() if key in n for v in vs]
+    def pick(tab, key, largest=False, last=None):
+        vals = sorted(v for n, vs in tab.items() if key in n for v in vs)
+        if last:
+            vals = vals[-last:]
+        vals = [v for _, v in vals]
         if not vals:
             raise SystemExit(f"kernel {key} not in counter run")
         return float(max(vals) if largest else np.median(vals))
 
-    # the calibration copies are the largest device copies of the run
+    # the calibration copies are the largest device copies of the run; the roofline kernel's
+    # launches on the tile shapes the autotuner chose are its last eight (3 warm-up + 5 timed)
     cf, cw = pick(f, "copyBuffer", True), pick(w, "copyBuffer", True)
-    kf, kw = pick(f, ROOF_KERNEL), pick(w, ROOF_KERNEL)
+    kf, kw = pick(f, ROOF_KERNEL, last=8), pick(w, ROOF_KERNEL, last=8)
     sf, sw = COPY_BYTES / (cf * 1024.0), COPY_BYTES / (cw * 1024.0)
     rec = {"kernel": ROOF_KERNEL, "source_hash": kernel_source_hash(),
            "fetch_kib_per_launch": kf, "write_kib_per_launch": kw,
