@@ -251,7 +251,9 @@ typedef struct {
  * change from the defaults must gain 2%) and applies it to every tile list of the context. cache_path (host string, optional): a JSON
  * file of earlier results keyed by (subdomains, n_b bucket of 32, precision, hybrid); a hit is
  * applied without timing, a miss is timed and written back. out: host, optional. Results of
- * F*Lambda do not depend on the tile shapes (each row's contraction order is fixed). */
+ * F*Lambda do not depend on max_red, max_d, xcd or fp64_first (each row's contraction order is
+ * fixed); split_d 0 against split_d > 0 changes the order of the FP64 rows of subdomains that failed
+ * the round-off test (one sum against four partial sums), a difference at FP64 round-off. */
 feti_status feti_autotune(feti_ctx* ctx, int reps, const char* cache_path, feti_tuning* out);
 
 /* Ranges of design d (0 <= d < n_designs) in the concatenated arrays. */

@@ -156,87 +156,185 @@ __global__ void __launch_bounds__(256) k_bt_forward(const SubMeta* __restrict__ 
 constexpr int kBfLd = 129;
 typedef double v4w __attribute__((ext_vector_type(4)));
 
+// 32 operands of one 16-row block of a row-major matrix (rows r0 .. r0+15 of `rows`, columns
+// 0 .. cols-1, zero outside) in the lane order of the 16x16x4 contractions: op[4Q + e] is row
+// r0 + m, column 16Q + 4g + e. All loads are issued before any is used.
+__device__ inline void bf_load_rowblock(double (&op)[32], const double* __restrict__ X, int r0, int rows, int cols) {
+    const int lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4, r = r0 + m;
+#pragma unroll
+    for (int Q = 0; Q < 8; ++Q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int q = 16 * Q + 4 * g + e;
+            op[4 * Q + e] = (q < cols && r < rows) ? X[(long long)r * cols + q] : 0.0;
+        }
+}
+
 __device__ inline void bf_syrk_update(double* A, const double* __restrict__ C, int n, int np) {
-    // lower 16x16 blocks (bi >= bj) of the n x n block, dealt round-robin to the wavefronts
+    // D -= C C^T on the lower 16x16 blocks of the n x n block (C is n x np). Wavefront w takes
+    // block row w and, if it is 4 or more, block row nb-1-w (nb <= 8: every block row exactly once,
+    // equal tile counts for nb = 8); the operands of a block row are loaded once, those of the next
+    // tile while the current one is on the matrix cores.
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
     const int nb = (n + 15) >> 4;
-    int idx = 0;
-    for (int bi = 0; bi < nb; ++bi)
-        for (int bj = 0; bj <= bi; ++bj, ++idx) {
-            if ((idx & 3) != wave) continue;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int bi = pass == 0 ? wave : nb - 1 - wave;
+        if (bi >= nb || (pass == 1 && bi < 4)) continue;
+        double a[32], b[32], bn[32];
+        bf_load_rowblock(a, C, 16 * bi, n, np);
+        bf_load_rowblock(b, C, 0, n, np);
+        for (int bj = 0; bj <= bi; ++bj) {
+            bf_load_rowblock(bn, C, 16 * (bj + 1), bj < bi ? n : 0, np);
             v4w acc = v4w{0.0, 0.0, 0.0, 0.0};
-            const int ra = 16 * bi + m, rb = 16 * bj + m;
-            for (int Q = 0; Q < (np + 15) / 16; ++Q) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int q = 16 * Q + 4 * g + e;
-                    const double a = (q < np && ra < n) ? C[(long long)ra * np + q] : 0.0;
-                    const double b = (q < np && rb < n) ? C[(long long)rb * np + q] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-                }
-            }
+            for (int u = 0; u < 32; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
             // D layout: rows g + 4v, column m
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * bi + g + 4 * v, j = 16 * bj + m;
                 if (i < n && j < n && j <= i) A[i * kBfLd + j] -= acc[v];
             }
+#pragma unroll
+            for (int u = 0; u < 32; ++u) b[u] = bn[u];
         }
+    }
 }
 
-// left-looking Cholesky of the lower triangle of A (n <= 128); returns 0 or the failing
-// column + 1 (uniform)
-__device__ inline int bf_potrf(double* A, int n, double* colv) {
-    const int tid = threadIdx.x, row = tid >> 1, half = tid & 1;
-    for (int j = 0; j < n; ++j) {
-        // A[i][j] -= sum_{q<j} A[i][q] A[j][q] for i >= j (two threads per row, halves of q)
-        double part = 0.0;
-        if (row < n && row >= j) {
-            const double* Ai = A + row * kBfLd;
-            const double* Aj = A + j * kBfLd;
-            const int qh = (j + 1) >> 1, q0 = half ? qh : 0, q1 = half ? j : qh;
-            for (int q = q0; q < q1; ++q) part += Ai[q] * Aj[q];
+// Diagonal-block inverses of the line factor: 8 blocks of 16 x 16, row stride 17.
+constexpr int kXdLd = 17;
+
+// Blocked right-looking Cholesky of the lower triangle of A (n <= 128 DOFs, zero-padded to
+// np = 16 ceil(n / 16) with every padded entry 0). Per 16-column panel: thread i (p0 <= i < np)
+// keeps row i of the panel in registers and the 16 columns are eliminated in turn, the pivot column
+// passing through LDS (double-buffered, one barrier a column); then the trailing lower triangle is
+// updated, A_IK -= L_I,panel L_K,panel^T, in 16 x 16 tiles on the FP64 matrix cores. Afterwards the
+// padded diagonal is set to 1, so L = diag(L_n, I). Returns 0 or the failing column + 1 (uniform).
+__device__ inline int bf_potrf_blocked(double* A, int n, int np, double* colv /* 2 x 128 */) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int nb = np >> 4;
+    for (int p0 = 0; p0 < n; p0 += 16) {
+        const int pb = min(16, n - p0), i = tid;
+        const bool own = i >= p0 && i < np;
+        double a[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = (own && p0 + c <= i) ? A[i * kBfLd + p0 + c] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            double* cv = colv + 128 * (jj & 1);
+            if (own) cv[i] = a[jj];
+            __syncthreads();
+            if (jj < pb) {
+                const int j = p0 + jj;
+                const double d = cv[j];
+                if (!(d > 0.0)) return j + 1;
+                const double piv = sqrt(d), inv = 1.0 / piv;
+                const double li = (own && i > j) ? cv[i] * inv : 0.0;
+                if (own && i >= j) a[jj] = i == j ? piv : li;
+#pragma unroll
+                for (int c = jj + 1; c < 16; ++c) a[c] = fma(-li, cv[p0 + c] * inv, a[c]);
+            }
         }
-        part += __shfl_xor(part, 1, 64);
-        if (row < n && row >= j && half == 0) colv[row] = A[row * kBfLd + j] - part;
+        if (own) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (p0 + c <= i) A[i * kBfLd + p0 + c] = a[c];
+        }
         __syncthreads();
-        const double d = colv[j];
-        if (!(d > 0.0)) return j + 1;
-        const double piv = sqrt(d), inv = 1.0 / piv;
-        if (row < n && row >= j && half == 0) A[row * kBfLd + j] = row == j ? piv : colv[row] * inv;
+        const int b1 = (p0 >> 4) + 1, mt = nb - b1, ntile = mt * (mt + 1) / 2;
+        for (int t = wave; t < ntile; t += 4) {
+            int I = 0;
+            while ((I + 1) * (I + 2) / 2 <= t) ++I;
+            const int K = t - I * (I + 1) / 2;
+            const int r0 = 16 * (b1 + I), k0 = 16 * (b1 + K);
+            v4w acc = v4w{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int q = p0 + g + 4 * kk;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(r0 + m) * kBfLd + q], A[(k0 + m) * kBfLd + q], acc, 0, 0, 0);
+            }
+            // D layout: rows g + 4v, column m
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A[(r0 + g + 4 * v) * kBfLd + k0 + m] -= acc[v];
+        }
         __syncthreads();
     }
+    if (tid >= n && tid < np) A[tid * kBfLd + tid] = 1.0;
+    __syncthreads();
     return 0;
 }
 
-// in-place inverse of the lower-triangular L in A: columns right to left, column j from the
-// trailing inverse already in place and L's own column j (kept until all rows are done)
-__device__ inline void bf_trtri(double* A, int n, double* colv) {
-    const int tid = threadIdx.x, row = tid >> 1, half = tid & 1;
-    for (int j = n - 1; j >= 0; --j) {
-        const double djj = 1.0 / A[j * kBfLd + j];
-        double part = 0.0;
-        if (row < n && row > j) {
-            // X[row][j] = -(sum_{q=j+1}^{row} X[row][q] L[q][j]) / L[j][j]
-            const double* Xi = A + row * kBfLd;
-            const int len = row - j, qh = j + 1 + (len >> 1);
-            const int q0 = half ? qh : j + 1, q1 = half ? row + 1 : qh;
-            for (int q = q0; q < q1; ++q) part += Xi[q] * A[q * kBfLd + j];
+// In-place inverse X = L^{-1} of the lower-triangular L in A (np x np, np a multiple of 16, unit
+// padded diagonal). First the 16 x 16 diagonal blocks, X_II = L_II^{-1}, one thread per column by
+// forward substitution into Xd; then block column J (wavefront J mod 4) from
+//   X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ,   I = J+1, ...,
+// on the FP64 matrix cores with the X_KJ tiles in registers (their accumulator layout is the
+// operand layout of the next product). X_IJ goes to the unused upper block (J, I), transposed, and a
+// last pass moves every block to its place in the lower triangle.
+__device__ inline void bf_trtri_blocked(double* A, int np, double* Xd) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int nb = np >> 4;
+    if (tid < np) {
+        const int I = tid >> 4, c = tid & 15;
+        const double* L = A + 16 * I * kBfLd + 16 * I;
+        double x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            x[j] = x[j] / L[j * kBfLd + j];
+#pragma unroll
+            for (int r = j + 1; r < 16; ++r) x[r] = fma(-L[r * kBfLd + j], x[j], x[r]);
         }
-        part += __shfl_xor(part, 1, 64);
-        __syncthreads();   // every row has read column j of L
-        if (row < n && half == 0) {
-            if (row > j) A[row * kBfLd + j] = -part * djj;
-            else if (row == j) A[row * kBfLd + j] = djj;
-        }
-        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Xd[(16 * I + r) * kXdLd + c] = x[r];
     }
+    __syncthreads();
+    for (int J = wave; J < nb; J += 4) {
+        v4w xt[8];
+#pragma unroll
+        for (int K = 0; K < 8; ++K) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xt[K][v] = K == J ? Xd[(16 * J + g + 4 * v) * kXdLd + m] : 0.0;
+        }
+#pragma unroll
+        for (int I = 1; I < 8; ++I) {
+            if (I > J && I < nb) {
+                v4w t = v4w{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int K = 0; K < I; ++K) {
+                    if (K >= J) {
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk)
+                            t = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(16 * I + m) * kBfLd + 16 * K + g + 4 * kk],
+                                                                     xt[K][kk], t, 0, 0, 0);
+                    }
+                }
+                v4w x = v4w{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xd[(16 * I + m) * kXdLd + g + 4 * kk], t[kk], x, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    xt[I][v] = -x[v];
+                    A[(16 * J + m) * kBfLd + 16 * I + g + 4 * v] = -x[v];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < np * np; e += 256) {
+        const int i = e / np, c = e - i * np;
+        if (c > i) continue;
+        A[i * kBfLd + c] = (i >> 4) == (c >> 4) ? Xd[i * kXdLd + (c & 15)] : A[c * kBfLd + i];
+    }
+    __syncthreads();
 }
 
 __global__ void __launch_bounds__(256) k_bt_factor128(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines,
                                                       double* Lbuf, double* Li, int* info) {
     __shared__ double A[128 * kBfLd];
-    __shared__ double colv[128];
+    __shared__ double colv[256];
+    __shared__ double Xd[128 * kXdLd];
     const int s = blockIdx.x;
     const SubMeta M = subs[s];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
@@ -244,17 +342,27 @@ __global__ void __launch_bounds__(256) k_bt_factor128(const SubMeta* __restrict_
         const LineMeta Lk = lines[M.line0 + k];
         const int n = Lk.n;
         if (n == 0) continue;
+        const int np = (n + 15) & ~15;
         double* D = Lbuf + Lk.off_diag;
-        for (int e = tid; e < n * n; e += 256) {
-            const int i = e / n, j = e - i * n;
-            A[i * kBfLd + j] = D[e];
+        for (int e0 = tid; e0 < np * np; e0 += 8 * 256) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + 256 * u, i = e / np, j = e - i * np;
+                v[u] = (e < np * np && i < n && j < n) ? D[i * n + j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + 256 * u, i = e / np, j = e - i * np;
+                if (e < np * np) A[i * kBfLd + j] = v[u];
+            }
         }
         __syncthreads();
         if (Lk.n_prev > 0) {
             bf_syrk_update(A, Lbuf + Lk.off_sub, n, Lk.n_prev);
             __syncthreads();
         }
-        const int r = bf_potrf(A, n, colv);
+        const int r = bf_potrf_blocked(A, n, np, colv);
         if (r) {
             if (tid == 0) info[s] = Lk.i0 + r;
             return;
@@ -264,7 +372,7 @@ __global__ void __launch_bounds__(256) k_bt_factor128(const SubMeta* __restrict_
             D[e] = j <= i ? A[i * kBfLd + j] : 0.0;
         }
         __syncthreads();
-        bf_trtri(A, n, colv);
+        bf_trtri_blocked(A, np, Xd);
         double* X = Li + Lk.off_inv;
         for (int e = tid; e < n * n; e += 256) {
             const int i = e / n, j = e - i * n;
@@ -277,23 +385,23 @@ __global__ void __launch_bounds__(256) k_bt_factor128(const SubMeta* __restrict_
                 // x all columns, every row block read completely before it is overwritten
                 double* Ab = Lbuf + Ln.off_sub;   // n_next x n
                 const int nn = Ln.n, ncb = (n + 15) >> 4;
+                double a[32];
+                if (wave < (nn + 15) / 16) bf_load_rowblock(a, Ab, 16 * wave, nn, n);
                 for (int rbk = wave; rbk < (nn + 15) / 16; rbk += 4) {
+                    double an[32];
+                    bf_load_rowblock(an, Ab, 16 * (rbk + 4), rbk + 4 < (nn + 15) / 16 ? nn : 0, n);
                     v4w acc[8];
 #pragma unroll
                     for (int cb = 0; cb < 8; ++cb) acc[cb] = v4w{0.0, 0.0, 0.0, 0.0};
-                    const int ra = 16 * rbk + m;
-                    for (int Q = 0; Q < (n + 15) / 16; ++Q) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int q = 16 * Q + 4 * g + e;
-                            const double a = (q < n && ra < nn) ? Ab[(long long)ra * n + q] : 0.0;
+                    for (int u = 0; u < 32; ++u) {
+                        const int q = 16 * (u >> 2) + 4 * g + (u & 3);
 #pragma unroll
-                            for (int cb = 0; cb < 8; ++cb) {
-                                if (cb < ncb) {
-                                    const int cc = 16 * cb + m;
-                                    const double b = (q < n && cc < n && q <= cc) ? A[cc * kBfLd + q] : 0.0;
-                                    acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
-                                }
+                        for (int cb = 0; cb < 8; ++cb) {
+                            if (cb < ncb) {
+                                const int cc = 16 * cb + m;
+                                const double b = (q < n && cc < n && q <= cc) ? A[cc * kBfLd + q] : 0.0;
+                                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b, acc[cb], 0, 0, 0);
                             }
                         }
                     }
@@ -304,6 +412,8 @@ __global__ void __launch_bounds__(256) k_bt_factor128(const SubMeta* __restrict_
                             const int rr = 16 * rbk + g + 4 * v, cc = 16 * cb + m;
                             if (cb < ncb && rr < nn && cc < n) Ab[(long long)rr * n + cc] = acc[cb][v];
                         }
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) a[u] = an[u];
                 }
             }
         }

@@ -581,8 +581,10 @@ def test_batched_designs_oracle_and_fd(dens):
 def test_autotune_shapes_and_cache(tmp_path):
     """F*Lambda tile-shape autotuner on the 8x4 modular design in mixed precision: the tuned
     shapes leave the product unchanged bit for bit (each row's contraction order does not
-    depend on the tiling), the chosen time is not worse than the default's, and a second call
-    with the same cache file applies the stored shapes without timing."""
+    depend on the tiling) unless the tuner drops the split contraction of the FP64 rows
+    (split_d 0: one sum where the default takes four partial sums), which may change them at FP64
+    round-off; the chosen time is not worse than the default's, and a second call with the same
+    cache file applies the stored shapes without timing."""
     prob = workloads.modular_2d(0)
     print("case autotune", flush=True)
     ctx = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", precision="fp32", tol=1e-8)
@@ -597,9 +599,14 @@ def test_autotune_shapes_and_cache(tmp_path):
         cache = tmp_path / "tune.json"
         t1 = ctx.feti_autotune(reps=3, cache=cache)
         assert t1["from_cache"] == 0 and t1["us"] <= t1["us_default"]
-        assert 1 <= t1["max_red"] <= 32 and 1 <= t1["max_d"] <= 16 and 1 <= t1["split_d"] <= 4
+        assert 1 <= t1["max_red"] <= 32 and 1 <= t1["max_d"] <= 16 and 0 <= t1["split_d"] <= 4
         ctx.feti_apply_F(32, prec, L, Q1)
-        assert torch.equal(Q0, Q1), prec
+        if t1["split_d"] > 0:
+            assert torch.equal(Q0, Q1), prec
+        else:
+            err = ((Q0 - Q1).norm(dim=0) / Q0.norm(dim=0)).max().item()
+            print(f"  {prec}: split_d 0, column-wise relative difference {err:.1e}", flush=True)
+            assert err <= 1e-13, prec
         t2 = ctx.feti_autotune(reps=3, cache=cache)
         assert t2["from_cache"] == 1
         assert (t2["max_red"], t2["max_d"], t2["xcd"], t2["split_d"]) == (t1["max_red"], t1["max_d"], t1["xcd"],
