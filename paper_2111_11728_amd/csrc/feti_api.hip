@@ -210,7 +210,7 @@ struct feti_ctx {
     GemmDesc *d_syrk = nullptr, *d_F = nullptr, *d_one = nullptr;
     PotrfDesc *d_potrf = nullptr, *d_potrf_one = nullptr;
     TrsmDesc *d_trsm = nullptr, *d_trsm_one = nullptr;
-    int syrk_tiles = 0, F_tiles = 0, max_nb_cols = 0;
+    int syrk_tdim = 0, F_tdim = 0, max_nb_cols = 0;
     int n_alpha = 0;
 
     // solve buffers
@@ -647,8 +647,8 @@ void build_layout(feti_ctx* c) {
         dpo[s] = PotrfDesc{M.off_P, M.n_b, M.n_b};
         dtr[s] = TrsmDesc{M.off_P, M.off_P, M.n_b, M.n_b, M.n_b, M.n_b};
         const int tb = (M.n_beta + 63) / 64, tf = (M.n_b + 63) / 64;
-        c->syrk_tiles = std::max(c->syrk_tiles, tb * tb);
-        c->F_tiles = std::max(c->F_tiles, tf * tf);
+        c->syrk_tdim = std::max(c->syrk_tdim, tb);
+        c->F_tdim = std::max(c->F_tdim, tf);
         c->max_nb_cols = std::max(c->max_nb_cols, M.n_b);
     }
     c->d_syrk = c->upload(dsy);
@@ -1023,7 +1023,7 @@ void dense_spd_inverse(feti_ctx* c, int n, const double* A, double* work, double
     launch_set_identity(Ainv, n, n, c->st);
     launch_trsm_identity(c->d_trsm_one, 1, n, work, Ainv, c->st);
     // Ainv currently holds X = L^{-1}; form X^T X into work, then copy
-    launch_gemm_tn(c->d_one, 1, ((n + 63) / 64) * ((n + 63) / 64), Ainv, Ainv, work, 1.0, 0.0, 1, c->st);
+    launch_gemm_tn(c->d_one, 1, (n + 63) / 64, Ainv, Ainv, work, 1.0, 0.0, 1, c->st);
     CHECK_LAUNCH();
     HIPCHK(hipMemcpyAsync(Ainv, work, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c->st));
 }
@@ -1045,7 +1045,7 @@ void coarse_inverse(feti_ctx* c) {
     check_info(c, nb, "coarse Cholesky");
     for (const CoarseBlk& b : B) launch_set_identity(c->Kcc_inv + b.off, b.n, b.n, st);
     launch_trsm_identity(c->d_cc_trsm, nb, maxn, c->Kcc_w, c->Kcc_inv, st);
-    launch_gemm_tn(c->d_cc_gemm, nb, ((maxn + 63) / 64) * ((maxn + 63) / 64), c->Kcc_inv, c->Kcc_inv, c->Kcc_w, 1.0,
+    launch_gemm_tn(c->d_cc_gemm, nb, (maxn + 63) / 64, c->Kcc_inv, c->Kcc_inv, c->Kcc_w, 1.0,
                    0.0, 1, st);
     CHECK_LAUNCH();
     HIPCHK(hipMemcpyAsync(c->Kcc_inv, c->Kcc_w, sizeof(double) * sz, hipMemcpyDeviceToDevice, st));
@@ -1172,7 +1172,7 @@ void numeric_setup(feti_ctx* c) {
     CHECK_LAUNCH();
     if (c->opts.precond == FETI_LUMPED || c->opts.precond == FETI_SUPERLUMPED) launch_pack_sym(ts, c->S, c->Pk, st);
     if (c->opts.precond == FETI_SUPERLUMPED) launch_pk_diag_only(ts, c->Pk, st);
-    launch_gemm_tn(dsy, nr, c->syrk_tiles, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
+    launch_gemm_tn(dsy, nr, c->syrk_tdim, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
     CHECK_LAUNCH();
     if (c->opts.precond == FETI_DIRICHLET) launch_pack_sym(ts, c->S, c->Pk, st);
     if (P.method == FETI_TFETI)
@@ -1186,7 +1186,7 @@ void numeric_setup(feti_ctx* c) {
     check_info(c, nr, "interface Schur complement Cholesky");
     launch_copy_Sbb(ts, c->S, c->W2, 1, st);
     launch_trsm_identity(dtr, nr, c->max_nb_cols, c->W1, c->W2, st);
-    launch_gemm_tn(dF, nr, c->F_tiles, c->W2, c->W2, c->F64, 1.0, 0.0, 1, st);
+    launch_gemm_tn(dF, nr, c->F_tdim, c->W2, c->W2, c->F64, 1.0, 0.0, 1, st);
     CHECK_LAUNCH();
     if (P.method == FETI_TFETI)
         launch_tfeti_fix(ts, c->Rb, c->tau, c->F64, st);

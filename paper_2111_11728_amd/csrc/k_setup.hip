@@ -149,8 +149,9 @@ __global__ void __launch_bounds__(256) k_bt_forward(const SubMeta* __restrict__ 
 // Block-tridiagonal Cholesky of K_ii for lines of at most 128 DOFs, one workgroup per
 // subdomain, the line's diagonal block resident in LDS (stride 129):
 //   D_k -= C_k C_k^T           (FP64 matrix cores, lower 16x16 blocks; C_k = L_{k,k-1})
-//   D_k  = L_kk L_kk^T          (left-looking, two threads per row)
-//   L_kk^{-1}                   (in place, right to left over the columns)
+//   D_k  = L_kk L_kk^T          (16-column panels: panel rows in registers, trailing update on
+//                                the matrix cores)
+//   L_kk^{-1}                   (16x16 diagonal inverses, then the block columns on the matrix cores)
 //   C_{k+1} = A_{k+1,k} L_kk^{-T}  (matrix cores, B operand from LDS, written over A_{k+1,k})
 // L_kk goes to its slot of L and L_kk^{-1} to the inverse buffer.
 constexpr int kBfLd = 129;
@@ -555,20 +556,33 @@ __global__ void __launch_bounds__(256, 2) k_bt_forward_mfma(const SubMeta* __res
 // in wavefront order. Rows and columns of the tile are permuted so that at step st lane
 // (m, g) reads A[4 st + g][i0 + 4m .. +3] and B[4 st + g][j0 + 4m .. +3]: accumulator row m'
 // of block ib is tile row 4 m' + ib, column n' of block jb is tile column 4 n' + jb.
-// symmetric (A == B): only tiles on or below the diagonal are computed; off-diagonal tiles
-// are written to both (i, j) and (j, i).
+// symmetric (A == B): only tiles on or below the diagonal are enumerated (tile t of a matrix is
+// the t-th of the lower triangle, row by row); off-diagonal tiles are written to both (i, j) and
+// (j, i). Placement: workgroups go to the eight XCDs in turn, so workgroup L serves matrix
+// (L mod 8) + 8 ((L / 8) / tiles) and all tiles of one matrix run on one XCD, where the column
+// blocks they share are read through one L2.
 typedef double v4g __attribute__((ext_vector_type(4)));
 constexpr int kGtRing = 6;
 
-__global__ void __launch_bounds__(256, 1) k_gemm_tn(const GemmDesc* __restrict__ desc, const double* Abase,
+__global__ void __launch_bounds__(256, 1) k_gemm_tn(const GemmDesc* __restrict__ desc, int nbatch, const double* Abase,
                                                     const double* Bbase, double* Cbase, double alpha, double beta,
                                                     int symmetric) {
     __shared__ double red[4 * 4096];
-    const GemmDesc d = desc[blockIdx.y];
-    const int tn = (d.n + 63) / 64;
-    const int ti = blockIdx.x / tn, tj = blockIdx.x % tn;
-    if (ti * 64 >= d.m) return;
-    if (symmetric && tj > ti) return;
+    const int wl = blockIdx.x + gridDim.x * blockIdx.y, slot = wl >> 3;
+    const int mat = (wl & 7) + 8 * (slot / (int)gridDim.x), tile = slot % (int)gridDim.x;
+    if (mat >= nbatch) return;
+    const GemmDesc d = desc[mat];
+    int ti, tj;
+    if (symmetric) {
+        ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+        tj = tile - ti * (ti + 1) / 2;
+    } else {
+        const int tn = (d.n + 63) / 64;
+        ti = tile / tn;
+        tj = tile % tn;
+    }
+    if (ti * 64 >= d.m || tj * 64 >= d.n) return;
     const double* A = Abase + d.a;
     const double* B = Bbase + d.b;
     double* C = Cbase + d.c;
@@ -630,12 +644,94 @@ __global__ void __launch_bounds__(256, 1) k_gemm_tn(const GemmDesc* __restrict__
     }
 }
 
-// Batched in-place Cholesky (one workgroup per matrix).
-__global__ void __launch_bounds__(256) k_potrf(const PotrfDesc* __restrict__ desc, double* base, int* info) {
-    __shared__ double lds[kLdsDoubles];
+// Batched in-place Cholesky of matrices of at most 512 rows, one 512-thread workgroup per matrix,
+// right-looking in 32-column panels. Thread i keeps row i of the panel in registers; the 32
+// columns are eliminated in turn with the pivot column passing through LDS (double-buffered, one
+// barrier a column). The finished panel goes to A and to LDS, and the trailing lower triangle is
+// updated, A_IK -= L_I,panel L_K,panel^T, in 16x16 tiles on the FP64 matrix cores (operands from
+// LDS, four tiles per wavefront in flight). Entries above the diagonal are left unspecified;
+// info = 0 or the failing column + 1.
+constexpr int kPpLd = 33;
+
+__global__ void __launch_bounds__(512) k_potrf512(const PotrfDesc* __restrict__ desc, double* base, int* info) {
+    __shared__ double P[512 * kPpLd];
+    __shared__ double colv[2 * 512];
     const PotrfDesc d = desc[blockIdx.x];
-    const int r = wg_potrf(d.n, base + d.a, d.lda, lds);
-    if (threadIdx.x == 0) info[blockIdx.x] = r;
+    double* A = base + d.a;
+    const long long lda = d.lda;
+    const int n = d.n;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    for (int k0 = 0; k0 < n; k0 += 32) {
+        const int kb = min(32, n - k0), i = tid;
+        const bool own = i >= k0 && i < n;
+        double a[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) a[c] = (own && c < kb && k0 + c <= i) ? A[i * lda + k0 + c] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 32; ++jj) {
+            double* cv = colv + 512 * (jj & 1);
+            if (own) cv[i] = a[jj];
+            __syncthreads();
+            if (jj < kb) {
+                const int j = k0 + jj;
+                const double dj = cv[j];
+                if (!(dj > 0.0)) {   // uniform: every thread read the same value
+                    if (tid == 0) info[blockIdx.x] = j + 1;
+                    return;
+                }
+                const double piv = sqrt(dj), inv = 1.0 / piv;
+                const double li = (own && i > j) ? cv[i] * inv : 0.0;
+                if (own && i >= j) a[jj] = i == j ? piv : li;
+#pragma unroll
+                for (int c = jj + 1; c < 32; ++c) {
+                    const double lk = k0 + c < n ? cv[k0 + c] * inv : 0.0;
+                    a[c] = fma(-li, lk, a[c]);
+                }
+            }
+        }
+        if (own) {
+#pragma unroll
+            for (int c = 0; c < 32; ++c) {
+                if (c < kb && k0 + c <= i) A[i * lda + k0 + c] = a[c];
+                P[i * kPpLd + c] = a[c];
+            }
+        }
+        __syncthreads();
+        const int t0 = k0 + kb, nbt = (n - t0 + 15) >> 4, ntile = nbt * (nbt + 1) / 2;
+        for (int tb = 4 * wave; tb < ntile; tb += 32) {
+            int r0[4], c0[4];
+            double cval[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = min(tb + u, ntile - 1);
+                int I = 0;
+                while ((I + 1) * (I + 2) / 2 <= t) ++I;
+                r0[u] = t0 + 16 * I;
+                c0[u] = t0 + 16 * (t - I * (I + 1) / 2);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0[u] + g + 4 * v, c = c0[u] + m;
+                    cval[u][v] = (tb + u < ntile && r < n && c < n) ? A[r * lda + c] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v4g acc = v4g{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(r0[u] + m) * kPpLd + 4 * kk + g],
+                                                               P[(c0[u] + m) * kPpLd + 4 * kk + g], acc, 0, 0, 0);
+                // D layout: rows g + 4v, column m
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0[u] + g + 4 * v, c = c0[u] + m;
+                    if (tb + u < ntile && r < n && c < n) A[r * lda + c] = cval[u][v] - acc[v];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) info[blockIdx.x] = 0;
 }
 
 // Blocked batched Cholesky for large matrices, three launches per panel of kPfB columns
@@ -1290,16 +1386,17 @@ void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, d
     if (t.n_sub && t.max_beta) k_bt_forward_mfma<<<dim3((t.max_beta + 63) / 64, t.n_sub), 256, 0, st>>>(t.subs, t.lines, L, Li, Z);
 }
 
-void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* A, const double* B, double* C,
+void launch_gemm_tn(const GemmDesc* d, int nbatch, int tdim, const double* A, const double* B, double* C,
                     double alpha, double beta, int symmetric, hipStream_t st) {
-    if (nbatch == 0 || max_tiles == 0) return;
-    k_gemm_tn<<<dim3(max_tiles, nbatch), 256, 0, st>>>(d, A, B, C, alpha, beta, symmetric);
+    if (nbatch == 0 || tdim == 0) return;
+    const int tiles = symmetric ? tdim * (tdim + 1) / 2 : tdim * tdim;
+    k_gemm_tn<<<dim3(tiles, 8 * ((nbatch + 7) / 8)), 256, 0, st>>>(d, nbatch, A, B, C, alpha, beta, symmetric);
 }
 
 void launch_potrf(const PotrfDesc* d, int nbatch, int max_n, double* base, int* info, hipStream_t st) {
     if (nbatch == 0) return;
     if (max_n <= 512) {   // one workgroup per matrix
-        k_potrf<<<nbatch, 256, 0, st>>>(d, base, info);
+        k_potrf512<<<nbatch, 512, 0, st>>>(d, base, info);
         return;
     }
     for (int p0 = 0; p0 < max_n; p0 += kPfB) {

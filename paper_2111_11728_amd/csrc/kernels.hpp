@@ -164,7 +164,9 @@ void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, hip
 // Z <- L^{-1} Z with the explicit diagonal inverses (matrix cores; lines <= 128 DOFs)
 void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, double* Z, hipStream_t st);
 void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st);
-void launch_gemm_tn(const GemmDesc* d, int nbatch, int max_tiles, const double* A, const double* B, double* C,
+// C = beta C + alpha A^T B per matrix of the batch; tdim: the largest number of 64-wide tiles
+// along one dimension of C over the batch
+void launch_gemm_tn(const GemmDesc* d, int nbatch, int tdim, const double* A, const double* B, double* C,
                     double alpha, double beta, int symmetric, hipStream_t st);
 // max_n: the largest n of the batch (above 512 the blocked multi-workgroup form runs)
 void launch_potrf(const PotrfDesc* d, int nbatch, int max_n, double* base, int* info, hipStream_t st);
