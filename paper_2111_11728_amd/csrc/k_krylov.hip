@@ -828,12 +828,18 @@ __global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict
             __syncthreads();   // (B_m)
             if (!go) break;
             // Schur-complement update of the remaining columns: A[i][l] -= lc_i lc_l
+            // (the column is read in two batches of sixteen 16-byte loads, all in flight together)
             if (rem) {
 #pragma unroll
-                for (int i = 0; i < 64; i += 2) {
-                    const double2 c2 = *reinterpret_cast<const double2*>(&Lm[m][i]);
-                    a[i] -= c2.x * lc;
-                    a[i + 1] -= c2.y * lc;
+                for (int h = 0; h < 64; h += 32) {
+                    double2 c2[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) c2[u] = *reinterpret_cast<const double2*>(&Lm[m][h + 2 * u]);
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        a[h + 2 * u] -= c2[u].x * lc;
+                        a[h + 2 * u + 1] -= c2[u].y * lc;
+                    }
                 }
                 diag -= lc * lc;
             }
@@ -853,14 +859,22 @@ __global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict
             if (p < 0) break;
             // LmT[p][q] = L_q[p] for q < m; entries q > m are zero (later steps write zeros
             // into row p: index p is no longer a candidate) and x[m] is still zero
-            double s0 = 0.0, s1 = 0.0;
+            // (row p in two batches of sixteen 16-byte loads in flight together, four partial sums)
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-            for (int q = 0; q < 64; q += 2) {
-                const double2 b = *reinterpret_cast<const double2*>(&LmT[p][q]);
-                s0 = fma(b.x, x[q], s0);
-                s1 = fma(b.y, x[q + 1], s1);
+            for (int h = 0; h < 64; h += 32) {
+                double2 bq[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) bq[u] = *reinterpret_cast<const double2*>(&LmT[p][h + 2 * u]);
+#pragma unroll
+                for (int u = 0; u < 16; u += 2) {
+                    s0 = fma(bq[u].x, x[h + 2 * u], s0);
+                    s1 = fma(bq[u].y, x[h + 2 * u + 1], s1);
+                    s2 = fma(bq[u + 1].x, x[h + 2 * u + 2], s2);
+                    s3 = fma(bq[u + 1].y, x[h + 2 * u + 3], s3);
+                }
             }
-            put64(x, m, ((l == p ? 1.0 : 0.0) - (s0 + s1)) * ipv_s[m]);
+            put64(x, m, ((l == p ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3))) * ipv_s[m]);
         }
         const int rank = m;
         // row l of T; components of indices never taken as pivots are exactly zero
