@@ -118,24 +118,57 @@ def pivoted_cholesky(D, rr_tol=1e-12, drop=1e-30):
     return T, rank
 
 
-def simultaneous(op, tol=1e-8, max_it=None, rr_tol=1e-12, one_group=False):
+def deflate(op, Y, r, rr_tol=1e-12):
+    """F-orthonormal basis of span(P Y) in blocks of 64 columns (each block orthogonalised against
+    the previous ones, then F-orthonormalised by the rank-revealing Cholesky of Sec. 3.3) and the
+    correction of the start: returns (Wd, Qd, lt, r) with lt = sum_b W_b W_b^T r0 and
+    r = r0 - P sum_b Q_b W_b^T r0, so that W_b^T r = 0 for every block."""
+    Wd, Qd = [], []
+    lt = np.zeros(op.n_lambda)
+    for c0 in range(0, Y.shape[1], 64):
+        W = op.project(Y[:, c0:c0 + 64])
+        for Wj, Qj in zip(Wd, Qd):
+            W = W - Wj @ (Qj.T @ W)
+        Q = op.apply_F(W)
+        D = Q.T @ W
+        T, rank = pivoted_cholesky(0.5 * (D + D.T), rr_tol)
+        if rank == 0:
+            continue
+        Wd.append(W @ T)
+        Qd.append(Q @ T)
+    for Wb, Qb in zip(Wd, Qd):
+        g = Wb.T @ r
+        lt += Wb @ g
+        r = r - op.project(Qb @ g[:, None])[:, 0]
+    return Wd, Qd, lt, r
+
+
+def simultaneous(op, tol=1e-8, max_it=None, rr_tol=1e-12, one_group=False, Y=None):
     """Algorithm 1 (Sec. 3.3). With one_group=True all subdomains feed a single
-    column: the fully orthogonalised PCG of Sec. 3.2."""
+    column: the fully orthogonalised PCG of Sec. 3.2. Y (n_lambda x m, optional): a deflation
+    space (oracle.deflation); its F-orthonormal basis is stored ahead of the iteration's own
+    directions and the start is corrected (deflate). eps_0 is that of the uncorrected start, so a
+    deflated and a plain solve stop at the same residual measure."""
     n = op.n_lambda
     lam0 = op.lambda0()
     r = op.project((op.d - op.apply_F(lam0[:, None])[:, 0])[:, None])[:, 0]
     Z = op.precondition(r, one_column=one_group)
-    W = op.project(Z)
+    eps0 = np.sqrt(max(float(r @ Z.sum(axis=1)), 0.0))
     lt = np.zeros(n)
     Wh, Qh = [], []
-    eps0 = np.sqrt(max(float(r @ Z.sum(axis=1)), 0.0))
+    if Y is not None and Y.shape[1] > 0 and eps0 > 0.0:
+        Wh, Qh, lt, r = deflate(op, Y, r, rr_tol)
+        Z = op.precondition(r, one_column=one_group)
+    W = op.project(Z)
+    for Wj, Qj in zip(Wh, Qh):
+        W = W - Wj @ (Qj.T @ W)
     hist = [eps0]
     ranks = []
     it = 0
-    kept = 0
+    kept = sum(Wj.shape[1] for Wj in Wh)
     max_it = n if max_it is None else max_it
     status = "ok"
-    conv = eps0 == 0.0
+    conv = eps0 == 0.0 or np.sqrt(max(float(r @ Z.sum(axis=1)), 0.0)) <= tol * eps0
     while not conv and it < max_it and kept < n:
         Q = op.apply_F(W)
         Delta = Q.T @ W
@@ -164,11 +197,13 @@ def simultaneous(op, tol=1e-8, max_it=None, rr_tol=1e-12, one_group=False):
     return Result(lam0 + lt, it, hist, conv, ranks, status)
 
 
-def solve(op, krylov="pcg", tol=1e-8, max_it=None, rr_tol=1e-12):
+def solve(op, krylov="pcg", tol=1e-8, max_it=None, rr_tol=1e-12, Y=None):
     if krylov == "pcg":
+        if Y is not None:
+            raise ValueError("deflation is taken with the orthogonalising iterations (fo, sfeti)")
         return pcg(op, tol, max_it)
     if krylov == "fo":
-        return simultaneous(op, tol, max_it, rr_tol, one_group=True)
+        return simultaneous(op, tol, max_it, rr_tol, one_group=True, Y=Y)
     if krylov == "sfeti":
-        return simultaneous(op, tol, max_it, rr_tol, one_group=False)
+        return simultaneous(op, tol, max_it, rr_tol, one_group=False, Y=Y)
     raise ValueError(krylov)
