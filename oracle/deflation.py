@@ -18,7 +18,10 @@ GenEO. It fixes neither the local problem nor the selection; the reading taken h
   P_s F_s = P_s G G^T are those of the symmetric C_s = G^T P_s G = L^T (omega S_s omega) L (omega = B_s^T diag(w_s) B_s, diagonal:
   the summed weights of each interface DOF), and for C_s x = mu x the vector y = P_s G x is an
   eigenvector of P_s F_s: y = diag(w_s) B_s u with u = S_s omega L x.
-* Selection: the m largest mu of every subdomain (m a parameter), optionally only those >= tau.
+* Selection: an invariant subspace of at most m modes per subdomain that is unique: the k largest
+  mu, k the largest count <= m whose k-th eigenvalue lies above both the threshold tau and a
+  relative gap, mu_k >= (1 + gap) mu_{k+1} (mu_{k+1} = 0 past the spectrum). A cluster of equal
+  eigenvalues is taken whole or not at all, so any eigensolver selects the same space.
 * Deflation: the span of the y of all subdomains is made F-orthonormal (in blocks of 64 columns,
   each orthogonalised against the previous blocks and F-orthonormalised by the rank-revealing
   Cholesky of Sec. 3.3), the start is corrected so that the residual is orthogonal to it, and the
@@ -30,9 +33,19 @@ from __future__ import annotations
 import numpy as np
 
 
-def local_modes(op, s, m, tau=0.0):
-    """(mu, U, Y) of subdomain s: the m largest eigenvalues mu of its local preconditioned
-    operator (those >= tau), the interface-DOF vectors u = S_s omega L x and the dual vectors
+def select_count(mu_desc, m, tau=0.0, gap=0.05):
+    """Number k of leading modes taken from eigenvalues sorted in decreasing order: the largest
+    k <= m with mu_k >= tau and mu_k >= (1 + gap) mu_{k+1}, or 0."""
+    for k in range(min(m, len(mu_desc)), 0, -1):
+        nxt = mu_desc[k] if k < len(mu_desc) else 0.0
+        if mu_desc[k - 1] >= tau and mu_desc[k - 1] >= (1.0 + gap) * nxt:
+            return k
+    return 0
+
+
+def local_modes(op, s, m, tau=0.0, gap=0.05):
+    """(mu, U, Y) of subdomain s: the selected largest eigenvalues mu of its local preconditioned
+    operator (select_count), the interface-DOF vectors u = S_s omega L x and the dual vectors
     y = diag(w_s) B_s u (length n_lambda, zero off the rows of s)."""
     Bb = op.cons.Bb[s]
     rows = np.unique(Bb.nonzero()[0])
@@ -50,19 +63,19 @@ def local_modes(op, s, m, tau=0.0):
     S = np.asarray(op.S[s])
     C = L.T @ (omega[:, None] * S * omega[None, :]) @ L
     mu, X = np.linalg.eigh(0.5 * (C + C.T))
-    order = np.argsort(mu)[::-1][:m]
-    order = order[mu[order] >= tau]
+    desc = np.argsort(mu)[::-1]
+    order = desc[:select_count(mu[desc], m, tau, gap)]
     U = S @ (omega[:, None] * (L @ X[:, order]))
     Y = np.zeros((op.n_lambda, order.size))
     Y[rows] = w[:, None] * (Bs @ U)
     return mu[order], U, Y
 
 
-def deflation_space(op, m, tau=0.0):
+def deflation_space(op, m, tau=0.0, gap=0.05):
     """Y = [y of subdomain 0 | y of subdomain 1 | ...] and the eigenvalues, subdomain by subdomain."""
     mus, Ys = [], []
     for s in range(len(op.dec.subs)):
-        mu, _, Y = local_modes(op, s, m, tau)
+        mu, _, Y = local_modes(op, s, m, tau, gap)
         mus.append(mu)
         Ys.append(Y)
     return np.hstack(Ys) if Ys else np.zeros((op.n_lambda, 0)), mus

@@ -8,6 +8,7 @@ read as in oracle/deflation.py), no GPU:
   TFETI);
 * a deflation space spanning the whole dual space solves the problem before the first iteration;
 * after the start correction the residual is orthogonal to the deflation space;
+* the selection takes a cluster of equal eigenvalues whole or not at all;
 * on the layered grid the orthogonalised PCG needs far fewer iterations with the 8 largest local
   modes of every subdomain deflated (measured here: FETI-DP 61 -> 18)."""
 import numpy as np
@@ -26,7 +27,7 @@ def test_local_modes_are_eigenpairs_of_the_local_preconditioned_operator(method)
     prob = workloads.inclusion_grid(nsub=(3, 2), m=6)
     op = _op(prob, method)
     for s in range(len(op.dec.subs)):
-        mu, _, Y = deflation.local_modes(op, s, 5)
+        mu, _, Y = deflation.local_modes(op, s, 5, gap=0.0)
         Bb = op.cons.Bb[s]
         rows = np.unique(Bb.nonzero()[0])
         Bs = Bb[rows].toarray()
@@ -54,6 +55,15 @@ def test_deflated_solve_reaches_the_direct_solution(method, kind):
     assert np.linalg.norm(u - u_star) <= 1e-8 * np.linalg.norm(u_star)
 
 
+def test_selection_takes_clusters_whole():
+    mu = np.array([5.0, 4.0, 3.0, 3.0, 3.0, 1.0])
+    assert deflation.select_count(mu, 3) == 2          # the cluster at 3 would be cut
+    assert deflation.select_count(mu, 5) == 5
+    assert deflation.select_count(mu, 8) == 6          # past the spectrum mu_{k+1} = 0
+    assert deflation.select_count(mu, 8, tau=3.5) == 2
+    assert deflation.select_count(np.full(4, 2.0), 2) == 0
+
+
 def test_full_space_deflation_solves_before_iterating():
     prob = workloads.cantilever_tfeti(2, nsub=(2, 2), m=4)
     op = _op(prob, "fetidp")
@@ -69,7 +79,7 @@ def test_full_space_deflation_solves_before_iterating():
 def test_residual_orthogonal_to_the_deflation_space(method):
     prob = workloads.inclusion_grid(nsub=(3, 3), m=6)
     op = _op(prob, method)
-    Y, _ = deflation.deflation_space(op, 4)
+    Y, _ = deflation.deflation_space(op, 4, gap=0.0)   # the selection is not what is tested here
     r0 = op.project((op.d - op.apply_F(op.lambda0()[:, None])[:, 0])[:, None])[:, 0]
     Wd, Qd, lt, r = krylov.deflate(op, Y, r0.copy())
     W = np.hstack(Wd)
