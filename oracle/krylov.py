@@ -28,9 +28,11 @@ class Result:
     status: str = "ok"
 
 
-def pcg(op, tol=1e-8, max_it=None):
+def pcg(op, tol=1e-8, max_it=None, Y=None):
     """Projected PCG: r = P(d - F lam), z = M r, w = P z (+ beta w_prev),
-    q = F w, a = r^T z / w^T q, lam += a w, r -= a P q."""
+    q = F w, a = r^T z / w^T q, lam += a w, r -= a P q. Y (optional): a deflation space
+    (oracle.deflation): the start is corrected (deflate) and the new part P z of every direction is
+    made F-orthogonal to it (deflated CG); eps_0 is that of the uncorrected start."""
     n = op.n_lambda
     max_it = n if max_it is None else max_it
     lam0 = op.lambda0()
@@ -40,9 +42,20 @@ def pcg(op, tol=1e-8, max_it=None):
     eps0 = np.sqrt(max(rz, 0.0))
     hist = [eps0]
     lt = np.zeros(n)
-    w = op.project(z[:, None])[:, 0]
+    Wd, Qd = [], []
+    if Y is not None and Y.shape[1] > 0 and eps0 > 0.0:
+        Wd, Qd, lt, r = deflate(op, Y, r)
+        z = op.precondition(r, one_column=True)[:, 0]
+        rz = float(r @ z)
+
+    def deflated(v):
+        for Wj, Qj in zip(Wd, Qd):
+            v = v - Wj @ (Qj.T @ v)
+        return v
+
+    w = deflated(op.project(z[:, None])[:, 0])
     it = 0
-    conv = eps0 == 0.0
+    conv = eps0 == 0.0 or np.sqrt(max(rz, 0.0)) <= tol * eps0
     while not conv and it < max_it:
         q = op.apply_F(w[:, None])[:, 0]
         wq = float(w @ q)
@@ -60,7 +73,7 @@ def pcg(op, tol=1e-8, max_it=None):
             break
         beta = rz_new / rz
         rz = rz_new
-        w = op.project(z[:, None])[:, 0] + beta * w
+        w = deflated(op.project(z[:, None])[:, 0]) + beta * w
     return Result(lam0 + lt, it, hist, conv)
 
 
@@ -199,9 +212,7 @@ def simultaneous(op, tol=1e-8, max_it=None, rr_tol=1e-12, one_group=False, Y=Non
 
 def solve(op, krylov="pcg", tol=1e-8, max_it=None, rr_tol=1e-12, Y=None):
     if krylov == "pcg":
-        if Y is not None:
-            raise ValueError("deflation is taken with the orthogonalising iterations (fo, sfeti)")
-        return pcg(op, tol, max_it)
+        return pcg(op, tol, max_it, Y=Y)
     if krylov == "fo":
         return simultaneous(op, tol, max_it, rr_tol, one_group=True, Y=Y)
     if krylov == "sfeti":

@@ -4,8 +4,8 @@ read as in oracle/deflation.py), no GPU:
 * the local eigenvalues mu against the nonzero eigenvalues of the dense local product P_s F_s
   (a general eigensolver on the product, not the symmetric reduction the oracle takes), and the
   dual vectors y as its eigenvectors;
-* deflated S-FETI and fully orthogonalised PCG reach the global direct solution (FETI-DP and
-  TFETI);
+* deflated S-FETI, fully orthogonalised PCG and PCG reach the global direct solution (FETI-DP
+  and TFETI);
 * a deflation space spanning the whole dual space solves the problem before the first iteration;
 * after the start correction the residual is orthogonal to the deflation space;
 * the selection takes a cluster of equal eigenvalues whole or not at all;
@@ -43,7 +43,8 @@ def test_local_modes_are_eigenpairs_of_the_local_preconditioned_operator(method)
         assert np.all(Y[np.setdiff1d(np.arange(op.n_lambda), rows)] == 0.0)
 
 
-@pytest.mark.parametrize("method,kind", [("fetidp", "sfeti"), ("fetidp", "fo"), ("tfeti", "sfeti"), ("tfeti", "fo")])
+@pytest.mark.parametrize("method,kind", [("fetidp", "sfeti"), ("fetidp", "fo"), ("fetidp", "pcg"), ("tfeti", "sfeti"),
+                                         ("tfeti", "fo"), ("tfeti", "pcg")])
 def test_deflated_solve_reaches_the_direct_solution(method, kind):
     prob = workloads.cantilever_tfeti(1, nsub=(3, 2), m=6)
     op = _op(prob, method)
@@ -93,11 +94,12 @@ def test_residual_orthogonal_to_the_deflation_space(method):
     assert np.abs(PY.T @ r).max() <= 1e-9 * np.abs(PY).max() * np.linalg.norm(r0)
 
 
-def test_fewer_iterations_on_the_layered_grid():
+@pytest.mark.parametrize("kind", ["fo", "pcg"])
+def test_fewer_iterations_on_the_layered_grid(kind):
     prob = workloads.layered_grid()
     op = _op(prob, "fetidp")
-    plain = krylov.solve(op, "fo", tol=1e-6)
+    plain = krylov.solve(op, kind, tol=1e-6)
     Y, mus = deflation.deflation_space(op, 8)
-    defl = krylov.solve(op, "fo", tol=1e-6, Y=Y)
+    defl = krylov.solve(op, kind, tol=1e-6, Y=Y)
     assert plain.converged and defl.converged
     assert defl.iters <= plain.iters // 2, (plain.iters, defl.iters)
