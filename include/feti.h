@@ -129,6 +129,23 @@ typedef struct {
                                  element check) and only one of each group is factorised and gets its
                                  local operators, which the others then use. Results are bit-identical
                                  to a setup without recycling. Single design only; 0 = off */
+    int defl_modes;           /* deflation of local interface modes (Sec. 6, item (ii): the
+                                 interface modes that slow the iteration are found by local
+                                 eigenproblems, as in GenEO, and taken out of the iteration).
+                                 Reading: for every subdomain s, the eigenpairs of its local
+                                 preconditioned operator P_s F_s (P_s its weighted preconditioner
+                                 block on its dual rows, F_s its block of the dual operator),
+                                 computed as C_s = L^T (omega S~ omega) L with F_s = L L^T and
+                                 omega the summed weights of each interface DOF; of its largest
+                                 eigenvalues, the k <= defl_modes (1..8) leading ones that end at
+                                 a 5% spectral gap, mu_k >= 1.05 mu_{k+1}, and lie above defl_tau.
+                                 The dual vectors y = diag(w_s) B_s S~ omega L x of all subdomains
+                                 are made F-orthonormal once per setup; every solve corrects its
+                                 start so that the residual is orthogonal to them, and FO, S-FETI
+                                 and PCG orthogonalise each new search direction against them
+                                 (deflated iterations). FETI-DP only, interface blocks of 32 to
+                                 576 DOFs; 0 = off */
+    double defl_tau;          /* deflation: smallest eigenvalue taken (0 = no threshold) */
 } feti_opts;
 
 typedef struct {
@@ -165,6 +182,9 @@ typedef struct {
                                  products run on the FP64 matrix cores inside a reduced-precision solve) */
     int n_setup_subs;         /* subdomains factorised at the last setup (n_sub unless opts.recycle
                                  found repeated module types) */
+    int n_defl;               /* opts.defl_modes: local modes selected at the last setup (all
+                                 subdomains), and the F-orthonormal deflation directions kept */
+    int n_defl_kept;
 } feti_sizes;
 
 /* One design of a batched context: its ranges in the concatenated arrays. */
@@ -296,6 +316,14 @@ feti_status feti_compliance_and_grad(feti_ctx* ctx, const double* rho, const dou
  * for a later warm start (feti_solve's lambda_init). lambda: device [n_lambda] output. FETI_EINVAL
  * before the first solve. */
 feti_status feti_get_lambda(feti_ctx* ctx, double* lambda);
+
+/* The local modes selected by opts.defl_modes at the last setup (deflation of local interface
+ * modes; Sec. 6, item (ii)). mu: device [n_sub * defl_modes], eigenvalue i of subdomain s at
+ * s * defl_modes + i in decreasing order, 0 past the modes selected for s; Y: device, optional,
+ * [n_lambda x n_defl] row-major, the dual vectors y of the selected modes, subdomain by subdomain
+ * (the vectors before F-orthonormalisation; the sign of each is arbitrary). FETI_EINVAL when the
+ * context has no deflation. */
+feti_status feti_get_deflation(feti_ctx* ctx, double* mu, double* Y);
 
 /* One design update of the SIMP problem of Sec. 1 (minimum compliance c(rho) = f^T u under a bound
  * on the material volume, unit element volumes) by optimality criteria: with B_e(L) =

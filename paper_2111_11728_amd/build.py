@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfeti.so")
 OBJ = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["k_setup.hip", "k_apply.hip", "k_krylov.hip", "k_solve.hip", "k_design.hip", "feti_api.hip"]
+HIP_SOURCES = ["k_setup.hip", "k_apply.hip", "k_krylov.hip", "k_solve.hip", "k_design.hip", "k_deflation.hip",
+               "feti_api.hip"]
 CXX_SOURCES = ["plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -212,6 +212,18 @@ struct feti_ctx {
     TrsmDesc *d_trsm = nullptr, *d_trsm_one = nullptr;
     int syrk_tdim = 0, F_tdim = 0, max_nb_cols = 0;
     int n_alpha = 0;
+    // deflation of local interface modes (opts.defl_modes): local operators at off_P (F_s factor,
+    // omega S~ omega, their product, C_s), interface weights omega, modes U (8 per interface DOF),
+    // eigenvalues, counts and first columns per subdomain, the dual vectors Y and their
+    // F-orthonormal blocks dfW / dfQ (n_lambda x 64 each, df_nd of them kept)
+    double *dfL = nullptr, *dfM = nullptr, *dfB = nullptr, *dfC = nullptr, *dfOmega = nullptr, *dfU = nullptr,
+           *dfMu = nullptr, *dfY = nullptr, *dfPsi = nullptr, *dfPad = nullptr;
+    int *dfCnt = nullptr, *dfCol0 = nullptr;
+    GemmDesc* d_df = nullptr;
+    std::vector<double*> dfW, dfQ;
+    const double** dfW_dev = nullptr;
+    const double** dfQ_dev = nullptr;
+    int df_cap = 0, df_nd = 0, n_defl = 0, n_defl_kept = 0;
 
     // solve buffers
     double *f_last = nullptr, *fi = nullptr, *fbeta = nullptr, *h = nullptr, *g = nullptr, *yb = nullptr,
@@ -655,6 +667,36 @@ void build_layout(feti_ctx* c) {
     c->d_F = c->upload(dF);
     c->d_potrf = c->upload(dpo);
     c->d_trsm = c->upload(dtr);
+    if (c->opts.defl_modes > 0 && P.n_lambda > 0) {
+        const long long oPt = oP;
+        std::vector<GemmDesc> dd(ns);
+        for (int s = 0; s < ns; ++s) {
+            const SubMeta& M = c->hsubs[s];
+            dd[s] = GemmDesc{M.off_P, M.off_P, M.off_P, M.n_b, M.n_b, M.n_b, M.n_b, M.n_b, M.n_b};
+        }
+        c->d_df = c->upload(dd);
+        c->dfL = c->alloc<double>(oPt);
+        c->dfM = c->alloc<double>(oPt);
+        c->dfB = c->alloc<double>(oPt);
+        c->dfC = c->alloc<double>(oPt);
+        c->dfOmega = c->alloc<double>(t.nb_tot);
+        c->dfU = c->alloc<double>(8 * t.nb_tot);
+        c->dfMu = c->alloc<double>((long long)ns * c->opts.defl_modes);
+        c->dfCnt = c->alloc<int>(ns);
+        c->dfCol0 = c->alloc<int>(ns);
+        c->df_cap = (ns * c->opts.defl_modes + 63) / 64;
+        const long long blk = (long long)P.n_lambda * 64;
+        c->dfY = c->alloc<double>(blk * c->df_cap);
+        double* wq = c->alloc<double>(2 * blk * c->df_cap);
+        for (int b = 0; b < c->df_cap; ++b) {
+            c->dfW.push_back(wq + blk * (2ll * b));
+            c->dfQ.push_back(wq + blk * (2ll * b + 1));
+        }
+        c->dfW_dev = c->upload(std::vector<const double*>(c->dfW.begin(), c->dfW.end()));
+        c->dfQ_dev = c->upload(std::vector<const double*>(c->dfQ.begin(), c->dfQ.end()));
+        c->dfPsi = c->alloc<double>(4096ll * c->df_cap);
+        c->dfPad = c->alloc<double>(blk);
+    }
     c->rep_of.resize(ns);
     for (int s = 0; s < ns; ++s) c->rep_of[s] = s;
     c->n_setup_subs = ns;
@@ -1097,6 +1139,8 @@ std::vector<int> find_modules(feti_ctx* c) {
 }
 
 // Assembly, factorisation and explicit local operators for the current densities.
+void build_deflation(feti_ctx* c);
+
 void numeric_setup(feti_ctx* c) {
     c->drop_graphs();
     Timer tm(c, 2);
@@ -1248,6 +1292,7 @@ void numeric_setup(feti_ctx* c) {
         CHECK_LAUNCH();
         dense_spd_inverse(c, c->n_alpha, c->GG, c->GG_w, c->GG_inv, "G G^T Cholesky");
     }
+    build_deflation(c);
     tm.stop();
 }
 
@@ -1488,6 +1533,99 @@ void ensure_history(feti_ctx* c, int kd, int need) {
     }
 }
 
+// Deflation of local interface modes (opts.defl_modes; Sec. 6, item (ii)), after the rest of the
+// setup: per subdomain F_s = L L^T, B = (omega S~ omega) L, C_s = L^T B, the selected largest
+// eigenpairs of C_s, the dual vectors y = diag(w_s) B_s omega^{-1} B x in Y, and the F-orthonormal
+// basis of span(Y) in blocks of 64: each block orthogonalised against the kept ones, multiplied by
+// F (FP64), F-orthonormalised by the rank-revealing Cholesky of its Gram matrix (Sec. 3.3).
+void build_deflation(feti_ctx* c) {
+    c->df_nd = c->n_defl = c->n_defl_kept = 0;
+    const int m = c->opts.defl_modes;
+    const int n = c->P.n_lambda;
+    if (m <= 0 || n == 0) return;
+    DevTopo& t = c->t;
+    hipStream_t st = c->st;
+    const int ns = t.n_sub;
+    launch_defl_local(t, c->F64, c->Pk, c->bg_w, c->dfOmega, c->dfL, c->dfM, st);
+    HIPCHK(hipMemsetAsync(c->info, 0, sizeof(int) * (ns + 8), st));
+    launch_potrf(c->d_potrf, ns, t.max_nb, c->dfL, c->info, st);
+    CHECK_LAUNCH();
+    check_info(c, ns, "deflation: Cholesky of F_s");
+    launch_defl_tril(t, c->dfL, st);
+    launch_gemm_tn(c->d_df, ns, c->F_tdim, c->dfM, c->dfL, c->dfB, 1.0, 0.0, 0, st);   // B = M^T L = M L
+    launch_gemm_tn(c->d_df, ns, c->F_tdim, c->dfL, c->dfB, c->dfC, 1.0, 0.0, 1, st);   // C = L^T B
+    launch_defl_eig(t, c->dfC, c->dfB, c->dfOmega, m, c->opts.defl_tau, kDeflGap, kDeflIters, c->dfU, c->dfMu,
+                    c->dfCnt, st);
+    CHECK_LAUNCH();
+    std::vector<int> cnt(ns), col0(ns);
+    HIPCHK(hipMemcpyAsync(cnt.data(), c->dfCnt, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int tot = 0;
+    for (int s = 0; s < ns; ++s) {
+        col0[s] = tot;
+        tot += cnt[s];
+    }
+    c->n_defl = tot;
+    if (tot == 0) return;
+    HIPCHK(hipMemcpyAsync(c->dfCol0, col0.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+    const int nblk = (tot + 63) / 64;
+    const long long blk = (long long)n * 64;
+    HIPCHK(hipMemsetAsync(c->dfY, 0, sizeof(double) * blk * nblk, st));
+    launch_defl_scatter(t, c->bg_w, c->dfU, c->dfCol0, c->dfCnt, c->dfY, st);
+    CHECK_LAUNCH();
+    const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
+    for (int b = 0; b < nblk; ++b) {
+        HIPCHK(hipMemcpyAsync(c->Zk, c->dfY + blk * b, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+        if (c->df_nd > 0) {
+            launch_gram(n, 64, 64, c->dfQ_dev, c->df_nd, c->Zk, c->part, c->dfPsi, st, false);
+            launch_ts_gemm(n, 64, c->df_nd, c->dfW_dev, c->dfPsi, c->Zk, c->Zk, -1.0, 1.0, st, false);
+        }
+        apply_F(c, 64, FETI_FP64, c->Zk, c->Qk);
+        launch_gram(n, 64, 64, c->qk_ptr, 1, c->Zk, c->part, c->Delta, st);
+        launch_pivchol(64, c->Delta, rr_tol, c->Tm, c->rank_dev, st, nullptr);
+        launch_ts_pair(n, 64, c->zk_ptr, c->qk_ptr, c->Tm, c->dfW[c->df_nd], c->dfQ[c->df_nd], st);
+        CHECK_LAUNCH();
+        int rank = 0;
+        HIPCHK(hipMemcpyAsync(c->hpin, c->rank_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::memcpy(&rank, c->hpin, sizeof(int));
+        if (rank > 0) {
+            ++c->df_nd;
+            c->n_defl_kept += rank;
+        }
+    }
+}
+
+// Z (n_lambda x kd, kd <= 64) <- Z - W_d (Q_d^T Z) against the kept deflation blocks (narrower
+// blocks go through the leading columns of a zero 64-column block, so that the 64-wide Gram and
+// update kernels serve every width)
+void orth_defl(feti_ctx* c, int kd, double* Z) {
+    if (c->df_nd == 0) return;
+    const int n = c->P.n_lambda;
+    hipStream_t st = c->st;
+    double* B = Z;
+    if (kd != 64) {
+        HIPCHK(hipMemsetAsync(c->dfPad, 0, sizeof(double) * n * 64, st));
+        launch_pad64(n, kd, 0, Z, c->dfPad, st);
+        B = c->dfPad;
+    }
+    launch_gram(n, 64, 64, c->dfQ_dev, c->df_nd, B, c->part, c->dfPsi, st, false);
+    launch_ts_gemm(n, 64, c->df_nd, c->dfW_dev, c->dfPsi, B, B, -1.0, 1.0, st, false);
+    if (kd != 64) launch_pad64(n, kd, 1, Z, c->dfPad, st);
+    CHECK_LAUNCH();
+}
+
+// start correction of a pass: lam += W_d W_d^T r, r -= Q_d W_d^T r (block by block), so that the
+// residual is orthogonal to the deflation space
+void deflate_start(feti_ctx* c) {
+    const int n = c->P.n_lambda;
+    for (int b = 0; b < c->df_nd; ++b) {
+        launch_gemv_t(n, 64, c->dfW[b], c->r, c->part, c->gam, c->st);
+        launch_update_lr(n, 64, c->dfW[b], c->dfQ[b], c->gam, c->lam, c->r, c->st, nullptr);
+    }
+    CHECK_LAUNCH();
+}
+
 struct KrylovOut {
     int iters = 0;
     int reduced = 0;   // iterations that applied the reduced-precision operator
@@ -1591,6 +1729,7 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
     precondition(c, c->r, c->zv, 1, 0);
     HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     project(c, 1, c->Zk);  // w = P z
+    orth_defl(c, 1, c->Zk);
     ddot(c, n, c->r, c->zv, 0);
     launch_seg_dot(c->t, 1, c->r, c->zv, c->part, c->scal + 16, st);
     double rz = read_scalars(c);
@@ -1633,6 +1772,7 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
             if (converged(c, o.eps, eps0, tol)) break;
             HIPCHK(hipMemcpyAsync(c->Zk, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
             project(c, 1, c->Zk);
+            orth_defl(c, 1, c->Zk);
             CHECK_LAUNCH();
             continue;
         }
@@ -1640,6 +1780,7 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
         rz = rz_new;
         HIPCHK(hipMemcpyAsync(c->Qtmp, c->zv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         project(c, 1, c->Qtmp);
+        orth_defl(c, 1, c->Qtmp);
         launch_axpby(n, 1.0, c->Qtmp, beta, c->Zk, st);
         CHECK_LAUNCH();
     }
@@ -1668,6 +1809,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
                 launch_ts_gemm(n, kd, nb_, c->WH_dev, c->Psi, Z, Z, -1.0, 1.0, st, f32);
             }
         }
+        orth_defl(c, kd, Z);
     };
     // Opt-in (orth_fp32): iterations on the reduced-precision operator also orthogonalise with the
     // FP32 forms. Their error tilts the new block against the stored ones in the F-inner product:
@@ -1700,6 +1842,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
     o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
     if (converged(c, o.eps, eps0, tol)) return o;
     project(c, kd, c->Zk);  // W_0 = P Z_0 (in place)
+    orth_defl(c, kd, c->Zk);
     // several designs: each stops searching (its direction columns are zeroed) once it has
     // converged or its kept directions span its own dual space, as a single design would
     const int nds = (int)c->designs.size();
@@ -1881,6 +2024,7 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
             launch_gram(n, kd, kd, c->QH_dev, nb_, c->Zk, c->part, c->Psi, st, false);
             launch_ts_gemm(n, kd, nb_, c->WH_dev, c->Psi, c->Zk, c->Zk, -1.0, 1.0, st, false);
         }
+        orth_defl(c, kd, c->Zk);
     };
     auto residual_dots = [&] {
         launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
@@ -1891,6 +2035,7 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
     o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
     if (converged(c, o.eps, eps0, tol) || max_it < 1) return o;
     project(c, kd, c->Zk);   // W_0 = P Z_0 (in place)
+    orth_defl(c, kd, c->Zk);
     // lambda correction buffers: buf(head) is the output of the last iteration enqueued
     int head = 0;
     auto buf = [&](int i) { return i == 0 ? c->lt : c->lt2; };
@@ -2138,6 +2283,7 @@ feti_status do_solve(feti_ctx* c, const double* f, double* u, const double* lam_
         if (eps0 > 0.0) {
             for (int pass = 0;; ++pass) {
                 HIPCHK(hipMemsetAsync(c->lt, 0, sizeof(double) * n, st));
+                if (c->df_nd > 0) deflate_start(c);
                 KrylovOut o;
                 const int left = max_it - tot.iters;
                 gate.prec = cur;
@@ -2371,6 +2517,10 @@ feti_status feti_setup(const feti_mesh* mesh, const feti_partition* part, const 
     if (!err.empty()) return fail(FETI_EINVAL, err);
     if (opts->krylov == FETI_SFETI && c->P.n_groups > kMaxDirs)
         return fail(FETI_EINVAL, "more than 64 simultaneous directions: set partition.group");
+    if (opts->defl_modes < 0 || opts->defl_modes > kDeflMaxModes || !(opts->defl_tau >= 0.0))
+        return fail(FETI_EINVAL, "defl_modes must lie in 0..8 and defl_tau be >= 0");
+    if (opts->defl_modes > 0 && (opts->method != FETI_DP || opts->recycle))
+        return fail(FETI_EINVAL, "deflation of local modes needs FETI-DP without factorisation recycling");
     c->opts = *opts;
     c->p = p;
     c->E0 = E0;
@@ -2396,6 +2546,7 @@ feti_status feti_setup_batched(int n_designs, const feti_mesh* meshes, const fet
     feti_status vs = validate_opts(opts);
     if (vs != FETI_OK) return vs;
     if (opts->method != FETI_DP) return fail(FETI_EINVAL, "batched designs need FETI-DP");
+    if (opts->defl_modes != 0) return fail(FETI_EINVAL, "deflation of local modes needs a single design");
     if (!(p >= 1.0) || !(E0 > 0.0) || !(Emin > 0.0) || !(Emin < E0))
         return fail(FETI_EINVAL, "need p >= 1 and 0 < Emin < E0");
     if (!rho) return fail(FETI_EINVAL, "null density array");
@@ -2595,6 +2746,24 @@ feti_status feti_get_lambda(feti_ctx* c, double* lambda) {
     });
 }
 
+feti_status feti_get_deflation(feti_ctx* c, double* mu, double* Y) {
+    if (!c || !mu) return fail(FETI_EINVAL, "null argument");
+    if (c->opts.defl_modes <= 0 || !c->dfMu) return fail(FETI_EINVAL, "the context has no deflation");
+    return guarded([&]() -> feti_status {
+        hipStream_t st = c->st;
+        HIPCHK(hipMemcpyAsync(mu, c->dfMu, sizeof(double) * c->t.n_sub * c->opts.defl_modes, hipMemcpyDeviceToDevice,
+                              st));
+        const long long n = c->P.n_lambda;
+        if (Y && c->n_defl > 0)
+            for (int b = 0; 64 * b < c->n_defl; ++b) {
+                const int w = std::min(64, c->n_defl - 64 * b);
+                HIPCHK(hipMemcpy2DAsync(Y + 64 * b, sizeof(double) * c->n_defl, c->dfY + n * 64 * b, sizeof(double) * 64,
+                                        sizeof(double) * w, n, hipMemcpyDeviceToDevice, st));
+            }
+        return FETI_OK;
+    });
+}
+
 feti_status feti_oc_update(feti_ctx* c, const double* rho, const double* dc, double volfrac, double move, double eta,
                            double rho_min, double* rho_new, double* lagrange) {
     if (!c || !rho || !dc || !rho_new) return fail(FETI_EINVAL, "null argument");
@@ -2660,6 +2829,8 @@ feti_status feti_get_sizes(feti_ctx* c, feti_sizes* out) {
     z.n_fp64_subs = c->n_fp64_subs;
     z.n_designs = (int)c->designs.size();
     z.n_setup_subs = c->n_setup_subs;
+    z.n_defl = c->n_defl;
+    z.n_defl_kept = c->n_defl_kept;
     z.sum_nb2_fp64 = 0;
     if (c->hybrid)
         for (int s = 0; s < P.n_sub; ++s)

@@ -164,6 +164,24 @@ void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, hip
 // Z <- L^{-1} Z with the explicit diagonal inverses (matrix cores; lines <= 128 DOFs)
 void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, double* Z, hipStream_t st);
 void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st);
+// along one dimension of C over the batch
+// Deflation of local interface modes: subspace width, the largest interface block held in LDS,
+// modes per subdomain, subspace iterations and the relative spectral gap that ends a selection
+constexpr int kDeflSubspace = 16;
+constexpr int kDeflMaxNb = 576;
+constexpr int kDeflMaxModes = 8;
+constexpr int kDeflIters = 40;
+constexpr double kDeflGap = 0.05;
+// omega (summed weights of each interface DOF), DL = F_s, DM = omega S~ omega (n_b x n_b at off_P)
+void launch_defl_local(const DevTopo& t, const double* F64, const double* Pk, const double* bg_w, double* omega,
+                       double* DL, double* DM, hipStream_t st);
+void launch_defl_tril(const DevTopo& t, double* DL, hipStream_t st);
+void launch_defl_eig(const DevTopo& t, const double* DC, const double* DB, const double* omega, int m, double tau,
+                     double gap, int n_it, double* U, double* mu, int* cnt, hipStream_t st);
+void launch_defl_scatter(const DevTopo& t, const double* bg_w, const double* U, const int* col0, const int* cnt,
+                         double* Y, hipStream_t st);
+// the first kd columns of the n x 64 block P from the n x kd block Z (dir 0), or back (dir 1)
+void launch_pad64(int n, int kd, int dir, double* Z, double* P, hipStream_t st);
 // C = beta C + alpha A^T B per matrix of the batch; tdim: the largest number of 64-wide tiles
 // along one dimension of C over the batch
 void launch_gemm_tn(const GemmDesc* d, int nbatch, int tdim, const double* A, const double* B, double* C,

@@ -45,7 +45,8 @@ class feti_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("scaling", C.c_int), ("krylov", C.c_int), ("precond", C.c_int),
                 ("precision", C.c_int), ("tol", C.c_double), ("max_it", C.c_int), ("rr_tol", C.c_double),
                 ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double), ("graphs", C.c_int),
-                ("orth_fp32", C.c_int), ("warm_start", C.c_int), ("recycle", C.c_int)]
+                ("orth_fp32", C.c_int), ("warm_start", C.c_int), ("recycle", C.c_int), ("defl_modes", C.c_int),
+                ("defl_tau", C.c_double)]
 
 
 class feti_info(C.Structure):
@@ -79,7 +80,8 @@ class feti_sizes(C.Structure):
                 ("n_alpha", C.c_int), ("n_groups", C.c_int), ("nb_max", C.c_int), ("nb_min", C.c_int),
                 ("n_loc_max", C.c_int), ("n_i_max", C.c_int), ("band_max", C.c_int), ("sum_nb2", C.c_longlong),
                 ("sum_nb_nc", C.c_longlong), ("device_bytes", C.c_longlong), ("n_fp64_subs", C.c_int),
-                ("n_designs", C.c_int), ("sum_nb2_fp64", C.c_longlong), ("n_setup_subs", C.c_int)]
+                ("n_designs", C.c_int), ("sum_nb2_fp64", C.c_longlong), ("n_setup_subs", C.c_int),
+                ("n_defl", C.c_int), ("n_defl_kept", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +113,7 @@ def lib():
             "feti_get_sizes": (I, [P, C.POINTER(feti_sizes)]),
             "feti_apply_F": (I, [P, I, I, P, P]),
             "feti_get_lambda": (I, [P, P]),
+            "feti_get_deflation": (I, [P, P, P]),
             "feti_oc_update": (I, [P, P, P, D, D, D, D, P, C.POINTER(C.c_double)]),
             "feti_adaptive_primal": (I, [C.POINTER(feti_mesh), C.POINTER(feti_partition), P, D, D, D, D, I,
                                          C.POINTER(C.c_int), I, C.POINTER(C.c_int)]),
@@ -160,7 +163,7 @@ class Spec:
 
     def __init__(self, prob, method="fetidp", scaling="k", krylov="pcg", precond="dirichlet", precision="fp64",
                  tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0, graphs=0, orth_fp32=0,
-                 primal_nodes=None, warm_start=0, recycle=0):
+                 primal_nodes=None, warm_start=0, recycle=0, defl_modes=0, defl_tau=0.0):
         self.prob = prob
         fixed = np.ascontiguousarray(prob.fixed_dofs(), dtype=np.int32)
         self._fixed = fixed
@@ -189,7 +192,7 @@ class Spec:
                                   else C.POINTER(C.c_int)())
         self.opts = feti_opts(METHODS[method], SCALINGS[scaling], KRYLOVS[krylov], PRECONDS[precond],
                               PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax, graphs,
-                              orth_fp32, warm_start, recycle)
+                              orth_fp32, warm_start, recycle, defl_modes, defl_tau)
 
 
 def feti_plan_sizes(spec: Spec) -> dict:
@@ -292,6 +295,9 @@ class Context:
 
     def feti_get_lambda(self, lam):
         _check(lib().feti_get_lambda(self.handle, _ptr(lam)))
+
+    def feti_get_deflation(self, mu, Y=None):
+        _check(lib().feti_get_deflation(self.handle, _ptr(mu), _ptr(Y)))
 
     def feti_oc_update(self, rho, dc, rho_new, volfrac, move=0.2, eta=0.5, rho_min=1e-3):
         """Returns the multiplier L of the volume bound."""
