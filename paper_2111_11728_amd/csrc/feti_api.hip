@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -235,9 +236,10 @@ struct feti_ctx {
            *scal = nullptr, *Psi = nullptr, *tmpv = nullptr, *zv = nullptr, *K0dev = nullptr;
     int* rank_dev = nullptr;         // inside scal (scal[8]), so one copy returns eps and rank
     double* hpin = nullptr;          // pinned host mirror of scal
-    // one-ahead S-FETI loop: per-iteration copies of scal (two slots) and their completion events
-    double* hslot[2] = {nullptr, nullptr};
-    hipEvent_t evr[2] = {nullptr, nullptr};
+    // one-ahead S-FETI loop: per-iteration copies of scal (two slots), published by the device
+    double* hslot[2] = {nullptr, nullptr};       // coherent, host-mapped: scalars, then a sequence number
+    double* hslot_dev[2] = {nullptr, nullptr};   // their device addresses
+    long long pub_seq = 0;                       // last sequence number published
     const double** qk_ptr = nullptr;    // device table holding the single pointer Qk
     const double** zk_ptr = nullptr;    // device table holding the single pointer Zk
     double* tcbuf = nullptr;            // coarse right-hand sides t (n_cg x k)
@@ -283,7 +285,6 @@ struct feti_ctx {
         if (hpin) hipHostFree(hpin);
         for (int q = 0; q < 2; ++q) {
             if (hslot[q]) hipHostFree(hslot[q]);
-            if (evr[q]) hipEventDestroy(evr[q]);
         }
         if (WH_dev) hipFree(WH_dev);
         if (QH_dev) hipFree(QH_dev);
@@ -968,8 +969,10 @@ void build_layout(feti_ctx* c) {
     c->rank_dev = reinterpret_cast<int*>(c->scal + 8);
     HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(double) * (16 + 3 * nd), hipHostMallocDefault));
     for (int q = 0; q < 2; ++q) {
-        HIPCHK(hipHostMalloc((void**)&c->hslot[q], sizeof(double) * (16 + 3 * nd), hipHostMallocDefault));
-        HIPCHK(hipEventCreateWithFlags(&c->evr[q], hipEventDisableTiming));
+        HIPCHK(hipHostMalloc((void**)&c->hslot[q], sizeof(double) * (16 + 3 * nd + 2),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+        std::memset(c->hslot[q], 0, sizeof(double) * (16 + 3 * nd + 2));
+        HIPCHK(hipHostGetDevicePointer((void**)&c->hslot_dev[q], c->hslot[q], 0));
     }
     c->eps0_d.assign(nd, 0.0);
     c->true_d.assign(nd, 0.0);
@@ -2000,6 +2003,24 @@ void wait_event(hipEvent_t e) {
     HIPCHK(r);
 }
 
+// Wait until the publish of sequence number seq has reached slot q (launch_publish: the scalars,
+// a system-scope fence, then the number). The stream is queried every 1024 polls: once it has
+// drained, the number must be there, and its absence is an error rather than an endless wait.
+void wait_published(feti_ctx* c, int q, int nsc, long long seq) {
+    volatile long long* flag = reinterpret_cast<volatile long long*>(c->hslot[q] + nsc);
+    for (long long spins = 1; *flag != seq; ++spins) {
+        if ((spins & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(c->st);
+            if (e == hipSuccess) {
+                if (*flag == seq) break;
+                throw HipError{"the per-iteration scalars did not reach the host"};
+            }
+            if (e != hipErrorNotReady) HIPCHK(e);
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+}
+
 // One pass of Algorithm 1 for a single design with the host one iteration behind the device:
 // iteration i+1 is enqueued before the scalars of iteration i (eps, rank, a probe's norms) are
 // read back, so the device runs the iterations back to back and never waits for the host.
@@ -2043,6 +2064,7 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
         int p_it = FETI_FP64;
         bool probed = false;
         int out = 0, slot = 0;
+        long long seq = 0;
     };
     int nb = 0;
     double eps_seen = o.eps, best = o.eps;
@@ -2093,8 +2115,8 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
         });
         orth(nb);
         sp.slot = it & 1;
-        HIPCHK(hipMemcpyAsync(c->hslot[sp.slot], c->scal, nsc * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(c->evr[sp.slot], st));
+        sp.seq = ++c->pub_seq;
+        launch_publish(c->scal, (int)nsc, c->hslot_dev[sp.slot], sp.seq, st);
         CHECK_LAUNCH();
         return sp;
     };
@@ -2106,7 +2128,7 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
             nxt = enqueue(it + 1);
             have_nxt = true;
         }
-        wait_event(c->evr[cur.slot]);
+        wait_published(c, cur.slot, (int)nsc, cur.seq);
         const double* hs = c->hslot[cur.slot];
         if (cur.probed) {
             const double e = hs[5] > 0.0 ? std::sqrt(hs[4] / hs[5]) : 0.0;

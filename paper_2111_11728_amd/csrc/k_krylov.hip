@@ -895,6 +895,18 @@ __global__ void __launch_bounds__(128) k_pivchol(int k, const double* __restrict
     }
 }
 
+// n scalars into host-mapped memory, then the sequence number seq after them, behind a
+// system-scope fence: a host that reads seq there also reads the scalars (one wavefront)
+__global__ void __launch_bounds__(64) k_publish(const double* __restrict__ src, int n, double* dst, long long seq) {
+    for (int i = threadIdx.x; i < n; i += 64) dst[i] = src[i];
+    __threadfence_system();
+    if (threadIdx.x == 0) *reinterpret_cast<volatile long long*>(dst + n) = seq;
+}
+
+void launch_publish(const double* src, int n, double* dst, long long seq, hipStream_t st) {
+    k_publish<<<1, 64, 0, st>>>(src, n, dst, seq);
+}
+
 void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st,
                     unsigned long long* kept_mask) {
     k_pivchol<<<1, 128, 0, st>>>(k, D, rr_tol, T, rank, kept_mask);

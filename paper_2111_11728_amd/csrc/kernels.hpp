@@ -289,6 +289,8 @@ void launch_ts_pair(int n, int kd, const double* const* Aptrs, const double* con
                     double* out, double* out2, hipStream_t st);
 void launch_ts_gemm(int n, int kd, int nblk, const double* const* Aptrs, const double* Mats, const double* C,
                     double* out, double alpha, double beta, hipStream_t st, bool f32 = false);
+// the n scalars src, then seq, into the host-mapped dst (seq last, after a system-scope fence)
+void launch_publish(const double* src, int n, double* dst, long long seq, hipStream_t st);
 void launch_pivchol(int k, const double* D, double rr_tol, double* T, int* rank, hipStream_t st,
                     unsigned long long* kept_mask = nullptr);   // kept_mask: bit j set when column j was kept
 // Z[:, c] = 0 for the columns c set in mask (n x k row-major)
