@@ -95,11 +95,11 @@ def test_full_size_local_operators(name, s):
     ctx.close()
 
 
-@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-10, 1e-8), ("fp32", 1e-8, 1e-6)])
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-10, 1e-8), ("fp32", 1e-8, 1e-6), ("bf16x3", 1e-8, 1e-6)])
 def test_full_size_c3_displacements(precision, tol, bound):
     """u at 4096 seeded DOFs of the 2.1 M-DOF headline workload against the global direct
-    solution; FP64 F*Lambda to 1e-8 and the mixed form to 1e-6, each solved to a residual
-    tolerance that reaches those errors at this contrast."""
+    solution; FP64 F*Lambda to 1e-8 and the mixed forms (FP32, and BF16 split products) to 1e-6,
+    each solved to a residual tolerance that reaches those errors at this contrast."""
     if not GOLDEN.exists():
         pytest.skip("tests/golden/c3_u_sample.npz not generated")
     g = np.load(GOLDEN)
