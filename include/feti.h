@@ -276,6 +276,11 @@ typedef struct {
  * the round-off test (one sum against four partial sums), a difference at FP64 round-off. */
 feti_status feti_autotune(feti_ctx* ctx, int reps, const char* cache_path, feti_tuning* out);
 
+/* Applies the given F*Lambda tile shapes (as feti_autotune would after a search), for callers that
+ * keep their own tuning. tune: host; its us, us_default and from_cache are not used. FETI_EINVAL
+ * when a shape lies outside the ranges above. */
+feti_status feti_set_tuning(feti_ctx* ctx, const feti_tuning* tune);
+
 /* Ranges of design d (0 <= d < n_designs) in the concatenated arrays. */
 feti_status feti_design_layout(feti_ctx* ctx, int d, feti_design* out);
 

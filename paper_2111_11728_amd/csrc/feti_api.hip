@@ -2599,7 +2599,7 @@ feti_status feti_setup_batched(int n_designs, const feti_mesh* meshes, const fet
 
 namespace {
 // Cache of tuned tile shapes: a JSON object with one entry per line,
-//   "key": {"max_red": 32, "max_d": 16, "xcd": 1, "split_d": 4, "us": 96.5},
+//   "key": {"max_red": 32, "max_d": 16, "xcd": 1, "split_d": 4, "fp64_first": 0, "us": 96.5},
 std::map<std::string, feti_tuning> read_tune_cache(const char* path) {
     std::map<std::string, feti_tuning> out;
     FILE* f = path ? std::fopen(path, "r") : nullptr;
@@ -2697,6 +2697,20 @@ feti_status feti_autotune(feti_ctx* c, int reps, const char* cache_path, feti_tu
             write_tune_cache(cache_path, cache);
         }
         if (out) *out = best;
+        return FETI_OK;
+    });
+}
+
+feti_status feti_set_tuning(feti_ctx* c, const feti_tuning* tune) {
+    if (!c || !tune) return fail(FETI_EINVAL, "null argument");
+    const feti_tuning& q = *tune;
+    if (q.max_red < 1 || q.max_red > 2 * kFlWaves || q.max_d < 1 || q.max_d > kFlWaves || q.split_d < 0 ||
+        q.split_d > 4 || (q.xcd != 0 && q.xcd != 1) || (q.fp64_first != 0 && q.fp64_first != 1))
+        return fail(FETI_EINVAL, "tile shapes out of range");
+    return guarded([&]() -> feti_status {
+        c->tune = q;
+        c->tune.from_cache = 0;
+        build_fl_tiles(c);
         return FETI_OK;
     });
 }

@@ -128,6 +128,7 @@ def lib():
             "feti_design_layout": (I, [P, I, C.POINTER(feti_design)]),
             "feti_design_residuals": (I, [P, C.POINTER(D), I]),
             "feti_autotune": (I, [P, I, C.c_char_p, C.POINTER(feti_tuning)]),
+            "feti_set_tuning": (I, [P, C.POINTER(feti_tuning)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -335,6 +336,11 @@ class Context:
         out = feti_tuning()
         _check(lib().feti_autotune(self.handle, reps, None if cache is None else str(cache).encode(), C.byref(out)))
         return out.as_dict()
+
+    def feti_set_tuning(self, max_red=32, max_d=16, xcd=1, split_d=4, fp64_first=0):
+        t = feti_tuning()
+        t.max_red, t.max_d, t.xcd, t.split_d, t.fp64_first = max_red, max_d, xcd, split_d, fp64_first
+        _check(lib().feti_set_tuning(self.handle, C.byref(t)))
 
     def feti_last_timing(self, what):
         ms = C.c_double(0)

@@ -616,6 +616,44 @@ def test_autotune_shapes_and_cache(tmp_path):
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["modular", "beta"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tile_shapes_leave_the_product_unchanged(name, prec):
+    """F*Lambda under explicit tile shapes (feti_set_tuning): reduced row blocks per tile, FP64
+    row blocks per tile, XCD placement and the position of the FP64 tiles change which workgroup
+    computes a row block, not the sequence of products for its rows, so every output bit is equal
+    across them, for 64 and 32 directions, FP64, the context's reduced (hybrid) product and the
+    all-FP32 one (among shapes with the same split contraction of the FP64 rows). The 8x4 modular
+    design has 16 reduced blocks and one FP64 block per subdomain, the 4x4 Beta design of 16^2 has
+    7 and 1 (the odd count gives the wavefront with one reduced and one FP64 block)."""
+    prob = workloads.modular_2d(0) if name == "modular" else workloads.beta_2d(0, nsub=(4, 4), m=16)
+    print(f"case tile shapes {name} {prec}", flush=True)
+    ctx = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", precision=prec, tol=1e-8)
+    n = ctx.sizes["n_lambda"]
+    g = torch.Generator(device=DEV)
+    g.manual_seed(5)
+    shapes = [dict(max_red=32, max_d=16, xcd=1, fp64_first=0), dict(max_red=16, max_d=4, xcd=0, fp64_first=1),
+              dict(max_red=1, max_d=1, xcd=1, fp64_first=0), dict(max_red=7, max_d=3, xcd=0, fp64_first=1)]
+    kinds = [("fp64", False)] + ([("fp32", False), ("fp32", True)] if prec == "fp32" else [])
+    for k in (64, 32):
+        L = torch.randn(n, k, generator=g, dtype=torch.float64, device=DEV)
+        for sd in (0, 2):
+            ref = {}
+            for i, shp in enumerate(shapes):
+                ctx.feti_set_tuning(split_d=sd, **shp)
+                for p, pure in kinds:
+                    Q = torch.zeros_like(L)
+                    ctx.feti_apply_F(k, p, L, Q, pure=pure)
+                    assert torch.isfinite(Q).all()
+                    if i == 0:
+                        ref[(p, pure)] = Q
+                    else:
+                        assert torch.equal(Q, ref[(p, pure)]), (k, sd, shp, p, pure)
+    with pytest.raises(feti.FetiError):
+        ctx.feti_set_tuning(max_red=33)
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["dirs64", "modular"])
 def test_graph_replay_matches_direct(name):
     """S-FETI with the per-iteration operator sequences replayed as captured hipGraphs (on a
