@@ -348,6 +348,8 @@ def main():
     ap.add_argument("--skip-fp64-solve", action="store_true")
     ap.add_argument("--orth-fp32", action="store_true",
                     help="opt-in: FP32 Gram-Schmidt against the stored directions on reduced iterations")
+    ap.add_argument("--precond-fp64", action="store_true",
+                    help="mixed solve: the preconditioner from its FP64 blocks (default: FP32 copies)")
     ap.add_argument("--max-it", type=int, default=1000)
     ap.add_argument("--flambda-only", action="store_true",
                     help="only the F*Lambda microbenchmark and a calibration copy (for counter runs)")
@@ -386,7 +388,8 @@ def main():
 
     def make(precision):
         spec = feti.Spec(prob, method="fetidp", scaling="k", krylov="sfeti", precond="dirichlet",
-                         precision=precision, tol=args.tol, max_it=args.max_it, orth_fp32=int(args.orth_fp32))
+                         precision=precision, tol=args.tol, max_it=args.max_it, orth_fp32=int(args.orth_fp32),
+                         precond_fp32=int(precision != "fp64" and not args.precond_fp64))
         t0 = time.perf_counter()
         cx = feti.Context(spec, rho)
         log(f"setup {precision}: {time.perf_counter() - t0:.2f} s, {cx.sizes['device_bytes'] / 2**30:.1f} GiB")
@@ -485,6 +488,26 @@ def main():
                  "grad_rel_diff_mixed_vs_fp64": float(torch.linalg.norm(g - g_m) / torch.linalg.norm(g))}
         vs_oracle["fp64"] = errors_vs_oracle(u, float(c.item()), g, args.dirs)
         ctx64.close()
+        del ctx64
+        torch.cuda.empty_cache()
+        # an FP64 solve to tol 1e-10 (untimed): the error that each timed solve keeps at its own
+        # tolerance, over the whole of u and g (the two solves stop at the same preconditioned
+        # residual along different search spaces, so their difference is of the size of that error)
+        spec_t = feti.Spec(prob, method="fetidp", scaling="k", krylov="sfeti", precond="dirichlet",
+                           precision="fp64", tol=1e-10, max_it=args.max_it)
+        ctx_t = feti.Context(spec_t, rho)
+        u_t = torch.zeros_like(u)
+        g_t = torch.zeros_like(g)
+        c_t = torch.zeros_like(c)
+        info_t = ctx_t.feti_compliance_and_grad(rho, f, c_t, g_t, u_t)
+        ctx_t.close()
+        nu_t, ng_t = torch.linalg.norm(u_t), torch.linalg.norm(g_t)
+        res64["vs_fp64_tol1e-10"] = {
+            "iters": info_t["iters"],
+            "u_err_mixed": float(torch.linalg.norm(u_m - u_t) / nu_t),
+            "u_err_fp64": float(torch.linalg.norm(u - u_t) / nu_t),
+            "g_err_mixed": float(torch.linalg.norm(g_m - g_t) / ng_t),
+            "g_err_fp64": float(torch.linalg.norm(g - g_t) / ng_t)}
 
     gpu_iters = info_m["iters"]
     # roofline of the dominant kernel of the timed solve: the in-solve F*Lambda local products
@@ -519,6 +542,7 @@ def main():
         "fp64_fallback": info_m["fp64_fallback"], "reduced_iters": info_m["reduced_iters"],
         "precision_probes": info_m["precision_probes"], "reduced_rel_err": info_m["reduced_rel_err"],
         "reduced_orth_err": info_m["reduced_orth_err"], "orth_fp32": int(args.orth_fp32),
+        "precond_fp32": int(not args.precond_fp64),
         "true_rel_res": info_m["true_rel_res"], "fp64": res64,
         "flambda": fl, "roofline": roof, "autotune": tune, "vs_oracle": vs_oracle,
     }

@@ -51,7 +51,8 @@ enum { FETI_PCG = 0, FETI_FO = 1, FETI_SFETI = 2 };         /* Sec. 2, Sec. 3.2,
 enum { FETI_DIRICHLET = 0, FETI_LUMPED = 1, FETI_SUPERLUMPED = 2 };   /* Sec. 3.1, Eq. (13): S~^s =
                                                                        S^s, K_bb or diag K_bb */
 enum { FETI_FP64 = 0, FETI_FP32 = 1, FETI_BF16X3 = 2 };     /* arithmetic of the F*Lambda product */
-enum { FETI_PURE = 16 };   /* or-ed into feti_apply_F's precision: no per-subdomain FP64 fallback */
+enum { FETI_PURE = 16 };          /* or-ed into feti_apply_F's precision: no per-subdomain FP64 fallback */
+enum { FETI_PRECOND_FP32 = 2 };   /* or-ed into feti_apply_precond's one_column: FP32 blocks */
 
 /* Structured grid and boundary conditions (Sec. 2, Eq. 2). */
 typedef struct {
@@ -146,6 +147,16 @@ typedef struct {
                                  (deflated iterations). FETI-DP only, interface blocks of 32 to
                                  576 DOFs; 0 = off */
     double defl_tau;          /* deflation: smallest eigenvalue taken (0 = no threshold) */
+    int precond_fp32;         /* FO or S-FETI with a reduced precision and the Dirichlet or lumped
+                                 preconditioner: 1 = the passes on the reduced-precision operator
+                                 apply the preconditioner (Sec. 3.1, Eq. 13) from an FP32 copy of its
+                                 blocks, made at every setup, with FP64 products and sums. Its
+                                 rounding changes only the search directions, which are then made
+                                 F-orthogonal in FP64 against every stored direction; the dual
+                                 iterate, the residual recurrence and the final FP64 true residual
+                                 (tested with the FP64 preconditioner) are as before. Half the
+                                 preconditioner's HBM reads. 0 (default) = FP64 blocks throughout;
+                                 FETI_EINVAL for other combinations. */
 } feti_opts;
 
 typedef struct {
@@ -373,7 +384,9 @@ feti_status feti_apply_F(feti_ctx* ctx, int k, int precision, const double* Lamb
 feti_status feti_apply_F_noalloc(feti_ctx* ctx, int k, int precision, const double* Lambda, double* Q);
 
 /* Z = [.., B~^s S~^s B~^sT r, ..] (Sec. 3.1 Eq. 13, Algorithm 1): r device [n_lambda];
- * Z device [n_lambda x n_groups] (one_column = 0) or [n_lambda] summed (one_column = 1). */
+ * Z device [n_lambda x n_groups] (one_column = 0) or [n_lambda] summed (one_column = 1).
+ * one_column or-ed with FETI_PRECOND_FP32: S~^s from its FP32 copy (a context set up with
+ * precond_fp32 = 1; FETI_EINVAL otherwise), FP64 products and sums. */
 feti_status feti_apply_precond(feti_ctx* ctx, const double* r, double* Z, int one_column);
 
 /* Y <- P Y with P = I - G^T (G G^T)^{-1} G (TFETI, Sec. 3.3); identity for FETI-DP.

@@ -156,6 +156,8 @@ struct feti_ctx {
     float* sw32 = nullptr;
     __hip_bfloat16 *swhi = nullptr, *swlo = nullptr;
     double *Pk = nullptr, *W1 = nullptr, *W2 = nullptr, *ypart = nullptr;
+    float* Pk32 = nullptr;   // opts.precond_fp32: the packed preconditioner tiles rounded to FP32
+    long long n_Pk = 0;
     double *Kc = nullptr, *Kcc = nullptr, *Kcc_w = nullptr, *Kcc_inv = nullptr;
     // designs held by the context (one, or several independent ones as a disjoint union)
     std::vector<DesignMeta> designs;
@@ -578,6 +580,8 @@ void build_layout(feti_ctx* c) {
     c->swhi = c->alloc<__hip_bfloat16>(oF);
     c->swlo = c->alloc<__hip_bfloat16>(oF);
     c->Pk = c->alloc<double>(std::max(1LL, oPk));
+    c->n_Pk = oPk;
+    if (c->opts.precond_fp32) c->Pk32 = c->alloc<float>(std::max(1LL, oPk));
     c->ypart = c->alloc<double>(std::max<long long>(1, (long long)kPsMaxSplit * t.nb_tot));
     c->W1 = c->alloc<double>(oP);
     c->W2 = c->alloc<double>(oP);
@@ -797,9 +801,8 @@ void build_layout(feti_ctx* c) {
         // sides) are staged once, and fr_pos places every fold entry in that union
         std::map<std::pair<int, int>, std::vector<int>> groups;
         for (int r = 0; r < P.n_lambda; ++r) groups[{P.row_s[2 * r], P.row_s[2 * r + 1]}].push_back(r);
-        std::vector<int> pr_ptr{0}, pr_rows, pu_ptr{0}, pu_cg, fpos((size_t)P.n_lambda * W, 0), pfn, ipos(P.n_lambda);
-        std::vector<long long> pyo;
-        std::vector<int8_t> psg;
+        std::vector<int> pr_ptr{0}, pu_ptr{0}, pu_cg, fpos((size_t)P.n_lambda * W, 0), ipos(P.n_lambda);
+        std::vector<int4> prec;
         int maxu = 0;
         for (auto& g : groups) {
             std::vector<int> U;
@@ -809,31 +812,27 @@ void build_layout(feti_ctx* c) {
             U.erase(std::unique(U.begin(), U.end()), U.end());
             maxu = std::max(maxu, (int)U.size());
             for (int r : g.second) {
-                const size_t i = pr_rows.size();
+                const size_t i = prec.size();
                 ipos[r] = (int)i;
-                pr_rows.push_back(r);
-                pfn.push_back(fn[r]);
-                for (int t2 = 0; t2 < 2; ++t2) {
-                    pyo.push_back(yo[2 * (size_t)r + t2]);
-                    psg.push_back(P.row_sg[2 * (size_t)r + t2]);
-                }
+                const int fl = fn[r] << 2 | (P.row_sg[2 * (size_t)r] < 0) | (P.row_sg[2 * (size_t)r + 1] < 0) << 1;
+                prec.push_back(int4{(int)yo[2 * (size_t)r], (int)yo[2 * (size_t)r + 1], fl, r});
                 for (int e = 0; e < fn[r]; ++e)
                     fpos[i * W + e] = (int)(std::lower_bound(U.begin(), U.end(), fc[(size_t)r * W + e]) - U.begin());
             }
-            pr_ptr.push_back((int)pr_rows.size());
+            pr_ptr.push_back((int)prec.size());
             pu_cg.insert(pu_cg.end(), U.begin(), U.end());
             pu_ptr.push_back((int)pu_cg.size());
         }
-        if (maxu <= kFoldPairMaxU) {
+        // local product rows are stored as int in the row records
+        if (maxu <= kFoldPairMaxU && t.nb_tot < (1LL << 31)) {
             t.n_pairs = (int)groups.size();
             t.pr_ptr = c->upload(pr_ptr);
-            t.pr_rows = c->upload(pr_rows);
             t.pu_ptr = c->upload(pu_ptr);
+            for (int e = 0; e < 4; ++e) pu_cg.push_back(0);   // 4-entry index loads near the end
             t.pu_cg = c->upload(pu_cg);
             t.fr_pos = c->upload(fpos);
-            t.pr_yo = c->upload(pyo);
-            t.pr_sg = c->upload(psg);
-            t.pr_fn = c->upload(pfn);
+            for (int e = 0; e < kFoldRows; ++e) prec.push_back(int4{-1, -1, 0, 0});   // a pass's last records
+            t.pr_rec = c->upload(prec);
             t.pr_ipos = c->upload(ipos);
             t.pr_fval = c->alloc<double>((long long)P.n_lambda * W);
         }
@@ -1222,6 +1221,7 @@ void numeric_setup(feti_ctx* c) {
     launch_gemm_tn(dsy, nr, c->syrk_tdim, c->Z, c->Z, c->S, -1.0, 1.0, 1, st);
     CHECK_LAUNCH();
     if (c->opts.precond == FETI_DIRICHLET) launch_pack_sym(ts, c->S, c->Pk, st);
+    if (c->Pk32) launch_round_f32(c->n_Pk, c->Pk, c->Pk32, st);
     if (P.method == FETI_TFETI)
         launch_tfeti_rbm(ts, c->S, c->Rb, c->Cit, c->tau, c->W1, st);
     else
@@ -1392,11 +1392,14 @@ void project(feti_ctx* c, int k, double* Y) {
     CHECK_LAUNCH();
 }
 
+// use_f32: a pass on the reduced-precision operator, which applies the FP32 copy of the blocks
+// when the context keeps one (opts.precond_fp32)
 void precondition(feti_ctx* c, const double* r, double* Z, int one_column, int use_f32) {
     DevTopo& t = c->t;
-    (void)use_f32;  // the preconditioner blocks stay FP64: FP32 rounding can make them indefinite
     if (c->opts.precond == FETI_SUPERLUMPED)
         launch_precond_diag(t, r, c->bg_w, c->Pk, c->yb, c->st);
+    else if (use_f32 && c->Pk32)
+        launch_precond_local32(t, r, c->bg_w, c->Pk32, c->ypart, c->yb, c->st);
     else
         launch_precond_local(t, r, c->bg_w, c->Pk, c->ypart, c->yb, c->st);
     launch_precond_scatter(t, one_column, c->w, c->yb, Z, c->st);
@@ -1793,6 +1796,8 @@ KrylovOut run_pcg(feti_ctx* c, PrecGate& g, double eps0, double tol, int max_it,
 // One pass of Algorithm 1 (simultaneous directions; kd = 1 is full orthogonalisation).
 KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, int max_it,
                     std::vector<double>& hist, std::vector<int>& ranks) {
+    // a pass on the reduced-precision operator applies the FP32 preconditioner blocks, if kept
+    const int red_pass = g.prec != FETI_FP64;
     KrylovOut o;
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
@@ -1839,7 +1844,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         }
     };
     const double rr_tol = c->opts.rr_tol > 0 ? c->opts.rr_tol : 1e-12;
-    precondition(c, c->r, c->Zk, one, 0);
+    precondition(c, c->r, c->Zk, one, red_pass);
     launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
     launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
     o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
@@ -1901,8 +1906,8 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         }
         CHECK_LAUNCH();
         ++nb;
-        run_graph(c, c->g_prec, kd, [&] {
-            precondition(c, c->r, c->Zk, one, 0);
+        run_graph(c, c->g_prec, 2 * kd + red_pass, [&] {
+            precondition(c, c->r, c->Zk, one, red_pass);
             launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
             launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
             project(c, kd, c->Zk);
@@ -1979,7 +1984,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             replaced = true;
             current_iterate(c, c->tmpv);
             true_residual(c, c->tmpv, c->r);
-            precondition(c, c->r, c->Zk, one, 0);
+            precondition(c, c->r, c->Zk, one, red_pass);
             launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
             launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
             o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
@@ -2033,6 +2038,8 @@ void wait_published(feti_ctx* c, int q, int nsc, long long seq) {
 // takes no reduced product while a probe's norms are still on their way.
 KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, int max_it,
                           std::vector<double>& hist, std::vector<int>& ranks) {
+    // a pass on the reduced-precision operator applies the FP32 preconditioner blocks, if kept
+    const int red_pass = g.prec != FETI_FP64;
     KrylovOut o;
     const int n = c->P.n_lambda;
     hipStream_t st = c->st;
@@ -2051,7 +2058,7 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
         launch_rowsum_dot(n, kd, c->r, c->Zk, c->part, c->scal, st);
         launch_seg_dot(c->t, kd, c->r, c->Zk, c->part, c->scal + 16, st);
     };
-    precondition(c, c->r, c->Zk, one, 0);
+    precondition(c, c->r, c->Zk, one, red_pass);
     residual_dots();
     o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
     if (converged(c, o.eps, eps0, tol) || max_it < 1) return o;
@@ -2108,8 +2115,8 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
         head = 1 - head;
         sp.out = head;
         ++nb;
-        run_graph(c, c->g_prec, kd, [&] {
-            precondition(c, c->r, c->Zk, one, 0);
+        run_graph(c, c->g_prec, 2 * kd + red_pass, [&] {
+            precondition(c, c->r, c->Zk, one, red_pass);
             residual_dots();
             project(c, kd, c->Zk);
         });
@@ -2185,7 +2192,7 @@ KrylovOut run_sfeti_ahead(feti_ctx* c, PrecGate& g, int kd, double eps0, double 
             replaced = true;
             current_iterate(c, c->tmpv);
             true_residual(c, c->tmpv, c->r);
-            precondition(c, c->r, c->Zk, one, 0);
+            precondition(c, c->r, c->Zk, one, red_pass);
             residual_dots();
             o.eps = std::sqrt(std::max(read_scalars(c), 0.0));
             eps_seen = o.eps;
@@ -2412,6 +2419,11 @@ feti_status validate_opts(const feti_opts* o) {
     if (o->precision != FETI_FP64 && o->precision != FETI_FP32 && o->precision != FETI_BF16X3)
         return fail(FETI_EINVAL, "unknown precision");
     if (!(o->tol >= 0.0)) return fail(FETI_EINVAL, "tol must be >= 0");
+    if (o->precond_fp32 != 0 &&
+        (o->precond_fp32 != 1 || o->precision == FETI_FP64 || o->krylov == FETI_PCG || o->precond == FETI_SUPERLUMPED))
+        return fail(FETI_EINVAL,
+                    "precond_fp32 is 0 or 1, and 1 needs a reduced precision, FO or S-FETI and the Dirichlet or "
+                    "lumped preconditioner");
     return FETI_OK;
 }
 
@@ -2917,8 +2929,12 @@ feti_status feti_apply_F_noalloc(feti_ctx* c, int k, int precision, const double
 
 feti_status feti_apply_precond(feti_ctx* c, const double* r, double* Z, int one_column) {
     if (!c || !r || !Z) return fail(FETI_EINVAL, "null argument");
+    const int f32 = (one_column & FETI_PRECOND_FP32) != 0;
+    one_column &= ~FETI_PRECOND_FP32;
+    if (one_column != 0 && one_column != 1) return fail(FETI_EINVAL, "one_column must be 0 or 1");
+    if (f32 && !c->Pk32) return fail(FETI_EINVAL, "FETI_PRECOND_FP32 needs a context set up with precond_fp32 = 1");
     return guarded([&]() -> feti_status {
-        precondition(c, r, Z, one_column, 0);
+        precondition(c, r, Z, one_column, f32);
         return FETI_OK;
     });
 }

@@ -754,10 +754,13 @@ __global__ void __launch_bounds__(256) k_scatter_fold(int n_lambda, int k, int W
 
 // The same per pair of subdomains, for blocks of 32 or more columns: workgroup g stages the
 // coarse solution rows of its group's corner union (at most 64 x 64) in LDS once; its sixteen
-// wavefronts then take the group's rows two at a time, a lane per column. Every per-row array is
-// stored in the group order, so a row's loads depend on nothing but its position, and a row's
-// fold entries (at most 64) come in with one vector load per table, lane e holding entry e, and
-// are broadcast by readlane: no memory load waits inside the fold loop.
+// wavefronts take the group's rows kFoldRows at a time each (wavefront w: rows w, w + 16, ...), a
+// lane per column. Every per-row array is stored in the group order, so a row's loads depend on
+// nothing but its position, and a row's fold entries (at most 64) come in with one vector load per
+// table, lane e holding entry e, and are broadcast by readlane: no memory load waits inside the
+// fold loop. The first pass's table and local-product loads are issued before the staging of the
+// coarse rows and its barrier (the only one, met by every wavefront), so the whole group's reads
+// are in flight together.
 __device__ __forceinline__ double bcast_lane(double v, int e) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), e);
@@ -765,12 +768,62 @@ __device__ __forceinline__ double bcast_lane(double v, int e) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// One pass's loads: rows base .. base + kFoldRows - 1 of the group. Their records are contiguous:
+// one scalar load from min(base, i1 - 1), which stays inside the table (it carries kFoldRows
+// padding records after its last row). Rows at or past i1 are masked (no fold entries, both
+// sides absent, no store), and an absent side reads local product row 0 and adds nothing, so the
+// loads carry no branches.
+// side[r] = sign_0 Y_0[c] + sign_1 Y_1[c] over the row's sides; fp/fv: the fold entry of lane c.
+typedef int fold_rec_t __attribute__((ext_vector_type(4 * kFoldRows)));
+template <typename TY>
+__device__ __forceinline__ void fold_rows_load(int base, int i1, int k, int W, int c, const int4* __restrict__ pr_rec,
+                                               const int* __restrict__ pr_fpos, const double* __restrict__ pr_fval,
+                                               const TY* __restrict__ Y, int4 (&rec)[kFoldRows],
+                                               double (&side)[kFoldRows], int (&fp)[kFoldRows],
+                                               double (&fv)[kFoldRows]) {
+    const int lb = min(base, i1 - 1);
+    const fold_rec_t all = *reinterpret_cast<const fold_rec_t*>(pr_rec + lb);
+#pragma unroll
+    for (int r = 0; r < kFoldRows; ++r) {
+        const bool in = base + r < i1 && lb == base;   // lb < base only when base >= i1
+        rec[r] = in ? int4{all[4 * r], all[4 * r + 1], all[4 * r + 2], all[4 * r + 3]} : int4{-1, -1, 0, 0};
+    }
+    const int cc = c < k ? c : 0;
+#pragma unroll
+    for (int r = 0; r < kFoldRows; ++r) {
+        const bool e = c < (rec[r].z >> 2);
+        const long long ce = e ? (long long)(base + r) * W + c : 0;
+        const int p = pr_fpos[ce];
+        const double v = pr_fval[ce];
+        fp[r] = e ? p : 0;
+        fv[r] = e ? v : 0.0;
+        const double a0 = (double)Y[(long long)max(rec[r].x, 0) * k + cc];
+        const double a1 = (double)Y[(long long)max(rec[r].y, 0) * k + cc];
+        const double s0 = (rec[r].z & 1) ? -1.0 : 1.0, s1 = (rec[r].z & 2) ? -1.0 : 1.0;
+        double sd = 0.0;
+        sd += rec[r].x >= 0 ? s0 * a0 : 0.0;
+        sd += rec[r].y >= 0 ? s1 * a1 : 0.0;
+        side[r] = sd;
+    }
+}
+
+// The fold sums and the stores of one pass.
+__device__ __forceinline__ void fold_rows_store(int base, int i1, int k, int c, const double (*vs)[64],
+                                                const int4 (&rec)[kFoldRows], const double (&side)[kFoldRows],
+                                                const int (&fp)[kFoldRows], const double (&fv)[kFoldRows],
+                                                double* __restrict__ Q) {
+#pragma unroll
+    for (int r = 0; r < kFoldRows; ++r) {
+        double a = 0.0;
+        const int ne = rec[r].z >> 2;
+        for (int e = 0; e < ne; ++e) a = fma(bcast_lane(fv[r], e), vs[__builtin_amdgcn_readlane(fp[r], e)][c], a);
+        if (base + r < i1 && c < k) Q[(long long)rec[r].w * k + c] = side[r] + a;
+    }
+}
+
 template <typename TY>
 __global__ void __launch_bounds__(1024) k_scatter_fold_pair(int k, int W, const int* __restrict__ pr_ptr,
-                                                            const int* __restrict__ pr_row,
-                                                            const long long* __restrict__ pr_yo,
-                                                            const int8_t* __restrict__ pr_sg,
-                                                            const int* __restrict__ pr_fn,
+                                                            const int4* __restrict__ pr_rec,
                                                             const int* __restrict__ pr_fpos,
                                                             const double* __restrict__ pr_fval,
                                                             const int* __restrict__ pu_ptr, const int* __restrict__ pu_cg,
@@ -778,41 +831,34 @@ __global__ void __launch_bounds__(1024) k_scatter_fold_pair(int k, int W, const 
                                                             double* __restrict__ Q) {
     __shared__ double vs[kFoldPairMaxU][64];
     const int g = blockIdx.x;
-    const int u0 = pu_ptr[g], nu = pu_ptr[g + 1] - u0;
-    for (int e = threadIdx.x; e < nu * 64; e += 1024) {
-        const int u = e >> 6, c = e & 63;
-        vs[u][c] = c < k ? v[(long long)pu_cg[u0 + u] * k + c] : 0.0;
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, c = threadIdx.x & 63;
-    const bool col = c < k;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), c = threadIdx.x & 63;
     const int i1 = pr_ptr[g + 1];
-    for (int i = pr_ptr[g] + wave; i < i1; i += 32) {
-        const bool two = i + 16 < i1;
-        const int ib = two ? i + 16 : i;
-        // both rows' loads issued before any use
-        const long long ya0 = pr_yo[2 * i], ya1 = pr_yo[2 * i + 1], yb0 = pr_yo[2 * ib], yb1 = pr_yo[2 * ib + 1];
-        const int nea = pr_fn[i], neb = pr_fn[ib];
-        const int fpa = c < nea ? pr_fpos[(long long)i * W + c] : 0;
-        const int fpb = c < neb ? pr_fpos[(long long)ib * W + c] : 0;
-        const double fva = c < nea ? pr_fval[(long long)i * W + c] : 0.0;
-        const double fvb = c < neb ? pr_fval[(long long)ib * W + c] : 0.0;
-        double va = 0.0, vb = 0.0;
-        if (col) {
-            if (ya0 >= 0) va += pr_sg[2 * i] * (double)Y[ya0 * k + c];
-            if (ya1 >= 0) va += pr_sg[2 * i + 1] * (double)Y[ya1 * k + c];
-            if (yb0 >= 0) vb += pr_sg[2 * ib] * (double)Y[yb0 * k + c];
-            if (yb1 >= 0) vb += pr_sg[2 * ib + 1] * (double)Y[yb1 * k + c];
-        }
-        double aa = 0.0, ab = 0.0;
-        for (int e = 0; e < nea; ++e)
-            aa = fma(bcast_lane(fva, e), vs[__builtin_amdgcn_readlane(fpa, e)][c], aa);
-        for (int e = 0; e < neb; ++e)
-            ab = fma(bcast_lane(fvb, e), vs[__builtin_amdgcn_readlane(fpb, e)][c], ab);
-        if (col) {
-            Q[(long long)pr_row[i] * k + c] = va + aa;
-            if (two) Q[(long long)pr_row[ib] * k + c] = vb + ab;
-        }
+    int base = pr_ptr[g] + kFoldRows * wave;
+    // the coarse rows of the union: wavefront w takes rows 4w .. 4w + 3 (at most 64 in all; one
+    // scalar load of their indices from u0 + min(4w, max(nu - 1, 0)), inside the table, which
+    // carries 4 padding entries at its end); their loads go out first, then the first pass's
+    static_assert(kFoldPairMaxU <= 64, "four union rows per wavefront");
+    const int u0 = pu_ptr[g], nu = pu_ptr[g + 1] - u0;
+    const int4 cg = *reinterpret_cast<const int4*>(pu_cg + u0 + min(4 * wave, max(nu - 1, 0)));
+    const int cgs[4] = {cg.x, cg.y, cg.z, cg.w};
+    double vr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        vr[q] = 0.0;
+        if (4 * wave + q < nu && c < k) vr[q] = v[(long long)cgs[q] * k + c];
+    }
+    int4 rec[kFoldRows];
+    double side[kFoldRows], fv[kFoldRows];
+    int fp[kFoldRows];
+    fold_rows_load(base, i1, k, W, c, pr_rec, pr_fpos, pr_fval, Y, rec, side, fp, fv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (4 * wave + q < nu) vs[4 * wave + q][c] = vr[q];
+    __syncthreads();
+    fold_rows_store(base, i1, k, c, vs, rec, side, fp, fv, Q);
+    for (base += 16 * kFoldRows; base < i1; base += 16 * kFoldRows) {
+        fold_rows_load(base, i1, k, W, c, pr_rec, pr_fpos, pr_fval, Y, rec, side, fp, fv);
+        fold_rows_store(base, i1, k, c, vs, rec, side, fp, fv, Q);
     }
 }
 
@@ -822,13 +868,11 @@ void launch_scatter_fold(const DevTopo& t, int k, int ytype_f32, const void* Y, 
     if (n == 0) return;
     if (k >= 32 && t.n_pairs > 0) {
         if (ytype_f32)
-            k_scatter_fold_pair<float><<<t.n_pairs, 1024, 0, st>>>(k, t.fr_w, t.pr_ptr, t.pr_rows, t.pr_yo, t.pr_sg,
-                                                                   t.pr_fn, t.fr_pos, t.pr_fval, t.pu_ptr, t.pu_cg,
-                                                                   (const float*)Y, v, Q);
+            k_scatter_fold_pair<float><<<t.n_pairs, 1024, 0, st>>>(k, t.fr_w, t.pr_ptr, t.pr_rec, t.fr_pos, t.pr_fval,
+                                                                   t.pu_ptr, t.pu_cg, (const float*)Y, v, Q);
         else
-            k_scatter_fold_pair<double><<<t.n_pairs, 1024, 0, st>>>(k, t.fr_w, t.pr_ptr, t.pr_rows, t.pr_yo, t.pr_sg,
-                                                                    t.pr_fn, t.fr_pos, t.pr_fval, t.pu_ptr, t.pu_cg,
-                                                                    (const double*)Y, v, Q);
+            k_scatter_fold_pair<double><<<t.n_pairs, 1024, 0, st>>>(k, t.fr_w, t.pr_ptr, t.pr_rec, t.fr_pos, t.pr_fval,
+                                                                    t.pu_ptr, t.pu_cg, (const double*)Y, v, Q);
         return;
     }
     const int grid = (int)((n + 255) / 256);
@@ -859,12 +903,37 @@ __device__ __forceinline__ int tri_col(int t) {   // J with J(J+1)/2 <= t < (J+1
     return J;
 }
 
+// The tiles' storage type TP: double, or float for the FP32 copy of the blocks (the products and
+// sums stay FP64: a stored value is converted exactly when it is used).
+typedef float ps4f_t __attribute__((ext_vector_type(4)));
+template <typename TP>
+struct PsRaw;
+template <>
+struct PsRaw<double> {
+    typedef ps4_t raw;
+    static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, int off) { return load4d(r, off); }
+    static __device__ __forceinline__ ps4_t wide(raw a) { return a; }
+};
+template <>
+struct PsRaw<float> {
+    typedef ps4f_t raw;
+    static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, int off) {
+        return __builtin_bit_cast(ps4f_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    }
+    static __device__ __forceinline__ ps4_t wide(raw a) {
+        return ps4_t{(double)a[0], (double)a[1], (double)a[2], (double)a[3]};
+    }
+};
+
+template <typename TP>
 __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict__ subs, const int4* __restrict__ work,
                                                       const int* __restrict__ bg_ptr,
                                                       const int* __restrict__ bg_row, const int8_t* __restrict__ bg_sg,
                                                       const double* __restrict__ bg_w, const double* __restrict__ r,
-                                                      const double* __restrict__ Pk, double* __restrict__ y,
+                                                      const TP* __restrict__ Pk, double* __restrict__ y,
                                                       long long ystride, int cap) {
+    typedef PsRaw<TP> R;
+    constexpr int kTileBytes = 4096 * (int)sizeof(TP);
     extern __shared__ double sh[];
     double* xs = sh;             // cap
     double* ys = sh + cap;       // cap
@@ -878,10 +947,11 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
     const int t0 = (int)((long long)g * nt / G), t1 = (int)((long long)(g + 1) * nt / G);
     // the part's tiles through a buffer resource: loads past its last tile return zeros, so the
     // ring's loads are unconditional and their waits counted, not drained
-    const __amdgpu_buffer_rsrc_t rs = rows_rsrc(Pk + M.off_Pk + (long long)t0 * 4096, (t1 - t0) * 32768);
-    const int toff = (i * 64 + 4 * jq) * 8;
-    auto ld = [&](int t) -> ps4_t { return load4d(rs, toff + (t - t0) * 32768); };
-    ps4_t ring[kPsRing];
+    const __amdgpu_buffer_rsrc_t rs =
+        rows_rsrc(reinterpret_cast<const double*>(Pk + M.off_Pk + (long long)t0 * 4096), (t1 - t0) * kTileBytes);
+    const int toff = (i * 64 + 4 * jq) * (int)sizeof(TP);
+    auto ld = [&](int t) -> typename R::raw { return R::load(rs, toff + (t - t0) * kTileBytes); };
+    typename R::raw ring[kPsRing];
 #pragma unroll
     for (int d = 0; d < kPsRing; ++d) ring[d] = ld(t0 + d);
     for (int q = tid; q < nT * 64; q += 1024) {
@@ -899,7 +969,7 @@ __global__ void __launch_bounds__(1024) k_precond_sym(const SubMeta* __restrict_
     for (int t = t0; t < t1; t += kPsRing) {
 #pragma unroll
         for (int d = 0; d < kPsRing; ++d) {
-            const ps4_t a = ring[d];
+            const ps4_t a = R::wide(ring[d]);
             ring[d] = ld(t + d + kPsRing);
             if (t + d < t1) {   // uniform over the workgroup
                 // row part: y_I[i] += sum_b S[i][b] x_J[b]
@@ -957,18 +1027,39 @@ __global__ void k_precond_sum(long long n, const int* __restrict__ bq_s, const i
     y[q] = v;
 }
 
-void launch_precond_local(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* ypart,
+template <typename TP>
+static void precond_local(const DevTopo& t, const double* r, const double* bg_w, const TP* Pk, double* ypart,
                           double* y, hipStream_t st) {
     if (t.nb_tot == 0 || t.ps_nwg == 0) return;
     const int cap = (t.max_nb + 63) / 64 * 64;
     const size_t sh = sizeof(double) * (2 * (size_t)cap + 16 * 64);
     if (t.ps_maxG == 1) {
-        k_precond_sym<<<t.ps_nwg, 1024, sh, st>>>(t.subs, t.ps_work, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, y, 0, cap);
+        k_precond_sym<TP>
+            <<<t.ps_nwg, 1024, sh, st>>>(t.subs, t.ps_work, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, y, 0, cap);
     } else {
-        k_precond_sym<<<t.ps_nwg, 1024, sh, st>>>(t.subs, t.ps_work, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk, ypart,
-                                                  t.nb_tot, cap);
+        k_precond_sym<TP><<<t.ps_nwg, 1024, sh, st>>>(t.subs, t.ps_work, t.bg_ptr, t.bg_row, t.bg_sg, bg_w, r, Pk,
+                                                      ypart, t.nb_tot, cap);
         k_precond_sum<<<(int)((t.nb_tot + 255) / 256), 256, 0, st>>>(t.nb_tot, t.bq_s, t.ps_G, ypart, y);
     }
+}
+
+void launch_precond_local(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* ypart,
+                          double* y, hipStream_t st) {
+    precond_local(t, r, bg_w, Pk, ypart, y, st);
+}
+
+void launch_precond_local32(const DevTopo& t, const double* r, const double* bg_w, const float* Pk32,
+                            double* ypart, double* y, hipStream_t st) {
+    precond_local(t, r, bg_w, Pk32, ypart, y, st);
+}
+
+__global__ void k_round_f32(long long n, const double* __restrict__ a, float* __restrict__ b) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+void launch_round_f32(long long n, const double* a, float* b, hipStream_t st) {
+    if (n > 0) k_round_f32<<<(int)((n + 255) / 256), 256, 0, st>>>(n, a, b);
 }
 
 // Z[row][c] = sum over the row's sides with g(s) == c of sign * w * y_s[j]  (kz = n_groups or 1).

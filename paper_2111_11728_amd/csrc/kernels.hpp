@@ -132,20 +132,18 @@ struct DevTopo {
     const int* fr_col = nullptr;      // [n_lambda x fr_w] global corner DOF
     double* fr_val = nullptr;         // [n_lambda x fr_w] values (set up with F_rc)
     int fr_w = 0;
-    // the same rows grouped by their pair of subdomains (n_pairs = 0: not built): rows
-    // pr_rows[pr_ptr[g] .. pr_ptr[g+1]), the union of their corner DOFs pu_cg[pu_ptr[g] .. ),
+    // the same rows grouped by their pair of subdomains (n_pairs = 0: not built): the rows at
+    // positions pr_ptr[g] .. pr_ptr[g+1]), the union of their corner DOFs pu_cg[pu_ptr[g] .. ),
     // and the position of every fold entry in its group's union
     int n_pairs = 0;
     const int* pr_ptr = nullptr;
-    const int* pr_rows = nullptr;
     const int* pu_ptr = nullptr;
     const int* pu_cg = nullptr;
     const int* fr_pos = nullptr;      // [pair position x fr_w], in the group order
-    // per row in the group order: the scatter sides (off_b + j or -1, sign), the fold entry count
-    // and values; pr_ipos[row] = the row's position
-    const long long* pr_yo = nullptr;
-    const int8_t* pr_sg = nullptr;
-    const int* pr_fn = nullptr;
+    // per row in the group order: pr_rec = {side 0's local product row off_b + j (or -1), the
+    // same for side 1, fold entry count << 2 | (sign_0 < 0) | (sign_1 < 0) << 1, lambda row};
+    // the fold values; pr_ipos[row] = the row's position
+    const int4* pr_rec = nullptr;
     double* pr_fval = nullptr;
     const int* pr_ipos = nullptr;
     int n_lines_tot = 0;              // interior line (2D) / plane (3D) blocks over all subdomains
@@ -230,6 +228,7 @@ void launch_rho_hash(const DevTopo& t, const double* rho, unsigned long long* ou
 void launch_rho_match(const DevTopo& t, const double* rho, const int* pairs, int npairs, int* flag, hipStream_t st);
 void launch_gather_rows(int n, int w, const int* map, const double* src, double* dst, hipStream_t st);
 constexpr int kFoldPairMaxU = 64;   // corner DOFs of two subdomains staged per group
+constexpr int kFoldRows = 4;        // rows per wavefront and pass of the pair scatter-fold
 // fr_val from the F_rc^T rows of the augmented operators (after launch_frc)
 void launch_fold_rows(const DevTopo& t, const double* F64, hipStream_t st);
 // Q = sum_s B_s Y_s + (B_r F_rc B_c) v: the scatter with the coarse fold of F*Lambda in one pass
@@ -244,6 +243,11 @@ void launch_precond_diag(const DevTopo& t, const double* r, const double* bg_w, 
 void launch_pk_diag_only(const DevTopo& t, double* Pk, hipStream_t st);
 void launch_precond_local(const DevTopo& t, const double* r, const double* bg_w, const double* Pk, double* ypart,
                           double* y, hipStream_t st);
+// the same from FP32 copies of the packed tiles (FP64 products and sums)
+void launch_precond_local32(const DevTopo& t, const double* r, const double* bg_w, const float* Pk32,
+                            double* ypart, double* y, hipStream_t st);
+// b[i] = a[i] rounded to FP32, i < n
+void launch_round_f32(long long n, const double* a, float* b, hipStream_t st);
 // Pk (packed upper tiles) <- the leading n_b x n_b block of S (ld n_beta)
 void launch_pack_sym(const DevTopo& t, const double* S, double* Pk, hipStream_t st);
 // Z[row][g(s)] = sum over sides sign * w * y_s[j]; one_column sums into column 0

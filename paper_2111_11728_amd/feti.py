@@ -23,6 +23,7 @@ FETI_PCG, FETI_FO, FETI_SFETI = 0, 1, 2
 FETI_DIRICHLET, FETI_LUMPED, FETI_SUPERLUMPED = 0, 1, 2
 FETI_FP64, FETI_FP32, FETI_BF16X3 = 0, 1, 2
 FETI_PURE = 16
+FETI_PRECOND_FP32 = 2
 
 METHODS = {"tfeti": FETI_TFETI, "fetidp": FETI_DP}
 SCALINGS = {"mult": FETI_MULT, "k": FETI_KSCALE}
@@ -46,7 +47,7 @@ class feti_opts(C.Structure):
                 ("precision", C.c_int), ("tol", C.c_double), ("max_it", C.c_int), ("rr_tol", C.c_double),
                 ("reorth", C.c_int), ("max_refine", C.c_int), ("relax", C.c_double), ("graphs", C.c_int),
                 ("orth_fp32", C.c_int), ("warm_start", C.c_int), ("recycle", C.c_int), ("defl_modes", C.c_int),
-                ("defl_tau", C.c_double)]
+                ("defl_tau", C.c_double), ("precond_fp32", C.c_int)]
 
 
 class feti_info(C.Structure):
@@ -164,7 +165,7 @@ class Spec:
 
     def __init__(self, prob, method="fetidp", scaling="k", krylov="pcg", precond="dirichlet", precision="fp64",
                  tol=1e-8, max_it=0, rr_tol=0.0, reorth=0, max_refine=-1, relax=0.0, graphs=0, orth_fp32=0,
-                 primal_nodes=None, warm_start=0, recycle=0, defl_modes=0, defl_tau=0.0):
+                 primal_nodes=None, warm_start=0, recycle=0, defl_modes=0, defl_tau=0.0, precond_fp32=0):
         self.prob = prob
         fixed = np.ascontiguousarray(prob.fixed_dofs(), dtype=np.int32)
         self._fixed = fixed
@@ -193,7 +194,7 @@ class Spec:
                                   else C.POINTER(C.c_int)())
         self.opts = feti_opts(METHODS[method], SCALINGS[scaling], KRYLOVS[krylov], PRECONDS[precond],
                               PRECISIONS[precision], tol, max_it, rr_tol, reorth, max_refine, relax, graphs,
-                              orth_fp32, warm_start, recycle, defl_modes, defl_tau)
+                              orth_fp32, warm_start, recycle, defl_modes, defl_tau, int(precond_fp32))
 
 
 def feti_plan_sizes(spec: Spec) -> dict:
@@ -315,8 +316,9 @@ class Context:
         p = PRECISIONS.get(precision, precision) | (FETI_PURE if pure else 0)
         _check(lib().feti_apply_F_noalloc(self.handle, k, p, _ptr(Lam), _ptr(Q)))
 
-    def feti_apply_precond(self, r, Z, one_column):
-        _check(lib().feti_apply_precond(self.handle, _ptr(r), _ptr(Z), int(one_column)))
+    def feti_apply_precond(self, r, Z, one_column, fp32=False):
+        flags = int(one_column) | (FETI_PRECOND_FP32 if fp32 else 0)
+        _check(lib().feti_apply_precond(self.handle, _ptr(r), _ptr(Z), flags))
 
     def feti_project(self, k, Y):
         _check(lib().feti_project(self.handle, k, _ptr(Y)))

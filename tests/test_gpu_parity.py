@@ -228,6 +228,51 @@ def test_apply_F_mixed(oracle_cache, name, precision, u, k):
 
 
 @pytest.mark.parametrize("name", ["c1", "3x3", "3d"])
+@pytest.mark.parametrize("precond", ["dirichlet", "lumped"])
+def test_preconditioner_fp32_blocks(oracle_cache, name, precond):
+    """The preconditioner from the FP32 copy of its blocks (precond_fp32) against the oracle's FP64
+    one, within the rounding of the stored values: |dy| <= u32 |w| |B| |S| |B^T| |w| |r| entry by
+    entry (the products and sums are FP64), and different from the FP64 blocks' result (the copy
+    is what ran)."""
+    prob, op = _oracle(oracle_cache, name, "fetidp", precond, "k")
+    print(f"case {name} {precond} fp32 blocks", flush=True)
+    ctx = _ctx(prob, method="fetidp", scaling="k", precond=precond, krylov="sfeti", precision="fp32",
+               precond_fp32=1)
+    n = op.n_lambda
+    r = np.random.default_rng(6).standard_normal(n)
+    kz = ctx.sizes["n_groups"]
+    bound = np.zeros((n, kz))
+    for s in range(len(op.dec.subs)):
+        Bb = abs(op.cons.Bb[s])
+        y = np.abs(np.asarray(op.S[s])) @ (Bb.T @ np.abs(op.w[s] * r))
+        bound[:, op.group[s]] += np.abs(op.w[s]) * (Bb @ y)
+    u32 = float(np.finfo(np.float32).eps) / 2
+    for one in (1, 0):
+        Z32 = torch.zeros((n, 1 if one else kz), dtype=torch.float64, device=DEV)
+        Z64 = torch.zeros_like(Z32)
+        ctx.feti_apply_precond(_t(r), Z32, one, fp32=True)
+        ctx.feti_apply_precond(_t(r), Z64, one)
+        ref = op.precondition(r, one_column=bool(one))
+        b = bound.sum(axis=1, keepdims=True) if one else bound
+        err32 = np.abs(Z32.cpu().numpy().reshape(ref.shape) - ref)
+        err64 = np.abs(Z64.cpu().numpy().reshape(ref.shape) - ref)
+        print(f"  one_column {one}: FP32 blocks max err/bound {float((err32 / (b + 1e-300)).max()):.2f}, "
+              f"FP64 blocks rel. err {float(err64.max() / np.abs(ref).max()):.1e}", flush=True)
+        assert np.all(err32 <= 1.01 * u32 * b + 1e-12 * np.abs(ref).max())
+        assert err32.max() > 100 * err64.max()
+    # the copy is refused without precond_fp32, and the option without a reduced precision
+    ctx.close()
+    ctx = _ctx(prob, method="fetidp", scaling="k", precond=precond)
+    with pytest.raises(feti.FetiError):
+        ctx.feti_apply_precond(_t(r), torch.zeros(n, dtype=torch.float64, device=DEV), 1, fp32=True)
+    ctx.close()
+    with pytest.raises(feti.FetiError):
+        _ctx(prob, method="fetidp", scaling="k", precond=precond, krylov="sfeti", precond_fp32=1)
+    with pytest.raises(feti.FetiError):
+        _ctx(prob, method="fetidp", scaling="k", precond=precond, krylov="pcg", precision="fp32", precond_fp32=1)
+
+
+@pytest.mark.parametrize("name", ["c1", "3x3", "3d"])
 @pytest.mark.parametrize("method", ["fetidp", "tfeti"])
 def test_preconditioner_and_rhs(oracle_cache, name, method):
     precond = "dirichlet"

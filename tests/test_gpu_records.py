@@ -147,13 +147,16 @@ def test_c2_remaining_variants_against_oracle(c2_bound, method, scaling, kr):
 
 
 @pytest.mark.parametrize("dirs", [64, 32])
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32+pk32"])
 def test_c3_sfeti_at_benchmark_tolerance(dirs, precision):
+    """fp32+pk32: the reduced-precision passes also apply the preconditioner from its FP32 blocks."""
     rec = _load("c3_sfeti.npz")
     key = f"k{dirs}_"
     prob = workloads.beta_2d(0, n_dirs=dirs)
     print(f"case c3 sfeti k={dirs} {precision} tol 1e-6", flush=True)
-    info, u, c, g = _solve(prob, precision=precision)
+    pk32 = precision.endswith("+pk32")
+    precision = precision.split("+")[0]
+    info, u, c, g = _solve(prob, precision=precision, precond_fp32=int(pk32))
     assert info["status"] == feti.FETI_OK and info["true_rel_res"] <= 1e-6
     it_o = int(rec[key + "iters"])
     ho = rec[key + "history"] / rec[key + "history"][0]
