@@ -534,17 +534,16 @@ __global__ void k_coarse_t(int n_cg, int k, const TT* __restrict__ T, const doub
 }
 
 // v = scale * Kinv t (n_cg x n_cg by n_cg x k, k <= 64) on the FP64 matrix cores: workgroup =
-// 16 rows of v, wavefront w = columns 16w..16w+15. Step Q contracts q = 16Q + 4g + s, so lane
-// (m, g) reads Kinv[p0 + m][16Q + 4g .. +3] (one 32-byte load) and t[16Q + 4g + s][16w + m].
-__global__ void __launch_bounds__(1024) k_coarse_v(const CoarseTile* __restrict__ tiles,
-                                                   const CoarseBlk* __restrict__ blks, int k, const double* __restrict__ tg,
-                                                   const double* __restrict__ Kg, double scale, double* __restrict__ vg) {
-    // workgroup: 16 rows of v inside one design's block (v_B = Kbar_B^{-1} t_B); wavefront
-    // (cg, ks) = (w mod 4, w / 4): columns 16 cg..16 cg + 15 and the 16-wide contraction slices
-    // Q = ks (mod 4), three slices of loads in flight; the four partial tiles are summed in LDS in
-    // a fixed order
+// 16 rows and 16 columns (16 blockIdx.y .. + 15) of v. Step Q contracts q = 16Q + 4g + s, so
+// lane (m, g) reads Kinv[p0 + m][16Q + 4g .. +3] (one 32-byte load) and t[16Q + 4g + s][col].
+__global__ void __launch_bounds__(256) k_coarse_v(const CoarseTile* __restrict__ tiles,
+                                                  const CoarseBlk* __restrict__ blks, int k, const double* __restrict__ tg,
+                                                  const double* __restrict__ Kg, double scale, double* __restrict__ vg) {
+    // workgroup: 16 rows of v inside one design's block (v_B = Kbar_B^{-1} t_B) and one 16-column
+    // group cg; wavefront ks takes the 16-wide contraction slices Q = ks (mod 4), three slices of
+    // loads in flight; the four partial tiles are summed in LDS in a fixed order
     typedef double v4 __attribute__((ext_vector_type(4)));
-    __shared__ double red[4][16][64];
+    __shared__ double red[4][16][16];
     const CoarseTile T = tiles[blockIdx.x];
     const CoarseBlk B = blks[T.blk];
     const int n_cg = B.n;
@@ -552,7 +551,7 @@ __global__ void __launch_bounds__(1024) k_coarse_v(const CoarseTile* __restrict_
     const double* __restrict__ t = tg + (long long)B.cg0 * k;
     double* __restrict__ v = vg + (long long)B.cg0 * k;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
-    const int cg = wave & 3, ks = wave >> 2;
+    const int cg = blockIdx.y, ks = wave;
     const int p0 = T.r0, col = 16 * cg + m;
     const int prow = p0 + m;
     const int nQ = (n_cg + 15) >> 4;
@@ -589,14 +588,14 @@ __global__ void __launch_bounds__(1024) k_coarse_v(const CoarseTile* __restrict_
     }
     // D layout: rows g + 4 j, column m
 #pragma unroll
-    for (int j = 0; j < 4; ++j) red[ks][g + 4 * j][col] = acc[j];
+    for (int j = 0; j < 4; ++j) red[ks][g + 4 * j][m] = acc[j];
     __syncthreads();
     if (ks == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = g + 4 * j, p = p0 + r;
             if (p < n_cg && col < k)
-                v[(long long)p * k + col] = scale * (((red[0][r][col] + red[1][r][col]) + red[2][r][col]) + red[3][r][col]);
+                v[(long long)p * k + col] = scale * (((red[0][r][m] + red[1][r][m]) + red[2][r][m]) + red[3][r][m]);
         }
     }
 }
@@ -611,7 +610,7 @@ void launch_coarse(const DevTopo& t, int k, int ytype_f32, const void* T, const 
     else
         k_coarse_t<double><<<(int)((n + 255) / 256), 256, 0, st>>>(t.n_cg, k, (const double*)T, add, t.cc_ptr,
                                                                    t.cc_s, t.cc_j, t.subs, tbuf);
-    k_coarse_v<<<t.n_ctiles, 1024, 0, st>>>(t.ctiles, t.cblk, k, tbuf, Kinv, scale, v);
+    k_coarse_v<<<dim3(t.n_ctiles, (k + 15) / 16), 256, 0, st>>>(t.ctiles, t.cblk, k, tbuf, Kinv, scale, v);
 }
 
 // Y_s[j][c] += sum_q F_rc^s[j][q] v[cg(s,q)][c]  (the coarse correction folded into the local
@@ -1085,7 +1084,8 @@ __global__ void k_precond_scatter(int n_lambda, int kz, int one_column, const in
 
 // kz = 64: a wavefront takes 64 rows; lane l first resolves row r0 + l (its one or two sides:
 // group and sign * w * y_s[j]), then the wavefront writes the 64 rows one after another, lane =
-// column (coalesced 512-byte rows), taking each row's values by shuffle. Same sums, same order.
+// column (coalesced 512-byte rows), taking each row's values by readlane (the row index is
+// wavefront-uniform: scalar reads, no LDS round trip). Same sums, same order.
 __global__ void __launch_bounds__(256) k_precond_scatter64(int n_lambda, const int* __restrict__ row_s,
                                                            const int* __restrict__ row_j,
                                                            const int8_t* __restrict__ row_sg,
@@ -1109,8 +1109,8 @@ __global__ void __launch_bounds__(256) k_precond_scatter64(int n_lambda, const i
     }
     const int nr = min(64, n_lambda - r0);
     for (int i = 0; i < nr; ++i) {
-        const int gai = __shfl(ga, i), gbi = __shfl(gb, i);
-        const double vai = __shfl(va, i), vbi = __shfl(vb, i);
+        const int gai = __builtin_amdgcn_readlane(ga, i), gbi = __builtin_amdgcn_readlane(gb, i);
+        const double vai = bcast_lane(va, i), vbi = bcast_lane(vb, i);
         double v = 0.0;
         if (lane == gai) v += vai;
         if (lane == gbi) v += vbi;

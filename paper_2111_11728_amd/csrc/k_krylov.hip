@@ -526,23 +526,24 @@ static void launch_gram64_reduce(int nwg, int contrib, int n, int nblk, int G, c
 }
 
 // part[c][0..63] = sum over the chunk's rows of A[row][:] * x[row] (A: n x 64). Lane = column;
-// a wavefront covers 8 rows per pass, four wavefronts summed in LDS (fixed order).
+// a wavefront covers 8 rows per pass (the loads of two passes in flight), four wavefronts summed
+// in LDS (fixed order).
 __global__ void __launch_bounds__(256) k_gemv_t64(int n, const double* __restrict__ A, const double* __restrict__ x,
                                                   double* __restrict__ part) {
     __shared__ double red[4][64];
     const int c = blockIdx.x, nchunk = gridDim.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r0 = (int)((long long)c * n / nchunk), r1 = (int)((long long)(c + 1) * n / nchunk);
     double acc = 0.0;
-    for (int rr = r0 + 8 * wave; rr < r1; rr += 32) {
-        double av[8], xv[8];
+    for (int rr = r0 + 8 * wave; rr < r1; rr += 64) {
+        double av[16], xv[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int row = rr + u;
+        for (int u = 0; u < 16; ++u) {
+            const int row = rr + (u < 8 ? u : 24 + u);   // this pass's 8 rows, then the next pass's
             av[u] = row < r1 ? A[(long long)row * 64 + lane] : 0.0;
             xv[u] = row < r1 ? x[row] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = fma(av[u], xv[u], acc);
+        for (int u = 0; u < 16; ++u) acc = fma(av[u], xv[u], acc);
     }
     red[wave][lane] = acc;
     __syncthreads();
