@@ -151,6 +151,7 @@ struct feti_ctx {
     long long bytes = 0;
 
     // numeric state
+    double* Emod = nullptr;   // SIMP moduli of the elements, per setup (Sec. 1, Eq. 1)
     double *rho = nullptr, *L = nullptr, *Li = nullptr, *Z = nullptr, *S = nullptr, *diag = nullptr, *F64 = nullptr;
     double* sw64 = nullptr;
     float* sw32 = nullptr;
@@ -591,6 +592,7 @@ void build_layout(feti_ctx* c) {
     c->tau = c->alloc<double>(ns);
     c->diag = c->alloc<double>(t.nloc_tot);
     c->rho = c->alloc<double>(P.n_el);
+    c->Emod = c->alloc<double>(std::max<long long>(1, P.n_el));
     c->info = c->alloc<int>(ns + 8);
     const int ncg = P.n_cg;
     // Kbar_cc: one dense block per design, 16-row tiles for the coarse solve
@@ -917,7 +919,6 @@ void build_layout(feti_ctx* c) {
     std::vector<double> K0 = element_K0(P.dim, P.nu);
     c->K0dev = c->upload(K0);
     t.K0dev = c->K0dev;
-    upload_K0(K0.data(), (int)std::lround(std::sqrt((double)K0.size())), c->st);
     CHECK_LAUNCH();
 
     // solve buffers
@@ -1177,7 +1178,8 @@ void numeric_setup(feti_ctx* c) {
     zero(c->info, (t.n_sub + 8) * 4);
     // every subdomain is assembled (its diagonal feeds the scaling weights); the factorisation
     // and the local operators are formed for the representatives only (ts, nr)
-    launch_assemble(t, c->rho, c->p, c->E0, c->Emin, c->L, c->Z, c->S, c->diag, st);
+    launch_simp_moduli(P.n_el, c->rho, c->p, c->E0, c->Emin, c->Emod, st);
+    launch_assemble(t, c->Emod, c->L, c->Z, c->S, c->diag, st);
     CHECK_LAUNCH();
     const std::vector<int> reps = find_modules(c);
     const int nr = (int)reps.size();
@@ -1456,9 +1458,12 @@ void compute_rhs(feti_ctx* c, const double* f) {
     if (f != c->f_last) HIPCHK(hipMemcpyAsync(c->f_last, f, sizeof(double) * P.n_dof, hipMemcpyDeviceToDevice, st));
     c->have_f = true;
     launch_scatter_f(t, f, c->fi, c->fbeta, st);
+    // g = f_beta - K_beta,i K_ii^{-1} f_i: the two band sweeps, then the coupling rows formed from
+    // the element densities (no pass over the stored Z = L^{-1} K_i,beta)
     HIPCHK(hipMemcpyAsync(c->h, c->fi, sizeof(double) * std::max<long long>(1, t.ni_tot), hipMemcpyDeviceToDevice, st));
     launch_bt_fsolve1(t, c->L, c->Li, c->h, st);
-    launch_zt_gemv(t, c->Z, c->h, c->fbeta, c->g, c->part, st);
+    launch_bt_bsolve1(t, c->L, c->Li, c->h, st);
+    launch_coupling(t, c->Emod, 1, c->h, c->fbeta, c->g, st);
     launch_local_F(t, c->F64, c->g, c->yb, c->yc, st);
     CHECK_LAUNCH();
     if (P.n_lambda > 0) {
@@ -2246,7 +2251,10 @@ void recover(feti_ctx* c, double* u) {
         alpha = c->alpha;
     }
     CHECK_LAUNCH();
-    launch_z_gemv(t, c->Z, c->ubeta, c->h, c->ui, st);
+    // u_i = K_ii^{-1} (f_i - K_i,beta u_beta): coupling rows from the element densities, then the
+    // two band sweeps
+    launch_coupling(t, c->Emod, 0, c->ubeta, c->fi, c->ui, st);
+    launch_bt_fsolve1(t, c->L, c->Li, c->ui, st);
     launch_bt_bsolve1(t, c->L, c->Li, c->ui, st);
     launch_assemble_loc(t, c->ui, c->ubeta, c->Cit, alpha, c->uloc, st);
     launch_average(t, c->uloc, u, st);

@@ -6,8 +6,6 @@
 
 namespace feti {
 
-__constant__ double c_K0[24 * 24];
-
 // ---------------------------------------------------------------------------------------
 // Assembly (Sec. 1 Eq. 1 and Sec. 2 Eq. 3): K^s = sum_e (Emin + rho_e^p (E0 - Emin)) K0.
 // One thread per (subdomain, local node a); it forms every dpn x dpn block K_ab with its
@@ -16,8 +14,8 @@ __constant__ double c_K0[24 * 24];
 //   (i, beta) -> Z (becomes L^{-1} K_i,beta), (beta, beta) -> S (becomes the Schur complement),
 //   diagonal -> diag (k-scaling). Each entry has exactly one writer: no atomics.
 __global__ void k_assemble(const SubMeta* __restrict__ subs, const LineMeta* __restrict__ lines, int dim,
-                           const double* __restrict__ rho, double p, double E0,
-                           double Emin, const int8_t* __restrict__ lcls, const int* __restrict__ lidx,
+                           const double* __restrict__ K0, const double* __restrict__ Emod,
+                           const int8_t* __restrict__ lcls, const int* __restrict__ lidx,
                            double* __restrict__ Lbuf, double* __restrict__ Zbuf, double* __restrict__ Sbuf,
                            double* __restrict__ diag) {
     const int s = blockIdx.y;
@@ -50,10 +48,10 @@ __global__ void k_assemble(const SubMeta* __restrict__ subs, const LineMeta* __r
                             const int cb = (bx - ex) + 2 * (by - ey) + (dim == 3 ? 4 * (bz - ez) : 0);
                             const long long ge = M.el0 + (long long)(M.lo[0] + ex) +
                                                  (long long)M.nelx * ((M.lo[1] + ey) + (long long)M.nely * (M.lo[2] + ez));
-                            const double E = Emin + pow(rho[ge], p) * (E0 - Emin);
+                            const double E = Emod[ge];
                             for (int ci = 0; ci < dpn; ++ci)
                                 for (int cj = 0; cj < dpn; ++cj)
-                                    blk[ci * dpn + cj] += E * c_K0[(ca * dpn + ci) * ne + cb * dpn + cj];
+                                    blk[ci * dpn + cj] += E * K0[(ca * dpn + ci) * ne + cb * dpn + cj];
                         }
                 const int line_b = dim == 2 ? by : bz;
                 for (int ci = 0; ci < dpn; ++ci) {
@@ -86,6 +84,109 @@ __global__ void k_assemble(const SubMeta* __restrict__ subs, const LineMeta* __r
                     }
                 }
             }
+}
+
+// ---------------------------------------------------------------------------------------
+// The interior-interface coupling blocks of K^s (Sec. 2, Eq. 3) applied without storing them:
+// the entries are formed from the element densities exactly as in k_assemble (same element
+// sums), one thread per (subdomain, local node a), only for node pairs (a, b) that carry the
+// two classes:
+//   to_beta = 0: out_i    = f_i    - K_i,beta in_beta  (rows: interior DOFs of a)
+//   to_beta = 1: out_beta = f_beta - K_beta,i in_i     (rows: interface and corner DOFs of a)
+// Interior vectors sit at off_i, beta vectors at off_b + off_c (interface DOFs, then corners).
+__global__ void k_coupling(const SubMeta* __restrict__ subs, int dim, const double* __restrict__ K0,
+                           const double* __restrict__ Emod, const int8_t* __restrict__ lcls, const int* __restrict__ lidx,
+                           int to_beta, const double* __restrict__ in, const double* __restrict__ f,
+                           double* __restrict__ out) {
+    const int s = blockIdx.y;
+    const SubMeta M = subs[s];
+    const int nnodes = M.nn[0] * M.nn[1] * M.nn[2];
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nnodes) return;
+    const int dpn = dim, ne = dpn << dim;
+    const long long ob = M.off_b + M.off_c;
+    // row DOFs of a in the output class
+    bool any_row = false;
+    for (int ci = 0; ci < dpn; ++ci) {
+        const int cp = lcls[M.off_loc + (long long)a * dpn + ci];
+        any_row |= to_beta ? (cp == CLS_B || cp == CLS_C) : cp == CLS_I;
+    }
+    if (!any_row) return;
+    const int ax = a % M.nn[0], ay = (a / M.nn[0]) % M.nn[1], az = a / (M.nn[0] * M.nn[1]);
+    const int ex_max = M.nn[0] - 1, ey_max = M.nn[1] - 1, ez_max = dim == 3 ? M.nn[2] - 1 : 1;
+    const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int dz = zlo; dz <= zhi; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int bx = ax + dx, by = ay + dy, bz = az + dz;
+                if (bx < 0 || by < 0 || bz < 0 || bx >= M.nn[0] || by >= M.nn[1] || bz >= M.nn[2]) continue;
+                const int b = bx + M.nn[0] * (by + M.nn[1] * bz);
+                // column DOFs of b in the input class, and their input values
+                double xin[3] = {0.0, 0.0, 0.0};
+                bool any_col = false;
+                for (int cj = 0; cj < dpn; ++cj) {
+                    const long long ql = M.off_loc + (long long)b * dpn + cj;
+                    const int cq = lcls[ql], iq = lidx[ql];
+                    if (to_beta ? cq == CLS_I : (cq == CLS_B || cq == CLS_C)) {
+                        any_col = true;
+                        xin[cj] = to_beta ? in[M.off_i + iq] : in[ob + (cq == CLS_B ? iq : M.n_b + iq)];
+                    }
+                }
+                if (!any_col) continue;
+                double blk[9];
+                for (int q = 0; q < 9; ++q) blk[q] = 0.0;
+                const int ex0 = max(max(ax, bx) - 1, 0), ex1 = min(min(ax, bx), ex_max - 1);
+                const int ey0 = max(max(ay, by) - 1, 0), ey1 = min(min(ay, by), ey_max - 1);
+                const int ez0 = dim == 3 ? max(max(az, bz) - 1, 0) : 0;
+                const int ez1 = dim == 3 ? min(min(az, bz), ez_max - 1) : 0;
+                for (int ez = ez0; ez <= ez1; ++ez)
+                    for (int ey = ey0; ey <= ey1; ++ey)
+                        for (int ex = ex0; ex <= ex1; ++ex) {
+                            const int ca = (ax - ex) + 2 * (ay - ey) + (dim == 3 ? 4 * (az - ez) : 0);
+                            const int cb = (bx - ex) + 2 * (by - ey) + (dim == 3 ? 4 * (bz - ez) : 0);
+                            const long long ge = M.el0 + (long long)(M.lo[0] + ex) +
+                                                 (long long)M.nelx * ((M.lo[1] + ey) + (long long)M.nely * (M.lo[2] + ez));
+                            const double E = Emod[ge];
+                            for (int ci = 0; ci < dpn; ++ci)
+                                for (int cj = 0; cj < dpn; ++cj)
+                                    blk[ci * dpn + cj] += E * K0[(ca * dpn + ci) * ne + cb * dpn + cj];
+                        }
+                // xin is zero for the DOFs of b outside the input class (fixed ones included)
+                for (int ci = 0; ci < dpn; ++ci)
+                    for (int cj = 0; cj < dpn; ++cj) acc[ci] = fma(blk[ci * dpn + cj], xin[cj], acc[ci]);
+            }
+    for (int ci = 0; ci < dpn; ++ci) {
+        const long long pl = M.off_loc + (long long)a * dpn + ci;
+        const int cp = lcls[pl], ip = lidx[pl];
+        if (to_beta) {
+            if (cp == CLS_B || cp == CLS_C) {
+                const long long o = ob + (cp == CLS_B ? ip : M.n_b + ip);
+                out[o] = f[o] - acc[ci];
+            }
+        } else if (cp == CLS_I) {
+            out[M.off_i + ip] = f[M.off_i + ip] - acc[ci];
+        }
+    }
+}
+
+void launch_coupling(const DevTopo& t, const double* Emod, int to_beta, const double* in, const double* f, double* out,
+                     hipStream_t st) {
+    dim3 grid((t.max_nodes + 255) / 256, t.n_sub);
+    k_coupling<<<grid, 256, 0, st>>>(t.subs, t.dim, t.K0dev, Emod, t.lcls, t.lidx, to_beta, in, f, out);
+}
+
+// SIMP moduli (Sec. 1, Eq. 1): E_e = Emin + rho_e^p (E0 - Emin), once per setup for the assembly
+// and the coupling rows of the solve
+__global__ void k_simp_moduli(long long n, const double* __restrict__ rho, double p, double E0, double Emin,
+                              double* __restrict__ Emod) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e < n) Emod[e] = Emin + pow(rho[e], p) * (E0 - Emin);
+}
+
+void launch_simp_moduli(long long n, const double* rho, double p, double E0, double Emin, double* Emod,
+                        hipStream_t st) {
+    if (n > 0) k_simp_moduli<<<(int)((n + 255) / 256), 256, 0, st>>>(n, rho, p, E0, Emin, Emod);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1277,10 +1378,6 @@ __global__ void k_set_identity(double* A, int n, long long lda) {
 // ---------------------------------------------------------------------------------------
 // host launchers
 
-void upload_K0(const double* K0, int n, hipStream_t st) {
-    hipMemcpyToSymbolAsync(HIP_SYMBOL(c_K0), K0, sizeof(double) * n * n, 0, hipMemcpyHostToDevice, st);
-}
-
 // ---- module types (factorisation recycling) ----
 // Element e of subdomain s in local lexicographic order (x fastest), as its global index.
 __device__ __forceinline__ long long sub_element(const SubMeta& M, int dim, int e) {
@@ -1352,11 +1449,10 @@ void launch_gather_rows(int n, int w, const int* map, const double* src, double*
     if (m) k_gather_rows<<<(int)((m + 255) / 256), 256, 0, st>>>(n, w, map, src, dst);
 }
 
-void launch_assemble(const DevTopo& t, const double* rho, double p, double E0, double Emin, double* L, double* Z,
-                     double* S, double* diag, hipStream_t st) {
+void launch_assemble(const DevTopo& t, const double* Emod, double* L, double* Z, double* S, double* diag,
+                     hipStream_t st) {
     dim3 grid((t.max_nodes + 255) / 256, t.n_sub);
-    k_assemble<<<grid, 256, 0, st>>>(t.subs, t.lines, t.dim, rho, p, E0, Emin, t.lcls, t.lidx,
-                                     L, Z, S, diag);
+    k_assemble<<<grid, 256, 0, st>>>(t.subs, t.lines, t.dim, t.K0dev, Emod, t.lcls, t.lidx, L, Z, S, diag);
 }
 
 void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st) {

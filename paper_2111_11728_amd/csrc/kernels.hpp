@@ -152,9 +152,15 @@ struct DevTopo {
 };
 
 // ---- setup (k_setup.hip) ----
-void upload_K0(const double* K0, int n, hipStream_t st);
-void launch_assemble(const DevTopo& t, const double* rho, double p, double E0, double Emin, double* L, double* Z,
-                     double* S, double* diag, hipStream_t st);
+// rows of K^s coupling interior and interface DOFs, applied from the element densities:
+// to_beta = 0: out_i = f_i - K_i,beta in_beta; to_beta = 1: out_beta = f_beta - K_beta,i in_i
+void launch_coupling(const DevTopo& t, const double* Emod, int to_beta, const double* in, const double* f, double* out,
+                     hipStream_t st);
+// Emod[e] = Emin + rho_e^p (E0 - Emin), e < n
+void launch_simp_moduli(long long n, const double* rho, double p, double E0, double Emin, double* Emod,
+                        hipStream_t st);
+void launch_assemble(const DevTopo& t, const double* Emod, double* L, double* Z, double* S, double* diag,
+                     hipStream_t st);
 void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st);
 // Block-tridiagonal Cholesky that also writes L_kk^{-1} (lines <= 128 DOFs; otherwise the
 // generic factorisation, and launch_bt_invert must follow)
