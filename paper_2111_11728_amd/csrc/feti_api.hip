@@ -825,8 +825,11 @@ void build_layout(feti_ctx* c) {
             pu_cg.insert(pu_cg.end(), U.begin(), U.end());
             pu_ptr.push_back((int)pu_cg.size());
         }
-        // local product rows are stored as int in the row records
-        if (maxu <= kFoldPairMaxU && t.nb_tot < (1LL << 31)) {
+        // local product rows are stored as int in the row records. The pair form sums a row's fold
+        // entries one at a time, so it pays only for narrow rows: 2D (at most 16 entries: 27.5 us
+        // at 16x16 subdomains against 58 us for the fold per subdomain, then the scatter); 3D rows
+        // carry up to 48 (145 us at 4x4x4 subdomains against 84 us), and take the two kernels.
+        if (maxu <= kFoldPairMaxU && W <= kFoldPairMaxW && t.nb_tot < (1LL << 31)) {
             t.n_pairs = (int)groups.size();
             t.pr_ptr = c->upload(pr_ptr);
             t.pu_ptr = c->upload(pu_ptr);
@@ -1353,7 +1356,12 @@ void apply_F_with(feti_ctx* c, int k, int prec, const double* Lam, double* Q, co
     if (time_it) HIPCHK(hipEventRecord(c->ev[3], st));
     if (c->P.method == FETI_DP && c->P.n_cg > 0) {
         launch_coarse(t, k, f32, b.T, nullptr, c->Kcc_inv, 1.0, b.v, b.tc, st);
-        launch_scatter_fold(t, k, f32, b.Y, b.v, Q, st);
+        if (k >= 32 && t.n_pairs == 0) {   // wide fold rows (3D): the fold per subdomain, then the scatter
+            launch_fold_coarse(t, k, f32, c->F64, b.v, b.Y, st);
+            launch_scatter(t, k, f32, b.Y, Q, st);
+        } else {
+            launch_scatter_fold(t, k, f32, b.Y, b.v, Q, st);
+        }
     } else {
         launch_scatter(t, k, f32, b.Y, Q, st);
     }
