@@ -14,7 +14,8 @@ written by make_krylov_goldens.py and make_c3_u_sample.py, which call only the o
   history, u at 4096 sampled DOFs against the oracle's solve at the same tolerance, the compliance
   and the gradient at 20 sampled elements.
 * 3D modular design, 4x4x4 subdomains of 12^3 (352 947 DOFs): u against the oracle's reference
-  solution (its FETI-DP at tol 1e-10; FP64 at tol 1e-10: 1e-8; FP32 F*Lambda at tol 1e-8: 1e-6), the
+  solution (its FETI-DP at tol 1e-9, the tightest level it reaches within a few dozen iterations;
+  FP64 at the same tol: 1e-8; FP32 F*Lambda at tol 1e-8: 1e-6), the
   gradient at 20 sampled elements against the oracle's formula on the GPU's u, and the S-FETI-DP
   iteration count and u at 1e-6 against the oracle's run at 1e-6.
 """
@@ -182,11 +183,12 @@ def test_c3_sfeti_at_benchmark_tolerance(dirs, precision):
     assert g_ok
 
 
-@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-10, 1e-8), ("fp32", 1e-8, 1e-6)])
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-9, 1e-8), ("fp32", 1e-8, 1e-6)])
 def test_c5_full_size_against_reference(precision, tol, bound):
     """u, c and the gradient against the oracle's reference solution of the 3D workload (its FETI-DP
-    at tol 1e-10; the global direct factorisation does not finish at this size); the gradient also
-    against the oracle's formula on the GPU's own u."""
+    at tol 1e-9; the global direct factorisation does not finish at this size, and solutions at a
+    tolerance lie about 65 times it from the converged one here, so the FP64 solve runs at the
+    reference's own tolerance); the gradient also against the oracle's formula on the GPU's own u."""
     rec = _load("c5_sfeti.npz")
     prob = workloads.modular_3d(0)
     print(f"case c5 {precision} tol {tol}", flush=True)
