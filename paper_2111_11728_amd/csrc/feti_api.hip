@@ -1876,6 +1876,21 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
             all_mask |= gmask[d];
         }
     if (seg) all_mask = nds >= 64 ? ~0ull : (1ull << nds) - 1;   // bit d: design d
+    // the precision gate's eps. Several designs: a reduced product moves design d's true residual
+    // away from its recursive one by about eta eps_d, which must stay below 0.1 tol eps0_d for
+    // every design still searching; the gate sees the worst ratio eps_d / eps0_d, on the scale
+    // of eps0 (one design: eps itself)
+    auto gate_eps = [&]() -> double {
+        if (nds <= 1) return o.eps;
+        double w = 0.0;
+        for (int d = 0; d < nds; ++d) {
+            const bool fz = multi ? (frozen & gmask[d]) != 0 : seg ? ((frozen >> d) & 1ull) != 0 : false;
+            const double e0 = c->eps0_d[d];
+            if (fz || !(e0 > 0.0)) continue;
+            w = std::max(w, std::sqrt(std::max(c->hpin[16 + d], 0.0)) / e0);
+        }
+        return w * eps0;
+    };
     int nb = 0;
     double best = o.eps;
     int it_best = 0;
@@ -1885,7 +1900,7 @@ KrylovOut run_sfeti(feti_ctx* c, PrecGate& g, int kd, double eps0, double tol, i
         double* Wn = (double*)c->WH[nb];
         double* Qn = (double*)c->QH[nb];
         const int probes_before = g.probes;
-        const int p_it = gated_apply(c, g, replaced, o.eps, eps0, kd, c->Zk, c->Qk, c->Qtmp);
+        const int p_it = gated_apply(c, g, replaced, gate_eps(), eps0, kd, c->Zk, c->Qk, c->Qtmp);
         const bool probed = g.probes != probes_before;
         o.reduced += p_it != FETI_FP64;
         if (seg) {
