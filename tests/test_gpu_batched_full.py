@@ -80,3 +80,29 @@ def test_full_batch_against_direct_and_single_design():
         assert g_err <= 1e-10
         assert c_err <= 1e-12
     ctx.close()
+
+
+def test_full_batch_mixed_precision_keeps_the_reduced_pass():
+    """The 0/1 batch of the benchmark (64 designs, tol 1e-6) with FP32 F*Lambda: the precision gate
+    takes the worst design's relative residual, so the reduced pass reaches the tolerance without
+    an FP64 restart and in the FP64 solve's iteration count (within 2); every design's true
+    residual meets the tolerance."""
+    probs = [workloads.uneven_design(0, d) for d in range(64)]
+    rho = _t(np.concatenate([p.rho for p in probs]))
+    f = _t(np.concatenate([p.load() for p in probs]))
+    its = {}
+    for precision in ("fp64", "fp32"):
+        specs = [feti.Spec(p, method="fetidp", scaling="k", krylov="sfeti", precision=precision, tol=1e-6,
+                           max_it=1000) for p in probs]
+        ctx = feti.BatchedContext(specs, rho)
+        u = torch.zeros(sum(p.n_dof for p in probs), dtype=torch.float64, device=DEV)
+        info = ctx.feti_solve(f, u)
+        res = ctx.feti_design_residuals()
+        ctx.close()
+        its[precision] = info["iters"]
+        print(f"case full batch {precision}: {info['iters']} iterations ({info['reduced_iters']} reduced, "
+              f"{info['fp64_fallback']} FP64 restarts), worst design residual {res.max():.2e}", flush=True)
+        assert (res <= 1e-6).all()
+        if precision == "fp32":
+            assert info["fp64_fallback"] == 0 and info["reduced_iters"] > 0
+    assert its["fp32"] <= its["fp64"] + 2
