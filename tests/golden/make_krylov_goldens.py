@@ -140,18 +140,44 @@ def c5():
     op = feti.FETIDP(prob, "dirichlet", "k")
     t_setup = time.perf_counter() - t0
     print(f"c5 setup {t_setup:.1f} s, n_lambda {op.n_lambda}", flush=True)
-    t0 = time.perf_counter()
-    ref = krylov.solve(op, "sfeti", tol=1e-9)
-    u_ref, _ = op.recover(ref.lam)
-    t_ref = time.perf_counter() - t0
-    g_ref = fem.compliance_gradient(prob, u_ref)
-    print(f"c5 reference solve (tol 1e-9) {ref.iters} iterations, {t_ref:.1f} s", flush=True)
-    r = _run(op, prob, "sfeti", 1e-6, idx, eidx)
+    _progress(op)
     model, threads, ncpu = _cpu()
-    np.savez(HERE / "c5_sfeti.npz", idx=idx, el_idx=eidx, u_ref=u_ref[idx], u_ref_norm=np.linalg.norm(u_ref),
-             c_ref=fem.compliance(prob.load(), u_ref), g_ref=g_ref[eidx], ref_iters=ref.iters, t_ref=t_ref,
-             t_setup=t_setup, n_lambda=op.n_lambda, cpu_model=model, threads=threads, cpu_count=ncpu,
-             **{f"k64_{key}": v for key, v in r.items()})
+    out = dict(idx=idx, el_idx=eidx, t_setup=t_setup, n_lambda=op.n_lambda, cpu_model=model, threads=threads,
+               cpu_count=ncpu)
+    # the benchmark's tolerance first (its record stands on its own), then the reference
+    r = _run(op, prob, "sfeti", 1e-6, idx, eidx)
+    out.update({f"k64_{key}": v for key, v in r.items()})
+    np.savez(HERE / "c5_sfeti.npz", **out)
+    t0 = time.perf_counter()
+    ref = krylov.solve(op, "sfeti", tol=1e-9, max_it=200)
+    t_ref = time.perf_counter() - t0
+    print(f"c5 reference solve (tol 1e-9) {ref.iters} iterations, converged {ref.converged}, {t_ref:.1f} s",
+          flush=True)
+    if ref.converged:
+        u_ref, _ = op.recover(ref.lam)
+        g_ref = fem.compliance_gradient(prob, u_ref)
+        out.update(u_ref=u_ref[idx], u_ref_norm=np.linalg.norm(u_ref), c_ref=fem.compliance(prob.load(), u_ref),
+                   g_ref=g_ref[eidx], ref_iters=ref.iters, t_ref=t_ref)
+        np.savez(HERE / "c5_sfeti.npz", **out)
+
+
+def _progress(op):
+    """Prints the preconditioned residual ratio each time the oracle preconditions a residual (one
+    line per iteration of a long run)."""
+    pc = op.precondition
+    state = {"eps0": None, "n": 0, "t0": time.perf_counter()}
+
+    def precondition(r, one_column=False):
+        Z = pc(r, one_column)
+        e = float(np.sqrt(max(float(r @ Z.sum(axis=1)), 0.0)))
+        if state["eps0"] is None:
+            state["eps0"] = e
+        state["n"] += 1
+        print(f"    precondition {state['n']}: eps/eps0 {e / state['eps0']:.3e} at {time.perf_counter() - state['t0']:.0f} s",
+              flush=True)
+        return Z
+
+    op.precondition = precondition
 
 
 class DenseF:
