@@ -826,10 +826,14 @@ void build_layout(feti_ctx* c) {
             pu_ptr.push_back((int)pu_cg.size());
         }
         // local product rows are stored as int in the row records. The pair form sums a row's fold
-        // entries one at a time, so it pays only for narrow rows: 2D (at most 16 entries: 27.5 us
-        // at 16x16 subdomains against 58 us for the fold per subdomain, then the scatter); 3D rows
-        // carry up to 48 (145 us at 4x4x4 subdomains against 84 us), and take the two kernels.
-        if (maxu <= kFoldPairMaxU && W <= kFoldPairMaxW && t.nb_tot < (1LL << 31)) {
+        // entries one at a time and runs a group's rows in one workgroup, so it pays only for
+        // narrow rows in long groups: 2D with 126-row groups (27.5 us at 16x16 subdomains of 64^2
+        // against 58 us for the fold per subdomain, then the scatter; solve 54.4 against 56.0 ms).
+        // 3D rows carry up to 48 entries (145 us at 4x4x4 subdomains against 84 us), and the
+        // batched 2D designs have groups of 30-94 rows (solve 152.4 against 148.2 ms): both take
+        // the two kernels.
+        const bool long_groups = (long long)P.n_lambda >= (long long)kFoldPairMinRows * (long long)groups.size();
+        if (maxu <= kFoldPairMaxU && W <= kFoldPairMaxW && long_groups && t.nb_tot < (1LL << 31)) {
             t.n_pairs = (int)groups.size();
             t.pr_ptr = c->upload(pr_ptr);
             t.pu_ptr = c->upload(pu_ptr);

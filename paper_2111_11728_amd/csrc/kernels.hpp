@@ -236,6 +236,7 @@ void launch_gather_rows(int n, int w, const int* map, const double* src, double*
 constexpr int kFoldPairMaxU = 64;   // corner DOFs of two subdomains staged per group
 constexpr int kFoldRows = 4;        // rows per wavefront and pass of the pair scatter-fold
 constexpr int kFoldPairMaxW = 32;   // widest fold row (entries) taken by the pair scatter-fold
+constexpr int kFoldPairMinRows = 96;   // shortest mean group (rows) taken by the pair scatter-fold
 // fr_val from the F_rc^T rows of the augmented operators (after launch_frc)
 void launch_fold_rows(const DevTopo& t, const double* F64, hipStream_t st);
 // Q = sum_s B_s Y_s + (B_r F_rc B_c) v: the scatter with the coarse fold of F*Lambda in one pass

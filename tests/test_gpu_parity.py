@@ -91,6 +91,8 @@ SMALL = {
     "3x3": lambda: workloads.cantilever_tfeti(2, nsub=(3, 3), m=5),
     "uneven": lambda: workloads.uneven_design(1, 0),
     "3d": lambda: workloads.modular_3d(1, nsub=(2, 2, 2), m=3),
+    # groups of 98 rows per pair of subdomains: the pair scatter-fold (blocks of 32 or more columns)
+    "pair": lambda: workloads.cantilever_tfeti(0, nsub=(2, 2), m=50),
 }
 
 
@@ -138,7 +140,7 @@ def test_fetidp_local_operators(oracle_cache, name, precond):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "3x3", "uneven", "3d"])
+@pytest.mark.parametrize("name", ["c1", "3x3", "uneven", "3d", "pair"])
 @pytest.mark.parametrize("method", ["fetidp", "tfeti"])
 @pytest.mark.parametrize("k", [1, 7, 64])
 def test_apply_F_fp64(oracle_cache, name, method, k):
@@ -209,7 +211,7 @@ def test_apply_F_fp64_well_conditioned(name, method, k):
 
 @pytest.mark.parametrize("k", [64, 16])
 @pytest.mark.parametrize("precision,u", [("fp32", 2.0 ** -24), ("bf16x3", 2.0 ** -16)])
-@pytest.mark.parametrize("name", ["c1", "uneven", "3d"])
+@pytest.mark.parametrize("name", ["c1", "uneven", "3d", "pair"])
 def test_apply_F_mixed(oracle_cache, name, precision, u, k):
     """Every row block in the reduced precision (an FP64 context has no hybrid lists), for the
     64-column and the 16-column forms of the kernel."""
