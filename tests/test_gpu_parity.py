@@ -701,24 +701,26 @@ def test_tile_shapes_leave_the_product_unchanged(name, prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["dirs64", "modular"])
-def test_graph_replay_matches_direct(name):
+@pytest.mark.parametrize("name,mixed", [("dirs64", False), ("modular", False), ("dirs64", True)])
+def test_graph_replay_matches_direct(name, mixed):
     """S-FETI with the per-iteration operator sequences replayed as captured hipGraphs (on a
     non-default stream) gives bit for bit the solution of direct launches, over three solves
     (every iteration replays the graphs) with direct F*Lambda work and synchronisations in
-    between; the graphs are recaptured after a new setup."""
+    between; the graphs are recaptured after a new setup. Mixed: FP32 F*Lambda and FP32
+    preconditioner blocks (one preconditioner graph per block precision)."""
     prob = (workloads.cantilever_tfeti(4, nsub=(8, 8), m=3) if name == "dirs64" else workloads.modular_2d(0))
-    print(f"case graphs {name}", flush=True)
+    print(f"case graphs {name} mixed {mixed}", flush=True)
+    mk = dict(precision="fp32", precond_fp32=1) if mixed else {}
     f = _t(prob.load())
     ref = torch.zeros(prob.n_dof, dtype=torch.float64, device=DEV)
-    c0 = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", tol=1e-10)
+    c0 = _ctx(prob, method="fetidp", scaling="k", krylov="sfeti", tol=1e-10, **mk)
     i0 = c0.feti_solve(f, ref)
     n = c0.sizes["n_lambda"]
     c0.close()
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     with torch.cuda.stream(side):
-        spec = feti.Spec(prob, method="fetidp", scaling="k", krylov="sfeti", tol=1e-10, graphs=1)
+        spec = feti.Spec(prob, method="fetidp", scaling="k", krylov="sfeti", tol=1e-10, graphs=1, **mk)
         cg = feti.Context(spec, _t(prob.rho))
         L = torch.ones(n, 8, dtype=torch.float64, device=DEV)
         Q = torch.zeros_like(L)
