@@ -211,6 +211,8 @@ struct feti_ctx {
     double *Rb = nullptr, *Cit = nullptr, *tau = nullptr, *GG = nullptr, *GG_w = nullptr, *GG_inv = nullptr;
     double *w = nullptr, *bg_w = nullptr;
     int* info = nullptr;
+    char* bt_ws = nullptr;   // plane-by-plane band Cholesky: descriptors and pivot flags
+    double* bt_T = nullptr;  // plane-by-plane L^{-1} K_i,beta: one plane block per subdomain
     GemmDesc *d_syrk = nullptr, *d_F = nullptr, *d_one = nullptr;
     PotrfDesc *d_potrf = nullptr, *d_potrf_one = nullptr;
     TrsmDesc *d_trsm = nullptr, *d_trsm_one = nullptr;
@@ -506,6 +508,7 @@ void build_layout(feti_ctx* c) {
         const int nlines = P.dim == 2 ? M.nn[1] : M.nn[2];
         const int per_line_nodes = P.dim == 2 ? M.nn[0] : M.nn[0] * M.nn[1];
         M.n_lines = nlines;
+        t.max_planes = std::max(t.max_planes, nlines);
         M.line0 = (long long)c->hlines.size();
         M.off_L = oL;
         int i0 = 0, prev = 0;
@@ -594,6 +597,8 @@ void build_layout(feti_ctx* c) {
     c->rho = c->alloc<double>(P.n_el);
     c->Emod = c->alloc<double>(std::max<long long>(1, P.n_el));
     c->info = c->alloc<int>(ns + 8);
+    if (t.max_line > 128) c->bt_ws = c->alloc<char>(bt_plane_ws_bytes(t));
+    if (t.max_line > kSweepMaxLine && t.max_line <= kSweepBigLine) c->bt_T = c->alloc<double>(bt_plane_fwd_doubles(t));
     const int ncg = P.n_cg;
     // Kbar_cc: one dense block per design, 16-row tiles for the coarse solve
     long long kcc_sz = 0;
@@ -1218,12 +1223,15 @@ void numeric_setup(feti_ctx* c) {
         dpo = c->d_potrf_r;
         dtr = c->d_trsm_r;
     }
-    launch_bt_factor_li(ts, c->L, c->Li, c->info, st);
+    launch_bt_factor_li(ts, c->L, c->Li, c->info, c->bt_ws, st);
     CHECK_LAUNCH();
     check_info(c, nr, "interior Cholesky");
     launch_bt_invert(t, c->L, c->Li, st);
     CHECK_LAUNCH();
-    launch_bt_forward_li(ts, c->L, c->Li, c->Z, st);
+    if (c->bt_T)
+        launch_bt_forward_planes(ts, c->L, c->Li, c->Z, c->bt_T, st);
+    else
+        launch_bt_forward_li(ts, c->L, c->Li, c->Z, st);
     CHECK_LAUNCH();
     if (c->opts.precond == FETI_LUMPED || c->opts.precond == FETI_SUPERLUMPED) launch_pack_sym(ts, c->S, c->Pk, st);
     if (c->opts.precond == FETI_SUPERLUMPED) launch_pk_diag_only(ts, c->Pk, st);

@@ -190,37 +190,71 @@ void launch_simp_moduli(long long n, const double* rho, double p, double E0, dou
 }
 
 // ---------------------------------------------------------------------------------------
-// Block-tridiagonal Cholesky of K_ii, one workgroup per subdomain, blocks = grid lines
-// (2D) or planes (3D): D_k = A_kk - L_{k,k-1} L_{k,k-1}^T = L_kk L_kk^T,
-// L_{k+1,k} = A_{k+1,k} L_kk^{-T}.
-__global__ void __launch_bounds__(256) k_bt_factor(const SubMeta* __restrict__ subs,
-                                                   const LineMeta* __restrict__ lines, double* Lbuf,
-                                                   int* info) {
+// Block-tridiagonal Cholesky of K_ii, blocks = grid lines (2D) or planes (3D), for lines of more
+// than 128 DOFs: plane by plane, each step batched over the subdomains,
+//   D_k = A_kk - C_k C_k^T          (k_plane_syrk: one workgroup per 64 x 64 lower tile)
+//   D_k = L_kk L_kk^T               (batched Cholesky, one workgroup per subdomain)
+//   C_{k+1} = A_{k+1,k} L_kk^{-T}   (k_plane_trsm: one workgroup per 64 rows of C_{k+1})
+// with C_k = L_{k,k-1} (row-major n_k x n_{k-1}, written over A_{k,k-1}).
+__global__ void __launch_bounds__(256) k_plane_syrk(const SubMeta* __restrict__ subs,
+                                                    const LineMeta* __restrict__ lines, int k, double* Lbuf) {
     __shared__ double lds[kLdsDoubles];
-    const int s = blockIdx.x;
-    const SubMeta M = subs[s];
-    for (int k = 0; k < M.n_lines; ++k) {
-        const LineMeta Lk = lines[M.line0 + k];
-        if (Lk.n == 0) continue;
-        double* D = Lbuf + Lk.off_diag;
-        if (Lk.n_prev > 0) {
-            const double* Ls = Lbuf + Lk.off_sub;
-            wg_gemm_sub(Lk.n, Lk.n, Lk.n_prev, Ls, Lk.n_prev, 1, Ls, 1, Lk.n_prev, D, Lk.n, 1, true, lds);
-        }
-        const int r = wg_potrf(Lk.n, D, Lk.n, lds);
-        if (r) {
-            if (threadIdx.x == 0) info[s] = Lk.i0 + r;
-            return;
-        }
-        if (k + 1 < M.n_lines) {
-            const LineMeta Ln = lines[M.line0 + k + 1];
-            if (Ln.n > 0) {
-                // X = A_{k+1,k} L_kk^{-T}: solve L_kk X^T = A^T in place (X^T(i, c) = X[c][i])
-                wg_trsm_lower(Lk.n, Ln.n, D, Lk.n, Lbuf + Ln.off_sub, 1, Lk.n, lds);
-            }
-        }
-        __syncthreads();
+    const SubMeta M = subs[blockIdx.y];
+    if (k >= M.n_lines) return;
+    const LineMeta Lk = lines[M.line0 + k];
+    const int nb = (Lk.n + 63) >> 6, t = blockIdx.x;
+    if (Lk.n_prev == 0 || t >= nb * (nb + 1) / 2) return;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    const double* Ls = Lbuf + Lk.off_sub;
+    wg_gemm_sub(min(64, Lk.n - 64 * I), min(64, Lk.n - 64 * J), Lk.n_prev, Ls + 64ll * I * Lk.n_prev, Lk.n_prev, 1,
+                Ls + 64ll * J * Lk.n_prev, 1, Lk.n_prev, Lbuf + Lk.off_diag + 64ll * I * Lk.n + 64 * J, Lk.n, 1,
+                false, lds);
+}
+
+__global__ void __launch_bounds__(256) k_plane_trsm(const SubMeta* __restrict__ subs,
+                                                    const LineMeta* __restrict__ lines, int k, double* Lbuf) {
+    __shared__ double lds[kLdsDoubles];
+    const SubMeta M = subs[blockIdx.y];
+    if (k + 1 >= M.n_lines) return;
+    const LineMeta Lk = lines[M.line0 + k], Ln = lines[M.line0 + k + 1];
+    const int c0 = blockIdx.x * 64;
+    if (Lk.n == 0 || c0 >= Ln.n) return;
+    // rows c0 .. c0+63 of X = A_{k+1,k} L_kk^{-T}: solve L_kk X^T = A^T in place (X^T(i, c) = X[c][i])
+    wg_trsm_lower(Lk.n, min(64, Ln.n - c0), Lbuf + Lk.off_diag, Lk.n, Lbuf + Ln.off_sub + (long long)c0 * Lk.n, 1,
+                  Lk.n, lds);
+}
+
+// Cholesky descriptor of plane k of every subdomain (empty past its last plane), and the
+// per-plane pivot flags cleared.
+__global__ void k_plane_descs(const SubMeta* __restrict__ subs, int ns, const LineMeta* __restrict__ lines,
+                              int np, PotrfDesc* __restrict__ pd, int* __restrict__ pinfo) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ns * np) return;
+    const int k = e / ns;
+    const SubMeta M = subs[e - k * ns];
+    PotrfDesc d{0, 0, 1};
+    if (k < M.n_lines) {
+        const LineMeta L = lines[M.line0 + k];
+        d = PotrfDesc{L.off_diag, L.n, max(L.n, 1)};
     }
+    pd[e] = d;
+    pinfo[e] = 0;
+}
+
+// info[s] = 0, or 1 + the interior DOF of the first non-positive pivot of subdomain s.
+__global__ void k_plane_info(const SubMeta* __restrict__ subs, int ns, const LineMeta* __restrict__ lines, int np,
+                             const int* __restrict__ pinfo, int* __restrict__ info) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const SubMeta M = subs[s];
+    int v = 0;
+    for (int k = 0; k < min(np, M.n_lines) && v == 0; ++k) {
+        const int r = pinfo[(long long)k * ns + s];
+        if (r) v = lines[M.line0 + k].i0 + r;
+    }
+    info[s] = v;
 }
 
 // Z <- L^{-1} Z for one chunk of 64 columns of Z = K_i,beta (row-major n_i x n_beta).
@@ -257,6 +291,90 @@ __global__ void __launch_bounds__(256) k_bt_forward(const SubMeta* __restrict__ 
 // L_kk goes to its slot of L and L_kk^{-1} to the inverse buffer.
 constexpr int kBfLd = 129;
 typedef double v4w __attribute__((ext_vector_type(4)));
+
+// Z <- L^{-1} Z (Z = K_i,beta, row-major n_i x n_beta) plane by plane with the explicit inverses
+// Li_k = L_kk^{-1}, each step batched over the subdomains on the FP64 matrix cores:
+//   MODE 0:  T_k = Z_k - C_k Z_{k-1}     (T_k in a work buffer, one n_k x n_beta block per subdomain)
+//   MODE 1:  Z_k = Li_k T_k              (Li_k lower triangular: columns past the row tile skipped)
+// Workgroup: one 64 x 64 output tile (blockIdx.x = row tile + ntr * column tile), four wavefronts
+// of 32 x 32; operands staged through LDS 16 deep. Lane (m, g) supplies A[row m][4s + g] and
+// B[4s + g][column m] at sub-step s; its results are rows g + 4v, column m of each 16 x 16 block.
+constexpr int kPfLd = 68;   // padded LDS row (doubles)
+template <int MODE>
+__global__ void __launch_bounds__(256) k_plane_fwd(const SubMeta* __restrict__ subs,
+                                                   const LineMeta* __restrict__ lines, int k, int ntr,
+                                                   const double* __restrict__ Lbuf, const double* __restrict__ Li,
+                                                   double* Z, double* T, long long tstride) {
+    __shared__ double As[16 * kPfLd], Bs[16 * kPfLd];
+    const SubMeta M = subs[blockIdx.y];
+    if (k >= M.n_lines) return;
+    const LineMeta Lk = lines[M.line0 + k];
+    const int r0 = 64 * (blockIdx.x % ntr), c0 = 64 * (blockIdx.x / ntr), nb = M.n_beta, n = Lk.n;
+    if (r0 >= n || c0 >= nb) return;
+    double* Zk = Z + M.off_Z + (long long)Lk.i0 * nb;
+    double* Tk = T + tstride * blockIdx.y;
+    const double* A;
+    const double* B;
+    int K, lda;
+    if (MODE == 0) {
+        A = Lbuf + Lk.off_sub;
+        lda = Lk.n_prev;
+        K = Lk.n_prev;
+        B = Zk - (long long)Lk.n_prev * nb;
+    } else {
+        A = Li + Lk.off_inv;
+        lda = n;
+        K = min(n, r0 + 64);
+        B = Tk;
+    }
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+    const int wr = 32 * (wave & 1), wc = 32 * (wave >> 1);
+    v4w acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4w{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < K; q0 += 16) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int e = tid + 256 * p;
+            const int qa = e & 15, ia = e >> 4;   // A: 16 consecutive columns of one row
+            const int r = r0 + ia, qq = q0 + qa;
+            As[qa * kPfLd + ia] = (r < n && qq < K) ? A[(long long)r * lda + qq] : 0.0;
+            const int jb = e & 63, qb = e >> 6;   // B: 64 consecutive columns of one row
+            const int qr = q0 + qb, cc = c0 + jb;
+            Bs[qb * kPfLd + jb] = (qr < K && cc < nb) ? B[(long long)qr * nb + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int q = 4 * s4 + g;
+            const double a0 = As[q * kPfLd + wr + m], a1 = As[q * kPfLd + wr + 16 + m];
+            const double b0 = Bs[q * kPfLd + wc + m], b1 = Bs[q * kPfLd + wc + 16 + m];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + wr + 16 * i + g + 4 * v, col = c0 + wc + 16 * j + m;
+                if (row < n && col < nb) {
+                    const long long o = (long long)row * nb + col;
+                    if (MODE == 0)
+                        Tk[o] = Zk[o] - acc[i][j][v];
+                    else
+                        Zk[o] = acc[i][j][v];
+                }
+            }
+}
+
 
 // 32 operands of one 16-row block of a row-major matrix (rows r0 .. r0+15 of `rows`, columns
 // 0 .. cols-1, zero outside) in the lane order of the 16x16x4 contractions: op[4Q + e] is row
@@ -1455,8 +1573,23 @@ void launch_assemble(const DevTopo& t, const double* Emod, double* L, double* Z,
     k_assemble<<<grid, 256, 0, st>>>(t.subs, t.lines, t.dim, t.K0dev, Emod, t.lcls, t.lidx, L, Z, S, diag);
 }
 
-void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st) {
-    k_bt_factor<<<t.n_sub, 256, 0, st>>>(t.subs, t.lines, L, info);
+size_t bt_plane_ws_bytes(const DevTopo& t) {
+    return (size_t)t.max_planes * t.n_sub * (sizeof(PotrfDesc) + sizeof(int));
+}
+
+void launch_bt_factor(const DevTopo& t, double* L, int* info, void* ws, hipStream_t st) {
+    const int ns = t.n_sub, np = t.max_planes;
+    if (ns == 0) return;
+    PotrfDesc* pd = static_cast<PotrfDesc*>(ws);
+    int* pinfo = reinterpret_cast<int*>(pd + (size_t)np * ns);
+    if (np > 0) k_plane_descs<<<(np * ns + 255) / 256, 256, 0, st>>>(t.subs, ns, t.lines, np, pd, pinfo);
+    const int nb = (t.max_line + 63) / 64;
+    for (int k = 0; k < np; ++k) {
+        if (k > 0 && nb > 0) k_plane_syrk<<<dim3(nb * (nb + 1) / 2, ns), 256, 0, st>>>(t.subs, t.lines, k, L);
+        launch_potrf(pd + (size_t)k * ns, ns, t.max_line, L, pinfo + (size_t)k * ns, st);
+        if (k + 1 < np && nb > 0) k_plane_trsm<<<dim3(nb, ns), 256, 0, st>>>(t.subs, t.lines, k, L);
+    }
+    k_plane_info<<<(ns + 255) / 256, 256, 0, st>>>(t.subs, ns, t.lines, np, pinfo, info);
 }
 
 void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st) {
@@ -1466,12 +1599,27 @@ void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t
 
 // FP64 MFMA factorisation with the inverses for lines <= 128 DOFs, else the generic path
 // followed by the separate inverse kernel
-void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, hipStream_t st) {
+void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, void* ws, hipStream_t st) {
     if (t.max_line <= 128) {
         if (t.n_sub) k_bt_factor128<<<t.n_sub, 256, 0, st>>>(t.subs, t.lines, L, Li, info);
         return;
     }
-    launch_bt_factor(t, L, info, st);
+    launch_bt_factor(t, L, info, ws, st);
+}
+
+long long bt_plane_fwd_doubles(const DevTopo& t) {
+    return (long long)t.max_line * t.max_beta * t.n_sub;
+}
+
+void launch_bt_forward_planes(const DevTopo& t, const double* L, const double* Li, double* Z, double* T,
+                              hipStream_t st) {
+    const int ntr = (t.max_line + 63) / 64, ntc = (t.max_beta + 63) / 64;
+    if (t.n_sub == 0 || ntr == 0 || ntc == 0) return;
+    const long long ts = (long long)t.max_line * t.max_beta;
+    for (int k = 0; k < t.max_planes; ++k) {
+        k_plane_fwd<0><<<dim3(ntr * ntc, t.n_sub), 256, 0, st>>>(t.subs, t.lines, k, ntr, L, Li, Z, T, ts);
+        k_plane_fwd<1><<<dim3(ntr * ntc, t.n_sub), 256, 0, st>>>(t.subs, t.lines, k, ntr, L, Li, Z, T, ts);
+    }
 }
 
 void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, double* Z, hipStream_t st) {

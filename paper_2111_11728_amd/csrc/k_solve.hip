@@ -234,7 +234,6 @@ __global__ void __launch_bounds__(kSwT) k_bt_bsweep(const SubMeta* __restrict__ 
 // forward sweep accumulates a row tile over its column tiles before one wavefront sum per row,
 // the backward sweep a column tile over its row tiles before one LDS reduction; the zero tiles
 // above the diagonal of L_kk^{-1} are skipped.
-constexpr int kSweepBigLine = 512;
 
 // a[p][h] = A[r0 + w + 16 p][c0 + l + 64 h] (row-major, ld columns; rows < nr, columns < nc and,
 // when lower, column <= row), 0 elsewhere

@@ -79,7 +79,7 @@ struct DevTopo {
     int dim = 2, n_sub = 0, n_lambda = 0, n_cg = 0, n_groups = 0, n_rbm = 0;
     int nel[3] = {0, 0, 0}, nsub[3] = {1, 1, 1};
     int max_nodes = 0, max_beta = 0, max_nb = 0, max_rows_F = 0, max_nloc = 0, max_nc = 0, max_ni = 0;
-    int max_line = 0;
+    int max_line = 0, max_planes = 0;   // DOFs of the longest line; lines (planes) per subdomain
     // coarse blocks (one per design) and the 16-row tiles of the coarse solve
     const int* cg_blk = nullptr;
     const CoarseBlk* cblk = nullptr;
@@ -161,13 +161,22 @@ void launch_simp_moduli(long long n, const double* rho, double p, double E0, dou
                         hipStream_t st);
 void launch_assemble(const DevTopo& t, const double* Emod, double* L, double* Z, double* S, double* diag,
                      hipStream_t st);
-void launch_bt_factor(const DevTopo& t, double* L, int* info, hipStream_t st);
+// Block-tridiagonal Cholesky, plane by plane batched over the subdomains; ws holds
+// bt_plane_ws_bytes(t) bytes (per-plane Cholesky descriptors and pivot flags)
+size_t bt_plane_ws_bytes(const DevTopo& t);
+void launch_bt_factor(const DevTopo& t, double* L, int* info, void* ws, hipStream_t st);
 // Block-tridiagonal Cholesky that also writes L_kk^{-1} (lines <= 128 DOFs; otherwise the
-// generic factorisation, and launch_bt_invert must follow)
-void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, hipStream_t st);
+// plane-by-plane factorisation, and launch_bt_invert must follow)
+void launch_bt_factor_li(const DevTopo& t, double* L, double* Li, int* info, void* ws, hipStream_t st);
 // Z <- L^{-1} Z with the explicit diagonal inverses (matrix cores; lines <= 128 DOFs)
 void launch_bt_forward_li(const DevTopo& t, const double* L, const double* Li, double* Z, hipStream_t st);
 void launch_bt_forward(const DevTopo& t, const double* L, double* Z, hipStream_t st);
+// Z <- L^{-1} Z plane by plane with the explicit inverses (matrix cores, batched over the
+// subdomains; lines of more than kSweepMaxLine and at most kSweepBigLine DOFs); T: work buffer of
+// bt_plane_fwd_doubles(t) doubles
+long long bt_plane_fwd_doubles(const DevTopo& t);
+void launch_bt_forward_planes(const DevTopo& t, const double* L, const double* Li, double* Z, double* T,
+                              hipStream_t st);
 // along one dimension of C over the batch
 // Deflation of local interface modes: subspace width, the largest interface block held in LDS,
 // modes per subdomain, subspace iterations and the relative spectral gap that ends a selection
@@ -342,6 +351,8 @@ void launch_bt_fsolve1(const DevTopo& t, const double* L, const double* Li, doub
 void launch_bt_bsolve1(const DevTopo& t, const double* L, const double* Li, double* x, hipStream_t st);
 void launch_bt_invert(const DevTopo& t, const double* L, double* Li, hipStream_t st);
 constexpr int kSweepMaxLine = 128;
+// longest line that still gets explicit diagonal inverses (launch_bt_invert) and the tiled sweeps
+constexpr int kSweepBigLine = 512;
 // g = fbeta - Z^T h; part: scratch of 8 (nb_tot + nc_tot) doubles
 void launch_zt_gemv(const DevTopo& t, const double* Z, const double* h, const double* fbeta, double* g, double* part,
                     hipStream_t st);
