@@ -960,7 +960,7 @@ __global__ void __launch_bounds__(512) k_potrf512(const PotrfDesc* __restrict__ 
 //   k_potrf_panel: L21 = A21 L11^{-T}, kPfRows rows per workgroup (one thread per row,
 //                  substitution against L11 in LDS);
 //   k_potrf_syrk:  A22 -= L21 L21^T on the lower 64x64 tiles of the trailing matrix, one
-//                  workgroup per tile (4x4 outputs per thread, operands in LDS).
+//                  workgroup per tile (FP64 matrix cores, operands in LDS).
 // info[b]: 0, or 1 + the column of the first non-positive pivot (as the one-workgroup form).
 constexpr int kPfB = 64, kPfRows = 128;
 __global__ void __launch_bounds__(256) k_potrf_diag(const PotrfDesc* __restrict__ desc, int p0, double* base,
@@ -1008,53 +1008,71 @@ __global__ void __launch_bounds__(256) k_potrf_panel(const PotrfDesc* __restrict
     }
 }
 
-__global__ void __launch_bounds__(256) k_potrf_syrk(const PotrfDesc* __restrict__ desc, int p0, double* base,
-                                                    const int* __restrict__ info) {
+// Trailing update with the factored panel columns p0 .. q0-1 (q0 = p0 + min(kw, n - p0), kw = 64
+// or 128, staged 64 at a time): strip = 0 updates every lower 64 x 64 tile of the trailing matrix
+// (rows and columns >= q0), strip = 1 only the tiles of its first 64 columns (the next panel).
+__global__ void __launch_bounds__(256) k_potrf_syrk(const PotrfDesc* __restrict__ desc, int p0, int kw, int strip,
+                                                    double* base, const int* __restrict__ info) {
     __shared__ double Ai[64][kPfB + 1];
     __shared__ double Aj[64][kPfB + 1];
     const PotrfDesc d = desc[blockIdx.y];
     if (p0 >= d.n) return;
-    const int b = min(kPfB, d.n - p0), q0 = p0 + b;
+    const int kcols = min(kw, d.n - p0), q0 = p0 + kcols;
     const int nt = (d.n - q0 + 63) / 64;
     const int t = blockIdx.x;
-    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    while (I * (I + 1) / 2 > t) --I;
-    const int J = t - I * (I + 1) / 2;
+    int I = t, J = 0;
+    if (!strip) {
+        I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        while (I * (I + 1) / 2 > t) --I;
+        J = t - I * (I + 1) / 2;
+    }
     if (I >= nt || info[blockIdx.y] != 0) return;   // uniform
     double* A = base + d.a;
     const int ri = q0 + 64 * I, rj = q0 + 64 * J;
-    for (int e = threadIdx.x; e < 64 * kPfB; e += 256) {
-        const int i = e / kPfB, k = e % kPfB;
-        Ai[i][k] = (ri + i < d.n && k < b) ? A[(long long)(ri + i) * d.lda + p0 + k] : 0.0;
-        Aj[i][k] = (rj + i < d.n && k < b) ? A[(long long)(rj + i) * d.lda + p0 + k] : 0.0;
-    }
-    __syncthreads();
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-    double acc[4][4];
+    // FP64 matrix cores: wavefront w takes the 32 x 32 quadrant (rows 32 (w & 1), columns
+    // 32 (w >> 1)); lane (m, g) supplies Ai[row m][4s + g] and Aj[column m][4s + g] at sub-step s,
+    // and holds rows g + 4v, column m of each 16 x 16 block. The quadrant above the diagonal of a
+    // diagonal tile only stages.
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, m = lane & 15, g = lane >> 4;
+    const int wr = 32 * (wave & 1), wc = 32 * (wave >> 1);
+    const bool work = !(J == I && wc > wr);
+    v4w acc[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < b; ++k) {
-        double x[4], y[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) x[r] = Ai[4 * tr + r][k];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) y[c] = Aj[4 * tc + c][k];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = fma(x[r], y[c], acc[r][c]);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = ri + 4 * tr + r, j = rj + 4 * tc + c;
-            if (i < d.n && j <= i) A[(long long)i * d.lda + j] -= acc[r][c];
+        for (int y = 0; y < 2; ++y) acc[x][y] = v4w{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < kcols; kc += kPfB) {
+        if (kc) __syncthreads();
+        for (int e = threadIdx.x; e < 64 * kPfB; e += 256) {
+            const int i = e / kPfB, k = e % kPfB;
+            const bool kin = kc + k < kcols;
+            Ai[i][k] = (ri + i < d.n && kin) ? A[(long long)(ri + i) * d.lda + p0 + kc + k] : 0.0;
+            Aj[i][k] = (rj + i < d.n && kin) ? A[(long long)(rj + i) * d.lda + p0 + kc + k] : 0.0;
         }
+        __syncthreads();
+        if (work) {
+#pragma unroll 4
+            for (int k = 0; k < kPfB; k += 4) {
+                const double a0 = Ai[wr + m][k + g], a1 = Ai[wr + 16 + m][k + g];
+                const double b0 = Aj[wc + m][k + g], b1 = Aj[wc + 16 + m][k + g];
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        }
+    }
+    if (!work) return;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = ri + wr + 16 * x + g + 4 * v, j = rj + wc + 16 * y + m;
+                if (i < d.n && j <= i) A[(long long)i * d.lda + j] -= acc[x][y][v];
+            }
 }
 
 // Batched B <- L^{-1} B for B holding the identity on entry (the explicit inverse of a
@@ -1643,13 +1661,20 @@ void launch_potrf(const PotrfDesc* d, int nbatch, int max_n, double* base, int* 
         k_potrf512<<<nbatch, 512, 0, st>>>(d, base, info);
         return;
     }
-    for (int p0 = 0; p0 < max_n; p0 += kPfB) {
+    // panels in pairs: the first panel's update of the second panel's columns, then one pass of
+    // both over the trailing matrix (half the passes of a panel-by-panel update)
+    for (int p0 = 0; p0 < max_n; p0 += 2 * kPfB) {
         k_potrf_diag<<<nbatch, 256, 0, st>>>(d, p0, base, info);
         const int rest = max_n - p0 - kPfB;
         if (rest <= 0) break;
         k_potrf_panel<<<dim3((rest + kPfRows - 1) / kPfRows, nbatch), 256, 0, st>>>(d, p0, base, info);
-        const int nt = (rest + 63) / 64;
-        k_potrf_syrk<<<dim3(nt * (nt + 1) / 2, nbatch), 256, 0, st>>>(d, p0, base, info);
+        k_potrf_syrk<<<dim3((rest + 63) / 64, nbatch), 256, 0, st>>>(d, p0, kPfB, 1, base, info);
+        k_potrf_diag<<<nbatch, 256, 0, st>>>(d, p0 + kPfB, base, info);
+        const int rest2 = rest - kPfB;
+        if (rest2 <= 0) break;
+        k_potrf_panel<<<dim3((rest2 + kPfRows - 1) / kPfRows, nbatch), 256, 0, st>>>(d, p0 + kPfB, base, info);
+        const int nt = (rest2 + 63) / 64;
+        k_potrf_syrk<<<dim3(nt * (nt + 1) / 2, nbatch), 256, 0, st>>>(d, p0, 2 * kPfB, 0, base, info);
     }
 }
 
