@@ -20,17 +20,21 @@ __device__ inline void wg_gemm_sub(int m, int n, int kk, const double* __restric
                                    long long sbn, double* C, long long sci, long long scj,
                                    bool lower_only, double* lds) {
     const int tid = threadIdx.x;
-    const int tr = tid >> 4, tc = tid & 15;
+    // FP64 matrix cores: wavefront w takes the 32 x 32 quadrant (rows 32 (w & 1), columns
+    // 32 (w >> 1)) of each 64 x 64 tile; lane (mm, g) supplies A[row mm][4s + g] and
+    // B[4s + g][column mm] at sub-step s, and holds rows g + 4v, column mm of each 16 x 16 block.
+    const int wave = tid >> 6, lane = tid & 63, mm = lane & 15, g = lane >> 4;
+    const int wr = 32 * (wave & 1), wc = 32 * (wave >> 1);
     double* As = lds;            // [32][64]
     double* Bs = lds + 32 * 64;  // [32][64]
     for (int i0 = 0; i0 < m; i0 += 64) {
         for (int j0 = 0; j0 < n; j0 += 64) {
             if (lower_only && j0 >= i0 + 64) continue;
-            double acc[4][4];
+            v4d_t acc[2][2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+                for (int y = 0; y < 2; ++y) acc[x][y] = v4d_t{0.0, 0.0, 0.0, 0.0};
             for (int k0 = 0; k0 < kk; k0 += 32) {
                 for (int e = tid; e < 64 * 32; e += kWG) {
                     int i, k;
@@ -41,27 +45,28 @@ __device__ inline void wg_gemm_sub(int m, int n, int kk, const double* __restric
                     Bs[k2 * 64 + j] = (j0 + j < n && k0 + k2 < kk) ? B[(k0 + k2) * sbk + (j0 + j) * sbn] : 0.0;
                 }
                 __syncthreads();
-#pragma unroll 8
-                for (int k = 0; k < 32; ++k) {
-                    double a[4], b[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) a[r] = As[k * 64 + tr * 4 + r];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) b[c] = Bs[k * 64 + tc * 4 + c];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+                for (int k = 0; k < 32; k += 4) {
+                    const double* Ar = As + (k + g) * 64;
+                    const double* Br = Bs + (k + g) * 64;
+                    const double a0 = Ar[wr + mm], a1 = Ar[wr + 16 + mm];
+                    const double b0 = Br[wc + mm], b1 = Br[wc + 16 + mm];
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
                 }
                 __syncthreads();
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    int i = i0 + tr * 4 + r, j = j0 + tc * 4 + c;
-                    if (i < m && j < n) C[i * sci + j * scj] -= acc[r][c];
-                }
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = i0 + wr + 16 * x + g + 4 * v, j = j0 + wc + 16 * y + mm;
+                        if (i < m && j < n) C[i * sci + j * scj] -= acc[x][y][v];
+                    }
         }
     }
     __syncthreads();
