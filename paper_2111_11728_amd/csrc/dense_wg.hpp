@@ -110,42 +110,47 @@ __device__ inline int wg_potrf(int n, double* A, long long lda, double* lds) {
 }
 
 // B <- L^{-1} B for lower-triangular L (n x n, row-major ldl, non-zero diagonal) and B with
-// ncols columns; element (i, c) of B lives at B[i*sbi + c*sbc]. Left-looking in blocks of 32
-// rows; each block is finished by one thread per column (no barriers inside the block).
+// ncols columns; element (i, c) of B lives at B[i*sbi + c*sbc]. Left-looking in blocks of RB
+// rows (each block's update from the rows above re-reads them, so larger blocks read less); each
+// block is finished by one thread per column (no barriers inside the block). lds must hold
+// kLdsDoubles doubles for RB = 32 and kLdsTrsm64 for RB = 64.
+constexpr int kLdsTrsm64 = 64 * 65 + 64 * 64;
+template <int RB = 32>
 __device__ inline void wg_trsm_lower(int n, int ncols, const double* __restrict__ L, long long ldl,
                                      double* B, long long sbi, long long sbc, double* lds) {
+    static_assert(RB == 32 || RB == 64, "row block");
     const int tid = threadIdx.x;
     for (int c0 = 0; c0 < ncols; c0 += 64) {
         const int nc = min(64, ncols - c0);
         double* Bc = B + c0 * sbc;
-        for (int I0 = 0; I0 < n; I0 += 32) {
-            const int rb = min(32, n - I0);
+        for (int I0 = 0; I0 < n; I0 += RB) {
+            const int rb = min(RB, n - I0);
             if (I0 > 0)
                 wg_gemm_sub(rb, nc, I0, L + (long long)I0 * ldl, ldl, 1, Bc, sbi, sbc, Bc + I0 * sbi, sbi, sbc,
                             false, lds);
-            double* Ld = lds;            // [32][33]
-            double* Bd = lds + 32 * 33;  // [32][64]
-            for (int e = tid; e < 32 * 32; e += kWG) {
-                int r = e >> 5, q = e & 31;
-                Ld[r * 33 + q] = (r < rb && q <= r) ? L[(I0 + r) * ldl + I0 + q] : 0.0;
+            double* Ld = lds;                   // [RB][RB + 1]
+            double* Bd = lds + RB * (RB + 1);   // [RB][64]
+            for (int e = tid; e < RB * RB; e += kWG) {
+                const int r = e / RB, q = e % RB;
+                Ld[r * (RB + 1) + q] = (r < rb && q <= r) ? L[(I0 + r) * ldl + I0 + q] : 0.0;
             }
-            for (int e = tid; e < 32 * 64; e += kWG) {
+            for (int e = tid; e < RB * 64; e += kWG) {
                 int r, c;
-                if (sbc == 1) { c = e & 63; r = e >> 6; } else { r = e & 31; c = e >> 5; }
+                if (sbc == 1) { c = e & 63; r = e >> 6; } else { r = e % RB; c = e / RB; }
                 Bd[r * 64 + c] = (r < rb && c < nc) ? Bc[(I0 + r) * sbi + c * sbc] : 0.0;
             }
             __syncthreads();
             if (tid < nc) {
                 for (int r = 0; r < rb; ++r) {
                     double v = Bd[r * 64 + tid];
-                    for (int q = 0; q < r; ++q) v -= Ld[r * 33 + q] * Bd[q * 64 + tid];
-                    Bd[r * 64 + tid] = v / Ld[r * 33 + r];
+                    for (int q = 0; q < r; ++q) v -= Ld[r * (RB + 1) + q] * Bd[q * 64 + tid];
+                    Bd[r * 64 + tid] = v / Ld[r * (RB + 1) + r];
                 }
             }
             __syncthreads();
-            for (int e = tid; e < 32 * 64; e += kWG) {
+            for (int e = tid; e < RB * 64; e += kWG) {
                 int r, c;
-                if (sbc == 1) { c = e & 63; r = e >> 6; } else { r = e & 31; c = e >> 5; }
+                if (sbc == 1) { c = e & 63; r = e >> 6; } else { r = e % RB; c = e / RB; }
                 if (r < rb && c < nc) Bc[(I0 + r) * sbi + c * sbc] = Bd[r * 64 + c];
             }
             __syncthreads();

@@ -1081,12 +1081,12 @@ __global__ void __launch_bounds__(256) k_potrf_syrk(const PotrfDesc* __restrict_
 // substitution starts at that row, on the trailing block of L.
 __global__ void __launch_bounds__(256) k_trsm(const TrsmDesc* __restrict__ desc, const double* Lbase,
                                               double* Bbase) {
-    __shared__ double lds[kLdsDoubles];
+    __shared__ double lds[kLdsTrsm64];
     const TrsmDesc d = desc[blockIdx.y];
     const int c0 = blockIdx.x * 64;
     if (c0 >= d.ncols || c0 >= d.n) return;
     const int nc = min(64, d.ncols - c0);
-    wg_trsm_lower(d.n - c0, nc, Lbase + d.l + (long long)c0 * d.ldl + c0, d.ldl, Bbase + d.b + (long long)c0 * d.ldb + c0,
+    wg_trsm_lower<64>(d.n - c0, nc, Lbase + d.l + (long long)c0 * d.ldl + c0, d.ldl, Bbase + d.b + (long long)c0 * d.ldb + c0,
                   d.ldb, 1, lds);
 }
 
